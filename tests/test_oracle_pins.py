@@ -1,0 +1,551 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: textbook
+constants, numbers printed in the paper, closed forms, quadratures of
+conserved-quantity orbit equations, the general (finite magnetisation)
+dispersion relation in its strong-field limit, independent numpy
+re-derivations from the paper's flat-space formulas, and convergence orders.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def ne_from_wp2(orc, s, x, t=0.0):
+    """electron density [cm^-3] from the oracle's w_p^2 / w_inf^2"""
+    c = orc.constants()
+    v0 = s["v0_kms"] / c["c_kms"]
+    w_inf2 = s["m_a_eV"] ** 2 * (1 + v0 ** 2)
+    return orc.wp2(s, x, t) * w_inf2 / c["wp2_per_ne"]
+
+
+# ---------------------------------------------------------------- units and constants
+def test_constants_textbook(orc):
+    c = orc.constants()
+    # critical field B_c = m_e^2 / e (natural Heaviside-Lorentz units, e^2 = 4 pi alpha): 4.414e13 G
+    Bc = c["m_e_eV"] ** 2 / math.sqrt(4 * math.pi * c["alpha"]) / c["gauss_eV2"]
+    assert abs(Bc / 4.414e13 - 1) < 2e-4
+    # plasma frequency in Gaussian CGS: w_p^2 = 4 pi n e^2 / m_e  [rad^2 s^-2], times hbar^2
+    me_g, hbar_eVs, e = 9.1093837015e-28, 6.582119569e-16, 4.803204712570263e-10
+    wp_eV = hbar_eVs * math.sqrt(4 * math.pi * e ** 2 / me_g)
+    assert abs(c["wp2_per_ne"] / wp_eV ** 2 - 1) < 1e-8
+    # electron cyclotron energy per gauss: hbar e B / (m_e c) = 1.15768e-8 eV
+    wc = c["gauss_eV2"] * math.sqrt(4 * math.pi * c["alpha"]) / c["m_e_eV"]
+    assert abs(wc / (hbar_eVs * e / (me_g * 2.99792458e10)) - 1) < 1e-8
+
+
+def test_density_normalisations_printed(orc):
+    """Sec. 6 prints n_GJ ~ 2e12 cm^-3 (P = 3.76 s, B0 = 2e14 G, r = R) and the twisted
+    magnetar density ~ 7e15 cm^-3 lambda sin^2 (psi/0.2)(B0/2e14 G)(R/r)^4, a ratio ~1e3 lambda."""
+    s_gj = W.star(B0_G=2e14, P_s=3.76, theta_m=0.0, density=W.DENSITY_GJ)
+    # point where the angular bracket |3 cos^2 - 1| is 1
+    x = 10.0 * np.array([math.sqrt(1 / 3), 0.0, math.sqrt(2 / 3)])
+    n_gj = ne_from_wp2(orc, s_gj, x)
+    assert 1.7e12 < n_gj < 2.3e12, n_gj
+    s_mag = W.star(B0_G=2e14, P_s=3.76, theta_m=0.0, density=W.DENSITY_MAGNETAR, psi_twist=0.2, multiplicity=1.0)
+    xe = np.array([10.0, 0.0, 0.0])  # magnetic equator at the surface
+    n_mag = ne_from_wp2(orc, s_mag, xe)
+    assert 6.0e15 < n_mag < 8.0e15, n_mag
+    assert 1e3 <= n_mag / n_gj < 1e4
+    # twisted density falls as r^-4 along a radial line
+    assert abs(ne_from_wp2(orc, s_mag, 2 * xe) / n_mag - 1 / 16) < 1e-14
+
+
+# ---------------------------------------------------------------- metric and Hamiltonian
+def test_inverse_metric_matches_spherical_chart(orc):
+    s = W.star(M_Msun=1.4)
+    rs = 2 * 1.4766250 * 1.4
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        r, th, ph = rng.uniform(11, 100), rng.uniform(0.1, 3.0), rng.uniform(0, 6.28)
+        x = r * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        # d x^i / d q^a for q = (r, theta, phi)
+        J = np.array([[math.sin(th) * math.cos(ph), r * math.cos(th) * math.cos(ph), -r * math.sin(th) * math.sin(ph)],
+                      [math.sin(th) * math.sin(ph), r * math.cos(th) * math.sin(ph), r * math.sin(th) * math.cos(ph)],
+                      [math.cos(th), -r * math.sin(th), 0.0]])
+        A = 1 - rs / r
+        gsph_inv = np.diag([A, 1 / r ** 2, 1 / (r * math.sin(th)) ** 2])
+        g_cart = J @ gsph_inv @ J.T
+        assert np.allclose(orc.inverse_metric(s, x), g_cart, rtol=0, atol=1e-13)
+
+
+def _general_dispersion(w, k, wp2, wL, cosB):
+    """Cold magnetised plasma, static frame, flat space (Sec. 4.1, the rewritten form of
+    eq. (DisRel)): k^2 [w^2 wL^2 (k^2 + wp^2) - wp^2 (wL.k)^2] - w^2 (w^2 - wp^2)(k^2 + wp^2)^2
+    with k^2 = -w^2 + |k|^2 and wL.k = wL |k| cos(theta_B)."""
+    k4 = -w ** 2 + k ** 2
+    wLk = wL * k * cosB
+    return k4 * (w ** 2 * wL ** 2 * (k4 + wp2) - wp2 * wLk ** 2) - w ** 2 * (w ** 2 - wp2) * (k4 + wp2) ** 2
+
+
+def test_lo_energy_is_strong_field_limit_of_general_dispersion(orc):
+    """The LO root of eq. (AnisotropicDisp) must be the omega_L -> infinity limit of the
+    general cold-plasma dispersion relation."""
+    mpmath.mp.dps = 60
+    s = W.star(M_Msun=0.0, theta_m=0.4, plasma=W.PLASMA_ANISO, density=W.DENSITY_GJ)
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(20, 40)
+        k = rng.normal(size=3) * rng.uniform(0.1, 1.5)
+        E = orc.energy(s, x, 0.0, k)
+        wp2 = orc.wp2(s, x, 0.0)
+        B = orc.bfield(s, x, 0.0)
+        cosB = float(np.dot(k, B) / np.linalg.norm(k) / np.linalg.norm(B))
+        kn = float(np.linalg.norm(k))
+        for wL in (1e4, 1e6):
+            f = lambda w: _general_dispersion(w, mpmath.mpf(kn), mpmath.mpf(wp2), mpmath.mpf(wL), mpmath.mpf(cosB))
+            root = mpmath.findroot(f, mpmath.mpf(E))
+            assert abs(float(root) / E - 1) < 50.0 * (max(wp2, 1.0) / wL) ** 2, (float(root), E, wL)
+
+
+@pytest.mark.parametrize("plasma", [W.PLASMA_ISO, W.PLASMA_ANISO])
+@pytest.mark.parametrize("M", [0.0, 1.4])
+def test_hamiltonian_vanishes_on_dispersion_relation(orc, plasma, M):
+    """H(x, k, k_t) = 0 when the static-frame frequency -k_t/sqrt(A) is the mode energy of
+    eq. (AnisotropicDisp) (or (energyIso)) at the same covariant spatial k."""
+    s = W.star(M_Msun=M, theta_m=0.3, plasma=plasma)
+    rs = 2 * 1.4766250 * M
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        x = rng.normal(size=3)
+        r = rng.uniform(12, 60)
+        x = x / np.linalg.norm(x) * r
+        t = rng.uniform(0, 3e5)
+        k = rng.normal(size=3) * 0.7
+        E = orc.energy(s, x, t, k)
+        y = np.concatenate([x, [t], k, [-E * math.sqrt(1 - rs / r)]])
+        assert abs(orc.hamiltonian(s, y)) < 1e-13
+
+
+def test_gradient_matches_finite_differences(orc):
+    s = W.star(M_Msun=1.4, theta_m=0.5, plasma=W.PLASMA_ANISO)
+    rng = np.random.default_rng(7)
+    for _ in range(8):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(12, 50)
+        y = np.concatenate([x, [rng.uniform(0, 3e5)], rng.normal(size=3) * 0.5, [-1.0]])
+        g = orc.grad_h(s, y)
+        for i in range(8):
+            h = 1e-6 * max(1.0, abs(y[i])) if i != 3 else 1e-2
+            yp, ym = y.copy(), y.copy()
+            yp[i] += h
+            ym[i] -= h
+            fd = (orc.hamiltonian(s, yp) - orc.hamiltonian(s, ym)) / (2 * h)
+            assert abs(fd - g[i]) <= 1e-6 * max(1e-6, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+# ---------------------------------------------------------------- random numbers
+M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+
+
+def _philox_py(ctr, key):
+    c = list(ctr)
+    k = list(key)
+    for r in range(10):
+        if r:
+            k = [(k[0] + W0) & 0xFFFFFFFF, (k[1] + W1) & 0xFFFFFFFF]
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [((p1 >> 32) ^ c[1] ^ k[0]) & 0xFFFFFFFF, p1 & 0xFFFFFFFF,
+             ((p0 >> 32) ^ c[3] ^ k[1]) & 0xFFFFFFFF, p0 & 0xFFFFFFFF]
+    return c
+
+
+def test_philox_matches_python_bigint(orc):
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        ctr = [int(v) for v in rng.integers(0, 2 ** 32, 4)]
+        key = [int(v) for v in rng.integers(0, 2 ** 32, 2)]
+        assert orc.philox(ctr, key) == _philox_py(ctr, key)
+
+
+def test_uniforms_chi2(orc):
+    u = np.array([orc.uniforms(0, 0, i) for i in range(4000)]).ravel()
+    assert u.min() > 0 and u.max() < 1
+    h, _ = np.histogram(u, bins=20, range=(0, 1))
+    exp = len(u) / 20
+    chi2 = ((h - exp) ** 2 / exp).sum()
+    assert chi2 < 45  # 19 dof, p ~ 1e-3
+
+
+# ---------------------------------------------------------------- resonance surface and seeds
+def test_resonance_radius_closed_form_flat(orc):
+    """Flat isotropic GJ: w_p = m_a at r_c^3 = R^3 n0 |3 cos^2 - 1| / n_res, n_res = m_a^2 / (4 pi alpha / m_e)."""
+    s = W.CFG1["star"]
+    c = orc.constants()
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    n_res = s["m_a_eV"] ** 2 / c["wp2_per_ne"]
+    for th in (0.0, math.pi / 2, 0.3, 1.2):
+        nh = np.array([math.sin(th), 0.0, math.cos(th)])
+        rc = orc.resonance_radius(s, nh, nh, 0.0)
+        expect = 10.0 * (n0 * abs(3 * math.cos(th) ** 2 - 1) / n_res) ** (1 / 3)
+        assert abs(rc / expect - 1) < 1e-13
+    # the quoted pole / equator radii of this workload
+    assert abs(orc.resonance_radius(s, np.array([0, 0, 1.0]), np.array([0, 0, 1.0]), 0.0) - 45.750) < 1e-3
+    assert abs(orc.resonance_radius(s, np.array([1.0, 0, 0]), np.array([1.0, 0, 0]), 0.0) - 36.312) < 1e-3
+
+
+def _axion_photon_state(s, x, khat, t0):
+    """photon state carrying the axion momentum at x (k_t = -1, static-frame |k_a|^2 = 1/A - m~^2)"""
+    c_kms = 299792.458
+    v0 = s["v0_kms"] / c_kms
+    ma2 = 1 / (1 + v0 ** 2)
+    rs = 2 * 1.4766250 * s["M_Msun"]
+    r = np.linalg.norm(x)
+    A = 1 - rs / r
+    ka = math.sqrt(1 / A - ma2)
+    n = x / r
+    ko = ka * khat
+    nko = n @ ko
+    k = ko - nko * n + nko / math.sqrt(A) * n
+    return np.concatenate([x, [t0], k, [-1.0]])
+
+
+def test_resonance_root_brute_force_gr(orc):
+    """Root of the foliation function = sign change of the photon Hamiltonian evaluated on
+    the axion momentum, found by a brute-force radial scan (anisotropic, GR, oblique)."""
+    s = W.CFG2["star"]
+    rng = np.random.default_rng(13)
+    found = 0
+    for _ in range(40):
+        nh = rng.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        kh = rng.normal(size=3)
+        kh /= np.linalg.norm(kh)
+        t0 = rng.uniform(0, 3e5)
+        rc = orc.resonance_radius(s, nh, kh, t0)
+        rr = np.linspace(10.0, 200.0, 20001)
+        Hs = np.array([orc.hamiltonian(s, _axion_photon_state(s, r * nh, kh, t0)) for r in rr])
+        sc = np.nonzero(np.sign(Hs[:-1]) != np.sign(Hs[1:]))[0]
+        if rc < 0:
+            assert len(sc) == 0 or Hs[0] < 0
+            continue
+        found += 1
+        assert len(sc) == 1  # uniqueness of the crossing
+        j = sc[0]
+        assert rr[j] - 1e-9 <= rc <= rr[j + 1] + 1e-9
+        assert abs(orc.hamiltonian(s, _axion_photon_state(s, rc * nh, kh, t0))) < 1e-12
+    assert found > 20
+
+
+@pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])
+def test_seeds_on_shell(orc, cfg):
+    rays, st = orc.sample(cfg["star"], cfg["seed"], 512)
+    ok = st == W.STATUS_OK
+    assert ok.sum() > 400
+    rs = 2 * 1.4766250 * cfg["star"]["M_Msun"]
+    for i in np.nonzero(ok)[0][:100]:
+        y = rays[:8, i]
+        assert abs(orc.hamiltonian(cfg["star"], y)) < 1e-13
+        r = np.linalg.norm(y[:3])
+        # the LO energy at the seed momentum is the local photon frequency 1/sqrt(A)
+        E = orc.energy(cfg["star"], y[:3], y[3], y[4:7])
+        assert abs(E * math.sqrt(1 - rs / r) - 1) < 1e-12
+    assert np.all(rays[8][ok] > 0)
+    assert np.all(rays[8][~ok] == 0)
+
+
+def test_foliation_width_below_ten_percent(orc):
+    """App. B: at the fiducial star (M = 1, m_a = 1e-5 eV, aligned, anisotropic plasma) the
+    radial width of the resonance foliation stays below the 10% level."""
+    s = W.star(M_Msun=1.0, theta_m=0.0, plasma=W.PLASMA_ANISO, m_a_eV=1e-5)
+    rng = np.random.default_rng(17)
+    for _ in range(10):
+        nh = rng.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        radii = []
+        for _ in range(200):
+            kh = rng.normal(size=3)
+            kh /= np.linalg.norm(kh)
+            rc = orc.resonance_radius(s, nh, kh, 0.0)
+            if rc > 0:
+                radii.append(rc)
+        if len(radii) > 10 and min(radii) > 15.0:
+            assert max(radii) / min(radii) < 1.10
+
+
+# ---------------------------------------------------------------- conversion weights
+@pytest.mark.parametrize("M", [0.0, 1.0])
+def test_zero_variance_spherical_weights(orc, M):
+    """Spherical profile w_p^2 ~ r^-3 with constant |B_perp|: every weight equals the closed
+    form of Sec. 4 (the analytic spherical-surface result the paper checks both tracers
+    against), here C_k n_c r_c^2 pi g^2 B^2 E^2 / |d w_p^2/dr|."""
+    s = W.star(M_Msun=M, plasma=W.PLASMA_ISO, density=W.DENSITY_SPHERICAL, weights=W.WEIGHTS_CONST_B,
+               kdir=W.KDIR_ISOTROPIC, B_test_G=1e12)
+    c = orc.constants()
+    rays, st = orc.sample(s, 0, 64)
+    assert np.all(st == 0)
+    w = rays[8]
+    assert np.ptp(w) <= 1e-12 * w.mean()
+    v0 = s["v0_kms"] / c["c_kms"]
+    ma = s["m_a_eV"]
+    w_inf = ma * math.sqrt(1 + v0 ** 2)
+    rs = 2 * c["GMsun_km"] * M
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    wp2R = c["wp2_per_ne"] * n0  # eV^2 at r = R
+    ma2 = ma ** 2
+    rc = 10.0 * (wp2R / ma2) ** (1 / 3)
+    assert abs(rays[9][0] / rc - 1) < 1e-13
+    A = 1 - rs / rc
+    hc = c["hbarc_eVkm"]
+    E = w_inf / math.sqrt(A)
+    ka = math.sqrt(w_inf ** 2 / A - ma2)
+    n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+    n_c = n_inf * ka / (ma * v0)
+    dwp2dr = 3 * ma2 / rc * hc  # |d w_p^2 / dr| in eV^3 (r in eV^-1)
+    g = 1e-12 * 1e-9
+    B = 1e12 * c["gauss_eV2"]
+    closed = 4 * math.pi * n_c * (rc / hc) ** 2 * math.pi * g ** 2 * B ** 2 * E ** 2 / dwp2dr
+    assert abs(w.mean() / closed - 1) < 1e-12
+    if M == 0.0:
+        # radiated power of a spherical conversion surface in the standard 1-D resonant picture:
+        # 4 pi r_c^2 * (pi/2) g^2 B^2 / (v_c |w_p'|) * rho_c v_c with rho_c = n_c m_a
+        wpprime = 1.5 * ma / rc / (1 / hc)
+        hook = 4 * math.pi * (rc / hc) ** 2 * 0.5 * math.pi * g ** 2 * B ** 2 * n_c * ma / wpprime
+        assert abs(w.mean() / hook - 1) < 2 * v0 ** 2
+
+
+def test_flat_anisotropic_weight_from_printed_probability(orc):
+    """M = 0: the oracle's cancelled form C_k n_c Vt Q must equal the paper's flat-space pieces
+    multiplied out literally: eq. (LOEnergy) for E, eq. (CPStrongB) for P_ag with
+    |v_a . grad E|, the flux projection cos(theta_n) v_a w of eq. (dPFlat), and the
+    surface measure from a numerical gradient of the resonance function."""
+    s = W.star(M_Msun=0.0, theta_m=0.0, plasma=W.PLASMA_ANISO, m_a_eV=2e-5, kdir=W.KDIR_ISOTROPIC)
+    c = orc.constants()
+    rays, st = orc.sample(s, 3, 64)
+    v0 = s["v0_kms"] / c["c_kms"]
+    ma = s["m_a_eV"]
+    w_inf = ma * math.sqrt(1 + v0 ** 2)
+    hc = c["hbarc_eVkm"]
+    g = 1e-12 * 1e-9
+    G2 = c["gauss_eV2"]
+    checked = 0
+    for i in np.nonzero(st == 0)[0][:20]:
+        x = rays[:3, i]
+        t0 = rays[3, i]
+        k = rays[4:7, i] * w_inf  # eV
+        r = np.linalg.norm(x)
+
+        def E_of(xx):  # eq. (LOEnergy), flat space
+            wp2 = orc.wp2(s, xx, t0) * w_inf ** 2
+            B = orc.bfield(s, xx, t0)
+            cb = k @ B / np.linalg.norm(k) / np.linalg.norm(B)
+            kk = k @ k
+            return math.sqrt(0.5 * (wp2 + kk + math.sqrt(kk ** 2 + wp2 ** 2 + 2 * kk * wp2 * (1 - 2 * cb ** 2))))
+
+        E = E_of(x)
+        assert abs(E / w_inf - 1) < 1e-12
+        hstep = 1e-4
+        gradE = np.array([(E_of(x + hstep * e) - E_of(x - hstep * e)) / (2 * hstep) for e in np.eye(3)]) * hc
+        B = orc.bfield(s, x, t0)
+        cb = k @ B / np.linalg.norm(k) / np.linalg.norm(B)
+        wp2 = orc.wp2(s, x, t0) * w_inf ** 2
+        Bm2 = (B @ B) * G2 ** 2
+        va = k / E
+        P = 0.5 * math.pi * g ** 2 * Bm2 * E ** 4 * (1 - cb ** 2) / (cb ** 2 * wp2 * (wp2 - 2 * E ** 2) + E ** 4) \
+            / abs(va @ gradE)
+        cos_n = (k @ gradE) / np.linalg.norm(k) / np.linalg.norm(gradE)
+        Q = abs(cos_n) * np.linalg.norm(va) * E * P
+        # surface measure: r^2 sqrt(1 + |grad_perp F|^2 / F_r^2) with F the resonance function
+        kh = k / np.linalg.norm(k)
+
+        def F_of(xx):
+            return E_of_shell(xx) - 0.0
+
+        def E_of_shell(xx):  # photon H evaluated on the axion momentum (zero on the surface)
+            return orc.hamiltonian(s, _axion_photon_state(s, xx, kh, t0))
+
+        gF = np.array([(F_of(x + hstep * e) - F_of(x - hstep * e)) / (2 * hstep) for e in np.eye(3)])
+        n = x / r
+        Fr = gF @ n
+        gperp = gF - Fr * n
+        V = r ** 2 * math.sqrt(1 + gperp @ gperp / Fr ** 2) / hc ** 2
+        n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+        w = 4 * math.pi * n_inf * V * Q
+        assert abs(w / rays[8, i] - 1) < 2e-6, (w, rays[8, i])
+        checked += 1
+    assert checked >= 10
+
+
+# ---------------------------------------------------------------- integrator
+def test_dopri_convergence_orders(orc):
+    # fixed steps: global error of order 5
+    errs = []
+    for h in (0.1, 0.05):
+        y, _, _, dense = orc.dopri_test(0, 1e-8, 1e-12, 2.0, h_fixed=h)
+        exact = np.concatenate([np.sin(np.array([1, 2, 3, 0.5]) * 2.0), np.cos(np.array([1, 2, 3, 0.5]) * 2.0)])
+        errs.append((np.abs(y - exact).max(), dense))
+    order = math.log2(errs[0][0] / errs[1][0])
+    assert 4.6 < order < 5.5, order
+    # continuous extension: local error O(h^5) (4th-order interpolant)
+    dorder = math.log2(errs[0][1] / errs[1][1])
+    assert 4.5 < dorder < 5.6, dorder
+    # adaptive: error follows the tolerance
+    e = []
+    for tol in (1e-6, 1e-9):
+        y, na, nr, _ = orc.dopri_test(1, tol, tol * 1e-3, 3.0)
+        exact = np.exp(np.array([1, -1, 0.5, -0.5, 2, -2, 0.25, 0]) * 3.0)
+        e.append(np.abs((y - exact) / exact).max())
+    assert e[1] < e[0] * 1e-2
+    assert e[1] < 1e-7
+
+
+def _trace_state(orc, s, t, y0):
+    rays = np.zeros((10, 1))
+    rays[:8, 0] = y0
+    fin, ifin = orc.trace_forward(s, t, rays)
+    return fin[:, 0], ifin[:, 0]
+
+
+def test_flat_vacuum_straight_lines(orc):
+    s = W.star(M_Msun=0.0, density=W.DENSITY_NONE, plasma=W.PLASMA_ISO)
+    t = W.tol()
+    rng = np.random.default_rng(19)
+    for _ in range(10):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(20, 50)
+        kdir = rng.normal(size=3)
+        kdir /= np.linalg.norm(kdir)
+        if kdir @ x < 0:
+            kdir = -kdir
+        y0 = np.concatenate([x, [0.0], kdir, [-1.0]])
+        fin, ifin = _trace_state(orc, s, t, y0)
+        assert ifin[2] == W.STATUS_ESCAPED
+        v = fin[4:7] / np.linalg.norm(fin[4:7])
+        assert np.abs(v - kdir).max() < 1e-15
+        # the end point lies on the straight line through x along kdir
+        d = fin[:3] - x
+        assert np.linalg.norm(np.cross(d, kdir)) < 1e-9 * np.linalg.norm(d)
+        assert abs(np.linalg.norm(fin[:3]) / 1e4 - 1) < 1e-12
+
+
+def _periapsis_state(s, r0, rs, wp2_r0):
+    A = 1 - rs / r0
+    kap = math.sqrt(1 / A - wp2_r0)
+    return np.array([r0, 0, 0, 0, 0, kap, 0, -1.0]), r0 * kap
+
+
+@pytest.mark.parametrize("M,density", [(1.4, W.DENSITY_NONE), (0.0, W.DENSITY_SPHERICAL),
+                                       (1.4, W.DENSITY_SPHERICAL)])
+def test_orbit_angle_matches_quadrature(orc, M, density):
+    """Position angle phi(r_max) of a ray started tangentially at periapsis r0 equals
+    int_{r0}^{r_max} L dr / (r^2 sqrt(A (1/A - w_p^2 - L^2/r^2))), from H = 0 with conserved
+    k_t = -1 and L = k_phi (Schwarzschild null geodesic when w_p = 0)."""
+    s = W.star(M_Msun=M, density=density, plasma=W.PLASMA_ISO, m_a_eV=1e-5, multiplicity=1.0)
+    t = W.tol(rtol=1e-12, atol=1e-15)
+    c = orc.constants()
+    rs = 2 * c["GMsun_km"] * M
+    r0 = 45.0  # outside the cut-off w_p = w of the spherical profile (about 37 km)
+    wp2_r0 = orc.wp2(s, np.array([r0, 0, 0]), 0.0)
+    y0, L = _periapsis_state(s, r0, rs, wp2_r0)
+    fin, ifin = _trace_state(orc, s, t, y0)
+    assert ifin[2] == W.STATUS_ESCAPED
+    phi_trace = math.atan2(fin[1], fin[0])
+    mpmath.mp.dps = 30
+    wp2R3 = mpmath.mpf(wp2_r0) * r0 ** 3  # spherical profile: w_p^2 = wp2R3 / r^3
+    # the double-precision start state sits on the level H = eps (not exactly 0); using that
+    # level keeps r0 an exact turning point of the quadrature
+    kap = mpmath.mpf(y0[5])
+    L = r0 * kap
+    eps = kap ** 2 - 1 / (1 - rs / mpmath.mpf(r0)) + wp2R3 / r0 ** 3
+
+    def integrand(r):
+        A = 1 - rs / r
+        q = A * (1 / A + eps - wp2R3 / r ** 3 - L ** 2 / r ** 2)
+        return L / (r ** 2 * mpmath.sqrt(q)) if q > 0 else mpmath.mpf(0)
+
+    # substitute r = r0 + u^2 to remove the inverse-square-root endpoint singularity
+    val = mpmath.quad(lambda u: 2 * u * integrand(r0 + u ** 2), [0, 1, mpmath.sqrt(1e4 - r0)])
+    assert abs(phi_trace - float(val)) < 1e-9, (phi_trace, float(val))
+
+
+def test_conserved_quantities(orc):
+    # aligned, static: k_t bit-constant and L_z conserved
+    cfg = W.CFG1
+    rays, st = orc.sample(cfg["star"], 0, 200)
+    fin, ifin = orc.trace_forward(cfg["star"], cfg["tol"], rays, st)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    assert np.all(fin[7][esc] == -1.0)
+    Lz0 = rays[0] * rays[5] - rays[1] * rays[4]
+    Lz1 = fin[0] * fin[5] - fin[1] * fin[4]
+    assert np.abs(Lz1 - Lz0)[esc].max() < 1e-5 * np.abs(Lz0[esc]).max()
+    # spherical plasma: the full angular momentum x cross k is conserved
+    s = W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO, weights=W.WEIGHTS_UNIT)
+    rays, st = orc.sample(s, 1, 100)
+    fin, ifin = orc.trace_forward(s, W.tol(), rays, st)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    L0 = np.cross(rays[:3].T, rays[4:7].T)
+    L1 = np.cross(fin[:3].T, fin[4:7].T)
+    assert np.abs(L1 - L0)[esc].max() < 1e-5 * np.abs(L0).max()
+
+
+def test_health_and_terminal_location(orc):
+    cfg = W.CFG2
+    rays, st = orc.sample(cfg["star"], 0, 256)
+    fin, ifin = orc.trace_forward(cfg["star"], cfg["tol"], rays, st)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    assert esc.sum() > 150
+    assert np.abs(fin[14][esc] / 1e4 - 1).max() < 1e-12
+    assert np.abs(fin[12][esc]).max() < 1e-4
+    assert np.median(np.abs(fin[12][esc])) < 1e-6
+
+
+def test_time_reversal_returns_to_seed(orc):
+    """Sec. 2.4: rays traced backward from the end state of a forward trace retrace the
+    same worldline back to the emission point."""
+    cfg = W.CFG2
+    t = W.tol(rtol=1e-11, atol=1e-14)
+    rays, st = orc.sample(cfg["star"], 0, 64)
+    ok = np.nonzero(st == 0)[0][:16]
+    fin, ifin = orc.trace_forward(cfg["star"], t, rays[:, ok], st[ok])
+    esc = ifin[2] == W.STATUS_ESCAPED
+    back, bif = orc.trace_reverse(cfg["star"], t, fin[:8, esc], fin[13, esc])
+    d = np.linalg.norm(back[:3] - rays[:3][:, ok][:, esc], axis=0)
+    assert d.max() < 1e-5, d.max()
+
+
+def test_binning_matches_numpy(orc):
+    cfg = W.CFG1
+    rays, st = orc.sample(cfg["star"], 0, 1024)
+    fin, ifin = orc.trace_forward(cfg["star"], cfg["tol"], rays, st)
+    hist, cnt, over = orc.bin_flux(fin, ifin, rays[8], cfg["bins"])
+    b = cfg["bins"]
+    esc = ifin[2] == W.STATUS_ESCAPED
+    it = np.minimum((fin[8][esc] / (math.pi / b["n_theta"])).astype(int), b["n_theta"] - 1)
+    ip = np.minimum((fin[10][esc] / (2 * math.pi / b["n_psi"])).astype(int), b["n_psi"] - 1)
+    iw = np.floor((fin[11][esc] - 1) / b["d_omega"] + 0.5).astype(int) + b["n_omega"] // 2
+    ref = np.zeros_like(hist)
+    np.add.at(ref, (it, ip, iw), rays[8][esc])
+    assert np.allclose(hist, ref, rtol=1e-14, atol=0)
+    assert cnt.sum() == esc.sum()
+    assert abs(hist.sum() - rays[8][esc].sum()) <= 1e-12 * rays[8][esc].sum()
+    assert np.all(iw == b["n_omega"] // 2)  # static star: every ray at the line centre
+
+
+def test_backward_events_on_spherical_resonance(orc):
+    """Isotropic spherical plasma around a Schwarzschild star: the production condition
+    k^gamma = k^a reduces to w_p = m_a, a sphere of closed-form radius; every recorded event
+    sits on it and a ray that enters and leaves records exactly two crossings with zero
+    Doppler shift.  (Without gravity the rays turn around just outside this sphere, the
+    difficulty Sec. 2.3 describes for backward tracing in flat space.)"""
+    s = W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO, m_a_eV=1e-5)
+    c = orc.constants()
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    rc = 10.0 * (c["wp2_per_ne"] * n0 / s["m_a_eV"] ** 2) ** (1 / 3)
+    image = dict(D_km=1e5, incl=1.0, phi_o=0.3, half_width_km=20.0, nx=16, ny=16)
+    # tight tolerance: G = H - w_p^2 + m_a^2, so the event radius inherits the drift of H
+    ev, nev, fin, ifin = orc.trace_backward(s, W.tol(r_max_km=1e5, rtol=1e-12, atol=1e-15), image, K=8)
+    hit = nev > 0
+    assert hit.sum() >= 8
+    for q in np.nonzero(hit)[0]:
+        for e in range(min(nev[q], 8)):
+            r = np.linalg.norm(ev[e, :3, q])
+            assert abs(r / rc - 1) < 1e-9
+            assert ev[e, 8, q] == 0.0
+        if ifin[2, q] == W.STATUS_ESCAPED:
+            assert nev[q] == 2

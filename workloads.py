@@ -1,0 +1,111 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the benchmark.
+
+This module holds parameter sets only (star, plasma, axion, tolerances, bins,
+image plane, instance grids).  It contains none of the ray-tracing arithmetic,
+so both the GPU path and the CPU oracle can take their inputs from it without
+sharing any of the method's code.
+
+Physical parameters follow the fiducial set of the paper (Sec. 5): coupling
+g = 1e-12 GeV^-1, dark-matter density 0.45 GeV cm^-3, axion speed 220 km/s,
+R = 10 km; each workload states its own deviations.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# enumerations of the star/plasma description (same numbering on both sides of the
+# boundary; they are part of the interface)
+PLASMA_ISO, PLASMA_ANISO = 0, 1
+DENSITY_GJ, DENSITY_MAGNETAR, DENSITY_SPHERICAL, DENSITY_NONE = 0, 1, 2, 3
+WEIGHTS_UNIT, WEIGHTS_CONVERSION, WEIGHTS_CONST_B = 0, 1, 2
+KDIR_ISOTROPIC, KDIR_OUTWARD = 0, 1
+
+STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
+STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE = 4, 5, 6
+
+FIDUCIAL = dict(
+    B0_G=1e14, P_s=1.0, theta_m=0.0, M_Msun=1.0, R_km=10.0, m_a_eV=1e-5,
+    g_agg_GeV=1e-12, v0_kms=220.0, rho_GeVcm3=0.45, multiplicity=1.0, psi_twist=0.2,
+    B_test_G=1e12, plasma=PLASMA_ANISO, density=DENSITY_GJ, weights=WEIGHTS_CONVERSION,
+    kdir=KDIR_ISOTROPIC,
+)
+
+TOL = dict(rtol=1e-8, atol=1e-12, r_max_km=1e4, max_steps=1 << 20)
+
+
+def star(**over) -> dict:
+    s = copy.deepcopy(FIDUCIAL)
+    for k, v in over.items():
+        if k not in s:
+            raise KeyError(f"unknown star field {k}")
+        s[k] = v
+    return s
+
+
+def tol(**over) -> dict:
+    t = dict(TOL)
+    t.update(over)
+    return t
+
+
+# -- the five workloads ------------------------------------------------------------------
+# 1: plain forward trace, small: flat metric, aligned dipole, isotropic plasma,
+#    outward axion directions, 32 x 64 x 32 bins.
+CFG1 = dict(
+    name="forward-small-flat-iso-4096",
+    star=star(M_Msun=0.0, theta_m=0.0, plasma=PLASMA_ISO, m_a_eV=1e-5, kdir=KDIR_OUTWARD),
+    tol=tol(), n=4096, seed=0,
+    bins=dict(n_theta=32, n_psi=64, n_omega=32, d_omega=6.25e-5),
+)
+# 2: full forward trace: Schwarzschild M = 1.4, oblique rotator, anisotropic LO plasma.
+CFG2 = dict(
+    name="forward-full-gr-aniso-oblique-1e6",
+    star=star(M_Msun=1.4, theta_m=0.3, plasma=PLASMA_ANISO, m_a_eV=2e-5, kdir=KDIR_ISOTROPIC),
+    tol=tol(), n=1_000_000, seed=0,
+    bins=dict(n_theta=64, n_psi=128, n_omega=64, d_omega=3.125e-5),
+)
+# 3: backward image: 1024^2 pixels at 1e5 km, inclination 60 deg, magnetar-like star
+#    with the twisted-magnetosphere density (model M1: lambda = 1, psi = 0.2).
+CFG3 = dict(
+    name="backward-image-1024sq-magnetar",
+    star=star(B0_G=1.6e14, P_s=3.76, theta_m=0.5, M_Msun=1.4, plasma=PLASMA_ANISO,
+              density=DENSITY_MAGNETAR, m_a_eV=1e-4, multiplicity=1.0, psi_twist=0.2),
+    tol=tol(r_max_km=1e5),
+    image=dict(D_km=1e5, incl=math.radians(60.0), phi_o=0.0, half_width_km=80.0, nx=1024, ny=1024),
+    K=8,
+)
+# 5: adjoint: config-1 rays, Gaussian-smoothed flux at 32 observers.
+CFG5 = dict(
+    name="adjoint-smoothed-flux-1e6",
+    star=CFG1["star"], tol=tol(), n=1_000_000, seed=0, n_obs=32, sigma=0.02, ckpt_every=64,
+)
+
+
+def observers(n_obs: int = 32) -> np.ndarray:
+    """Observer directions in the (x, z) plane at polar angles (j + 1/2) pi / n_obs."""
+    th = (np.arange(n_obs) + 0.5) * math.pi / n_obs
+    return np.stack([np.sin(th), np.zeros_like(th), np.cos(th)], axis=1)
+
+
+def batched_instances(n_inst: int = 256, seed: int = 1, n_lo: float = 1e4, n_hi: float = 2e5):
+    """Config 4: 16 axion masses (log-spaced over [1e-6, 1e-4] eV) x 16 inclinations
+    (linear over [0, 1.2] rad) of the config-1 star; ray counts log-uniform over
+    [n_lo, n_hi] drawn with numpy's PCG64 seeded `seed`."""
+    side = int(round(math.sqrt(n_inst)))
+    rng = np.random.default_rng(seed)
+    u = rng.random(n_inst)
+    counts = np.floor(np.exp(math.log(n_lo) + u * (math.log(n_hi) - math.log(n_lo)))).astype(np.int64)
+    stars = []
+    for k in range(n_inst):
+        ia, it = k % side, k // side
+        ma = 10.0 ** (-6.0 + 2.0 * ia / (side - 1))
+        thm = 1.2 * it / (side - 1)
+        stars.append(star(M_Msun=0.0, theta_m=thm, plasma=PLASMA_ISO, m_a_eV=ma, kdir=KDIR_OUTWARD))
+    return stars, counts
+
+
+CFG4 = dict(name="batched-256-instances", n_inst=256, seed=1, bins=dict(n_theta=64, n_psi=128, n_omega=1,
+                                                                        d_omega=1.0))
