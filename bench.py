@@ -1,0 +1,160 @@
+"""Throughput of the ray-tracing hot path on one MI355X.
+
+One step = one pass of the forward hot path over one batch of synthetic input:
+resonance seeding (rt_sample_resonance) -> adaptive FP64 DOPRI5 tracing to r_max
+(rt_trace_forward) -> sky/frequency binning (rt_bin_flux), on the full forward
+workload: 1e6 rays, Schwarzschild M = 1.4 Msun, oblique rotator theta_m = 0.3,
+anisotropic strongly magnetised plasma (LO mode), GJ density, m_a = 2e-5 eV,
+64 x 128 x 64 bins, rtol 1e-8.
+
+Prints one JSON line: value = accepted ray-steps per second of the whole step
+(whole-job throughput, inputs resident in HBM); rays/s alongside; the roofline of
+the dominant kernel (the persistent tracing kernel, FP64 vector ALU bound); and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, AMD published (256 CU x 128 FLOP/clk x 2.4 GHz)
+
+
+def variant_key(star):
+    pl = "iso" if star["plasma"] == 0 else "aniso"
+    de = ["gj", "magnetar", "spherical", "none"][star["density"]]
+    ob = "oblique" if math.sin(star["theta_m"]) != 0.0 else "aligned"
+    return f"{pl}_{de}_{ob}"
+
+
+def flop_table():
+    with open(os.path.join(ROOT, "paper_2309_08655_amd", "flops.json")) as f:
+        return json.load(f)
+
+
+def cpu_baseline(cfg, n_sample, threads):
+    """The oracle as it stands, on the first n_sample rays of the same workload."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    rays, st = oracle.sample(cfg["star"], cfg["seed"], n_sample, nthreads=threads)
+    fin, ifin = oracle.trace_forward(cfg["star"], cfg["tol"], rays, st, nthreads=threads)
+    oracle.bin_flux(fin, ifin, rays[8], cfg["bins"])
+    dt = time.perf_counter() - t0
+    steps = float(ifin[0].sum())
+    return dict(value=steps / dt, unit="ray-steps/s", cores=threads, kind="oracle",
+                sample=f"first {n_sample} rays of the same workload (seed, trace, bin), {dt:.2f} s, "
+                       f"rays/s {float((st == 0).sum()) / dt:.4g}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="rays per step (default: the workload's 1e6)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the tracer shards rays across GPUs by index with no "
+              "communication until one histogram all-reduce, which this build does not run; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2309_08655_amd as rt
+    import workloads as W
+
+    cfg = dict(W.CFG2)
+    n = args.n or cfg["n"]
+    sched = json.loads(args.schedule) if args.schedule else None
+    dev = torch.device("cuda")
+    rays = torch.empty((10, n), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    fin = torch.empty((rt.RT_NFIN, n), dtype=torch.float64, device=dev)
+    ifin = torch.empty((rt.RT_NIFIN, n), dtype=torch.int32, device=dev)
+    ws = rt.workspace(rt.OP_TRACE_FORWARD, n)
+    wsb = rt.workspace(rt.OP_BIN, n)
+    b = cfg["bins"]
+    hist = torch.empty((1, b["n_theta"], b["n_psi"], b["n_omega"]), dtype=torch.float64, device=dev)
+    cnt = torch.empty_like(hist)
+    over = torch.empty(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    ev_trace = []
+
+    def step(record=False):
+        rt.rt_sample_resonance(cfg["star"], cfg["seed"], n, rays=rays, status=status)
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, status, schedule=sched, ws=ws, fin=fin, ifin=ifin)
+        if record:
+            e1.record(stream)
+            ev_trace.append((e0, e1))
+        rt.rt_bin_flux(fin, ifin, rays[8], b, ws=wsb, hist=hist, cnt=cnt, over=over)
+
+    print(f"bench: {cfg['name']} n={n} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(record=True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_step = total_ms / args.steps
+    trace_ms = float(np.mean([a.elapsed_time(bb) for a, bb in ev_trace]))
+
+    ifn = ifin.cpu().numpy()
+    stn = status.cpu().numpy()
+    acc = float(ifn[0].astype(np.float64).sum())
+    rej = float(ifn[1].astype(np.float64).sum())
+    n_traced = float((stn == 0).sum())
+    steps_per_s = acc / (ms_step * 1e-3)
+    rays_per_s = n_traced / (ms_step * 1e-3)
+
+    ft = flop_table()[variant_key(cfg["star"])]
+    # algorithmic work of one rt_trace_forward launch: every attempted step costs one DOPRI5
+    # attempt; the init pass costs 2 right-hand sides per traced ray (FSAL derivative and the
+    # starting-step probe)
+    flops = (acc + rej) * ft["attempt"] + n_traced * 2 * ft["rhs"]
+    achieved_tflops = flops / (trace_ms * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=achieved_tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
+                    kernel="rt_trace_forward (trace_init_kernel + trace_fwd_kernel)",
+                    trace_ms=trace_ms, flop_per_attempt=ft["attempt"], flop_per_rhs=ft["rhs"],
+                    attempted_steps=acc + rej)
+    out = dict(metric="ray-steps/s and rays/s at rtol 1e-8 (FP64), plain vs batched vs adjoint",
+               value=steps_per_s, unit="ray-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload=cfg["name"], rays_per_step=n, form="plain",
+                           rays_per_s=rays_per_s, accepted_steps=acc, rejected_steps=rej,
+                           statuses={str(k): int(v) for k, v in zip(*np.unique(ifn[2], return_counts=True))}),
+               roofline=roofline)
+    if not args.no_cpu:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/* rt.h -- C ABI of the MI355X (gfx950) ray tracer for axion-photon conversion
+ * around neutron stars (McDonald & Witte, "Generalized Ray Tracing for Axions
+ * in Astrophysical Plasmas", arXiv:2309.08655).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers to caller-owned, contiguous memory in
+ *   structure-of-arrays layout: a "[F][n]" array holds field F of ray i at
+ *   element F*n + i.  Struct arguments (rt_star, rt_tol, ...) are HOST memory,
+ *   read during the call and not retained.
+ * - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *   NULL = the default stream).  No call allocates device memory, frees it or
+ *   synchronises; scratch memory comes from a caller workspace whose size
+ *   rt_workspace_size() reports.
+ * - Return value: RT_OK (0) or a negative code.  Arguments are validated on the
+ *   host before anything is launched; on error nothing is launched and
+ *   rt_last_error() returns a message (thread-local).
+ * - Per-ray outcomes are reported in status arrays (RT_ST_*), never as errors.
+ * - Integrator units: lengths and times in km, covariant momentum in units of
+ *   the axion energy at infinity w_inf = m_a sqrt(1 + v0^2) (so k_t = -1 at
+ *   emission).  State order: (x, y, z, t, k_x, k_y, k_z, k_t), Cartesian chart
+ *   of the Schwarzschild metric (x = r n with r the areal radius).
+ * - Calls that overlap on one stream-ordered workspace race; distinct
+ *   workspaces may run concurrently.
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RT_OK = 0, RT_EINVAL = -1, RT_EHIP = -2, RT_ENOWS = -3, RT_EUNSUPPORTED = -4 };
+
+/* per-ray status */
+enum { RT_ST_OK = 0, RT_ST_ESCAPED = 1, RT_ST_HIT_STAR = 2, RT_ST_NO_RESONANCE = 3,
+       RT_ST_MAX_STEPS = 4, RT_ST_STEP_UNDERFLOW = 5, RT_ST_NONFINITE = 6 };
+
+enum { RT_PLASMA_ISO = 0, RT_PLASMA_ANISO = 1 };                /* Sec. 4.1 */
+enum { RT_DENSITY_GJ = 0, RT_DENSITY_MAGNETAR = 1,              /* eqs. (GJDensity), (neMag) */
+       RT_DENSITY_SPHERICAL = 2, RT_DENSITY_NONE = 3 };         /* test profiles */
+enum { RT_WEIGHTS_UNIT = 0, RT_WEIGHTS_CONVERSION = 1, RT_WEIGHTS_CONST_B = 2 };
+enum { RT_KDIR_ISOTROPIC = 0, RT_KDIR_OUTWARD = 1 };
+
+/* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
+typedef struct rt_star {
+    double B0_G;          /* polar surface dipole field [G] */
+    double P_s;           /* rotation period [s] */
+    double theta_m;       /* angle between magnetic and rotation axes [rad] */
+    double M_Msun;        /* stellar mass [M_sun]; 0 = flat spacetime */
+    double R_km;          /* stellar radius [km] */
+    double m_a_eV;        /* axion mass [eV] */
+    double g_agg_GeV;     /* axion-photon coupling [GeV^-1] */
+    double v0_kms;        /* axion speed at infinity [km/s] */
+    double rho_GeVcm3;    /* dark-matter density at infinity [GeV cm^-3] */
+    double multiplicity;  /* charge multiplicity lambda */
+    double psi_twist;     /* magnetar twist psi (RT_DENSITY_MAGNETAR) */
+    double B_test_G;      /* constant |B_perp| used by RT_WEIGHTS_CONST_B [G] */
+    int32_t plasma;       /* RT_PLASMA_* */
+    int32_t density;      /* RT_DENSITY_* */
+    int32_t weights;      /* RT_WEIGHTS_* */
+    int32_t kdir;         /* RT_KDIR_*: axion directions isotropic or in the outward hemisphere */
+} rt_star;
+
+/* Integrator tolerances: embedded DOPRI5 error test with scale atol + rtol max(|y|,|y_new|)
+   over all 8 components; rays stop at r = r_max_km (located on the continuous extension). */
+typedef struct rt_tol {
+    double rtol, atol, r_max_km;
+    int64_t max_steps;    /* accepted steps per ray before RT_ST_MAX_STEPS */
+} rt_tol;
+
+/* Sky binning (Sec. 2.2, the top-hat window D): n_theta bins of pi/n_theta in the polar
+   angle, n_psi bins of 2 pi/n_psi in the co-rotating azimuth, n_omega bins of width
+   d_omega in (w_f - 1) with the line centre w_f = 1 at the centre of bin n_omega/2. */
+typedef struct rt_bins {
+    int32_t n_theta, n_psi, n_omega;
+    double d_omega;
+} rt_bins;
+
+/* Image plane of the backward tracer (Sec. 2.1): nx x ny square pixels of side
+   2 half_width_km / nx centred on the line of sight at distance D_km, observer at polar
+   angle incl and azimuth phi_o. */
+typedef struct rt_image {
+    double D_km, incl, phi_o, half_width_km;
+    int32_t nx, ny;
+} rt_image;
+
+/* Launch schedule of the persistent tracing kernels (chosen by the autotuner). */
+typedef struct rt_schedule {
+    int32_t block;        /* threads per workgroup: 64, 128 or 256 */
+    int32_t waves_per_cu; /* resident waves per CU requested (0 = occupancy limit) */
+    int32_t refill_min;   /* idle lanes a wave waits for before refilling from the queue */
+    int32_t chunk;        /* queue entries taken per refilled lane (reserved, 1) */
+} rt_schedule;
+
+/* Number of doubles / int32 per final record (fin: "[RT_NFIN][n]", ifin: "[RT_NIFIN][n]"):
+   fin  = x, y, z, t, k_x, k_y, k_z, k_t (final state), theta, phi, psi (co-rotating
+          azimuth in [0, 2 pi)), omega (= -k_t), H, lambda, r, h_next
+   ifin = accepted steps, rejected steps, status */
+#define RT_NFIN 16
+#define RT_NIFIN 3
+/* backward event record: x, y, z, t, k_x, k_y, k_z, k_t, Doppler ratio (-k_t - 1),
+   local frequency (-k_t / sqrt(A)) */
+#define RT_NEV 10
+
+enum { RT_OP_TRACE_FORWARD = 1, RT_OP_TRACE_BACKWARD = 2, RT_OP_BIN = 3, RT_OP_BATCHED = 4,
+       RT_OP_FLUX_GRAD = 5 };
+
+/* rt_sample_resonance -- seed forward rays on the resonance foliation and weight them
+ * (Sec. 2.2 eq. (Power); Sec. 3 eqs. (Hypersurfaces), (ForwardTracingEquation1);
+ *  Sec. 4.2 eq. (PowerCurved); Sec. 4.3 eq. (fa_approx); Sec. 4.4 eqs. (ProbIsoCurved),
+ *  (CPAnisoCurved)).
+ * Ray i (global index first + j) draws Philox4x32-10 uniforms with key = seed and counter
+ * (i, instance, block); emission direction uniform in (cos theta, phi), axion direction
+ * isotropic (or outward hemisphere), emission time uniform over one period.  The photon
+ * takes the axion's 4-momentum where the kinematic matching k^a = k^gamma holds.
+ * Output rays "[10][n]": x, y, z, t, k_x, k_y, k_z, k_t, w, r_c; status[n] = RT_ST_OK or
+ * RT_ST_NO_RESONANCE (then w = 0).  The unbiased power estimate is (1/n) sum w [eV^2].
+ * Errors: RT_EINVAL for n < 0, null arrays or non-finite / out-of-range parameters. */
+int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t instance, int64_t first, int64_t n,
+                        double* rays, int32_t* status, void* stream);
+
+/* rt_trace_forward -- integrate Hamilton's equations (Sec. 2 eq. (Hamilton)) with the
+ * strong-field Hamiltonian (Sec. 4.1 eq. (StrongBHam)) from each seed to r = r_max with
+ * adaptive FP64 Dormand-Prince 5(4), one ray per lane in a persistent work-queue kernel.
+ * rays "[>=8][n]" (only the first 8 fields are read), status[n] (rays with status != OK are
+ * copied through untraced).  Output fin "[RT_NFIN][n]", ifin "[RT_NIFIN][n]".
+ * Workspace: rt_workspace_size(RT_OP_TRACE_FORWARD, n) bytes, device memory.
+ * sched may be NULL (defaults).  Errors: RT_EINVAL, RT_ENOWS (workspace too small). */
+int rt_trace_forward(const rt_star* star, const rt_tol* tol, const double* rays, const int32_t* status,
+                     int64_t n, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
+                     const rt_schedule* sched, void* stream);
+
+/* rt_bin_flux -- top-hat sky/frequency binning of escaped rays (Sec. 2.2): hist and cnt are
+ * "[n_theta][n_psi][n_omega]" (sum of w and ray count, both double, overwritten), over[2]
+ * = (weight, count) of escaped rays outside the frequency range.  Bins are privatised in
+ * LDS tiles and merged with FP64 atomics, so sums are exact up to summation order.
+ * inst_offset: NULL for one instance, else a DEVICE array of n_inst + 1 ray offsets and
+ * hist/cnt hold n_inst consecutive maps.  Workspace: rt_workspace_size(RT_OP_BIN, n). */
+int rt_bin_flux(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
+                const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* rt_trace_backward -- trace the nx x ny parallel rays of an image plane backwards in the
+ * worldline parameter (Sec. 2.1; Sec. 2.3 for the role of gravity) through every level
+ * crossing k^gamma = k^a (sign change of G = g^{mu nu} k_mu k_nu + m_a^2, Sec. 3), until the
+ * ray hits the star or recedes beyond 1.01 D.  k_t = -1 (monochromatic, Sec. 4.3), |k| from
+ * the LO branch of eq. (AnisotropicDisp).  Events are sampled at 1/4, 1/2, 3/4 and 1 of
+ * every accepted step and bisected on the continuous extension.
+ * Output: ev "[K][RT_NEV][nx*ny]" (first K events per pixel, pixel index i*ny + j),
+ * nev[nx*ny] (all crossings, may exceed K), fin/ifin as for rt_trace_forward.
+ * Workspace: rt_workspace_size(RT_OP_TRACE_BACKWARD, nx*ny). */
+int rt_trace_backward(const rt_star* star, const rt_tol* tol, const rt_image* image, int32_t K, double* ev,
+                      int32_t* nev, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
+                      const rt_schedule* sched, void* stream);
+
+/* rt_trace_batched -- many star instances in one persistent launch (seeding, tracing and
+ * per-instance binning), for parameter scans.  stars: HOST array of n_inst rt_star sharing
+ * plasma/density/weights/kdir; ray_offset: HOST array of n_inst + 1 prefix offsets (instance
+ * k owns global rays [ray_offset[k], ray_offset[k+1]) and draws Philox counter
+ * (i - ray_offset[k], k)).  rays "[10][N]", fin, ifin as above for N = ray_offset[n_inst];
+ * maps/cnt "[n_inst][n_theta][n_psi][n_omega]".  One call issues a fixed sequence of
+ * kernels (no host synchronisation), so it can be captured into a hipGraph.
+ * Workspace: rt_workspace_size(RT_OP_BATCHED, N) + 16 n_inst + 64 bytes. */
+int rt_trace_batched(const rt_star* stars, int32_t n_inst, const int64_t* ray_offset, uint64_t seed,
+                     const rt_tol* tol, const rt_bins* bins, double* rays, int32_t* status, double* fin,
+                     int32_t* ifin, double* maps, double* cnt, void* ws, size_t ws_bytes,
+                     const rt_schedule* sched, void* stream);
+
+/* rt_flux_grad -- Gaussian-smoothed flux F_j = (1/n) sum_escaped w_i K(n_i . o_j),
+ * K(c) = exp((c - 1)/sigma^2)/(2 pi sigma^2), at n_obs observer directions, and its
+ * gradient with respect to p = (B0, P, theta_m, M, R, m_a) by a hand-written
+ * discretise-then-differentiate adjoint of the accepted DOPRI5 steps (steps frozen),
+ * including the seed root, the weights and the terminal-event location.
+ * phase 0 (forward): seeds, traces with a checkpoint of (y, h) every ckpt_every accepted
+ *   steps, writes flux[n_obs] (device).
+ * phase 1 (reverse): given gbar[n_obs] (device), recomputes each segment from its
+ *   checkpoint and sweeps back through the stages; writes grad[6] = sum_j gbar_j dF_j/dp
+ *   (device).  Needs the workspace of the forward phase unchanged.
+ * obs: HOST array "[n_obs][3]" of unit vectors.  Workspace:
+ *   rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt). */
+int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
+                 int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
+                 const double* gbar, double* flux, double* grad, void* ws, size_t ws_bytes, void* stream);
+
+size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int32_t max_ckpt);
+
+/* Workspace bytes needed by op (RT_OP_*) for n rays. */
+size_t rt_workspace_size(int32_t op, int64_t n);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* rt_last_error(void);
+
+/* Library build string (compiler, target). */
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_H */

@@ -701,7 +701,7 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
             ++nrej;
             h *= std::max(0.2, 0.9 * std::pow(err, -0.2));
             facmax = 1.0;
-            if (std::fabs(h) < 1e-14 * (1.0 + std::fabs(lam))) { o.status = ORC_STEP_UNDERFLOW; break; }
+            if (!(std::fabs(h) >= 1e-14 * (1.0 + std::fabs(lam)))) { o.status = ORC_STEP_UNDERFLOW; break; }
             continue;
         }
         // accepted
@@ -757,7 +757,7 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
                 o.status = ORC_MAX_STEPS;
                 break;
             }
-            if (std::fabs(h) < 1e-14 * (1.0 + std::fabs(lam))) {
+            if (!(std::fabs(h) >= 1e-14 * (1.0 + std::fabs(lam)))) {
                 for (int i = 0; i < 8; ++i) o.yf[i] = y[i];
                 o.status = ORC_STEP_UNDERFLOW;
                 break;
@@ -868,7 +868,7 @@ static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, 
             ++nrej;
             h *= std::max(0.2, 0.9 * std::pow(err, -0.2));
             facmax = 1.0;
-            if (std::fabs(h) < 1e-14 * (1.0 + std::fabs(lam))) { status = ORC_STEP_UNDERFLOW; break; }
+            if (!(std::fabs(h) >= 1e-14 * (1.0 + std::fabs(lam)))) { status = ORC_STEP_UNDERFLOW; break; }
             continue;
         }
         ++nacc;
@@ -914,7 +914,7 @@ static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, 
         h = cap(y, k1, h * fac);
         facmax = 10.0;
         if (nacc >= tol.max_steps) { status = ORC_MAX_STEPS; break; }
-        if (std::fabs(h) < 1e-14 * (1.0 + std::fabs(lam))) { status = ORC_STEP_UNDERFLOW; break; }
+        if (!(std::fabs(h) >= 1e-14 * (1.0 + std::fabs(lam)))) { status = ORC_STEP_UNDERFLOW; break; }
     }
     for (int d = 0; d < 8; ++d) yend[d] = y[d];
     nev[slot] = ne;

@@ -1,0 +1,211 @@
+"""Python binding of the gfx950 ray-tracing library (librt.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/rt.h.  PyTorch provides device
+memory and the current HIP stream.  The binding refuses to run when the
+library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librt.so")
+
+RT_NFIN, RT_NIFIN, RT_NEV = 16, 3, 10
+OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD = 1, 2, 3, 4, 5
+FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi", "omega", "H", "lam", "r", "h"]
+
+EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_batched",
+           "rt_flux_grad", "rt_flux_grad_workspace_size", "rt_workspace_size", "rt_last_error", "rt_version"]
+
+
+class RtStar(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV", "g_agg_GeV",
+                                          "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")] + \
+               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir")]
+
+
+class RtTol(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("r_max_km", C.c_double), ("max_steps", C.c_int64)]
+
+
+class RtBins(C.Structure):
+    _fields_ = [("n_theta", C.c_int32), ("n_psi", C.c_int32), ("n_omega", C.c_int32), ("d_omega", C.c_double)]
+
+
+class RtImage(C.Structure):
+    _fields_ = [("D_km", C.c_double), ("incl", C.c_double), ("phi_o", C.c_double), ("half_width_km", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+class RtSchedule(C.Structure):
+    _fields_ = [("block", C.c_int32), ("waves_per_cu", C.c_int32), ("refill_min", C.c_int32), ("chunk", C.c_int32)]
+
+
+class RtError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load librt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RtError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          f"(python -m paper_2309_08655_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, ip, lp = C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p
+        sp, tp = C.POINTER(RtStar), C.POINTER(RtTol)
+        L.rt_sample_resonance.argtypes = [sp, C.c_uint64, C.c_int32, C.c_int64, C.c_int64, dp, ip, vp]
+        L.rt_trace_forward.argtypes = [sp, tp, dp, ip, C.c_int64, dp, ip, vp, C.c_size_t,
+                                       C.POINTER(RtSchedule), vp]
+        L.rt_bin_flux.argtypes = [dp, ip, dp, C.c_int64, C.POINTER(RtBins), lp, C.c_int32, dp, dp, dp, vp,
+                                  C.c_size_t, vp]
+        L.rt_trace_backward.argtypes = [sp, tp, C.POINTER(RtImage), C.c_int32, dp, ip, dp, ip, vp, C.c_size_t,
+                                        C.POINTER(RtSchedule), vp]
+        L.rt_trace_batched.argtypes = [sp, C.c_int32, C.POINTER(C.c_int64), C.c_uint64, tp, C.POINTER(RtBins), dp,
+                                       ip, dp, ip, dp, dp, vp, C.c_size_t, C.POINTER(RtSchedule), vp]
+        L.rt_flux_grad.argtypes = [sp, tp, C.c_uint64, C.c_int64, C.POINTER(C.c_double), C.c_int32, C.c_double,
+                                   C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, vp, C.c_size_t, vp]
+        L.rt_flux_grad_workspace_size.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+        L.rt_flux_grad_workspace_size.restype = C.c_size_t
+        L.rt_workspace_size.argtypes = [C.c_int32, C.c_int64]
+        L.rt_workspace_size.restype = C.c_size_t
+        L.rt_last_error.restype = C.c_char_p
+        L.rt_version.restype = C.c_char_p
+        for name in EXPORTS:
+            if not hasattr(L, name):
+                raise RtError(f"librt.so does not export {name}")
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().rt_last_error().decode()
+        raise RtError(f"{what} failed ({rc}): {msg}")
+
+
+def make_star(d: dict) -> RtStar:
+    s = RtStar()
+    for name, _ in RtStar._fields_:
+        setattr(s, name, d[name])
+    return s
+
+
+def make_tol(d: dict) -> RtTol:
+    return RtTol(d["rtol"], d["atol"], d["r_max_km"], int(d["max_steps"]))
+
+
+def make_bins(d: dict) -> RtBins:
+    return RtBins(d["n_theta"], d["n_psi"], d["n_omega"], d["d_omega"])
+
+
+def make_image(d: dict) -> RtImage:
+    return RtImage(d["D_km"], d["incl"], d["phi_o"], d["half_width_km"], d["nx"], d["ny"])
+
+
+def make_schedule(d: dict | None):
+    if d is None:
+        return None
+    return RtSchedule(d.get("block", 256), d.get("waves_per_cu", 0), d.get("refill_min", 16), d.get("chunk", 1))
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _device():
+    if not torch.cuda.is_available():
+        raise RtError("no HIP device visible: the ray tracer runs only on the GPU")
+    return torch.device("cuda")
+
+
+def workspace(op: int, n: int) -> torch.Tensor:
+    nbytes = max(int(lib().rt_workspace_size(op, n)), 256)
+    return torch.empty(nbytes, dtype=torch.uint8, device=_device())
+
+
+# --------------------------------------------------------------------------- entry points
+def rt_sample_resonance(star: dict, seed: int, n: int, instance: int = 0, first: int = 0, rays=None, status=None):
+    """Seed n forward rays: returns (rays[10, n] float64, status[n] int32) on the GPU."""
+    dev = _device()
+    rays = torch.empty((10, n), dtype=torch.float64, device=dev) if rays is None else rays
+    status = torch.empty(n, dtype=torch.int32, device=dev) if status is None else status
+    s = make_star(star)
+    _check(lib().rt_sample_resonance(C.byref(s), seed, instance, first, n, _ptr(rays), _ptr(status), _stream()),
+           "rt_sample_resonance")
+    return rays, status
+
+
+def rt_trace_forward(star: dict, tol: dict, rays: torch.Tensor, status: torch.Tensor | None = None,
+                     schedule: dict | None = None, ws: torch.Tensor | None = None, fin=None, ifin=None):
+    """Trace seeds to r_max: returns (fin[16, n] float64, ifin[3, n] int32)."""
+    dev = _device()
+    n = rays.shape[1]
+    rays = rays.contiguous()
+    if rays.shape[0] < 8:
+        raise RtError("rays must have at least 8 rows")
+    fin = torch.empty((RT_NFIN, n), dtype=torch.float64, device=dev) if fin is None else fin
+    ifin = torch.empty((RT_NIFIN, n), dtype=torch.int32, device=dev) if ifin is None else ifin
+    ws = workspace(OP_TRACE_FORWARD, n) if ws is None else ws
+    s, t = make_star(star), make_tol(tol)
+    sc = make_schedule(schedule)
+    # the kernels index rays as [field][n]: pass a view with exactly n columns
+    _check(lib().rt_trace_forward(C.byref(s), C.byref(t), _ptr(rays), _ptr(status), n, _ptr(fin), _ptr(ifin),
+                                  _ptr(ws), ws.numel(), C.byref(sc) if sc is not None else None, _stream()),
+           "rt_trace_forward")
+    return fin, ifin
+
+
+def rt_bin_flux(fin: torch.Tensor, ifin: torch.Tensor, w: torch.Tensor, bins: dict, inst_offset=None,
+                n_inst: int = 1, ws=None, hist=None, cnt=None, over=None):
+    dev = _device()
+    n = fin.shape[1]
+    nmaps = n_inst if inst_offset is not None else 1
+    shape = (nmaps, bins["n_theta"], bins["n_psi"], bins["n_omega"])
+    hist = torch.empty(shape, dtype=torch.float64, device=dev) if hist is None else hist
+    cnt = torch.empty(shape, dtype=torch.float64, device=dev) if cnt is None else cnt
+    over = torch.empty(2, dtype=torch.float64, device=dev) if over is None else over
+    ws = workspace(OP_BIN, n) if ws is None else ws
+    b = make_bins(bins)
+    _check(lib().rt_bin_flux(_ptr(fin), _ptr(ifin), _ptr(w.contiguous()), n, C.byref(b), _ptr(inst_offset),
+                             n_inst, _ptr(hist), _ptr(cnt), _ptr(over), _ptr(ws), ws.numel(), _stream()),
+           "rt_bin_flux")
+    if inst_offset is None:
+        return hist[0], cnt[0], over
+    return hist, cnt, over
+
+
+def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: dict | None = None, ws=None):
+    dev = _device()
+    n = image["nx"] * image["ny"]
+    ev = torch.empty((K, RT_NEV, n), dtype=torch.float64, device=dev)
+    nev = torch.empty(n, dtype=torch.int32, device=dev)
+    fin = torch.empty((RT_NFIN, n), dtype=torch.float64, device=dev)
+    ifin = torch.empty((RT_NIFIN, n), dtype=torch.int32, device=dev)
+    ws = workspace(OP_TRACE_BACKWARD, n) if ws is None else ws
+    s, t, im = make_star(star), make_tol(tol), make_image(image)
+    sc = make_schedule(schedule)
+    _check(lib().rt_trace_backward(C.byref(s), C.byref(t), C.byref(im), K, _ptr(ev), _ptr(nev), _ptr(fin),
+                                   _ptr(ifin), _ptr(ws), ws.numel(), C.byref(sc) if sc is not None else None,
+                                   _stream()), "rt_trace_backward")
+    return ev, nev, fin, ifin
+
+
+def version() -> str:
+    return lib().rt_version().decode()

@@ -1,0 +1,57 @@
+"""Build the gfx950 HIP library librt.so in-tree with hipcc."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "librt.so")
+SOURCES = ["rt_api.hip", "rt_forward.hip", "rt_pending.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-munsafe-fp-atomics",
+    # never emit packed FP32 arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+FLOPS_JSON = os.path.join(HERE, "flops.json")
+
+
+def build_flop_table(verbose: bool = False) -> str:
+    """Compile and run the host-side operation counter of the device templates
+    (csrc/flopcount.cpp) and store its table next to the library."""
+    exe = os.path.join(HERE, "_flopcount.bin")
+    cmd = [HIPCC, "-std=c++17", "-O1", "-o", exe, os.path.join(CSRC, "flopcount.cpp")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    json.loads(out)
+    with open(FLOPS_JSON, "w") as f:
+        f.write(out)
+    os.remove(exe)
+    return FLOPS_JSON
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    build_flop_table(verbose)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    print(LIB)

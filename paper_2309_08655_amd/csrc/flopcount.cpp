@@ -1,0 +1,77 @@
+// Static FP64 operation count of the tracer's arithmetic, obtained by running
+// the device templates (gradient of H, one DOPRI5 attempt) on the host with a
+// counting scalar.  Convention: +, -, x each 1; fused multiply-add 2; division,
+// reciprocal, square root, pow 1 each; sin and cos 1 each; negation, |.|,
+// max/min, comparisons 0.  Prints one JSON object keyed by the physics variant.
+#include <cmath>
+#include <cstdio>
+
+static long long g_flops = 0;
+
+struct FC {
+    double v;
+    FC() : v(0.0) {}
+    FC(double x) : v(x) {}
+};
+inline FC operator+(FC a, FC b) { ++g_flops; return FC(a.v + b.v); }
+inline FC operator-(FC a, FC b) { ++g_flops; return FC(a.v - b.v); }
+inline FC operator*(FC a, FC b) { ++g_flops; return FC(a.v * b.v); }
+inline FC operator/(FC a, FC b) { ++g_flops; return FC(a.v / b.v); }
+inline FC operator+(double a, FC b) { ++g_flops; return FC(a + b.v); }
+inline FC operator+(FC a, double b) { ++g_flops; return FC(a.v + b); }
+inline FC operator-(double a, FC b) { ++g_flops; return FC(a - b.v); }
+inline FC operator-(FC a, double b) { ++g_flops; return FC(a.v - b); }
+inline FC operator*(double a, FC b) { ++g_flops; return FC(a * b.v); }
+inline FC operator*(FC a, double b) { ++g_flops; return FC(a.v * b); }
+inline FC operator/(FC a, double b) { ++g_flops; return FC(a.v / b); }
+inline FC operator/(double a, FC b) { ++g_flops; return FC(a / b.v); }
+inline FC operator-(FC a) { return FC(-a.v); }
+inline FC sqrt(FC a) { ++g_flops; return FC(std::sqrt(a.v)); }
+inline FC rcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
+inline FC fabs(FC a) { return FC(std::fabs(a.v)); }
+inline FC fmax(FC a, FC b) { return FC(std::fmax(a.v, b.v)); }
+inline void sincos_t(FC a, FC* s, FC* c) { g_flops += 2; s->v = std::sin(a.v); c->v = std::cos(a.v); }
+inline double value(FC a) { return a.v; }
+inline bool finite_value(FC a) { return std::isfinite(a.v); }
+
+#include "rt_device.hpp"
+#include "rt_integrator.hpp"
+
+using namespace rtd;
+
+static InstT<FC> inst(int plasma, int density, bool oblique) {
+    InstT<FC> I;
+    I.rs = FC(4.13); I.R = FC(10.0); I.Om = FC(2e-5); I.cm = FC(oblique ? 0.95 : 1.0);
+    I.sm = FC(oblique ? 0.3 : 0.0); I.Cwp = FC(1.0); I.R3 = FC(1000.0); I.ma2 = FC(0.99);
+    I.plasma = plasma; I.density = density; I.oblique = oblique ? 1 : 0;
+    return I;
+}
+
+int main() {
+    const char* pn[2] = {"iso", "aniso"};
+    const char* dn[4] = {"gj", "magnetar", "spherical", "none"};
+    std::printf("{");
+    bool first = true;
+    for (int pl = 0; pl < 2; ++pl)
+        for (int de = 0; de < 4; ++de)
+            for (int ob = 0; ob < 2; ++ob) {
+                InstT<FC> I = inst(pl, de, ob != 0);
+                FC y[8] = {FC(20.0), FC(5.0), FC(7.0), FC(100.0), FC(0.3), FC(0.2), FC(0.1), FC(-1.0)};
+                FC f[8];
+                g_flops = 0;
+                rhs(I, y, f, 1.0);
+                long long frhs = g_flops;
+                StagesT<FC> S;
+                for (int d = 0; d < 8; ++d) S.K[0][d] = f[d];
+                FC ynew[8];
+                g_flops = 0;
+                auto fn = [&](const FC* yy, FC* ff) { rhs(I, yy, ff, 1.0); };
+                dopri_attempt(fn, y, S, FC(0.1), ynew, 1e-8, 1e-12);
+                long long fstep = g_flops + 3;  // + step-size update (pow, x0.9, x h)
+                std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld}", first ? "" : ", ", pn[pl], dn[de],
+                            ob ? "oblique" : "aligned", frhs, fstep);
+                first = false;
+            }
+    std::printf("}\n");
+    return 0;
+}

@@ -1,0 +1,175 @@
+// Host side of the C ABI: validation, constants, schedules, workspace sizes,
+// error strings.
+#include "rt_common.hpp"
+
+#include <string>
+
+namespace rtd {
+
+static thread_local std::string g_err;
+
+void set_error(const char* msg) { g_err = msg ? msg : ""; }
+void clear_error() { g_err.clear(); }
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::string m = std::string(what) + ": " + hipGetErrorString(e);
+        set_error(m.c_str());
+        return RT_EHIP;
+    }
+    return RT_OK;
+}
+
+static bool finite_all(const double* v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+bool validate_star(const rt_star* s) {
+    if (!s) { set_error("null rt_star"); return false; }
+    double v[12] = {s->B0_G, s->P_s, s->theta_m, s->M_Msun, s->R_km, s->m_a_eV,
+                    s->g_agg_GeV, s->v0_kms, s->rho_GeVcm3, s->multiplicity, s->psi_twist, s->B_test_G};
+    if (!finite_all(v, 12)) { set_error("rt_star: non-finite parameter"); return false; }
+    if (!(s->B0_G > 0 && s->P_s > 0 && s->R_km > 0 && s->m_a_eV > 0 && s->v0_kms > 0 && s->rho_GeVcm3 > 0 &&
+          s->multiplicity > 0)) {
+        set_error("rt_star: B0, P, R, m_a, v0, rho and multiplicity must be positive");
+        return false;
+    }
+    if (!(2.0 * phys::GMsun_km * s->M_Msun < s->R_km)) {
+        set_error("rt_star: the star must be larger than its Schwarzschild radius");
+        return false;
+    }
+    if (s->plasma < 0 || s->plasma > 1 || s->density < 0 || s->density > 3 || s->weights < 0 || s->weights > 2 ||
+        s->kdir < 0 || s->kdir > 1) {
+        set_error("rt_star: enumeration out of range");
+        return false;
+    }
+    return true;
+}
+
+bool validate_tol(const rt_tol* t) {
+    if (!t) { set_error("null rt_tol"); return false; }
+    if (!(std::isfinite(t->rtol) && t->rtol > 0 && std::isfinite(t->atol) && t->atol > 0 &&
+          std::isfinite(t->r_max_km) && t->r_max_km > 0 && t->max_steps > 0)) {
+        set_error("rt_tol: rtol, atol, r_max must be positive and finite, max_steps positive");
+        return false;
+    }
+    if (t->max_steps > INT32_MAX) { set_error("rt_tol: max_steps exceeds 2^31 - 1"); return false; }
+    return true;
+}
+
+InstT<double> make_inst(const rt_star& s) {
+    InstT<double> I;
+    I.rs = 2.0 * phys::GMsun_km * s.M_Msun;
+    I.R = s.R_km;
+    I.R3 = s.R_km * s.R_km * s.R_km;
+    double Om_s = 2.0 * phys::pi / s.P_s;
+    I.Om = Om_s / phys::c_kms;
+    I.cm = std::cos(s.theta_m);
+    I.sm = std::sin(s.theta_m);
+    I.oblique = (I.sm != 0.0) ? 1 : 0;
+    double v0 = s.v0_kms / phys::c_kms;
+    double w_inf = s.m_a_eV * std::sqrt(1.0 + v0 * v0);
+    I.ma2 = 1.0 / (1.0 + v0 * v0);
+    double Cp = phys::wp2_per_ne() / (w_inf * w_inf);
+    // Goldreich-Julian number density scale Omega B0 / (4 pi e c) [cm^-3]
+    double n0 = Om_s * s.B0_G / (4.0 * phys::pi * phys::e_statC * phys::c_cms);
+    switch (s.density) {
+        case RT_DENSITY_GJ: I.Cwp = Cp * s.multiplicity * n0; break;
+        case RT_DENSITY_MAGNETAR:
+            // lambda psi B0 (R/r)^3 sin^2 / (4 pi e r_cm), r_cm = 1e5 r_km
+            I.Cwp = Cp * s.multiplicity * s.psi_twist * s.B0_G / (4.0 * phys::pi * phys::e_statC * 1.0e5);
+            break;
+        case RT_DENSITY_SPHERICAL: I.Cwp = Cp * s.multiplicity * n0; break;
+        default: I.Cwp = 0.0; break;
+    }
+    I.plasma = s.plasma;
+    I.density = s.density;
+    return I;
+}
+
+SeedC make_seed_consts(const rt_star& s) {
+    SeedC C;
+    double v0 = s.v0_kms / phys::c_kms;
+    C.B0 = s.B0_G;
+    C.period_km = s.P_s * phys::c_kms;
+    C.w_inf = s.m_a_eV * std::sqrt(1.0 + v0 * v0);
+    double rho_eV4 = s.rho_GeVcm3 * 1.0e9 * phys::hbarc_eVcm * phys::hbarc_eVcm * phys::hbarc_eVcm;
+    double n_inf = rho_eV4 / s.m_a_eV;
+    double k0 = s.m_a_eV * v0;
+    C.nc_per_ka = n_inf * C.w_inf / k0;
+    double g = s.g_agg_GeV * 1.0e-9;
+    C.g2 = g * g;
+    C.G2 = phys::gauss_eV2();
+    C.Btest = s.B_test_G;
+    C.hbarc = phys::hbarc_eVkm;
+    C.weights = s.weights;
+    C.kdir = s.kdir;
+    return C;
+}
+
+int device_cu_count() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+rt_schedule resolve_schedule(const rt_schedule* s) {
+    rt_schedule r;
+    r.block = 256;
+    r.waves_per_cu = 0;
+    r.refill_min = 16;
+    r.chunk = 1;
+    if (s) {
+        if (s->block == 64 || s->block == 128 || s->block == 256) r.block = s->block;
+        if (s->waves_per_cu > 0 && s->waves_per_cu <= 32) r.waves_per_cu = s->waves_per_cu;
+        if (s->refill_min >= 1 && s->refill_min <= 64) r.refill_min = s->refill_min;
+    }
+    return r;
+}
+
+int persistent_grid(const rt_schedule& sc, const void* kernel, int block) {
+    int cus = device_cu_count();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    if (sc.waves_per_cu > 0) {
+        int want = (sc.waves_per_cu * 64 + block - 1) / block;
+        if (want < per_cu) per_cu = want;
+        if (per_cu < 1) per_cu = 1;
+    }
+    return cus * per_cu;
+}
+
+}  // namespace rtd
+
+using namespace rtd;
+
+extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
+    if (n < 0) n = 0;
+    switch (op) {
+        case RT_OP_TRACE_FORWARD:
+        case RT_OP_TRACE_BACKWARD:
+        case RT_OP_BATCHED:
+            return fwd_ws_bytes(n);
+        case RT_OP_BIN:
+            return align256(sizeof(int32_t) * (size_t)n);
+        default:
+            return 0;
+    }
+}
+
+extern "C" const char* rt_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* rt_version(void) {
+    return "rt-gfx950 FP64 DOPRI5 ray tracer (hipcc " __VERSION__ ")";
+}

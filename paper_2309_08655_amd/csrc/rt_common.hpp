@@ -1,0 +1,127 @@
+// Host-side helpers shared by the translation units of the HIP library:
+// argument validation, error reporting, physical constants and the
+// conversion of an rt_star into integrator units, workspace layout and
+// launch geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/rt.h"
+#include "rt_device.hpp"
+#include "rt_integrator.hpp"
+
+#define RT_NFIN_ 16
+#define RT_NIFIN_ 3
+#define RT_NEV_ 10
+
+namespace rtd {
+
+// ---------------------------------------------------------------------------
+// error reporting (thread-local message)
+// ---------------------------------------------------------------------------
+void set_error(const char* msg);
+void clear_error();
+inline int fail(int code, const char* msg) {
+    set_error(msg);
+    return code;
+}
+int check_launch(const char* what);
+
+// ---------------------------------------------------------------------------
+// physical constants (CODATA 2018; IAU 2015 nominal G M_sun)
+// ---------------------------------------------------------------------------
+namespace phys {
+constexpr double pi = 3.14159265358979323846;
+constexpr double c_kms = 299792.458;
+constexpr double c_cms = 2.99792458e10;
+constexpr double hbarc_eVkm = 1.973269804e-10;
+constexpr double hbarc_eVcm = 1.973269804e-5;
+constexpr double alpha = 1.0 / 137.035999084;
+constexpr double m_e_eV = 510998.95;
+constexpr double e_statC = 4.803204712570263e-10;
+constexpr double GMsun_km = 1.4766250;
+constexpr double erg_per_eV = 1.602176634e-12;
+// 1 G in eV^2 (Heaviside-Lorentz, hbar = c = 1): B^2/(8 pi) erg/cm^3 = B_HL^2 / 2
+inline double gauss_eV2() { return std::sqrt(hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / (erg_per_eV * 4.0 * pi)); }
+// w_p^2 = 4 pi alpha n_e / m_e  [eV^2 per cm^-3]
+inline double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / m_e_eV; }
+}  // namespace phys
+
+bool validate_star(const rt_star* s);
+bool validate_tol(const rt_tol* t);
+InstT<double> make_inst(const rt_star& s);
+SeedC make_seed_consts(const rt_star& s);
+
+// ---------------------------------------------------------------------------
+// workspace of the persistent kernels
+// ---------------------------------------------------------------------------
+struct WorkCtr {
+    unsigned long long head;  // next list entry to hand out
+    unsigned long long len;   // list length
+    unsigned long long pad[30];
+};
+
+struct FwdWs {
+    WorkCtr* ctr;
+    int32_t* list;
+    double* h0;
+    double* k1;
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
+    char* p = (char*)ws;
+    FwdWs W;
+    W.ctr = (WorkCtr*)p;
+    p += align256(sizeof(WorkCtr));
+    W.list = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)n);
+    W.h0 = (double*)p;
+    p += align256(sizeof(double) * (size_t)n);
+    W.k1 = (double*)p;
+    return W;
+}
+
+inline size_t fwd_ws_bytes(int64_t n) {
+    return align256(sizeof(WorkCtr)) + align256(sizeof(int32_t) * (size_t)n) + align256(sizeof(double) * (size_t)n) +
+           align256(sizeof(double) * 8 * (size_t)n);
+}
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+int device_cu_count();
+inline int grid_for(int64_t n, int block, int per_thread) {
+    int64_t g = (n + (int64_t)block * per_thread - 1) / ((int64_t)block * per_thread);
+    int64_t cap = (int64_t)device_cu_count() * 16;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+rt_schedule resolve_schedule(const rt_schedule* s);
+// workgroups of a persistent launch: CUs x resident workgroups per CU
+int persistent_grid(const rt_schedule& sc, const void* kernel, int block);
+
+struct TolC {
+    double rtol, atol, rmax;
+    long long max_steps;
+};
+int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
+                     const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
+
+// small utility kernels (defined per translation unit)
+static __global__ void zero_ctr_kernel(WorkCtr* c) {
+    if (threadIdx.x == 0) { c->head = 0ull; c->len = 0ull; }
+}
+static __global__ void fill_kernel(double* p, int64_t n, double v) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace rtd

@@ -1,0 +1,369 @@
+// Device-side physics of the ray tracer (gfx950, FP64).
+//
+// Hamiltonian rays of McDonald & Witte, arXiv:2309.08655:
+//   Sec. 2, eq. (Hamilton):           x' = dH/dk, k' = -dH/dx
+//   Sec. 4.1, eqs. (StrongBHam), (SchwarzshildMetric1):
+//       H = g^{mu nu} k_mu k_nu + (w^2 - k_par^2) w_p^2 / w^2  (strongly magnetised, LO mode)
+//       H = g^{mu nu} k_mu k_nu + w_p^2                         (isotropic, eq. (DispIsotropic))
+//   Sec. 5, eq. (GJDensity) and Sec. 6, eq. (neMag): plasma densities.
+//
+// State y = (x, y, z, t, k_x, k_y, k_z, k_t) in the Cartesian Schwarzschild chart
+// (x = r n, r the areal radius; km), covariant momentum in units of the axion
+// energy at infinity.  Inverse metric: g^tt = -1/A, g^ij = delta^ij - s n^i n^j,
+// with A = 1 - s and s = r_s / r.  The static plasma frame sees w^2 = k_t^2 / A;
+// its orthonormal components of k are sqrt(A)(n.k) radially, unchanged tangentially.
+//
+// The gradient of H is derived by hand (no automatic differentiation on the hot
+// path).  Writing q = n.k, mu = m.n for the magnetic axis m(t), and
+// N = (1 + 2 sqrt(A)) mu q - m.k, the dipole field direction gives
+//   k_par^2 = N^2 / (1 + 3 mu^2),   K = k_par^2 / w^2 = A N^2 / (k_t^2 (1 + 3 mu^2)),
+//   H_aniso = H_vac + P (1 - K),    H_vac = -k_t^2/A + |k|^2 - s q^2,  P = w_p^2 / w_inf^2.
+// Every function is templated on the scalar so the same code runs in FP64 and
+// in forward-mode dual numbers (Hessian-vector products of the adjoint).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtd {
+
+// ----------------------------------------------------------------------------
+// minimal forward-mode dual number with N tangents (device and host)
+// ----------------------------------------------------------------------------
+template <int N>
+struct gdual {
+    double v;
+    double d[N];
+    __host__ __device__ gdual() : v(0.0) {
+        for (int i = 0; i < N; ++i) d[i] = 0.0;
+    }
+    __host__ __device__ gdual(double c) : v(c) {
+        for (int i = 0; i < N; ++i) d[i] = 0.0;
+    }
+};
+
+#define RT_HD __host__ __device__ __forceinline__
+
+using ::sqrt;
+
+template <int N> RT_HD gdual<N> operator+(const gdual<N>& a, const gdual<N>& b) {
+    gdual<N> r; r.v = a.v + b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+template <int N> RT_HD gdual<N> operator-(const gdual<N>& a, const gdual<N>& b) {
+    gdual<N> r; r.v = a.v - b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+template <int N> RT_HD gdual<N> operator-(const gdual<N>& a) {
+    gdual<N> r; r.v = -a.v;
+    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+template <int N> RT_HD gdual<N> operator*(const gdual<N>& a, const gdual<N>& b) {
+    gdual<N> r; r.v = a.v * b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = fma(a.d[i], b.v, a.v * b.d[i]);
+    return r;
+}
+template <int N> RT_HD gdual<N> operator*(double a, const gdual<N>& b) {
+    gdual<N> r; r.v = a * b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i];
+    return r;
+}
+template <int N> RT_HD gdual<N> operator*(const gdual<N>& b, double a) { return a * b; }
+template <int N> RT_HD gdual<N> operator+(double a, const gdual<N>& b) { gdual<N> r = b; r.v = a + b.v; return r; }
+template <int N> RT_HD gdual<N> operator+(const gdual<N>& b, double a) { gdual<N> r = b; r.v = b.v + a; return r; }
+template <int N> RT_HD gdual<N> operator-(double a, const gdual<N>& b) { return a + (-b); }
+template <int N> RT_HD gdual<N> operator-(const gdual<N>& b, double a) { gdual<N> r = b; r.v = b.v - a; return r; }
+template <int N> RT_HD gdual<N> rcp(const gdual<N>& a) {
+    gdual<N> r; r.v = 1.0 / a.v;
+    double g = -r.v * r.v;
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
+template <int N> RT_HD gdual<N> operator/(const gdual<N>& a, const gdual<N>& b) { return a * rcp(b); }
+template <int N> RT_HD gdual<N> operator/(double a, const gdual<N>& b) { return a * rcp(b); }
+template <int N> RT_HD gdual<N> operator/(const gdual<N>& a, double b) { return a * (1.0 / b); }
+template <int N> RT_HD gdual<N> sqrt(const gdual<N>& a) {
+    gdual<N> r; r.v = ::sqrt(a.v);
+    double g = 0.5 / r.v;
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
+template <int N> RT_HD void sincos_t(const gdual<N>& a, gdual<N>* s, gdual<N>* c) {
+    double sv, cv;
+    ::sincos(a.v, &sv, &cv);
+    s->v = sv; c->v = cv;
+    for (int i = 0; i < N; ++i) { s->d[i] = cv * a.d[i]; c->d[i] = -sv * a.d[i]; }
+}
+RT_HD double rcp(double a) { return 1.0 / a; }
+RT_HD void sincos_t(double a, double* s, double* c) { ::sincos(a, s, c); }
+RT_HD double value(double a) { return a; }
+template <int N> RT_HD double value(const gdual<N>& a) { return a.v; }
+
+// ----------------------------------------------------------------------------
+// instance constants (integrator units: km, k in units of w_inf)
+// ----------------------------------------------------------------------------
+enum { PL_ISO = 0, PL_ANISO = 1 };
+enum { DEN_GJ = 0, DEN_MAG = 1, DEN_SPH = 2, DEN_NONE = 3 };
+enum { W_UNIT = 0, W_CONV = 1, W_CONV_CONSTB = 2 };
+enum { KD_ISO = 0, KD_OUT = 1 };
+enum { ST_OK = 0, ST_ESCAPED = 1, ST_HIT_STAR = 2, ST_NO_RESONANCE = 3, ST_MAX_STEPS = 4,
+       ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6 };
+
+template <class T>
+struct InstT {
+    T rs;      // Schwarzschild radius [km]
+    T R;       // stellar radius [km]
+    T Om;      // rotation rate / c [rad/km]
+    T cm, sm;  // cos / sin of the magnetic inclination
+    T Cwp;     // plasma coefficient: P = Cwp * shape
+    T R3;      // R^3
+    T ma2;     // (m_a / w_inf)^2
+    int plasma, density;
+    int oblique;  // sm != 0
+};
+
+// Weight and seeding constants, host-computed (physical units noted)
+struct SeedC {
+    double B0;          // polar surface field [G]
+    double period_km;   // P c [km]
+    double w_inf;       // axion energy at infinity [eV]
+    double nc_per_ka;   // n_inf w_inf / k0 [eV^3], multiplies |k_a|/w_inf
+    double g2;          // coupling^2 [eV^-2]
+    double G2;          // 1 gauss in eV^2
+    double Btest;       // constant |B_perp| [G] (zero-variance test)
+    double hbarc;       // [eV km]
+    int weights, kdir;
+};
+
+// ----------------------------------------------------------------------------
+// plasma: P = w_p^2 / w_inf^2, its spatial gradient and time derivative
+// ----------------------------------------------------------------------------
+template <class T>
+struct Plasma {
+    T P, gx, gy, gz, gt;
+};
+
+// magnetic axis m(t) and its time derivative
+template <class T>
+RT_HD void magnetic_axis(const InstT<T>& I, const T& t, T m[3], T mt[3]) {
+    if (I.oblique) {
+        T s, c;
+        sincos_t(I.Om * t, &s, &c);
+        m[0] = I.sm * c; m[1] = I.sm * s; m[2] = I.cm;
+        T w = I.Om * I.sm;
+        mt[0] = -(w * s); mt[1] = w * c; mt[2] = T(0.0);
+    } else {
+        m[0] = T(0.0); m[1] = T(0.0); m[2] = I.cm;
+        mt[0] = T(0.0); mt[1] = T(0.0); mt[2] = T(0.0);
+    }
+}
+
+// n = unit position, ir = 1/r, m = axis, mu = m.n, dmu = dm/dt . n
+template <class T>
+RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const T m[3], const T& mu,
+                            const T& dmu) {
+    Plasma<T> p;
+    if (I.density == DEN_NONE) {
+        p.P = T(0.0); p.gx = T(0.0); p.gy = T(0.0); p.gz = T(0.0); p.gt = T(0.0);
+        return p;
+    }
+    T ir3 = ir * ir * ir;
+    T D3 = I.Cwp * I.R3 * ir3;  // Cwp (R/r)^3
+    if (I.density == DEN_GJ) {
+        // P = D3 |g|, g = 3 n_z mu - cos(theta_m)
+        // grad g = (3/r)(mu z + n_z m - 2 n_z mu n)
+        T g = 3.0 * n[2] * mu - I.cm;
+        double sg = (value(g) < 0.0) ? -1.0 : 1.0;
+        T ag = sg * g;
+        p.P = D3 * ag;
+        T c = D3 * ir;
+        T a = 3.0 * sg;
+        T nzmu2 = 2.0 * n[2] * mu;
+        // components: c * [a (mu e_z + n_z m - 2 n_z mu n) - 3 |g| n]
+        T rad = a * nzmu2 + 3.0 * ag;  // coefficient of -n
+        p.gx = c * (a * (n[2] * m[0]) - rad * n[0]);
+        p.gy = c * (a * (n[2] * m[1]) - rad * n[1]);
+        p.gz = c * (a * (mu + n[2] * m[2]) - rad * n[2]);
+        p.gt = D3 * a * n[2] * dmu;
+    } else if (I.density == DEN_MAG) {
+        // P = D3 (1 - mu^2) / r; grad P = (D3/r^2)(-4 (1 - mu^2) n - 2 mu (m - mu n))
+        T s2 = 1.0 - mu * mu;
+        T D4 = D3 * ir;
+        p.P = D4 * s2;
+        T c = D4 * ir;
+        T rad = 4.0 * s2 - 2.0 * mu * mu;  // coefficient of -n
+        T tm = 2.0 * mu;                   // coefficient of -m
+        p.gx = -(c * (rad * n[0] + tm * m[0]));
+        p.gy = -(c * (rad * n[1] + tm * m[1]));
+        p.gz = -(c * (rad * n[2] + tm * m[2]));
+        p.gt = -(D4 * tm * dmu);
+    } else {
+        // spherical test profile P = D3
+        p.P = D3;
+        T c = -3.0 * D3 * ir;
+        p.gx = c * n[0]; p.gy = c * n[1]; p.gz = c * n[2];
+        p.gt = T(0.0);
+    }
+    return p;
+}
+
+// ----------------------------------------------------------------------------
+// gradient of H: g = (dH/dx, dH/dy, dH/dz, dH/dt, dH/dk_x, dH/dk_y, dH/dk_z, dH/dk_t)
+// ----------------------------------------------------------------------------
+template <class T>
+RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
+    const T& kx = y[4]; const T& ky = y[5]; const T& kz = y[6]; const T& kt = y[7];
+    T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    T r = sqrt(r2);
+    T ir = rcp(r);
+    T n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
+    T s = I.rs * ir;
+    T A = 1.0 - s;
+    T iA = rcp(A);
+    T q = n[0] * kx + n[1] * ky + n[2] * kz;
+    T kt2 = kt * kt;
+    // vacuum: dH/dk = 2k - 2 s q n; dH/dk_t = -2 k_t / A;
+    //         dH/dx = (s/r) [(k_t^2/A^2 + 3 q^2) n - 2 q k]
+    T sq2 = 2.0 * s * q;
+    g[4] = 2.0 * kx - sq2 * n[0];
+    g[5] = 2.0 * ky - sq2 * n[1];
+    g[6] = 2.0 * kz - sq2 * n[2];
+    g[7] = -2.0 * kt * iA;
+    T sr = s * ir;
+    T cn = sr * (kt2 * iA * iA + 3.0 * q * q);
+    T ck = 2.0 * sr * q;
+    g[0] = cn * n[0] - ck * kx;
+    g[1] = cn * n[1] - ck * ky;
+    g[2] = cn * n[2] - ck * kz;
+    g[3] = T(0.0);
+    if (I.density == DEN_NONE) return;
+
+    T m[3], mt[3];
+    magnetic_axis(I, y[3], m, mt);
+    T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    T dmu = mt[0] * n[0] + mt[1] * n[1] + mt[2] * n[2];
+    Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
+    if (I.plasma == PL_ISO) {
+        g[0] = g[0] + p.gx; g[1] = g[1] + p.gy; g[2] = g[2] + p.gz;
+        g[3] = g[3] + p.gt;
+        return;
+    }
+    // anisotropic (strong-B LO mode): H += P (1 - K)
+    T a = sqrt(A);
+    T b = 1.0 + 2.0 * a;
+    T mk = m[0] * kx + m[1] * ky + m[2] * kz;
+    T Nn = b * mu * q - mk;
+    T den = rcp(1.0 + 3.0 * mu * mu);
+    T ikt2 = rcp(kt2);
+    T N2d = Nn * Nn * ikt2 * den;  // N^2 / (k_t^2 (1 + 3 mu^2))
+    T K = A * N2d;
+    T c1 = 2.0 * A * Nn * ikt2 * den;  // dK/dN
+    // dK/dk = c1 (b mu n - m)
+    T bmu = b * mu;
+    T PK = p.P * c1;
+    g[4] = g[4] - PK * (bmu * n[0] - m[0]);
+    g[5] = g[5] - PK * (bmu * n[1] - m[1]);
+    g[6] = g[6] - PK * (bmu * n[2] - m[2]);
+    // dK/dk_t = -2 K / k_t  ->  dH/dk_t += 2 P K / k_t
+    g[7] = g[7] + 2.0 * p.P * K * rcp(kt);
+    // dN/dx = (mu q s /(a r)) n + b [q (m - mu n) + mu (k - q n)] / r
+    // dK/dx = N2d (s/r) n + c1 dN/dx - 6 K mu den (m - mu n) / r
+    T e_n = N2d * sr + c1 * (mu * q * s * ir * rcp(a)) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
+    T e_m = c1 * b * ir * q - 6.0 * K * mu * den * ir;
+    T e_k = c1 * b * ir * mu;
+    T omK = 1.0 - K;
+    g[0] = g[0] + omK * p.gx - p.P * (e_n * n[0] + e_m * m[0] + e_k * kx);
+    g[1] = g[1] + omK * p.gy - p.P * (e_n * n[1] + e_m * m[1] + e_k * ky);
+    g[2] = g[2] + omK * p.gz - p.P * (e_n * n[2] + e_m * m[2] + e_k * kz);
+    // time: dN/dt = b q dmu - mt.k ; dK/dt = c1 dN/dt - 6 K mu den dmu
+    if (I.oblique) {
+        T mtk = mt[0] * kx + mt[1] * ky + mt[2] * kz;
+        T dKdt = c1 * (b * q * dmu - mtk) - 6.0 * K * mu * den * dmu;
+        g[3] = g[3] + omK * p.gt - p.P * dKdt;
+    }
+}
+
+// Hamilton's equations, eq. (Hamilton); sign = -1 integrates backwards in the worldline parameter.
+template <class T>
+RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign) {
+    T g[8];
+    grad_h(I, y, g);
+    for (int i = 0; i < 4; ++i) {
+        f[i] = sign * g[4 + i];
+        f[4 + i] = -sign * g[i];
+    }
+}
+
+// H itself (health checks and the backward event function)
+template <class T>
+RT_HD T hamiltonian(const InstT<T>& I, const T y[8]) {
+    T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    T r = sqrt(r2);
+    T ir = rcp(r);
+    T n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
+    T s = I.rs * ir;
+    T A = 1.0 - s;
+    T q = n[0] * y[4] + n[1] * y[5] + n[2] * y[6];
+    T kk = y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
+    T Hv = -(y[7] * y[7]) * rcp(A) + kk - s * q * q;
+    if (I.density == DEN_NONE) return Hv;
+    T m[3], mt[3];
+    magnetic_axis(I, y[3], m, mt);
+    T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    T dmu = T(0.0);
+    Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
+    if (I.plasma == PL_ISO) return Hv + p.P;
+    T a = sqrt(A);
+    T mk = m[0] * y[4] + m[1] * y[5] + m[2] * y[6];
+    T Nn = (1.0 + 2.0 * a) * mu * q - mk;
+    T K = A * Nn * Nn * rcp(y[7] * y[7] * (1.0 + 3.0 * mu * mu));
+    return Hv + p.P * (1.0 - K);
+}
+
+// g^{mu nu} k_mu k_nu (vacuum part of H)
+template <class T>
+RT_HD T g_kk(const InstT<T>& I, const T y[8]) {
+    T r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    T ir = rcp(r);
+    T s = I.rs * ir;
+    T q = (y[0] * y[4] + y[1] * y[5] + y[2] * y[6]) * ir;
+    T kk = y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
+    return -(y[7] * y[7]) * rcp(1.0 - s) + kk - s * q * q;
+}
+
+// dipole field direction u = 3 mu n - m (|u|^2 = 1 + 3 mu^2) and magnitude factor
+template <class T>
+RT_HD void dipole_dir(const T n[3], const T m[3], const T& mu, T u[3]) {
+    for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - m[i];
+}
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al. 2011)
+// ----------------------------------------------------------------------------
+RT_HD void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                         uint32_t out[4]) {
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// 52 random bits -> (m + 1/2) 2^-52 in (0, 1)
+RT_HD double unit_from_bits(uint32_t hi, uint32_t lo) {
+    uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)m + 0.5) * 2.220446049250313e-16;
+}
+
+}  // namespace rtd

@@ -1,0 +1,539 @@
+// Forward path of the ray tracer on gfx950: resonance seeding, the persistent
+// DOPRI5 tracing kernel and sky binning.  One ray per lane, FP64 throughout.
+//
+// McDonald & Witte, arXiv:2309.08655: Sec. 2.2 (forward Monte Carlo power,
+// eq. (Power), top-hat binning), Sec. 3 (foliation, eq. (Hypersurfaces);
+// forward-tracing equation (ForwardTracingEquation1)), Sec. 4.1-4.4
+// (Hamiltonian, surface measure, focusing, conversion probability).
+#include "rt_common.hpp"
+
+namespace rtd {
+
+// ----------------------------------------------------------------------------
+// seeding
+// ----------------------------------------------------------------------------
+
+// Resonance function of the foliation along the radial line through n at the
+// emission time (axis m fixed), at radius r:
+//   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
+// (isotropic: F = P - m_a^2).  cos^2 theta_B is constant along the line.
+__device__ static double resonance_line(const InstT<double>& I, const double n[3], const double m[3], double mu,
+                                        double cB2, double r) {
+    double ir = 1.0 / r;
+    Plasma<double> p = plasma_eval(I, n, ir, m, mu, 0.0);
+    if (I.plasma == PL_ISO) return p.P - I.ma2;
+    double w2 = 1.0 / (1.0 - I.rs * ir);
+    return p.P * (w2 - (w2 - I.ma2) * cB2) - I.ma2 * w2;
+}
+
+// The same function at a general point x (for its spatial gradient, by dual numbers).
+template <class T>
+__device__ static T resonance_point(const InstT<double>& I, const T x[3], const double m[3], const double kh[3]) {
+    T r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    T ir = rcp(r);
+    T n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
+    T mm[3] = {T(m[0]), T(m[1]), T(m[2])};
+    T mu = mm[0] * n[0] + mm[1] * n[1] + mm[2] * n[2];
+    InstT<T> J;
+    J.rs = T(I.rs); J.R = T(I.R); J.Om = T(I.Om); J.cm = T(I.cm); J.sm = T(I.sm); J.Cwp = T(I.Cwp);
+    J.R3 = T(I.R3); J.ma2 = T(I.ma2); J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
+    Plasma<T> p = plasma_eval(J, n, ir, mm, mu, T(0.0));
+    if (I.plasma == PL_ISO) return p.P - I.ma2;
+    T u[3];
+    dipole_dir(n, mm, mu, u);
+    T ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
+    T cB2 = ku * ku * rcp(1.0 + 3.0 * mu * mu);
+    T w2 = rcp(1.0 - I.rs * ir);
+    return p.P * (w2 - (w2 - I.ma2) * cB2) - I.ma2 * w2;
+}
+
+__device__ static void seed_one(const InstT<double>& I, const SeedC& C, uint64_t seed, int32_t instance,
+                                int64_t gi, double out[10], int32_t* status) {
+    uint32_t o[4];
+    double u[6];
+    for (uint32_t blk = 0; blk < 3; ++blk) {
+        philox4x32_10((uint32_t)(uint64_t)gi, (uint32_t)((uint64_t)gi >> 32), (uint32_t)instance, blk,
+                      (uint32_t)seed, (uint32_t)(seed >> 32), o);
+        u[2 * blk] = unit_from_bits(o[0], o[1]);
+        u[2 * blk + 1] = unit_from_bits(o[2], o[3]);
+    }
+    // emission direction uniform in (cos theta, phi)
+    double ct = 2.0 * u[0] - 1.0;
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double sp, cp;
+    sincos(2.0 * M_PI * u[1], &sp, &cp);
+    double n[3] = {st * cp, st * sp, ct};
+    double kh[3];
+    {
+        double sa, ca;
+        sincos(2.0 * M_PI * u[3], &sa, &ca);
+        if (C.kdir == KD_ISO) {
+            double c = 2.0 * u[2] - 1.0, s = sqrt(fmax(0.0, 1.0 - c * c));
+            kh[0] = s * ca; kh[1] = s * sa; kh[2] = c;
+        } else {
+            // outward hemisphere about n: polar cosine u3, azimuth in the (theta-hat, phi-hat) basis
+            double c = u[2], s = sqrt(fmax(0.0, 1.0 - c * c));
+            double e1[3] = {ct * cp, ct * sp, -st};
+            double e2[3] = {-sp, cp, 0.0};
+            for (int d = 0; d < 3; ++d) kh[d] = c * n[d] + s * (ca * e1[d] + sa * e2[d]);
+        }
+    }
+    double t0 = u[4] * C.period_km;
+    double m[3], mt[3];
+    magnetic_axis(I, t0, m, mt);
+    double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    double ud[3];
+    dipole_dir(n, m, mu, ud);
+    double ku = kh[0] * ud[0] + kh[1] * ud[1] + kh[2] * ud[2];
+    double cB2 = ku * ku / (1.0 + 3.0 * mu * mu);
+
+    // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
+    double R = I.R;
+    double rc = -1.0;
+    if (resonance_line(I, n, m, mu, cB2, R) > 0.0) {
+        double lo = R, hi = 2.0 * R;
+        int j = 0;
+        while (!(resonance_line(I, n, m, mu, cB2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
+        if (resonance_line(I, n, m, mu, cB2, hi) < 0.0) {
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (resonance_line(I, n, m, mu, cB2, mid) > 0.0) lo = mid; else hi = mid;
+            }
+            rc = 0.5 * (lo + hi);
+        }
+    }
+    if (rc < 0.0) {
+        for (int d = 0; d < 10; ++d) out[d] = 0.0;
+        out[9] = -1.0;
+        *status = ST_NO_RESONANCE;
+        return;
+    }
+    *status = ST_OK;
+    double s = I.rs / rc;
+    double A = 1.0 - s;
+    double sA = sqrt(A);
+    double ka = sqrt(1.0 / A - I.ma2);
+    double x[3] = {rc * n[0], rc * n[1], rc * n[2]};
+    // photon covariant momentum from the static-frame axion momentum |k_a| kh
+    double ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
+    double nko = n[0] * ko[0] + n[1] * ko[1] + n[2] * ko[2];
+    double corr = nko / sA - nko;
+    double k[3] = {ko[0] + corr * n[0], ko[1] + corr * n[1], ko[2] + corr * n[2]};
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = t0;
+    out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = -1.0;
+    out[9] = rc;
+    if (C.weights == W_UNIT) { out[8] = 1.0; return; }
+
+    // ---- weight w = C_k n_c Vt Q ----
+    const double Ck = (C.kdir == KD_ISO) ? 4.0 * M_PI : 2.0 * M_PI;
+    double n_c = C.nc_per_ka * ka;
+    // surface element from grad F (dual numbers, 3 tangents)
+    gdual<3> xd[3];
+    for (int d = 0; d < 3; ++d) { xd[d] = gdual<3>(x[d]); xd[d].d[d] = 1.0; }
+    gdual<3> Fd = resonance_point(I, xd, m, kh);
+    double Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
+    double gp2 = 0.0;
+    for (int d = 0; d < 3; ++d) { double gp = Fd.d[d] - Fr * n[d]; gp2 += gp * gp; }
+    double Vt = sA * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr)) / (C.hbarc * C.hbarc);
+    double E = C.w_inf / sA;
+    double Rr = I.R / rc;
+    double Bmag = 0.5 * C.B0 * Rr * Rr * Rr * sqrt(1.0 + 3.0 * mu * mu);
+    double Bperp2 = (C.weights == W_CONV_CONSTB) ? (C.Btest * C.G2) * (C.Btest * C.G2)
+                                                  : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2);
+    double Q;
+    double ir = 1.0 / rc;
+    Plasma<double> p = plasma_eval(I, n, ir, m, mu, 0.0);
+    if (I.plasma == PL_ISO) {
+        double gn = n[0] * p.gx + n[1] * p.gy + n[2] * p.gz;
+        double g2 = p.gx * p.gx + p.gy * p.gy + p.gz * p.gz - s * gn * gn;
+        double dwp2 = C.hbarc * C.w_inf * C.w_inf * sqrt(g2);
+        Q = M_PI * C.g2 * Bperp2 * E * E / dwp2;
+    } else {
+        // dE/dx at fixed covariant k from H(x, k_t, k) = 0 with w = -k_t/sqrt(A):
+        //   dE/dx = (dH/dx) / (sqrt(A) dH/dk_t) - w s/(2 A r) n
+        double y[8] = {x[0], x[1], x[2], t0, k[0], k[1], k[2], -1.0};
+        double g[8];
+        grad_h(I, y, g);
+        double w = 1.0 / sA;
+        double c0 = 1.0 / (sA * g[7]);
+        double c1 = w * s * ir / (2.0 * A);
+        double dE[3] = {g[0] * c0 - c1 * n[0], g[1] * c0 - c1 * n[1], g[2] * c0 - c1 * n[2]};
+        double dn = n[0] * dE[0] + n[1] * dE[1] + n[2] * dE[2];
+        double dE2 = dE[0] * dE[0] + dE[1] * dE[1] + dE[2] * dE[2] - s * dn * dn;
+        double dEn = C.hbarc * C.w_inf * sqrt(dE2);
+        double wp2 = p.P * C.w_inf * C.w_inf;
+        double c2 = cB2, s2 = 1.0 - cB2;
+        double Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
+        double E2 = E * E;
+        Q = 0.5 * M_PI * C.g2 * Bperp2 * E2 * E2 * E / (Dd * dEn);
+    }
+    out[8] = Ck * n_c * Vt * Q;
+}
+
+__global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedC C, uint64_t seed, int32_t instance,
+                                                     int64_t first, int64_t n, double* __restrict__ rays,
+                                                     int32_t* __restrict__ status) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        double o[10];
+        int32_t st;
+        seed_one(I, C, seed, instance, first + j, o, &st);
+        for (int d = 0; d < 10; ++d) rays[d * n + j] = o[d];
+        status[j] = st;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// tracing: init pass (FSAL derivative, starting step, compacted work list)
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
+                                                         const int32_t* __restrict__ status, int64_t n,
+                                                         WorkCtr* ctr, int32_t* __restrict__ list,
+                                                         double* __restrict__ h0s, double* __restrict__ k1s,
+                                                         double* __restrict__ fin, int32_t* __restrict__ ifin) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        int64_t j = base + threadIdx.x;
+        bool valid = j < n;
+        bool ok = valid && (status == nullptr || status[j] == ST_OK);
+        if (valid && !ok) {
+            for (int d = 0; d < RT_NFIN_; ++d) fin[d * n + j] = 0.0;
+            ifin[j] = 0;
+            ifin[n + j] = 0;
+            ifin[2 * n + j] = status[j];
+        }
+        if (ok) {
+            double y[8], f0[8];
+            for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
+            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+            f(y, f0);
+            double h = initial_step(f, y, f0, tol.rtol, tol.atol);
+            h0s[j] = h;
+            for (int d = 0; d < 8; ++d) k1s[d * n + j] = f0[d];
+        }
+        // wave-aggregated append to the work list
+        unsigned long long mask = __ballot(ok);
+        if (mask) {
+            int lane = __lane_id();
+            int leader = __ffsll((long long)mask) - 1;
+            unsigned long long pos = 0;
+            if (lane == leader) pos = atomicAdd(&ctr->len, (unsigned long long)__popcll(mask));
+            pos = __shfl(pos, leader);
+            if (ok) {
+                unsigned long long below = mask & ((1ull << lane) - 1ull);
+                list[pos + __popcll(below)] = (int32_t)j;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void write_final(const InstT<double>& I, const double yf[8], double lam, double h,
+                                            int nacc, int nrej, int status, int64_t j, int64_t n,
+                                            double* __restrict__ fin, int32_t* __restrict__ ifin) {
+    double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
+    double ir = 1.0 / r;
+    double nn[3] = {yf[0] * ir, yf[1] * ir, yf[2] * ir};
+    double A = 1.0 - I.rs * ir;
+    double q = nn[0] * yf[4] + nn[1] * yf[5] + nn[2] * yf[6];
+    double c = (sqrt(A) - 1.0) * q;
+    double v[3] = {yf[4] + c * nn[0], yf[5] + c * nn[1], yf[6] + c * nn[2]};
+    double vn = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] *= vn; v[1] *= vn; v[2] *= vn;
+    double theta = atan2(sqrt(v[0] * v[0] + v[1] * v[1]), v[2]);
+    double phi = atan2(v[1], v[0]);
+    double psi = fmod(phi - I.Om * (yf[3] - r), 2.0 * M_PI);
+    if (psi < 0.0) psi += 2.0 * M_PI;
+    if (psi >= 2.0 * M_PI) psi -= 2.0 * M_PI;
+    for (int d = 0; d < 8; ++d) fin[d * n + j] = yf[d];
+    fin[8 * n + j] = theta;
+    fin[9 * n + j] = phi;
+    fin[10 * n + j] = psi;
+    fin[11 * n + j] = -yf[7];
+    fin[12 * n + j] = hamiltonian(I, yf);
+    fin[13 * n + j] = lam;
+    fin[14 * n + j] = r;
+    fin[15 * n + j] = h;
+    ifin[j] = nacc;
+    ifin[n + j] = nrej;
+    ifin[2 * n + j] = status;
+}
+
+// ----------------------------------------------------------------------------
+// persistent tracing kernel: each lane integrates rays taken from the work list
+// until the list is exhausted; a wave refills its idle lanes with one atomic
+// ----------------------------------------------------------------------------
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
+                                                          int64_t n, WorkCtr* ctr, const int32_t* __restrict__ list,
+                                                          const double* __restrict__ h0s,
+                                                          const double* __restrict__ k1s, double* __restrict__ fin,
+                                                          int32_t* __restrict__ ifin, int refill_min) {
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long nlist = ctr->len;
+    bool active = false;
+    bool exhausted = false;
+    int64_t j = 0;
+    double y[8], ynew[8];
+    Stages S;
+    double h = 0.0, lam = 0.0, facmax = 10.0;
+    int nacc = 0, nrej = 0;
+    for (int d = 0; d < 8; ++d) { y[d] = 0.0; S.K[0][d] = 0.0; }
+    y[0] = 1e4;  // harmless dummy state for idle lanes
+    y[7] = -1.0;
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+
+    while (true) {
+        unsigned long long idle = __ballot(!active);
+        if (idle && !exhausted) {
+            int cnt = __popcll(idle);
+            if (cnt >= refill_min || idle == __ballot(true)) {
+                int leader = __ffsll((long long)idle) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&ctr->head, (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                if (!active) {
+                    unsigned long long q = base + __popcll(idle & below);
+                    if (q < nlist) {
+                        j = list[q];
+                        for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
+                        h = h0s[j];
+                        lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
+                        active = true;
+                    }
+                }
+                if (base + (unsigned long long)cnt >= nlist) exhausted = true;
+            }
+        }
+        if (__ballot(active) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+
+        double err = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
+        if (active) {
+            bool acc = err <= 1.0;
+            if (!acc) {
+                ++nrej;
+                h *= step_factor(err, facmax, false);
+                facmax = 1.0;
+                if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) {
+                    write_final(I, y, lam, h, nacc, nrej, ST_STEP_UNDERFLOW, j, n, fin, ifin);
+                    active = false;
+                }
+            } else {
+                ++nacc;
+                double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+                bool fin_ok = true;
+                for (int d = 0; d < 8; ++d) fin_ok = fin_ok && isfinite(ynew[d]);
+                if (!fin_ok) {
+                    write_final(I, ynew, lam + h, h, nacc, nrej, ST_NONFINITE, j, n, fin, ifin);
+                    active = false;
+                } else if (rnew <= I.R) {
+                    write_final(I, ynew, lam + h, h, nacc, nrej, ST_HIT_STAR, j, n, fin, ifin);
+                    active = false;
+                } else if (rnew >= tol.rmax) {
+                    // locate r(theta) = r_max on the continuous extension (60 bisections)
+                    double lo = 0.0, hi = 1.0;
+                    double yt[8];
+                    for (int it = 0; it < 60; ++it) {
+                        double mid = 0.5 * (lo + hi);
+                        dense_at(y, ynew, S, h, mid, yt, 0, 3);
+                        double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
+                        if (rm >= tol.rmax) hi = mid; else lo = mid;
+                    }
+                    dense_at(y, ynew, S, h, hi, yt, 0, 8);
+                    write_final(I, yt, lam + hi * h, h, nacc, nrej, ST_ESCAPED, j, n, fin, ifin);
+                    active = false;
+                } else {
+                    lam += h;
+                    for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+                    h *= step_factor(err, facmax, true);
+                    facmax = 10.0;
+                    if (nacc >= tol.max_steps) {
+                        write_final(I, y, lam, h, nacc, nrej, ST_MAX_STEPS, j, n, fin, ifin);
+                        active = false;
+                    } else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) {
+                        write_final(I, y, lam, h, nacc, nrej, ST_STEP_UNDERFLOW, j, n, fin, ifin);
+                        active = false;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// binning: per-ray keys, then LDS-privatised tiles merged with FP64 atomics
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) bin_keys_kernel(const double* __restrict__ fin, const int32_t* __restrict__ ifin,
+                                                       int64_t n, int32_t nt, int32_t np, int32_t nw, double dw,
+                                                       const int64_t* __restrict__ inst_offset, int32_t n_inst,
+                                                       int32_t* __restrict__ keys, const double* __restrict__ w,
+                                                       double* __restrict__ over) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const double dth = M_PI / nt, dps = 2.0 * M_PI / np;
+    const int64_t per = (int64_t)nt * np * nw;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t key = -1;
+        if (ifin[2 * n + i] == ST_ESCAPED) {
+            double th = fin[8 * n + i], ps = fin[10 * n + i], om = fin[11 * n + i];
+            int it = (int)floor(th / dth);
+            it = it < 0 ? 0 : (it > nt - 1 ? nt - 1 : it);
+            int ip = (int)floor(ps / dps);
+            ip = ip < 0 ? 0 : (ip > np - 1 ? np - 1 : ip);
+            double iwf = floor((om - 1.0) / dw + 0.5) + (double)(nw / 2);
+            if (iwf >= 0.0 && iwf < (double)nw) {
+                int64_t inst = 0;
+                if (inst_offset != nullptr) {
+                    // instance owning ray i: largest k with inst_offset[k] <= i
+                    int lo = 0, hi = n_inst - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (inst_offset[mid] <= i) lo = mid; else hi = mid - 1;
+                    }
+                    inst = lo;
+                }
+                key = (int32_t)(inst * per + ((int64_t)it * np + ip) * nw + (int64_t)iwf);
+            } else {
+                atomicAdd(&over[0], w[i]);
+                atomicAdd(&over[1], 1.0);
+            }
+        }
+        keys[i] = key;
+    }
+}
+
+constexpr int BIN_TILE = 4096;  // bins per LDS tile: 2 x 32 KiB of FP64
+
+__global__ void __launch_bounds__(256) bin_tiles_kernel(const int32_t* __restrict__ keys, const double* __restrict__ w,
+                                                        int64_t n, int64_t nbins, int64_t chunk,
+                                                        double* __restrict__ hist, double* __restrict__ cnt) {
+    __shared__ double sh_w[BIN_TILE];
+    __shared__ double sh_c[BIN_TILE];
+    const int64_t tile0 = (int64_t)blockIdx.x * BIN_TILE;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = (r0 + chunk < n) ? r0 + chunk : n;
+    for (int b = threadIdx.x; b < BIN_TILE; b += blockDim.x) { sh_w[b] = 0.0; sh_c[b] = 0.0; }
+    __syncthreads();
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        int32_t k = keys[i];
+        int64_t rel = (int64_t)k - tile0;
+        if (k >= 0 && rel >= 0 && rel < BIN_TILE) {
+            atomicAdd(&sh_w[rel], w[i]);
+            atomicAdd(&sh_c[rel], 1.0);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < BIN_TILE; b += blockDim.x) {
+        int64_t gb = tile0 + b;
+        if (gb < nbins && sh_c[b] != 0.0) {
+            atomicAdd(&hist[gb], sh_w[b]);
+            atomicAdd(&cnt[gb], sh_c[b]);
+        }
+    }
+}
+
+}  // namespace rtd
+
+using namespace rtd;
+
+extern "C" int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t instance, int64_t first, int64_t n,
+                                   double* rays, int32_t* status, void* stream) {
+    clear_error();
+    if (!validate_star(star)) return RT_EINVAL;
+    if (n < 0 || first < 0) return fail(RT_EINVAL, "rt_sample_resonance: negative n or first");
+    if (n == 0) return RT_OK;
+    if (!rays || !status) return fail(RT_EINVAL, "rt_sample_resonance: null output array");
+    InstT<double> I = make_inst(*star);
+    SeedC C = make_seed_consts(*star);
+    int grid = grid_for(n, 256, 8);
+    hipLaunchKernelGGL(sample_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, I, C, seed, instance, first, n,
+                       rays, status);
+    return check_launch("sample_kernel");
+}
+
+extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const double* rays, const int32_t* status,
+                                int64_t n, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
+                                const rt_schedule* sched, void* stream) {
+    clear_error();
+    if (!validate_star(star) || !validate_tol(tol)) return RT_EINVAL;
+    if (n < 0) return fail(RT_EINVAL, "rt_trace_forward: negative n");
+    if (n == 0) return RT_OK;
+    if (n > INT32_MAX) return fail(RT_EINVAL, "rt_trace_forward: n exceeds 2^31 - 1");
+    if (!rays || !fin || !ifin) return fail(RT_EINVAL, "rt_trace_forward: null array");
+    size_t need = rt_workspace_size(RT_OP_TRACE_FORWARD, n);
+    if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_trace_forward: workspace too small");
+    rt_schedule sc = resolve_schedule(sched);
+    InstT<double> I = make_inst(*star);
+    TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
+    FwdWs W = carve_fwd_ws(ws, n);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(zero_ctr_kernel, dim3(1), dim3(64), 0, st, W.ctr);
+    int grid = grid_for(n, 256, 8);
+    hipLaunchKernelGGL(trace_init_kernel, dim3(grid), dim3(256), 0, st, I, T, rays, status, n, W.ctr, W.list, W.h0,
+                       W.k1, fin, ifin);
+    int rc = check_launch("trace_init_kernel");
+    if (rc) return rc;
+    return launch_trace_fwd(sc, I, T, rays, n, W, fin, ifin, st);
+}
+
+namespace rtd {
+template <int BLOCK>
+static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays,
+                            int64_t n, const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK>, BLOCK);
+    hipLaunchKernelGGL(trace_fwd_kernel<BLOCK>, dim3(grid), dim3(BLOCK), 0, st, I, T, rays, n, W.ctr, W.list, W.h0,
+                       W.k1, fin, ifin, sc.refill_min);
+    return check_launch("trace_fwd_kernel");
+}
+
+int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
+                     const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    switch (sc.block) {
+        case 64: return launch_fwd_block<64>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 128: return launch_fwd_block<128>(sc, I, T, rays, n, W, fin, ifin, st);
+        default: return launch_fwd_block<256>(sc, I, T, rays, n, W, fin, ifin, st);
+    }
+}
+}  // namespace rtd
+
+extern "C" int rt_bin_flux(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
+                           const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over,
+                           void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!bins || bins->n_theta <= 0 || bins->n_psi <= 0 || bins->n_omega <= 0 || !(bins->d_omega > 0.0))
+        return fail(RT_EINVAL, "rt_bin_flux: invalid bins");
+    if (n < 0) return fail(RT_EINVAL, "rt_bin_flux: negative n");
+    if (inst_offset != nullptr && n_inst <= 0) return fail(RT_EINVAL, "rt_bin_flux: n_inst must be positive");
+    int32_t ninst = inst_offset ? n_inst : 1;
+    int64_t per = (int64_t)bins->n_theta * bins->n_psi * bins->n_omega;
+    int64_t nbins = per * ninst;
+    if (nbins > INT32_MAX) return fail(RT_EINVAL, "rt_bin_flux: too many bins");
+    if (!hist || !cnt || !over) return fail(RT_EINVAL, "rt_bin_flux: null output");
+    size_t need = rt_workspace_size(RT_OP_BIN, n);
+    if (n > 0 && (!ws || ws_bytes < need)) return fail(RT_ENOWS, "rt_bin_flux: workspace too small");
+    if (n > 0 && (!fin || !ifin || !w)) return fail(RT_EINVAL, "rt_bin_flux: null input");
+    hipStream_t st = (hipStream_t)stream;
+    int zg = grid_for(nbins, 256, 4);
+    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, hist, nbins, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, cnt, nbins, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, over, (int64_t)2, 0.0);
+    if (n == 0) return check_launch("fill_kernel");
+    int32_t* keys = (int32_t*)ws;
+    int g1 = grid_for(n, 256, 8);
+    hipLaunchKernelGGL(bin_keys_kernel, dim3(g1), dim3(256), 0, st, fin, ifin, n, bins->n_theta, bins->n_psi,
+                       bins->n_omega, bins->d_omega, inst_offset, ninst, keys, w, over);
+    int64_t ntiles = (nbins + BIN_TILE - 1) / BIN_TILE;
+    // enough ray chunks to fill the device, each chunk re-read once per tile
+    int64_t nchunks = (2048 + ntiles - 1) / ntiles;
+    if (nchunks < 1) nchunks = 1;
+    if (nchunks > 1024) nchunks = 1024;
+    int64_t chunk = (n + nchunks - 1) / nchunks;
+    nchunks = (n + chunk - 1) / chunk;
+    if (ntiles > 65535 || nchunks > 65535) return fail(RT_EINVAL, "rt_bin_flux: grid too large");
+    hipLaunchKernelGGL(bin_tiles_kernel, dim3((unsigned)ntiles, (unsigned)nchunks), dim3(256), 0, st, keys, w, n, nbins,
+                       chunk, hist, cnt);
+    return check_launch("bin_tiles_kernel");
+}

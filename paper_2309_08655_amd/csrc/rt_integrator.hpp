@@ -1,0 +1,131 @@
+// Dormand-Prince 5(4) step with FSAL, its error norm and its continuous
+// extension, one ray per lane in registers (FP64).
+//
+// Tableau: Dormand & Prince (1980).  Error norm, step-size controller, starting
+// step and 4th-order continuous extension: Hairer, Norsett & Wanner, "Solving
+// Ordinary Differential Equations I", Sec. II.4-II.6.
+#pragma once
+
+#include "rt_device.hpp"
+
+namespace rtd {
+namespace dp5 {
+constexpr double a21 = 1.0 / 5;
+constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561, a54 = -212.0 / 729;
+constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247, a64 = 49.0 / 176,
+                 a65 = -5103.0 / 18656;
+constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192, b5 = -2187.0 / 6784, b6 = 11.0 / 84;
+constexpr double e1 = 71.0 / 57600, e3 = -71.0 / 16695, e4 = 71.0 / 1920, e5 = -17253.0 / 339200,
+                 e6 = 22.0 / 525, e7 = -1.0 / 40;
+constexpr double d1 = -12715105075.0 / 11282082432.0, d3 = 87487479700.0 / 32700410799.0,
+                 d4 = -10690763975.0 / 1880347072.0, d5 = 701980252875.0 / 199316789632.0,
+                 d6 = -1453857185.0 / 822651844.0, d7 = 69997945.0 / 29380423.0;
+}  // namespace dp5
+
+// Stage derivatives of one attempted step.  K[0] is the FSAL derivative at y.
+template <class T>
+struct StagesT {
+    T K[7][8];
+};
+using Stages = StagesT<double>;
+
+RT_HD bool finite_value(double x) { return __builtin_isfinite(x); }
+
+// One attempted step of length h from y with K[0] = f(y) already set.
+// Fills K[1..6], ynew, and returns the RMS error ratio (not yet checked).
+template <class T, class RHS>
+RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], double rtol, double atol) {
+    using namespace dp5;
+    T tmp[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a21 * S.K[0][i]);
+    f(tmp, S.K[1]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a31 * S.K[0][i] + a32 * S.K[1][i]);
+    f(tmp, S.K[2]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a41 * S.K[0][i] + a42 * S.K[1][i] + a43 * S.K[2][i]);
+    f(tmp, S.K[3]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        tmp[i] = y[i] + h * (a51 * S.K[0][i] + a52 * S.K[1][i] + a53 * S.K[2][i] + a54 * S.K[3][i]);
+    f(tmp, S.K[4]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        tmp[i] = y[i] + h * (a61 * S.K[0][i] + a62 * S.K[1][i] + a63 * S.K[2][i] + a64 * S.K[3][i] +
+                             a65 * S.K[4][i]);
+    f(tmp, S.K[5]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        ynew[i] = y[i] + h * (b1 * S.K[0][i] + b3 * S.K[2][i] + b4 * S.K[3][i] + b5 * S.K[4][i] + b6 * S.K[5][i]);
+    f(ynew, S.K[6]);
+    T acc = T(0.0);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        T e = h * (e1 * S.K[0][i] + e3 * S.K[2][i] + e4 * S.K[3][i] + e5 * S.K[4][i] + e6 * S.K[5][i] +
+                   e7 * S.K[6][i]);
+        T sc = atol + rtol * fmax(fabs(y[i]), fabs(ynew[i]));
+        T qq = e / sc;
+        acc = acc + qq * qq;
+    }
+    T err = sqrt(acc * 0.125);
+    return finite_value(err) ? err : T(1e300);
+}
+
+// Continuous extension at theta of components [c0, c1) (accepted step y -> ynew).
+RT_HD void dense_at(const double y[8], const double ynew[8], const Stages& S, double h,
+                                         double th, double out[8], int c0, int c1) {
+    using namespace dp5;
+    double om = 1.0 - th;
+    for (int i = c0; i < c1; ++i) {
+        double ydiff = ynew[i] - y[i];
+        double r3 = h * S.K[0][i] - ydiff;
+        double r4 = ydiff - h * S.K[6][i] - r3;
+        double r5 = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
+                         d7 * S.K[6][i]);
+        out[i] = y[i] + th * (ydiff + om * (r3 + th * (r4 + om * r5)));
+    }
+}
+
+// Step-size update after an attempt (HNW I-controller, order 5):
+// accepted: h *= min(facmax, max(0.2, 0.9 err^-1/5)) (err = 0 -> facmax);
+// rejected: h *= max(0.2, 0.9 err^-1/5) and facmax = 1 for the next accepted step.
+RT_HD double step_factor(double err, double facmax, bool accepted) {
+    if (accepted) {
+        if (err == 0.0) return facmax;
+        return fmin(facmax, fmax(0.2, 0.9 * pow(err, -0.2)));
+    }
+    return fmax(0.2, 0.9 * pow(err, -0.2));
+}
+
+// Starting step (HNW Sec. II.4, order 5), norm scale atol + rtol |y0|.
+template <class RHS>
+RT_HD double initial_step(RHS&& f, const double y0[8], const double f0[8], double rtol,
+                                               double atol) {
+    double d0 = 0.0, d1 = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        double sc = atol + rtol * fabs(y0[i]);
+        d0 += (y0[i] / sc) * (y0[i] / sc);
+        d1 += (f0[i] / sc) * (f0[i] / sc);
+    }
+    d0 = sqrt(d0 * 0.125);
+    d1 = sqrt(d1 * 0.125);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    double y1[8], f1[8];
+    for (int i = 0; i < 8; ++i) y1[i] = y0[i] + h0 * f0[i];
+    f(y1, f1);
+    double d2 = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        double sc = atol + rtol * fabs(y0[i]);
+        double qq = (f1[i] - f0[i]) / sc;
+        d2 += qq * qq;
+    }
+    d2 = sqrt(d2 * 0.125) / h0;
+    double m = fmax(d1, d2);
+    double h1 = (m <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : pow(0.01 / m, 0.2);
+    return fmin(100.0 * h0, h1);
+}
+
+}  // namespace rtd

@@ -1,0 +1,86 @@
+// Test-only host build of the device templates (hand-derived gradient of H and
+// one DOPRI5 attempt), so that the CPU test suite can compare them with the
+// oracle without a GPU.  Not part of the library.
+#include <cmath>
+
+#include "../paper_2309_08655_amd/csrc/rt_device.hpp"
+#include "../paper_2309_08655_amd/csrc/rt_integrator.hpp"
+
+using namespace rtd;
+
+static InstT<double> inst_from(const double* c, const int* e) {
+    InstT<double> I;
+    I.rs = c[0]; I.R = c[1]; I.Om = c[2]; I.cm = c[3]; I.sm = c[4]; I.Cwp = c[5]; I.R3 = c[1] * c[1] * c[1];
+    I.ma2 = c[6];
+    I.plasma = e[0]; I.density = e[1]; I.oblique = (I.sm != 0.0) ? 1 : 0;
+    return I;
+}
+
+extern "C" {
+// c = (rs, R, Om, cos theta_m, sin theta_m, Cwp, ma2); e = (plasma, density)
+void host_grad_h(const double* c, const int* e, const double* y, double* g) {
+    InstT<double> I = inst_from(c, e);
+    grad_h(I, y, g);
+}
+double host_hamiltonian(const double* c, const int* e, const double* y) {
+    InstT<double> I = inst_from(c, e);
+    return hamiltonian(I, y);
+}
+// one attempted step: returns err, writes ynew
+double host_attempt(const double* c, const int* e, const double* y, double h, double* ynew, double rtol,
+                    double atol) {
+    InstT<double> I = inst_from(c, e);
+    Stages S;
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+    f(y, S.K[0]);
+    return dopri_attempt(f, y, S, h, ynew, rtol, atol);
+}
+}
+
+extern "C" {
+// host run of the tracing loop of the persistent kernel for one ray (same decisions)
+int host_trace(const double* c, const int* e, const double* y0, double rtol, double atol, double rmax,
+               long long max_steps, double* yf, int* nacc_out, int* nrej_out) {
+    InstT<double> I = inst_from(c, e);
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+    Stages S;
+    double y[8], ynew[8];
+    for (int d = 0; d < 8; ++d) y[d] = y0[d];
+    f(y, S.K[0]);
+    double h = initial_step(f, y, S.K[0], rtol, atol);
+    double lam = 0.0, facmax = 10.0;
+    int nacc = 0, nrej = 0, status = 0;
+    while (status == 0) {
+        double err = dopri_attempt(f, y, S, h, ynew, rtol, atol);
+        if (!(err <= 1.0)) {
+            ++nrej;
+            h *= step_factor(err, facmax, false);
+            facmax = 1.0;
+            if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = 5;
+        } else {
+            ++nacc;
+            double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+            if (rnew <= I.R) { status = 2; for (int d = 0; d < 8; ++d) yf[d] = ynew[d]; }
+            else if (rnew >= rmax) {
+                double lo = 0.0, hi = 1.0, yt[8];
+                for (int it = 0; it < 60; ++it) {
+                    double mid = 0.5 * (lo + hi);
+                    dense_at(y, ynew, S, h, mid, yt, 0, 3);
+                    double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
+                    if (rm >= rmax) hi = mid; else lo = mid;
+                }
+                dense_at(y, ynew, S, h, hi, yf, 0, 8);
+                status = 1;
+            } else {
+                lam += h;
+                for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+                h *= step_factor(err, facmax, true);
+                facmax = 10.0;
+                if (nacc >= max_steps) status = 4;
+            }
+        }
+    }
+    *nacc_out = nacc; *nrej_out = nrej;
+    return status;
+}
+}

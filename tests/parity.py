@@ -1,0 +1,97 @@
+"""Comparison helpers for GPU-vs-oracle parity tests.
+
+Conditioning.  The Goldreich-Julian density is |rho|/e: the plasma frequency has a
+V-shaped minimum on the null surface Omega.B = 0, so the force -grad(w_p^2) is
+discontinuous there and rays that cross or are channelled along that surface make
+the adaptive step control reject many steps.  For such rays the discrete solution
+at rtol 1e-8 is ill-conditioned: perturbing the seed by one part in 1e15 changes the
+asymptotic direction by up to ~1e-5 rad (while rays that never cross it agree to
+~1e-11).  Two independent implementations differ at the roundoff level, so a per-ray
+tolerance below a ray's own conditioning is unattainable.  Each ray's conditioning
+is therefore measured with the oracle alone (the oracle re-run from seeds perturbed
+by 2^-50 relative) and the tolerance applied per class:
+  well-conditioned rays (oracle self-difference <= 1e-11 rad under four
+      perturbations, same step counts):
+      direction <= 1e-9 rad, |d omega| <= 1e-12 (the per-ray target);
+  ill-conditioned rays: direction <= 1e-4 rad (the discretisation-error scale:
+      rtol 1e-8 against rtol 1e-12 differs by up to ~5e-5 rad), and the distribution
+      of GPU-oracle differences no wider than 10x the oracle's own self-differences
+      (median and 90th percentile).
+Statuses must agree (a ray may switch between escaping and hitting the star only if
+it is ill-conditioned; at most 0.5% of rays)."""
+import numpy as np
+
+WELL_TOL = 1e-11     # oracle self-difference defining a well-conditioned ray [rad]
+DIR_TOL = 1e-9       # per-ray direction tolerance for well-conditioned rays [rad]
+OMEGA_TOL = 1e-12    # energy at infinity, well-conditioned rays
+ILL_DIR_TOL = 1e-4   # direction tolerance for ill-conditioned rays [rad]
+
+
+def unit(theta, phi):
+    return np.stack([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+
+
+def angle_between(th1, ph1, th2, ph2):
+    """angular distance, accurate for tiny angles"""
+    a, b = unit(th1, ph1), unit(th2, ph2)
+    return 2.0 * np.arcsin(np.clip(np.linalg.norm(a - b, axis=0) / 2.0, 0.0, 1.0))
+
+
+def oracle_conditioning(orc, star, tol, rays, status, fin_o, ifin_o):
+    """Per-ray self-difference of the oracle under 2^-50 relative perturbations (both
+    signs) of the seed position and momentum.  Returns (selfdiff[n], seq_changed[n])."""
+    eps = 2.0 ** -50
+    sd = np.zeros(rays.shape[1])
+    changed = np.zeros(rays.shape[1], dtype=bool)
+    for sl, f in ((slice(0, 3), 1 + eps), (slice(4, 7), 1 - eps), (slice(0, 3), 1 - eps), (slice(4, 7), 1 + eps)):
+        r2 = np.array(rays, copy=True)
+        r2[sl] *= f
+        fin2, ifin2 = orc.trace_forward(star, tol, r2, status)
+        d = angle_between(fin2[8], fin2[9], fin_o[8], fin_o[9])
+        sd = np.maximum(sd, np.where((ifin2[2] == 1) & (ifin_o[2] == 1), d, 0.0))
+        changed |= (ifin2[0] != ifin_o[0]) | (ifin2[1] != ifin_o[1]) | (ifin2[2] != ifin_o[2])
+    return sd, changed
+
+
+def assert_trace_parity(fin_g, ifin_g, fin_o, ifin_o, selfdiff, seq_changed, max_status_mismatch_frac=5e-3):
+    st_g, st_o = ifin_g[2], ifin_o[2]
+    well = (selfdiff <= WELL_TOL) & ~seq_changed
+    mism = st_g != st_o
+    assert not (mism & well).any(), ("status mismatch on well-conditioned rays", np.nonzero(mism & well)[0][:10])
+    assert mism.sum() <= max(1, max_status_mismatch_frac * len(st_o)), ("status mismatches", int(mism.sum()))
+    esc = (st_o == 1) & (st_g == 1)
+    d = angle_between(fin_g[8], fin_g[9], fin_o[8], fin_o[9])
+    dw = np.abs(fin_g[11] - fin_o[11])
+    wc = esc & well
+    ill = esc & ~well
+    out = dict(n=int(len(st_o)), escaped=int(esc.sum()), well=int(wc.sum()), ill=int(ill.sum()),
+               status_mismatch=int(mism.sum()),
+               max_dir_well=float(d[wc].max()) if wc.any() else 0.0,
+               max_domega_well=float(dw[wc].max()) if wc.any() else 0.0,
+               max_dir_ill=float(d[ill].max()) if ill.any() else 0.0)
+    assert out["max_dir_well"] <= DIR_TOL, out
+    assert out["max_domega_well"] <= OMEGA_TOL, out
+    assert out["max_dir_ill"] <= ILL_DIR_TOL, out
+    if ill.sum() >= 20:
+        for q in (0.5, 0.9):
+            a, b = np.quantile(d[ill], q), np.quantile(selfdiff[ill], q)
+            out[f"q{int(q * 100)}_ill_gpu"] = float(a)
+            out[f"q{int(q * 100)}_ill_self"] = float(b)
+            assert a <= 10.0 * b + 1e-12, (q, a, b, out)
+    return out
+
+
+def same_bin_mask(fin_a, ifin_a, fin_b, ifin_b, bins):
+    """rays that both runs put in the same (theta, psi, omega) bin"""
+    import math
+    dth, dps = math.pi / bins["n_theta"], 2 * math.pi / bins["n_psi"]
+
+    def key(fin, ifin):
+        it = np.minimum(np.floor(fin[8] / dth).astype(np.int64), bins["n_theta"] - 1)
+        ip = np.minimum(np.floor(fin[10] / dps).astype(np.int64), bins["n_psi"] - 1)
+        iw = np.floor((fin[11] - 1.0) / bins["d_omega"] + 0.5).astype(np.int64) + bins["n_omega"] // 2
+        k = (it * bins["n_psi"] + ip) * bins["n_omega"] + iw
+        return np.where(ifin[2] == 1, k, -1)
+
+    ka, kb = key(fin_a, ifin_a), key(fin_b, ifin_b)
+    return ka == kb, ka, kb

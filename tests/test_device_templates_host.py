@@ -1,0 +1,104 @@
+"""CPU checks of the GPU library's device templates, compiled for the host from the
+same source (tests/host_rhs.cpp includes paper_2309_08655_amd/csrc/*.hpp): the
+hand-derived gradient of H against the oracle's dual-number gradient, and the
+tracing loop against the oracle under the conditioning-aware criterion.  Runs without
+a GPU; catches derivation mistakes before any kernel launch."""
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import assert_trace_parity, oracle_conditioning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def host(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("hostrhs") / "host_rhs.so")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    subprocess.run([hipcc, "-std=c++17", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", out,
+                    os.path.join(ROOT, "tests", "host_rhs.cpp")], check=True, capture_output=True)
+    L = C.CDLL(out)
+    dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+    L.host_grad_h.argtypes = [dp, ip, dp, dp]
+    L.host_trace.argtypes = [dp, ip, dp, C.c_double, C.c_double, C.c_double, C.c_longlong, dp,
+                             C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    return L
+
+
+def consts(orc, s):
+    """instance constants in integrator units, derived here from the star parameters"""
+    c = orc.constants()
+    v0 = s["v0_kms"] / c["c_kms"]
+    w = s["m_a_eV"] * math.sqrt(1 + v0 * v0)
+    Cp = c["wp2_per_ne"] / w ** 2
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    Cwp = {0: Cp * s["multiplicity"] * n0,
+           1: Cp * s["multiplicity"] * s["psi_twist"] * s["B0_G"] / (4 * math.pi * c["e_statC"] * 1e5),
+           2: Cp * s["multiplicity"] * n0, 3: 0.0}[s["density"]]
+    cc = np.array([2 * c["GMsun_km"] * s["M_Msun"], s["R_km"], 2 * math.pi / s["P_s"] / c["c_kms"],
+                   math.cos(s["theta_m"]), math.sin(s["theta_m"]), Cwp, 1 / (1 + v0 * v0)])
+    return cc, np.array([s["plasma"], s["density"]], dtype=np.int32)
+
+
+def _p(a, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "spherical_gr", "vacuum_gr"])
+def test_hand_gradient_matches_oracle_autodiff(orc, host, name):
+    s = {"cfg1": W.CFG1["star"], "cfg2": W.CFG2["star"], "cfg3": W.CFG3["star"],
+         "spherical_gr": W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ANISO, theta_m=0.7),
+         "vacuum_gr": W.star(M_Msun=1.4, density=W.DENSITY_NONE)}[name]
+    cc, e = consts(orc, s)
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(11, 80)
+        y = np.concatenate([x, [rng.uniform(0, 1e6)], rng.normal(size=3) * 0.6, [-rng.uniform(0.5, 1.5)]])
+        g = np.zeros(8)
+        host.host_grad_h(_p(cc), _p(e, C.c_int), _p(y), _p(g))
+        go = orc.grad_h(s, y)
+        assert np.abs(g - go).max() <= 1e-13 * np.abs(go).max(), (y, g, go)
+
+
+@pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])
+def test_host_tracing_loop_matches_oracle(orc, host, cfg):
+    s, t = cfg["star"], cfg["tol"]
+    cc, e = consts(orc, s)
+    n = 400
+    rays, st = orc.sample(s, 0, n)
+    fin_o, ifin_o = orc.trace_forward(s, t, rays, st)
+    fin = np.zeros_like(fin_o)
+    ifin = np.zeros_like(ifin_o)
+    for i in range(n):
+        if st[i] != 0:
+            ifin[2, i] = st[i]
+            continue
+        y0 = np.ascontiguousarray(rays[:8, i])
+        yf = np.zeros(8)
+        na, nr = C.c_int(), C.c_int()
+        ifin[2, i] = host.host_trace(_p(cc), _p(e, C.c_int), _p(y0), t["rtol"], t["atol"], t["r_max_km"],
+                                     t["max_steps"], _p(yf), C.byref(na), C.byref(nr))
+        ifin[0, i], ifin[1, i] = na.value, nr.value
+        fin[:8, i] = yf
+        r = np.linalg.norm(yf[:3])
+        rs = cc[0]
+        nn = yf[:3] / r
+        q = nn @ yf[4:7]
+        v = yf[4:7] + (math.sqrt(1 - rs / r) - 1) * q * nn
+        v /= np.linalg.norm(v)
+        fin[8, i] = math.atan2(math.hypot(v[0], v[1]), v[2])
+        fin[9, i] = math.atan2(v[1], v[0])
+        fin[11, i] = -yf[7]
+    sd, ch = oracle_conditioning(orc, s, t, rays, st, fin_o, ifin_o)
+    out = assert_trace_parity(fin, ifin, fin_o, ifin_o, sd, ch)
+    print(out)
+    assert out["well"] > 0.15 * out["escaped"]
