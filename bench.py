@@ -64,7 +64,18 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=src.numel() * 8, repeats=5)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the tracer shards rays across GPUs by index with no "
               "communication until one histogram all-reduce, which this build does not run; use --gpus 1.",
@@ -124,6 +135,9 @@ def main():
 
     ifn = ifin.cpu().numpy()
     stn = status.cpu().numpy()
+    # wave-iterations of the persistent loop (third 64-bit word of the work counter)
+    wave_iters = int(ws[16:24].cpu().numpy().view(np.uint64)[0])
+    att = (ifn[0].astype(np.int64) + ifn[1])[stn == 0]
     acc = float(ifn[0].astype(np.float64).sum())
     rej = float(ifn[1].astype(np.float64).sum())
     n_traced = float((stn == 0).sum())
@@ -147,7 +161,11 @@ def main():
                data="synthetic",
                config=dict(workload=cfg["name"], rays_per_step=n, form="plain",
                            rays_per_s=rays_per_s, accepted_steps=acc, rejected_steps=rej,
-                           statuses={str(k): int(v) for k, v in zip(*np.unique(ifn[2], return_counts=True))}),
+                           statuses={str(k): int(v) for k, v in zip(*np.unique(ifn[2], return_counts=True))},
+                           lane_efficiency=(acc + rej) / max(1, 64 * wave_iters),
+                           attempts_per_ray=dict(mean=float(att.mean()), p99=float(np.percentile(att, 99)),
+                                                 p9999=float(np.percentile(att, 99.99)), max=int(att.max())),
+                           schedule=sched),
                roofline=roofline)
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))

@@ -93,7 +93,8 @@ typedef struct rt_schedule {
     int32_t block;        /* threads per workgroup: 64, 128 or 256 */
     int32_t waves_per_cu; /* resident waves per CU requested (0 = occupancy limit) */
     int32_t refill_min;   /* idle lanes a wave waits for before refilling from the queue */
-    int32_t chunk;        /* queue entries taken per refilled lane (reserved, 1) */
+    int32_t occupancy;    /* register budget of the tracing kernels: 1 = one wave per SIMD (no
+                             spills), 2 = two waves per SIMD (a few spills to scratch) */
 } rt_schedule;
 
 /* Number of doubles / int32 per final record (fin: "[RT_NFIN][n]", ifin: "[RT_NIFIN][n]"):

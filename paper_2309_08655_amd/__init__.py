@@ -43,7 +43,8 @@ class RtImage(C.Structure):
 
 
 class RtSchedule(C.Structure):
-    _fields_ = [("block", C.c_int32), ("waves_per_cu", C.c_int32), ("refill_min", C.c_int32), ("chunk", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("waves_per_cu", C.c_int32), ("refill_min", C.c_int32),
+                ("occupancy", C.c_int32)]
 
 
 class RtError(RuntimeError):
@@ -115,7 +116,7 @@ def make_image(d: dict) -> RtImage:
 def make_schedule(d: dict | None):
     if d is None:
         return None
-    return RtSchedule(d.get("block", 256), d.get("waves_per_cu", 0), d.get("refill_min", 16), d.get("chunk", 1))
+    return RtSchedule(d.get("block", 256), d.get("waves_per_cu", 0), d.get("refill_min", 4), d.get("occupancy", 2))
 
 
 def _ptr(t: torch.Tensor | None):
@@ -194,14 +195,15 @@ def rt_bin_flux(fin: torch.Tensor, ifin: torch.Tensor, w: torch.Tensor, bins: di
 def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: dict | None = None, ws=None):
     dev = _device()
     n = image["nx"] * image["ny"]
-    ev = torch.empty((K, RT_NEV, n), dtype=torch.float64, device=dev)
+    ev = torch.empty((max(K, 1), RT_NEV, n), dtype=torch.float64, device=dev)[:K]
     nev = torch.empty(n, dtype=torch.int32, device=dev)
     fin = torch.empty((RT_NFIN, n), dtype=torch.float64, device=dev)
     ifin = torch.empty((RT_NIFIN, n), dtype=torch.int32, device=dev)
     ws = workspace(OP_TRACE_BACKWARD, n) if ws is None else ws
     s, t, im = make_star(star), make_tol(tol), make_image(image)
     sc = make_schedule(schedule)
-    _check(lib().rt_trace_backward(C.byref(s), C.byref(t), C.byref(im), K, _ptr(ev), _ptr(nev), _ptr(fin),
+    _check(lib().rt_trace_backward(C.byref(s), C.byref(t), C.byref(im), K, C.c_void_p(ev.data_ptr()), _ptr(nev),
+                                   _ptr(fin),
                                    _ptr(ifin), _ptr(ws), ws.numel(), C.byref(sc) if sc is not None else None,
                                    _stream()), "rt_trace_backward")
     return ev, nev, fin, ifin

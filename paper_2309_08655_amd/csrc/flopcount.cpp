@@ -28,6 +28,8 @@ inline FC operator/(double a, FC b) { ++g_flops; return FC(a / b.v); }
 inline FC operator-(FC a) { return FC(-a.v); }
 inline FC sqrt(FC a) { ++g_flops; return FC(std::sqrt(a.v)); }
 inline FC rcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
+inline FC frcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
+inline FC frsqrt(FC a) { ++g_flops; return FC(1.0 / std::sqrt(a.v)); }
 inline FC fabs(FC a) { return FC(std::fabs(a.v)); }
 inline FC fmax(FC a, FC b) { return FC(std::fmax(a.v, b.v)); }
 inline void sincos_t(FC a, FC* s, FC* c) { g_flops += 2; s->v = std::sin(a.v); c->v = std::cos(a.v); }

@@ -127,12 +127,13 @@ rt_schedule resolve_schedule(const rt_schedule* s) {
     rt_schedule r;
     r.block = 256;
     r.waves_per_cu = 0;
-    r.refill_min = 16;
-    r.chunk = 1;
+    r.refill_min = 4;
+    r.occupancy = 2;
     if (s) {
         if (s->block == 64 || s->block == 128 || s->block == 256) r.block = s->block;
         if (s->waves_per_cu > 0 && s->waves_per_cu <= 32) r.waves_per_cu = s->waves_per_cu;
         if (s->refill_min >= 1 && s->refill_min <= 64) r.refill_min = s->refill_min;
+        if (s->occupancy == 1 || s->occupancy == 2) r.occupancy = s->occupancy;
     }
     return r;
 }
@@ -150,6 +151,67 @@ int persistent_grid(const rt_schedule& sc, const void* kernel, int block) {
     return cus * per_cu;
 }
 
+// ---------------------------------------------------------------------------
+// counting sort of the work list by bucket key
+// ---------------------------------------------------------------------------
+static __global__ void order_clear_kernel(int32_t* buckets, WorkCtr* ctr) {
+    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) buckets[b] = 0;
+    if (threadIdx.x == 0) { ctr->head = 0ull; ctr->len = 0ull; ctr->iters = 0ull; }
+}
+
+static __global__ void order_hist_kernel(const int32_t* __restrict__ keys, int64_t n, int32_t* buckets) {
+    __shared__ int32_t sh[ORDER_BUCKETS];
+    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) sh[b] = 0;
+    __syncthreads();
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t k = keys[i];
+        if (k >= 0 && k < ORDER_BUCKETS) atomicAdd(&sh[k], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x)
+        if (sh[b]) atomicAdd(&buckets[b], sh[b]);
+}
+
+// exclusive prefix sum over the buckets (one workgroup of 1024 threads, 4 buckets each)
+static __global__ void __launch_bounds__(1024) order_scan_kernel(int32_t* buckets, WorkCtr* ctr) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    int32_t v[4], s = 0;
+    for (int q = 0; q < 4; ++q) { v[q] = buckets[4 * t + q]; s += v[q]; }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t add = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int32_t base = part[t] - s;
+    for (int q = 0; q < 4; ++q) { buckets[4 * t + q] = base; base += v[q]; }
+    if (t == 1023) ctr->len = (unsigned long long)part[1023];
+}
+
+static __global__ void order_scatter_kernel(const int32_t* __restrict__ keys, int64_t n, int32_t* buckets,
+                                            int32_t* __restrict__ list) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int32_t k = keys[i];
+        if (k >= 0 && k < ORDER_BUCKETS) list[atomicAdd(&buckets[k], 1)] = (int32_t)i;
+    }
+}
+
+int order_work_list(const FwdWs& W, int64_t n, hipStream_t st) {
+    static_assert(ORDER_BUCKETS == 4096, "scan kernel assumes 4096 buckets");
+    hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(256), 0, st, W.buckets, W.ctr);
+    int g = grid_for(n, 256, 16);
+    hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, st, W.keys, n, W.buckets);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, st, W.buckets, W.ctr);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.keys, n, W.buckets,
+                       W.list);
+    return check_launch("order_work_list");
+}
+
 }  // namespace rtd
 
 using namespace rtd;
@@ -158,9 +220,10 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
     if (n < 0) n = 0;
     switch (op) {
         case RT_OP_TRACE_FORWARD:
-        case RT_OP_TRACE_BACKWARD:
         case RT_OP_BATCHED:
             return fwd_ws_bytes(n);
+        case RT_OP_TRACE_BACKWARD:  // + initial states of the pixels
+            return fwd_ws_bytes(n) + align256(sizeof(double) * 8 * (size_t)n);
         case RT_OP_BIN:
             return align256(sizeof(int32_t) * (size_t)n);
         default:

@@ -61,16 +61,25 @@ SeedC make_seed_consts(const rt_star& s);
 // workspace of the persistent kernels
 // ---------------------------------------------------------------------------
 struct WorkCtr {
-    unsigned long long head;  // next list entry to hand out
-    unsigned long long len;   // list length
-    unsigned long long pad[30];
+    unsigned long long head;   // next list entry to hand out
+    unsigned long long len;    // list length
+    unsigned long long iters;  // wave-iterations of the persistent loop (lane efficiency diagnostic)
+    unsigned long long pad[29];
 };
+
+// Work-list ordering: rays are handed out in ascending order of a cost key (a
+// bucket of log2(r/R) of the seed radius for forward rays: rays seeded deep in
+// the magnetosphere take the most steps), so long rays start first and the
+// persistent kernel's tail stays short.
+constexpr int ORDER_BUCKETS = 4096;
 
 struct FwdWs {
     WorkCtr* ctr;
     int32_t* list;
     double* h0;
     double* k1;
+    int32_t* keys;     // [n] bucket of each ray (-1: not traced)
+    int32_t* buckets;  // [ORDER_BUCKETS] counts, then insertion offsets
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -85,13 +94,21 @@ inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     W.h0 = (double*)p;
     p += align256(sizeof(double) * (size_t)n);
     W.k1 = (double*)p;
+    p += align256(sizeof(double) * 8 * (size_t)n);
+    W.keys = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)n);
+    W.buckets = (int32_t*)p;
     return W;
 }
 
 inline size_t fwd_ws_bytes(int64_t n) {
     return align256(sizeof(WorkCtr)) + align256(sizeof(int32_t) * (size_t)n) + align256(sizeof(double) * (size_t)n) +
-           align256(sizeof(double) * 8 * (size_t)n);
+           align256(sizeof(double) * 8 * (size_t)n) + align256(sizeof(int32_t) * (size_t)n) +
+           align256(sizeof(int32_t) * ORDER_BUCKETS);
 }
+
+// builds W.list from W.keys (counting sort by bucket; order inside a bucket is arbitrary)
+int order_work_list(const FwdWs& W, int64_t n, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // launch geometry
@@ -117,7 +134,7 @@ int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& 
 
 // small utility kernels (defined per translation unit)
 static __global__ void zero_ctr_kernel(WorkCtr* c) {
-    if (threadIdx.x == 0) { c->head = 0ull; c->len = 0ull; }
+    if (threadIdx.x == 0) { c->head = 0ull; c->len = 0ull; c->iters = 0ull; }
 }
 static __global__ void fill_kernel(double* p, int64_t n, double v) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;

@@ -98,6 +98,37 @@ template <int N> RT_HD void sincos_t(const gdual<N>& a, gdual<N>* s, gdual<N>* c
     for (int i = 0; i < N; ++i) { s->d[i] = cv * a.d[i]; c->d[i] = -sv * a.d[i]; }
 }
 RT_HD double rcp(double a) { return 1.0 / a; }
+RT_HD double fabs_v(double a) { return fabs(a); }
+
+// Reciprocal and reciprocal square root from the hardware estimates (v_rcp_f64,
+// v_rsq_f64) refined by two Newton steps: within about one ulp for the normal,
+// finite arguments that occur here, at a fraction of the cost of a correctly
+// rounded division or square root.  Host builds use the exact operations.
+RT_HD double frcp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
+}
+RT_HD double frsqrt(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double y = __builtin_amdgcn_rsq(x);
+    double hx = 0.5 * x;
+    double e = fma(-(hx * y), y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-(hx * y), y, 0.5);
+    return fma(y, e, y);
+#else
+    return 1.0 / ::sqrt(x);
+#endif
+}
+template <int N> RT_HD gdual<N> frcp(const gdual<N>& a) { return rcp(a); }
+template <int N> RT_HD gdual<N> frsqrt(const gdual<N>& a) { return rcp(sqrt(a)); }
 RT_HD void sincos_t(double a, double* s, double* c) { ::sincos(a, s, c); }
 RT_HD double value(double a) { return a; }
 template <int N> RT_HD double value(const gdual<N>& a) { return a.v; }
@@ -146,12 +177,86 @@ struct Plasma {
     T P, gx, gy, gz, gt;
 };
 
+// sin and cos of a rotation angle from Taylor polynomials (the series of sin and
+// cos truncated after x^13 and x^14, error below 3e-17 for |x| <= 1/2), after
+// halving the angle until |x| <= 1/2 and doubling back.  No table, no library call.
+template <class T>
+RT_HD void small_angle_sincos(T x, T* s, T* c) {
+    int k = 0;
+    while (!(fabs(value(x)) <= 0.5) && k < 64) { x = 0.5 * x; ++k; }
+    T x2 = x * x;
+    T ps = 1.0 / 6227020800.0;
+    ps = -1.0 / 39916800.0 + x2 * ps;
+    ps = 1.0 / 362880.0 + x2 * ps;
+    ps = -1.0 / 5040.0 + x2 * ps;
+    ps = 1.0 / 120.0 + x2 * ps;
+    ps = -1.0 / 6.0 + x2 * ps;
+    T sn = x + (x * x2) * ps;
+    T pc = -1.0 / 87178291200.0;
+    pc = 1.0 / 479001600.0 + x2 * pc;
+    pc = -1.0 / 3628800.0 + x2 * pc;
+    pc = 1.0 / 40320.0 + x2 * pc;
+    pc = -1.0 / 720.0 + x2 * pc;
+    pc = 1.0 / 24.0 + x2 * pc;
+    pc = -0.5 + x2 * pc;
+    T cs = 1.0 + x2 * pc;
+    for (; k > 0; --k) {
+        T s2 = 2.0 * (sn * cs);
+        T c2 = cs * cs - sn * sn;
+        sn = s2;
+        cs = c2;
+    }
+    *s = sn;
+    *c = cs;
+}
+
+// Rotation phase of the magnetic axis relative to a reference time t0 at which
+// (cos, sin)(Omega t0) = (c0, s0) are known; the tracing kernels keep the
+// reference at the start of the current step, so the per-stage angle is small.
+struct AxisRef {
+    double t0, c0, s0;
+};
+
+// reference phase at time t (angle reduced to [-pi, pi] first)
+template <class T>
+RT_HD AxisRef axis_ref_at(const InstT<T>& I, double t) {
+    AxisRef r;
+    r.t0 = t;
+    double x = value(I.Om) * t;
+    x -= 6.283185307179586 * rint(x * 0.15915494309189535);
+    double s, c;
+    small_angle_sincos(x, &s, &c);
+    r.c0 = c;
+    r.s0 = s;
+    return r;
+}
+
+// move the reference to time t (rotation by the small step angle, renormalised)
+template <class T>
+RT_HD void axis_ref_advance(const InstT<T>& I, AxisRef& r, double t) {
+    double sd, cd;
+    small_angle_sincos(value(I.Om) * (t - r.t0), &sd, &cd);
+    double c = r.c0 * cd - r.s0 * sd;
+    double s = r.s0 * cd + r.c0 * sd;
+    double nrm = frsqrt(c * c + s * s);
+    r.c0 = c * nrm;
+    r.s0 = s * nrm;
+    r.t0 = t;
+}
+
 // magnetic axis m(t) and its time derivative
 template <class T>
-RT_HD void magnetic_axis(const InstT<T>& I, const T& t, T m[3], T mt[3]) {
+RT_HD void magnetic_axis(const InstT<T>& I, const T& t, T m[3], T mt[3], const AxisRef* ref = nullptr) {
     if (I.oblique) {
         T s, c;
-        sincos_t(I.Om * t, &s, &c);
+        if (ref != nullptr) {
+            T sd, cd;
+            small_angle_sincos(I.Om * (t - ref->t0), &sd, &cd);
+            c = ref->c0 * cd - ref->s0 * sd;
+            s = ref->s0 * cd + ref->c0 * sd;
+        } else {
+            sincos_t(I.Om * t, &s, &c);
+        }
         m[0] = I.sm * c; m[1] = I.sm * s; m[2] = I.cm;
         T w = I.Om * I.sm;
         mt[0] = -(w * s); mt[1] = w * c; mt[2] = T(0.0);
@@ -214,15 +319,17 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
 // gradient of H: g = (dH/dx, dH/dy, dH/dz, dH/dt, dH/dk_x, dH/dk_y, dH/dk_z, dH/dk_t)
 // ----------------------------------------------------------------------------
 template <class T>
-RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
+RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = nullptr) {
     const T& kx = y[4]; const T& ky = y[5]; const T& kz = y[6]; const T& kt = y[7];
     T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-    T r = sqrt(r2);
-    T ir = rcp(r);
+    T ir = frsqrt(r2);
     T n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
     T s = I.rs * ir;
     T A = 1.0 - s;
-    T iA = rcp(A);
+    // 1/sqrt(A) serves the anisotropic term; 1/A follows from it
+    const bool aniso = (I.plasma == PL_ANISO) && (I.density != DEN_NONE);
+    T ia = aniso ? frsqrt(A) : T(0.0);
+    T iA = aniso ? ia * ia : frcp(A);
     T q = n[0] * kx + n[1] * ky + n[2] * kz;
     T kt2 = kt * kt;
     // vacuum: dH/dk = 2k - 2 s q n; dH/dk_t = -2 k_t / A;
@@ -242,7 +349,7 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
     if (I.density == DEN_NONE) return;
 
     T m[3], mt[3];
-    magnetic_axis(I, y[3], m, mt);
+    magnetic_axis(I, y[3], m, mt, ref);
     T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
     T dmu = mt[0] * n[0] + mt[1] * n[1] + mt[2] * n[2];
     Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
@@ -252,12 +359,13 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
         return;
     }
     // anisotropic (strong-B LO mode): H += P (1 - K)
-    T a = sqrt(A);
+    T a = A * ia;
     T b = 1.0 + 2.0 * a;
     T mk = m[0] * kx + m[1] * ky + m[2] * kz;
     T Nn = b * mu * q - mk;
-    T den = rcp(1.0 + 3.0 * mu * mu);
-    T ikt2 = rcp(kt2);
+    T den = frcp(1.0 + 3.0 * mu * mu);
+    T ikt = frcp(kt);
+    T ikt2 = ikt * ikt;
     T N2d = Nn * Nn * ikt2 * den;  // N^2 / (k_t^2 (1 + 3 mu^2))
     T K = A * N2d;
     T c1 = 2.0 * A * Nn * ikt2 * den;  // dK/dN
@@ -268,10 +376,10 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
     g[5] = g[5] - PK * (bmu * n[1] - m[1]);
     g[6] = g[6] - PK * (bmu * n[2] - m[2]);
     // dK/dk_t = -2 K / k_t  ->  dH/dk_t += 2 P K / k_t
-    g[7] = g[7] + 2.0 * p.P * K * rcp(kt);
+    g[7] = g[7] + 2.0 * p.P * K * ikt;
     // dN/dx = (mu q s /(a r)) n + b [q (m - mu n) + mu (k - q n)] / r
     // dK/dx = N2d (s/r) n + c1 dN/dx - 6 K mu den (m - mu n) / r
-    T e_n = N2d * sr + c1 * (mu * q * s * ir * rcp(a)) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
+    T e_n = N2d * sr + c1 * (mu * q * s * ir * ia) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
     T e_m = c1 * b * ir * q - 6.0 * K * mu * den * ir;
     T e_k = c1 * b * ir * mu;
     T omK = 1.0 - K;
@@ -288,9 +396,9 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8]) {
 
 // Hamilton's equations, eq. (Hamilton); sign = -1 integrates backwards in the worldline parameter.
 template <class T>
-RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign) {
+RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign, const AxisRef* ref = nullptr) {
     T g[8];
-    grad_h(I, y, g);
+    grad_h(I, y, g, ref);
     for (int i = 0; i < 4; ++i) {
         f[i] = sign * g[4 + i];
         f[4 + i] = -sign * g[i];
@@ -299,7 +407,7 @@ RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign) {
 
 // H itself (health checks and the backward event function)
 template <class T>
-RT_HD T hamiltonian(const InstT<T>& I, const T y[8]) {
+RT_HD T hamiltonian(const InstT<T>& I, const T y[8], const AxisRef* ref = nullptr) {
     T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
     T r = sqrt(r2);
     T ir = rcp(r);
@@ -311,7 +419,7 @@ RT_HD T hamiltonian(const InstT<T>& I, const T y[8]) {
     T Hv = -(y[7] * y[7]) * rcp(A) + kk - s * q * q;
     if (I.density == DEN_NONE) return Hv;
     T m[3], mt[3];
-    magnetic_axis(I, y[3], m, mt);
+    magnetic_axis(I, y[3], m, mt, ref);
     T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
     T dmu = T(0.0);
     Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
@@ -326,12 +434,11 @@ RT_HD T hamiltonian(const InstT<T>& I, const T y[8]) {
 // g^{mu nu} k_mu k_nu (vacuum part of H)
 template <class T>
 RT_HD T g_kk(const InstT<T>& I, const T y[8]) {
-    T r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    T ir = rcp(r);
+    T ir = frsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
     T s = I.rs * ir;
     T q = (y[0] * y[4] + y[1] * y[5] + y[2] * y[6]) * ir;
     T kk = y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
-    return -(y[7] * y[7]) * rcp(1.0 - s) + kk - s * q * q;
+    return -(y[7] * y[7]) * frcp(1.0 - s) + kk - s * q * q;
 }
 
 // dipole field direction u = 3 mu n - m (|u|^2 = 1 + 3 mu^2) and magnitude factor

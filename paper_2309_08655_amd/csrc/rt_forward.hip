@@ -189,21 +189,19 @@ __global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedC C, u
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
                                                          const int32_t* __restrict__ status, int64_t n,
-                                                         WorkCtr* ctr, int32_t* __restrict__ list,
-                                                         double* __restrict__ h0s, double* __restrict__ k1s,
-                                                         double* __restrict__ fin, int32_t* __restrict__ ifin) {
+                                                         int32_t* __restrict__ keys, double* __restrict__ h0s,
+                                                         double* __restrict__ k1s, double* __restrict__ fin,
+                                                         int32_t* __restrict__ ifin) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        int64_t j = base + threadIdx.x;
-        bool valid = j < n;
-        bool ok = valid && (status == nullptr || status[j] == ST_OK);
-        if (valid && !ok) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        bool ok = (status == nullptr || status[j] == ST_OK);
+        int32_t key = -1;
+        if (!ok) {
             for (int d = 0; d < RT_NFIN_; ++d) fin[d * n + j] = 0.0;
             ifin[j] = 0;
             ifin[n + j] = 0;
             ifin[2 * n + j] = status[j];
-        }
-        if (ok) {
+        } else {
             double y[8], f0[8];
             for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
             auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
@@ -211,60 +209,21 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I, TolC t
             double h = initial_step(f, y, f0, tol.rtol, tol.atol);
             h0s[j] = h;
             for (int d = 0; d < 8; ++d) k1s[d * n + j] = f0[d];
+            // cost key: rays seeded close to the star take the most steps
+            double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+            double u = log2(fmax(r / I.R, 1.0)) * (ORDER_BUCKETS / 8.0);
+            key = (u >= 0.0 && u < (double)(ORDER_BUCKETS - 1)) ? (int32_t)u : ORDER_BUCKETS - 1;
         }
-        // wave-aggregated append to the work list
-        unsigned long long mask = __ballot(ok);
-        if (mask) {
-            int lane = __lane_id();
-            int leader = __ffsll((long long)mask) - 1;
-            unsigned long long pos = 0;
-            if (lane == leader) pos = atomicAdd(&ctr->len, (unsigned long long)__popcll(mask));
-            pos = __shfl(pos, leader);
-            if (ok) {
-                unsigned long long below = mask & ((1ull << lane) - 1ull);
-                list[pos + __popcll(below)] = (int32_t)j;
-            }
-        }
+        keys[j] = key;
     }
-}
-
-__device__ __forceinline__ void write_final(const InstT<double>& I, const double yf[8], double lam, double h,
-                                            int nacc, int nrej, int status, int64_t j, int64_t n,
-                                            double* __restrict__ fin, int32_t* __restrict__ ifin) {
-    double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
-    double ir = 1.0 / r;
-    double nn[3] = {yf[0] * ir, yf[1] * ir, yf[2] * ir};
-    double A = 1.0 - I.rs * ir;
-    double q = nn[0] * yf[4] + nn[1] * yf[5] + nn[2] * yf[6];
-    double c = (sqrt(A) - 1.0) * q;
-    double v[3] = {yf[4] + c * nn[0], yf[5] + c * nn[1], yf[6] + c * nn[2]};
-    double vn = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    v[0] *= vn; v[1] *= vn; v[2] *= vn;
-    double theta = atan2(sqrt(v[0] * v[0] + v[1] * v[1]), v[2]);
-    double phi = atan2(v[1], v[0]);
-    double psi = fmod(phi - I.Om * (yf[3] - r), 2.0 * M_PI);
-    if (psi < 0.0) psi += 2.0 * M_PI;
-    if (psi >= 2.0 * M_PI) psi -= 2.0 * M_PI;
-    for (int d = 0; d < 8; ++d) fin[d * n + j] = yf[d];
-    fin[8 * n + j] = theta;
-    fin[9 * n + j] = phi;
-    fin[10 * n + j] = psi;
-    fin[11 * n + j] = -yf[7];
-    fin[12 * n + j] = hamiltonian(I, yf);
-    fin[13 * n + j] = lam;
-    fin[14 * n + j] = r;
-    fin[15 * n + j] = h;
-    ifin[j] = nacc;
-    ifin[n + j] = nrej;
-    ifin[2 * n + j] = status;
 }
 
 // ----------------------------------------------------------------------------
 // persistent tracing kernel: each lane integrates rays taken from the work list
 // until the list is exhausted; a wave refills its idle lanes with one atomic
 // ----------------------------------------------------------------------------
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
+template <int BLOCK, int MINW>
+__global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
                                                           int64_t n, WorkCtr* ctr, const int32_t* __restrict__ list,
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
@@ -272,6 +231,7 @@ __global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC 
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
+    unsigned long long iters = 0;
     bool active = false;
     bool exhausted = false;
     int64_t j = 0;
@@ -282,7 +242,8 @@ __global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC 
     for (int d = 0; d < 8; ++d) { y[d] = 0.0; S.K[0][d] = 0.0; }
     y[0] = 1e4;  // harmless dummy state for idle lanes
     y[7] = -1.0;
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+    AxisRef ref = axis_ref_at(I, 0.0);
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref); };
 
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -300,6 +261,7 @@ __global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC 
                         for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
                         h = h0s[j];
                         lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
+                        if (I.oblique) ref = axis_ref_at(I, y[3]);
                         active = true;
                     }
                 }
@@ -310,57 +272,100 @@ __global__ void __launch_bounds__(BLOCK) trace_fwd_kernel(InstT<double> I, TolC 
             if (exhausted) break;
             continue;
         }
+        ++iters;
 
         double err = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
-        if (active) {
-            bool acc = err <= 1.0;
-            if (!acc) {
-                ++nrej;
-                h *= step_factor(err, facmax, false);
-                facmax = 1.0;
-                if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) {
-                    write_final(I, y, lam, h, nacc, nrej, ST_STEP_UNDERFLOW, j, n, fin, ifin);
-                    active = false;
+        if (!active) continue;
+        // on termination y holds the final state (the raw record is completed by
+        // finalize_kernel, which keeps the observables out of this loop)
+        int status = ST_OK;
+        double lam_out = lam;
+        if (!(err <= 1.0)) {
+            ++nrej;
+            h *= step_factor(err, facmax, false);
+            facmax = 1.0;
+            if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
+        } else {
+            ++nacc;
+            double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+            bool finite_ok = true;
+            for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(ynew[d]);
+            if (finite_ok && rnew >= tol.rmax) {
+                // locate r(theta) = r_max on the continuous extension (60 bisections)
+                double lo = 0.0, hi = 1.0;
+                double yt[8];
+                for (int it = 0; it < 60; ++it) {
+                    double mid = 0.5 * (lo + hi);
+                    dense_at(y, ynew, S, h, mid, yt, 0, 3);
+                    double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
+                    if (rm >= tol.rmax) hi = mid; else lo = mid;
                 }
+                dense_at(y, ynew, S, h, hi, yt, 0, 8);
+                for (int d = 0; d < 8; ++d) y[d] = yt[d];
+                status = ST_ESCAPED;
+                lam_out = lam + hi * h;
             } else {
-                ++nacc;
-                double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
-                bool fin_ok = true;
-                for (int d = 0; d < 8; ++d) fin_ok = fin_ok && isfinite(ynew[d]);
-                if (!fin_ok) {
-                    write_final(I, ynew, lam + h, h, nacc, nrej, ST_NONFINITE, j, n, fin, ifin);
-                    active = false;
+                if (I.oblique && finite_ok && rnew > I.R) axis_ref_advance(I, ref, ynew[3]);
+                for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+                lam += h;
+                lam_out = lam;
+                if (!finite_ok) {
+                    status = ST_NONFINITE;
                 } else if (rnew <= I.R) {
-                    write_final(I, ynew, lam + h, h, nacc, nrej, ST_HIT_STAR, j, n, fin, ifin);
-                    active = false;
-                } else if (rnew >= tol.rmax) {
-                    // locate r(theta) = r_max on the continuous extension (60 bisections)
-                    double lo = 0.0, hi = 1.0;
-                    double yt[8];
-                    for (int it = 0; it < 60; ++it) {
-                        double mid = 0.5 * (lo + hi);
-                        dense_at(y, ynew, S, h, mid, yt, 0, 3);
-                        double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
-                        if (rm >= tol.rmax) hi = mid; else lo = mid;
-                    }
-                    dense_at(y, ynew, S, h, hi, yt, 0, 8);
-                    write_final(I, yt, lam + hi * h, h, nacc, nrej, ST_ESCAPED, j, n, fin, ifin);
-                    active = false;
+                    status = ST_HIT_STAR;
                 } else {
-                    lam += h;
-                    for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
                     h *= step_factor(err, facmax, true);
                     facmax = 10.0;
-                    if (nacc >= tol.max_steps) {
-                        write_final(I, y, lam, h, nacc, nrej, ST_MAX_STEPS, j, n, fin, ifin);
-                        active = false;
-                    } else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) {
-                        write_final(I, y, lam, h, nacc, nrej, ST_STEP_UNDERFLOW, j, n, fin, ifin);
-                        active = false;
-                    }
+                    if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
+                    else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
                 }
             }
         }
+        if (status != ST_OK) {
+            for (int d = 0; d < 8; ++d) fin[d * n + j] = y[d];
+            fin[13 * n + j] = lam_out;
+            fin[15 * n + j] = h;
+            ifin[j] = nacc;
+            ifin[n + j] = nrej;
+            ifin[2 * n + j] = status;
+            active = false;
+        }
+    }
+    if (lane == 0) atomicAdd(&ctr->iters, iters);
+}
+
+// Observables of every traced ray from its final state (Sec. 2.2: the asymptotic
+// direction is binned on the sky): static-frame direction (theta, phi), the
+// azimuth psi in the frame co-rotating with the star at the arrival time t - r,
+// the energy at infinity -k_t, H and r.
+__global__ void __launch_bounds__(256) finalize_kernel(InstT<double> I, const int32_t* __restrict__ list,
+                                                       const WorkCtr* ctr, int64_t n, double* __restrict__ fin) {
+    const int64_t nlist = (int64_t)ctr->len;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nlist; q += stride) {
+        int64_t j = list[q];
+        double yf[8];
+        for (int d = 0; d < 8; ++d) yf[d] = fin[d * n + j];
+        double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
+        double ir = 1.0 / r;
+        double nn[3] = {yf[0] * ir, yf[1] * ir, yf[2] * ir};
+        double A = 1.0 - I.rs * ir;
+        double qn = nn[0] * yf[4] + nn[1] * yf[5] + nn[2] * yf[6];
+        double c = (sqrt(A) - 1.0) * qn;
+        double v[3] = {yf[4] + c * nn[0], yf[5] + c * nn[1], yf[6] + c * nn[2]};
+        double vn = 1.0 / sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        v[0] *= vn; v[1] *= vn; v[2] *= vn;
+        double theta = atan2(sqrt(v[0] * v[0] + v[1] * v[1]), v[2]);
+        double phi = atan2(v[1], v[0]);
+        double psi = fmod(phi - I.Om * (yf[3] - r), 2.0 * M_PI);
+        if (psi < 0.0) psi += 2.0 * M_PI;
+        if (psi >= 2.0 * M_PI) psi -= 2.0 * M_PI;
+        fin[8 * n + j] = theta;
+        fin[9 * n + j] = phi;
+        fin[10 * n + j] = psi;
+        fin[11 * n + j] = -yf[7];
+        fin[12 * n + j] = hamiltonian(I, yf);
+        fin[14 * n + j] = r;
     }
 }
 
@@ -470,31 +475,42 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     FwdWs W = carve_fwd_ws(ws, n);
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(zero_ctr_kernel, dim3(1), dim3(64), 0, st, W.ctr);
     int grid = grid_for(n, 256, 8);
-    hipLaunchKernelGGL(trace_init_kernel, dim3(grid), dim3(256), 0, st, I, T, rays, status, n, W.ctr, W.list, W.h0,
-                       W.k1, fin, ifin);
+    hipLaunchKernelGGL(trace_init_kernel, dim3(grid), dim3(256), 0, st, I, T, rays, status, n, W.keys, W.h0, W.k1,
+                       fin, ifin);
     int rc = check_launch("trace_init_kernel");
+    if (rc) return rc;
+    rc = order_work_list(W, n, st);
     if (rc) return rc;
     return launch_trace_fwd(sc, I, T, rays, n, W, fin, ifin, st);
 }
 
 namespace rtd {
-template <int BLOCK>
+template <int BLOCK, int MINW>
 static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays,
                             int64_t n, const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
-    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK>, BLOCK);
-    hipLaunchKernelGGL(trace_fwd_kernel<BLOCK>, dim3(grid), dim3(BLOCK), 0, st, I, T, rays, n, W.ctr, W.list, W.h0,
-                       W.k1, fin, ifin, sc.refill_min);
-    return check_launch("trace_fwd_kernel");
+    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW>, BLOCK);
+    hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW>), dim3(grid), dim3(BLOCK), 0, st, I, T, rays, n, W.ctr, W.list,
+                       W.h0, W.k1, fin, ifin, sc.refill_min);
+    int rc = check_launch("trace_fwd_kernel");
+    if (rc) return rc;
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, W.list, W.ctr, n, fin);
+    return check_launch("finalize_kernel");
 }
 
 int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
                      const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    if (sc.occupancy == 2) {
+        switch (sc.block) {
+            case 64: return launch_fwd_block<64, 2>(sc, I, T, rays, n, W, fin, ifin, st);
+            case 128: return launch_fwd_block<128, 2>(sc, I, T, rays, n, W, fin, ifin, st);
+            default: return launch_fwd_block<256, 2>(sc, I, T, rays, n, W, fin, ifin, st);
+        }
+    }
     switch (sc.block) {
-        case 64: return launch_fwd_block<64>(sc, I, T, rays, n, W, fin, ifin, st);
-        case 128: return launch_fwd_block<128>(sc, I, T, rays, n, W, fin, ifin, st);
-        default: return launch_fwd_block<256>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 64: return launch_fwd_block<64, 1>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 128: return launch_fwd_block<128, 1>(sc, I, T, rays, n, W, fin, ifin, st);
+        default: return launch_fwd_block<256, 1>(sc, I, T, rays, n, W, fin, ifin, st);
     }
 }
 }  // namespace rtd

@@ -67,7 +67,7 @@ RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], doub
         T e = h * (e1 * S.K[0][i] + e3 * S.K[2][i] + e4 * S.K[3][i] + e5 * S.K[4][i] + e6 * S.K[5][i] +
                    e7 * S.K[6][i]);
         T sc = atol + rtol * fmax(fabs(y[i]), fabs(ynew[i]));
-        T qq = e / sc;
+        T qq = e * frcp(sc);
         acc = acc + qq * qq;
     }
     T err = sqrt(acc * 0.125);

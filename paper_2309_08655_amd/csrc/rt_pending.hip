@@ -4,10 +4,6 @@
 
 using namespace rtd;
 
-extern "C" int rt_trace_backward(const rt_star*, const rt_tol*, const rt_image*, int32_t, double*, int32_t*, double*,
-                                 int32_t*, void*, size_t, const rt_schedule*, void*) {
-    return fail(RT_EUNSUPPORTED, "rt_trace_backward: not available in this build");
-}
 extern "C" int rt_trace_batched(const rt_star*, int32_t, const int64_t*, uint64_t, const rt_tol*, const rt_bins*,
                                 double*, int32_t*, double*, int32_t*, double*, double*, void*, size_t,
                                 const rt_schedule*, void*) {
