@@ -55,6 +55,77 @@ def cpu_baseline(cfg, n_sample, threads):
                        f"rays/s {float((st == 0).sum()) / dt:.4g}")
 
 
+def bench_batched(args, rt, W, np, torch):
+    """Batched persistent launch over the 256-instance scan (16 axion masses x 16
+    inclinations, 1e4-2e5 rays each): autotuned schedule, captured into one hipGraph;
+    compared with one launch of each entry point per instance."""
+    from paper_2309_08655_amd import autotune
+    stars, counts = W.batched_instances(W.CFG4["n_inst"], seed=W.CFG4["seed"])
+    tol, bins = W.tol(), W.CFG4["bins"]
+    print(f"bench: batched {len(stars)} instances, {int(counts.sum())} rays", file=sys.stderr, flush=True)
+    b = rt.Batch(stars, counts, W.CFG4["seed"], tol, bins)
+    best, times = (None, None)
+    if not args.no_tune:
+        def run_sc(sc):
+            b.set_schedule(sc)
+            b.run()
+        best, times = autotune.tune(run_sc, key=f"batched|{len(stars)}|{int(counts.sum())}", reps=2,
+                                    candidates=[c for c in autotune.CANDIDATES
+                                                if c["block"] == 256 and c["refill_min"] in (4, 16)])
+    b.set_schedule(best)
+    g = b.capture()
+    for _ in range(max(1, args.warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = max(2, min(args.steps, 5))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ifn = b.ifin.cpu().numpy()
+    acc = float(ifn[0].astype(np.float64).sum())
+    traced = float((b.status.cpu().numpy() == 0).sum())
+    # one launch of each entry point per instance, on buffers sized for the largest instance
+    nmax = int(counts.max())
+    dev = torch.device("cuda")
+    rays = torch.empty((10, nmax), dtype=torch.float64, device=dev)
+    st = torch.empty(nmax, dtype=torch.int32, device=dev)
+    fin = torch.empty((rt.RT_NFIN, nmax), dtype=torch.float64, device=dev)
+    ifin = torch.empty((rt.RT_NIFIN, nmax), dtype=torch.int32, device=dev)
+    ws = rt.workspace(rt.OP_TRACE_FORWARD, nmax)
+    wsb = rt.workspace(rt.OP_BIN, nmax)
+    hist = torch.empty((1, bins["n_theta"], bins["n_psi"], bins["n_omega"]), dtype=torch.float64, device=dev)
+    cnt = torch.empty_like(hist)
+    over = torch.empty(2, dtype=torch.float64, device=dev)
+
+    def per_instance():
+        for k, s in enumerate(stars):
+            m = int(counts[k])
+            t_ = st[:m]
+            # contiguous [F][m] views over the front of the max-size buffers
+            rr = rays.view(-1)[:10 * m].view(10, m)
+            ff = fin.view(-1)[:rt.RT_NFIN * m].view(rt.RT_NFIN, m)
+            ii = ifin.view(-1)[:rt.RT_NIFIN * m].view(rt.RT_NIFIN, m)
+            rt.rt_sample_resonance(s, W.CFG4["seed"], m, instance=k, rays=rr, status=t_)
+            rt.rt_trace_forward(s, tol, rr, t_, schedule=best, ws=ws, fin=ff, ifin=ii)
+            rt.rt_bin_flux(ff, ii, rr[8], bins, ws=wsb, hist=hist, cnt=cnt, over=over)
+
+    # kernels and buffers are already warm from the batched runs: time a single pass
+    torch.cuda.synchronize()
+    e0.record()
+    per_instance()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1)
+    return dict(workload=W.CFG4["name"], instances=len(stars), rays=int(counts.sum()), traced_rays=traced,
+                ms_per_launch=ms, ray_steps_per_s=acc / (ms * 1e-3), rays_per_s=traced / (ms * 1e-3),
+                accepted_steps=acc, schedule=best, graph="one hipGraph replay per launch",
+                per_instance_ms=ms_loop, speedup_vs_per_instance=ms_loop / ms, tune_ms=times)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +135,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
+    ap.add_argument("--forms", type=str, default="plain,batched",
+                    help="comma list of forms to time: plain (the headline value), batched")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default schedule)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -91,6 +165,7 @@ def main():
     cfg = dict(W.CFG2)
     n = args.n or cfg["n"]
     sched = json.loads(args.schedule) if args.schedule else None
+    forms = set(args.forms.split(","))
     dev = torch.device("cuda")
     rays = torch.empty((10, n), dtype=torch.float64, device=dev)
     status = torch.empty(n, dtype=torch.int32, device=dev)
@@ -117,6 +192,15 @@ def main():
             e1.record(stream)
             ev_trace.append((e0, e1))
         rt.rt_bin_flux(fin, ifin, rays[8], b, ws=wsb, hist=hist, cnt=cnt, over=over)
+
+    tune_times = None
+    if sched is None and not args.no_tune:
+        from paper_2309_08655_amd import autotune
+        rt.rt_sample_resonance(cfg["star"], cfg["seed"], n, rays=rays, status=status)
+        sched, tune_times = autotune.tune(
+            lambda sc: rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, status, schedule=sc, ws=ws, fin=fin,
+                                           ifin=ifin), key=f"{cfg['name']}|{n}")
+        print(f"bench: autotuned schedule {sched}", file=sys.stderr, flush=True)
 
     print(f"bench: {cfg['name']} n={n} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -165,8 +249,10 @@ def main():
                            lane_efficiency=(acc + rej) / max(1, 64 * wave_iters),
                            attempts_per_ray=dict(mean=float(att.mean()), p99=float(np.percentile(att, 99)),
                                                  p9999=float(np.percentile(att, 99.99)), max=int(att.max())),
-                           schedule=sched),
+                           schedule=sched, autotune_ms=tune_times),
                roofline=roofline)
+    if "batched" in forms:
+        out["forms"] = dict(batched=bench_batched(args, rt, W, np, torch))
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)

@@ -158,18 +158,38 @@ int rt_trace_backward(const rt_star* star, const rt_tol* tol, const rt_image* im
                       int32_t* nev, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
                       const rt_schedule* sched, void* stream);
 
-/* rt_trace_batched -- many star instances in one persistent launch (seeding, tracing and
- * per-instance binning), for parameter scans.  stars: HOST array of n_inst rt_star sharing
- * plasma/density/weights/kdir; ray_offset: HOST array of n_inst + 1 prefix offsets (instance
- * k owns global rays [ray_offset[k], ray_offset[k+1]) and draws Philox counter
- * (i - ray_offset[k], k)).  rays "[10][N]", fin, ifin as above for N = ray_offset[n_inst];
- * maps/cnt "[n_inst][n_theta][n_psi][n_omega]".  One call issues a fixed sequence of
- * kernels (no host synchronisation), so it can be captured into a hipGraph.
- * Workspace: rt_workspace_size(RT_OP_BATCHED, N) + 16 n_inst + 64 bytes. */
-int rt_trace_batched(const rt_star* stars, int32_t n_inst, const int64_t* ray_offset, uint64_t seed,
-                     const rt_tol* tol, const rt_bins* bins, double* rays, int32_t* status, double* fin,
-                     int32_t* ifin, double* maps, double* cnt, void* ws, size_t ws_bytes,
-                     const rt_schedule* sched, void* stream);
+/* Batched persistent launch (parameter scans): many star instances traced by one
+ * persistent work-queue kernel.  Instances share plasma, density, weights and kdir; each
+ * has its own parameters and ray count.  Instance k owns the global rays
+ * [ray_offset[k], ray_offset[k+1]) and seeds ray i with Philox counter (i - ray_offset[k], k),
+ * so its rays are identical to rt_sample_resonance(..., instance = k, first = 0, ...). */
+typedef struct rt_batch {        /* filled by rt_batch_prepare; plain host data */
+    int32_t n_inst;
+    int32_t any_oblique;
+    int64_t n_rays;              /* N = ray_offset[n_inst] */
+    int64_t n_bin_blocks;
+    int32_t plasma, density;
+    size_t ws_bytes;
+} rt_batch;
+
+/* Workspace bytes for a batch (device memory), from the HOST offsets array. */
+size_t rt_batch_workspace_size(int32_t n_inst, const int64_t* ray_offset);
+
+/* rt_batch_prepare -- validate the instances and upload their constant tables into the
+ * workspace (HOST arrays stars[n_inst], ray_offset[n_inst+1]).  Synchronises `stream` once;
+ * the host arrays may be released on return.  Not capturable; call it before capturing
+ * rt_trace_batched.  Errors: RT_EINVAL (invalid or inconsistent instances), RT_ENOWS. */
+int rt_batch_prepare(const rt_star* stars, int32_t n_inst, const int64_t* ray_offset, rt_batch* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* rt_trace_batched -- seed, order, trace (one persistent kernel over all instances),
+ * finalise and bin every instance of a prepared batch.  Issues a fixed sequence of
+ * kernels with no host synchronisation, allocation or memset, so it can be captured
+ * into a hipGraph and replayed.  rays "[10][N]", status[N], fin "[RT_NFIN][N]",
+ * ifin "[RT_NIFIN][N]", maps/cnt "[n_inst][n_theta][n_psi][n_omega]" (overwritten). */
+int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, const rt_bins* bins, double* rays,
+                     int32_t* status, double* fin, int32_t* ifin, double* maps, double* cnt, void* ws,
+                     size_t ws_bytes, const rt_schedule* sched, void* stream);
 
 /* rt_flux_grad -- Gaussian-smoothed flux F_j = (1/n) sum_escaped w_i K(n_i . o_j),
  * K(c) = exp((c - 1)/sigma^2)/(2 pi sigma^2), at n_obs observer directions, and its

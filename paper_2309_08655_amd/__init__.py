@@ -20,7 +20,8 @@ OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD = 1, 2, 3,
 FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi", "omega", "H", "lam", "r", "h"]
 
 EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_batched",
-           "rt_flux_grad", "rt_flux_grad_workspace_size", "rt_workspace_size", "rt_last_error", "rt_version"]
+           "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
+           "rt_workspace_size", "rt_last_error", "rt_version"]
 
 
 class RtStar(C.Structure):
@@ -47,6 +48,11 @@ class RtSchedule(C.Structure):
                 ("occupancy", C.c_int32)]
 
 
+class RtBatch(C.Structure):
+    _fields_ = [("n_inst", C.c_int32), ("any_oblique", C.c_int32), ("n_rays", C.c_int64), ("n_bin_blocks", C.c_int64),
+                ("plasma", C.c_int32), ("density", C.c_int32), ("ws_bytes", C.c_size_t)]
+
+
 class RtError(RuntimeError):
     pass
 
@@ -71,8 +77,11 @@ def lib():
                                   C.c_size_t, vp]
         L.rt_trace_backward.argtypes = [sp, tp, C.POINTER(RtImage), C.c_int32, dp, ip, dp, ip, vp, C.c_size_t,
                                         C.POINTER(RtSchedule), vp]
-        L.rt_trace_batched.argtypes = [sp, C.c_int32, C.POINTER(C.c_int64), C.c_uint64, tp, C.POINTER(RtBins), dp,
-                                       ip, dp, ip, dp, dp, vp, C.c_size_t, C.POINTER(RtSchedule), vp]
+        L.rt_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
+        L.rt_batch_workspace_size.restype = C.c_size_t
+        L.rt_batch_prepare.argtypes = [sp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(RtBatch), vp, C.c_size_t, vp]
+        L.rt_trace_batched.argtypes = [C.POINTER(RtBatch), C.c_uint64, tp, C.POINTER(RtBins), dp, ip, dp, ip, dp, dp,
+                                       vp, C.c_size_t, C.POINTER(RtSchedule), vp]
         L.rt_flux_grad.argtypes = [sp, tp, C.c_uint64, C.c_int64, C.POINTER(C.c_double), C.c_int32, C.c_double,
                                    C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, vp, C.c_size_t, vp]
         L.rt_flux_grad_workspace_size.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32]
@@ -211,3 +220,63 @@ def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: 
 
 def version() -> str:
     return lib().rt_version().decode()
+
+
+class Batch:
+    """A prepared batch of star instances (rt_batch_prepare) with its device buffers.
+
+    run() issues the whole pipeline (seed, order, trace, finalise, per-instance maps) on
+    the current stream; capture() records it into a torch.cuda.CUDAGraph for replay."""
+
+    def __init__(self, stars, counts, seed, tol, bins, schedule=None):
+        import numpy as np
+        dev = _device()
+        self.n_inst = len(stars)
+        self.offsets = np.zeros(self.n_inst + 1, dtype=np.int64)
+        self.offsets[1:] = np.cumsum(np.asarray(counts, dtype=np.int64))
+        self.N = int(self.offsets[-1])
+        self.seed, self.tol, self.bins, self.schedule = seed, dict(tol), dict(bins), schedule
+        arr = (RtStar * self.n_inst)(*[make_star(s) for s in stars])
+        self._stars = arr
+        offp = self.offsets.ctypes.data_as(C.POINTER(C.c_int64))
+        nbytes = int(lib().rt_batch_workspace_size(self.n_inst, offp))
+        if nbytes == 0:
+            raise RtError("invalid batch")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.batch = RtBatch()
+        _check(lib().rt_batch_prepare(arr, self.n_inst, offp, C.byref(self.batch), _ptr(self.ws), nbytes,
+                                      _stream()), "rt_batch_prepare")
+        N = self.N
+        self.rays = torch.empty((10, N), dtype=torch.float64, device=dev)
+        self.status = torch.empty(N, dtype=torch.int32, device=dev)
+        self.fin = torch.empty((RT_NFIN, N), dtype=torch.float64, device=dev)
+        self.ifin = torch.empty((RT_NIFIN, N), dtype=torch.int32, device=dev)
+        shape = (self.n_inst, bins["n_theta"], bins["n_psi"], bins["n_omega"])
+        self.maps = torch.empty(shape, dtype=torch.float64, device=dev)
+        self.cnt = torch.empty(shape, dtype=torch.float64, device=dev)
+        self._t, self._b = make_tol(self.tol), make_bins(self.bins)
+        self._sc = make_schedule(schedule)
+
+    def set_schedule(self, schedule):
+        self.schedule = schedule
+        self._sc = make_schedule(schedule)
+
+    def run(self):
+        _check(lib().rt_trace_batched(C.byref(self.batch), self.seed, C.byref(self._t), C.byref(self._b),
+                                      _ptr(self.rays), _ptr(self.status), _ptr(self.fin), _ptr(self.ifin),
+                                      _ptr(self.maps), _ptr(self.cnt), _ptr(self.ws), self.ws.numel(),
+                                      C.byref(self._sc) if self._sc is not None else None, _stream()),
+               "rt_trace_batched")
+
+    def capture(self):
+        """Record run() into a CUDA/HIP graph (one hipGraphLaunch per replay)."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()  # warm-up outside capture (occupancy queries, module load)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            self.run()
+        return g

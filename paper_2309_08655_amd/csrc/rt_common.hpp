@@ -131,6 +131,17 @@ struct TolC {
 };
 int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
                      const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
+int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, const InstT<double>* itab,
+                             const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
+                             const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
+int launch_sample_batched(const InstT<double>* itab, const SeedC* ctab, const int64_t* off, int32_t n_inst,
+                          uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st);
+int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
+                      const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
+                      int32_t* ifin, hipStream_t st);
+int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
+               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, int32_t* keys,
+               hipStream_t st);
 
 // small utility kernels (defined per translation unit)
 static __global__ void zero_ctr_kernel(WorkCtr* c) {

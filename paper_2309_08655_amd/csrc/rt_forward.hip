@@ -171,6 +171,34 @@ __device__ static void seed_one(const InstT<double>& I, const SeedC& C, uint64_t
     out[8] = Ck * n_c * Vt * Q;
 }
 
+// instance owning global ray i: largest k with off[k] <= i
+__device__ __forceinline__ int32_t find_instance(const int64_t* __restrict__ off, int32_t n_inst, int64_t i) {
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) sample_batched_kernel(const InstT<double>* __restrict__ itab,
+                                                             const SeedC* __restrict__ ctab,
+                                                             const int64_t* __restrict__ off, int32_t n_inst,
+                                                             uint64_t seed, int64_t N, double* __restrict__ rays,
+                                                             int32_t* __restrict__ status,
+                                                             int32_t* __restrict__ inst_of) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < N; gi += stride) {
+        int32_t k = find_instance(off, n_inst, gi);
+        double o[10];
+        int32_t st;
+        seed_one(itab[k], ctab[k], seed, k, gi - off[k], o, &st);
+        for (int d = 0; d < 10; ++d) rays[d * N + gi] = o[d];
+        status[gi] = st;
+        inst_of[gi] = k;
+    }
+}
+
 __global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedC C, uint64_t seed, int32_t instance,
                                                      int64_t first, int64_t n, double* __restrict__ rays,
                                                      int32_t* __restrict__ status) {
@@ -187,13 +215,16 @@ __global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedC C, u
 // ----------------------------------------------------------------------------
 // tracing: init pass (FSAL derivative, starting step, compacted work list)
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
+__global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
+                                                         const int32_t* __restrict__ inst_of, TolC tol,
+                                                         const double* __restrict__ rays,
                                                          const int32_t* __restrict__ status, int64_t n,
                                                          int32_t* __restrict__ keys, double* __restrict__ h0s,
                                                          double* __restrict__ k1s, double* __restrict__ fin,
                                                          int32_t* __restrict__ ifin) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
         bool ok = (status == nullptr || status[j] == ST_OK);
         int32_t key = -1;
         if (!ok) {
@@ -222,12 +253,20 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I, TolC t
 // persistent tracing kernel: each lane integrates rays taken from the work list
 // until the list is exhausted; a wave refills its idle lanes with one atomic
 // ----------------------------------------------------------------------------
-template <int BLOCK, int MINW>
-__global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I, TolC tol, const double* __restrict__ rays,
+// BATCHED: rays of many star instances share the queue; a lane loads its ray's
+// instance constants on refill (plasma and density types are common to all
+// instances; the rotating-axis formula is used for every lane when any instance
+// is oblique, exact for the aligned ones).
+template <int BLOCK, int MINW, bool BATCHED>
+__global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
+                                                          const int32_t* __restrict__ inst_of, int any_oblique,
+                                                          TolC tol, const double* __restrict__ rays,
                                                           int64_t n, WorkCtr* ctr, const int32_t* __restrict__ list,
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
                                                           int32_t* __restrict__ ifin, int refill_min) {
+    InstT<double> I = I0;
+    if (BATCHED) I.oblique = any_oblique;
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
@@ -258,6 +297,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I,
                     unsigned long long q = base + __popcll(idle & below);
                     if (q < nlist) {
                         j = list[q];
+                        if (BATCHED) {
+                            I = itab[inst_of[j]];
+                            I.oblique = any_oblique;
+                        }
                         for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
                         h = h0s[j];
                         lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
@@ -338,12 +381,15 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I,
 // direction is binned on the sky): static-frame direction (theta, phi), the
 // azimuth psi in the frame co-rotating with the star at the arrival time t - r,
 // the energy at infinity -k_t, H and r.
-__global__ void __launch_bounds__(256) finalize_kernel(InstT<double> I, const int32_t* __restrict__ list,
-                                                       const WorkCtr* ctr, int64_t n, double* __restrict__ fin) {
+__global__ void __launch_bounds__(256) finalize_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
+                                                       const int32_t* __restrict__ inst_of,
+                                                       const int32_t* __restrict__ list, const WorkCtr* ctr,
+                                                       int64_t n, double* __restrict__ fin) {
     const int64_t nlist = (int64_t)ctr->len;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nlist; q += stride) {
         int64_t j = list[q];
+        const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
         double yf[8];
         for (int d = 0; d < 8; ++d) yf[d] = fin[d * n + j];
         double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
@@ -475,10 +521,7 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     FwdWs W = carve_fwd_ws(ws, n);
     hipStream_t st = (hipStream_t)stream;
-    int grid = grid_for(n, 256, 8);
-    hipLaunchKernelGGL(trace_init_kernel, dim3(grid), dim3(256), 0, st, I, T, rays, status, n, W.keys, W.h0, W.k1,
-                       fin, ifin);
-    int rc = check_launch("trace_init_kernel");
+    int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st);
     if (rc) return rc;
     rc = order_work_list(W, n, st);
     if (rc) return rc;
@@ -486,32 +529,92 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
 }
 
 namespace rtd {
-template <int BLOCK, int MINW>
-static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays,
-                            int64_t n, const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
-    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW>, BLOCK);
-    hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW>), dim3(grid), dim3(BLOCK), 0, st, I, T, rays, n, W.ctr, W.list,
-                       W.h0, W.k1, fin, ifin, sc.refill_min);
+template <int BLOCK, int MINW, bool BATCHED>
+static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
+                            const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
+                            const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED>, BLOCK);
+    hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED>), dim3(grid), dim3(BLOCK), 0, st, I, itab, inst_of,
+                       any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, W.list, W.ctr, n, fin);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, itab, inst_of, W.list, W.ctr,
+                       n, fin);
     return check_launch("finalize_kernel");
+}
+
+template <bool BATCHED>
+static int launch_trace_variant(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
+                                const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
+                                const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    if (sc.occupancy == 2) {
+        switch (sc.block) {
+            case 64: return launch_fwd_block<64, 2, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+            case 128: return launch_fwd_block<128, 2, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+            default: return launch_fwd_block<256, 2, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+        }
+    }
+    switch (sc.block) {
+        case 64: return launch_fwd_block<64, 1, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+        case 128: return launch_fwd_block<128, 1, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+        default: return launch_fwd_block<256, 1, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+    }
 }
 
 int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
                      const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
-    if (sc.occupancy == 2) {
-        switch (sc.block) {
-            case 64: return launch_fwd_block<64, 2>(sc, I, T, rays, n, W, fin, ifin, st);
-            case 128: return launch_fwd_block<128, 2>(sc, I, T, rays, n, W, fin, ifin, st);
-            default: return launch_fwd_block<256, 2>(sc, I, T, rays, n, W, fin, ifin, st);
-        }
-    }
-    switch (sc.block) {
-        case 64: return launch_fwd_block<64, 1>(sc, I, T, rays, n, W, fin, ifin, st);
-        case 128: return launch_fwd_block<128, 1>(sc, I, T, rays, n, W, fin, ifin, st);
-        default: return launch_fwd_block<256, 1>(sc, I, T, rays, n, W, fin, ifin, st);
-    }
+    return launch_trace_variant<false>(sc, I, nullptr, nullptr, 0, T, rays, n, W, fin, ifin, st);
+}
+
+int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, const InstT<double>* itab,
+                             const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
+                             const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    return launch_trace_variant<true>(sc, I0, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+}
+
+int launch_sample_batched(const InstT<double>* itab, const SeedC* ctab, const int64_t* off, int32_t n_inst,
+                          uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st) {
+    hipLaunchKernelGGL(sample_batched_kernel, dim3(grid_for(N, 256, 8)), dim3(256), 0, st, itab, ctab, off, n_inst,
+                       seed, N, rays, status, inst_of);
+    return check_launch("sample_batched_kernel");
+}
+
+int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
+                      const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
+                      int32_t* ifin, hipStream_t st) {
+    hipLaunchKernelGGL(trace_init_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, T, rays,
+                       status, n, W.keys, W.h0, W.k1, fin, ifin);
+    return check_launch("trace_init_kernel");
+}
+
+}  // namespace rtd
+
+namespace rtd {
+int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
+               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, int32_t* keys,
+               hipStream_t st) {
+    int32_t ninst = inst_offset ? n_inst : 1;
+    int64_t per = (int64_t)bins->n_theta * bins->n_psi * bins->n_omega;
+    int64_t nbins = per * ninst;
+    int zg = grid_for(nbins, 256, 4);
+    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, hist, nbins, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, cnt, nbins, 0.0);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, over, (int64_t)2, 0.0);
+    if (n == 0) return check_launch("fill_kernel");
+    int g1 = grid_for(n, 256, 8);
+    hipLaunchKernelGGL(bin_keys_kernel, dim3(g1), dim3(256), 0, st, fin, ifin, n, bins->n_theta, bins->n_psi,
+                       bins->n_omega, bins->d_omega, inst_offset, ninst, keys, w, over);
+    int64_t ntiles = (nbins + BIN_TILE - 1) / BIN_TILE;
+    // enough ray chunks to fill the device, each chunk re-read once per tile
+    int64_t nchunks = (2048 + ntiles - 1) / ntiles;
+    if (nchunks < 1) nchunks = 1;
+    if (nchunks > 1024) nchunks = 1024;
+    int64_t chunk = (n + nchunks - 1) / nchunks;
+    nchunks = (n + chunk - 1) / chunk;
+    if (ntiles > 65535 || nchunks > 65535) return fail(RT_EINVAL, "rt_bin_flux: grid too large");
+    hipLaunchKernelGGL(bin_tiles_kernel, dim3((unsigned)ntiles, (unsigned)nchunks), dim3(256), 0, st, keys, w, n, nbins,
+                       chunk, hist, cnt);
+    return check_launch("bin_tiles_kernel");
 }
 }  // namespace rtd
 
@@ -531,25 +634,5 @@ extern "C" int rt_bin_flux(const double* fin, const int32_t* ifin, const double*
     size_t need = rt_workspace_size(RT_OP_BIN, n);
     if (n > 0 && (!ws || ws_bytes < need)) return fail(RT_ENOWS, "rt_bin_flux: workspace too small");
     if (n > 0 && (!fin || !ifin || !w)) return fail(RT_EINVAL, "rt_bin_flux: null input");
-    hipStream_t st = (hipStream_t)stream;
-    int zg = grid_for(nbins, 256, 4);
-    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, hist, nbins, 0.0);
-    hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, cnt, nbins, 0.0);
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, over, (int64_t)2, 0.0);
-    if (n == 0) return check_launch("fill_kernel");
-    int32_t* keys = (int32_t*)ws;
-    int g1 = grid_for(n, 256, 8);
-    hipLaunchKernelGGL(bin_keys_kernel, dim3(g1), dim3(256), 0, st, fin, ifin, n, bins->n_theta, bins->n_psi,
-                       bins->n_omega, bins->d_omega, inst_offset, ninst, keys, w, over);
-    int64_t ntiles = (nbins + BIN_TILE - 1) / BIN_TILE;
-    // enough ray chunks to fill the device, each chunk re-read once per tile
-    int64_t nchunks = (2048 + ntiles - 1) / ntiles;
-    if (nchunks < 1) nchunks = 1;
-    if (nchunks > 1024) nchunks = 1024;
-    int64_t chunk = (n + nchunks - 1) / nchunks;
-    nchunks = (n + chunk - 1) / chunk;
-    if (ntiles > 65535 || nchunks > 65535) return fail(RT_EINVAL, "rt_bin_flux: grid too large");
-    hipLaunchKernelGGL(bin_tiles_kernel, dim3((unsigned)ntiles, (unsigned)nchunks), dim3(256), 0, st, keys, w, n, nbins,
-                       chunk, hist, cnt);
-    return check_launch("bin_tiles_kernel");
+    return launch_bin(fin, ifin, w, n, bins, inst_offset, n_inst, hist, cnt, over, (int32_t*)ws, (hipStream_t)stream);
 }

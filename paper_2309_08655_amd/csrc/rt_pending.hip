@@ -4,11 +4,6 @@
 
 using namespace rtd;
 
-extern "C" int rt_trace_batched(const rt_star*, int32_t, const int64_t*, uint64_t, const rt_tol*, const rt_bins*,
-                                double*, int32_t*, double*, int32_t*, double*, double*, void*, size_t,
-                                const rt_schedule*, void*) {
-    return fail(RT_EUNSUPPORTED, "rt_trace_batched: not available in this build");
-}
 extern "C" int rt_flux_grad(const rt_star*, const rt_tol*, uint64_t, int64_t, const double*, int32_t, double, int32_t,
                             int32_t, int32_t, const double*, double*, double*, void*, size_t, void*) {
     return fail(RT_EUNSUPPORTED, "rt_flux_grad: not available in this build");
