@@ -80,7 +80,8 @@ def lib():
                                          C.c_int32, dp, ip, dp, ip, C.c_int]
         L.orc_dopri_test.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.c_double, dp]
-        L.orc_flux_fwdmode.argtypes = [sp, tp, C.c_uint64, C.c_int64, dp, C.c_int32, C.c_double, dp, dp, C.c_int]
+        L.orc_flux_fwdmode.argtypes = [sp, tp, C.c_uint64, C.c_int64, dp, C.c_int32, C.c_double, dp, dp, dp, dp, ip,
+                                        C.c_int]
         L.orc_flux_replay.argtypes = [sp, tp, C.c_uint64, C.c_int64, dp, C.c_int32, C.c_double, C.c_int32,
                                       C.c_int32, dp, ip, ip, dp, C.c_int]
         _lib = L
@@ -244,13 +245,24 @@ def dopri_test(problem, rtol, atol, t_end, h_fixed=0.0):
     return y, na.value, nr.value, de.value
 
 
-def flux_fwdmode(s, t, seed, n, obs, sigma, nthreads=0):
+def flux_fwdmode(s, t, seed, n, obs, sigma, nthreads=0, per_ray=False):
+    """Smoothed flux F[n_obs] and dF/dp [n_obs, 6] by forward mode (steps frozen).
+    per_ray=True also returns each ray's share fray[n, n_obs], dray[n, n_obs, 6]
+    and status[n]."""
     obs = np.ascontiguousarray(obs, dtype=np.float64)
     nobs = obs.shape[0]
     flux = np.zeros(nobs)
     dflux = np.zeros((nobs, 6))
+    if per_ray:
+        fray, dray, st = np.zeros((n, nobs)), np.zeros((n, nobs, 6)), np.zeros(n, dtype=np.int32)
+        pf, pd, ps = _dp(fray), _dp(dray), _ip(st)
+    else:
+        pf = pd = None
+        ps = None
     lib().orc_flux_fwdmode(C.byref(make_star(s)), C.byref(make_tol(t)), seed, n, _dp(obs), nobs, sigma, _dp(flux),
-                           _dp(dflux), nthreads)
+                           _dp(dflux), pf, pd, ps, nthreads)
+    if per_ray:
+        return flux, dflux, fray, dray, st
     return flux, dflux
 
 

@@ -94,10 +94,13 @@ int orc_dopri_test(int32_t problem, double rtol, double atol, double t_end, doub
                    int64_t* n_acc, int64_t* n_rej, double h_fixed, double* dense_err);
 
 /* smoothed flux and its forward-mode derivative with respect to
-   (B0, P, theta_m, M, R, m_a); steps frozen at the nominal run */
+   (B0, P, theta_m, M, R, m_a); steps frozen at the nominal run.  If fray/dray are
+   not NULL they receive each ray's share (w K / n and its derivative; zero for rays
+   that do not escape) and ray_status each ray's status. */
 int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_t n,
                      const double* obs /*[n_obs][3]*/, int32_t n_obs, double sigma,
-                     double* flux /*[n_obs]*/, double* dflux /*[n_obs][6]*/, int nthreads);
+                     double* flux /*[n_obs]*/, double* dflux /*[n_obs][6]*/, double* fray /*[n][n_obs] or NULL*/,
+                     double* dray /*[n][n_obs][6] or NULL*/, int32_t* ray_status /*[n] or NULL*/, int nthreads);
 /* smoothed flux with a replayed step sequence (for frozen-step finite differences);
    hseq[n][max_steps] step sizes recorded by a nominal run when record != 0 */
 int orc_flux_replay(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_t n,

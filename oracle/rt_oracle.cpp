@@ -1181,7 +1181,8 @@ int orc_dopri_test(int32_t problem, double rtol, double atol, double t_end, doub
 }
 
 int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_t n, const double* obs,
-                     int32_t n_obs, double sigma, double* flux, double* dflux, int nthreads) {
+                     int32_t n_obs, double sigma, double* flux, double* dflux, double* fray, double* dray,
+                     int32_t* ray_status, int nthreads) {
     using D6 = Dual<6, double>;
     D6 p[6];
     double pv[6] = {s->B0_G, s->P_s, s->theta_m, s->M_Msun, s->R_km, s->m_a_eV};
@@ -1193,9 +1194,15 @@ int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64
         std::vector<double> loc((size_t)n_obs * 7, 0.0);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t i = 0; i < n; ++i) {
+            if (fray)
+                for (int j = 0; j < n_obs; ++j) fray[(size_t)i * n_obs + j] = 0.0;
+            if (dray)
+                for (int q = 0; q < n_obs * 6; ++q) dray[(size_t)i * n_obs * 6 + q] = 0.0;
             SeedOut<D6> so = seed_ray(I, seed, 0, i);
+            if (ray_status) ray_status[i] = so.status;
             if (so.status != ORC_OK) continue;
             TraceOut<D6> o = trace_one<D6, D6>(I, *tol, so.y, 1.0, nullptr, nullptr, 0);
+            if (ray_status) ray_status[i] = o.status;
             if (o.status != ORC_ESCAPED) continue;
             D6 th, ph, ps, v[3];
             observables(I, o.yf, th, ph, ps, v);
@@ -1205,6 +1212,9 @@ int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64
                 D6 contrib = so.w * kernel_K(c, sigma);
                 loc[(size_t)j * 7] += contrib.v;
                 for (int q = 0; q < 6; ++q) loc[(size_t)j * 7 + 1 + q] += contrib.d[q];
+                if (fray) fray[(size_t)i * n_obs + j] = contrib.v / (double)n;
+                if (dray)
+                    for (int q = 0; q < 6; ++q) dray[((size_t)i * n_obs + j) * 6 + q] = contrib.d[q] / (double)n;
             }
         }
 #pragma omp critical

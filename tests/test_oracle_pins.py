@@ -549,3 +549,66 @@ def test_backward_events_on_spherical_resonance(orc):
             assert ev[e, 8, q] == 0.0
         if ifin[2, q] == W.STATUS_ESCAPED:
             assert nev[q] == 2
+
+
+# ---------------------------------------------------------------- smoothed flux and its derivative
+def test_smoothed_flux_kernel_normalisation(orc):
+    """K(c) = exp((c - 1)/sigma^2)/(2 pi sigma^2) integrates to 1 - exp(-2/sigma^2) over the sphere,
+    so unit-weight rays spread uniformly on the sky (a Fibonacci lattice) give F = 1/(4 pi)."""
+    m = 400_000
+    k = np.arange(m) + 0.5
+    th = np.arccos(1.0 - 2.0 * k / m)
+    ps = np.mod(math.pi * (1.0 + math.sqrt(5.0)) * k, 2 * math.pi)
+    fin = np.zeros((16, m))
+    fin[8], fin[10] = th, ps
+    ifin = np.zeros((3, m), dtype=np.int32)
+    ifin[2] = W.STATUS_ESCAPED
+    obs = W.observers(8)
+    for sigma in (0.05, 0.1):
+        F = orc.smoothed_flux(fin, ifin, np.ones(m), obs, sigma, m)
+        assert np.allclose(F, (1.0 - math.exp(-2.0 / sigma ** 2)) / (4 * math.pi), rtol=1e-3)
+
+
+def test_forward_mode_flux_equals_traced_flux(orc):
+    """The forward-mode run's value part is the smoothed flux of the plain trace."""
+    s, t = W.CFG1["star"], W.CFG1["tol"]
+    n, obs = 200, W.observers(32)
+    F, _, fray, _, st = orc.flux_fwdmode(s, t, 0, n, obs, 0.02, per_ray=True)
+    rays, status = orc.sample(s, 0, n)
+    fin, ifin = orc.trace_forward(s, t, rays, status)
+    Ft = orc.smoothed_flux(fin, ifin, rays[8], obs, 0.02, n)
+    assert np.array_equal(st, ifin[2])
+    assert np.allclose(F, Ft, rtol=1e-12, atol=1e-12 * np.abs(Ft).max())
+    assert np.allclose(fray.sum(axis=0), F, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("plasma", [W.PLASMA_ISO, W.PLASMA_ANISO])
+def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma):
+    """dF/dp by forward mode against central differences of the flux recomputed with the
+    nominal accepted step sequence replayed (the map the derivative is of), for all six
+    parameters, on a star whose density has no kink (the spherical test profile) so that
+    the map is smooth: the error falls as the square of the step (central differences)
+    down to the roundoff floor."""
+    s = W.star(M_Msun=1.4, theta_m=0.3, density=W.DENSITY_SPHERICAL, plasma=plasma, m_a_eV=1e-5,
+               kdir=W.KDIR_OUTWARD)
+    t = W.tol()
+    n, obs, sigma = 120, W.observers(32), 0.05
+    F, dF = orc.flux_fwdmode(s, t, 0, n, obs, sigma)
+    _, hseq, nseq, stat = orc.flux_replay(s, t, 0, n, obs, sigma, True)
+    assert (stat == W.STATUS_ESCAPED).sum() > 100
+
+    def fd(k, rel):
+        d = rel * abs(s[k])
+        sp, sm = dict(s), dict(s)
+        sp[k], sm[k] = s[k] + d, s[k] - d
+        fp = orc.flux_replay(sp, t, 0, n, obs, sigma, False, hseq, nseq, stat)[0]
+        fm = orc.flux_replay(sm, t, 0, n, obs, sigma, False, hseq, nseq, stat)[0]
+        return (fp - fm) / (2 * d)
+
+    for q, k in enumerate(("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")):
+        scale = np.abs(dF[:, q]).max()
+        e3 = np.abs(fd(k, 1e-3) - dF[:, q]).max() / scale
+        e5 = np.abs(fd(k, 1e-5) - dF[:, q]).max() / scale
+        assert e5 < 1e-7, (k, e5)
+        # second-order convergence where truncation dominates
+        assert e3 < 1e-4 and (e3 < 1e-8 or e3 > 20 * e5), (k, e3, e5)
