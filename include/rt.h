@@ -191,25 +191,39 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
                      int32_t* status, double* fin, int32_t* ifin, double* maps, double* cnt, void* ws,
                      size_t ws_bytes, const rt_schedule* sched, void* stream);
 
-/* rt_flux_grad -- Gaussian-smoothed flux F_j = (1/n) sum_escaped w_i K(n_i . o_j),
- * K(c) = exp((c - 1)/sigma^2)/(2 pi sigma^2), at n_obs observer directions, and its
- * gradient with respect to p = (B0, P, theta_m, M, R, m_a) by a hand-written
- * discretise-then-differentiate adjoint of the accepted DOPRI5 steps (steps frozen),
- * including the seed root, the weights and the terminal-event location.
- * phase 0 (forward): seeds, traces with a checkpoint of (y, h) every ckpt_every accepted
- *   steps, writes flux[n_obs] (device).
- * phase 1 (reverse): given gbar[n_obs] (device), recomputes each segment from its
- *   checkpoint and sweeps back through the stages; writes grad[6] = sum_j gbar_j dF_j/dp
- *   (device).  Needs the workspace of the forward phase unchanged.
- * obs: HOST array "[n_obs][3]" of unit vectors.  Workspace:
- *   rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt). */
+/* rt_flux_grad -- Gaussian-smoothed flux and its gradient with respect to the star
+ * parameters p = (B0, P, theta_m, M, R, m_a), by a discretise-then-differentiate adjoint.
+ *   F_j = (1/n) sum_{escaped i} w_i K(n_i . o_j),  K(c) = exp((c - 1)/sigma^2) / (2 pi sigma^2),
+ * the forward estimator of Sec. 2.2 with the weights of Secs. 3-4, smoothed on the sky
+ * so that it is differentiable; n_i is the arrival direction in the frame co-rotating
+ * with the star (the direction that rt_trace_forward reports as (theta, psi)).
+ * The derivative is that of the computed map: accepted DOPRI5 step sizes and each ray's
+ * status frozen at the nominal p; resonance root, photon momentum and weight differentiated
+ * through the seeding; the r = r_max crossing implicitly on the continuous extension; every
+ * accepted step through its stages (Hamilton's equations, Sec. 2 eq. (Hamilton)).
+ *   phase 0 (forward): seeds n rays (seed, instance 0), traces them with a checkpoint of
+ *     (y, h, controller state) every ckpt_every accepted steps, writes flux[n_obs] (device)
+ *     and, if ray_info != NULL, ray_info "[3][n]" = n_acc, n_rej, status (device).
+ *     A ray that would need more than max_ckpt checkpoints ends as RT_ST_MAX_STEPS.
+ *   phase 1 (reverse): given gbar[n_obs] (device), recomputes each segment from its
+ *     checkpoint and sweeps back through the stages; writes grad[6] = sum_j gbar_j dF_j/dp
+ *     (device) and, if grad_rays != NULL, each ray's share "[n][6]" (zero for rays that
+ *     do not escape).  Needs the workspace of the phase-0 call of the same arguments,
+ *     unchanged; phase-1 calls may be repeated with other gbar.
+ * obs: HOST array "[n_obs][3]" of unit vectors, 1 <= n_obs <= 64; sigma > 0 [rad];
+ * 1 <= ckpt_every <= 1024; max_ckpt >= 1; weights RT_WEIGHTS_CONST_B is not supported.
+ * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt) bytes (about
+ * n (320 + 80 max_ckpt) + 4.7 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
+ * RT_EUNSUPPORTED or RT_EHIP. */
 int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
                  int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
-                 const double* gbar, double* flux, double* grad, void* ws, size_t ws_bytes, void* stream);
+                 const double* gbar, double* flux, double* grad, double* grad_rays, int32_t* ray_info, void* ws,
+                 size_t ws_bytes, void* stream);
 
 size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int32_t max_ckpt);
 
-/* Workspace bytes needed by op (RT_OP_*) for n rays. */
+/* Workspace bytes needed by op (RT_OP_*) for n rays; RT_OP_FLUX_GRAD is
+ * rt_flux_grad_workspace_size(n, 64, 64, 64). */
 size_t rt_workspace_size(int32_t op, int64_t n);
 
 /* Message of the last failed call on this thread ("" if none). */

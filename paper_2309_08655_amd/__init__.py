@@ -83,7 +83,7 @@ def lib():
         L.rt_trace_batched.argtypes = [C.POINTER(RtBatch), C.c_uint64, tp, C.POINTER(RtBins), dp, ip, dp, ip, dp, dp,
                                        vp, C.c_size_t, C.POINTER(RtSchedule), vp]
         L.rt_flux_grad.argtypes = [sp, tp, C.c_uint64, C.c_int64, C.POINTER(C.c_double), C.c_int32, C.c_double,
-                                   C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, vp, C.c_size_t, vp]
+                                   C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, dp, ip, vp, C.c_size_t, vp]
         L.rt_flux_grad_workspace_size.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32]
         L.rt_flux_grad_workspace_size.restype = C.c_size_t
         L.rt_workspace_size.argtypes = [C.c_int32, C.c_int64]
@@ -220,6 +220,82 @@ def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: 
 
 def version() -> str:
     return lib().rt_version().decode()
+
+
+PARAMS = ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")  # differentiable star parameters
+
+
+def flux_grad_workspace_size(n: int, n_obs: int, ckpt_every: int = 64, max_ckpt: int = 64) -> int:
+    return int(lib().rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt))
+
+
+def rt_flux_grad(star: dict, tol: dict, seed: int, n: int, obs, sigma: float, phase: int, ws: torch.Tensor,
+                 ckpt_every: int = 64, max_ckpt: int = 64, gbar=None, flux=None, grad=None, grad_rays=None,
+                 ray_info=None):
+    """One phase of rt_flux_grad (0: forward, writes flux; 1: reverse, writes grad)."""
+    import numpy as np
+    obs_h = np.ascontiguousarray(np.asarray(obs, dtype=np.float64).reshape(-1, 3))
+    s, t = make_star(star), make_tol(tol)
+    _check(lib().rt_flux_grad(C.byref(s), C.byref(t), seed, n, obs_h.ctypes.data_as(C.POINTER(C.c_double)),
+                              obs_h.shape[0], sigma, ckpt_every, max_ckpt, phase, _ptr(gbar), _ptr(flux), _ptr(grad),
+                              _ptr(grad_rays), _ptr(ray_info), _ptr(ws), ws.numel(), _stream()), "rt_flux_grad")
+
+
+class FluxGrad:
+    """One smoothed-flux evaluation and its adjoint, holding the workspace between them.
+
+    forward() traces n rays with checkpoints and returns F[n_obs]; backward(gbar) returns
+    sum_j gbar_j dF_j/dp for p = PARAMS (and may be called again with another gbar)."""
+
+    def __init__(self, star, tol, seed, n, obs, sigma, ckpt_every=64, max_ckpt=64):
+        import numpy as np
+        dev = _device()
+        self.star, self.tol, self.seed, self.n = dict(star), dict(tol), int(seed), int(n)
+        self.obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64).reshape(-1, 3))
+        self.sigma, self.ckpt_every, self.max_ckpt = float(sigma), int(ckpt_every), int(max_ckpt)
+        nbytes = flux_grad_workspace_size(self.n, self.obs.shape[0], self.ckpt_every, self.max_ckpt)
+        if nbytes == 0:
+            raise RtError("rt_flux_grad: invalid sizes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.flux = torch.empty(self.obs.shape[0], dtype=torch.float64, device=dev)
+        self.grad = torch.empty(6, dtype=torch.float64, device=dev)
+
+    def _call(self, phase, **kw):
+        rt_flux_grad(self.star, self.tol, self.seed, self.n, self.obs, self.sigma, phase, self.ws,
+                     self.ckpt_every, self.max_ckpt, **kw)
+
+    def forward(self, ray_info: bool = False):
+        info = torch.empty((RT_NIFIN, self.n), dtype=torch.int32, device=self.flux.device) if ray_info else None
+        self._call(0, flux=self.flux, ray_info=info)
+        return (self.flux, info) if ray_info else self.flux
+
+    def backward(self, gbar: torch.Tensor, per_ray: bool = False):
+        gbar = gbar.to(device=self.flux.device, dtype=torch.float64).contiguous()
+        gr = torch.empty((self.n, 6), dtype=torch.float64, device=self.flux.device) if per_ray else None
+        self._call(1, gbar=gbar, grad=self.grad, grad_rays=gr)
+        return (self.grad, gr) if per_ray else self.grad
+
+
+class FluxFn(torch.autograd.Function):
+    """F = FluxFn.apply(params, star, tol, seed, n, obs, sigma[, ckpt_every, max_ckpt]):
+    params is a float64 tensor of the six PARAMS (its values replace the star's);
+    F[n_obs] is differentiable with respect to params through the GPU adjoint."""
+
+    @staticmethod
+    def forward(ctx, params, star, tol, seed, n, obs, sigma, ckpt_every=64, max_ckpt=64):
+        s = dict(star)
+        for k, v in zip(PARAMS, params.detach().double().cpu().tolist()):
+            s[k] = v
+        fg = FluxGrad(s, tol, seed, n, obs, sigma, ckpt_every, max_ckpt)
+        flux = fg.forward().clone()
+        ctx.fg = fg
+        ctx.pdev = params.device
+        return flux.to(params.device)
+
+    @staticmethod
+    def backward(ctx, gflux):
+        g = ctx.fg.backward(gflux).clone().to(ctx.pdev)
+        return (g,) + (None,) * 8
 
 
 class Batch:

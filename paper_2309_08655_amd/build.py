@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt.so")
-SOURCES = ["rt_api.hip", "rt_forward.hip", "rt_backward.hip", "rt_batched.hip", "rt_pending.hip"]
+SOURCES = ["rt_api.hip", "rt_forward.hip", "rt_backward.hip", "rt_batched.hip", "rt_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,337 @@
+// Gaussian-smoothed flux and its gradient with respect to the star parameters
+// p = (B0, P, theta_m, M, R, m_a) by a hand-written discretise-then-differentiate
+// adjoint of the DOPRI5 ray integrator (McDonald & Witte, arXiv:2309.08655: the
+// forward estimator of Sec. 2.2 with the conversion weights of Sec. 4, rays of
+// Sec. 2 eq. (Hamilton) with the Hamiltonian of Sec. 4.1 eq. (StrongBHam)).
+//
+//   F_j = (1/N) sum_{escaped i} w_i K(n_i . o_j),  K(c) = exp((c - 1)/sigma^2) / (2 pi sigma^2),
+//   n_i = static-frame direction at r = r_max, rotated into the frame co-rotating
+//         with the star at the arrival time t - r.
+//
+// The differentiated map is the one the forward pass computed: the accepted step
+// sizes h_n are frozen (the controller is not differentiated), each ray's status
+// is frozen, the resonance root, the photon momentum and the weight are
+// differentiated through the seeding (forward mode, 6 tangents), the crossing
+// r = r_max through the implicit function theorem on the continuous extension,
+// and every accepted step through its stages:
+//   y_{n+1} = y_n + h sum_i b_i K_i,  K_i = f(Y_i),  Y_i = y_n + h sum_{j<i} a_ij K_j.
+// Stage vector-Jacobian products: with f = J grad(H), J = [[0, I], [-I, 0]],
+//   v^T df/dy = Hess(H) (J^T v), one directional derivative of the hand-derived
+//   gradient in dual numbers, and v^T df/dp from 6 more tangents.
+// Memory: (y, h, facmax) is checkpointed every C accepted steps; the reverse
+// sweep recomputes each segment from its checkpoint into a per-lane replay
+// buffer and walks it backwards.  Forward and recompute run the same
+// non-inlined step function, so the recomputed step sequence is bit-identical.
+// The per-ray pieces live in rt_adjoint.hpp (also compiled for the host in tests);
+// this file holds the workspace layout, the two persistent kernels and the entry.
+#include "rt_adjoint.hpp"
+#include "rt_common.hpp"
+
+namespace rtd {
+
+constexpr int REV_LANES = 65536;  // lanes of the reverse kernel (one replay buffer each)
+constexpr int MAX_OBS = 64;
+
+struct ParamVec {
+    double p[6];  // (B0 [G], P [s], theta_m [rad], M [Msun], R [km], m_a [eV])
+};
+
+struct AdjWs {
+    FwdWs fw;
+    double* rays;     // [10][n] seeds
+    int32_t* status;  // [n] seed status
+    double* fin;      // [RT_NFIN][n] written by the trace set-up for rays it does not trace
+    int32_t* ifin;    // [RT_NIFIN][n]: n_acc, n_rej, status
+    int32_t* nseg;    // [n] checkpoints stored
+    double* theta;    // [n] location of r = r_max on the last step
+    double* ckpt;     // [max_ckpt][10][n]: y[8], h, facmax
+    WorkCtr* rctr;    // reverse work list: head, len, iters = steps the recompute missed
+    int32_t* rlist;   // [n] escaped rays
+    double* obs;      // [n_obs][3]
+    double* facc;     // [MAX_OBS] flux accumulators
+    double* gacc;     // [8] gradient accumulators
+    double* replay;   // [C * 9][REV_LANES]
+};
+
+static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int32_t Kc, AdjWs* W) {
+    char* p = (char*)base;
+    auto take = [&](size_t bytes) {
+        char* q = p;
+        p += align256(bytes);
+        return q;
+    };
+    char* fwbase = take(fwd_ws_bytes(n));
+    char* rays = take(sizeof(double) * 10 * (size_t)n);
+    char* status = take(sizeof(int32_t) * (size_t)n);
+    char* fin = take(sizeof(double) * RT_NFIN_ * (size_t)n);
+    char* ifin = take(sizeof(int32_t) * RT_NIFIN_ * (size_t)n);
+    char* nseg = take(sizeof(int32_t) * (size_t)n);
+    char* theta = take(sizeof(double) * (size_t)n);
+    char* ckpt = take(sizeof(double) * 10 * (size_t)Kc * (size_t)n);
+    char* rctr = take(sizeof(WorkCtr));
+    char* rlist = take(sizeof(int32_t) * (size_t)n);
+    char* obs = take(sizeof(double) * 3 * (size_t)n_obs);
+    char* facc = take(sizeof(double) * MAX_OBS);
+    char* gacc = take(sizeof(double) * 8);
+    char* replay = take(sizeof(double) * 9 * (size_t)C * REV_LANES);
+    if (W) {
+        W->fw = carve_fwd_ws(fwbase, n);
+        W->rays = (double*)rays;
+        W->status = (int32_t*)status;
+        W->fin = (double*)fin;
+        W->ifin = (int32_t*)ifin;
+        W->nseg = (int32_t*)nseg;
+        W->theta = (double*)theta;
+        W->ckpt = (double*)ckpt;
+        W->rctr = (WorkCtr*)rctr;
+        W->rlist = (int32_t*)rlist;
+        W->obs = (double*)obs;
+        W->facc = (double*)facc;
+        W->gacc = (double*)gacc;
+        W->replay = (double*)replay;
+    }
+    return (size_t)(p - (char*)base);
+}
+
+// forward pass: persistent, one ray per lane with wave-aggregated refill from the
+// cost-ordered work list; checkpoints, the escaped list and the flux
+__global__ void __launch_bounds__(256) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
+                                                      const int32_t* __restrict__ list, const double* __restrict__ rays,
+                                                      const double* __restrict__ h0s, int C, int Kc,
+                                                      double* __restrict__ ckpt, int32_t* __restrict__ nseg_out,
+                                                      double* __restrict__ theta_out, int32_t* __restrict__ ifin,
+                                                      WorkCtr* rctr, int32_t* __restrict__ rlist,
+                                                      const double* __restrict__ obs, int n_obs, double sigma,
+                                                      double* __restrict__ facc) {
+    __shared__ double sh_f[MAX_OBS];
+    for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) sh_f[q] = 0.0;
+    __syncthreads();
+    const int lane = __lane_id();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long nlist = ctr->len;
+    bool active = false, exhausted = false;
+    int64_t j = 0;
+    AdjRay R;
+    auto store = [&](int s, const double* y, double h, double facmax) {
+        for (int d = 0; d < 8; ++d) ckpt[((int64_t)s * 10 + d) * n + j] = y[d];
+        ckpt[((int64_t)s * 10 + 8) * n + j] = h;
+        ckpt[((int64_t)s * 10 + 9) * n + j] = facmax;
+    };
+    while (true) {
+        unsigned long long idle = __ballot(!active);
+        if (idle && !exhausted) {
+            int cnt = __popcll(idle);
+            int leader = __ffsll((long long)idle) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&ctr->head, (unsigned long long)cnt);
+            base = __shfl(base, leader);
+            if (!active) {
+                unsigned long long qq = base + __popcll(idle & below);
+                if (qq < nlist) {
+                    j = list[qq];
+                    double y0[8];
+                    for (int d = 0; d < 8; ++d) y0[d] = rays[d * n + j];
+                    adj_ray_start(I, y0, h0s[j], R, store);
+                    active = true;
+                }
+            }
+            if (base + (unsigned long long)cnt >= nlist) exhausted = true;
+        }
+        if (__ballot(active) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (!active) continue;
+        double yf[8], th = 0.0;
+        const int status = adj_ray_step(I, tol, C, Kc, R, store, yf, &th);
+        if (status != ST_OK) {
+            ifin[j] = R.nacc;
+            ifin[n + j] = R.nrej;
+            ifin[2 * n + j] = status;
+            nseg_out[j] = R.nseg;
+            if (status == ST_ESCAPED) {
+                theta_out[j] = th;
+                const double w = rays[8 * n + j];
+                double nh[3];
+                arrival_direction(I, yf, nh);
+                for (int o = 0; o < n_obs; ++o) {
+                    const double c = nh[0] * obs[3 * o] + nh[1] * obs[3 * o + 1] + nh[2] * obs[3 * o + 2];
+                    atomicAdd(&sh_f[o], w * smoothing_kernel(c, sigma));
+                }
+                unsigned long long pos = atomicAdd(&rctr->len, 1ull);
+                rlist[pos] = (int32_t)j;
+            }
+            active = false;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_obs; q += blockDim.x)
+        if (sh_f[q] != 0.0) atomicAdd(&facc[q], sh_f[q]);
+}
+
+__global__ void adj_scale_kernel(const double* acc, int m, double s, double* out) {
+    for (int q = threadIdx.x; q < m; q += blockDim.x) out[q] = acc[q] * s;
+}
+
+// Seal of a completed forward phase: a word derived from the arguments that shape the
+// workspace.  The reverse kernel does nothing unless it finds the seal of its own
+// arguments (a reverse call on a workspace without its forward phase).
+static unsigned long long adj_seal(int64_t n, int32_t n_obs, int32_t C, int32_t Kc) {
+    unsigned long long h = 0x9e3779b97f4a7c15ull;
+    const unsigned long long v[4] = {(unsigned long long)n, (unsigned long long)n_obs, (unsigned long long)C,
+                                     (unsigned long long)Kc};
+    for (int i = 0; i < 4; ++i) h = (h ^ v[i]) * 0x100000001b3ull;
+    return h;
+}
+
+__global__ void adj_set_seal_kernel(WorkCtr* rctr, unsigned long long seal) {
+    if (threadIdx.x == 0) rctr->pad[0] = seal;
+}
+
+__global__ void adj_bad_seal_kernel(const WorkCtr* rctr, unsigned long long seal, double* grad) {
+    if (threadIdx.x < 6 && rctr->pad[0] != seal) grad[threadIdx.x] = __builtin_nan("");
+}
+
+__global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int clear_list) {
+    for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) facc[q] = 0.0;
+    for (int q = threadIdx.x; q < 8; q += blockDim.x) gacc[q] = 0.0;
+    if (threadIdx.x == 0) {
+        rctr->head = 0ull;
+        rctr->iters = 0ull;
+        if (clear_list) {
+            rctr->len = 0ull;
+            rctr->pad[0] = 0ull;
+        }
+    }
+}
+
+// reverse pass: one escaped ray per lane, handed out by a lane atomic
+__global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P, StarFixed fx, TolC tol,
+                                                     uint64_t seed, int64_t n, const int32_t* __restrict__ ifin,
+                                                     const int32_t* __restrict__ nseg_in,
+                                                     const double* __restrict__ theta_in,
+                                                     const double* __restrict__ ckpt, int C, WorkCtr* rctr,
+                                                     const int32_t* __restrict__ rlist, const double* __restrict__ obs,
+                                                     int n_obs, double sigma, const double* __restrict__ gbar,
+                                                     double* __restrict__ replay, double* __restrict__ gacc,
+                                                     double* __restrict__ grad_rays, double inv_n, int Kc,
+                                                     unsigned long long seal) {
+    if (rctr->pad[0] != seal) return;  // no forward phase of these arguments in this workspace
+    const int64_t lane_g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    AdjParams A;
+    make_adj_params(P.p, fx, A);
+    double pacc[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long missing = 0;
+    const unsigned long long rlen = rctr->len < (unsigned long long)n ? rctr->len : (unsigned long long)n;
+    auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 9 + d) * REV_LANES + lane_g]; };
+    while (true) {
+        const unsigned long long qq = atomicAdd(&rctr->head, 1ull);
+        if (qq >= rlen) break;
+        const int64_t j = rlist[qq];
+        if (j < 0 || j >= n) continue;
+        const int S = ifin[j], nseg = nseg_in[j];
+        if (nseg < 1 || nseg > Kc || S < 1 || S > nseg * C) continue;
+        auto load = [&](int s, double* y, double* h, double* facmax) {
+            for (int d = 0; d < 8; ++d) y[d] = ckpt[((int64_t)s * 10 + d) * n + j];
+            *h = ckpt[((int64_t)s * 10 + 8) * n + j];
+            *facmax = ckpt[((int64_t)s * 10 + 9) * n + j];
+        };
+        double pb[6] = {0, 0, 0, 0, 0, 0};
+        missing += (unsigned long long)adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], C, load, rb, obs,
+                                                       gbar, n_obs, sigma, pb);
+        for (int q = 0; q < 6; ++q) pacc[q] += pb[q];
+        if (grad_rays)
+            for (int q = 0; q < 6; ++q) grad_rays[j * 6 + q] = pb[q] * inv_n;
+    }
+    for (int q = 0; q < 6; ++q) {
+        double v = pacc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (threadIdx.x == 0) atomicAdd(&gacc[q], v);
+    }
+    if (missing) atomicAdd(&rctr->iters, missing);
+}
+
+}  // namespace rtd
+
+using namespace rtd;
+
+extern "C" size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int32_t max_ckpt) {
+    if (n < 0 || n_obs <= 0 || n_obs > MAX_OBS || ckpt_every <= 0 || max_ckpt <= 0) return 0;
+    return adj_ws_layout(nullptr, n, n_obs, ckpt_every, max_ckpt, nullptr);
+}
+
+__global__ void adj_ray_info_kernel(const int32_t* __restrict__ ifin, int64_t n, int32_t* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n; i += stride) out[i] = ifin[i];
+}
+
+extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
+                            int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
+                            const double* gbar, double* flux, double* grad, double* grad_rays, int32_t* ray_info,
+                            void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!validate_star(star) || !validate_tol(tol)) return RT_EINVAL;
+    if (n <= 0 || n > INT32_MAX) return fail(RT_EINVAL, "rt_flux_grad: n must be in [1, 2^31 - 1]");
+    if (n_obs <= 0 || n_obs > MAX_OBS || !obs) return fail(RT_EINVAL, "rt_flux_grad: 1 <= n_obs <= 64 observers");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(RT_EINVAL, "rt_flux_grad: sigma must be positive");
+    if (ckpt_every <= 0 || ckpt_every > 1024 || max_ckpt <= 0)
+        return fail(RT_EINVAL, "rt_flux_grad: need 1 <= ckpt_every <= 1024 and max_ckpt >= 1");
+    if (star->weights == RT_WEIGHTS_CONST_B) return fail(RT_EUNSUPPORTED, "rt_flux_grad: constant-B test weights");
+    if (phase != 0 && phase != 1) return fail(RT_EINVAL, "rt_flux_grad: phase must be 0 (forward) or 1 (reverse)");
+    const size_t need = rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt);
+    if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_flux_grad: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    AdjWs W;
+    adj_ws_layout(ws, n, n_obs, ckpt_every, max_ckpt, &W);
+    InstT<double> I = make_inst(*star);
+    I.oblique = 1;  // the rotating-axis formula throughout (exact at theta_m = 0, and theta_m tangents flow)
+    TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
+    if (phase == 0) {
+        if (!flux) return fail(RT_EINVAL, "rt_flux_grad: null flux");
+        if (hipMemcpyAsync(W.obs, obs, sizeof(double) * 3 * n_obs, hipMemcpyHostToDevice, st) != hipSuccess)
+            return fail(RT_EHIP, "rt_flux_grad: observer upload failed");
+        hipLaunchKernelGGL(adj_clear_kernel, dim3(1), dim3(64), 0, st, W.facc, W.gacc, W.rctr, 1);
+        int rc = check_launch("adj_clear_kernel");
+        if (rc) return rc;
+        rc = rt_sample_resonance(star, seed, 0, 0, n, W.rays, W.status, stream);
+        if (rc) return rc;
+        rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st);
+        if (rc) return rc;
+        rc = order_work_list(W.fw, n, st);
+        if (rc) return rc;
+        const rt_schedule sc = resolve_schedule(nullptr);
+        const int grid = persistent_grid(sc, (const void*)adj_fwd_kernel, 256);
+        hipLaunchKernelGGL(adj_fwd_kernel, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
+                           W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.rctr, W.rlist, W.obs,
+                           n_obs, sigma, W.facc);
+        rc = check_launch("adj_fwd_kernel");
+        if (rc) return rc;
+        hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.facc, n_obs, 1.0 / (double)n, flux);
+        hipLaunchKernelGGL(adj_set_seal_kernel, dim3(1), dim3(64), 0, st, W.rctr,
+                           adj_seal(n, n_obs, ckpt_every, max_ckpt));
+        rc = check_launch("adj_set_seal_kernel");
+        if (rc || !ray_info) return rc;
+        hipLaunchKernelGGL(adj_ray_info_kernel, dim3(grid_for(3 * n, 256, 8)), dim3(256), 0, st, W.ifin, n, ray_info);
+        return check_launch("adj_ray_info_kernel");
+    }
+    if (!gbar || !grad) return fail(RT_EINVAL, "rt_flux_grad: null gbar or grad");
+    hipLaunchKernelGGL(adj_clear_kernel, dim3(1), dim3(64), 0, st, W.facc, W.gacc, W.rctr, 0);
+    int rc = check_launch("adj_clear_kernel");
+    if (rc) return rc;
+    if (grad_rays) {
+        hipLaunchKernelGGL(fill_kernel, dim3(grid_for(6 * n, 256, 8)), dim3(256), 0, st, grad_rays, 6 * n, 0.0);
+        rc = check_launch("fill_kernel");
+        if (rc) return rc;
+    }
+    const unsigned long long seal = adj_seal(n, n_obs, ckpt_every, max_ckpt);
+    ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
+    StarFixed fx = star_fixed(*star);
+    hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.ifin, W.nseg,
+                       W.theta, W.ckpt, ckpt_every, W.rctr, W.rlist, W.obs, n_obs, sigma, gbar, W.replay, W.gacc,
+                       grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    rc = check_launch("adj_rev_kernel");
+    if (rc) return rc;
+    hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.gacc, 6, 1.0 / (double)n, grad);
+    hipLaunchKernelGGL(adj_bad_seal_kernel, dim3(1), dim3(64), 0, st, W.rctr, seal, grad);
+    return check_launch("adj_bad_seal_kernel");
+}

@@ -1,0 +1,415 @@
+// Per-ray pieces of the smoothed-flux adjoint (host and device): the step shared
+// by the forward pass and the recompute, the arrival direction and smoothing
+// kernel, the forward step with checkpoints, and the reverse sweep of one ray.
+//
+// McDonald & Witte, arXiv:2309.08655: forward estimator Sec. 2.2 eq. (Power),
+// rays Sec. 2 eq. (Hamilton) with the Hamiltonian of Sec. 4.1 eq. (StrongBHam),
+// seeding and weights Secs. 3-4 (rt_seed.hpp).
+//
+//   F_j = (1/N) sum_{escaped i} w_i K(n_i . o_j),  K(c) = exp((c - 1)/sigma^2) / (2 pi sigma^2).
+//
+// Differentiated map (discretise, then differentiate): accepted step sizes h_n and
+// every ray's status frozen at the nominal parameters; seed root, photon momentum
+// and weight by forward mode (6 tangents); the crossing r = r_max by the implicit
+// function theorem on the continuous extension; every accepted step through its
+// stages, y_{n+1} = y_n + h sum_i b_i K_i, K_i = f(Y_i), Y_i = y_n + h sum_{j<i} a_ij K_j.
+// With f = J grad(H), J = [[0, I], [-I, 0]], the stage products are
+//   v^T df/dy = Hess(H) (J^T v)   (one directional derivative of the hand-derived
+//   gradient in dual numbers),    v^T df/dp from six further tangents.
+#pragma once
+
+#include "rt_integrator.hpp"
+#include "rt_seed.hpp"
+
+#define RT_HD_NOINLINE __host__ __device__ __attribute__((noinline))
+
+namespace rtd {
+
+typedef gdual<7> D7;
+typedef gdual<6> D6;
+typedef gdual<14> D14;
+
+// ----------------------------------------------------------------------------
+// the step shared by the forward pass and the recompute: compiled once, so the
+// recomputed accept/reject decisions and step sizes are bit-identical
+// ----------------------------------------------------------------------------
+RT_HD_NOINLINE void adj_rhs(InstT<double> I, const double* y, double* f) { rhs(I, y, f, 1.0); }
+
+// One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
+// the last = f(ynew)), ynew and, if Ys != nullptr, the stage states Ys[0..47]
+// (Ys[0..7] = y).  Applies the step-size controller to *h and *facmax and returns
+// 1 if the step is accepted.
+RT_HD_NOINLINE int adj_attempt(InstT<double> I, double rtol, double atol, const double* y, double* K, double* ynew,
+                               double* h, double* facmax, double* Ys) {
+    using namespace dp5;
+    const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
+                            {a31, a32, 0, 0, 0, 0},
+                            {a41, a42, a43, 0, 0, 0},
+                            {a51, a52, a53, a54, 0, 0},
+                            {a61, a62, a63, a64, a65, 0},
+                            {b1, 0.0, b3, b4, b5, b6}};
+    const double hh = *h;
+    double tmp[8];
+    if (Ys)
+        for (int d = 0; d < 8; ++d) Ys[d] = y[d];
+    for (int s = 0; s < 6; ++s) {
+        for (int d = 0; d < 8; ++d) {
+            double acc = 0.0;
+            for (int q = 0; q <= s; ++q) acc += A[s][q] * K[q * 8 + d];
+            tmp[d] = y[d] + hh * acc;
+        }
+        if (s < 5) {
+            if (Ys)
+                for (int d = 0; d < 8; ++d) Ys[(s + 1) * 8 + d] = tmp[d];
+        } else {
+            for (int d = 0; d < 8; ++d) ynew[d] = tmp[d];
+        }
+        adj_rhs(I, tmp, K + (s + 1) * 8);
+    }
+    const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
+    double acc = 0.0;
+    for (int d = 0; d < 8; ++d) {
+        double e = 0.0;
+        for (int q = 0; q < 7; ++q) e += E[q] * K[q * 8 + d];
+        e *= hh;
+        const double sc = atol + rtol * fmax(fabs(y[d]), fabs(ynew[d]));
+        const double qq = e / sc;
+        acc += qq * qq;
+    }
+    double err = sqrt(acc * 0.125);
+    if (!__builtin_isfinite(err)) err = 1e300;
+    if (!(err <= 1.0)) {
+        *h = hh * step_factor(err, *facmax, false);
+        *facmax = 1.0;
+        return 0;
+    }
+    *h = hh * step_factor(err, *facmax, true);
+    *facmax = 10.0;
+    return 1;
+}
+
+// ----------------------------------------------------------------------------
+// observables
+// ----------------------------------------------------------------------------
+// Arrival direction of Sec. 2.2: static-frame momentum at the final point,
+// normalised, rotated by -Omega (t - r) about the rotation axis (frame co-rotating
+// with the star at the arrival time).
+template <class T>
+RT_HD void arrival_direction(const InstT<T>& I, const T yf[8], T nh[3]) {
+    T r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
+    T ir = rcp(r);
+    T nn[3] = {yf[0] * ir, yf[1] * ir, yf[2] * ir};
+    T A = 1.0 - I.rs * ir;
+    T q = nn[0] * yf[4] + nn[1] * yf[5] + nn[2] * yf[6];
+    T c = (sqrt(A) - 1.0) * q;
+    T v[3] = {yf[4] + c * nn[0], yf[5] + c * nn[1], yf[6] + c * nn[2]};
+    T vn = rcp(sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    T sa, ca;
+    sincos_t(I.Om * (yf[3] - r), &sa, &ca);
+    nh[0] = (v[0] * ca + v[1] * sa) * vn;
+    nh[1] = (v[1] * ca - v[0] * sa) * vn;
+    nh[2] = v[2] * vn;
+}
+
+// G = sum_j gbar_j K(n . o_j), K(c) = exp((c - 1)/sigma^2) / (2 pi sigma^2)
+template <class T>
+RT_HD T observer_sum(const InstT<T>& I, const T yf[8], const double* obs, const double* gbar, int n_obs,
+                     double sigma) {
+    T nh[3];
+    arrival_direction(I, yf, nh);
+    const double is2 = 1.0 / (sigma * sigma);
+    const double norm = 1.0 / (2.0 * phys::pi * sigma * sigma);
+    T G = T(0.0);
+    for (int j = 0; j < n_obs; ++j) {
+        T cj = nh[0] * obs[3 * j] + nh[1] * obs[3 * j + 1] + nh[2] * obs[3 * j + 2];
+        G = G + (gbar[j] * norm) * exp((cj - 1.0) * is2);
+    }
+    return G;
+}
+
+RT_HD double smoothing_kernel(double c, double sigma) {
+    return exp((c - 1.0) / (sigma * sigma)) / (2.0 * phys::pi * sigma * sigma);
+}
+
+// ----------------------------------------------------------------------------
+// forward pass of one ray, with checkpoints of (y, h, facmax) every C accepted steps
+// ----------------------------------------------------------------------------
+struct AdjRay {
+    double y[8], K[56];
+    double h, facmax, lam;
+    int nacc, nrej, nseg;
+};
+
+template <class Store>
+RT_HD void adj_ray_start(const InstT<double>& I, const double y0[8], double h0, AdjRay& R, Store&& store) {
+    for (int d = 0; d < 8; ++d) R.y[d] = y0[d];
+    adj_rhs(I, R.y, R.K);
+    R.h = h0;
+    R.facmax = 10.0;
+    R.lam = 0.0;
+    R.nacc = 0;
+    R.nrej = 0;
+    R.nseg = 1;
+    store(0, R.y, R.h, R.facmax);
+}
+
+// One attempt; returns ST_OK while the ray continues.  On ST_ESCAPED, yf is the
+// state at r = r_max on the last step's continuous extension and *theta its location.
+template <class Store>
+RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, AdjRay& R, Store&& store, double yf[8],
+                       double* theta) {
+    double ynew[8];
+    const double hused = R.h;
+    if (!adj_attempt(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr)) {
+        ++R.nrej;
+        return (fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam))) ? ST_OK : ST_STEP_UNDERFLOW;
+    }
+    ++R.nacc;
+    const double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+    bool finite_ok = true;
+    for (int d = 0; d < 8; ++d) finite_ok = finite_ok && __builtin_isfinite(ynew[d]);
+    if (finite_ok && rnew >= tol.rmax) {
+        // r = r_max on the continuous extension (60 bisections)
+        Stages S;
+        for (int s = 0; s < 7; ++s)
+            for (int d = 0; d < 8; ++d) S.K[s][d] = R.K[s * 8 + d];
+        double lo = 0.0, hi = 1.0;
+        for (int it = 0; it < 60; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            dense_at(R.y, ynew, S, hused, mid, yf, 0, 3);
+            const double rm = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
+            if (rm >= tol.rmax) hi = mid; else lo = mid;
+        }
+        dense_at(R.y, ynew, S, hused, hi, yf, 0, 8);
+        *theta = hi;
+        R.lam += hi * hused;
+        return ST_ESCAPED;
+    }
+    for (int d = 0; d < 8; ++d) {
+        R.y[d] = ynew[d];
+        R.K[d] = R.K[48 + d];
+    }
+    R.lam += hused;
+    if (!finite_ok) return ST_NONFINITE;
+    if (rnew <= value(I.R)) return ST_HIT_STAR;
+    if (R.nacc >= tol.max_steps) return ST_MAX_STEPS;
+    if (!(fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam)))) return ST_STEP_UNDERFLOW;
+    if (R.nacc % C == 0) {
+        if (R.nseg >= Kc) return ST_MAX_STEPS;  // beyond the checkpoint budget
+        store(R.nseg, R.y, R.h, R.facmax);
+        ++R.nseg;
+    }
+    return ST_OK;
+}
+
+// ----------------------------------------------------------------------------
+// reverse sweep
+// ----------------------------------------------------------------------------
+// Parameter-tangent copies of the instance: slots 1..6 for the stage products
+// (slot 0 is the state direction), 0..5 for the seed, 8..13 for the observable
+// (slots 0..7 are the final state).
+struct AdjParams {
+    InstT<D7> Ip;
+    InstT<D6> I6;
+    SeedT<D6> C6;
+    InstT<D14> I14;
+};
+
+RT_HD void make_adj_params(const double p[6], const StarFixed& fx, AdjParams& A) {
+    D7 p7[6];
+    D6 p6[6];
+    D14 p14[6];
+    for (int q = 0; q < 6; ++q) {
+        p7[q] = D7(p[q]);
+        p7[q].d[1 + q] = 1.0;
+        p6[q] = D6(p[q]);
+        p6[q].d[q] = 1.0;
+        p14[q] = D14(p[q]);
+        p14[q].d[8 + q] = 1.0;
+    }
+    A.Ip = make_inst_t<D7>(p7, fx);
+    A.I6 = make_inst_t<D6>(p6, fx);
+    A.C6 = make_seed_t<D6>(p6, fx);
+    A.I14 = make_inst_t<D14>(p14, fx);
+    // the rotating-axis formula throughout: exact at theta_m = 0 and theta_m tangents flow
+    A.Ip.oblique = 1;
+    A.I6.oblique = 1;
+    A.I14.oblique = 1;
+}
+
+// v^T df/dy (vy) and v^T df/dp (vp) at the state Y
+RT_HD_NOINLINE void rhs_vjp(const InstT<D7>& Ip, const double* Y, const double* v, double* vy, double* vp) {
+    D7 yd[8], fd[8];
+    for (int i = 0; i < 4; ++i) {
+        yd[i] = D7(Y[i]);
+        yd[i].d[0] = -v[4 + i];  // u = J^T v: u_x = -v_k
+        yd[4 + i] = D7(Y[4 + i]);
+        yd[4 + i].d[0] = v[i];  // u_k = v_x
+    }
+    rhs(Ip, yd, fd, 1.0);
+    // the tangent of f is J Hess(H) u; Hess(H) u = J^T (J Hess(H) u)
+    for (int i = 0; i < 4; ++i) {
+        vy[i] = -fd[4 + i].d[0];
+        vy[4 + i] = fd[i].d[0];
+    }
+    for (int q = 0; q < 6; ++q) {
+        double a = 0.0;
+        for (int i = 0; i < 8; ++i) a += v[i] * fd[i].d[1 + q];
+        vp[q] = a;
+    }
+}
+
+// Adjoint of the six stages of a step: on entry Kb[8 i .. 8 i + 7] holds the
+// adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and pb.
+RT_HD void stages_adjoint(const InstT<D7>& Ip, const double* Ys, double h, double* Kb, double* yb, double* pb) {
+    using namespace dp5;
+    const double A[6][5] = {{0, 0, 0, 0, 0},
+                            {a21, 0, 0, 0, 0},
+                            {a31, a32, 0, 0, 0},
+                            {a41, a42, a43, 0, 0},
+                            {a51, a52, a53, a54, 0},
+                            {a61, a62, a63, a64, a65}};
+    double vy[8], vp[6];
+    for (int i = 5; i >= 0; --i) {
+        rhs_vjp(Ip, Ys + i * 8, Kb + i * 8, vy, vp);
+        for (int q = 0; q < 6; ++q) pb[q] += vp[q];
+        for (int d = 0; d < 8; ++d) yb[d] += vy[d];
+        for (int jj = 0; jj < i; ++jj) {
+            const double c = h * A[i][jj];
+            if (c != 0.0)
+                for (int d = 0; d < 8; ++d) Kb[jj * 8 + d] += c * vy[d];
+        }
+    }
+}
+
+// Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing at
+// theta on the last step).  load(s, y, &h, &facmax) reads checkpoint s; rb(idx, d)
+// is the replay buffer (C steps x 9 values).  Adds d(w G(y_f))/dp to pb.  Returns the
+// number of steps the recompute could not reproduce (0 when all is well).
+template <class Load, class Replay>
+RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
+                          int nseg, double th, int C, Load&& load, Replay&& rb, const double* obs, const double* gbar,
+                          int n_obs, double sigma, double pb[6]) {
+    using namespace dp5;
+    D6 sd[10];
+    seed_ray<D6>(A.I6, A.C6, seed, 0, j, sd);
+    const double w = sd[8].v;
+    double yb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double wG = 0.0;
+    int missing = 0;
+    for (int s = nseg - 1; s >= 0; --s) {
+        // recompute the segment from its checkpoint
+        double y[8], ynew[8], K[56], h, facmax;
+        load(s, y, &h, &facmax);
+        const int first = s * C;
+        const int count = (S - first < C) ? (S - first) : C;
+        adj_rhs(I, y, K);
+        int stored = 0;
+        for (int guard = 0; stored < count && guard < 64 * C; ++guard) {
+            const double hused = h;
+            if (!adj_attempt(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr)) continue;
+            for (int d = 0; d < 8; ++d) rb(stored, d) = y[d];
+            rb(stored, 8) = hused;
+            ++stored;
+            for (int d = 0; d < 8; ++d) {
+                y[d] = ynew[d];
+                K[d] = K[48 + d];
+            }
+        }
+        missing += count - stored;
+        // walk the segment backwards
+        for (int idx = stored - 1; idx >= 0; --idx) {
+            double yn[8], Ys[48], Kb[48];
+            for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
+            const double hn = rb(idx, 8);
+            double hdummy = hn, fdummy = 10.0;
+            adj_rhs(I, yn, K);
+            adj_attempt(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys);
+            if (first + idx == S - 1) {
+                // y_f = E(theta) = y + cy (ynew - y) + h (c3 - c4) K1 - h c4 K7 + c5 h sum_i d_i K_i
+                const double t = th, om = 1.0 - t;
+                const double c3 = t * om, c4 = t * t * om, c5 = t * t * om * om, cy = t - c3 + 2.0 * c4;
+                const double dd[7] = {d1, 0.0, d3, d4, d5, d6, d7};
+                double yf[8], yth[8];
+                for (int d = 0; d < 8; ++d) {
+                    const double ydiff = ynew[d] - yn[d];
+                    const double r3 = hn * K[d] - ydiff;
+                    const double r4 = ydiff - hn * K[48 + d] - r3;
+                    double r5 = 0.0;
+                    for (int q = 0; q < 7; ++q) r5 += dd[q] * K[q * 8 + d];
+                    r5 *= hn;
+                    const double Qq = r3 + t * (r4 + om * r5);
+                    yf[d] = yn[d] + t * (ydiff + om * Qq);
+                    const double dP = -Qq + om * (r4 + (1.0 - 2.0 * t) * r5);
+                    yth[d] = ydiff + om * Qq + t * dP;  // dE/dtheta
+                }
+                // the observable with 8 state and 6 parameter tangents
+                D14 yd[8];
+                for (int d = 0; d < 8; ++d) {
+                    yd[d] = D14(yf[d]);
+                    yd[d].d[d] = 1.0;
+                }
+                D14 G = observer_sum(A.I14, yd, obs, gbar, n_obs, sigma);
+                wG = G.v;
+                double gyf[8];
+                for (int d = 0; d < 8; ++d) gyf[d] = w * G.d[d];
+                for (int q = 0; q < 6; ++q) pb[q] += w * G.d[8 + q];
+                // crossing r(E(theta)) = r_max: remove the component along dE/dtheta
+                const double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
+                const double gr[3] = {yf[0] / r, yf[1] / r, yf[2] / r};
+                double num = 0.0, den = 0.0;
+                for (int d = 0; d < 8; ++d) num += gyf[d] * yth[d];
+                for (int d = 0; d < 3; ++d) den += gr[d] * yth[d];
+                const double beta = num / den;
+                for (int d = 0; d < 3; ++d) gyf[d] -= beta * gr[d];
+                // through E at fixed theta
+                double ynb[8], K7b[8];
+                for (int d = 0; d < 8; ++d) {
+                    ynb[d] = cy * gyf[d];
+                    yb[d] = (1.0 - cy) * gyf[d];
+                    Kb[d] = hn * (c3 - c4 + c5 * d1) * gyf[d];
+                    Kb[8 + d] = 0.0;
+                    Kb[16 + d] = hn * c5 * d3 * gyf[d];
+                    Kb[24 + d] = hn * c5 * d4 * gyf[d];
+                    Kb[32 + d] = hn * c5 * d5 * gyf[d];
+                    Kb[40 + d] = hn * c5 * d6 * gyf[d];
+                    K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
+                }
+                // K7 = f(ynew)
+                double vy[8], vp[6];
+                rhs_vjp(A.Ip, ynew, K7b, vy, vp);
+                for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
+                for (int q = 0; q < 6; ++q) pb[q] += vp[q];
+                // ynew = y + h sum_i b_i K_i
+                for (int d = 0; d < 8; ++d) {
+                    yb[d] += ynb[d];
+                    Kb[d] += hn * b1 * ynb[d];
+                    Kb[16 + d] += hn * b3 * ynb[d];
+                    Kb[24 + d] += hn * b4 * ynb[d];
+                    Kb[32 + d] += hn * b5 * ynb[d];
+                    Kb[40 + d] += hn * b6 * ynb[d];
+                }
+            } else {
+                // y_{n+1} = y_n + h sum_i b_i K_i; yb holds the adjoint of y_{n+1}
+                for (int d = 0; d < 8; ++d) {
+                    Kb[d] = hn * b1 * yb[d];
+                    Kb[8 + d] = 0.0;
+                    Kb[16 + d] = hn * b3 * yb[d];
+                    Kb[24 + d] = hn * b4 * yb[d];
+                    Kb[32 + d] = hn * b5 * yb[d];
+                    Kb[40 + d] = hn * b6 * yb[d];
+                }
+            }
+            stages_adjoint(A.Ip, Ys, hn, Kb, yb, pb);
+        }
+    }
+    // seed: y_0(p) and w(p)
+    for (int q = 0; q < 6; ++q) {
+        double a = wG * sd[8].d[q];
+        for (int d = 0; d < 8; ++d) a += yb[d] * sd[d].d[q];
+        pb[q] += a;
+    }
+    return missing;
+}
+
+}  // namespace rtd

@@ -60,54 +60,29 @@ bool validate_tol(const rt_tol* t) {
     return true;
 }
 
-InstT<double> make_inst(const rt_star& s) {
-    InstT<double> I;
-    I.rs = 2.0 * phys::GMsun_km * s.M_Msun;
-    I.R = s.R_km;
-    I.R3 = s.R_km * s.R_km * s.R_km;
-    double Om_s = 2.0 * phys::pi / s.P_s;
-    I.Om = Om_s / phys::c_kms;
-    I.cm = std::cos(s.theta_m);
-    I.sm = std::sin(s.theta_m);
-    I.oblique = (I.sm != 0.0) ? 1 : 0;
-    double v0 = s.v0_kms / phys::c_kms;
-    double w_inf = s.m_a_eV * std::sqrt(1.0 + v0 * v0);
-    I.ma2 = 1.0 / (1.0 + v0 * v0);
-    double Cp = phys::wp2_per_ne() / (w_inf * w_inf);
-    // Goldreich-Julian number density scale Omega B0 / (4 pi e c) [cm^-3]
-    double n0 = Om_s * s.B0_G / (4.0 * phys::pi * phys::e_statC * phys::c_cms);
-    switch (s.density) {
-        case RT_DENSITY_GJ: I.Cwp = Cp * s.multiplicity * n0; break;
-        case RT_DENSITY_MAGNETAR:
-            // lambda psi B0 (R/r)^3 sin^2 / (4 pi e r_cm), r_cm = 1e5 r_km
-            I.Cwp = Cp * s.multiplicity * s.psi_twist * s.B0_G / (4.0 * phys::pi * phys::e_statC * 1.0e5);
-            break;
-        case RT_DENSITY_SPHERICAL: I.Cwp = Cp * s.multiplicity * n0; break;
-        default: I.Cwp = 0.0; break;
-    }
-    I.plasma = s.plasma;
-    I.density = s.density;
-    return I;
+StarFixed star_fixed(const rt_star& s) {
+    StarFixed f;
+    f.g_agg_GeV = s.g_agg_GeV;
+    f.v0_kms = s.v0_kms;
+    f.rho_GeVcm3 = s.rho_GeVcm3;
+    f.multiplicity = s.multiplicity;
+    f.psi_twist = s.psi_twist;
+    f.B_test_G = s.B_test_G;
+    f.plasma = s.plasma;
+    f.density = s.density;
+    f.weights = s.weights;
+    f.kdir = s.kdir;
+    return f;
 }
 
-SeedC make_seed_consts(const rt_star& s) {
-    SeedC C;
-    double v0 = s.v0_kms / phys::c_kms;
-    C.B0 = s.B0_G;
-    C.period_km = s.P_s * phys::c_kms;
-    C.w_inf = s.m_a_eV * std::sqrt(1.0 + v0 * v0);
-    double rho_eV4 = s.rho_GeVcm3 * 1.0e9 * phys::hbarc_eVcm * phys::hbarc_eVcm * phys::hbarc_eVcm;
-    double n_inf = rho_eV4 / s.m_a_eV;
-    double k0 = s.m_a_eV * v0;
-    C.nc_per_ka = n_inf * C.w_inf / k0;
-    double g = s.g_agg_GeV * 1.0e-9;
-    C.g2 = g * g;
-    C.G2 = phys::gauss_eV2();
-    C.Btest = s.B_test_G;
-    C.hbarc = phys::hbarc_eVkm;
-    C.weights = s.weights;
-    C.kdir = s.kdir;
-    return C;
+InstT<double> make_inst(const rt_star& s) {
+    double p[6] = {s.B0_G, s.P_s, s.theta_m, s.M_Msun, s.R_km, s.m_a_eV};
+    return make_inst_t<double>(p, star_fixed(s));
+}
+
+SeedT<double> make_seed_consts(const rt_star& s) {
+    double p[6] = {s.B0_G, s.P_s, s.theta_m, s.M_Msun, s.R_km, s.m_a_eV};
+    return make_seed_t<double>(p, star_fixed(s));
 }
 
 int device_cu_count() {
@@ -226,6 +201,8 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
             return fwd_ws_bytes(n) + align256(sizeof(double) * 8 * (size_t)n);
         case RT_OP_BIN:
             return align256(sizeof(int32_t) * (size_t)n);
+        case RT_OP_FLUX_GRAD:  // 64 observers, a checkpoint every 64 steps, up to 64 of them
+            return rt_flux_grad_workspace_size(n, 64, 64, 64);
         default:
             return 0;
     }

@@ -6,7 +6,7 @@
 // Workspace layout (after rt_batch_prepare):
 //   [forward-tracer workspace for N rays]
 //   inst_of[N] (int32)   bin keys[N] (int32)
-//   itab[n_inst] (InstT)  ctab[n_inst] (SeedC)  offsets[n_inst + 1] (int64)
+//   itab[n_inst] (InstT)  ctab[n_inst] (SeedT)  offsets[n_inst + 1] (int64)
 //   bin block table[n_blocks] (instance, first ray, end ray)
 #include "rt_common.hpp"
 
@@ -26,7 +26,7 @@ struct BatchWs {
     int32_t* inst_of;
     int32_t* keys;
     InstT<double>* itab;
-    SeedC* ctab;
+    SeedT<double>* ctab;
     int64_t* off;
     BinBlock* blocks;
 };
@@ -42,7 +42,7 @@ static int64_t bin_blocks_for(const int64_t* off, int32_t n_inst) {
 
 static size_t batch_tail_bytes(int32_t n_inst, int64_t N, int64_t n_blocks) {
     return align256(sizeof(int32_t) * (size_t)N) * 2 + align256(sizeof(InstT<double>) * (size_t)n_inst) +
-           align256(sizeof(SeedC) * (size_t)n_inst) + align256(sizeof(int64_t) * (size_t)(n_inst + 1)) +
+           align256(sizeof(SeedT<double>) * (size_t)n_inst) + align256(sizeof(int64_t) * (size_t)(n_inst + 1)) +
            align256(sizeof(BinBlock) * (size_t)(n_blocks > 0 ? n_blocks : 1));
 }
 
@@ -56,8 +56,8 @@ static BatchWs carve_batch_ws(void* ws, int32_t n_inst, int64_t N) {
     p += align256(sizeof(int32_t) * (size_t)N);
     B.itab = (InstT<double>*)p;
     p += align256(sizeof(InstT<double>) * (size_t)n_inst);
-    B.ctab = (SeedC*)p;
-    p += align256(sizeof(SeedC) * (size_t)n_inst);
+    B.ctab = (SeedT<double>*)p;
+    p += align256(sizeof(SeedT<double>) * (size_t)n_inst);
     B.off = (int64_t*)p;
     p += align256(sizeof(int64_t) * (size_t)(n_inst + 1));
     B.blocks = (BinBlock*)p;
@@ -152,7 +152,7 @@ extern "C" int rt_batch_prepare(const rt_star* stars, int32_t n_inst, const int6
     BatchWs B = carve_batch_ws(ws, n_inst, N);
     int64_t nb = bin_blocks_for(ray_offset, n_inst);
     InstT<double>* it = new InstT<double>[n_inst];
-    SeedC* ct = new SeedC[n_inst];
+    SeedT<double>* ct = new SeedT<double>[n_inst];
     BinBlock* bb = new BinBlock[nb > 0 ? nb : 1];
     int any_oblique = 0;
     int64_t q = 0;
@@ -170,7 +170,7 @@ extern "C" int rt_batch_prepare(const rt_star* stars, int32_t n_inst, const int6
     }
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(B.itab, it, sizeof(InstT<double>) * n_inst, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(B.ctab, ct, sizeof(SeedC) * n_inst, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(B.ctab, ct, sizeof(SeedT<double>) * n_inst, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(B.off, ray_offset, sizeof(int64_t) * (n_inst + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nb > 0) e = hipMemcpyAsync(B.blocks, bb, sizeof(BinBlock) * nb, hipMemcpyHostToDevice, st);

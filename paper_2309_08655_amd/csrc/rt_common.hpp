@@ -14,6 +14,7 @@
 #include "../../include/rt.h"
 #include "rt_device.hpp"
 #include "rt_integrator.hpp"
+#include "rt_seed.hpp"
 
 #define RT_NFIN_ 16
 #define RT_NIFIN_ 3
@@ -32,30 +33,11 @@ inline int fail(int code, const char* msg) {
 }
 int check_launch(const char* what);
 
-// ---------------------------------------------------------------------------
-// physical constants (CODATA 2018; IAU 2015 nominal G M_sun)
-// ---------------------------------------------------------------------------
-namespace phys {
-constexpr double pi = 3.14159265358979323846;
-constexpr double c_kms = 299792.458;
-constexpr double c_cms = 2.99792458e10;
-constexpr double hbarc_eVkm = 1.973269804e-10;
-constexpr double hbarc_eVcm = 1.973269804e-5;
-constexpr double alpha = 1.0 / 137.035999084;
-constexpr double m_e_eV = 510998.95;
-constexpr double e_statC = 4.803204712570263e-10;
-constexpr double GMsun_km = 1.4766250;
-constexpr double erg_per_eV = 1.602176634e-12;
-// 1 G in eV^2 (Heaviside-Lorentz, hbar = c = 1): B^2/(8 pi) erg/cm^3 = B_HL^2 / 2
-inline double gauss_eV2() { return std::sqrt(hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / (erg_per_eV * 4.0 * pi)); }
-// w_p^2 = 4 pi alpha n_e / m_e  [eV^2 per cm^-3]
-inline double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / m_e_eV; }
-}  // namespace phys
-
 bool validate_star(const rt_star* s);
 bool validate_tol(const rt_tol* t);
 InstT<double> make_inst(const rt_star& s);
-SeedC make_seed_consts(const rt_star& s);
+SeedT<double> make_seed_consts(const rt_star& s);
+StarFixed star_fixed(const rt_star& s);
 
 // ---------------------------------------------------------------------------
 // workspace of the persistent kernels
@@ -125,16 +107,12 @@ rt_schedule resolve_schedule(const rt_schedule* s);
 // workgroups of a persistent launch: CUs x resident workgroups per CU
 int persistent_grid(const rt_schedule& sc, const void* kernel, int block);
 
-struct TolC {
-    double rtol, atol, rmax;
-    long long max_steps;
-};
 int launch_trace_fwd(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
                      const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
 int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, const InstT<double>* itab,
                              const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                              const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
-int launch_sample_batched(const InstT<double>* itab, const SeedC* ctab, const int64_t* off, int32_t n_inst,
+int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, const int64_t* off, int32_t n_inst,
                           uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st);
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,

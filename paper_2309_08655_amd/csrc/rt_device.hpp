@@ -25,80 +25,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rtd {
 
 // ----------------------------------------------------------------------------
-// minimal forward-mode dual number with N tangents (device and host)
+// scalar helpers (double)
 // ----------------------------------------------------------------------------
-template <int N>
-struct gdual {
-    double v;
-    double d[N];
-    __host__ __device__ gdual() : v(0.0) {
-        for (int i = 0; i < N; ++i) d[i] = 0.0;
-    }
-    __host__ __device__ gdual(double c) : v(c) {
-        for (int i = 0; i < N; ++i) d[i] = 0.0;
-    }
-};
-
 #define RT_HD __host__ __device__ __forceinline__
 
 using ::sqrt;
+using ::fabs;
+using ::exp;
+using ::atan2;
 
-template <int N> RT_HD gdual<N> operator+(const gdual<N>& a, const gdual<N>& b) {
-    gdual<N> r; r.v = a.v + b.v;
-    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
-    return r;
-}
-template <int N> RT_HD gdual<N> operator-(const gdual<N>& a, const gdual<N>& b) {
-    gdual<N> r; r.v = a.v - b.v;
-    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
-    return r;
-}
-template <int N> RT_HD gdual<N> operator-(const gdual<N>& a) {
-    gdual<N> r; r.v = -a.v;
-    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
-    return r;
-}
-template <int N> RT_HD gdual<N> operator*(const gdual<N>& a, const gdual<N>& b) {
-    gdual<N> r; r.v = a.v * b.v;
-    for (int i = 0; i < N; ++i) r.d[i] = fma(a.d[i], b.v, a.v * b.d[i]);
-    return r;
-}
-template <int N> RT_HD gdual<N> operator*(double a, const gdual<N>& b) {
-    gdual<N> r; r.v = a * b.v;
-    for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i];
-    return r;
-}
-template <int N> RT_HD gdual<N> operator*(const gdual<N>& b, double a) { return a * b; }
-template <int N> RT_HD gdual<N> operator+(double a, const gdual<N>& b) { gdual<N> r = b; r.v = a + b.v; return r; }
-template <int N> RT_HD gdual<N> operator+(const gdual<N>& b, double a) { gdual<N> r = b; r.v = b.v + a; return r; }
-template <int N> RT_HD gdual<N> operator-(double a, const gdual<N>& b) { return a + (-b); }
-template <int N> RT_HD gdual<N> operator-(const gdual<N>& b, double a) { gdual<N> r = b; r.v = b.v - a; return r; }
-template <int N> RT_HD gdual<N> rcp(const gdual<N>& a) {
-    gdual<N> r; r.v = 1.0 / a.v;
-    double g = -r.v * r.v;
-    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
-    return r;
-}
-template <int N> RT_HD gdual<N> operator/(const gdual<N>& a, const gdual<N>& b) { return a * rcp(b); }
-template <int N> RT_HD gdual<N> operator/(double a, const gdual<N>& b) { return a * rcp(b); }
-template <int N> RT_HD gdual<N> operator/(const gdual<N>& a, double b) { return a * (1.0 / b); }
-template <int N> RT_HD gdual<N> sqrt(const gdual<N>& a) {
-    gdual<N> r; r.v = ::sqrt(a.v);
-    double g = 0.5 / r.v;
-    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
-    return r;
-}
-template <int N> RT_HD void sincos_t(const gdual<N>& a, gdual<N>* s, gdual<N>* c) {
-    double sv, cv;
-    ::sincos(a.v, &sv, &cv);
-    s->v = sv; c->v = cv;
-    for (int i = 0; i < N; ++i) { s->d[i] = cv * a.d[i]; c->d[i] = -sv * a.d[i]; }
-}
 RT_HD double rcp(double a) { return 1.0 / a; }
-RT_HD double fabs_v(double a) { return fabs(a); }
+RT_HD double value(double a) { return a; }
+RT_HD void sincos_t(double a, double* s, double* c) { ::sincos(a, s, c); }
 
 // Reciprocal and reciprocal square root from the hardware estimates (v_rcp_f64,
 // v_rsq_f64) refined by two Newton steps: within about one ulp for the normal,
@@ -127,11 +70,120 @@ RT_HD double frsqrt(double x) {
     return 1.0 / ::sqrt(x);
 #endif
 }
-template <int N> RT_HD gdual<N> frcp(const gdual<N>& a) { return rcp(a); }
-template <int N> RT_HD gdual<N> frsqrt(const gdual<N>& a) { return rcp(sqrt(a)); }
-RT_HD void sincos_t(double a, double* s, double* c) { ::sincos(a, s, c); }
-RT_HD double value(double a) { return a; }
-template <int N> RT_HD double value(const gdual<N>& a) { return a.v; }
+
+// ----------------------------------------------------------------------------
+// forward-mode dual number with N tangents of scalar type T (nestable:
+// gdual<3, gdual<6>> carries mixed second derivatives), device and host
+// ----------------------------------------------------------------------------
+template <int N, class T = double>
+struct gdual {
+    T v;
+    T d[N];
+    __host__ __device__ gdual() : v(0.0) {
+        for (int i = 0; i < N; ++i) d[i] = T(0.0);
+    }
+    __host__ __device__ gdual(double c) : v(c) {
+        for (int i = 0; i < N; ++i) d[i] = T(0.0);
+    }
+    template <class U, class = typename std::enable_if<std::is_same<U, T>::value && !std::is_same<U, double>::value>::type>
+    __host__ __device__ gdual(const U& c) : v(c) {
+        for (int i = 0; i < N; ++i) d[i] = T(0.0);
+    }
+};
+
+template <int N, class T> RT_HD double value(const gdual<N, T>& a) { return value(a.v); }
+
+template <class X> struct is_dual { static const bool value = false; };
+template <int N, class T> struct is_dual<gdual<N, T>> { static const bool value = true; };
+
+// overwrite the value part, keeping every tangent
+RT_HD void set_value(double& a, double v) { a = v; }
+template <int N, class T> RT_HD void set_value(gdual<N, T>& a, double v) { set_value(a.v, v); }
+
+template <int N, class T> RT_HD gdual<N, T> operator+(const gdual<N, T>& a, const gdual<N, T>& b) {
+    gdual<N, T> r; r.v = a.v + b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> operator-(const gdual<N, T>& a, const gdual<N, T>& b) {
+    gdual<N, T> r; r.v = a.v - b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> operator-(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = -a.v;
+    for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> operator*(const gdual<N, T>& a, const gdual<N, T>& b) {
+    gdual<N, T> r; r.v = a.v * b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+    return r;
+}
+// scalar (double, or the inner type T) on either side
+template <int N, class T, class U>
+using gd_scalar = typename std::enable_if<std::is_same<U, double>::value ||
+                                              (std::is_same<U, T>::value && !std::is_same<T, double>::value),
+                                          gdual<N, T>>::type;
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator*(const U& a, const gdual<N, T>& b) {
+    gdual<N, T> r; r.v = a * b.v;
+    for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i];
+    return r;
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator*(const gdual<N, T>& b, const U& a) {
+    return a * b;
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator+(const U& a, const gdual<N, T>& b) {
+    gdual<N, T> r = b; r.v = a + b.v; return r;
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator+(const gdual<N, T>& b, const U& a) {
+    gdual<N, T> r = b; r.v = b.v + a; return r;
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator-(const U& a, const gdual<N, T>& b) {
+    return a + (-b);
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator-(const gdual<N, T>& b, const U& a) {
+    gdual<N, T> r = b; r.v = b.v - a; return r;
+}
+template <int N, class T> RT_HD gdual<N, T> rcp(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = rcp(a.v);
+    T g = -(r.v * r.v);
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> operator/(const gdual<N, T>& a, const gdual<N, T>& b) {
+    return a * rcp(b);
+}
+template <int N, class T, class U> RT_HD gd_scalar<N, T, U> operator/(const U& a, const gdual<N, T>& b) {
+    return a * rcp(b);
+}
+template <int N, class T> RT_HD gdual<N, T> operator/(const gdual<N, T>& a, double b) { return a * (1.0 / b); }
+template <int N, class T> RT_HD gdual<N, T> sqrt(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = sqrt(a.v);
+    T g = 0.5 * rcp(r.v);
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
+template <int N, class T> RT_HD void sincos_t(const gdual<N, T>& a, gdual<N, T>* s, gdual<N, T>* c) {
+    T sv, cv;
+    sincos_t(a.v, &sv, &cv);
+    s->v = sv; c->v = cv;
+    for (int i = 0; i < N; ++i) { s->d[i] = cv * a.d[i]; c->d[i] = -(sv * a.d[i]); }
+}
+template <int N, class T> RT_HD gdual<N, T> exp(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = exp(a.v);
+    for (int i = 0; i < N; ++i) r.d[i] = r.v * a.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> atan2(const gdual<N, T>& y, const gdual<N, T>& x) {
+    gdual<N, T> r; r.v = atan2(y.v, x.v);
+    T den = rcp(x.v * x.v + y.v * y.v);
+    for (int i = 0; i < N; ++i) r.d[i] = (x.v * y.d[i] - y.v * x.d[i]) * den;
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> fabs(const gdual<N, T>& a) { return (value(a) < 0.0) ? -a : a; }
+template <int N, class T> RT_HD gdual<N, T> frcp(const gdual<N, T>& a) { return rcp(a); }
+template <int N, class T> RT_HD gdual<N, T> frsqrt(const gdual<N, T>& a) { return rcp(sqrt(a)); }
 
 // ----------------------------------------------------------------------------
 // instance constants (integrator units: km, k in units of w_inf)
@@ -154,19 +206,6 @@ struct InstT {
     T ma2;     // (m_a / w_inf)^2
     int plasma, density;
     int oblique;  // sm != 0
-};
-
-// Weight and seeding constants, host-computed (physical units noted)
-struct SeedC {
-    double B0;          // polar surface field [G]
-    double period_km;   // P c [km]
-    double w_inf;       // axion energy at infinity [eV]
-    double nc_per_ka;   // n_inf w_inf / k0 [eV^3], multiplies |k_a|/w_inf
-    double g2;          // coupling^2 [eV^-2]
-    double G2;          // 1 gauss in eV^2
-    double Btest;       // constant |B_perp| [G] (zero-variance test)
-    double hbarc;       // [eV km]
-    int weights, kdir;
 };
 
 // ----------------------------------------------------------------------------

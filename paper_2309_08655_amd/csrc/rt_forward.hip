@@ -13,162 +13,11 @@ namespace rtd {
 // seeding
 // ----------------------------------------------------------------------------
 
-// Resonance function of the foliation along the radial line through n at the
-// emission time (axis m fixed), at radius r:
-//   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
-// (isotropic: F = P - m_a^2).  cos^2 theta_B is constant along the line.
-__device__ static double resonance_line(const InstT<double>& I, const double n[3], const double m[3], double mu,
-                                        double cB2, double r) {
-    double ir = 1.0 / r;
-    Plasma<double> p = plasma_eval(I, n, ir, m, mu, 0.0);
-    if (I.plasma == PL_ISO) return p.P - I.ma2;
-    double w2 = 1.0 / (1.0 - I.rs * ir);
-    return p.P * (w2 - (w2 - I.ma2) * cB2) - I.ma2 * w2;
-}
-
-// The same function at a general point x (for its spatial gradient, by dual numbers).
-template <class T>
-__device__ static T resonance_point(const InstT<double>& I, const T x[3], const double m[3], const double kh[3]) {
-    T r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-    T ir = rcp(r);
-    T n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
-    T mm[3] = {T(m[0]), T(m[1]), T(m[2])};
-    T mu = mm[0] * n[0] + mm[1] * n[1] + mm[2] * n[2];
-    InstT<T> J;
-    J.rs = T(I.rs); J.R = T(I.R); J.Om = T(I.Om); J.cm = T(I.cm); J.sm = T(I.sm); J.Cwp = T(I.Cwp);
-    J.R3 = T(I.R3); J.ma2 = T(I.ma2); J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
-    Plasma<T> p = plasma_eval(J, n, ir, mm, mu, T(0.0));
-    if (I.plasma == PL_ISO) return p.P - I.ma2;
-    T u[3];
-    dipole_dir(n, mm, mu, u);
-    T ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
-    T cB2 = ku * ku * rcp(1.0 + 3.0 * mu * mu);
-    T w2 = rcp(1.0 - I.rs * ir);
-    return p.P * (w2 - (w2 - I.ma2) * cB2) - I.ma2 * w2;
-}
-
-__device__ static void seed_one(const InstT<double>& I, const SeedC& C, uint64_t seed, int32_t instance,
-                                int64_t gi, double out[10], int32_t* status) {
-    uint32_t o[4];
-    double u[6];
-    for (uint32_t blk = 0; blk < 3; ++blk) {
-        philox4x32_10((uint32_t)(uint64_t)gi, (uint32_t)((uint64_t)gi >> 32), (uint32_t)instance, blk,
-                      (uint32_t)seed, (uint32_t)(seed >> 32), o);
-        u[2 * blk] = unit_from_bits(o[0], o[1]);
-        u[2 * blk + 1] = unit_from_bits(o[2], o[3]);
-    }
-    // emission direction uniform in (cos theta, phi)
-    double ct = 2.0 * u[0] - 1.0;
-    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
-    double sp, cp;
-    sincos(2.0 * M_PI * u[1], &sp, &cp);
-    double n[3] = {st * cp, st * sp, ct};
-    double kh[3];
-    {
-        double sa, ca;
-        sincos(2.0 * M_PI * u[3], &sa, &ca);
-        if (C.kdir == KD_ISO) {
-            double c = 2.0 * u[2] - 1.0, s = sqrt(fmax(0.0, 1.0 - c * c));
-            kh[0] = s * ca; kh[1] = s * sa; kh[2] = c;
-        } else {
-            // outward hemisphere about n: polar cosine u3, azimuth in the (theta-hat, phi-hat) basis
-            double c = u[2], s = sqrt(fmax(0.0, 1.0 - c * c));
-            double e1[3] = {ct * cp, ct * sp, -st};
-            double e2[3] = {-sp, cp, 0.0};
-            for (int d = 0; d < 3; ++d) kh[d] = c * n[d] + s * (ca * e1[d] + sa * e2[d]);
-        }
-    }
-    double t0 = u[4] * C.period_km;
-    double m[3], mt[3];
-    magnetic_axis(I, t0, m, mt);
-    double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
-    double ud[3];
-    dipole_dir(n, m, mu, ud);
-    double ku = kh[0] * ud[0] + kh[1] * ud[1] + kh[2] * ud[2];
-    double cB2 = ku * ku / (1.0 + 3.0 * mu * mu);
-
-    // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
-    double R = I.R;
-    double rc = -1.0;
-    if (resonance_line(I, n, m, mu, cB2, R) > 0.0) {
-        double lo = R, hi = 2.0 * R;
-        int j = 0;
-        while (!(resonance_line(I, n, m, mu, cB2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
-        if (resonance_line(I, n, m, mu, cB2, hi) < 0.0) {
-            for (int it = 0; it < 200; ++it) {
-                double mid = 0.5 * (lo + hi);
-                if (mid <= lo || mid >= hi) break;
-                if (resonance_line(I, n, m, mu, cB2, mid) > 0.0) lo = mid; else hi = mid;
-            }
-            rc = 0.5 * (lo + hi);
-        }
-    }
-    if (rc < 0.0) {
-        for (int d = 0; d < 10; ++d) out[d] = 0.0;
-        out[9] = -1.0;
-        *status = ST_NO_RESONANCE;
-        return;
-    }
-    *status = ST_OK;
-    double s = I.rs / rc;
-    double A = 1.0 - s;
-    double sA = sqrt(A);
-    double ka = sqrt(1.0 / A - I.ma2);
-    double x[3] = {rc * n[0], rc * n[1], rc * n[2]};
-    // photon covariant momentum from the static-frame axion momentum |k_a| kh
-    double ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
-    double nko = n[0] * ko[0] + n[1] * ko[1] + n[2] * ko[2];
-    double corr = nko / sA - nko;
-    double k[3] = {ko[0] + corr * n[0], ko[1] + corr * n[1], ko[2] + corr * n[2]};
-    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = t0;
-    out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = -1.0;
-    out[9] = rc;
-    if (C.weights == W_UNIT) { out[8] = 1.0; return; }
-
-    // ---- weight w = C_k n_c Vt Q ----
-    const double Ck = (C.kdir == KD_ISO) ? 4.0 * M_PI : 2.0 * M_PI;
-    double n_c = C.nc_per_ka * ka;
-    // surface element from grad F (dual numbers, 3 tangents)
-    gdual<3> xd[3];
-    for (int d = 0; d < 3; ++d) { xd[d] = gdual<3>(x[d]); xd[d].d[d] = 1.0; }
-    gdual<3> Fd = resonance_point(I, xd, m, kh);
-    double Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
-    double gp2 = 0.0;
-    for (int d = 0; d < 3; ++d) { double gp = Fd.d[d] - Fr * n[d]; gp2 += gp * gp; }
-    double Vt = sA * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr)) / (C.hbarc * C.hbarc);
-    double E = C.w_inf / sA;
-    double Rr = I.R / rc;
-    double Bmag = 0.5 * C.B0 * Rr * Rr * Rr * sqrt(1.0 + 3.0 * mu * mu);
-    double Bperp2 = (C.weights == W_CONV_CONSTB) ? (C.Btest * C.G2) * (C.Btest * C.G2)
-                                                  : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2);
-    double Q;
-    double ir = 1.0 / rc;
-    Plasma<double> p = plasma_eval(I, n, ir, m, mu, 0.0);
-    if (I.plasma == PL_ISO) {
-        double gn = n[0] * p.gx + n[1] * p.gy + n[2] * p.gz;
-        double g2 = p.gx * p.gx + p.gy * p.gy + p.gz * p.gz - s * gn * gn;
-        double dwp2 = C.hbarc * C.w_inf * C.w_inf * sqrt(g2);
-        Q = M_PI * C.g2 * Bperp2 * E * E / dwp2;
-    } else {
-        // dE/dx at fixed covariant k from H(x, k_t, k) = 0 with w = -k_t/sqrt(A):
-        //   dE/dx = (dH/dx) / (sqrt(A) dH/dk_t) - w s/(2 A r) n
-        double y[8] = {x[0], x[1], x[2], t0, k[0], k[1], k[2], -1.0};
-        double g[8];
-        grad_h(I, y, g);
-        double w = 1.0 / sA;
-        double c0 = 1.0 / (sA * g[7]);
-        double c1 = w * s * ir / (2.0 * A);
-        double dE[3] = {g[0] * c0 - c1 * n[0], g[1] * c0 - c1 * n[1], g[2] * c0 - c1 * n[2]};
-        double dn = n[0] * dE[0] + n[1] * dE[1] + n[2] * dE[2];
-        double dE2 = dE[0] * dE[0] + dE[1] * dE[1] + dE[2] * dE[2] - s * dn * dn;
-        double dEn = C.hbarc * C.w_inf * sqrt(dE2);
-        double wp2 = p.P * C.w_inf * C.w_inf;
-        double c2 = cB2, s2 = 1.0 - cB2;
-        double Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
-        double E2 = E * E;
-        Q = 0.5 * M_PI * C.g2 * Bperp2 * E2 * E2 * E / (Dd * dEn);
-    }
-    out[8] = Ck * n_c * Vt * Q;
+// Not inlined: the single-instance and the batched sampling kernels run this one copy of
+// the code, so a ray's seed is the same bits whichever kernel produced it.
+__device__ static __noinline__ void seed_one(const InstT<double>& I, const SeedT<double>& C, uint64_t seed,
+                                             int32_t instance, int64_t gi, double out[10], int32_t* status) {
+    *status = seed_ray<double>(I, C, seed, instance, gi, out);
 }
 
 // instance owning global ray i: largest k with off[k] <= i
@@ -182,7 +31,7 @@ __device__ __forceinline__ int32_t find_instance(const int64_t* __restrict__ off
 }
 
 __global__ void __launch_bounds__(256) sample_batched_kernel(const InstT<double>* __restrict__ itab,
-                                                             const SeedC* __restrict__ ctab,
+                                                             const SeedT<double>* __restrict__ ctab,
                                                              const int64_t* __restrict__ off, int32_t n_inst,
                                                              uint64_t seed, int64_t N, double* __restrict__ rays,
                                                              int32_t* __restrict__ status,
@@ -199,7 +48,7 @@ __global__ void __launch_bounds__(256) sample_batched_kernel(const InstT<double>
     }
 }
 
-__global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedC C, uint64_t seed, int32_t instance,
+__global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedT<double> C, uint64_t seed, int32_t instance,
                                                      int64_t first, int64_t n, double* __restrict__ rays,
                                                      int32_t* __restrict__ status) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -498,7 +347,7 @@ extern "C" int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t i
     if (n == 0) return RT_OK;
     if (!rays || !status) return fail(RT_EINVAL, "rt_sample_resonance: null output array");
     InstT<double> I = make_inst(*star);
-    SeedC C = make_seed_consts(*star);
+    SeedT<double> C = make_seed_consts(*star);
     int grid = grid_for(n, 256, 8);
     hipLaunchKernelGGL(sample_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, I, C, seed, instance, first, n,
                        rays, status);
@@ -572,7 +421,7 @@ int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, con
     return launch_trace_variant<true>(sc, I0, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
 }
 
-int launch_sample_batched(const InstT<double>* itab, const SeedC* ctab, const int64_t* off, int32_t n_inst,
+int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, const int64_t* off, int32_t n_inst,
                           uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st) {
     hipLaunchKernelGGL(sample_batched_kernel, dim3(grid_for(N, 256, 8)), dim3(256), 0, st, itab, ctab, off, n_inst,
                        seed, N, rays, status, inst_of);

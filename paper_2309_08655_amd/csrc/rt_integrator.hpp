@@ -24,6 +24,12 @@ constexpr double d1 = -12715105075.0 / 11282082432.0, d3 = 87487479700.0 / 32700
                  d6 = -1453857185.0 / 822651844.0, d7 = 69997945.0 / 29380423.0;
 }  // namespace dp5
 
+// tolerances and limits of one trace in integrator units (km)
+struct TolC {
+    double rtol, atol, rmax;
+    long long max_steps;
+};
+
 // Stage derivatives of one attempted step.  K[0] is the FSAL derivative at y.
 template <class T>
 struct StagesT {

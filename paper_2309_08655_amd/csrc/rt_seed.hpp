@@ -1,0 +1,310 @@
+// Star constants and resonance seeding, generic in the scalar type so that the
+// same code yields values (double) and their derivatives with respect to the six
+// star parameters p = (B0, P, theta_m, M, R, m_a) (dual numbers), for the adjoint.
+//
+// McDonald & Witte, arXiv:2309.08655: Sec. 2.2 eq. (Power) (forward Monte Carlo),
+// Sec. 3 eqs. (Hypersurfaces), (ForwardTracingEquation1) (resonance foliation),
+// Sec. 4.2 eqs. (RaidalHypersurface)-(PowerCurved) (surface measure), Sec. 4.3
+// eq. (fa_approx) (focused axion density), Sec. 4.4 eqs. (ProbIsoCurved),
+// (CPAnisoCurved) (conversion probability times flux projection), Sec. 5 eq.
+// (GJDensity) and Sec. 6 eq. (neMag) (densities).
+#pragma once
+
+#include "rt_device.hpp"
+
+namespace rtd {
+
+// CODATA 2018 / IAU 2015 constants used by the library
+namespace phys {
+constexpr double pi = 3.14159265358979323846;
+constexpr double c_kms = 299792.458;
+constexpr double c_cms = 2.99792458e10;
+constexpr double hbarc_eVkm = 1.973269804e-10;
+constexpr double hbarc_eVcm = 1.973269804e-5;
+constexpr double alpha = 1.0 / 137.035999084;
+constexpr double m_e_eV = 510998.95;
+constexpr double e_statC = 4.803204712570263e-10;
+constexpr double GMsun_km = 1.4766250;
+constexpr double erg_per_eV = 1.602176634e-12;
+// 1 G in eV^2 (Heaviside-Lorentz, hbar = c = 1): B^2/(8 pi) erg/cm^3 = B_HL^2 / 2
+RT_HD double gauss_eV2() { return ::sqrt(hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / (erg_per_eV * 4.0 * pi)); }
+// w_p^2 = 4 pi alpha n_e / m_e  [eV^2 per cm^-3]
+RT_HD double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / m_e_eV; }
+}  // namespace phys
+
+// parameters of a star that are never differentiated
+struct StarFixed {
+    double g_agg_GeV, v0_kms, rho_GeVcm3, multiplicity, psi_twist, B_test_G;
+    int plasma, density, weights, kdir;
+};
+
+// seeding / weight constants
+template <class T>
+struct SeedT {
+    T B0;          // polar surface field [G]
+    T period_km;   // P c [km]
+    T w_inf;       // axion energy at infinity [eV]
+    T nc_per_ka;   // n_inf w_inf / k0 [eV^3], multiplies |k_a|/w_inf
+    double g2;     // coupling^2 [eV^-2]
+    double G2;     // 1 gauss in eV^2
+    double Btest;  // constant |B_perp| [G] (zero-variance test)
+    double hbarc;  // [eV km]
+    int weights, kdir;
+};
+
+template <class T>
+RT_HD void sincos_any(const T& x, T* s, T* c) {
+    sincos_t(x, s, c);
+}
+
+// integrator-unit constants of one star: p = (B0 [G], P [s], theta_m [rad], M [Msun], R [km], m_a [eV])
+template <class T>
+RT_HD InstT<T> make_inst_t(const T p[6], const StarFixed& f) {
+    InstT<T> I;
+    const T& B0 = p[0]; const T& Ps = p[1]; const T& th = p[2];
+    const T& M = p[3]; const T& R = p[4]; const T& ma = p[5];
+    I.rs = (2.0 * phys::GMsun_km) * M;
+    I.R = R;
+    I.R3 = R * R * R;
+    T Om_s = (2.0 * phys::pi) * rcp(Ps);
+    I.Om = Om_s * (1.0 / phys::c_kms);
+    T s_, c_;
+    sincos_any(th, &s_, &c_);
+    I.cm = c_;
+    I.sm = s_;
+    I.oblique = (value(s_) != 0.0) ? 1 : 0;
+    double v0 = f.v0_kms / phys::c_kms;
+    T w_inf = ma * ::sqrt(1.0 + v0 * v0);
+    I.ma2 = T(1.0 / (1.0 + v0 * v0));
+    T Cp = phys::wp2_per_ne() * rcp(w_inf * w_inf);
+    // Goldreich-Julian number density scale Omega B0 / (4 pi e c) [cm^-3]
+    T n0 = Om_s * B0 * (1.0 / (4.0 * phys::pi * phys::e_statC * phys::c_cms));
+    if (f.density == DEN_GJ || f.density == DEN_SPH) {
+        I.Cwp = (Cp * n0) * f.multiplicity;
+    } else if (f.density == DEN_MAG) {
+        // lambda psi B0 (R/r)^3 sin^2 / (4 pi e r_cm), r_cm = 1e5 r_km
+        I.Cwp = Cp * B0 * (f.multiplicity * f.psi_twist / (4.0 * phys::pi * phys::e_statC * 1.0e5));
+    } else {
+        I.Cwp = T(0.0);
+    }
+    I.plasma = f.plasma;
+    I.density = f.density;
+    return I;
+}
+
+template <class T>
+RT_HD SeedT<T> make_seed_t(const T p[6], const StarFixed& f) {
+    SeedT<T> C;
+    double v0 = f.v0_kms / phys::c_kms;
+    C.B0 = p[0];
+    C.period_km = p[1] * phys::c_kms;
+    C.w_inf = p[5] * ::sqrt(1.0 + v0 * v0);
+    double rho_eV4 = f.rho_GeVcm3 * 1.0e9 * phys::hbarc_eVcm * phys::hbarc_eVcm * phys::hbarc_eVcm;
+    // n_inf w_inf / k0 = (rho / m_a) sqrt(1 + v0^2) / v0
+    C.nc_per_ka = rho_eV4 * (::sqrt(1.0 + v0 * v0) / v0) * rcp(p[5]);
+    double g = f.g_agg_GeV * 1.0e-9;
+    C.g2 = g * g;
+    C.G2 = phys::gauss_eV2();
+    C.Btest = f.B_test_G;
+    C.hbarc = phys::hbarc_eVkm;
+    C.weights = f.weights;
+    C.kdir = f.kdir;
+    return C;
+}
+
+template <class S, class T>
+RT_HD InstT<S> lift_inst(const InstT<T>& I) {
+    InstT<S> J;
+    J.rs = S(I.rs); J.R = S(I.R); J.Om = S(I.Om); J.cm = S(I.cm); J.sm = S(I.sm); J.Cwp = S(I.Cwp);
+    J.R3 = S(I.R3); J.ma2 = S(I.ma2);
+    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
+    return J;
+}
+
+// Resonance function of the foliation (kinematic matching k^a = k^gamma at fixed axion
+// direction kh in the static frame and fixed emission time):
+//   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
+// (isotropic plasma: F = P - m_a^2), at a general point x, for axis m.
+template <class S, class T>
+RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3]) {
+    InstT<S> J = lift_inst<S>(I);
+    S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    S ir = rcp(r);
+    S n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
+    S mm[3] = {S(m[0]), S(m[1]), S(m[2])};
+    S mu = mm[0] * n[0] + mm[1] * n[1] + mm[2] * n[2];
+    Plasma<S> pl = plasma_eval(J, n, ir, mm, mu, S(0.0));
+    if (I.plasma == PL_ISO) return pl.P - J.ma2;
+    S u[3];
+    for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - mm[i];
+    S ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
+    S cB2 = ku * ku * rcp(1.0 + 3.0 * mu * mu);
+    S w2 = rcp(1.0 - J.rs * ir);
+    return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+}
+
+// F along the radial line through n at radius r (values only: the bisection)
+template <class T>
+RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m[3], double mu, double cB2,
+                            double r) {
+    InstT<double> J;
+    J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
+    J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2);
+    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
+    double ir = 1.0 / r;
+    Plasma<double> pl = plasma_eval(J, n, ir, m, mu, 0.0);
+    if (I.plasma == PL_ISO) return pl.P - J.ma2;
+    double w2 = 1.0 / (1.0 - J.rs * ir);
+    return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+}
+
+// the six uniforms of ray gi (Philox4x32-10, key = seed, counter = (gi, instance, block))
+RT_HD void ray_uniforms(uint64_t seed, int32_t instance, int64_t gi, double u[6]) {
+    uint32_t o[4];
+    for (uint32_t blk = 0; blk < 3; ++blk) {
+        philox4x32_10((uint32_t)(uint64_t)gi, (uint32_t)((uint64_t)gi >> 32), (uint32_t)instance, blk,
+                      (uint32_t)seed, (uint32_t)(seed >> 32), o);
+        u[2 * blk] = unit_from_bits(o[0], o[1]);
+        u[2 * blk + 1] = unit_from_bits(o[2], o[3]);
+    }
+}
+
+// One seed: emission point on the resonance, photon momentum = axion momentum, weight.
+// out = (x, y, z, t, k_x, k_y, k_z, k_t, w, r_c); returns the status.
+template <class T>
+RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t instance, int64_t gi, T out[10]) {
+    double u[6];
+    ray_uniforms(seed, instance, gi, u);
+    // emission direction uniform in (cos theta, phi)
+    double ct = 2.0 * u[0] - 1.0;
+    double st = ::sqrt(fmax(0.0, 1.0 - ct * ct));
+    double sp, cp;
+    sincos_t(2.0 * phys::pi * u[1], &sp, &cp);
+    double n[3] = {st * cp, st * sp, ct};
+    double kh[3];
+    {
+        double sa, ca;
+        sincos_t(2.0 * phys::pi * u[3], &sa, &ca);
+        if (C.kdir == KD_ISO) {
+            double c = 2.0 * u[2] - 1.0, s = ::sqrt(fmax(0.0, 1.0 - c * c));
+            kh[0] = s * ca; kh[1] = s * sa; kh[2] = c;
+        } else {
+            // outward hemisphere about n: polar cosine u3, azimuth in the (theta-hat, phi-hat) basis
+            double c = u[2], s = ::sqrt(fmax(0.0, 1.0 - c * c));
+            double e1[3] = {ct * cp, ct * sp, -st};
+            double e2[3] = {-sp, cp, 0.0};
+            for (int d = 0; d < 3; ++d) kh[d] = c * n[d] + s * (ca * e1[d] + sa * e2[d]);
+        }
+    }
+    T t0 = u[4] * C.period_km;
+    T mT[3], mtT[3];
+    magnetic_axis(I, t0, mT, mtT);
+    double m[3] = {value(mT[0]), value(mT[1]), value(mT[2])};
+    double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    double ud[3];
+    for (int d = 0; d < 3; ++d) ud[d] = 3.0 * mu * n[d] - m[d];
+    double ku = kh[0] * ud[0] + kh[1] * ud[1] + kh[2] * ud[2];
+    double cB2 = ku * ku / (1.0 + 3.0 * mu * mu);
+
+    // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
+    double R = value(I.R);
+    double rcv = -1.0;
+    if (resonance_line(I, n, m, mu, cB2, R) > 0.0) {
+        double lo = R, hi = 2.0 * R;
+        int j = 0;
+        while (!(resonance_line(I, n, m, mu, cB2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
+        if (resonance_line(I, n, m, mu, cB2, hi) < 0.0) {
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                if (resonance_line(I, n, m, mu, cB2, mid) > 0.0) lo = mid; else hi = mid;
+            }
+            rcv = 0.5 * (lo + hi);
+        }
+    }
+    if (rcv < 0.0) {
+        for (int d = 0; d < 10; ++d) out[d] = T(0.0);
+        out[9] = T(-1.0);
+        return ST_NO_RESONANCE;
+    }
+    // r_c carries dr_c/dp = -(dF/dp)/(dF/dr) through one Newton correction (a no-op on the value)
+    T rc = T(rcv);
+    if constexpr (is_dual<T>::value) {
+        typedef gdual<1, T> D1;
+        D1 rd{T(rcv)};
+        rd.d[0] = T(1.0);
+        D1 xd[3] = {rd * n[0], rd * n[1], rd * n[2]};
+        D1 Fd = resonance_point<D1, T>(I, xd, mT, kh);
+        rc = T(rcv) - Fd.v * rcp(Fd.d[0]);
+        set_value(rc, rcv);
+    }
+    T s = I.rs * rcp(rc);
+    T A = 1.0 - s;
+    T sA = sqrt(A);
+    T ka = sqrt(rcp(A) - I.ma2);
+    T x[3] = {rc * n[0], rc * n[1], rc * n[2]};
+    // photon covariant momentum from the static-frame axion momentum |k_a| kh
+    T ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
+    T nko = n[0] * ko[0] + n[1] * ko[1] + n[2] * ko[2];
+    T corr = nko * rcp(sA) - nko;
+    T k[3] = {ko[0] + corr * n[0], ko[1] + corr * n[1], ko[2] + corr * n[2]};
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = t0;
+    out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = T(-1.0);
+    out[9] = rc;
+    if (C.weights == W_UNIT) { out[8] = T(1.0); return ST_OK; }
+
+    // ---- weight w = C_k n_c Vt Q ----
+    const double Ck = (C.kdir == KD_ISO) ? 4.0 * phys::pi : 2.0 * phys::pi;
+    T n_c = C.nc_per_ka * ka;
+    // surface element from grad F (dual numbers over x, 3 tangents)
+    typedef gdual<3, T> D3;
+    D3 xd[3];
+    for (int d = 0; d < 3; ++d) { xd[d] = D3(x[d]); xd[d].d[d] = T(1.0); }
+    D3 Fd = resonance_point<D3, T>(I, xd, mT, kh);
+    T Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
+    T gp2 = T(0.0);
+    for (int d = 0; d < 3; ++d) { T gp = Fd.d[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
+    T Vt = sA * rc * rc * sqrt(1.0 + gp2 * rcp(A * Fr * Fr)) * (1.0 / (C.hbarc * C.hbarc));
+    T E = C.w_inf * rcp(sA);
+    T ir = rcp(rc);
+    T Rr = I.R * ir;
+    T nT[3] = {T(n[0]), T(n[1]), T(n[2])};
+    T muT = mT[0] * nT[0] + mT[1] * nT[1] + mT[2] * nT[2];
+    T Bmag = 0.5 * C.B0 * Rr * Rr * Rr * sqrt(1.0 + 3.0 * muT * muT);
+    T uT[3];
+    for (int d = 0; d < 3; ++d) uT[d] = 3.0 * muT * nT[d] - mT[d];
+    T kuT = kh[0] * uT[0] + kh[1] * uT[1] + kh[2] * uT[2];
+    T cB2T = kuT * kuT * rcp(1.0 + 3.0 * muT * muT);
+    T Bperp2 = (C.weights == W_CONV_CONSTB) ? T((C.Btest * C.G2) * (C.Btest * C.G2))
+                                            : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2T);
+    T Q;
+    Plasma<T> pl = plasma_eval(I, nT, ir, mT, muT, T(0.0));
+    if (I.plasma == PL_ISO) {
+        T gn = n[0] * pl.gx + n[1] * pl.gy + n[2] * pl.gz;
+        T g2 = pl.gx * pl.gx + pl.gy * pl.gy + pl.gz * pl.gz - s * gn * gn;
+        T dwp2 = C.hbarc * C.w_inf * C.w_inf * sqrt(g2);
+        Q = (phys::pi * C.g2) * Bperp2 * E * E * rcp(dwp2);
+    } else {
+        // dE/dx at fixed covariant k from H(x, k_t, k) = 0 with w = -k_t/sqrt(A):
+        //   dE/dx = (dH/dx) / (sqrt(A) dH/dk_t) - w s/(2 A r) n
+        T y[8] = {x[0], x[1], x[2], t0, k[0], k[1], k[2], T(-1.0)};
+        T g[8];
+        grad_h(I, y, g);
+        T w = rcp(sA);
+        T c0 = rcp(sA * g[7]);
+        T c1 = w * s * ir * rcp(2.0 * A);
+        T dE[3] = {g[0] * c0 - c1 * n[0], g[1] * c0 - c1 * n[1], g[2] * c0 - c1 * n[2]};
+        T dn = n[0] * dE[0] + n[1] * dE[1] + n[2] * dE[2];
+        T dE2 = dE[0] * dE[0] + dE[1] * dE[1] + dE[2] * dE[2] - s * dn * dn;
+        T dEn = C.hbarc * C.w_inf * sqrt(dE2);
+        T wp2 = pl.P * C.w_inf * C.w_inf;
+        T c2 = cB2T, s2 = 1.0 - cB2T;
+        T Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
+        T E2 = E * E;
+        Q = (0.5 * phys::pi * C.g2) * Bperp2 * E2 * E2 * E * rcp(Dd * dEn);
+    }
+    out[8] = Ck * n_c * Vt * Q;
+    return ST_OK;
+}
+
+}  // namespace rtd

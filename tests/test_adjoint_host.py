@@ -1,0 +1,108 @@
+"""The hand-written adjoint of the smoothed flux (paper_2309_08655_amd/csrc/rt_adjoint.hpp),
+compiled for the host from the same source, against the oracle's forward-mode derivatives
+ray by ray.  Runs without a GPU.
+
+Per ray, the adjoint and forward mode differentiate the same frozen-step map when the two
+integrators take the same steps, which they do on rays that are well conditioned (the
+oracle's own direction changes by <= 1e-11 rad and its step counts do not change when the
+seed is perturbed by 2^-50): there the derivatives must agree to 1e-8 (relative norm over
+the six parameters, each scaled by its RMS over the rays).  Ill-conditioned rays (those
+that graze the kink of the Goldreich-Julian density) take different step sequences in any
+two implementations; they are reported, and their statuses must still agree."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import WELL_TOL, oracle_conditioning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PER_RAY_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def hadj(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("hostadj") / "host_adjoint.so")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    subprocess.run([hipcc, "-std=c++17", "-O2", "-fPIC", "-shared", "-o", out,
+                    os.path.join(ROOT, "tests", "host_adjoint.cpp")], check=True, capture_output=True)
+    L = C.CDLL(out)
+    dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+    L.host_flux_grad.restype = C.c_longlong
+    L.host_flux_grad.argtypes = [dp, dp, ip, dp, C.c_longlong, C.c_ulonglong, C.c_longlong, dp, C.c_int, C.c_double,
+                                 dp, C.c_int, C.c_int, dp, dp, ip, ip, dp]
+    return L
+
+
+def host_flux_grad(L, s, t, seed, n, obs, sigma, gbar, C_every=64, max_ckpt=4096):
+    P = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    p = np.array([s[k] for k in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")])
+    fd = np.array([s[k] for k in ("g_agg_GeV", "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")])
+    fi = np.array([s["plasma"], s["density"], s["weights"], s["kdir"]], dtype=np.int32)
+    tl = np.array([t["rtol"], t["atol"], t["r_max_km"]])
+    obs = np.ascontiguousarray(obs, dtype=np.float64)
+    flux, grad = np.zeros(len(obs)), np.zeros(6)
+    st, na, gr = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32), np.zeros((n, 6))
+    ip = C.POINTER(C.c_int)
+    miss = L.host_flux_grad(P(p), P(fd), fi.ctypes.data_as(ip), P(tl), int(t["max_steps"]), seed, n, P(obs),
+                            len(obs), sigma, P(np.ascontiguousarray(gbar, dtype=np.float64)), C_every, max_ckpt,
+                            P(flux), P(grad), st.ctypes.data_as(ip), na.ctypes.data_as(ip), P(gr))
+    return flux, grad, st, na, gr, miss
+
+
+def per_ray_errors(g, go):
+    sc = np.sqrt((go ** 2).mean(axis=0))
+    sc = np.where(sc > 0, sc, 1.0)
+    num = np.linalg.norm((g - go) / sc, axis=1)
+    den = np.linalg.norm(go / sc, axis=1)
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
+
+
+CASES = {
+    "cfg1-gj-iso-aligned": (W.CFG1["star"], 200),
+    "cfg2-gj-aniso-gr-oblique": (W.CFG2["star"], 120),
+    "spherical-aniso-gr-oblique": (W.star(M_Msun=1.4, theta_m=0.3, density=W.DENSITY_SPHERICAL,
+                                          plasma=W.PLASMA_ANISO, m_a_eV=1e-5, kdir=W.KDIR_OUTWARD), 120),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_host_adjoint_matches_oracle_forward_mode(orc, hadj, case):
+    s, n = CASES[case]
+    t = W.tol()
+    obs, sigma = W.observers(32), 0.02 if "spherical" not in case else 0.05
+    gbar = np.random.default_rng(7).standard_normal(32)
+    fh, gh, st, na, gr, miss = host_flux_grad(hadj, s, t, 0, n, obs, sigma, gbar)
+    assert miss == 0
+    F, dF, fray, dray, sto = orc.flux_fwdmode(s, t, 0, n, obs, sigma, per_ray=True)
+    assert np.array_equal(st, sto)
+    go = np.einsum("j,njq->nq", gbar, dray)
+    rays, status = orc.sample(s, 0, n)
+    fin, ifin = orc.trace_forward(s, t, rays, status)
+    sd, ch = oracle_conditioning(orc, s, t, rays, status, fin, ifin)
+    well = (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED)
+    assert well.sum() >= 20
+    assert np.array_equal(na[well], ifin[0][well])
+    err = per_ray_errors(gr, go)
+    assert err[well].max() <= PER_RAY_TOL, (case, err[well].max())
+    if well.sum() == (sto == W.STATUS_ESCAPED).sum():
+        # every escaped ray is well conditioned: the totals agree as well
+        assert np.abs(fh - F).max() <= 1e-9 * np.abs(F).max()
+        assert np.linalg.norm(gh - gbar @ dF) <= PER_RAY_TOL * np.linalg.norm(gbar @ dF)
+
+
+def test_host_adjoint_checkpoint_interval_is_invisible(hadj):
+    """The recompute from checkpoints reproduces the forward steps exactly, so the gradient
+    does not depend on the checkpoint interval (bit for bit)."""
+    s, t = W.CFG1["star"], W.tol()
+    obs, gbar = W.observers(32), np.ones(32)
+    a = host_flux_grad(hadj, s, t, 0, 64, obs, 0.02, gbar, C_every=64)
+    b = host_flux_grad(hadj, s, t, 0, 64, obs, 0.02, gbar, C_every=1, max_ckpt=1 << 16)
+    c = host_flux_grad(hadj, s, t, 0, 64, obs, 0.02, gbar, C_every=7)
+    for x in (b, c):
+        assert np.array_equal(a[4], x[4]) and np.array_equal(a[0], x[0]) and x[5] == 0

@@ -1,0 +1,183 @@
+"""GPU parity of the smoothed-flux adjoint (rt_flux_grad) against the oracle's forward-mode
+derivatives, through the C ABI.
+
+Per ray: on well-conditioned escaped rays (the oracle's direction moves by <= 1e-11 rad and
+its step counts stay put under 2^-50 seed perturbations) the GPU and the oracle integrate
+the same frozen-step map, so each ray's gradient share must agree to 1e-8 (relative norm
+over the six parameters, each scaled by its RMS over the rays).  Statuses must agree on
+every ray.  On a star without the Goldreich-Julian kink every ray is well conditioned and
+the totals must agree too: flux 1e-9, gradient 1e-8 (vector norm).  With the kink, the
+total flux may differ by no more than the ill-conditioned rays' own share.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import WELL_TOL, oracle_conditioning
+
+pytestmark = pytest.mark.gpu
+
+PER_RAY_TOL = 1e-8
+SPHERICAL = W.star(M_Msun=1.4, theta_m=0.3, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ANISO, m_a_eV=1e-5,
+                   kdir=W.KDIR_OUTWARD)
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_08655_amd as rt
+    rt.lib()
+    return rt
+
+
+def per_ray_errors(g, go):
+    sc = np.sqrt((go ** 2).mean(axis=0))
+    sc = np.where(sc > 0, sc, 1.0)
+    num = np.linalg.norm((g - go) / sc, axis=1)
+    den = np.linalg.norm(go / sc, axis=1)
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
+
+
+def gpu_flux_grad(rt, star, tol, seed, n, obs, sigma, gbar, ckpt_every=64, max_ckpt=64):
+    import torch
+    fg = rt.FluxGrad(star, tol, seed, n, obs, sigma, ckpt_every, max_ckpt)
+    F, info = fg.forward(ray_info=True)
+    g, gr = fg.backward(torch.as_tensor(gbar), per_ray=True)
+    torch.cuda.synchronize()
+    return F.cpu().numpy(), g.cpu().numpy(), gr.cpu().numpy(), info.cpu().numpy()
+
+
+def well_conditioned(orc, star, tol, n, sto):
+    rays, status = orc.sample(star, 0, n)
+    fin, ifin = orc.trace_forward(star, tol, rays, status)
+    sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin)
+    return (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED), ifin
+
+
+@pytest.mark.parametrize("name,star,n,sigma", [
+    ("cfg1-gj-iso-aligned", W.CFG1["star"], 600, 0.02),
+    ("cfg2-gj-aniso-gr-oblique", W.CFG2["star"], 300, 0.02),
+    ("spherical-aniso-gr-oblique", SPHERICAL, 300, 0.05),
+    ("ragged-n-37", W.CFG1["star"], 37, 0.02),
+])
+def test_flux_grad_matches_oracle(rt, orc, name, star, n, sigma):
+    print(f"adjoint parity {name} n={n}", flush=True)
+    tol = W.tol()
+    obs = W.observers(32)
+    gbar = np.random.default_rng(11).standard_normal(32)
+    F, g, gr, info = gpu_flux_grad(rt, star, tol, 0, n, obs, sigma, gbar)
+    Fo, dFo, fray, dray, sto = orc.flux_fwdmode(star, tol, 0, n, obs, sigma, per_ray=True)
+    assert np.array_equal(info[2], sto)
+    well, ifin = well_conditioned(orc, star, tol, n, sto)
+    assert np.array_equal(info[0][well], ifin[0][well])
+    go = np.einsum("j,njq->nq", gbar, dray)
+    err = per_ray_errors(gr, go)
+    if well.any():
+        assert err[well].max() <= PER_RAY_TOL, (name, err[well].max())
+    assert np.all(gr[sto != W.STATUS_ESCAPED] == 0.0)
+    assert np.allclose(gr.sum(axis=0), g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
+    esc = sto == W.STATUS_ESCAPED
+    if well.sum() == esc.sum():
+        assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
+        assert np.linalg.norm(g - gbar @ dFo) <= PER_RAY_TOL * np.linalg.norm(gbar @ dFo)
+    else:
+        ill_share = fray[esc & ~well].sum(axis=0)
+        assert np.all(np.abs(F - Fo) <= 1e-9 * np.abs(Fo).max() + ill_share)
+    print(name, "well", int(well.sum()), "escaped", int(esc.sum()), "max per-ray err (well)",
+          float(err[well].max()) if well.any() else None, flush=True)
+
+
+def test_checkpoint_interval_is_invisible(rt):
+    """Forward pass and recompute run the same step code, so the checkpoint interval
+    changes nothing: per-ray gradients are identical bit for bit."""
+    star, tol = W.CFG1["star"], W.tol()
+    obs, gbar = W.observers(32), np.ones(32)
+    a = gpu_flux_grad(rt, star, tol, 0, 256, obs, 0.02, gbar, ckpt_every=64, max_ckpt=64)
+    b = gpu_flux_grad(rt, star, tol, 0, 256, obs, 0.02, gbar, ckpt_every=1, max_ckpt=4096)
+    c = gpu_flux_grad(rt, star, tol, 0, 256, obs, 0.02, gbar, ckpt_every=13, max_ckpt=400)
+    for x in (b, c):
+        assert np.array_equal(a[2], x[2])
+        assert np.array_equal(a[3], x[3])
+
+
+def test_reverse_is_linear_in_gbar_and_repeatable(rt):
+    import torch
+    star, tol = W.CFG1["star"], W.tol()
+    obs = W.observers(32)
+    fg = rt.FluxGrad(star, tol, 0, 300, obs, 0.02)
+    fg.forward()
+    rng = np.random.default_rng(5)
+    a, b = rng.standard_normal(32), rng.standard_normal(32)
+    ga = fg.backward(torch.as_tensor(a)).cpu().numpy().copy()
+    gb = fg.backward(torch.as_tensor(b)).cpu().numpy().copy()
+    gab = fg.backward(torch.as_tensor(2.0 * a - 3.0 * b)).cpu().numpy().copy()
+    ga2 = fg.backward(torch.as_tensor(a)).cpu().numpy().copy()
+    assert np.allclose(ga, ga2, rtol=1e-12, atol=0.0)
+    assert np.allclose(gab, 2.0 * ga - 3.0 * gb, rtol=1e-10, atol=1e-10 * np.abs(gab).max())
+
+
+def test_checkpoint_budget_and_errors(rt):
+    import torch
+    star, tol = W.CFG1["star"], W.tol()
+    obs = W.observers(4)
+    # budget of one checkpoint every 8 steps, at most 2: rays longer than 16 steps end as MAX_STEPS
+    fg = rt.FluxGrad(star, tol, 0, 64, obs, 0.05, ckpt_every=8, max_ckpt=2)
+    _, info = fg.forward(ray_info=True)
+    info = info.cpu().numpy()
+    assert np.all(info[0][info[2] == W.STATUS_ESCAPED] <= 16)
+    assert np.all(info[2][info[0] > 16] != W.STATUS_ESCAPED)
+    # a reverse call on a workspace without its forward phase computes nothing (NaN)
+    fresh = rt.FluxGrad(star, tol, 0, 64, obs, 0.05)
+    fresh.ws.zero_()
+    g = fresh.backward(torch.ones(4, dtype=torch.float64)).cpu().numpy()
+    assert np.all(np.isnan(g))
+    # argument validation
+    with pytest.raises(rt.RtError):
+        rt.rt_flux_grad(star, tol, 0, 64, np.zeros((65, 3)), 0.02, 0, fg.ws)
+    with pytest.raises(rt.RtError):
+        rt.rt_flux_grad(star, tol, 0, 64, obs, -1.0, 0, fg.ws, flux=fg.flux)
+    with pytest.raises(rt.RtError):
+        rt.rt_flux_grad(star, tol, 0, 64, obs, 0.02, 0, fg.ws[:100], flux=fg.flux)
+    with pytest.raises(rt.RtError):
+        rt.rt_flux_grad(star, tol, 0, 64, obs, 0.02, 2, fg.ws, flux=fg.flux)
+
+
+def test_autograd_function(rt, orc):
+    import torch
+    star, tol = W.CFG1["star"], W.tol()
+    obs = W.observers(32)
+    p = torch.tensor([star[k] for k in rt.PARAMS], dtype=torch.float64, requires_grad=True)
+    F = rt.FluxFn.apply(p, star, tol, 0, 200, obs, 0.02)
+    w = torch.linspace(-1.0, 1.0, 32, dtype=torch.float64)
+    (F.cpu() * w).sum().backward()
+    fg = rt.FluxGrad(star, tol, 0, 200, obs, 0.02)
+    fg.forward()
+    g = fg.backward(w).cpu()
+    # totals are sums of per-wave partials in arrival order: equal to roundoff, not bit for bit
+    assert torch.allclose(p.grad.cpu(), g, rtol=1e-12, atol=0.0)
+
+
+def test_full_size_sampled(rt, orc):
+    """The benchmark configuration (1e6 rays, 32 observers, checkpoints every 64 steps):
+    the first 1000 rays' gradient shares against the oracle's, ray by ray (shares are
+    divided by n, so the oracle's are rescaled by 1000 / 1e6)."""
+    import torch
+    cfg = W.CFG5
+    star, tol, n = cfg["star"], cfg["tol"], cfg["n"]
+    obs = W.observers(cfg["n_obs"])
+    gbar = np.random.default_rng(3).standard_normal(cfg["n_obs"])
+    print("adjoint full size", n, flush=True)
+    F, g, gr, info = gpu_flux_grad(rt, star, tol, cfg["seed"], n, obs, cfg["sigma"], gbar, cfg["ckpt_every"], 64)
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(g))
+    m = 1000
+    Fo, dFo, fray, dray, sto = orc.flux_fwdmode(star, tol, cfg["seed"], m, obs, cfg["sigma"], per_ray=True)
+    assert np.array_equal(info[2][:m], sto)
+    well, _ = well_conditioned(orc, star, tol, m, sto)
+    go = np.einsum("j,njq->nq", gbar, dray) * (m / n)
+    err = per_ray_errors(gr[:m], go)
+    assert err[well].max() <= PER_RAY_TOL, err[well].max()
+    esc = info[2] == W.STATUS_ESCAPED
+    assert esc.mean() > 0.9
+    torch.cuda.synchronize()
