@@ -27,6 +27,38 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, AMD published (256 CU x 128 FLOP/clk x 2.4 GHz)
 
 
+# HBM traffic of the tracing kernel, measured with hardware counters (FETCH_SIZE and
+# WRITE_SIZE per dispatch, each scaled by what it reads for a copy of known size) on this
+# workload; valid only while the kernel's sources are the ones it was measured on
+HBM_SUMMARY = os.path.join(ROOT, "profiles", "trace_fwd_kernel_forward-full-1e6_hbm.md")
+TRACE_SOURCES = ["rt_forward.hip", "rt_common.hpp", "rt_device.hpp", "rt_integrator.hpp", "rt_seed.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_08655_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hbm_traffic(n):
+    """Counter-measured HBM bytes per launch of the tracing kernel, or None when there is no
+    measurement for these sources and this ray count."""
+    if not os.path.exists(HBM_SUMMARY):
+        return None
+    vals = {}
+    with open(HBM_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash() or int(vals.get("rays", -1)) != n:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def variant_key(star):
     pl = "iso" if star["plasma"] == 0 else "aniso"
     de = ["gj", "magnetar", "spherical", "none"][star["density"]]
@@ -126,6 +158,54 @@ def bench_batched(args, rt, W, np, torch):
                 per_instance_ms=ms_loop, speedup_vs_per_instance=ms_loop / ms, tune_ms=times)
 
 
+def bench_adjoint(args, rt, W, np, torch):
+    """Smoothed flux at 32 observers and its gradient with respect to the six star parameters
+    (config-1 star, 1e6 rays, checkpoint every 64 accepted steps): forward phase (trace with
+    checkpoints) and reverse phase (recompute + stage adjoints) timed separately."""
+    cfg = W.CFG5
+    star, tol, n, C = cfg["star"], cfg["tol"], cfg["n"], cfg["ckpt_every"]
+    obs = W.observers(cfg["n_obs"])
+    print(f"bench: adjoint {cfg['name']} n={n}", file=sys.stderr, flush=True)
+    fg = rt.FluxGrad(star, tol, cfg["seed"], n, obs, cfg["sigma"], C, 64)
+    gbar = torch.linspace(-1.0, 1.0, cfg["n_obs"], dtype=torch.float64, device="cuda")
+    _, info = fg.forward(ray_info=True)
+    fg.backward(gbar)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    reps = max(2, min(args.steps, 5))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for r in range(reps):
+        ev[r][0].record(stream)
+        fg.forward()
+        ev[r][1].record(stream)
+        fg.backward(gbar)
+        ev[r][2].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    rev_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    inf = info.cpu().numpy().astype(np.int64)
+    acc, rej, st = inf[0], inf[1], inf[2]
+    traced = st != W.STATUS_NO_RESONANCE
+    esc = st == W.STATUS_ESCAPED
+    # the adjoint always runs the rotating-axis formula, so the oblique variant's counts apply
+    ft = flop_table()["iso_gj_oblique"]
+    flops_fwd = float((acc + rej)[traced].sum()) * ft["attempt"] + float(traced.sum()) * 3 * ft["rhs"]
+    nseg = (acc[esc] + C - 1) // C
+    # reverse, per escaped ray: recompute every attempt of its segments, then per accepted step
+    # one FSAL derivative + one attempt (stage states) + the six stage adjoints + the b-weights
+    flops_rev = (float((acc + rej)[esc].sum()) * ft["attempt"] + float(nseg.sum()) * ft["rhs"]
+                 + float(acc[esc].sum()) * (ft["rhs"] + ft["attempt"] + ft["stages_adjoint"] + 80))
+    tot_ms = fwd_ms + rev_ms
+    return dict(workload=cfg["name"], rays=n, traced_rays=int(traced.sum()), escaped_rays=int(esc.sum()),
+                observers=cfg["n_obs"], ckpt_every=C, forward_ms=fwd_ms, reverse_ms=rev_ms,
+                ms_per_gradient=tot_ms, accepted_steps=float(acc[traced].sum()),
+                ray_steps_per_s=float(acc[traced].sum()) / (tot_ms * 1e-3),
+                rays_per_s=float(traced.sum()) / (tot_ms * 1e-3),
+                forward_tflops=flops_fwd / (fwd_ms * 1e-3) / 1e12, reverse_tflops=flops_rev / (rev_ms * 1e-3) / 1e12,
+                flop_per_vjp=ft["vjp"], flop_per_stage_adjoint=ft["stages_adjoint"],
+                checkpoint_bytes=int(nseg.sum()) * 80, workspace_bytes=int(fg.ws.numel()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,9 +215,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched",
-                    help="comma list of forms to time: plain (the headline value), batched")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default schedule)")
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint",
+                    help="comma list of forms to time beside plain (the headline value): batched, adjoint")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the plain form's schedule too (default: the library's default schedule)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -179,22 +261,13 @@ def main():
     over = torch.empty(2, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    ev_trace = []
-
-    def step(record=False):
+    def step():
         rt.rt_sample_resonance(cfg["star"], cfg["seed"], n, rays=rays, status=status)
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
         rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, status, schedule=sched, ws=ws, fin=fin, ifin=ifin)
-        if record:
-            e1.record(stream)
-            ev_trace.append((e0, e1))
         rt.rt_bin_flux(fin, ifin, rays[8], b, ws=wsb, hist=hist, cnt=cnt, over=over)
 
     tune_times = None
-    if sched is None and not args.no_tune:
+    if sched is None and args.tune:
         from paper_2309_08655_amd import autotune
         rt.rt_sample_resonance(cfg["star"], cfg["seed"], n, rays=rays, status=status)
         sched, tune_times = autotune.tune(
@@ -208,14 +281,19 @@ def main():
     torch.cuda.synchronize()
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    # HIP events around every launch of the persistent tracing kernel, on its stream
+    rt.timing(True)
     t_start.record(stream)
     for k in range(args.steps):
-        step(record=True)
+        step()
     t_end.record(stream)
     torch.cuda.synchronize()
+    rt.timing(False)
     total_ms = t_start.elapsed_time(t_end)
     ms_step = total_ms / args.steps
-    trace_ms = float(np.mean([a.elapsed_time(bb) for a, bb in ev_trace]))
+    ktimes = [ms for name, ms in rt.kernel_times() if name == "trace_fwd_kernel"]
+    assert len(ktimes) == args.steps, ktimes
+    trace_ms = float(np.mean(ktimes))
 
     ifn = ifin.cpu().numpy()
     stn = status.cpu().numpy()
@@ -229,16 +307,14 @@ def main():
     rays_per_s = n_traced / (ms_step * 1e-3)
 
     ft = flop_table()[variant_key(cfg["star"])]
-    # algorithmic work of one rt_trace_forward launch: every attempted step costs one DOPRI5
-    # attempt; the init pass costs 2 right-hand sides per traced ray (FSAL derivative and the
-    # starting-step probe)
-    flops = (acc + rej) * ft["attempt"] + n_traced * 2 * ft["rhs"]
+    # algorithmic work of one launch of the persistent tracing kernel: one DOPRI5 attempt per
+    # attempted step (the FSAL derivative and starting step come from the init kernel)
+    flops = (acc + rej) * ft["attempt"]
     achieved_tflops = flops / (trace_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=achieved_tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, traffic=None,
-                    kernel="rt_trace_forward (trace_init_kernel + trace_fwd_kernel)",
-                    trace_ms=trace_ms, flop_per_attempt=ft["attempt"], flop_per_rhs=ft["rhs"],
-                    attempted_steps=acc + rej)
+                    frac=achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, traffic=hbm_traffic(n),
+                    kernel="trace_fwd_kernel", kernel_ms=trace_ms, flop_per_attempt=ft["attempt"],
+                    attempted_steps=acc + rej, flop_per_launch=flops)
     out = dict(metric="ray-steps/s and rays/s at rtol 1e-8 (FP64), plain vs batched vs adjoint",
                value=steps_per_s, unit="ray-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
@@ -251,8 +327,11 @@ def main():
                                                  p9999=float(np.percentile(att, 99.99)), max=int(att.max())),
                            schedule=sched, autotune_ms=tune_times),
                roofline=roofline)
+    out["forms"] = {}
     if "batched" in forms:
-        out["forms"] = dict(batched=bench_batched(args, rt, W, np, torch))
+        out["forms"]["batched"] = bench_batched(args, rt, W, np, torch)
+    if "adjoint" in forms:
+        out["forms"]["adjoint"] = bench_adjoint(args, rt, W, np, torch)
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)

@@ -21,7 +21,9 @@ FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi",
 
 EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_batched",
            "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
-           "rt_workspace_size", "rt_last_error", "rt_version"]
+           "rt_workspace_size", "rt_timing", "rt_kernel_times", "rt_last_error", "rt_version"]
+KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace_bwd_kernel", 4: "adj_fwd_kernel",
+                5: "adj_rev_kernel"}
 
 
 class RtStar(C.Structure):
@@ -88,6 +90,9 @@ def lib():
         L.rt_flux_grad_workspace_size.restype = C.c_size_t
         L.rt_workspace_size.argtypes = [C.c_int32, C.c_int64]
         L.rt_workspace_size.restype = C.c_size_t
+        L.rt_timing.argtypes = [C.c_int32]
+        L.rt_kernel_times.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32]
+        L.rt_kernel_times.restype = C.c_int32
         L.rt_last_error.restype = C.c_char_p
         L.rt_version.restype = C.c_char_p
         for name in EXPORTS:
@@ -220,6 +225,19 @@ def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: 
 
 def version() -> str:
     return lib().rt_version().decode()
+
+
+def timing(on: bool):
+    """Start (clearing earlier records) or stop HIP-event timing of the persistent kernels."""
+    _check(lib().rt_timing(1 if on else 0), "rt_timing")
+
+
+def kernel_times(max_n: int = 1024):
+    """[(kernel name, milliseconds)] of the launches recorded since timing(True)."""
+    ms = (C.c_double * max_n)()
+    kd = (C.c_int32 * max_n)()
+    m = lib().rt_kernel_times(ms, kd, max_n)
+    return [(KERNEL_KINDS.get(kd[i], str(kd[i])), ms[i]) for i in range(m)]
 
 
 PARAMS = ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")  # differentiable star parameters

@@ -1,8 +1,9 @@
 // Static FP64 operation count of the tracer's arithmetic, obtained by running
-// the device templates (gradient of H, one DOPRI5 attempt) on the host with a
-// counting scalar.  Convention: +, -, x each 1; fused multiply-add 2; division,
-// reciprocal, square root, pow 1 each; sin and cos 1 each; negation, |.|,
-// max/min, comparisons 0.  Prints one JSON object keyed by the physics variant.
+// the device templates (gradient of H, one DOPRI5 attempt, the adjoint's stage
+// products in 7-tangent dual numbers) on the host with a counting scalar.
+// Convention: +, -, x each 1; fused multiply-add 2; division, reciprocal,
+// square root, pow 1 each; sin and cos 1 each; negation, |.|, max/min,
+// comparisons 0.  Prints one JSON object keyed by the physics variant.
 #include <cmath>
 #include <cstdio>
 
@@ -36,8 +37,7 @@ inline void sincos_t(FC a, FC* s, FC* c) { g_flops += 2; s->v = std::sin(a.v); c
 inline double value(FC a) { return a.v; }
 inline bool finite_value(FC a) { return std::isfinite(a.v); }
 
-#include "rt_device.hpp"
-#include "rt_integrator.hpp"
+#include "rt_adjoint.hpp"
 
 using namespace rtd;
 
@@ -70,8 +70,24 @@ int main() {
                 auto fn = [&](const FC* yy, FC* ff) { rhs(I, yy, ff, 1.0); };
                 dopri_attempt(fn, y, S, FC(0.1), ynew, 1e-8, 1e-12);
                 long long fstep = g_flops + 3;  // + step-size update (pow, x0.9, x h)
-                std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld}", first ? "" : ", ", pn[pl], dn[de],
-                            ob ? "oblique" : "aligned", frhs, fstep);
+                // adjoint: one stage vector-Jacobian product (dual-number Hessian-vector product
+                // with 6 parameter tangents) and the reverse sweep through the six stages of a step
+                typedef gdual<7, FC> D7F;
+                InstT<D7F> Ip = lift_inst<D7F>(I);
+                FC v[8], vy[8], vp[6], Ys[48], Kb[48], yb[8], pb[6];
+                for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); }
+                for (int d = 0; d < 48; ++d) { Ys[d] = y[d % 8]; Kb[d] = FC(0.01 * d); }
+                for (int q = 0; q < 6; ++q) pb[q] = FC(0.0);
+                g_flops = 0;
+                rhs_vjp<FC>(Ip, y, v, vy, vp);
+                long long fvjp = g_flops;
+                g_flops = 0;
+                stages_adjoint<FC>(Ip, Ys, FC(0.1), Kb, yb, pb);
+                long long fstages = g_flops;
+                std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld, \"vjp\": %lld, "
+                            "\"stages_adjoint\": %lld}",
+                            first ? "" : ", ", pn[pl], dn[de], ob ? "oblique" : "aligned", frhs, fstep, fvjp,
+                            fstages);
                 first = false;
             }
     std::printf("}\n");

@@ -301,9 +301,11 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         const rt_schedule sc = resolve_schedule(nullptr);
         const int grid = persistent_grid(sc, (const void*)adj_fwd_kernel, 256);
+        timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         hipLaunchKernelGGL(adj_fwd_kernel, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
                            W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.rctr, W.rlist, W.obs,
                            n_obs, sigma, W.facc);
+        timing_end(st);
         rc = check_launch("adj_fwd_kernel");
         if (rc) return rc;
         hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.facc, n_obs, 1.0 / (double)n, flux);
@@ -326,9 +328,11 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     const unsigned long long seal = adj_seal(n, n_obs, ckpt_every, max_ckpt);
     ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
     StarFixed fx = star_fixed(*star);
+    timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
     hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.ifin, W.nseg,
                        W.theta, W.ckpt, ckpt_every, W.rctr, W.rlist, W.obs, n_obs, sigma, gbar, W.replay, W.gacc,
                        grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    timing_end(st);
     rc = check_launch("adj_rev_kernel");
     if (rc) return rc;
     hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.gacc, 6, 1.0 / (double)n, grad);

@@ -237,13 +237,16 @@ RT_HD void make_adj_params(const double p[6], const StarFixed& fx, AdjParams& A)
     A.I14.oblique = 1;
 }
 
-// v^T df/dy (vy) and v^T df/dp (vp) at the state Y
-RT_HD_NOINLINE void rhs_vjp(const InstT<D7>& Ip, const double* Y, const double* v, double* vy, double* vp) {
-    D7 yd[8], fd[8];
+// v^T df/dy (vy) and v^T df/dp (vp) at the state Y (S = double; generic for the
+// host operation counter)
+template <class S = double>
+RT_HD_NOINLINE void rhs_vjp(const InstT<gdual<7, S>>& Ip, const S* Y, const S* v, S* vy, S* vp) {
+    typedef gdual<7, S> DS;
+    DS yd[8], fd[8];
     for (int i = 0; i < 4; ++i) {
-        yd[i] = D7(Y[i]);
+        yd[i] = DS(Y[i]);
         yd[i].d[0] = -v[4 + i];  // u = J^T v: u_x = -v_k
-        yd[4 + i] = D7(Y[4 + i]);
+        yd[4 + i] = DS(Y[4 + i]);
         yd[4 + i].d[0] = v[i];  // u_k = v_x
     }
     rhs(Ip, yd, fd, 1.0);
@@ -253,15 +256,16 @@ RT_HD_NOINLINE void rhs_vjp(const InstT<D7>& Ip, const double* Y, const double* 
         vy[4 + i] = fd[i].d[0];
     }
     for (int q = 0; q < 6; ++q) {
-        double a = 0.0;
-        for (int i = 0; i < 8; ++i) a += v[i] * fd[i].d[1 + q];
+        S a = v[0] * fd[0].d[1 + q];
+        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + q];
         vp[q] = a;
     }
 }
 
 // Adjoint of the six stages of a step: on entry Kb[8 i .. 8 i + 7] holds the
 // adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and pb.
-RT_HD void stages_adjoint(const InstT<D7>& Ip, const double* Ys, double h, double* Kb, double* yb, double* pb) {
+template <class S = double>
+RT_HD void stages_adjoint(const InstT<gdual<7, S>>& Ip, const S* Ys, S h, S* Kb, S* yb, S* pb) {
     using namespace dp5;
     const double A[6][5] = {{0, 0, 0, 0, 0},
                             {a21, 0, 0, 0, 0},
@@ -269,15 +273,15 @@ RT_HD void stages_adjoint(const InstT<D7>& Ip, const double* Ys, double h, doubl
                             {a41, a42, a43, 0, 0},
                             {a51, a52, a53, a54, 0},
                             {a61, a62, a63, a64, a65}};
-    double vy[8], vp[6];
+    S vy[8], vp[6];
     for (int i = 5; i >= 0; --i) {
-        rhs_vjp(Ip, Ys + i * 8, Kb + i * 8, vy, vp);
-        for (int q = 0; q < 6; ++q) pb[q] += vp[q];
-        for (int d = 0; d < 8; ++d) yb[d] += vy[d];
+        rhs_vjp<S>(Ip, Ys + i * 8, Kb + i * 8, vy, vp);
+        for (int q = 0; q < 6; ++q) pb[q] = pb[q] + vp[q];
+        for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
         for (int jj = 0; jj < i; ++jj) {
-            const double c = h * A[i][jj];
-            if (c != 0.0)
-                for (int d = 0; d < 8; ++d) Kb[jj * 8 + d] += c * vy[d];
+            if (A[i][jj] == 0.0) continue;
+            const S c = h * A[i][jj];
+            for (int d = 0; d < 8; ++d) Kb[jj * 8 + d] = Kb[jj * 8 + d] + c * vy[d];
         }
     }
 }
@@ -377,7 +381,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 }
                 // K7 = f(ynew)
                 double vy[8], vp[6];
-                rhs_vjp(A.Ip, ynew, K7b, vy, vp);
+                rhs_vjp<double>(A.Ip, ynew, K7b, vy, vp);
                 for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
                 for (int q = 0; q < 6; ++q) pb[q] += vp[q];
                 // ynew = y + h sum_i b_i K_i
@@ -400,7 +404,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     Kb[40 + d] = hn * b6 * yb[d];
                 }
             }
-            stages_adjoint(A.Ip, Ys, hn, Kb, yb, pb);
+            stages_adjoint<double>(A.Ip, Ys, hn, Kb, yb, pb);
         }
     }
     // seed: y_0(p) and w(p)

@@ -210,6 +210,66 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
 
 extern "C" const char* rt_last_error(void) { return g_err.c_str(); }
 
+// ---------------------------------------------------------------------------
+// kernel timing: a pool of event pairs, one per timed launch, read after the fact
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int TIMING_SLOTS = 1024;
+struct Timing {
+    bool on = false;
+    int used = 0;
+    int open = -1;  // slot whose start event is recorded and stop is pending
+    int kinds[TIMING_SLOTS];
+    hipEvent_t ev[TIMING_SLOTS][2];
+    bool created = false;
+};
+Timing g_timing;
+}  // namespace
+
+void rtd::timing_begin(hipStream_t st, int kind) {
+    Timing& T = g_timing;
+    if (!T.on || T.used >= TIMING_SLOTS) return;
+    const int k = T.used;
+    if (hipEventRecord(T.ev[k][0], st) != hipSuccess) return;
+    T.kinds[k] = kind;
+    T.open = k;
+}
+
+void rtd::timing_end(hipStream_t st) {
+    Timing& T = g_timing;
+    if (!T.on || T.open < 0) return;
+    if (hipEventRecord(T.ev[T.open][1], st) == hipSuccess) T.used = T.open + 1;
+    T.open = -1;
+}
+
+extern "C" int rt_timing(int32_t on) {
+    clear_error();
+    Timing& T = g_timing;
+    if (on && !T.created) {
+        for (int k = 0; k < TIMING_SLOTS; ++k)
+            for (int e = 0; e < 2; ++e)
+                if (hipEventCreate(&T.ev[k][e]) != hipSuccess) return fail(RT_EHIP, "rt_timing: hipEventCreate failed");
+        T.created = true;
+    }
+    T.on = on != 0;
+    T.open = -1;
+    if (T.on) T.used = 0;  // stopping keeps the records for rt_kernel_times
+    return RT_OK;
+}
+
+extern "C" int32_t rt_kernel_times(double* ms, int32_t* kind, int32_t max) {
+    Timing& T = g_timing;
+    int m = T.used < max ? T.used : max;
+    for (int k = 0; k < m; ++k) {
+        float t = -1.0f;
+        if (hipEventSynchronize(T.ev[k][1]) != hipSuccess || hipEventElapsedTime(&t, T.ev[k][0], T.ev[k][1]) != hipSuccess)
+            t = -1.0f;
+        if (ms) ms[k] = (double)t;
+        if (kind) kind[k] = T.kinds[k];
+    }
+    return m;
+}
+
 extern "C" const char* rt_version(void) {
     return "rt-gfx950 FP64 DOPRI5 ray tracer (hipcc " __VERSION__ ")";
 }

@@ -239,8 +239,10 @@ static int launch_bwd_block(const rt_schedule& sc, const InstT<double>& I, const
                             const FwdWs& W, const double* y0s, int32_t K, double* ev, int32_t* nev, double* fin,
                             int32_t* ifin, hipStream_t st) {
     int grid = persistent_grid(sc, (const void*)trace_bwd_kernel<BLOCK, MINW>, BLOCK);
+    timing_begin(st, RT_KERNEL_TRACE_BACKWARD);
     hipLaunchKernelGGL((trace_bwd_kernel<BLOCK, MINW>), dim3(grid), dim3(BLOCK), 0, st, I, T, D, n, W.ctr, W.list,
                        W.h0, W.k1, y0s, K, ev, nev, fin, ifin, sc.refill_min);
+    timing_end(st);
     return check_launch("trace_bwd_kernel");
 }
 

@@ -121,6 +121,11 @@ int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t 
                const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, int32_t* keys,
                hipStream_t st);
 
+// optional HIP-event timing of the persistent kernels (rt_timing / rt_kernel_times):
+// record a start/stop pair on the launch stream around one kernel launch
+void timing_begin(hipStream_t st, int kind);
+void timing_end(hipStream_t st);
+
 // small utility kernels (defined per translation unit)
 static __global__ void zero_ctr_kernel(WorkCtr* c) {
     if (threadIdx.x == 0) { c->head = 0ull; c->len = 0ull; c->iters = 0ull; }

@@ -383,8 +383,10 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
                             const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                             const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
     int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED>, BLOCK);
+    timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
     hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED>), dim3(grid), dim3(BLOCK), 0, st, I, itab, inst_of,
                        any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min);
+    timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;
     hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, itab, inst_of, W.list, W.ctr,

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "rt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(rt_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|size_t|const char\*)\s+(rt_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -36,6 +36,8 @@ def test_workspace_sizes_and_version():
     L = rt.lib()
     assert L.rt_workspace_size(rt.OP_TRACE_FORWARD, 1000) >= 76 * 1000
     assert L.rt_workspace_size(rt.OP_BIN, 1000) >= 4 * 1000
+    assert L.rt_workspace_size(rt.OP_FLUX_GRAD, 1000) == L.rt_flux_grad_workspace_size(1000, 64, 64, 64) > 0
+    assert L.rt_flux_grad_workspace_size(1000, 65, 64, 64) == 0
     assert b"gfx950" in L.rt_version()
 
 
