@@ -158,6 +158,45 @@ def bench_batched(args, rt, W, np, torch):
                 per_instance_ms=ms_loop, speedup_vs_per_instance=ms_loop / ms, tune_ms=times)
 
 
+def bench_backward(args, rt, W, np, torch):
+    """Backward image: 1024^2 pixels at 1e5 km traced inward through the magnetar-like star,
+    recording up to 8 production events per ray."""
+    cfg = W.CFG3
+    star, tol, image, K = cfg["star"], cfg["tol"], cfg["image"], cfg["K"]
+    n = image["nx"] * image["ny"]
+    print(f"bench: backward {cfg['name']} n={n}", file=sys.stderr, flush=True)
+    ws = rt.workspace(rt.OP_TRACE_BACKWARD, n)
+    rt.rt_trace_backward(star, tol, image, K, ws=ws)
+    torch.cuda.synchronize()
+    reps = max(2, min(args.steps, 3))
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rt.timing(True)
+    e0.record(stream)
+    for _ in range(reps):
+        ev, nev, fin, ifin = rt.rt_trace_backward(star, tol, image, K, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rt.timing(False)
+    ms_call = e0.elapsed_time(e1) / reps
+    kt = [ms for name, ms in rt.kernel_times() if name == "trace_bwd_kernel"]
+    kernel_ms = float(np.mean(kt))
+    inf = ifin.cpu().numpy().astype(np.int64)
+    nv = nev.cpu().numpy().astype(np.int64)
+    acc, rej = float(inf[0].sum()), float(inf[1].sum())
+    ft = flop_table()[variant_key(star)]
+    # per attempt one DOPRI5 attempt; per accepted step four probes of G on the continuous
+    # extension; per recorded event 60 bisection probes
+    flops = (acc + rej) * ft["attempt"] + acc * 4 * ft["event_probe"] + float(nv.sum()) * 60 * ft["event_probe"]
+    tf = flops / (kernel_ms * 1e-3) / 1e12
+    st = {str(k): int(v) for k, v in zip(*np.unique(inf[2], return_counts=True))}
+    return dict(workload=cfg["name"], pixels=n, events=int(nv.sum()), rays_with_events=int((nv > 0).sum()),
+                statuses=st, accepted_steps=acc, rejected_steps=rej, ms_per_image=ms_call, kernel_ms=kernel_ms,
+                rays_per_s=n / (ms_call * 1e-3), ray_steps_per_s=acc / (ms_call * 1e-3), kernel_tflops=tf,
+                kernel_frac=tf / FP64_VECTOR_PEAK_TFLOPS, flop_per_attempt=ft["attempt"],
+                flop_per_event_probe=ft["event_probe"])
+
+
 def bench_adjoint(args, rt, W, np, torch):
     """Smoothed flux at 32 observers and its gradient with respect to the six star parameters
     (config-1 star, 1e6 rays, checkpoint every 64 accepted steps): forward phase (trace with
@@ -215,8 +254,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched,adjoint",
-                    help="comma list of forms to time beside plain (the headline value): batched, adjoint")
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward",
+                    help="comma list of forms to time beside plain (the headline value): batched, adjoint, "
+                         "backward")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the plain form's schedule too (default: the library's default schedule)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
@@ -332,6 +372,8 @@ def main():
         out["forms"]["batched"] = bench_batched(args, rt, W, np, torch)
     if "adjoint" in forms:
         out["forms"]["adjoint"] = bench_adjoint(args, rt, W, np, torch)
+    if "backward" in forms:
+        out["forms"]["backward"] = bench_backward(args, rt, W, np, torch)
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)

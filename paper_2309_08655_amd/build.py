@@ -12,8 +12,14 @@ LIB = os.path.join(HERE, "librt.so")
 SOURCES = ["rt_api.hip", "rt_forward.hip", "rt_backward.hip", "rt_batched.hip", "rt_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# Per-file additions.  The adjoint's forward pass and its recompute inline the same step
+# code into two kernels; without floating-point contraction every operation is a plain
+# IEEE operation, so both produce the same bits and the recompute replays the forward
+# pass's accept/reject decisions exactly.
+FILE_FLAGS = {"rt_adjoint.hip": ["-ffp-contract=off"]}
+
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
     # never emit packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,12 +47,26 @@ def build_flop_table(verbose: bool = False) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    import concurrent.futures as cf
+    import tempfile
+    inc = os.path.join(HERE, "..", "include")
+    with tempfile.TemporaryDirectory(prefix="rt_build_") as tmpdir:
+        cmds, objs = [], []
+        for src in SOURCES:
+            obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
+            objs.append(obj)
+            cmds.append([HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), "-I", inc, "-c", os.path.join(CSRC, src),
+                         "-o", obj])
+        with cf.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            for cmd in cmds:
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+            list(ex.map(lambda c: subprocess.run(c, check=True), cmds))
+        tmp = LIB + ".tmp"
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     build_flop_table(verbose)
     return LIB

@@ -84,10 +84,18 @@ int main() {
                 g_flops = 0;
                 stages_adjoint<FC>(Ip, Ys, FC(0.1), Kb, yb, pb);
                 long long fstages = g_flops;
+                // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension
+                FC yt[8];
+                for (int d = 0; d < 8; ++d) S.K[6][d] = S.K[0][d];
+                g_flops = 0;
+                dense_at(y, ynew, S, FC(0.1), FC(0.5), yt, 0, 8);
+                FC G = g_kk(I, yt) + I.ma2;
+                (void)G;
+                long long fprobe = g_flops;
                 std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld, \"vjp\": %lld, "
-                            "\"stages_adjoint\": %lld}",
+                            "\"stages_adjoint\": %lld, \"event_probe\": %lld}",
                             first ? "" : ", ", pn[pl], dn[de], ob ? "oblique" : "aligned", frhs, fstep, fvjp,
-                            fstages);
+                            fstages, fprobe);
                 first = false;
             }
     std::printf("}\n");

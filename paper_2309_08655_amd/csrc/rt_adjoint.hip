@@ -20,8 +20,10 @@
 //   gradient in dual numbers, and v^T df/dp from 6 more tangents.
 // Memory: (y, h, facmax) is checkpointed every C accepted steps; the reverse
 // sweep recomputes each segment from its checkpoint into a per-lane replay
-// buffer and walks it backwards.  Forward and recompute run the same
-// non-inlined step function, so the recomputed step sequence is bit-identical.
+// buffer and walks it backwards.  This file is compiled without floating-point
+// contraction, so the forward pass and the recompute, which inline the same step
+// code, produce the same bits; a ray whose recompute does not end exactly on its
+// next checkpoint gets a NaN gradient share.
 // The per-ray pieces live in rt_adjoint.hpp (also compiled for the host in tests);
 // this file holds the workspace layout, the two persistent kernels and the entry.
 #include "rt_adjoint.hpp"
@@ -237,8 +239,13 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *facmax = ckpt[((int64_t)s * 10 + 9) * n + j];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        missing += (unsigned long long)adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], C, load, rb, obs,
-                                                       gbar, n_obs, sigma, pb);
+        const int miss = adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], C, load, rb, obs, gbar, n_obs,
+                                         sigma, pb);
+        if (miss) {
+            // the recompute did not reproduce the forward pass: no gradient for this ray
+            missing += (unsigned long long)miss;
+            for (int q = 0; q < 6; ++q) pb[q] = __builtin_nan("");
+        }
         for (int q = 0; q < 6; ++q) pacc[q] += pb[q];
         if (grad_rays)
             for (int q = 0; q < 6; ++q) grad_rays[j * 6 + q] = pb[q] * inv_n;

@@ -30,17 +30,19 @@ typedef gdual<6> D6;
 typedef gdual<14> D14;
 
 // ----------------------------------------------------------------------------
-// the step shared by the forward pass and the recompute: compiled once, so the
-// recomputed accept/reject decisions and step sizes are bit-identical
+// the step shared by the forward pass and the recompute.  The library compiles this
+// file without floating-point contraction, so every copy of it computes the same
+// bits and the recompute reproduces the forward pass's decisions and step sizes
+// (the reverse sweep checks this at every checkpoint).
 // ----------------------------------------------------------------------------
-RT_HD_NOINLINE void adj_rhs(InstT<double> I, const double* y, double* f) { rhs(I, y, f, 1.0); }
+RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) { rhs(I, y, f, 1.0); }
 
 // One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
 // the last = f(ynew)), ynew and, if Ys != nullptr, the stage states Ys[0..47]
 // (Ys[0..7] = y).  Applies the step-size controller to *h and *facmax and returns
 // 1 if the step is accepted.
-RT_HD_NOINLINE int adj_attempt(InstT<double> I, double rtol, double atol, const double* y, double* K, double* ynew,
-                               double* h, double* facmax, double* Ys) {
+RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
+                      double* h, double* facmax, double* Ys) {
     using namespace dp5;
     const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
                             {a31, a32, 0, 0, 0, 0},
@@ -52,9 +54,12 @@ RT_HD_NOINLINE int adj_attempt(InstT<double> I, double rtol, double atol, const 
     double tmp[8];
     if (Ys)
         for (int d = 0; d < 8; ++d) Ys[d] = y[d];
+#pragma unroll
     for (int s = 0; s < 6; ++s) {
+#pragma unroll
         for (int d = 0; d < 8; ++d) {
             double acc = 0.0;
+#pragma unroll
             for (int q = 0; q <= s; ++q) acc += A[s][q] * K[q * 8 + d];
             tmp[d] = y[d] + hh * acc;
         }
@@ -68,8 +73,10 @@ RT_HD_NOINLINE int adj_attempt(InstT<double> I, double rtol, double atol, const 
     }
     const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
     double acc = 0.0;
+#pragma unroll
     for (int d = 0; d < 8; ++d) {
         double e = 0.0;
+#pragma unroll
         for (int q = 0; q < 7; ++q) e += E[q] * K[q * 8 + d];
         e *= hh;
         const double sc = atol + rtol * fmax(fabs(y[d]), fabs(ynew[d]));
@@ -289,7 +296,7 @@ RT_HD void stages_adjoint(const InstT<gdual<7, S>>& Ip, const S* Ys, S h, S* Kb,
 // Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing at
 // theta on the last step).  load(s, y, &h, &facmax) reads checkpoint s; rb(idx, d)
 // is the replay buffer (C steps x 9 values).  Adds d(w G(y_f))/dp to pb.  Returns the
-// number of steps the recompute could not reproduce (0 when all is well).
+// number of steps or checkpoints the recompute could not reproduce (0 when all is well).
 template <class Load, class Replay>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
                           int nseg, double th, int C, Load&& load, Replay&& rb, const double* obs, const double* gbar,
@@ -321,6 +328,14 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             }
         }
         missing += count - stored;
+        if (stored == count && s + 1 < nseg) {
+            // the recomputed segment must end exactly on the next checkpoint
+            double yc[8], hc, fc;
+            load(s + 1, yc, &hc, &fc);
+            bool same = (hc == h) && (fc == facmax);
+            for (int d = 0; d < 8; ++d) same = same && (yc[d] == y[d]);
+            if (!same) ++missing;
+        }
         // walk the segment backwards
         for (int idx = stored - 1; idx >= 0; --idx) {
             double yn[8], Ys[48], Kb[48];

@@ -81,16 +81,16 @@ RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], doub
 }
 
 // Continuous extension at theta of components [c0, c1) (accepted step y -> ynew).
-RT_HD void dense_at(const double y[8], const double ynew[8], const Stages& S, double h,
-                                         double th, double out[8], int c0, int c1) {
+template <class T>
+RT_HD void dense_at(const T y[8], const T ynew[8], const StagesT<T>& S, T h, T th, T out[8], int c0, int c1) {
     using namespace dp5;
-    double om = 1.0 - th;
+    T om = 1.0 - th;
     for (int i = c0; i < c1; ++i) {
-        double ydiff = ynew[i] - y[i];
-        double r3 = h * S.K[0][i] - ydiff;
-        double r4 = ydiff - h * S.K[6][i] - r3;
-        double r5 = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
-                         d7 * S.K[6][i]);
+        T ydiff = ynew[i] - y[i];
+        T r3 = h * S.K[0][i] - ydiff;
+        T r4 = ydiff - h * S.K[6][i] - r3;
+        T r5 = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
+                    d7 * S.K[6][i]);
         out[i] = y[i] + th * (ydiff + om * (r3 + th * (r4 + om * r5)));
     }
 }
