@@ -176,20 +176,14 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
     bool finite_ok = true;
     for (int d = 0; d < 8; ++d) finite_ok = finite_ok && __builtin_isfinite(ynew[d]);
     if (finite_ok && rnew >= tol.rmax) {
-        // r = r_max on the continuous extension (60 bisections)
+        // r = r_max on the continuous extension
         Stages S;
         for (int s = 0; s < 7; ++s)
             for (int d = 0; d < 8; ++d) S.K[s][d] = R.K[s * 8 + d];
-        double lo = 0.0, hi = 1.0;
-        for (int it = 0; it < 60; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            dense_at(R.y, ynew, S, hused, mid, yf, 0, 3);
-            const double rm = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
-            if (rm >= tol.rmax) hi = mid; else lo = mid;
-        }
-        dense_at(R.y, ynew, S, hused, hi, yf, 0, 8);
-        *theta = hi;
-        R.lam += hi * hused;
+        const double th = locate_crossing(R.y, ynew, S, hused, tol.rmax);
+        dense_at(R.y, ynew, S, hused, th, yf, 0, 8);
+        *theta = th;
+        R.lam += th * hused;
         return ST_ESCAPED;
     }
     for (int d = 0; d < 8; ++d) {

@@ -183,19 +183,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
             bool finite_ok = true;
             for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(ynew[d]);
             if (finite_ok && rnew >= tol.rmax) {
-                // locate r(theta) = r_max on the continuous extension (60 bisections)
-                double lo = 0.0, hi = 1.0;
+                // locate r(theta) = r_max on the continuous extension
+                const double th = locate_crossing(y, ynew, S, h, tol.rmax);
                 double yt[8];
-                for (int it = 0; it < 60; ++it) {
-                    double mid = 0.5 * (lo + hi);
-                    dense_at(y, ynew, S, h, mid, yt, 0, 3);
-                    double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
-                    if (rm >= tol.rmax) hi = mid; else lo = mid;
-                }
-                dense_at(y, ynew, S, h, hi, yt, 0, 8);
+                dense_at(y, ynew, S, h, th, yt, 0, 8);
                 for (int d = 0; d < 8; ++d) y[d] = yt[d];
                 status = ST_ESCAPED;
-                lam_out = lam + hi * h;
+                lam_out = lam + th * h;
             } else {
                 if (I.oblique && finite_ok && rnew > I.R) axis_ref_advance(I, ref, ynew[3]);
                 for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }

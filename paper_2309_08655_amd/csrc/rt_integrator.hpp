@@ -95,6 +95,58 @@ RT_HD void dense_at(const T y[8], const T ynew[8], const StagesT<T>& S, T h, T t
     }
 }
 
+// Location theta in (0, 1] of the crossing |x(theta)| = rmax on the continuous extension
+// of an accepted step that starts inside (|y| < rmax) and ends outside (|ynew| >= rmax):
+// Newton's method on phi(theta) = x.x - rmax^2 from the linear interpolation of r,
+// safeguarded by the bracket [lo, hi] (a step leaving it bisects instead).  Converges
+// to the root to about an ulp in a few iterations, where plain bisection to the same
+// precision takes 60 evaluations.
+RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stages& S, double h, double rmax) {
+    using namespace dp5;
+    double a[3], b[3], c[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = ynew[i] - y[i];
+        b[i] = h * S.K[0][i] - a[i];
+        c[i] = a[i] - h * S.K[6][i] - b[i];
+        d[i] = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
+                    d7 * S.K[6][i]);
+    }
+    const double r0 = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    const double r1 = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+    const double R2 = rmax * rmax;
+    double lo = 0.0, hi = 1.0;
+    double th = (r1 > r0) ? (rmax - r0) / (r1 - r0) : 1.0;
+    if (!(th > 0.0 && th <= 1.0)) th = 0.5;
+    for (int it = 0; it < 16; ++it) {
+        const double om = 1.0 - th;
+        double x2 = 0.0, xdx = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            const double q = b[i] + th * (c[i] + om * d[i]);
+            const double p = a[i] + om * q;
+            const double xi = y[i] + th * p;
+            const double dxi = p + th * (-q + om * (c[i] + (1.0 - 2.0 * th) * d[i]));
+            x2 += xi * xi;
+            xdx += xi * dxi;
+        }
+        const double phi = x2 - R2;
+        if (phi == 0.0) break;  // th is the root
+        if (phi > 0.0) hi = th; else lo = th;
+        const double step = phi / (2.0 * xdx);
+        double tn = th - step;
+        if (tn > lo && tn < hi) {
+            if (fabs(step) <= 4.0e-16 * th) {  // converged to about an ulp
+                th = tn;
+                break;
+            }
+        } else {
+            if (hi - lo <= 4.0e-16 * hi) break;  // the bracket is down to an ulp
+            tn = 0.5 * (lo + hi);
+        }
+        th = tn;
+    }
+    return th;
+}
+
 // Step-size update after an attempt (HNW I-controller, order 5):
 // accepted: h *= min(facmax, max(0.2, 0.9 err^-1/5)) (err = 0 -> facmax);
 // rejected: h *= max(0.2, 0.9 err^-1/5) and facmax = 1 for the next accepted step.

@@ -39,8 +39,9 @@ double host_attempt(const double* c, const int* e, const double* y, double h, do
 
 extern "C" {
 // host run of the tracing loop of the persistent kernel for one ray (same decisions)
+// locate = 0: the kernels' Newton locator of the r = rmax crossing; 1: 60 bisections
 int host_trace(const double* c, const int* e, const double* y0, double rtol, double atol, double rmax,
-               long long max_steps, double* yf, int* nacc_out, int* nrej_out) {
+               long long max_steps, double* yf, int* nacc_out, int* nrej_out, int locate) {
     InstT<double> I = inst_from(c, e);
     auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
     Stages S;
@@ -62,14 +63,20 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
             double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
             if (rnew <= I.R) { status = 2; for (int d = 0; d < 8; ++d) yf[d] = ynew[d]; }
             else if (rnew >= rmax) {
-                double lo = 0.0, hi = 1.0, yt[8];
-                for (int it = 0; it < 60; ++it) {
-                    double mid = 0.5 * (lo + hi);
-                    dense_at(y, ynew, S, h, mid, yt, 0, 3);
-                    double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
-                    if (rm >= rmax) hi = mid; else lo = mid;
+                double th;
+                if (locate == 0) {
+                    th = locate_crossing(y, ynew, S, h, rmax);
+                } else {
+                    double lo = 0.0, hi = 1.0, yt[8];
+                    for (int it = 0; it < 60; ++it) {
+                        double mid = 0.5 * (lo + hi);
+                        dense_at(y, ynew, S, h, mid, yt, 0, 3);
+                        double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
+                        if (rm >= rmax) hi = mid; else lo = mid;
+                    }
+                    th = hi;
                 }
-                dense_at(y, ynew, S, h, hi, yf, 0, 8);
+                dense_at(y, ynew, S, h, th, yf, 0, 8);
                 status = 1;
             } else {
                 lam += h;

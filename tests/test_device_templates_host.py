@@ -29,7 +29,7 @@ def host(tmp_path_factory):
     dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
     L.host_grad_h.argtypes = [dp, ip, dp, dp]
     L.host_trace.argtypes = [dp, ip, dp, C.c_double, C.c_double, C.c_double, C.c_longlong, dp,
-                             C.POINTER(C.c_int), C.POINTER(C.c_int)]
+                             C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]
     return L
 
 
@@ -86,7 +86,7 @@ def test_host_tracing_loop_matches_oracle(orc, host, cfg):
         yf = np.zeros(8)
         na, nr = C.c_int(), C.c_int()
         ifin[2, i] = host.host_trace(_p(cc), _p(e, C.c_int), _p(y0), t["rtol"], t["atol"], t["r_max_km"],
-                                     t["max_steps"], _p(yf), C.byref(na), C.byref(nr))
+                                     t["max_steps"], _p(yf), C.byref(na), C.byref(nr), 0)
         ifin[0, i], ifin[1, i] = na.value, nr.value
         fin[:8, i] = yf
         r = np.linalg.norm(yf[:3])
@@ -102,3 +102,33 @@ def test_host_tracing_loop_matches_oracle(orc, host, cfg):
     out = assert_trace_parity(fin, ifin, fin_o, ifin_o, sd, ch)
     print(out)
     assert out["well"] > 0.15 * out["escaped"]
+
+
+@pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])
+def test_newton_crossing_locator_matches_bisection(orc, host, cfg):
+    """The kernels locate r = r_max on the last step's continuous extension by a
+    safeguarded Newton iteration; the definition is 60 bisections.  Same step sequence,
+    so the final states must agree to roundoff (1e-13 relative, r = r_max to 1e-15)."""
+    s, t = cfg["star"], cfg["tol"]
+    cc, e = consts(orc, s)
+    rays, st = orc.sample(s, 0, 300)
+    worst, nesc = 0.0, 0
+    for i in range(rays.shape[1]):
+        if st[i] != 0:
+            continue
+        y0 = np.ascontiguousarray(rays[:8, i])
+        out = []
+        for mode in (0, 1):
+            yf = np.zeros(8)
+            na, nr = C.c_int(), C.c_int()
+            stt = host.host_trace(_p(cc), _p(e, C.c_int), _p(y0), t["rtol"], t["atol"], t["r_max_km"],
+                                  t["max_steps"], _p(yf), C.byref(na), C.byref(nr), mode)
+            out.append((stt, na.value, nr.value, yf))
+        assert out[0][:3] == out[1][:3]
+        if out[0][0] == W.STATUS_ESCAPED:
+            nesc += 1
+            a, b = out[0][3], out[1][3]
+            assert abs(np.linalg.norm(a[:3]) / t["r_max_km"] - 1.0) < 1e-15
+            worst = max(worst, float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300 + np.abs(b).max() * 1e-3))))
+    assert nesc > 200
+    assert worst < 1e-13, worst
