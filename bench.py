@@ -30,7 +30,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, AMD published (256 CU x 128 FLOP/clk x
 # HBM traffic of the tracing kernel, measured with hardware counters (FETCH_SIZE and
 # WRITE_SIZE per dispatch, each scaled by what it reads for a copy of known size) on this
 # workload; valid only while the kernel's sources are the ones it was measured on
-HBM_SUMMARY = os.path.join(ROOT, "profiles", "trace_fwd_kernel_forward-full-1e6_hbm.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_fwd_kernel_forward-full-1e6_counters.md")
 TRACE_SOURCES = ["rt_forward.hip", "rt_common.hpp", "rt_device.hpp", "rt_integrator.hpp", "rt_seed.hpp"]
 
 
@@ -43,20 +43,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def hbm_traffic(n):
-    """Counter-measured HBM bytes per launch of the tracing kernel, or None when there is no
-    measurement for these sources and this ray count."""
-    if not os.path.exists(HBM_SUMMARY):
-        return None
+def counter_values(n):
+    """Counter-measured values per launch of the tracing kernel (HBM bytes, hardware FP64
+    flops), or {} when there is no measurement for these sources and this ray count."""
+    if not os.path.exists(COUNTER_SUMMARY):
+        return {}
     vals = {}
-    with open(HBM_SUMMARY) as f:
+    with open(COUNTER_SUMMARY) as f:
         for line in f:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != kernel_source_hash() or int(vals.get("rays", -1)) != n:
-        return None
-    return float(vals["hbm_bytes_per_launch"])
+        return {}
+    return {k: float(v) for k, v in vals.items() if k.endswith("_per_launch")}
 
 
 def variant_key(star):
@@ -351,10 +351,16 @@ def main():
     # attempted step (the FSAL derivative and starting step come from the init kernel)
     flops = (acc + rej) * ft["attempt"]
     achieved_tflops = flops / (trace_ms * 1e-3) / 1e12
+    cv = counter_values(n)
     roofline = dict(bound="alu", achieved=achieved_tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, traffic=hbm_traffic(n),
+                    frac=achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, traffic=cv.get("hbm_bytes_per_launch"),
                     kernel="trace_fwd_kernel", kernel_ms=trace_ms, flop_per_attempt=ft["attempt"],
                     attempted_steps=acc + rej, flop_per_launch=flops)
+    if "hw_fp64_flops_per_launch" in cv:
+        # the hardware's own FP64 operation count (every lane of every issued FP64
+        # instruction: library expansions, Newton refinements, idle lanes included)
+        hw = cv["hw_fp64_flops_per_launch"] / (trace_ms * 1e-3) / 1e12
+        roofline.update(hw_fp64_tflops=hw, hw_fp64_frac=hw / FP64_VECTOR_PEAK_TFLOPS)
     out = dict(metric="ray-steps/s and rays/s at rtol 1e-8 (FP64), plain vs batched vs adjoint",
                value=steps_per_s, unit="ray-steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
