@@ -150,12 +150,26 @@ RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stag
 // Step-size update after an attempt (HNW I-controller, order 5):
 // accepted: h *= min(facmax, max(0.2, 0.9 err^-1/5)) (err = 0 -> facmax);
 // rejected: h *= max(0.2, 0.9 err^-1/5) and facmax = 1 for the next accepted step.
+// err^(-1/5) for the controller: a single-precision estimate refined by two Newton steps
+// in double on u = x^5 err = 1 (x <- x (1 - (u - 1)/(5 u))), accurate to a few ulp.  err
+// is clamped to [1e-30, 1e30], outside which the factor saturates at facmax or 0.2 anyway.
+RT_HD double inv_fifth_root(double err) {
+    const double e = fmin(fmax(err, 1e-30), 1e30);
+    double x = (double)exp2f(-0.2f * log2f((float)e));
+    for (int it = 0; it < 2; ++it) {
+        const double x2 = x * x;
+        const double u = x2 * x2 * x * e;
+        x = x - x * (u - 1.0) / (5.0 * u);
+    }
+    return x;
+}
+
 RT_HD double step_factor(double err, double facmax, bool accepted) {
     if (accepted) {
         if (err == 0.0) return facmax;
-        return fmin(facmax, fmax(0.2, 0.9 * pow(err, -0.2)));
+        return fmin(facmax, fmax(0.2, 0.9 * inv_fifth_root(err)));
     }
-    return fmax(0.2, 0.9 * pow(err, -0.2));
+    return fmax(0.2, 0.9 * inv_fifth_root(err));
 }
 
 // Starting step (HNW Sec. II.4, order 5), norm scale atol + rtol |y0|.

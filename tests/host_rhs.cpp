@@ -91,3 +91,9 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
     return status;
 }
 }
+
+extern "C" {
+// the controller's err^(-1/5) and step factor
+double host_inv_fifth_root(double err) { return inv_fifth_root(err); }
+double host_step_factor(double err, double facmax, int accepted) { return step_factor(err, facmax, accepted != 0); }
+}
