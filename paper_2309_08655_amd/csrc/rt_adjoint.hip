@@ -20,10 +20,10 @@
 //   gradient in dual numbers, and v^T df/dp from 6 more tangents.
 // Memory: (y, h, facmax) is checkpointed every C accepted steps; the reverse
 // sweep recomputes each segment from its checkpoint into a per-lane replay
-// buffer and walks it backwards.  This file is compiled without floating-point
-// contraction, so the forward pass and the recompute, which inline the same step
-// code, produce the same bits; a ray whose recompute does not end exactly on its
-// next checkpoint gets a NaN gradient share.
+// buffer and walks it backwards.  This file is compiled with multiply-add fusion
+// decided per source expression only (-ffp-contract=on), so the forward pass and the
+// recompute, which inline the same step code, produce the same bits; a ray whose
+// recompute does not end exactly on its next checkpoint gets a NaN gradient share.
 // The per-ray pieces live in rt_adjoint.hpp (also compiled for the host in tests);
 // this file holds the workspace layout, the two persistent kernels and the entry.
 #include "rt_adjoint.hpp"

@@ -31,9 +31,9 @@ typedef gdual<14> D14;
 
 // ----------------------------------------------------------------------------
 // the step shared by the forward pass and the recompute.  The library compiles this
-// file without floating-point contraction, so every copy of it computes the same
-// bits and the recompute reproduces the forward pass's decisions and step sizes
-// (the reverse sweep checks this at every checkpoint).
+// file with multiply-add fusion decided per source expression only, so every copy of
+// it computes the same bits and the recompute reproduces the forward pass's decisions
+// and step sizes (the reverse sweep checks this at every checkpoint).
 // ----------------------------------------------------------------------------
 RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) { rhs(I, y, f, 1.0); }
 

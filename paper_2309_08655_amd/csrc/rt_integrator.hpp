@@ -44,34 +44,39 @@ RT_HD bool finite_value(double x) { return __builtin_isfinite(x); }
 template <class T, class RHS>
 RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], double rtol, double atol) {
     using namespace dp5;
+    // h folded into the tableau once per attempt: each stage state is then an FMA chain
+    const T h21 = h * a21, h31 = h * a31, h32 = h * a32, h41 = h * a41, h42 = h * a42, h43 = h * a43;
+    const T h51 = h * a51, h52 = h * a52, h53 = h * a53, h54 = h * a54;
+    const T h61 = h * a61, h62 = h * a62, h63 = h * a63, h64 = h * a64, h65 = h * a65;
+    const T hb1 = h * b1, hb3 = h * b3, hb4 = h * b4, hb5 = h * b5, hb6 = h * b6;
     T tmp[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a21 * S.K[0][i]);
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h21 * S.K[0][i];
     f(tmp, S.K[1]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a31 * S.K[0][i] + a32 * S.K[1][i]);
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h31 * S.K[0][i] + h32 * S.K[1][i];
     f(tmp, S.K[2]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h * (a41 * S.K[0][i] + a42 * S.K[1][i] + a43 * S.K[2][i]);
+    for (int i = 0; i < 8; ++i) tmp[i] = y[i] + h41 * S.K[0][i] + h42 * S.K[1][i] + h43 * S.K[2][i];
     f(tmp, S.K[3]);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-        tmp[i] = y[i] + h * (a51 * S.K[0][i] + a52 * S.K[1][i] + a53 * S.K[2][i] + a54 * S.K[3][i]);
+        tmp[i] = y[i] + h51 * S.K[0][i] + h52 * S.K[1][i] + h53 * S.K[2][i] + h54 * S.K[3][i];
     f(tmp, S.K[4]);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-        tmp[i] = y[i] + h * (a61 * S.K[0][i] + a62 * S.K[1][i] + a63 * S.K[2][i] + a64 * S.K[3][i] +
-                             a65 * S.K[4][i]);
+        tmp[i] = y[i] + h61 * S.K[0][i] + h62 * S.K[1][i] + h63 * S.K[2][i] + h64 * S.K[3][i] + h65 * S.K[4][i];
     f(tmp, S.K[5]);
 #pragma unroll
     for (int i = 0; i < 8; ++i)
-        ynew[i] = y[i] + h * (b1 * S.K[0][i] + b3 * S.K[2][i] + b4 * S.K[3][i] + b5 * S.K[4][i] + b6 * S.K[5][i]);
+        ynew[i] = y[i] + hb1 * S.K[0][i] + hb3 * S.K[2][i] + hb4 * S.K[3][i] + hb5 * S.K[4][i] + hb6 * S.K[5][i];
     f(ynew, S.K[6]);
+    const T he1 = h * e1, he3 = h * e3, he4 = h * e4, he5 = h * e5, he6 = h * e6, he7 = h * e7;
     T acc = T(0.0);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        T e = h * (e1 * S.K[0][i] + e3 * S.K[2][i] + e4 * S.K[3][i] + e5 * S.K[4][i] + e6 * S.K[5][i] +
-                   e7 * S.K[6][i]);
+        T e = he1 * S.K[0][i] + he3 * S.K[2][i] + he4 * S.K[3][i] + he5 * S.K[4][i] + he6 * S.K[5][i] +
+              he7 * S.K[6][i];
         T sc = atol + rtol * fmax(fabs(y[i]), fabs(ynew[i]));
         T qq = e * frcp(sc);
         acc = acc + qq * qq;
