@@ -71,18 +71,17 @@ int main() {
                 dopri_attempt(fn, y, S, FC(0.1), ynew, 1e-8, 1e-12);
                 long long fstep = g_flops + 3;  // + step-size update (pow, x0.9, x h)
                 // adjoint: one stage vector-Jacobian product (dual-number Hessian-vector product
-                // with 6 parameter tangents) and the reverse sweep through the six stages of a step
-                typedef gdual<7, FC> D7F;
-                InstT<D7F> Ip = lift_inst<D7F>(I);
-                FC v[8], vy[8], vp[6], Ys[48], Kb[48], yb[8], pb[6];
+                // with 3 parameter-channel tangents plus the vacuum part) and the reverse sweep
+                // through the six stages of a step
+                FC v[8], vy[8], vc[4], Ys[48], Kb[48], yb[8], tc[4];
                 for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); }
                 for (int d = 0; d < 48; ++d) { Ys[d] = y[d % 8]; Kb[d] = FC(0.01 * d); }
-                for (int q = 0; q < 6; ++q) pb[q] = FC(0.0);
+                for (int q = 0; q < 4; ++q) tc[q] = FC(0.0);
                 g_flops = 0;
-                rhs_vjp<FC>(Ip, y, v, vy, vp);
+                rhs_vjp<FC>(I, y, v, vy, vc);
                 long long fvjp = g_flops;
                 g_flops = 0;
-                stages_adjoint<FC>(Ip, Ys, FC(0.1), Kb, yb, pb);
+                stages_adjoint<FC>(I, Ys, FC(0.1), Kb, yb, tc);
                 long long fstages = g_flops;
                 // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension
                 FC yt[8];

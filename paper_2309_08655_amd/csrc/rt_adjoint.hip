@@ -209,7 +209,8 @@ __global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int 
 
 // reverse pass: one escaped ray per lane, handed out by a lane atomic
 __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P, StarFixed fx, TolC tol,
-                                                     uint64_t seed, int64_t n, const int32_t* __restrict__ ifin,
+                                                     uint64_t seed, int64_t n, const double* __restrict__ rays,
+                                                     const int32_t* __restrict__ ifin,
                                                      const int32_t* __restrict__ nseg_in,
                                                      const double* __restrict__ theta_in,
                                                      const double* __restrict__ ckpt, int C, WorkCtr* rctr,
@@ -239,8 +240,8 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *facmax = ckpt[((int64_t)s * 10 + 9) * n + j];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        const int miss = adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], C, load, rb, obs, gbar, n_obs,
-                                         sigma, pb);
+        const int miss = adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, obs,
+                                         gbar, n_obs, sigma, pb);
         if (miss) {
             // the recompute did not reproduce the forward pass: no gradient for this ray
             missing += (unsigned long long)miss;
@@ -336,9 +337,9 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
     StarFixed fx = star_fixed(*star);
     timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
-    hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.ifin, W.nseg,
-                       W.theta, W.ckpt, ckpt_every, W.rctr, W.rlist, W.obs, n_obs, sigma, gbar, W.replay, W.gacc,
-                       grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays, W.ifin,
+                       W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.rlist, W.obs, n_obs, sigma, gbar, W.replay,
+                       W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
     timing_end(st);
     rc = check_launch("adj_rev_kernel");
     if (rc) return rc;

@@ -25,7 +25,6 @@
 
 namespace rtd {
 
-typedef gdual<7> D7;
 typedef gdual<6> D6;
 typedef gdual<14> D14;
 
@@ -206,67 +205,131 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
 // ----------------------------------------------------------------------------
 // reverse sweep
 // ----------------------------------------------------------------------------
-// Parameter-tangent copies of the instance: slots 1..6 for the stage products
-// (slot 0 is the state direction), 0..5 for the seed, 8..13 for the observable
-// (slots 0..7 are the final state).
-struct AdjParams {
-    InstT<D7> Ip;
-    InstT<D6> I6;
-    SeedT<D6> C6;
-    InstT<D14> I14;
+// The right-hand side depends on the star parameters only through the instance
+// constants rs, Om, (cos, sin) theta_m and the plasma coefficient Cwp R^3, and it is
+// linear in the last: H = H_vac + P or H_vac + P (1 - K) with P proportional to Cwp R^3.
+// The parameter part of a stage product is therefore v^T df/dp = sum_c T_c M_cp over
+// four channels c: the tangents of rs, Om and theta_m (dual numbers) and the plasma
+// channel T = v.(f - f_vac) with its log-derivative.  M (4 x 6) is computed once from
+// the instance constants in 6-tangent dual numbers.
+template <class S = double>
+struct VjpInst {
+    InstT<gdual<4, S>> I4;  // slot 0: state direction; slots 1..3: rs, Om, theta_m
+    InstT<S> Ivac;          // the same star without plasma
 };
 
-RT_HD void make_adj_params(const double p[6], const StarFixed& fx, AdjParams& A) {
-    D7 p7[6];
-    D6 p6[6];
-    D14 p14[6];
-    for (int q = 0; q < 6; ++q) {
-        p7[q] = D7(p[q]);
-        p7[q].d[1 + q] = 1.0;
-        p6[q] = D6(p[q]);
-        p6[q].d[q] = 1.0;
-        p14[q] = D14(p[q]);
-        p14[q].d[8 + q] = 1.0;
-    }
-    A.Ip = make_inst_t<D7>(p7, fx);
-    A.I6 = make_inst_t<D6>(p6, fx);
-    A.C6 = make_seed_t<D6>(p6, fx);
-    A.I14 = make_inst_t<D14>(p14, fx);
-    // the rotating-axis formula throughout: exact at theta_m = 0 and theta_m tangents flow
-    A.Ip.oblique = 1;
-    A.I6.oblique = 1;
-    A.I14.oblique = 1;
+// What the reverse sweep of a ray needs besides the double instance: the parameter
+// values, from which each dual-number instance is built where it is used (so that no
+// dual instance stays live, in registers, across the sweep).
+struct AdjParams {
+    double p[6];
+    StarFixed fx;
+};
+
+template <class S>
+RT_HD VjpInst<S> make_vjp_inst(const InstT<S>& I) {
+    typedef gdual<4, S> D4;
+    VjpInst<S> V;
+    V.I4 = lift_inst<D4>(I);
+    V.I4.rs.d[1] = S(1.0);
+    V.I4.Om.d[2] = S(1.0);
+    V.I4.cm.d[3] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
+    V.I4.sm.d[3] = I.cm;
+    V.Ivac = I;
+    V.Ivac.density = DEN_NONE;
+    return V;
 }
 
-// v^T df/dy (vy) and v^T df/dp (vp) at the state Y (S = double; generic for the
-// host operation counter)
+RT_HD void make_adj_params(const double p[6], const StarFixed& fx, AdjParams& A) {
+    for (int q = 0; q < 6; ++q) A.p[q] = p[q];
+    A.fx = fx;
+}
+
+// The observable at the final state: returns G = sum_j gbar_j K(n . o_j) and writes
+// dG/dy_f (8) and dG/dp (6), by dual numbers with 14 tangents.
+RT_HD_NOINLINE double observable_grad(const AdjParams& A, const double* yf, const double* obs, const double* gbar,
+                                      int n_obs, double sigma, double* gy, double* gp) {
+    D14 p14[6];
+    for (int q = 0; q < 6; ++q) {
+        p14[q] = D14(A.p[q]);
+        p14[q].d[8 + q] = 1.0;
+    }
+    InstT<D14> I14 = make_inst_t<D14>(p14, A.fx);
+    I14.oblique = 1;
+    D14 yd[8];
+    for (int d = 0; d < 8; ++d) {
+        yd[d] = D14(yf[d]);
+        yd[d].d[d] = 1.0;
+    }
+    D14 G = observer_sum(I14, yd, obs, gbar, n_obs, sigma);
+    for (int d = 0; d < 8; ++d) gy[d] = G.d[d];
+    for (int q = 0; q < 6; ++q) gp[q] = G.d[8 + q];
+    return G.v;
+}
+
+// End of a ray's sweep: the seed's sensitivities (root, momentum and weight in
+// 6-tangent dual numbers) contracted with the adjoint of y_0 and with G(y_f), and the
+// stage products' parameter channels mapped to the parameters,
+//   M = d(rs, Om, theta_m, log(Cwp R^3))/dp   (theta_m enters only through its own channel).
+RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t j, const double* yb, double wG,
+                                      const double* tc, double* pb) {
+    D6 p6[6];
+    for (int q = 0; q < 6; ++q) {
+        p6[q] = D6(A.p[q]);
+        p6[q].d[q] = 1.0;
+    }
+    InstT<D6> I6 = make_inst_t<D6>(p6, A.fx);
+    I6.oblique = 1;
+    const SeedT<D6> C6 = make_seed_t<D6>(p6, A.fx);
+    D6 sd[10];
+    seed_ray<D6>(I6, C6, seed, 0, j, sd);
+    const double cw = I6.Cwp.v, r3 = I6.R3.v;
+    for (int q = 0; q < 6; ++q) {
+        double a = wG * sd[8].d[q];
+        for (int d = 0; d < 8; ++d) a += yb[d] * sd[d].d[q];
+        a += tc[0] * I6.rs.d[q] + tc[1] * I6.Om.d[q] + ((q == 2) ? tc[2] : 0.0);
+        if (cw != 0.0 && r3 != 0.0) a += tc[3] * (I6.Cwp.d[q] / cw + I6.R3.d[q] / r3);
+        pb[q] += a;
+    }
+}
+
+// v^T df/dy (vy) and the four channels vc of v^T df/dp at the state Y (S = double;
+// generic for the host operation counter)
 template <class S = double>
-RT_HD_NOINLINE void rhs_vjp(const InstT<gdual<7, S>>& Ip, const S* Y, const S* v, S* vy, S* vp) {
-    typedef gdual<7, S> DS;
+RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc) {
+    typedef gdual<4, S> DS;
+    const VjpInst<S> V = make_vjp_inst<S>(I);
     DS yd[8], fd[8];
     for (int i = 0; i < 4; ++i) {
         yd[i] = DS(Y[i]);
-        yd[i].d[0] = -v[4 + i];  // u = J^T v: u_x = -v_k
+        yd[i].d[0] = S(0.0) - v[4 + i];  // u = J^T v: u_x = -v_k
         yd[4 + i] = DS(Y[4 + i]);
         yd[4 + i].d[0] = v[i];  // u_k = v_x
     }
-    rhs(Ip, yd, fd, 1.0);
+    rhs(V.I4, yd, fd, 1.0);
     // the tangent of f is J Hess(H) u; Hess(H) u = J^T (J Hess(H) u)
     for (int i = 0; i < 4; ++i) {
-        vy[i] = -fd[4 + i].d[0];
+        vy[i] = S(0.0) - fd[4 + i].d[0];
         vy[4 + i] = fd[i].d[0];
     }
-    for (int q = 0; q < 6; ++q) {
-        S a = v[0] * fd[0].d[1 + q];
-        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + q];
-        vp[q] = a;
+    for (int c = 0; c < 3; ++c) {
+        S a = v[0] * fd[0].d[1 + c];
+        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + c];
+        vc[c] = a;
     }
+    // plasma channel: v.(f - f_vac)
+    S fv[8];
+    rhs(V.Ivac, Y, fv, 1.0);
+    S a = v[0] * (fd[0].v - fv[0]);
+    for (int i = 1; i < 8; ++i) a = a + v[i] * (fd[i].v - fv[i]);
+    vc[3] = a;
 }
 
 // Adjoint of the six stages of a step: on entry Kb[8 i .. 8 i + 7] holds the
-// adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and pb.
+// adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and to the
+// parameter channels tc.
 template <class S = double>
-RT_HD void stages_adjoint(const InstT<gdual<7, S>>& Ip, const S* Ys, S h, S* Kb, S* yb, S* pb) {
+RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* tc) {
     using namespace dp5;
     const double A[6][5] = {{0, 0, 0, 0, 0},
                             {a21, 0, 0, 0, 0},
@@ -274,10 +337,10 @@ RT_HD void stages_adjoint(const InstT<gdual<7, S>>& Ip, const S* Ys, S h, S* Kb,
                             {a41, a42, a43, 0, 0},
                             {a51, a52, a53, a54, 0},
                             {a61, a62, a63, a64, a65}};
-    S vy[8], vp[6];
+    S vy[8], vc[4];
     for (int i = 5; i >= 0; --i) {
-        rhs_vjp<S>(Ip, Ys + i * 8, Kb + i * 8, vy, vp);
-        for (int q = 0; q < 6; ++q) pb[q] = pb[q] + vp[q];
+        rhs_vjp<S>(I, Ys + i * 8, Kb + i * 8, vy, vc);
+        for (int c = 0; c < 4; ++c) tc[c] = tc[c] + vc[c];
         for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
         for (int jj = 0; jj < i; ++jj) {
             if (A[i][jj] == 0.0) continue;
@@ -293,12 +356,10 @@ RT_HD void stages_adjoint(const InstT<gdual<7, S>>& Ip, const S* Ys, S h, S* Kb,
 // number of steps or checkpoints the recompute could not reproduce (0 when all is well).
 template <class Load, class Replay>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
-                          int nseg, double th, int C, Load&& load, Replay&& rb, const double* obs, const double* gbar,
-                          int n_obs, double sigma, double pb[6]) {
+                          int nseg, double th, double w, int C, Load&& load, Replay&& rb, const double* obs,
+                          const double* gbar, int n_obs, double sigma, double pb[6]) {
     using namespace dp5;
-    D6 sd[10];
-    seed_ray<D6>(A.I6, A.C6, seed, 0, j, sd);
-    const double w = sd[8].v;
+    double tc[4] = {0.0, 0.0, 0.0, 0.0};  // parameter channels of the stage products
     double yb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double wG = 0.0;
     int missing = 0;
@@ -357,16 +418,10 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     yth[d] = ydiff + om * Qq + t * dP;  // dE/dtheta
                 }
                 // the observable with 8 state and 6 parameter tangents
-                D14 yd[8];
-                for (int d = 0; d < 8; ++d) {
-                    yd[d] = D14(yf[d]);
-                    yd[d].d[d] = 1.0;
-                }
-                D14 G = observer_sum(A.I14, yd, obs, gbar, n_obs, sigma);
-                wG = G.v;
-                double gyf[8];
-                for (int d = 0; d < 8; ++d) gyf[d] = w * G.d[d];
-                for (int q = 0; q < 6; ++q) pb[q] += w * G.d[8 + q];
+                double gyf[8], gp[6];
+                wG = observable_grad(A, yf, obs, gbar, n_obs, sigma, gyf, gp);
+                for (int d = 0; d < 8; ++d) gyf[d] *= w;
+                for (int q = 0; q < 6; ++q) pb[q] += w * gp[q];
                 // crossing r(E(theta)) = r_max: remove the component along dE/dtheta
                 const double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
                 const double gr[3] = {yf[0] / r, yf[1] / r, yf[2] / r};
@@ -389,10 +444,10 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
                 }
                 // K7 = f(ynew)
-                double vy[8], vp[6];
-                rhs_vjp<double>(A.Ip, ynew, K7b, vy, vp);
+                double vy[8], vc[4];
+                rhs_vjp<double>(I, ynew, K7b, vy, vc);
                 for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
-                for (int q = 0; q < 6; ++q) pb[q] += vp[q];
+                for (int c = 0; c < 4; ++c) tc[c] += vc[c];
                 // ynew = y + h sum_i b_i K_i
                 for (int d = 0; d < 8; ++d) {
                     yb[d] += ynb[d];
@@ -413,15 +468,11 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     Kb[40 + d] = hn * b6 * yb[d];
                 }
             }
-            stages_adjoint<double>(A.Ip, Ys, hn, Kb, yb, pb);
+            stages_adjoint<double>(I, Ys, hn, Kb, yb, tc);
         }
     }
-    // seed: y_0(p) and w(p)
-    for (int q = 0; q < 6; ++q) {
-        double a = wG * sd[8].d[q];
-        for (int d = 0; d < 8; ++d) a += yb[d] * sd[d].d[q];
-        pb[q] += a;
-    }
+    // seed: y_0(p) and w(p); the stage products' channels
+    seed_and_channels(A, seed, j, yb, wG, tc, pb);
     return missing;
 }
 

@@ -78,7 +78,8 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
         };
         auto rb = [&](int idx, int d) -> double& { return rbuf[(size_t)idx * 9 + d]; };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, C, load, rb, obs, gbar, n_obs, sigma, pb);
+        missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, seedv[8], C, load, rb, obs, gbar, n_obs,
+                                   sigma, pb);
         for (int q = 0; q < 6; ++q) {
             gray[i * 6 + q] = pb[q] / (double)n;
             grad[q] += pb[q];
