@@ -30,6 +30,7 @@ inline FC operator-(FC a) { return FC(-a.v); }
 inline FC sqrt(FC a) { ++g_flops; return FC(std::sqrt(a.v)); }
 inline FC rcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
 inline FC frcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
+inline FC frcp_coarse(FC a) { ++g_flops; return FC(1.0 / a.v); }
 inline FC frsqrt(FC a) { ++g_flops; return FC(1.0 / std::sqrt(a.v)); }
 inline FC fabs(FC a) { return FC(std::fabs(a.v)); }
 inline FC fmax(FC a, FC b) { return FC(std::fmax(a.v, b.v)); }

@@ -58,6 +58,16 @@ RT_HD double frcp(double x) {
     return 1.0 / x;
 #endif
 }
+// One Newton step only: about 1e-14 relative, for values that merely feed the step
+// controller's accept test and step-size heuristic.
+RT_HD double frcp_coarse(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+#else
+    return 1.0 / x;
+#endif
+}
 RT_HD double frsqrt(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
     double y = __builtin_amdgcn_rsq(x);
@@ -216,11 +226,27 @@ struct Plasma {
     T P, gx, gy, gz, gt;
 };
 
-// sin and cos of a rotation angle from Taylor polynomials (the series of sin and
-// cos truncated after x^13 and x^14, error below 3e-17 for |x| <= 1/2), after
-// halving the angle until |x| <= 1/2 and doubling back.  No table, no library call.
+// sin and cos of a rotation angle from Taylor polynomials: for |x| <= 1/32 the
+// series truncated after x^7 and x^8; otherwise after x^13 and x^14 (error below
+// 3e-17 for |x| <= 1/2), after halving the angle until |x| <= 1/2 and doubling back.
+// No table, no library call.
 template <class T>
 RT_HD void small_angle_sincos(T x, T* s, T* c) {
+    if (fabs(value(x)) <= 0.03125) {
+        // the angles of the tracing kernels' stages: the series to x^7 and x^8 is exact to
+        // below 3e-18 relative for |x| <= 1/32
+        const T x2 = x * x;
+        T ps = -1.0 / 5040.0;
+        ps = 1.0 / 120.0 + x2 * ps;
+        ps = -1.0 / 6.0 + x2 * ps;
+        *s = x + (x * x2) * ps;
+        T pc = 1.0 / 40320.0;
+        pc = -1.0 / 720.0 + x2 * pc;
+        pc = 1.0 / 24.0 + x2 * pc;
+        pc = -0.5 + x2 * pc;
+        *c = 1.0 + x2 * pc;
+        return;
+    }
     int k = 0;
     while (!(fabs(value(x)) <= 0.5) && k < 64) { x = 0.5 * x; ++k; }
     T x2 = x * x;

@@ -78,7 +78,7 @@ RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], doub
         T e = he1 * S.K[0][i] + he3 * S.K[2][i] + he4 * S.K[3][i] + he5 * S.K[4][i] + he6 * S.K[5][i] +
               he7 * S.K[6][i];
         T sc = atol + rtol * fmax(fabs(y[i]), fabs(ynew[i]));
-        T qq = e * frcp(sc);
+        T qq = e * frcp_coarse(sc);
         acc = acc + qq * qq;
     }
     T err = sqrt(acc * 0.125);
