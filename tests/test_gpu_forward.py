@@ -194,3 +194,23 @@ def test_schedules_give_identical_rays(rt, orc, sched):
     f1, i1 = rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, st, schedule=sched)
     assert np.array_equal(_np(i0), _np(i1))
     assert np.array_equal(_np(f0), _np(f1))
+
+
+def test_kernel_timing_records_each_launch(rt):
+    """rt_timing / rt_kernel_times bracket every launch of the tracing kernel with a HIP
+    event pair on the caller's stream; stopping keeps the records, starting clears them."""
+    import torch
+    cfg = W.CFG1
+    rays, st = rt.rt_sample_resonance(cfg["star"], 0, 2000)
+    rt.timing(True)
+    for _ in range(3):
+        rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, st)
+    rt.timing(False)
+    rt.rt_trace_forward(cfg["star"], cfg["tol"], rays, st)  # not recorded
+    torch.cuda.synchronize()
+    kt = rt.kernel_times()
+    assert [name for name, _ in kt] == ["trace_fwd_kernel"] * 3
+    assert all(ms > 0.0 for _, ms in kt)
+    rt.timing(True)
+    rt.timing(False)
+    assert rt.kernel_times() == []
