@@ -213,7 +213,7 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
  * obs: HOST array "[n_obs][3]" of unit vectors, 1 <= n_obs <= 64; sigma > 0 [rad];
  * 1 <= ckpt_every <= 1024; max_ckpt >= 1; weights RT_WEIGHTS_CONST_B is not supported.
  * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt) bytes (about
- * n (320 + 80 max_ckpt) + 4.7 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
+ * n (316 + 80 max_ckpt) + 4.7 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
  * RT_EUNSUPPORTED or RT_EHIP. */
 int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
                  int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,

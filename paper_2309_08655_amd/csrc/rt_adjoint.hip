@@ -47,8 +47,7 @@ struct AdjWs {
     int32_t* nseg;    // [n] checkpoints stored
     double* theta;    // [n] location of r = r_max on the last step
     double* ckpt;     // [max_ckpt][10][n]: y[8], h, facmax
-    WorkCtr* rctr;    // reverse work list: head, len, iters = steps the recompute missed
-    int32_t* rlist;   // [n] escaped rays
+    WorkCtr* rctr;    // reverse pass: head of the work list, seal, iters = steps the recompute missed
     double* obs;      // [n_obs][3]
     double* facc;     // [MAX_OBS] flux accumulators
     double* gacc;     // [8] gradient accumulators
@@ -71,7 +70,6 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
     char* theta = take(sizeof(double) * (size_t)n);
     char* ckpt = take(sizeof(double) * 10 * (size_t)Kc * (size_t)n);
     char* rctr = take(sizeof(WorkCtr));
-    char* rlist = take(sizeof(int32_t) * (size_t)n);
     char* obs = take(sizeof(double) * 3 * (size_t)n_obs);
     char* facc = take(sizeof(double) * MAX_OBS);
     char* gacc = take(sizeof(double) * 8);
@@ -86,7 +84,6 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
         W->theta = (double*)theta;
         W->ckpt = (double*)ckpt;
         W->rctr = (WorkCtr*)rctr;
-        W->rlist = (int32_t*)rlist;
         W->obs = (double*)obs;
         W->facc = (double*)facc;
         W->gacc = (double*)gacc;
@@ -96,13 +93,12 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 }
 
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
-// cost-ordered work list; checkpoints, the escaped list and the flux
+// cost-ordered work list; checkpoints, per-ray counters and the flux
 __global__ void __launch_bounds__(256) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
                                                       const double* __restrict__ h0s, int C, int Kc,
                                                       double* __restrict__ ckpt, int32_t* __restrict__ nseg_out,
                                                       double* __restrict__ theta_out, int32_t* __restrict__ ifin,
-                                                      WorkCtr* rctr, int32_t* __restrict__ rlist,
                                                       const double* __restrict__ obs, int n_obs, double sigma,
                                                       double* __restrict__ facc) {
     __shared__ double sh_f[MAX_OBS];
@@ -160,8 +156,6 @@ __global__ void __launch_bounds__(256) adj_fwd_kernel(InstT<double> I, TolC tol,
                     const double c = nh[0] * obs[3 * o] + nh[1] * obs[3 * o + 1] + nh[2] * obs[3 * o + 2];
                     atomicAdd(&sh_f[o], w * smoothing_kernel(c, sigma));
                 }
-                unsigned long long pos = atomicAdd(&rctr->len, 1ull);
-                rlist[pos] = (int32_t)j;
             }
             active = false;
         }
@@ -169,6 +163,19 @@ __global__ void __launch_bounds__(256) adj_fwd_kernel(InstT<double> I, TolC tol,
     __syncthreads();
     for (int q = threadIdx.x; q < n_obs; q += blockDim.x)
         if (sh_f[q] != 0.0) atomicAdd(&facc[q], sh_f[q]);
+}
+
+// Reverse work list: escaped rays ordered by accepted steps, longest first, so that the
+// 64 rays a wave takes together have (nearly) the same segment and step counts and
+// its lanes walk them in lockstep.
+__global__ void adj_rev_keys_kernel(const int32_t* __restrict__ ifin, int64_t n, int32_t* __restrict__ keys) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const int32_t na = ifin[j];
+        keys[j] = (ifin[2 * n + j] == ST_ESCAPED)
+                      ? (ORDER_BUCKETS - 1) - (na < ORDER_BUCKETS - 1 ? (na > 0 ? na : 0) : ORDER_BUCKETS - 1)
+                      : -1;
+    }
 }
 
 __global__ void adj_scale_kernel(const double* acc, int m, double s, double* out) {
@@ -214,7 +221,8 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
                                                      const int32_t* __restrict__ nseg_in,
                                                      const double* __restrict__ theta_in,
                                                      const double* __restrict__ ckpt, int C, WorkCtr* rctr,
-                                                     const int32_t* __restrict__ rlist, const double* __restrict__ obs,
+                                                     const WorkCtr* lctr, const int32_t* __restrict__ rlist,
+                                                     const double* __restrict__ obs,
                                                      int n_obs, double sigma, const double* __restrict__ gbar,
                                                      double* __restrict__ replay, double* __restrict__ gacc,
                                                      double* __restrict__ grad_rays, double inv_n, int Kc,
@@ -225,11 +233,17 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     make_adj_params(P.p, fx, A);
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long missing = 0;
-    const unsigned long long rlen = rctr->len < (unsigned long long)n ? rctr->len : (unsigned long long)n;
+    const unsigned long long rlen = lctr->len < (unsigned long long)n ? lctr->len : (unsigned long long)n;
     auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 9 + d) * REV_LANES + lane_g]; };
+    const int lane = __lane_id();
     while (true) {
-        const unsigned long long qq = atomicAdd(&rctr->head, 1ull);
-        if (qq >= rlen) break;
+        // the wave takes 64 consecutive rays of the step-ordered list
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&rctr->head, 64ull);
+        base = __shfl(base, 0);
+        if (base >= rlen) break;
+        const unsigned long long qq = base + (unsigned long long)lane;
+        if (qq >= rlen) continue;
         const int64_t j = rlist[qq];
         if (j < 0 || j >= n) continue;
         const int S = ifin[j], nseg = nseg_in[j];
@@ -311,10 +325,16 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         const int grid = persistent_grid(sc, (const void*)adj_fwd_kernel, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         hipLaunchKernelGGL(adj_fwd_kernel, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
-                           W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.rctr, W.rlist, W.obs,
-                           n_obs, sigma, W.facc);
+                           W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma,
+                           W.facc);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");
+        if (rc) return rc;
+        // the forward list is spent: reuse its buffers for the step-ordered reverse list
+        hipLaunchKernelGGL(adj_rev_keys_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.ifin, n, W.fw.keys);
+        rc = check_launch("adj_rev_keys_kernel");
+        if (rc) return rc;
+        rc = order_work_list(W.fw, n, st);
         if (rc) return rc;
         hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.facc, n_obs, 1.0 / (double)n, flux);
         hipLaunchKernelGGL(adj_set_seal_kernel, dim3(1), dim3(64), 0, st, W.rctr,
@@ -338,8 +358,8 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     StarFixed fx = star_fixed(*star);
     timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
     hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays, W.ifin,
-                       W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.rlist, W.obs, n_obs, sigma, gbar, W.replay,
-                       W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
+                       W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs, sigma, gbar,
+                       W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
     timing_end(st);
     rc = check_launch("adj_rev_kernel");
     if (rc) return rc;
