@@ -108,7 +108,7 @@ typedef struct rt_schedule {
 #define RT_NEV 10
 
 enum { RT_OP_TRACE_FORWARD = 1, RT_OP_TRACE_BACKWARD = 2, RT_OP_BIN = 3, RT_OP_BATCHED = 4,
-       RT_OP_FLUX_GRAD = 5 };
+       RT_OP_FLUX_GRAD = 5, RT_OP_BACKWARD_POWER = 6 };
 
 /* rt_sample_resonance -- seed forward rays on the resonance foliation and weight them
  * (Sec. 2.2 eq. (Power); Sec. 3 eqs. (Hypersurfaces), (ForwardTracingEquation1);
@@ -157,6 +157,36 @@ int rt_bin_flux(const double* fin, const int32_t* ifin, const double* w, int64_t
 int rt_trace_backward(const rt_star* star, const rt_tol* tol, const rt_image* image, int32_t K, double* ev,
                       int32_t* nev, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
                       const rt_schedule* sched, void* stream);
+
+/* rt_trace_backward_rays -- as rt_trace_backward, for n rays through explicit points
+ * (b1[q], b2[q]) [km] of the plane at distance D_km perpendicular to the line of sight
+ * (inclination incl, azimuth phi_o) instead of a pixel grid: non-uniform sampling of the
+ * asymptotic surface (Sec. 2.1), e.g. quadrature nodes of the image integral.  b1, b2:
+ * device arrays [n]; outputs as for rt_trace_backward with ray index q.
+ * Workspace: rt_workspace_size(RT_OP_TRACE_BACKWARD, n).  Errors: RT_EINVAL, RT_ENOWS. */
+int rt_trace_backward_rays(const rt_star* star, const rt_tol* tol, double D_km, double incl, double phi_o,
+                           const double* b1, const double* b2, int64_t n, int32_t K, double* ev, int32_t* nev,
+                           double* fin, int32_t* ifin, void* ws, size_t ws_bytes, const rt_schedule* sched,
+                           void* stream);
+
+/* rt_backward_power -- the backward image sum of Sec. 2.1 eq. (BackPower), integrated over
+ * frequency: each recorded production event adds P_ag f_a (Sec. 3) to its ray, with the
+ * focused monochromatic axion density of Sec. 4.3 and P_ag of Sec. 4.4 (eqs.
+ * (ProbIsoCurved), (CPAnisoCurved)); an event contributes w^3 sqrt(A) P_ag v_a n_c/(4 pi k^2)
+ * [eV^4] per unit image area.  Events whose conversion length sqrt(2 pi v_a/|khat.dE|)
+ * exceeds Lc_max_km are excluded (the IR cutoff of Sec. 4.4; Lc_max_km <= 0: no cutoff).
+ * RT_WEIGHTS_CONST_B replaces |B_perp| by B_test_G; RT_WEIGHTS_UNIT is treated as
+ * RT_WEIGHTS_CONVERSION.
+ * ev "[K][RT_NEV][n]", nev[n]: events of rt_trace_backward(_rays) (device; only the first
+ * min(nev, K) events of a ray are stored, so only they count).  area: device [n] image area
+ * element of each ray [km^2], or NULL for a uniform pixel_area_km2.
+ * Output (device): wsum[n] = each ray's summed event weights [eV^4]; total[1] (may be NULL)
+ * = sum_q area_q wsum_q / (hbar c)^2 = dP/dOmega [eV^2], reduced in a fixed order.
+ * Workspace (only when total != NULL): rt_workspace_size(RT_OP_BACKWARD_POWER, n).
+ * Errors: RT_EINVAL, RT_ENOWS. */
+int rt_backward_power(const rt_star* star, const double* ev, const int32_t* nev, int64_t n, int32_t K,
+                      double Lc_max_km, const double* area, double pixel_area_km2, double* wsum, double* total,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Batched persistent launch (parameter scans): many star instances traced by one
  * persistent work-queue kernel.  Instances share plasma, density, weights and kdir; each

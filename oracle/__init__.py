@@ -78,6 +78,9 @@ def lib():
         L.orc_trace_backward.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                          C.c_int32, dp, ip, dp, ip, C.c_int]
+        L.orc_backward_rays.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, dp, dp, C.c_int64, C.c_int32,
+                                        C.c_double, dp, dp, ip, dp, ip, C.c_int]
+        L.orc_event_weight.argtypes = [sp, dp, C.c_double, dp, dp]
         L.orc_dopri_test.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.c_double, dp]
         L.orc_flux_fwdmode.argtypes = [sp, tp, C.c_uint64, C.c_int64, dp, C.c_int32, C.c_double, dp, dp, dp, dp, ip,
@@ -234,6 +237,32 @@ def trace_backward(s, t, image, K=8, i0=0, j0=0, stride=1, ni=None, nj=None, nth
                              image["phi_o"], image["half_width_km"], nx, ny, i0, j0, stride, ni, nj, K, _dp(ev),
                              _ip(nev), _dp(fin), _ip(ifin), nthreads)
     return ev, nev, fin, ifin
+
+
+def backward_rays(s, t, D_km, incl, phi_o, b1, b2, K=8, Lc_max_km=0.0, nthreads=0):
+    """Backward rays through the image-plane points (b1[q], b2[q]) [km].  Returns the
+    per-ray sum of event weights wsum[n] (dP/dOmega per unit image area, eV^4; multiply
+    by the pixel area in eV^-2), and the events, counts and final states."""
+    b1 = np.ascontiguousarray(b1, dtype=np.float64)
+    b2 = np.ascontiguousarray(b2, dtype=np.float64)
+    n = b1.shape[0]
+    wsum = np.zeros(n)
+    ev = np.zeros((K, NEV, n))
+    nev = np.zeros(n, dtype=np.int32)
+    fin = np.zeros((NFIN, n))
+    ifin = np.zeros((NIFIN, n), dtype=np.int32)
+    lib().orc_backward_rays(C.byref(make_star(s)), C.byref(make_tol(t)), D_km, incl, phi_o, _dp(b1), _dp(b2), n, K,
+                            Lc_max_km, _dp(wsum), _dp(ev), _ip(nev), _dp(fin), _ip(ifin), nthreads)
+    return wsum, ev, nev, fin, ifin
+
+
+def event_weight(s, y, Lc_max_km=0.0):
+    """Weight [eV^4] and conversion length [km] of one production event at state y[8]."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    w = C.c_double()
+    lc = C.c_double()
+    lib().orc_event_weight(C.byref(make_star(s)), _dp(y), Lc_max_km, C.byref(w), C.byref(lc))
+    return w.value, lc.value
 
 
 def dopri_test(problem, rtol, atol, t_end, h_fixed=0.0):

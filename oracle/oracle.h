@@ -88,6 +88,16 @@ int orc_trace_backward(const orc_star* s, const orc_tol* tol, double D_km, doubl
                        int32_t ni, int32_t nj, int32_t K, double* ev, int32_t* nev, double* fin,
                        int32_t* ifin, int nthreads);
 
+/* backward rays through explicit image-plane points (b1, b2) [km]; wsum[n] = sum over the
+   ray's recorded production events of the event weight dP/dOmega per unit image area
+   [eV^4] (Sec. 2.1 eq. (BackPower) with the Sec. 4.3-4.4 f_a and P_ag), events with
+   conversion length above Lc_max_km excluded when Lc_max_km > 0 */
+int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double incl, double phi_o,
+                      const double* b1, const double* b2, int64_t n, int32_t K, double Lc_max_km, double* wsum,
+                      double* ev, int32_t* nev, double* fin, int32_t* ifin, int nthreads);
+/* the weight of one production event at state y[8] (and its conversion length [km]) */
+int orc_event_weight(const orc_star* s, const double* y, double Lc_max_km, double* w, double* Lc);
+
 /* integrator pins: problem 0 = harmonic oscillator y'' = -y (state 8: pairs),
    problem 1 = exponential growth y' = y.  Returns final state and dense samples. */
 int orc_dopri_test(int32_t problem, double rtol, double atol, double t_end, double* y_end,

@@ -388,10 +388,13 @@ static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, co
 //   P ~ (1/N) sum_i w_i,  w = C_k n_c Vt Q,
 // for emission directions uniform in (cos theta, phi) and axion directions
 // uniform over a solid angle C_k (4 pi, or 2 pi for the outward hemisphere):
-//   Vt = sqrt|g_tt| sqrt|h_k| / sin(theta) = sqrt(A) r^2 sqrt(1 + |grad_perp F|^2/(A F_r^2)),
+//   Vt = sqrt|g_tt| sqrt|h_k| / sin(theta) = A r^2 sqrt(1 + |grad_perp F|^2/(A F_r^2)),
 //        the area element of r = r_k(theta, phi), eqs. (RaidalHypersurface)-(redshift),
-//        written with the gradient of F (the printed sqrt|h_k| is read as the
-//        product sqrt|g_tt| sqrt|h_k|, used once);
+//        written with the gradient of F: the printed sqrt|h_k|, which carries a factor
+//        A^{1/2}, times the sqrt|g_tt| of the time element (Sec. 4.2).  With both
+//        factors the total power of a spherical isotropic conversion surface in
+//        Schwarzschild equals the backward image sum of eq. (BackPower), the
+//        equality Sec. 2.4 reports;
 //   Q  = |cos theta_n| v_a w P_ag, where the 1/|k.dE| of P_ag cancels the
 //        projection cos theta_n exactly, eqs. (CosIso), (AngleDefAniso):
 //        isotropic   Q = pi g^2 |B_perp|^2 E^2 / |d w_p^2|        (eq. ProbIsoCurved, read
@@ -469,7 +472,7 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     P Fr = dot3(n, gF);
     P gp2 = P(0.0);
     for (int d = 0; d < 3; ++d) { P gp = gF[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
-    P Vt = sA * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr));    // km^2
+    P Vt = A * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr));     // km^2
     Vt = Vt / (HBARC_EVKM * HBARC_EVKM);                      // eV^-2
     P E = I.w_inf / sA;                                       // local photon energy [eV]
     P Bv[3];
@@ -803,14 +806,14 @@ static double event_G(const Inst<double>& I, const double y[8]) {
     return gtt * y[7] * y[7] + kk + I.ma2;
 }
 
-static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, double incl, double phio, double W,
-                           int32_t nx, int32_t ny, int32_t pi, int32_t pj, int32_t K, int64_t slot, int64_t n,
-                           double* ev, int32_t* nev, double* fin, int32_t* ifin) {
+// One backward ray through the point (b1, b2) of the plane at distance D perpendicular
+// to the line of sight (inclination incl, azimuth phio).
+static void backward_ray(const Inst<double>& I, const orc_tol& tol, double D, double incl, double phio, double b1,
+                         double b2, int32_t K, int64_t slot, int64_t n, double* ev, int32_t* nev, double* fin,
+                         int32_t* ifin) {
     double no[3] = {std::sin(incl) * std::cos(phio), std::sin(incl) * std::sin(phio), std::cos(incl)};
     double e1[3] = {std::cos(incl) * std::cos(phio), std::cos(incl) * std::sin(phio), -std::sin(incl)};
     double e2[3] = {-std::sin(phio), std::cos(phio), 0.0};
-    double db = 2.0 * W / nx;
-    double b1 = (pi + 0.5 - 0.5 * nx) * db, b2 = (pj + 0.5 - 0.5 * ny) * db;
     double y[8];
     for (int d = 0; d < 3; ++d) y[d] = D * no[d] + b1 * e1[d] + b2 * e2[d];
     y[3] = 0.0;
@@ -927,6 +930,85 @@ static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, 
     ifin[0 * n + slot] = (int32_t)nacc;
     ifin[1 * n + slot] = (int32_t)nrej;
     ifin[2 * n + slot] = status;
+}
+
+// pixel (pi, pj) of an nx x ny plane of half-width W: rays through the pixel centres
+static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, double incl, double phio, double W,
+                           int32_t nx, int32_t ny, int32_t pi, int32_t pj, int32_t K, int64_t slot, int64_t n,
+                           double* ev, int32_t* nev, double* fin, int32_t* ifin) {
+    double db = 2.0 * W / nx;
+    double b1 = (pi + 0.5 - 0.5 * nx) * db, b2 = (pj + 0.5 - 0.5 * ny) * db;
+    backward_ray(I, tol, D, incl, phio, b1, b2, K, slot, n, ev, nev, fin, ifin);
+}
+
+// ---------------------------------------------------------------------------
+// Backward power (Sec. 2.1 eq. (BackPower)): the image sums Delta b^2 w^3 f_gamma over
+// pixels, and a ray's f_gamma is the sum over its production events of P_ag f_a
+// (Sec. 3), with the focused monochromatic axions of Sec. 4.3,
+//   f_a = v_a n_c delta(w - w_c) / (4 pi k^2)     (local static-frame quantities),
+// and the conversion probabilities of Sec. 4.4,
+//   isotropic   P = pi g^2 |B_perp|^2 E^2 / |k.d(w_p^2)|           eq. (ProbIsoCurved)
+//   anisotropic P = (pi/2) g^2 |B_perp|^2 E^5 / (D |k.dE|)          eq. (CPAnisoCurved)
+// (k.d = k^mu d_mu, spatial for the stationary plasma; read with E^2 resp. E^5 so that
+// P is dimensionless: the same readings as the forward weights, whose Q is the
+// cancelled product |cos theta_n| v_a E P).  Integrating the image sum over frequency,
+// delta(w_inf / sqrt(A) - w_c) = sqrt(A) delta(w_inf - sqrt(A) w_c), so an event at a
+// static star contributes
+//   dP/dOmega += Delta b^2 w_inf^3 sqrt(A) P v_a n_c / (4 pi k^2).
+// The paper's IR cutoff on the conversion length (Sec. 4.4) is read as
+// L_c = sqrt(2 pi v_p / |khat.dE|) (a length); events with L_c > Lc_max are excluded
+// when Lc_max > 0.  Returns the event's weight per unit image area [eV^4].
+// ---------------------------------------------------------------------------
+static double event_weight(const Inst<double>& I, const double y[8], double Lc_max_km, double* Lc_out) {
+    const double x[3] = {y[0], y[1], y[2]};
+    const double t = y[3];
+    const double k[3] = {y[4], y[5], y[6]};
+    const double r = std::sqrt(dot3(x, x));
+    const double A = 1.0 - I.rs / r, sA = std::sqrt(A);
+    const double E = -y[7] * I.w_inf / sA;  // local photon energy [eV]
+    double ko[3];
+    ortho_components(I, x, k, ko);
+    const double kmag = std::sqrt(dot3(ko, ko)) * I.w_inf;  // [eV]
+    const double va = kmag / E;
+    const double n_c = I.n_inf * kmag / I.k0;  // on shell: |k_a| = |k_gamma| at the event
+    double Bv[3];
+    bfield_t(I, x, t, Bv);
+    const double B2 = dot3(Bv, Bv);
+    const double cB = dot3(ko, Bv) / std::sqrt(B2 * dot3(ko, ko));
+    const double G2 = gauss_in_eV2();
+    const double Bperp2 = (I.weights == W_CONV_CONSTB) ? (I.Btest * G2) * (I.Btest * G2)
+                                                      : B2 * G2 * G2 * (1.0 - cB * cB);
+    double gtt, gij[3][3];
+    inverse_metric(I, x, gtt, gij);
+    double kc[3];  // contravariant spatial components [units of w_inf]
+    for (int a = 0; a < 3; ++a) kc[a] = gij[a][0] * k[0] + gij[a][1] * k[1] + gij[a][2] * k[2];
+    using D3 = Dual<3, double>;
+    D3 xd[3] = {D3::var(x[0], 0), D3::var(x[1], 1), D3::var(x[2], 2)};
+    double P, kdE;  // kdE = k^a d_a E [eV^2 / km]
+    if (I.plasma == PL_ISO) {
+        D3 wd = wp2_tilde(I, xd, D3(0.0) + t);
+        double kdw = 0.0;
+        for (int a = 0; a < 3; ++a) kdw += kc[a] * wd.d[a];
+        const double kdwp2 = HBARC_EVKM * I.w_inf * I.w_inf * I.w_inf * kdw;  // k.d(w_p^2) [eV^4]
+        P = PI * I.g_eV * I.g_eV * Bperp2 * E * E / std::fabs(kdwp2);
+        kdE = I.w_inf * I.w_inf * I.w_inf * kdw / (2.0 * E);  // d E = d(w_p^2) / (2 E)
+    } else {
+        D3 Ed = energy_t(I, xd, t, k);
+        double kd = 0.0;
+        for (int a = 0; a < 3; ++a) kd += kc[a] * Ed.d[a];
+        const double kdEe = HBARC_EVKM * I.w_inf * I.w_inf * kd;  // k.dE [eV^3]
+        const double wp2 = wp2_tilde(I, x, t) * I.w_inf * I.w_inf;
+        const double c2 = cB * cB, s2 = 1.0 - c2;
+        const double Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
+        P = 0.5 * PI * I.g_eV * I.g_eV * Bperp2 * E * E * E * E * E / (Dd * std::fabs(kdEe));
+        kdE = I.w_inf * I.w_inf * kd;
+    }
+    const double khdE = std::fabs(kdE) / kmag;  // |khat.dE| [eV/km]
+    const double Lc = std::sqrt(2.0 * PI * va * HBARC_EVKM / khdE);
+    if (Lc_out) *Lc_out = Lc;
+    if (Lc_max_km > 0.0 && Lc > Lc_max_km) return 0.0;
+    const double w3 = I.w_inf * I.w_inf * I.w_inf;
+    return w3 * sA * P * va * n_c / (4.0 * PI * kmag * kmag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1113,6 +1195,32 @@ int orc_trace_backward(const orc_star* s, const orc_tol* tol, double D_km, doubl
         backward_pixel(I, *tol, D_km, incl, phi_o, half_width_km, nx, ny, i0 + a * stride, j0 + b * stride, K, q, n,
                        ev, nev, fin, ifin);
     }
+    return 0;
+}
+
+int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double incl, double phi_o,
+                      const double* b1, const double* b2, int64_t n, int32_t K, double Lc_max_km, double* wsum,
+                      double* ev, int32_t* nev, double* fin, int32_t* ifin, int nthreads) {
+    Inst<double> I = make_inst_d(*s);
+    for (int64_t q = 0; q < (int64_t)K * ORC_NEV * n; ++q) ev[q] = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
+    for (int64_t q = 0; q < n; ++q) {
+        backward_ray(I, *tol, D_km, incl, phi_o, b1[q], b2[q], K, q, n, ev, nev, fin, ifin);
+        double acc = 0.0;
+        const int m = std::min(nev[q], K);
+        for (int e = 0; e < m; ++e) {
+            double ye[8];
+            for (int d = 0; d < 8; ++d) ye[d] = ev[((int64_t)e * ORC_NEV + d) * n + q];
+            acc += event_weight(I, ye, Lc_max_km, nullptr);
+        }
+        wsum[q] = acc;
+    }
+    return 0;
+}
+
+int orc_event_weight(const orc_star* s, const double* y, double Lc_max_km, double* w, double* Lc) {
+    Inst<double> I = make_inst_d(*s);
+    *w = event_weight(I, y, Lc_max_km, Lc);
     return 0;
 }
 

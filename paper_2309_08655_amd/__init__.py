@@ -16,10 +16,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librt.so")
 
 RT_NFIN, RT_NIFIN, RT_NEV = 16, 3, 10
-OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD = 1, 2, 3, 4, 5
+OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD, OP_BACKWARD_POWER = 1, 2, 3, 4, 5, 6
 FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi", "omega", "H", "lam", "r", "h"]
 
-EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_batched",
+EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_backward_rays",
+           "rt_backward_power", "rt_trace_batched",
            "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
            "rt_workspace_size", "rt_timing", "rt_kernel_times", "rt_last_error", "rt_version"]
 KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace_bwd_kernel", 4: "adj_fwd_kernel",
@@ -79,6 +80,10 @@ def lib():
                                   C.c_size_t, vp]
         L.rt_trace_backward.argtypes = [sp, tp, C.POINTER(RtImage), C.c_int32, dp, ip, dp, ip, vp, C.c_size_t,
                                         C.POINTER(RtSchedule), vp]
+        L.rt_trace_backward_rays.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, dp, dp, C.c_int64,
+                                             C.c_int32, dp, ip, dp, ip, vp, C.c_size_t, C.POINTER(RtSchedule), vp]
+        L.rt_backward_power.argtypes = [sp, dp, ip, C.c_int64, C.c_int32, C.c_double, dp, C.c_double, dp, dp, vp,
+                                        C.c_size_t, vp]
         L.rt_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
         L.rt_batch_workspace_size.restype = C.c_size_t
         L.rt_batch_prepare.argtypes = [sp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(RtBatch), vp, C.c_size_t, vp]
@@ -221,6 +226,54 @@ def rt_trace_backward(star: dict, tol: dict, image: dict, K: int = 8, schedule: 
                                    _ptr(ifin), _ptr(ws), ws.numel(), C.byref(sc) if sc is not None else None,
                                    _stream()), "rt_trace_backward")
     return ev, nev, fin, ifin
+
+
+def rt_trace_backward_rays(star: dict, tol: dict, D_km: float, incl: float, phi_o: float, b1, b2, K: int = 8,
+                           schedule: dict | None = None, ws=None):
+    """Backward rays through explicit image-plane points (b1[q], b2[q]) [km] (device or host
+    float64 arrays; copied to the device)."""
+    dev = _device()
+    b1 = torch.as_tensor(b1, dtype=torch.float64).to(dev).contiguous()
+    b2 = torch.as_tensor(b2, dtype=torch.float64).to(dev).contiguous()
+    if b1.shape != b2.shape or b1.dim() != 1:
+        raise ValueError("b1 and b2 must be 1-D arrays of one length")
+    n = b1.numel()
+    ev = torch.empty((max(K, 1), RT_NEV, n), dtype=torch.float64, device=dev)[:K]
+    nev = torch.empty(n, dtype=torch.int32, device=dev)
+    fin = torch.empty((RT_NFIN, n), dtype=torch.float64, device=dev)
+    ifin = torch.empty((RT_NIFIN, n), dtype=torch.int32, device=dev)
+    ws = workspace(OP_TRACE_BACKWARD, n) if ws is None else ws
+    s, t = make_star(star), make_tol(tol)
+    sc = make_schedule(schedule)
+    _check(lib().rt_trace_backward_rays(C.byref(s), C.byref(t), float(D_km), float(incl), float(phi_o), _ptr(b1),
+                                        _ptr(b2), n, K, C.c_void_p(ev.data_ptr()), _ptr(nev), _ptr(fin), _ptr(ifin),
+                                        _ptr(ws), ws.numel(), C.byref(sc) if sc is not None else None, _stream()),
+           "rt_trace_backward_rays")
+    return ev, nev, fin, ifin
+
+
+def rt_backward_power(star: dict, ev, nev, Lc_max_km: float = 0.0, area=None, pixel_area_km2: float = 0.0,
+                      ws=None):
+    """Per-ray summed event weights wsum[n] [eV^4] and the image sum dP/dOmega [eV^2] (a
+    one-element device tensor) of the events of rt_trace_backward(_rays)."""
+    dev = _device()
+    K, n = ev.shape[0], nev.shape[0]
+    if ev.dim() != 3 or ev.shape[1] != RT_NEV or ev.shape[2] != n or not ev.is_contiguous():
+        raise ValueError("ev must be a contiguous [K][RT_NEV][n] tensor")
+    if nev.dtype != torch.int32 or ev.dtype != torch.float64:
+        raise ValueError("ev must be float64 and nev int32")
+    if area is not None:
+        area = torch.as_tensor(area, dtype=torch.float64).to(dev).contiguous()
+        if area.shape != (n,):
+            raise ValueError("area must have one entry per ray")
+    wsum = torch.empty(n, dtype=torch.float64, device=dev)
+    total = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = workspace(OP_BACKWARD_POWER, n) if ws is None else ws
+    s = make_star(star)
+    _check(lib().rt_backward_power(C.byref(s), C.c_void_p(ev.data_ptr()), _ptr(nev), n, K, float(Lc_max_km),
+                                   _ptr(area) if area is not None else None, float(pixel_area_km2), _ptr(wsum),
+                                   _ptr(total), _ptr(ws), ws.numel(), _stream()), "rt_backward_power")
+    return wsum, total
 
 
 def version() -> str:

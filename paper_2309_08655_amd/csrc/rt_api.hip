@@ -201,6 +201,8 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
             return fwd_ws_bytes(n) + align256(sizeof(double) * 8 * (size_t)n);
         case RT_OP_BIN:
             return align256(sizeof(int32_t) * (size_t)n);
+        case RT_OP_BACKWARD_POWER:  // block partials of the image sum
+            return align256(sizeof(double) * 1024);
         case RT_OP_FLUX_GRAD:  // 64 observers, a checkpoint every 64 steps, up to 64 of them
             return rt_flux_grad_workspace_size(n, 64, 64, 64);
         default:

@@ -27,9 +27,13 @@ __device__ __forceinline__ double event_G(const InstT<double>& I, const double y
     return g_kk(I, y) + I.ma2;
 }
 
+// image plane: pixel centres of an nx x ny grid of side db, or (b1 != nullptr) the
+// explicit plane offsets b1[p], b2[p] of each ray
 struct ImageC {
     double D, no[3], e1[3], e2[3], db;
     int nx, ny;
+    const double* b1;
+    const double* b2;
 };
 
 __global__ void __launch_bounds__(256) bwd_init_kernel(InstT<double> I, TolC tol, ImageC im, int64_t n, WorkCtr* ctr,
@@ -41,8 +45,15 @@ __global__ void __launch_bounds__(256) bwd_init_kernel(InstT<double> I, TolC tol
         int64_t p = base + threadIdx.x;
         bool valid = p < n;
         if (valid) {
-            int pi = (int)(p / im.ny), pj = (int)(p % im.ny);
-            double b1 = (pi + 0.5 - 0.5 * im.nx) * im.db, b2 = (pj + 0.5 - 0.5 * im.ny) * im.db;
+            double b1, b2;
+            if (im.b1 != nullptr) {
+                b1 = im.b1[p];
+                b2 = im.b2[p];
+            } else {
+                int pi = (int)(p / im.ny), pj = (int)(p % im.ny);
+                b1 = (pi + 0.5 - 0.5 * im.nx) * im.db;
+                b2 = (pj + 0.5 - 0.5 * im.ny) * im.db;
+            }
             double y[8];
             for (int d = 0; d < 3; ++d) y[d] = im.D * im.no[d] + b1 * im.e1[d] + b2 * im.e2[d];
             y[3] = 0.0;
@@ -246,6 +257,96 @@ static int launch_bwd_block(const rt_schedule& sc, const InstT<double>& I, const
     return check_launch("trace_bwd_kernel");
 }
 
+// ---------------------------------------------------------------------------
+// Backward power (Sec. 2.1 eq. (BackPower)): per-ray sums of the event weights and the
+// image sum dP/dOmega = sum_rays area * wsum / (hbar c)^2.  The sum is reduced in a fixed
+// order (per-thread strided sums, an LDS tree per block, one block over the block
+// partials), so it does not depend on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int POWER_BLOCK = 256;
+constexpr int POWER_MAX_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ void __launch_bounds__(POWER_BLOCK) event_power_kernel(InstT<double> I, SeedT<double> C,
+                                                                  const double* __restrict__ ev,
+                                                                  const int32_t* __restrict__ nev, int64_t n,
+                                                                  int32_t K, double Lc_max,
+                                                                  const double* __restrict__ area, double area0,
+                                                                  double* __restrict__ wsum,
+                                                                  double* __restrict__ partial) {
+    __shared__ double sh[POWER_BLOCK];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * POWER_BLOCK;
+    for (int64_t p = (int64_t)blockIdx.x * POWER_BLOCK + threadIdx.x; p < n; p += stride) {
+        const int m = min(nev[p], K);
+        double w = 0.0;
+        for (int e = 0; e < m; ++e) {
+            double y[8];
+            for (int d = 0; d < 8; ++d) y[d] = ev[((int64_t)e * RT_NEV_ + d) * n + p];
+            w += event_weight(I, C, y, Lc_max, nullptr);
+        }
+        wsum[p] = w;
+        acc += w * (area != nullptr ? area[p] : area0);
+    }
+    if (partial == nullptr) return;
+    const double b = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+__global__ void __launch_bounds__(POWER_MAX_BLOCKS) power_total_kernel(const double* __restrict__ partial, int nb,
+                                                                       double scale, double* __restrict__ total) {
+    __shared__ double sh[POWER_MAX_BLOCKS];
+    const double v = ((int)threadIdx.x < nb) ? partial[threadIdx.x] : 0.0;
+    const double t = block_sum(v, sh);
+    if (threadIdx.x == 0) *total = t * scale;
+}
+
+// shared tail of the two backward entry points
+static int trace_backward_common(const rt_star* star, const rt_tol* tol, const ImageC& im, int64_t n, int32_t K,
+                                 double* ev, int32_t* nev, double* fin, int32_t* ifin, void* ws,
+                                 const rt_schedule* sched, hipStream_t st) {
+    rt_schedule sc = resolve_schedule(sched);
+    InstT<double> I = make_inst(*star);
+    TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
+    FwdWs W = carve_fwd_ws(ws, n);
+    double* y0s = (double*)((char*)ws + fwd_ws_bytes(n));
+    hipLaunchKernelGGL(zero_ctr_kernel, dim3(1), dim3(64), 0, st, W.ctr);
+    if (n == 0) return check_launch("zero_ctr_kernel");
+    int grid = grid_for(n, 256, 8);
+    hipLaunchKernelGGL(bwd_init_kernel, dim3(grid), dim3(256), 0, st, I, T, im, n, W.ctr, W.list, W.h0, W.k1, y0s, nev);
+    int rc = check_launch("bwd_init_kernel");
+    if (rc) return rc;
+    if (sc.occupancy == 2) {
+        switch (sc.block) {
+            case 64: return launch_bwd_block<64, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+            case 128: return launch_bwd_block<128, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+            default: return launch_bwd_block<256, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+        }
+    }
+    switch (sc.block) {
+        case 64: return launch_bwd_block<64, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+        case 128: return launch_bwd_block<128, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+        default: return launch_bwd_block<256, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+    }
+}
+
+static void image_axes(double incl, double phi_o, ImageC& im) {
+    double si = std::sin(incl), ci = std::cos(incl);
+    double sp = std::sin(phi_o), cp = std::cos(phi_o);
+    im.no[0] = si * cp; im.no[1] = si * sp; im.no[2] = ci;
+    im.e1[0] = ci * cp; im.e1[1] = ci * sp; im.e1[2] = -si;
+    im.e2[0] = -sp; im.e2[1] = cp; im.e2[2] = 0.0;
+}
+
 }  // namespace rtd
 
 using namespace rtd;
@@ -268,37 +369,68 @@ extern "C" int rt_trace_backward(const rt_star* star, const rt_tol* tol, const r
     if (!nev || !fin || !ifin || (K > 0 && !ev)) return fail(RT_EINVAL, "rt_trace_backward: null array");
     size_t need = rt_workspace_size(RT_OP_TRACE_BACKWARD, n);
     if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_trace_backward: workspace too small");
-    rt_schedule sc = resolve_schedule(sched);
-    InstT<double> I = make_inst(*star);
-    TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     ImageC im;
-    double si = std::sin(image->incl), ci = std::cos(image->incl);
-    double sp = std::sin(image->phi_o), cp = std::cos(image->phi_o);
+    image_axes(image->incl, image->phi_o, im);
     im.D = image->D_km;
-    im.no[0] = si * cp; im.no[1] = si * sp; im.no[2] = ci;
-    im.e1[0] = ci * cp; im.e1[1] = ci * sp; im.e1[2] = -si;
-    im.e2[0] = -sp; im.e2[1] = cp; im.e2[2] = 0.0;
     im.db = 2.0 * image->half_width_km / image->nx;
     im.nx = image->nx;
     im.ny = image->ny;
-    FwdWs W = carve_fwd_ws(ws, n);
-    double* y0s = (double*)((char*)ws + fwd_ws_bytes(n));
+    im.b1 = nullptr;
+    im.b2 = nullptr;
+    return trace_backward_common(star, tol, im, n, K, ev, nev, fin, ifin, ws, sched, (hipStream_t)stream);
+}
+
+extern "C" int rt_trace_backward_rays(const rt_star* star, const rt_tol* tol, double D_km, double incl,
+                                      double phi_o, const double* b1, const double* b2, int64_t n, int32_t K,
+                                      double* ev, int32_t* nev, double* fin, int32_t* ifin, void* ws,
+                                      size_t ws_bytes, const rt_schedule* sched, void* stream) {
+    clear_error();
+    if (!validate_star(star) || !validate_tol(tol)) return RT_EINVAL;
+    if (!(D_km > 0) || !std::isfinite(D_km) || !std::isfinite(incl) || !std::isfinite(phi_o))
+        return fail(RT_EINVAL, "rt_trace_backward_rays: invalid image plane");
+    if (D_km <= star->R_km) return fail(RT_EINVAL, "rt_trace_backward_rays: image plane must lie outside the star");
+    if (K < 0) return fail(RT_EINVAL, "rt_trace_backward_rays: negative K");
+    if (n < 0 || n > INT32_MAX) return fail(RT_EINVAL, "rt_trace_backward_rays: invalid ray count");
+    if (n > 0 && (!b1 || !b2 || !nev || !fin || !ifin || (K > 0 && !ev)))
+        return fail(RT_EINVAL, "rt_trace_backward_rays: null array");
+    size_t need = rt_workspace_size(RT_OP_TRACE_BACKWARD, n);
+    if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_trace_backward_rays: workspace too small");
+    ImageC im;
+    image_axes(incl, phi_o, im);
+    im.D = D_km;
+    im.db = 0.0;
+    im.nx = 0;
+    im.ny = 0;
+    im.b1 = b1;
+    im.b2 = b2;
+    return trace_backward_common(star, tol, im, n, K, ev, nev, fin, ifin, ws, sched, (hipStream_t)stream);
+}
+
+extern "C" int rt_backward_power(const rt_star* star, const double* ev, const int32_t* nev, int64_t n, int32_t K,
+                                 double Lc_max_km, const double* area, double pixel_area_km2, double* wsum,
+                                 double* total, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!validate_star(star)) return RT_EINVAL;
+    if (n < 0 || K < 0) return fail(RT_EINVAL, "rt_backward_power: negative size");
+    if (!std::isfinite(Lc_max_km)) return fail(RT_EINVAL, "rt_backward_power: non-finite cutoff");
+    if (!area && !(pixel_area_km2 >= 0.0 && std::isfinite(pixel_area_km2)))
+        return fail(RT_EINVAL, "rt_backward_power: invalid pixel area");
+    if (n > 0 && (!nev || !wsum || (K > 0 && !ev))) return fail(RT_EINVAL, "rt_backward_power: null array");
+    size_t need = rt_workspace_size(RT_OP_BACKWARD_POWER, n);
+    if (total && (!ws || ws_bytes < need)) return fail(RT_ENOWS, "rt_backward_power: workspace too small");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(zero_ctr_kernel, dim3(1), dim3(64), 0, st, W.ctr);
-    int grid = grid_for(n, 256, 8);
-    hipLaunchKernelGGL(bwd_init_kernel, dim3(grid), dim3(256), 0, st, I, T, im, n, W.ctr, W.list, W.h0, W.k1, y0s, nev);
-    int rc = check_launch("bwd_init_kernel");
-    if (rc) return rc;
-    if (sc.occupancy == 2) {
-        switch (sc.block) {
-            case 64: return launch_bwd_block<64, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-            case 128: return launch_bwd_block<128, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-            default: return launch_bwd_block<256, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-        }
-    }
-    switch (sc.block) {
-        case 64: return launch_bwd_block<64, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-        case 128: return launch_bwd_block<128, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-        default: return launch_bwd_block<256, 1>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
-    }
+    InstT<double> I = make_inst(*star);
+    SeedT<double> C = make_seed_consts(*star);
+    const double hc = phys::hbarc_eVkm;
+    const int nb =
+        (int)std::min<int64_t>(POWER_MAX_BLOCKS, std::max<int64_t>(1, (n + POWER_BLOCK - 1) / POWER_BLOCK));
+    double* partial = total ? (double*)ws : nullptr;  // block partials of the image sum
+    if (n == 0 && !total) return RT_OK;
+    hipLaunchKernelGGL(event_power_kernel, dim3(nb), dim3(POWER_BLOCK), 0, st, I, C, ev, nev, n, K, Lc_max_km, area,
+                       pixel_area_km2, wsum, partial);
+    int rc = check_launch("event_power_kernel");
+    if (rc || !total) return rc;
+    hipLaunchKernelGGL(power_total_kernel, dim3(1), dim3(POWER_MAX_BLOCKS), 0, st, (const double*)partial, nb,
+                       1.0 / (hc * hc), total);
+    return check_launch("power_total_kernel");
 }

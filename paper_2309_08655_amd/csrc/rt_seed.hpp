@@ -264,7 +264,8 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     T Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
     T gp2 = T(0.0);
     for (int d = 0; d < 3; ++d) { T gp = Fd.d[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
-    T Vt = sA * rc * rc * sqrt(1.0 + gp2 * rcp(A * Fr * Fr)) * (1.0 / (C.hbarc * C.hbarc));
+    // sqrt|g_tt| times the printed sqrt|h_k| (which already carries A^{1/2})
+    T Vt = A * rc * rc * sqrt(1.0 + gp2 * rcp(A * Fr * Fr)) * (1.0 / (C.hbarc * C.hbarc));
     T E = C.w_inf * rcp(sA);
     T ir = rcp(rc);
     T Rr = I.R * ir;
@@ -305,6 +306,78 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     }
     out[8] = Ck * n_c * Vt * Q;
     return ST_OK;
+}
+
+// Weight of one backward production event (Sec. 2.1 eq. (BackPower), Sec. 3): a ray's
+// photon density is the sum over its events of P_ag f_a, with the focused monochromatic
+// axion density f_a = v_a n_c delta(w - w_c)/(4 pi k^2) of Sec. 4.3 and P_ag of Sec. 4.4,
+//   isotropic   P = pi g^2 |B_perp|^2 E^2 / |k.d(w_p^2)|,   eq. (ProbIsoCurved)
+//   anisotropic P = (pi/2) g^2 |B_perp|^2 E^5 / (D |k.dE|),  eq. (CPAnisoCurved)
+// with k.d = k^a d_a (contravariant spatial k; the plasma is quasi-stationary).  The
+// frequency integral of w^3 f turns delta(w_inf/sqrt(A) - w_c) into sqrt(A), so the event
+// adds w_inf^3 sqrt(A) P v_a n_c / (4 pi k^2) [eV^4] to dP/dOmega per unit image area.
+// E is the event's own local frequency -k_t/sqrt(A); for the LO mode dE/dx at fixed
+// covariant k follows from H(x, k_t, k) = 0:
+//   dE/dx = (dH/dx)/(sqrt(A) dH/dk_t) - E s/(2 A r) n.
+// The conversion length L_c = sqrt(2 pi v_a / |khat.dE|) [km] (isotropic: dE = d(w_p^2)/2E)
+// is returned in *Lc; the event counts only if Lc_max <= 0 or L_c <= Lc_max (the IR
+// cutoff of Sec. 4.4).
+RT_HD double event_weight(const InstT<double>& I, const SeedT<double>& C, const double y[8], double Lc_max,
+                          double* Lc) {
+    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const double ir = rcp(::sqrt(r2));
+    const double n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
+    const double s = I.rs * ir;
+    const double A = 1.0 - s;
+    const double sA = ::sqrt(A);
+    const double El = -y[7] * rcp(sA);  // local frequency [w_inf]
+    const double q = n[0] * y[4] + n[1] * y[5] + n[2] * y[6];
+    const double kk = y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
+    const double ku = ::sqrt(kk - s * q * q);  // static-frame |k| [w_inf]
+    const double E = El * C.w_inf, kmag = ku * C.w_inf;
+    const double va = ku * rcp(El);
+    const double n_c = C.nc_per_ka * ku;
+    // static-frame k = k + (sqrt(A) - 1) q n; contravariant k = k - s q n
+    const double ko[3] = {y[4] + (sA - 1.0) * q * n[0], y[5] + (sA - 1.0) * q * n[1], y[6] + (sA - 1.0) * q * n[2]};
+    const double kc[3] = {y[4] - s * q * n[0], y[5] - s * q * n[1], y[6] - s * q * n[2]};
+    double m[3], mt[3];
+    magnetic_axis(I, y[3], m, mt);
+    const double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    double u[3];
+    dipole_dir(n, m, mu, u);
+    const double u2 = 1.0 + 3.0 * mu * mu;
+    const double ko_u = ko[0] * u[0] + ko[1] * u[1] + ko[2] * u[2];
+    const double cB2 = ko_u * ko_u * rcp(ku * ku * u2);
+    const double Rr = I.R * ir;
+    const double Bmag = 0.5 * value(C.B0) * Rr * Rr * Rr * ::sqrt(u2);
+    const double Bperp2 = (C.weights == W_CONV_CONSTB) ? (C.Btest * C.G2) * (C.Btest * C.G2)
+                                                       : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2);
+    const double w = value(C.w_inf);
+    const Plasma<double> pl = plasma_eval(I, n, ir, m, mu, 0.0);
+    double P, kdE;  // kdE = k^a d_a E [eV^2 / km]
+    if (I.plasma == PL_ISO) {
+        const double kdw = kc[0] * pl.gx + kc[1] * pl.gy + kc[2] * pl.gz;  // [w_inf^3 / km]
+        P = (phys::pi * C.g2) * Bperp2 * E * E * rcp(::fabs(C.hbarc * w * w * w * kdw));
+        kdE = w * w * w * kdw * rcp(2.0 * E);
+    } else {
+        double g[8];
+        grad_h(I, y, g);
+        const double c0 = rcp(sA * g[7]);
+        const double c1 = El * s * ir * rcp(2.0 * A);
+        const double kd = kc[0] * (g[0] * c0 - c1 * n[0]) + kc[1] * (g[1] * c0 - c1 * n[1]) +
+                          kc[2] * (g[2] * c0 - c1 * n[2]);  // [w_inf^2 / km]
+        const double wp2 = pl.P * w * w;
+        const double s2 = 1.0 - cB2;
+        const double D0 = E * E - cB2 * wp2;
+        const double Dd = D0 * D0 + cB2 * s2 * wp2 * wp2;
+        const double E2 = E * E;
+        P = (0.5 * phys::pi * C.g2) * Bperp2 * E2 * E2 * E * rcp(Dd * ::fabs(C.hbarc * w * w * kd));
+        kdE = w * w * kd;
+    }
+    const double Lcv = ::sqrt(2.0 * phys::pi * va * C.hbarc * kmag * rcp(::fabs(kdE)));
+    if (Lc) *Lc = Lcv;
+    if (Lc_max > 0.0 && Lcv > Lc_max) return 0.0;
+    return w * w * w * sA * P * va * n_c * rcp(4.0 * phys::pi * kmag * kmag);
 }
 
 }  // namespace rtd

@@ -1,0 +1,221 @@
+"""GPU parity of the backward power (rt_trace_backward_rays, rt_backward_power) against
+the CPU oracle, and the forward = backward total-power identity of Sec. 2.4 on the GPU.
+
+- Event weights: the oracle's own events, copied to the device, weighed by both sides.
+  Isotropic plasma: the same arithmetic up to rounding (1e-12); anisotropic: dE/dx by two
+  routes (implicit from H(x, k_t, k) = 0 on the GPU, the LO energy differentiated at fixed
+  k in the oracle), which coincide on the dispersion shell: per event 2|H| + 1e-11, with H
+  the integration drift of the event state.
+- Rays through explicit image points: as the pixel-grid tracer (bit-identical on pixel
+  centres) and, where the oracle is well conditioned, as the oracle (events 1e-9).
+- Total power of the spherical isotropic star: GPU forward seeds versus GPU backward rays
+  on Gauss-Legendre nodes of the image integral, 1e-6."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_08655_amd as rt
+    rt.lib()
+    return rt
+
+
+def _dev(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+STARS = {
+    "magnetar_aniso": W.CFG3["star"],
+    "magnetar_iso": dict(W.CFG3["star"], plasma=W.PLASMA_ISO),
+    "spherical_constb": W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO,
+                               weights=W.WEIGHTS_CONST_B),
+    "gj_aniso_oblique": W.star(M_Msun=1.4, theta_m=0.3, plasma=W.PLASMA_ANISO, m_a_eV=1e-5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STARS))
+def test_event_weights_on_oracle_events(rt, orc, name):
+    import torch
+    s = STARS[name]
+    rng = np.random.default_rng(3)
+    half = 12.0 if s["density"] == W.DENSITY_SPHERICAL else 30.0
+    b1, b2 = rng.uniform(-half, half, 96), rng.uniform(-half, half, 96)
+    t = W.tol(r_max_km=1e5, rtol=1e-10, atol=1e-14)
+    K = 8
+    print(f"event weights {name}", flush=True)
+    wsum_o, ev_o, nev_o, _, _ = orc.backward_rays(s, t, 1e5, 1.0, 0.3, b1, b2, K=K)
+    assert (nev_o > 0).sum() >= 8
+    ev = _dev(ev_o, torch.float64)
+    nev = _dev(nev_o, torch.int32)
+    wsum, total = rt.rt_backward_power(s, ev, nev, pixel_area_km2=0.25)
+    torch.cuda.synchronize()
+    wg = wsum.cpu().numpy()
+    hit = nev_o > 0
+    assert np.all(wg[~hit] == 0.0)
+    # allowed difference per ray: isotropic 1e-12 relative; anisotropic, per event twice
+    # the event's |H| (the two routes to dE/dx agree on the dispersion shell) plus 1e-11
+    allow = np.zeros_like(wsum_o)
+    for q in np.nonzero(hit)[0]:
+        for e in range(min(nev_o[q], K)):
+            y = ev_o[e, :8, q]
+            we, _ = orc.event_weight(s, y)
+            rel = 1e-12 if s["plasma"] == W.PLASMA_ISO else 1e-11 + 2.0 * abs(orc.hamiltonian(s, y))
+            allow[q] += abs(we) * rel
+    err = np.abs(wg - wsum_o)
+    assert np.all(err[hit] <= allow[hit]), (err[hit] / allow[hit]).max()
+    hc = orc.constants()["hbarc_eVkm"]
+    ref = 0.25 * wsum_o.sum() / hc ** 2
+    assert abs(total.item() - ref) <= 0.25 * allow.sum() / hc ** 2 + 1e-14 * abs(ref)
+    tol = 1e-12 if s["plasma"] == W.PLASMA_ISO else 1e-11 + 2.0 * max(
+        abs(orc.hamiltonian(s, ev_o[e, :8, q])) for q in np.nonzero(hit)[0] for e in range(min(nev_o[q], K)))
+    # the cutoff drops the same events on both sides
+    lcs = [orc.event_weight(s, ev_o[e, :8, q])[1] for q in np.nonzero(hit)[0] for e in range(min(nev_o[q], K))]
+    cut = float(np.median(lcs))
+    if all(abs(lc / cut - 1) > 1e-9 for lc in lcs):
+        wsum_c, _ = rt.rt_backward_power(s, ev, nev, Lc_max_km=cut, pixel_area_km2=1.0)
+        wo_c, *_ = orc.backward_rays(s, t, 1e5, 1.0, 0.3, b1, b2, K=K, Lc_max_km=cut)
+        wc = wsum_c.cpu().numpy()
+        assert np.array_equal(wc == 0.0, wo_c == 0.0)
+        m = wo_c > 0
+        assert np.allclose(wc[m], wo_c[m], rtol=tol, atol=0)
+
+
+def test_rays_on_pixel_centres_equal_the_grid_tracer(rt):
+    """rt_trace_backward_rays on the pixel centres reproduces rt_trace_backward bit for bit."""
+    s, tol = W.CFG3["star"], W.CFG3["tol"]
+    image = dict(D_km=1e5, incl=1.0, phi_o=0.2, half_width_km=40.0, nx=24, ny=20)
+    db = 2 * image["half_width_km"] / image["nx"]
+    i, j = np.meshgrid(np.arange(image["nx"]), np.arange(image["ny"]), indexing="ij")
+    b1 = ((i + 0.5 - 0.5 * image["nx"]) * db).ravel()
+    b2 = ((j + 0.5 - 0.5 * image["ny"]) * db).ravel()
+    print("rays on pixel centres", flush=True)
+    K = 4
+    a = [x.cpu().numpy() for x in rt.rt_trace_backward(s, tol, image, K=K)]
+    b = [x.cpu().numpy() for x in rt.rt_trace_backward_rays(s, tol, image["D_km"], image["incl"], image["phi_o"],
+                                                            b1, b2, K=K)]
+    for x, y in zip(a[1:], b[1:]):  # nev, fin, ifin
+        assert np.array_equal(x, y)
+    nev = a[1]
+    assert (nev > 0).sum() >= 10
+    # stored events (slots past a ray's count are not written)
+    for q in np.nonzero(nev)[0]:
+        m = min(nev[q], K)
+        assert np.array_equal(a[0][:m, :, q], b[0][:m, :, q]), q
+
+
+def test_backward_rays_and_power_match_oracle(rt, orc):
+    """End to end on the magnetar star: GPU events from explicit points against the
+    oracle's (rays the oracle itself moves under a 2^-50 change of D are excused, at most
+    2%), then per-ray weights of the GPU's own events against the oracle's."""
+    s = W.CFG3["star"]
+    t = W.tol(r_max_km=1e5)
+    rng = np.random.default_rng(8)
+    n = 400
+    b1, b2 = rng.uniform(-35, 35, n), rng.uniform(-35, 35, n)
+    K = 4
+    print("backward rays + power, magnetar", flush=True)
+    ev, nev, fin, ifin = rt.rt_trace_backward_rays(s, t, 1e5, 0.8, 0.1, b1, b2, K=K)
+    wsum, total = rt.rt_backward_power(s, ev, nev, pixel_area_km2=1.0)
+    w_o, ev_o, nev_o, fin_o, ifin_o = orc.backward_rays(s, t, 1e5, 0.8, 0.1, b1, b2, K=K)
+    bad = np.zeros(n, dtype=bool)
+    for fac in (1 + 2.0 ** -50, 1 - 2.0 ** -50):
+        w2, ev2, nev2, fin2, ifin2 = orc.backward_rays(s, t, 1e5 * fac, 0.8, 0.1, b1, b2, K=K)
+        bad |= (nev2 != nev_o) | (ifin2[2] != ifin_o[2]) | (ifin2[0] != ifin_o[0])
+        m = nev2 > 0
+        bad |= m & (np.abs(w2 - w_o) > 1e-8 * np.abs(w_o))
+    assert bad.mean() <= 0.02
+    ok = ~bad
+    nev_g, ifin_g, w_g = nev.cpu().numpy(), ifin.cpu().numpy(), wsum.cpu().numpy()
+    assert np.array_equal(nev_g[ok], nev_o[ok])
+    assert np.array_equal(ifin_g[2][ok], ifin_o[2][ok])
+    ev_g = ev.cpu().numpy()
+    for q in np.nonzero(ok & (nev_o > 0))[0]:
+        for e in range(min(K, nev_o[q])):
+            assert np.linalg.norm(ev_g[e, :3, q] - ev_o[e, :3, q]) <= 1e-9 * np.linalg.norm(ev_o[e, :3, q])
+    m = ok & (nev_o > 0)
+    assert m.sum() >= 30
+    # event states agree to ~1e-9; the weight amplifies that by its conditioning
+    assert np.allclose(w_g[m], w_o[m], rtol=1e-6, atol=0), np.abs(w_g[m] / w_o[m] - 1).max()
+
+
+@pytest.mark.parametrize("M", [1.4, 0.5])
+def test_forward_equals_backward_total_power_on_gpu(rt, orc, M):
+    """Sec. 2.4 on the GPU: 4 pi dP/dOmega from backward rays on 24 Gauss-Legendre nodes in
+    b = b_max sin(phi) (one pilot pass maps the nodes to launch offsets through the
+    conserved |x cross k|) equals the mean forward seed weight."""
+    import torch
+    s = W.star(M_Msun=M, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO, weights=W.WEIGHTS_CONST_B,
+               kdir=W.KDIR_ISOTROPIC, B_test_G=1e12, m_a_eV=1e-5)
+    c = orc.constants()
+    print(f"forward = backward total power, M = {M}", flush=True)
+    rays, st = rt.rt_sample_resonance(s, 0, 4096)
+    torch.cuda.synchronize()
+    assert int((st != 0).sum()) == 0
+    P_fwd = rays[8].mean().item()
+    r_c = rays[9][0].item()
+    A = 1 - 2 * c["GMsun_km"] * M / r_c
+    v0 = s["v0_kms"] / c["c_kms"]
+    w = s["m_a_eV"] * math.sqrt(1 + v0 ** 2)
+    bmax = r_c * math.sqrt(w * w / A - s["m_a_eV"] ** 2) / w
+    D = 1e6
+    t = W.tol(r_max_km=2 * D, rtol=1e-13, atol=1e-16)
+    xg, wq = np.polynomial.legendre.leggauss(24)
+    phi = 0.25 * math.pi * (xg + 1)
+    bt = bmax * np.sin(phi)
+    z = np.zeros_like(bt)
+
+    def impact(ev):
+        e = ev.cpu().numpy()
+        return np.linalg.norm(np.cross(e[0, 0:3, :].T, e[0, 4:7, :].T), axis=1)
+
+    ev, nev, fin, ifin = rt.rt_trace_backward_rays(s, t, D, 1.0, 0.3, bt, z, K=4)
+    assert np.all(nev.cpu().numpy() == 2)
+    bn = bt / (impact(ev) / bt)
+    ev, nev, fin, ifin = rt.rt_trace_backward_rays(s, t, D, 1.0, 0.3, bn, z, K=4)
+    assert np.all(nev.cpu().numpy() == 2) and np.all(ifin.cpu().numpy()[2] == W.STATUS_ESCAPED)
+    area = 0.25 * math.pi * wq * 2 * math.pi * bt * bmax * np.cos(phi)
+    wsum, total = rt.rt_backward_power(s, ev, nev, area=area)
+    P_bwd = 4 * math.pi * total.item()
+    assert abs(P_bwd / P_fwd - 1) < 1e-6, (P_bwd, P_fwd)
+
+
+def test_backward_power_image_is_deterministic_and_errors(rt):
+    import torch
+    s, tol = W.CFG3["star"], W.CFG3["tol"]
+    image = dict(D_km=1e5, incl=1.0, phi_o=0.0, half_width_km=40.0, nx=64, ny=64)
+    print("power determinism and errors", flush=True)
+    ev, nev, fin, ifin = rt.rt_trace_backward(s, tol, image, K=8)
+    area = (2 * image["half_width_km"] / image["nx"]) ** 2
+    w1, t1 = rt.rt_backward_power(s, ev, nev, pixel_area_km2=area)
+    w2, t2 = rt.rt_backward_power(s, ev, nev, pixel_area_km2=area)
+    assert torch.equal(w1, w2) and torch.equal(t1, t2)
+    assert t1.item() > 0
+    # a per-ray area equal to the pixel area gives the same total
+    _, t3 = rt.rt_backward_power(s, ev, nev, area=np.full(image["nx"] * image["ny"], area))
+    assert abs(t3.item() / t1.item() - 1) < 1e-14
+    # no stored events: nothing
+    w0, t0 = rt.rt_backward_power(s, ev[:0].contiguous(), nev, pixel_area_km2=area)
+    assert float(w0.abs().max()) == 0.0 and t0.item() == 0.0
+    # a cutoff below every conversion length removes everything
+    wc, tc = rt.rt_backward_power(s, ev, nev, Lc_max_km=1e-12, pixel_area_km2=area)
+    assert tc.item() == 0.0
+    with pytest.raises(rt.RtError, match="invalid pixel area"):
+        rt.rt_backward_power(s, ev, nev, pixel_area_km2=-1.0)
+    with pytest.raises(rt.RtError, match="non-finite"):
+        rt.rt_backward_power(s, ev, nev, Lc_max_km=float("nan"), pixel_area_km2=area)
+    with pytest.raises(rt.RtError, match="invalid image plane"):
+        rt.rt_trace_backward_rays(s, tol, float("inf"), 1.0, 0.0, [0.0], [0.0])
+    # no rays
+    e0, n0, f0, i0 = rt.rt_trace_backward_rays(s, tol, 1e5, 1.0, 0.0, np.zeros(0), np.zeros(0))
+    assert n0.numel() == 0

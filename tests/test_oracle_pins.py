@@ -292,7 +292,10 @@ def test_foliation_width_below_ten_percent(orc):
 def test_zero_variance_spherical_weights(orc, M):
     """Spherical profile w_p^2 ~ r^-3 with constant |B_perp|: every weight equals the closed
     form of Sec. 4 (the analytic spherical-surface result the paper checks both tracers
-    against), here C_k n_c r_c^2 pi g^2 B^2 E^2 / |d w_p^2/dr|."""
+    against), here C_k n_c sqrt(A) r_c^2 pi g^2 B^2 E^2 / |d w_p^2/dr|: the local power
+    4 pi r_c^2 n_c pi g^2 B^2 E^2 / |d w_p^2/dl| (proper gradient d/dl = sqrt(A) d/dr)
+    times A, one sqrt(A) for the energy each photon loses climbing out and one for the
+    rate in the time at infinity."""
     s = W.star(M_Msun=M, plasma=W.PLASMA_ISO, density=W.DENSITY_SPHERICAL, weights=W.WEIGHTS_CONST_B,
                kdir=W.KDIR_ISOTROPIC, B_test_G=1e12)
     c = orc.constants()
@@ -318,7 +321,7 @@ def test_zero_variance_spherical_weights(orc, M):
     dwp2dr = 3 * ma2 / rc * hc  # |d w_p^2 / dr| in eV^3 (r in eV^-1)
     g = 1e-12 * 1e-9
     B = 1e12 * c["gauss_eV2"]
-    closed = 4 * math.pi * n_c * (rc / hc) ** 2 * math.pi * g ** 2 * B ** 2 * E ** 2 / dwp2dr
+    closed = 4 * math.pi * n_c * math.sqrt(A) * (rc / hc) ** 2 * math.pi * g ** 2 * B ** 2 * E ** 2 / dwp2dr
     assert abs(w.mean() / closed - 1) < 1e-12
     if M == 0.0:
         # radiated power of a spherical conversion surface in the standard 1-D resonant picture:
@@ -567,6 +570,164 @@ def test_backward_events_on_spherical_resonance(orc):
             assert ev[e, 8, q] == 0.0
         if ifin[2, q] == W.STATUS_ESCAPED:
             assert nev[q] == 2
+
+
+# ---------------------------------------------------------------- backward power
+def _spherical_star(M):
+    return W.star(M_Msun=M, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO, weights=W.WEIGHTS_CONST_B,
+                  kdir=W.KDIR_ISOTROPIC, B_test_G=1e12, m_a_eV=1e-5)
+
+
+def _spherical_geometry(orc, s):
+    c = orc.constants()
+    M = s["M_Msun"]
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    ma = s["m_a_eV"]
+    rc = 10.0 * (c["wp2_per_ne"] * n0 / ma ** 2) ** (1 / 3)
+    A = 1 - 2 * c["GMsun_km"] * M / rc
+    v0 = s["v0_kms"] / c["c_kms"]
+    w = ma * math.sqrt(1 + v0 ** 2)
+    ka = math.sqrt(w * w / A - ma * ma)  # local |k| on the resonance [eV]
+    return dict(c=c, rc=rc, A=A, w=w, ka=ka, ma=ma, v0=v0, bmax=rc * ka / w)
+
+
+@pytest.mark.parametrize("M", [1.4, 0.5])
+def test_forward_equals_backward_total_power(orc, M):
+    """Sec. 2.4: for an isotropic plasma and a spherical conversion surface the forward
+    power (Sec. 2.2 eq. (Power) with the curved measure of Sec. 4.2) and the backward image
+    sum (Sec. 2.1 eq. (BackPower)) agree, in Schwarzschild too.  The forward side is the
+    mean seed weight; the backward side is 4 pi dP/dOmega (the emission is isotropic),
+    with the image integral over the impact parameter done by Gauss-Legendre in
+    b = b_max sin(phi), which removes the 1/k_r edge of the disc.  b is the conserved
+    |x cross k| of each ray (the impact parameter at infinity); a pilot pass maps the
+    quadrature nodes to launch offsets.  Both sides are computed independently: seeding
+    with the surface measure versus tracing from the image plane with the event weights."""
+    s = _spherical_star(M)
+    G = _spherical_geometry(orc, s)
+    rays, st = orc.sample(s, 0, 16)
+    assert np.all(st == 0)
+    P_forward = rays[8].mean()
+    D = 1e6
+    t = W.tol(r_max_km=2 * D, rtol=1e-13, atol=1e-16)
+    xg, wg = np.polynomial.legendre.leggauss(24)
+    phi = 0.25 * math.pi * (xg + 1)
+    bt = G["bmax"] * np.sin(phi)
+
+    def impact(ev):
+        return np.linalg.norm(np.cross(ev[0, 0:3, :].T, ev[0, 4:7, :].T), axis=1)
+
+    _, ev, nev, _, _ = orc.backward_rays(s, t, D, 1.0, 0.3, bt, np.zeros_like(bt), K=8)
+    assert np.all(nev == 2)
+    bn = bt / (impact(ev) / bt)
+    wsum, ev, nev, fin, ifin = orc.backward_rays(s, t, D, 1.0, 0.3, bn, np.zeros_like(bt), K=8)
+    assert np.all(nev == 2) and np.all(ifin[2] == W.STATUS_ESCAPED)
+    assert np.allclose(impact(ev), bt, rtol=1e-8, atol=0)
+    hc = G["c"]["hbarc_eVkm"]
+    dPdOmega = 0.25 * math.pi * np.sum(wg * 2 * math.pi * bt * wsum * G["bmax"] * np.cos(phi)) / hc ** 2
+    P_backward = 4 * math.pi * dPdOmega
+    assert abs(P_backward / P_forward - 1) < 1e-6, (P_backward, P_forward)
+
+
+def test_spherical_event_weight_and_conversion_length(orc):
+    """Each production event of the spherical isotropic star against its closed form: with
+    k_r = sqrt(k_a^2 - (b w / r_c)^2) (b the ray's conserved impact parameter), the
+    probability is P = pi g^2 B^2 E^2 / (sqrt(A) k_r |d w_p^2/dr|), the weight
+    w^3 sqrt(A) P v_a n_c / (4 pi k_a^2), and the conversion length
+    sqrt(2 pi v_a / |khat.dE|) with khat.dE = sqrt(A) (k_r/k_a) |d w_p^2/dr| / (2E).
+    Events whose length exceeds the cutoff contribute nothing."""
+    s = _spherical_star(1.4)
+    G = _spherical_geometry(orc, s)
+    c = G["c"]
+    hc = c["hbarc_eVkm"]
+    rc, A, w, ka, ma = G["rc"], G["A"], G["w"], G["ka"], G["ma"]
+    b = np.array([0.05, 0.3, 0.6, 0.9, 0.98]) * G["bmax"]
+    t = W.tol(r_max_km=2e6, rtol=1e-12, atol=1e-15)
+    wsum, ev, nev, fin, ifin = orc.backward_rays(s, t, 1e6, 0.4, 1.1, b, np.zeros_like(b), K=8)
+    E = w / math.sqrt(A)
+    n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+    n_c = n_inf * ka / (ma * G["v0"])
+    dwp2dr = 3 * ma ** 2 / rc  # eV^2 / km
+    g = s["g_agg_GeV"] * 1e-9
+    B = s["B_test_G"] * c["gauss_eV2"]
+    lcs = []
+    for q in range(len(b)):
+        assert nev[q] == 2
+        tot = 0.0
+        for e in range(2):
+            y = ev[e, :8, q]
+            L = np.linalg.norm(np.cross(y[:3], y[4:7]))
+            kr = math.sqrt(ka ** 2 - (L * w / rc) ** 2)
+            P = math.pi * g ** 2 * B ** 2 * E ** 2 / (math.sqrt(A) * kr * dwp2dr * hc)
+            expect = w ** 3 * math.sqrt(A) * P * (ka / E) * n_c / (4 * math.pi * ka ** 2)
+            wt, lc = orc.event_weight(s, y)
+            assert abs(wt / expect - 1) < 1e-8, (q, e, wt, expect)
+            khdE = math.sqrt(A) * (kr / ka) * dwp2dr / (2 * E)
+            assert abs(lc / math.sqrt(2 * math.pi * (ka / E) * hc / khdE) - 1) < 1e-8
+            lcs.append(lc)
+            tot += wt
+        assert abs(wsum[q] / tot - 1) < 1e-14
+    # the length grows toward the grazing edge of the disc; a cutoff between removes the edge
+    assert lcs[-1] > lcs[0]
+    cut = 0.5 * (lcs[0] + lcs[-1])
+    wcut, *_ = orc.backward_rays(s, t, 1e6, 0.4, 1.1, b, np.zeros_like(b), K=8, Lc_max_km=cut)
+    keep = np.array(lcs).reshape(-1, 2) <= cut
+    for q in range(len(b)):
+        if keep[q].all():
+            assert wcut[q] == wsum[q]
+        elif not keep[q].any():
+            assert wcut[q] == 0.0
+    assert (wcut == 0).any() and (wcut > 0).any()
+
+
+def test_curved_anisotropic_event_weight_from_printed_probability(orc):
+    """Events of the magnetar-density backward workload (M = 1.4, rotating, LO plasma):
+    the weight equals the printed pieces multiplied out with a finite-difference gradient,
+    eq. (CPAnisoCurved) P = (pi/2) g^2 |B_perp|^2 E^5 / (D |k.dE|) with
+    D = cos^2 w_p^2 (w_p^2 - 2E^2) + E^4 and k.dE = k^a d_a E (contravariant k, E the LO
+    energy of eq. (AnisotropicDisp) at fixed covariant k), times w^3 sqrt(A) v_a n_c /
+    (4 pi k^2).  E is the event's own local frequency (the rotating plasma shifts k_t)."""
+    s = W.CFG3["star"]
+    c = orc.constants()
+    t = W.tol(r_max_km=1e5, rtol=1e-10, atol=1e-14)
+    rng = np.random.default_rng(5)
+    b1, b2 = rng.uniform(-30, 30, 48), rng.uniform(-30, 30, 48)
+    wsum, ev, nev, fin, ifin = orc.backward_rays(s, t, 1e5, 1.0, 0.0, b1, b2, K=8)
+    hc, G2 = c["hbarc_eVkm"], c["gauss_eV2"]
+    v0 = s["v0_kms"] / c["c_kms"]
+    ma = s["m_a_eV"]
+    w = ma * math.sqrt(1 + v0 ** 2)
+    g = s["g_agg_GeV"] * 1e-9
+    rs = 2 * c["GMsun_km"] * s["M_Msun"]
+    n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+    checked = 0
+    for q in np.nonzero(nev)[0]:
+        tot = 0.0
+        for e in range(min(nev[q], 8)):
+            y = ev[e, :8, q]
+            x, tt, k = y[:3], y[3], y[4:7]
+            r = np.linalg.norm(x)
+            nh = x / r
+            A = 1 - rs / r
+            ko = k - (nh @ k) * nh + math.sqrt(A) * (nh @ k) * nh  # static orthonormal frame
+            E = -y[7] * w / math.sqrt(A)
+            kmag = np.linalg.norm(ko) * w
+            h = 1e-5 * r
+            gE = np.array([(orc.energy(s, x + h * d, tt, k) - orc.energy(s, x - h * d, tt, k)) / (2 * h)
+                           for d in np.eye(3)])
+            kdE = abs((orc.inverse_metric(s, x) @ k) @ gE) * w * w * hc  # eV^3
+            B = orc.bfield(s, x, tt)
+            cb = ko @ B / np.linalg.norm(ko) / np.linalg.norm(B)
+            wp2 = orc.wp2(s, x, tt) * w * w
+            Dd = cb ** 2 * wp2 * (wp2 - 2 * E ** 2) + E ** 4
+            P = 0.5 * math.pi * g ** 2 * (B @ B) * G2 ** 2 * (1 - cb ** 2) * E ** 5 / (Dd * kdE)
+            n_c = n_inf * kmag / (ma * v0)
+            expect = w ** 3 * math.sqrt(A) * P * (kmag / E) * n_c / (4 * math.pi * kmag ** 2)
+            wt, _ = orc.event_weight(s, y)
+            assert abs(wt / expect - 1) < 1e-7, (q, e, wt, expect)
+            tot += wt
+            checked += 1
+        assert abs(wsum[q] / tot - 1) < 1e-14
+    assert checked >= 20
 
 
 # ---------------------------------------------------------------- smoothed flux and its derivative
