@@ -190,11 +190,76 @@ def bench_backward(args, rt, W, np, torch):
     flops = (acc + rej) * ft["attempt"] + acc * 4 * ft["event_probe"] + float(nv.sum()) * 60 * ft["event_probe"]
     tf = flops / (kernel_ms * 1e-3) / 1e12
     st = {str(k): int(v) for k, v in zip(*np.unique(inf[2], return_counts=True))}
-    return dict(workload=cfg["name"], pixels=n, events=int(nv.sum()), rays_with_events=int((nv > 0).sum()),
-                statuses=st, accepted_steps=acc, rejected_steps=rej, ms_per_image=ms_call, kernel_ms=kernel_ms,
-                rays_per_s=n / (ms_call * 1e-3), ray_steps_per_s=acc / (ms_call * 1e-3), kernel_tflops=tf,
-                kernel_frac=tf / FP64_VECTOR_PEAK_TFLOPS, flop_per_attempt=ft["attempt"],
-                flop_per_event_probe=ft["event_probe"])
+    out = dict(workload=cfg["name"], pixels=n, events=int(nv.sum()), rays_with_events=int((nv > 0).sum()),
+               statuses=st, accepted_steps=acc, rejected_steps=rej, ms_per_image=ms_call, kernel_ms=kernel_ms,
+               rays_per_s=n / (ms_call * 1e-3), ray_steps_per_s=acc / (ms_call * 1e-3), kernel_tflops=tf,
+               kernel_frac=tf / FP64_VECTOR_PEAK_TFLOPS, flop_per_attempt=ft["attempt"],
+               flop_per_event_probe=ft["event_probe"])
+    out["power"] = bench_backward_power(args, rt, W, np, torch, cfg, ev, nev)
+    return out
+
+
+def bench_backward_power(args, rt, W, np, torch, cfg, ev, nev):
+    """rt_backward_power over the image's recorded events: dP/dOmega of the image (1 km
+    conversion-length cutoff, as in the paper) and the event-weight kernel's time against
+    its algorithmic bytes: per pixel the event count (4 B) and the weight sum (8 B), per
+    stored event its 8 state doubles (64 B)."""
+    image, K = cfg["image"], cfg["K"]
+    n = image["nx"] * image["ny"]
+    area = (2 * image["half_width_km"] / image["nx"]) ** 2
+    ws = rt.workspace(rt.OP_BACKWARD_POWER, n)
+    rt.rt_backward_power(cfg["star"], ev, nev, 1.0, pixel_area_km2=area, ws=ws)
+    torch.cuda.synchronize()
+    reps = max(3, min(args.steps, 10))
+    rt.timing(True)
+    for _ in range(reps):
+        wsum, total = rt.rt_backward_power(cfg["star"], ev, nev, 1.0, pixel_area_km2=area, ws=ws)
+    torch.cuda.synchronize()
+    rt.timing(False)
+    kt = [ms for name, ms in rt.kernel_times() if name == "event_power_kernel"]
+    kernel_ms = float(np.mean(kt))
+    stored = float(torch.clamp(nev.to(torch.int64), max=K).sum().item())
+    nbytes = n * (4 + 8) + stored * 64
+    _, total_nocut = rt.rt_backward_power(cfg["star"], ev, nev, 0.0, pixel_area_km2=area, ws=ws)
+    return dict(dP_dOmega_eV2=total.item(), dP_dOmega_no_cutoff_eV2=total_nocut.item(), Lc_max_km=1.0,
+                kernel_ms=kernel_ms, stored_events=stored, algorithmic_bytes=nbytes,
+                achieved_GBps=nbytes / (kernel_ms * 1e-3) / 1e9,
+                hbm_frac=nbytes / (kernel_ms * 1e-3) / 8e12)
+
+
+def forward_vs_backward_total(rt, W, np, torch, n_mu=24, n_phi=8, npx=1024, half_width=70.0):
+    """Total power of the magnetar workload star two ways (Sec. 2.4 reports agreement within
+    a few percent): forward, the escaped seed weight over N = 2e6 seeds; backward, the image
+    sum dP/dOmega over n_mu Gauss-Legendre polar nodes x n_phi azimuths of npx^2 pixels at
+    1e5 km, integrated over the sky (the rotating star's total is time independent)."""
+    star = W.CFG3["star"]
+    tol = W.tol(r_max_km=1e5)
+    N = 2_000_000
+    print("bench: forward vs backward total power", file=sys.stderr, flush=True)
+    t0 = time.time()
+    rays, st = rt.rt_sample_resonance(star, 7, N)
+    fin, ifin = rt.rt_trace_forward(star, tol, rays, st)
+    esc = ifin[2] == 1
+    P_fwd = rays[8][esc].sum().item() / N
+    xg, wg = np.polynomial.legendre.leggauss(n_mu)
+    image = dict(D_km=1e5, half_width_km=half_width, nx=npx, ny=npx)
+    area = (2 * half_width / npx) ** 2
+    ws = rt.workspace(rt.OP_TRACE_BACKWARD, npx * npx)
+    wsp = rt.workspace(rt.OP_BACKWARD_POWER, npx * npx)
+    acc = {0.0: 0.0, 1.0: 0.0, 2.0: 0.0}
+    for a in range(n_mu):
+        for b in range(n_phi):
+            image["incl"] = math.acos(xg[a])
+            image["phi_o"] = 2 * math.pi * (b + 0.5) / n_phi
+            ev, nev, _, _ = rt.rt_trace_backward(star, tol, image, K=8, ws=ws)
+            for Lc in acc:
+                _, tot = rt.rt_backward_power(star, ev, nev, Lc, pixel_area_km2=area, ws=wsp)
+                acc[Lc] += tot.item() * wg[a] * 2 * math.pi / n_phi
+    return dict(workload=f"{W.CFG3['name']} star, {n_mu}x{n_phi} directions x {npx}^2 pixels, {N} forward seeds",
+                P_forward_eV2=P_fwd, P_backward_eV2={f"Lc_max_{k:g}km" if k else "no_cutoff": v
+                                                     for k, v in acc.items()},
+                ratio={f"Lc_max_{k:g}km" if k else "no_cutoff": v / P_fwd for k, v in acc.items()},
+                seconds=time.time() - t0)
 
 
 def bench_adjoint(args, rt, W, np, torch):
@@ -254,9 +319,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward",
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,fbtotal",
                     help="comma list of forms to time beside plain (the headline value): batched, adjoint, "
-                         "backward")
+                         "backward, fbtotal (forward against backward total power of the magnetar star)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the plain form's schedule too (default: the library's default schedule)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
@@ -380,6 +445,8 @@ def main():
         out["forms"]["adjoint"] = bench_adjoint(args, rt, W, np, torch)
     if "backward" in forms:
         out["forms"]["backward"] = bench_backward(args, rt, W, np, torch)
+    if "fbtotal" in forms:
+        out["forms"]["forward_vs_backward"] = forward_vs_backward_total(rt, W, np, torch)
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
         print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)

@@ -258,14 +258,14 @@ size_t rt_workspace_size(int32_t op, int64_t n);
 
 /* Kernel timing.  rt_timing(1) starts recording (and forgets earlier records): every
  * later launch of a persistent tracing kernel (trace_fwd_kernel of rt_trace_forward or
- * rt_trace_batched, trace_bwd_kernel of rt_trace_backward, the forward and reverse
- * kernels of rt_flux_grad) is bracketed by a HIP event pair recorded on the caller's
+ * rt_trace_batched, trace_bwd_kernel of rt_trace_backward(_rays), the forward and reverse
+ * kernels of rt_flux_grad) and of the event-weight kernel of rt_backward_power is bracketed by a HIP event pair recorded on the caller's
  * stream, up to 1024 launches; rt_timing(0) stops recording.  rt_kernel_times waits
  * for the recorded launches and writes up to max durations [ms] and kernel kinds
  * (RT_KERNEL_*) in launch order; returns the count.  Recording is process-wide and not
  * thread-safe, and must be off while a stream is being captured into a graph. */
 enum { RT_KERNEL_TRACE_FORWARD = 1, RT_KERNEL_TRACE_BATCHED = 2, RT_KERNEL_TRACE_BACKWARD = 3,
-       RT_KERNEL_ADJOINT_FORWARD = 4, RT_KERNEL_ADJOINT_REVERSE = 5 };
+       RT_KERNEL_ADJOINT_FORWARD = 4, RT_KERNEL_ADJOINT_REVERSE = 5, RT_KERNEL_EVENT_POWER = 6 };
 int rt_timing(int32_t on);
 int32_t rt_kernel_times(double* ms, int32_t* kind, int32_t max);
 

@@ -24,7 +24,7 @@ EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_b
            "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
            "rt_workspace_size", "rt_timing", "rt_kernel_times", "rt_last_error", "rt_version"]
 KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace_bwd_kernel", 4: "adj_fwd_kernel",
-                5: "adj_rev_kernel"}
+                5: "adj_rev_kernel", 6: "event_power_kernel"}
 
 
 class RtStar(C.Structure):

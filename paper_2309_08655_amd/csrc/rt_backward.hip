@@ -426,8 +426,10 @@ extern "C" int rt_backward_power(const rt_star* star, const double* ev, const in
         (int)std::min<int64_t>(POWER_MAX_BLOCKS, std::max<int64_t>(1, (n + POWER_BLOCK - 1) / POWER_BLOCK));
     double* partial = total ? (double*)ws : nullptr;  // block partials of the image sum
     if (n == 0 && !total) return RT_OK;
+    timing_begin(st, RT_KERNEL_EVENT_POWER);
     hipLaunchKernelGGL(event_power_kernel, dim3(nb), dim3(POWER_BLOCK), 0, st, I, C, ev, nev, n, K, Lc_max_km, area,
                        pixel_area_km2, wsum, partial);
+    timing_end(st);
     int rc = check_launch("event_power_kernel");
     if (rc || !total) return rc;
     hipLaunchKernelGGL(power_total_kernel, dim3(1), dim3(POWER_MAX_BLOCKS), 0, st, (const double*)partial, nb,
