@@ -262,6 +262,41 @@ def forward_vs_backward_total(rt, W, np, torch, n_mu=24, n_phi=8, npx=1024, half
                 seconds=time.time() - t0)
 
 
+def bench_maxwell(args, rt, W, np, torch):
+    """The plain step on the full forward workload with Maxwellian axion momenta at infinity
+    (Sec. 4.3 eq. (GaussianDist)) beside the monochromatic one: time per step, total escaped
+    power and the spread of the photons' energies at infinity (the line width)."""
+    cfg = W.CFG2
+    n = cfg["n"]
+    out = {}
+    for label, speeds in (("monochromatic", W.SPEEDS_MONO), ("maxwellian", W.SPEEDS_MAXWELL)):
+        star = dict(cfg["star"], speeds=speeds)
+        print(f"bench: maxwell form, {label}", file=sys.stderr, flush=True)
+        ws = rt.workspace(rt.OP_TRACE_FORWARD, n)
+        rays, st = rt.rt_sample_resonance(star, cfg["seed"], n)
+        fin, ifin = rt.rt_trace_forward(star, cfg["tol"], rays, st, ws=ws)
+        torch.cuda.synchronize()
+        reps = max(2, min(args.steps, 5))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(torch.cuda.current_stream())
+        for _ in range(reps):
+            rays, st = rt.rt_sample_resonance(star, cfg["seed"], n)
+            fin, ifin = rt.rt_trace_forward(star, cfg["tol"], rays, st, ws=ws)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        esc = ifin[2] == 1
+        om = fin[11][esc]
+        wt = rays[8][esc]
+        mean = float((om * wt).sum() / wt.sum())
+        sd = float(torch.sqrt(((om - mean) ** 2 * wt).sum() / wt.sum()))
+        out[label] = dict(ms_per_step=e0.elapsed_time(e1) / reps,
+                          ray_steps_per_s=float(ifin[0].double().sum()) / (e0.elapsed_time(e1) / reps * 1e-3),
+                          escaped_power_eV2=float(wt.sum()) / n, omega_mean=mean, omega_sd=sd)
+    out["power_ratio"] = out["maxwellian"]["escaped_power_eV2"] / out["monochromatic"]["escaped_power_eV2"]
+    out["workload"] = cfg["name"] + " with Maxwellian |k_inf| (dispersion k0 = m_a v0)"
+    return out
+
+
 def bench_adjoint(args, rt, W, np, torch):
     """Smoothed flux at 32 observers and its gradient with respect to the six star parameters
     (config-1 star, 1e6 rays, checkpoint every 64 accepted steps): forward phase (trace with
@@ -319,9 +354,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,fbtotal",
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,fbtotal",
                     help="comma list of forms to time beside plain (the headline value): batched, adjoint, "
-                         "backward, fbtotal (forward against backward total power of the magnetar star)")
+                         "backward, maxwell (Maxwellian axion speeds), fbtotal (forward against backward "
+                         "total power of the magnetar star)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the plain form's schedule too (default: the library's default schedule)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
@@ -445,6 +481,8 @@ def main():
         out["forms"]["adjoint"] = bench_adjoint(args, rt, W, np, torch)
     if "backward" in forms:
         out["forms"]["backward"] = bench_backward(args, rt, W, np, torch)
+    if "maxwell" in forms:
+        out["forms"]["maxwell"] = bench_maxwell(args, rt, W, np, torch)
     if "fbtotal" in forms:
         out["forms"]["forward_vs_backward"] = forward_vs_backward_total(rt, W, np, torch)
     if not args.no_cpu:

@@ -44,6 +44,7 @@ enum { RT_DENSITY_GJ = 0, RT_DENSITY_MAGNETAR = 1,              /* eqs. (GJDensi
        RT_DENSITY_SPHERICAL = 2, RT_DENSITY_NONE = 3 };         /* test profiles */
 enum { RT_WEIGHTS_UNIT = 0, RT_WEIGHTS_CONVERSION = 1, RT_WEIGHTS_CONST_B = 2 };
 enum { RT_KDIR_ISOTROPIC = 0, RT_KDIR_OUTWARD = 1 };
+enum { RT_SPEEDS_MONO = 0, RT_SPEEDS_MAXWELL = 1 };
 
 /* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
 typedef struct rt_star {
@@ -63,6 +64,8 @@ typedef struct rt_star {
     int32_t density;      /* RT_DENSITY_* */
     int32_t weights;      /* RT_WEIGHTS_* */
     int32_t kdir;         /* RT_KDIR_*: axion directions isotropic or in the outward hemisphere */
+    int32_t speeds;       /* RT_SPEEDS_*: axion momentum at infinity k0 = m_a v0 (Sec. 4.3 eq.
+                             (fa_approx)) or Maxwellian with dispersion k0 (eq. (GaussianDist)) */
 } rt_star;
 
 /* Integrator tolerances: embedded DOPRI5 error test with scale atol + rtol max(|y|,|y_new|)
@@ -116,8 +119,12 @@ enum { RT_OP_TRACE_FORWARD = 1, RT_OP_TRACE_BACKWARD = 2, RT_OP_BIN = 3, RT_OP_B
  *  (CPAnisoCurved)).
  * Ray i (global index first + j) draws Philox4x32-10 uniforms with key = seed and counter
  * (i, instance, block); emission direction uniform in (cos theta, phi), axion direction
- * isotropic (or outward hemisphere), emission time uniform over one period.  The photon
- * takes the axion's 4-momentum where the kinematic matching k^a = k^gamma holds.
+ * isotropic (or outward hemisphere), emission time uniform over one period; with
+ * RT_SPEEDS_MAXWELL the sixth uniform gives |k_inf| by inverting the Maxwellian's
+ * distribution function (Sec. 4.3 eq. (GaussianDist)), the ray's energy at infinity is
+ * sqrt(m_a^2 + k_inf^2) (k_t = -that / (m_a sqrt(1 + v0^2))) and its focused density
+ * n_inf |k_a| / k_inf.  The photon takes the axion's 4-momentum where the kinematic
+ * matching k^a = k^gamma holds.
  * Output rays "[10][n]": x, y, z, t, k_x, k_y, k_z, k_t, w, r_c; status[n] = RT_ST_OK or
  * RT_ST_NO_RESONANCE (then w = 0).  The unbiased power estimate is (1/n) sum w [eV^2].
  * Errors: RT_EINVAL for n < 0, null arrays or non-finite / out-of-range parameters. */
@@ -176,7 +183,8 @@ int rt_trace_backward_rays(const rt_star* star, const rt_tol* tol, double D_km, 
  * [eV^4] per unit image area.  Events whose conversion length sqrt(2 pi v_a/|khat.dE|)
  * exceeds Lc_max_km are excluded (the IR cutoff of Sec. 4.4; Lc_max_km <= 0: no cutoff).
  * RT_WEIGHTS_CONST_B replaces |B_perp| by B_test_G; RT_WEIGHTS_UNIT is treated as
- * RT_WEIGHTS_CONVERSION.
+ * RT_WEIGHTS_CONVERSION.  Monochromatic axions only (RT_SPEEDS_MAXWELL: RT_EUNSUPPORTED; its
+ * image would need a frequency integral over traced frequencies).
  * ev "[K][RT_NEV][n]", nev[n]: events of rt_trace_backward(_rays) (device; only the first
  * min(nev, K) events of a ray are stored, so only they count).  area: device [n] image area
  * element of each ray [km^2], or NULL for a uniform pixel_area_km2.

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class Star(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV", "g_agg_GeV",
                                           "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")] + \
-               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir")]
+               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds")]
 
 
 class Tol(C.Structure):
@@ -81,6 +81,8 @@ def lib():
         L.orc_backward_rays.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, dp, dp, C.c_int64, C.c_int32,
                                         C.c_double, dp, dp, ip, dp, ip, C.c_int]
         L.orc_event_weight.argtypes = [sp, dp, C.c_double, dp, dp]
+        L.orc_maxwell_x.argtypes = [C.c_double]
+        L.orc_maxwell_x.restype = C.c_double
         L.orc_dopri_test.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.c_double, dp]
         L.orc_flux_fwdmode.argtypes = [sp, tp, C.c_uint64, C.c_int64, dp, C.c_int32, C.c_double, dp, dp, dp, dp, ip,
@@ -254,6 +256,11 @@ def backward_rays(s, t, D_km, incl, phi_o, b1, b2, K=8, Lc_max_km=0.0, nthreads=
     lib().orc_backward_rays(C.byref(make_star(s)), C.byref(make_tol(t)), D_km, incl, phi_o, _dp(b1), _dp(b2), n, K,
                             Lc_max_km, _dp(wsum), _dp(ev), _ip(nev), _dp(fin), _ip(ifin), nthreads)
     return wsum, ev, nev, fin, ifin
+
+
+def maxwell_x(u):
+    """(|k_inf|/k0)^2 at quantile u of the Maxwellian momentum distribution."""
+    return lib().orc_maxwell_x(float(u))
 
 
 def event_weight(s, y, Lc_max_km=0.0):

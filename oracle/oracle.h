@@ -37,6 +37,7 @@ typedef struct {
     int32_t density;      /* 0 Goldreich-Julian, 1 magnetar, 2 spherical test, 3 none */
     int32_t weights;      /* 0 unit, 1 conversion, 2 conversion with constant |B_perp| */
     int32_t kdir;         /* 0 isotropic axion directions, 1 outward hemisphere */
+    int32_t speeds;       /* 0 every axion at |k_inf| = m_a v0; 1 Maxwellian |k_inf|, dispersion k0 = m_a v0 */
 } orc_star;
 
 typedef struct {
@@ -95,6 +96,8 @@ int orc_trace_backward(const orc_star* s, const orc_tol* tol, double D_km, doubl
 int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double incl, double phi_o,
                       const double* b1, const double* b2, int64_t n, int32_t K, double Lc_max_km, double* wsum,
                       double* ev, int32_t* nev, double* fin, int32_t* ifin, int nthreads);
+/* x = (|k_inf|/k0)^2 at quantile u of the Maxwellian of Sec. 4.3 eq. (GaussianDist) */
+double orc_maxwell_x(double u);
 /* the weight of one production event at state y[8] (and its conversion length [km]) */
 int orc_event_weight(const orc_star* s, const double* y, double Lc_max_km, double* w, double* Lc);
 

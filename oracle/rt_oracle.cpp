@@ -69,6 +69,7 @@ static double wp2_per_ne() { return 4.0 * PI * ALPHA * HBARC_EVCM * HBARC_EVCM *
 enum { PL_ISO = 0, PL_ANISO = 1 };
 enum { DEN_GJ = 0, DEN_MAG = 1, DEN_SPH = 2, DEN_NONE = 3 };
 enum { W_UNIT = 0, W_CONV = 1, W_CONV_CONSTB = 2 };
+enum { SP_MONO = 0, SP_MAXWELL = 1 };
 enum { KD_ISO = 0, KD_OUT = 1 };
 
 // ---------------------------------------------------------------------------
@@ -112,6 +113,45 @@ static void ray_uniforms(uint64_t seed, int32_t instance, int64_t i, double u[6]
 }
 
 // ---------------------------------------------------------------------------
+// Maxwellian momenta at infinity, eq. (GaussianDist): f ~ exp(-k^2/k0^2), so x = (k/k0)^2
+// has the Gamma(3/2) distribution (density x^{1/2} e^{-x} / Gamma(3/2)), with distribution
+// function G(x) = P(3/2, x), the regularised lower incomplete gamma function:
+//   G(x)     = x^{3/2} e^{-x} / Gamma(5/2) sum_{j>=0} x^j / ((5/2)(7/2)...(3/2 + j))
+//              (the power series, every term positive),
+//   1 - G(x) = erfc(sqrt x) + (2/sqrt pi) sqrt(x) e^{-x}.
+// x is the root of G(x) = u (u < 1/2, by the series) or of 1 - G(x) = 1 - u (u >= 1/2, where
+// the complement keeps its digits), found by bisection on [0, 100].
+// ---------------------------------------------------------------------------
+static double gamma32_lower(double x) {
+    double term = 1.0, sum = 1.0;
+    for (int j = 1; j < 200; ++j) {
+        term *= x / (1.5 + j);
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return std::pow(x, 1.5) * std::exp(-x) / (0.75 * std::sqrt(PI)) * sum;
+}
+
+static double maxwell_x(double u) {
+    const double c = 2.0 / std::sqrt(PI);
+    const bool upper = u >= 0.5;
+    const double target = upper ? 1.0 - u : u;
+    auto f = [&](double x) {
+        const double s = std::sqrt(x);
+        return upper ? std::erfc(s) + c * s * std::exp(-x) : gamma32_lower(x);
+    };
+    double lo = 0.0, hi = 100.0;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        // G increases with x; 1 - G decreases
+        const bool below = upper ? (f(mid) > target) : (f(mid) < target);
+        if (below) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
 // Star instance.  The six differentiable parameters (B0, P, theta_m, M, R, m_a)
 // are of type P (double, or a dual number for forward-mode derivatives).
 // ---------------------------------------------------------------------------
@@ -124,13 +164,14 @@ struct Inst {
     P B0;      // polar surface field [G]
     P Cwp;     // w_p^2 / w_inf^2 = Cwp * (density shape)
     P ma2;     // (m_a / w_inf)^2
+    double kv2;  // (k0 / w_inf)^2 = v0^2 / (1 + v0^2) = 1 - ma2, formed without cancellation
     P w_inf;   // axion energy at infinity [eV]
     P n_inf;   // axion number density at infinity [eV^3]
     P k0;      // axion momentum at infinity [eV]
     P Period;  // [s]
     double g_eV;   // coupling [eV^-1]
     double Btest;  // constant |B_perp| of the zero-variance test [G]
-    int plasma, density, weights, kdir;
+    int plasma, density, weights, kdir, speeds;
 };
 
 template <class P>
@@ -149,6 +190,7 @@ static Inst<P> make_inst(const orc_star& s, const P p[6]) {
     I.w_inf = ma * std::sqrt(1.0 + v0 * v0);  // w_inf^2 = m_a^2 + k0^2 with k0 = m_a v0
     I.k0 = ma * v0;
     I.ma2 = P(1.0 / (1.0 + v0 * v0)) + 0.0 * ma;  // (m_a/w_inf)^2 does not depend on m_a
+    I.kv2 = v0 * v0 / (1.0 + v0 * v0);
     P Cp = wp2_per_ne() / (I.w_inf * I.w_inf);   // [cm^3]
     // Goldreich-Julian: n = 2 Omega.B / e (Heaviside-Lorentz) = Omega B0/(4 pi e c) (R/r)^3 |...| (Gaussian)
     P n0 = Om_s * B0 / (4.0 * PI * E_STATC * C_CMS);
@@ -164,6 +206,7 @@ static Inst<P> make_inst(const orc_star& s, const P p[6]) {
     I.g_eV = s.g_agg_GeV * 1.0e-9;
     I.Btest = s.B_test_G;
     I.plasma = s.plasma; I.density = s.density; I.weights = s.weights; I.kdir = s.kdir;
+    I.speeds = s.speeds;
     return I;
 }
 
@@ -322,16 +365,18 @@ static S energy_t(const Inst<P>& I, const S x[3], const P& t, const K k[3]) {
 // that momentum into the photon dispersion relation (AnisotrpoicDisp) gives
 //   F = w_p^2 (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2 = 0
 // (isotropic plasma: F = w_p^2 - m_a^2).  k-hat is held fixed as a direction in
-// the static orthonormal frame, and the emission time t0 is held fixed.
+// the static orthonormal frame, and the emission time t0 is held fixed.  om2 is
+// the square of the axion's energy at infinity in units of w_inf (1 for the
+// monochromatic distribution).
 // ---------------------------------------------------------------------------
 template <class S, class P>
-static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double khat[3]) {
+static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double khat[3], double om2 = 1.0) {
     S tt = S(0.0) + t0;
     S wp2 = wp2_tilde(I, x, tt);
     if (I.plasma == PL_ISO) return wp2 - I.ma2;
     S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     S A = 1.0 - I.rs / r;
-    S w2 = 1.0 / A;
+    S w2 = om2 / A;
     S ka2 = w2 - I.ma2;
     S B[3];
     bfield_t(I, x, tt, B);
@@ -340,9 +385,10 @@ static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double k
 }
 
 template <class P>
-static P F_on_ray(const Inst<P>& I, const P& r, const double n[3], const P& t0, const double khat[3]) {
+static P F_on_ray(const Inst<P>& I, const P& r, const double n[3], const P& t0, const double khat[3],
+                  double om2) {
     P x[3] = {r * n[0], r * n[1], r * n[2]};
-    return resonance_F(I, x, t0, khat);
+    return resonance_F(I, x, t0, khat, om2);
 }
 
 // Root of F along the radial line through n, above the stellar surface.
@@ -350,10 +396,11 @@ static P F_on_ray(const Inst<P>& I, const P& r, const double n[3], const P& t0, 
 // [R, R 2^j]; for dual parameters a final Newton correction carries the
 // implicit-function derivative dr/dp = -(dF/dp)/(dF/dr).
 template <class P>
-static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, const double khat[3]) {
+static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, const double khat[3],
+                            double om2 = 1.0) {
     double R = val(I.R);
     Inst<double> Id;  // value copy for the bracketing
-    auto Fval = [&](double r) { return val(F_on_ray(I, P(0.0) + r, n, t0, khat)); };
+    auto Fval = [&](double r) { return val(F_on_ray(I, P(0.0) + r, n, t0, khat, om2)); };
     if (!(Fval(R) > 0.0)) return P(-1.0);
     double lo = R, hi = 2.0 * R;
     int j = 0;
@@ -369,7 +416,7 @@ static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, co
         using D1 = Dual<1, P>;
         D1 rd = D1::var(P(0.0) + rc, 0);
         D1 xd[3] = {rd * n[0], rd * n[1], rd * n[2]};
-        D1 Fd = resonance_F(I, xd, t0, khat);
+        D1 Fd = resonance_F(I, xd, t0, khat, om2);
         P corr = Fd.v / Fd.d[0];
         P out = (P(0.0) + rc) - corr;
         out.v = rc;
@@ -437,7 +484,15 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     }
     // emission time uniform over one period [km]
     P t0 = u[4] * I.Period * C_KMS;
-    P rc = resonance_radius_t(I, n, t0, kh);
+    // the axion's momentum at infinity: k0 = m_a v0 for every axion (eq. (fa_approx)), or
+    // drawn from the Maxwellian of eq. (GaussianDist) with the sixth uniform; its energy at
+    // infinity in units of w_inf is om, with om^2 = (1 + x v0^2) / (1 + v0^2), x = (k/k0)^2
+    double x2 = 1.0;
+    if (I.speeds == SP_MAXWELL) x2 = maxwell_x(u[5]);
+    const double ma2v = val(I.ma2);
+    const double om2 = ma2v + x2 * I.kv2;
+    const double om = std::sqrt(om2);
+    P rc = resonance_radius_t(I, n, t0, kh, om2);
     o.rc = rc;
     if (val(rc) < 0.0) {
         for (int d = 0; d < 8; ++d) o.y[d] = P(0.0);
@@ -448,7 +503,9 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     o.status = ORC_OK;
     P A = 1.0 - I.rs / rc;
     P sA = sqrt(A);
-    P ka = sqrt(1.0 / A - I.ma2);  // |k_a| / w_inf in the static frame
+    // |k_a| / w_inf in the static frame: |k_a|^2 = om^2/A - m~^2 = (x kv2 + m~^2 rs/r) / A,
+    // the second form without the cancellation of the first (|k_a| << w_inf far from the star)
+    P ka = sqrt((x2 * I.kv2 + I.ma2 * (I.rs / rc)) / A);
     P x[3] = {rc * n[0], rc * n[1], rc * n[2]};
     // photon momentum = axion momentum: orthonormal |k_a| khat -> Cartesian covariant
     P ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
@@ -457,24 +514,24 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     for (int d = 0; d < 3; ++d) k[d] = (ko[d] - nko * n[d]) + (nko / sA) * n[d];
     for (int d = 0; d < 3; ++d) { o.y[d] = x[d]; o.y[4 + d] = k[d]; }
     o.y[3] = t0;
-    o.y[7] = P(-1.0);
+    o.y[7] = P(-om);
 
     if (I.weights == W_UNIT) { o.w = P(1.0); return o; }
 
     // ---- weight ----
     const double Ck = (I.kdir == KD_ISO) ? 4.0 * PI : 2.0 * PI;
-    P n_c = I.n_inf * ka * I.w_inf / I.k0;
+    P n_c = I.n_inf * ka * I.w_inf / (I.k0 * std::sqrt(x2));  // n_inf |k_a| / |k_inf|
     // surface element from the gradient of F at fixed khat and t0
     using D3 = Dual<3, P>;
     D3 xd[3] = {D3::var(x[0], 0), D3::var(x[1], 1), D3::var(x[2], 2)};
-    D3 Fd = resonance_F(I, xd, t0, kh);
+    D3 Fd = resonance_F(I, xd, t0, kh, om2);
     P gF[3] = {Fd.d[0], Fd.d[1], Fd.d[2]};
     P Fr = dot3(n, gF);
     P gp2 = P(0.0);
     for (int d = 0; d < 3; ++d) { P gp = gF[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
     P Vt = A * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr));     // km^2
     Vt = Vt / (HBARC_EVKM * HBARC_EVKM);                      // eV^-2
-    P E = I.w_inf / sA;                                       // local photon energy [eV]
+    P E = om * I.w_inf / sA;                                  // local photon energy [eV]
     P Bv[3];
     bfield_t(I, x, t0, Bv);
     P B2 = dot3(Bv, Bv);
@@ -1217,6 +1274,8 @@ int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double
     }
     return 0;
 }
+
+double orc_maxwell_x(double u) { return maxwell_x(u); }
 
 int orc_event_weight(const orc_star* s, const double* y, double Lc_max_km, double* w, double* Lc) {
     Inst<double> I = make_inst_d(*s);

@@ -30,7 +30,7 @@ KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace
 class RtStar(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV", "g_agg_GeV",
                                           "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")] + \
-               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir")]
+               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds")]
 
 
 class RtTol(C.Structure):

@@ -411,6 +411,8 @@ extern "C" int rt_backward_power(const rt_star* star, const double* ev, const in
                                  double* total, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (!validate_star(star)) return RT_EINVAL;
+    if (star->speeds != RT_SPEEDS_MONO)
+        return fail(RT_EUNSUPPORTED, "rt_backward_power: the event weights assume monochromatic axions");
     if (n < 0 || K < 0) return fail(RT_EINVAL, "rt_backward_power: negative size");
     if (!std::isfinite(Lc_max_km)) return fail(RT_EINVAL, "rt_backward_power: non-finite cutoff");
     if (!area && !(pixel_area_km2 >= 0.0 && std::isfinite(pixel_area_km2)))

@@ -35,7 +35,7 @@ RT_HD double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * 
 // parameters of a star that are never differentiated
 struct StarFixed {
     double g_agg_GeV, v0_kms, rho_GeVcm3, multiplicity, psi_twist, B_test_G;
-    int plasma, density, weights, kdir;
+    int plasma, density, weights, kdir, speeds;
 };
 
 // seeding / weight constants
@@ -49,7 +49,8 @@ struct SeedT {
     double G2;     // 1 gauss in eV^2
     double Btest;  // constant |B_perp| [G] (zero-variance test)
     double hbarc;  // [eV km]
-    int weights, kdir;
+    double kv2;    // (k0 / w_inf)^2 = v0^2 / (1 + v0^2)
+    int weights, kdir, speeds;
 };
 
 template <class T>
@@ -109,6 +110,8 @@ RT_HD SeedT<T> make_seed_t(const T p[6], const StarFixed& f) {
     C.hbarc = phys::hbarc_eVkm;
     C.weights = f.weights;
     C.kdir = f.kdir;
+    C.speeds = f.speeds;
+    C.kv2 = v0 * v0 / (1.0 + v0 * v0);
     return C;
 }
 
@@ -126,7 +129,7 @@ RT_HD InstT<S> lift_inst(const InstT<T>& I) {
 //   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
 // (isotropic plasma: F = P - m_a^2), at a general point x, for axis m.
 template <class S, class T>
-RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3]) {
+RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3], double om2) {
     InstT<S> J = lift_inst<S>(I);
     S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     S ir = rcp(r);
@@ -139,14 +142,14 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
     for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - mm[i];
     S ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
     S cB2 = ku * ku * rcp(1.0 + 3.0 * mu * mu);
-    S w2 = rcp(1.0 - J.rs * ir);
+    S w2 = om2 * rcp(1.0 - J.rs * ir);
     return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
 }
 
 // F along the radial line through n at radius r (values only: the bisection)
 template <class T>
 RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m[3], double mu, double cB2,
-                            double r) {
+                            double om2, double r) {
     InstT<double> J;
     J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
     J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2);
@@ -154,8 +157,45 @@ RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m
     double ir = 1.0 / r;
     Plasma<double> pl = plasma_eval(J, n, ir, m, mu, 0.0);
     if (I.plasma == PL_ISO) return pl.P - J.ma2;
-    double w2 = 1.0 / (1.0 - J.rs * ir);
+    double w2 = om2 / (1.0 - J.rs * ir);
     return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+}
+
+// Maxwellian momenta at infinity (Sec. 4.3 eq. (GaussianDist)): x = (|k_inf|/k0)^2 has the
+// Gamma(3/2) distribution, density (2/sqrt pi) sqrt(x) e^{-x}.  maxwell_x(u) solves G(x) = u
+// for its distribution function by Newton's method inside a shrinking bracket, with G from
+// its power series x^{3/2} e^{-x}/Gamma(5/2) sum_j x^j/((5/2)...(3/2+j)) below the median and
+// 1 - G = erfc(sqrt x) + (2/sqrt pi) sqrt(x) e^{-x} above it.
+RT_HD double maxwell_x(double u) {
+    const double c = 1.1283791670955126;  // 2/sqrt(pi)
+    const bool upper = u >= 0.5;
+    const double target = upper ? 1.0 - u : u;
+    double lo = 0.0, hi = 100.0;
+    // starting point: the leading term x^{3/2}/Gamma(5/2) below the median, the tail
+    // c sqrt(x) e^{-x} ~ 1 - u above it
+    double x = upper ? fmax(1.2, -::log(target)) : ::pow(1.3293403881791355 * target, 2.0 / 3.0);
+    for (int it = 0; it < 100; ++it) {
+        const double sx = ::sqrt(x), ex = ::exp(-x);
+        double g;  // signed so that g increases with x
+        if (upper) {
+            g = target - (::erfc(sx) + c * sx * ex);
+        } else {
+            double term = 1.0, sum = 1.0;
+            for (int j = 1; j < 60; ++j) {
+                term *= x / (1.5 + j);
+                sum += term;
+                if (term < 1e-17 * sum) break;
+            }
+            g = x * sx * ex * (sum / 1.3293403881791355) - target;
+        }
+        if (g < 0.0) lo = x; else hi = x;
+        const double dg = c * sx * ex;
+        double xn = (dg > 0.0) ? x - g / dg : 0.5 * (lo + hi);
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (::fabs(xn - x) <= 2e-16 * xn || hi - lo <= 2e-16 * hi) { x = xn; break; }
+        x = xn;
+    }
+    return x;
 }
 
 // the six uniforms of ray gi (Philox4x32-10, key = seed, counter = (gi, instance, block))
@@ -205,19 +245,24 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     for (int d = 0; d < 3; ++d) ud[d] = 3.0 * mu * n[d] - m[d];
     double ku = kh[0] * ud[0] + kh[1] * ud[1] + kh[2] * ud[2];
     double cB2 = ku * ku / (1.0 + 3.0 * mu * mu);
+    // momentum at infinity: k0 = m_a v0, or Maxwellian (x = (k/k0)^2 from the sixth uniform);
+    // energy at infinity om = sqrt(m~^2 + x kv2) in units of w_inf
+    const double x2 = (C.speeds == SP_MAXWELL) ? maxwell_x(u[5]) : 1.0;
+    const double om2 = value(I.ma2) + x2 * C.kv2;
+    const double om = ::sqrt(om2);
 
     // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
     double R = value(I.R);
     double rcv = -1.0;
-    if (resonance_line(I, n, m, mu, cB2, R) > 0.0) {
+    if (resonance_line(I, n, m, mu, cB2, om2, R) > 0.0) {
         double lo = R, hi = 2.0 * R;
         int j = 0;
-        while (!(resonance_line(I, n, m, mu, cB2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
-        if (resonance_line(I, n, m, mu, cB2, hi) < 0.0) {
+        while (!(resonance_line(I, n, m, mu, cB2, om2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
+        if (resonance_line(I, n, m, mu, cB2, om2, hi) < 0.0) {
             for (int it = 0; it < 200; ++it) {
                 double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
-                if (resonance_line(I, n, m, mu, cB2, mid) > 0.0) lo = mid; else hi = mid;
+                if (resonance_line(I, n, m, mu, cB2, om2, mid) > 0.0) lo = mid; else hi = mid;
             }
             rcv = 0.5 * (lo + hi);
         }
@@ -234,14 +279,15 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
         D1 rd{T(rcv)};
         rd.d[0] = T(1.0);
         D1 xd[3] = {rd * n[0], rd * n[1], rd * n[2]};
-        D1 Fd = resonance_point<D1, T>(I, xd, mT, kh);
+        D1 Fd = resonance_point<D1, T>(I, xd, mT, kh, om2);
         rc = T(rcv) - Fd.v * rcp(Fd.d[0]);
         set_value(rc, rcv);
     }
     T s = I.rs * rcp(rc);
     T A = 1.0 - s;
     T sA = sqrt(A);
-    T ka = sqrt(rcp(A) - I.ma2);
+    // |k_a|^2 = om^2/A - m~^2 = (x kv2 + m~^2 s)/A without the cancellation of the first form
+    T ka = sqrt((x2 * C.kv2 + I.ma2 * s) * rcp(A));
     T x[3] = {rc * n[0], rc * n[1], rc * n[2]};
     // photon covariant momentum from the static-frame axion momentum |k_a| kh
     T ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
@@ -249,24 +295,24 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     T corr = nko * rcp(sA) - nko;
     T k[3] = {ko[0] + corr * n[0], ko[1] + corr * n[1], ko[2] + corr * n[2]};
     out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = t0;
-    out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = T(-1.0);
+    out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = T(-om);
     out[9] = rc;
     if (C.weights == W_UNIT) { out[8] = T(1.0); return ST_OK; }
 
     // ---- weight w = C_k n_c Vt Q ----
     const double Ck = (C.kdir == KD_ISO) ? 4.0 * phys::pi : 2.0 * phys::pi;
-    T n_c = C.nc_per_ka * ka;
+    T n_c = C.nc_per_ka * ka * (1.0 / ::sqrt(x2));  // n_inf |k_a| / |k_inf|
     // surface element from grad F (dual numbers over x, 3 tangents)
     typedef gdual<3, T> D3;
     D3 xd[3];
     for (int d = 0; d < 3; ++d) { xd[d] = D3(x[d]); xd[d].d[d] = T(1.0); }
-    D3 Fd = resonance_point<D3, T>(I, xd, mT, kh);
+    D3 Fd = resonance_point<D3, T>(I, xd, mT, kh, om2);
     T Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
     T gp2 = T(0.0);
     for (int d = 0; d < 3; ++d) { T gp = Fd.d[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
     // sqrt|g_tt| times the printed sqrt|h_k| (which already carries A^{1/2})
     T Vt = A * rc * rc * sqrt(1.0 + gp2 * rcp(A * Fr * Fr)) * (1.0 / (C.hbarc * C.hbarc));
-    T E = C.w_inf * rcp(sA);
+    T E = (C.w_inf * om) * rcp(sA);
     T ir = rcp(rc);
     T Rr = I.R * ir;
     T nT[3] = {T(n[0]), T(n[1]), T(n[2])};
@@ -288,10 +334,10 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     } else {
         // dE/dx at fixed covariant k from H(x, k_t, k) = 0 with w = -k_t/sqrt(A):
         //   dE/dx = (dH/dx) / (sqrt(A) dH/dk_t) - w s/(2 A r) n
-        T y[8] = {x[0], x[1], x[2], t0, k[0], k[1], k[2], T(-1.0)};
+        T y[8] = {x[0], x[1], x[2], t0, k[0], k[1], k[2], T(-om)};
         T g[8];
         grad_h(I, y, g);
-        T w = rcp(sA);
+        T w = om * rcp(sA);
         T c0 = rcp(sA * g[7]);
         T c1 = w * s * ir * rcp(2.0 * A);
         T dE[3] = {g[0] * c0 - c1 * n[0], g[1] * c0 - c1 * n[1], g[2] * c0 - c1 * n[2]};

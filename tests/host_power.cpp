@@ -9,7 +9,7 @@ using namespace rtd;
 
 extern "C" {
 // p = (B0, P, theta_m, M, R, m_a); fd = (g_agg, v0, rho, multiplicity, psi, B_test);
-// fi = (plasma, density, weights, kdir)
+// fi = (plasma, density, weights, kdir, speeds)
 double host_event_weight(const double* p, const double* fd, const int* fi, const double* y, double Lc_max,
                          double* Lc) {
     StarFixed fx;
@@ -23,6 +23,7 @@ double host_event_weight(const double* p, const double* fd, const int* fi, const
     fx.density = fi[1];
     fx.weights = fi[2];
     fx.kdir = fi[3];
+    fx.speeds = fi[4];
     InstT<double> I = make_inst_t<double>(p, fx);
     SeedT<double> C = make_seed_t<double>(p, fx);
     return event_weight(I, C, y, Lc_max, Lc);

@@ -35,7 +35,7 @@ def host_weight(L, s, y, Lc_max=0.0):
     P = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
     p = np.array([s[k] for k in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")])
     fd = np.array([s[k] for k in ("g_agg_GeV", "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")])
-    fi = np.array([s["plasma"], s["density"], s["weights"], s["kdir"]], dtype=np.int32)
+    fi = np.array([s["plasma"], s["density"], s["weights"], s["kdir"], s["speeds"]], dtype=np.int32)
     lc = C.c_double()
     y = np.ascontiguousarray(y, dtype=np.float64)
     w = L.host_event_weight(P(p), P(fd), fi.ctypes.data_as(C.POINTER(C.c_int)), P(y), Lc_max, C.byref(lc))

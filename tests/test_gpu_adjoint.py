@@ -61,6 +61,7 @@ def well_conditioned(orc, star, tol, n, sto):
     ("cfg2-gj-aniso-gr-oblique", W.CFG2["star"], 300, 0.02),
     ("spherical-aniso-gr-oblique", SPHERICAL, 300, 0.05),
     ("ragged-n-37", W.CFG1["star"], 37, 0.02),
+    ("spherical-maxwellian", dict(SPHERICAL, speeds=W.SPEEDS_MAXWELL), 300, 0.05),
 ])
 def test_flux_grad_matches_oracle(rt, orc, name, star, n, sigma):
     print(f"adjoint parity {name} n={n}", flush=True)

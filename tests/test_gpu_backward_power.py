@@ -210,6 +210,8 @@ def test_backward_power_image_is_deterministic_and_errors(rt):
     # a cutoff below every conversion length removes everything
     wc, tc = rt.rt_backward_power(s, ev, nev, Lc_max_km=1e-12, pixel_area_km2=area)
     assert tc.item() == 0.0
+    with pytest.raises(rt.RtError, match="monochromatic"):
+        rt.rt_backward_power(dict(s, speeds=W.SPEEDS_MAXWELL), ev, nev, pixel_area_km2=area)
     with pytest.raises(rt.RtError, match="invalid pixel area"):
         rt.rt_backward_power(s, ev, nev, pixel_area_km2=-1.0)
     with pytest.raises(rt.RtError, match="non-finite"):

@@ -34,13 +34,18 @@ def _np(t):
     return t.cpu().numpy()
 
 
+# the full forward workload with Maxwellian axion momenta at infinity (Sec. 4.3)
+CFG2M = dict(W.CFG2, name="forward-gr-aniso-oblique-maxwellian", star=dict(W.CFG2["star"], speeds=W.SPEEDS_MAXWELL))
+CFG1M = dict(W.CFG1, name="forward-flat-iso-maxwellian", star=dict(W.CFG1["star"], speeds=W.SPEEDS_MAXWELL))
+
+
 def _cfg2_small(n):
     c = dict(W.CFG2)
     c["n"] = n
     return c
 
 
-@pytest.mark.parametrize("cfg,n", [(W.CFG1, 4096), (W.CFG2, 3000), (W.CFG1, 37)])
+@pytest.mark.parametrize("cfg,n", [(W.CFG1, 4096), (W.CFG2, 3000), (W.CFG1, 37), (CFG1M, 4096), (CFG2M, 3000)])
 def test_sample_matches_oracle(rt, orc, cfg, n):
     print(f"sample parity {cfg['name']} n={n}", flush=True)
     rays_g, st_g = rt.rt_sample_resonance(cfg["star"], cfg["seed"], n)
@@ -63,7 +68,7 @@ def test_sample_offset_and_instance(rt, orc):
     assert np.allclose(_np(rays_g)[:8, ok], rays_o[:8, ok], rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("cfg,n", [(W.CFG1, 4096), (W.CFG2, 2048), (W.CFG1, 4096 + 37)])
+@pytest.mark.parametrize("cfg,n", [(W.CFG1, 4096), (W.CFG2, 2048), (W.CFG1, 4096 + 37), (CFG2M, 2048)])
 def test_trace_matches_oracle(rt, orc, cfg, n):
     """Tracer parity from the oracle's own seeds."""
     import torch

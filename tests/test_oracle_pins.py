@@ -315,7 +315,7 @@ def test_zero_variance_spherical_weights(orc, M):
     A = 1 - rs / rc
     hc = c["hbarc_eVkm"]
     E = w_inf / math.sqrt(A)
-    ka = math.sqrt(w_inf ** 2 / A - ma2)
+    ka = math.sqrt(ma2 * (v0 ** 2 + rs / rc) / A)  # = sqrt(w_inf^2/A - m_a^2), without cancellation
     n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
     n_c = n_inf * ka / (ma * v0)
     dwp2dr = 3 * ma2 / rc * hc  # |d w_p^2 / dr| in eV^3 (r in eV^-1)
@@ -329,6 +329,71 @@ def test_zero_variance_spherical_weights(orc, M):
         wpprime = 1.5 * ma / rc / (1 / hc)
         hook = 4 * math.pi * (rc / hc) ** 2 * 0.5 * math.pi * g ** 2 * B ** 2 * n_c * ma / wpprime
         assert abs(w.mean() / hook - 1) < 2 * v0 ** 2
+
+
+def test_maxwell_sampler_matches_library_and_moments(orc):
+    """Sec. 4.3 eq. (GaussianDist): x = (|k_inf|/k0)^2 of a Maxwellian has the Gamma(3/2)
+    distribution.  The oracle's inverse against scipy's inverse regularised incomplete gamma
+    functions in both tails, down to the smallest and largest uniforms the seeding draws,
+    and the midpoint rule over u of x, sqrt(x), x^2 against the moments 3/2, 2/sqrt(pi), 15/4."""
+    from scipy.special import gammaincinv, gammainccinv
+    for u in (2.0 ** -53, 1e-12, 1e-3, 0.1, 0.3, 0.4999, 0.5, 0.7, 0.9, 1 - 1e-9, 1 - 2.0 ** -53):
+        x = orc.maxwell_x(u)
+        ref = gammaincinv(1.5, u) if u < 0.5 else gammainccinv(1.5, 1.0 - u)
+        assert abs(x / ref - 1) < 1e-13, (u, x, ref)
+    n = 20000
+    xs = np.array([orc.maxwell_x((j + 0.5) / n) for j in range(n)])
+    assert abs(xs.mean() / 1.5 - 1) < 3e-5
+    assert abs(np.sqrt(xs).mean() / (2 / math.sqrt(math.pi)) - 1) < 1e-5
+    assert abs((xs ** 2).mean() / 3.75 - 1) < 3e-4
+
+
+@pytest.mark.parametrize("M", [0.0, 1.0])
+def test_maxwellian_spherical_weights(orc, M):
+    """Maxwellian speeds on the spherical constant-B surface: each ray carries the
+    monochromatic closed form at its own |k_inf| (drawn from its sixth uniform, inverted
+    here with scipy): energy at infinity w = sqrt(m_a^2 + k_inf^2), k_t = -w/w_ref,
+    n_c = n_inf |k_a| / k_inf with |k_a|^2 = w^2/A - m_a^2, E = w/sqrt(A); the resonance
+    of the isotropic plasma (w_p = m_a) does not move.  A static star keeps each ray's
+    frequency to the end."""
+    from scipy.special import gammaincinv, gammainccinv
+    s = W.star(M_Msun=M, plasma=W.PLASMA_ISO, density=W.DENSITY_SPHERICAL, weights=W.WEIGHTS_CONST_B,
+               kdir=W.KDIR_ISOTROPIC, B_test_G=1e12, speeds=W.SPEEDS_MAXWELL)
+    c = orc.constants()
+    n = 64
+    rays, st = orc.sample(s, 5, n)
+    assert np.all(st == 0)
+    mono, _ = orc.sample(dict(s, speeds=W.SPEEDS_MONO), 5, n)
+    assert np.array_equal(rays[9], mono[9])
+    v0 = s["v0_kms"] / c["c_kms"]
+    ma = s["m_a_eV"]
+    w_ref = ma * math.sqrt(1 + v0 ** 2)
+    k0 = ma * v0
+    rc = rays[9][0]
+    A = 1 - 2 * c["GMsun_km"] * M / rc
+    hc = c["hbarc_eVkm"]
+    n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+    dwp2dr = 3 * ma ** 2 / rc * hc
+    g = s["g_agg_GeV"] * 1e-9
+    B = s["B_test_G"] * c["gauss_eV2"]
+    xs = []
+    for i in range(n):
+        u5 = orc.uniforms(5, 0, i)[5]
+        x = gammaincinv(1.5, u5) if u5 < 0.5 else gammainccinv(1.5, 1.0 - u5)
+        xs.append(x)
+        kinf = k0 * math.sqrt(x)
+        w = math.sqrt(ma ** 2 + kinf ** 2)
+        assert abs(-rays[7][i] / (w / w_ref) - 1) < 1e-14
+        ka = math.sqrt((kinf ** 2 + ma ** 2 * (1 - A)) / A)  # = sqrt(w^2/A - m_a^2), without cancellation
+        E = w / math.sqrt(A)
+        closed = 4 * math.pi * (n_inf * ka / kinf) * math.sqrt(A) * (rc / hc) ** 2 * math.pi * g ** 2 * B ** 2 \
+            * E ** 2 / dwp2dr
+        assert abs(rays[8][i] / closed - 1) < 1e-12, (i, rays[8][i], closed)
+    assert np.ptp(xs) > 1.0  # the draws really spread
+    fin, ifin = orc.trace_forward(s, W.tol(), rays, st)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    assert esc.sum() >= n // 2
+    assert np.allclose(fin[11][esc], -rays[7][esc], rtol=1e-12, atol=0)
 
 
 def test_flat_anisotropic_weight_from_printed_probability(orc):

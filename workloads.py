@@ -22,6 +22,7 @@ PLASMA_ISO, PLASMA_ANISO = 0, 1
 DENSITY_GJ, DENSITY_MAGNETAR, DENSITY_SPHERICAL, DENSITY_NONE = 0, 1, 2, 3
 WEIGHTS_UNIT, WEIGHTS_CONVERSION, WEIGHTS_CONST_B = 0, 1, 2
 KDIR_ISOTROPIC, KDIR_OUTWARD = 0, 1
+SPEEDS_MONO, SPEEDS_MAXWELL = 0, 1
 
 STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
 STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE = 4, 5, 6
@@ -30,7 +31,7 @@ FIDUCIAL = dict(
     B0_G=1e14, P_s=1.0, theta_m=0.0, M_Msun=1.0, R_km=10.0, m_a_eV=1e-5,
     g_agg_GeV=1e-12, v0_kms=220.0, rho_GeVcm3=0.45, multiplicity=1.0, psi_twist=0.2,
     B_test_G=1e12, plasma=PLASMA_ANISO, density=DENSITY_GJ, weights=WEIGHTS_CONVERSION,
-    kdir=KDIR_ISOTROPIC,
+    kdir=KDIR_ISOTROPIC, speeds=SPEEDS_MONO,
 )
 
 TOL = dict(rtol=1e-8, atol=1e-12, r_max_km=1e4, max_steps=1 << 20)
