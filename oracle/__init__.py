@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
 class Star(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV", "g_agg_GeV",
                                           "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")] + \
-               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds")]
+               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds", "flags")]
 
 
 class Tol(C.Structure):
@@ -81,6 +81,8 @@ def lib():
         L.orc_backward_rays.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, dp, dp, C.c_int64, C.c_int32,
                                         C.c_double, dp, dp, ip, dp, ip, C.c_int]
         L.orc_event_weight.argtypes = [sp, dp, C.c_double, dp, dp]
+        L.orc_cyclotron_depth.argtypes = [sp, dp, ip, dp, C.c_int64, dp, dp]
+        L.orc_open_field.argtypes = [sp, dp, C.c_double]
         L.orc_maxwell_x.argtypes = [C.c_double]
         L.orc_maxwell_x.restype = C.c_double
         L.orc_dopri_test.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int64),
@@ -115,7 +117,8 @@ def make_tol(d: dict) -> Tol:
 def constants() -> dict:
     out = np.zeros(16)
     m = lib().orc_constants(_dp(out), 16)
-    names = ["c_kms", "hbarc_eVkm", "alpha", "m_e_eV", "e_statC", "GMsun_km", "gauss_eV2", "wp2_per_ne"]
+    names = ["c_kms", "hbarc_eVkm", "alpha", "m_e_eV", "e_statC", "GMsun_km", "gauss_eV2", "wp2_per_ne",
+             "hbar_omega_c_per_G"]
     return dict(zip(names, out[:m]))
 
 
@@ -256,6 +259,23 @@ def backward_rays(s, t, D_km, incl, phi_o, b1, b2, K=8, Lc_max_km=0.0, nthreads=
     lib().orc_backward_rays(C.byref(make_star(s)), C.byref(make_tol(t)), D_km, incl, phi_o, _dp(b1), _dp(b2), n, K,
                             Lc_max_km, _dp(wsum), _dp(ev), _ip(nev), _dp(fin), _ip(ifin), nthreads)
     return wsum, ev, nev, fin, ifin
+
+
+def cyclotron_depth(s, fin, ifin, r_emit):
+    """Resonant cyclotron optical depth tau[n] of escaped forward rays and the resonance radius
+    r_cyc[n] (-1 where there is none)."""
+    fin = np.ascontiguousarray(fin, dtype=np.float64)
+    ifin = np.ascontiguousarray(ifin, dtype=np.int32)
+    r_emit = np.ascontiguousarray(r_emit, dtype=np.float64)
+    n = fin.shape[1]
+    tau, rc = np.zeros(n), np.zeros(n)
+    lib().orc_cyclotron_depth(C.byref(make_star(s)), _dp(fin), _ip(ifin), _dp(r_emit), n, _dp(tau), _dp(rc))
+    return tau, rc
+
+
+def open_field(s, x, t):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return bool(lib().orc_open_field(C.byref(make_star(s)), _dp(x), float(t)))
 
 
 def maxwell_x(u):

@@ -38,6 +38,7 @@ typedef struct {
     int32_t weights;      /* 0 unit, 1 conversion, 2 conversion with constant |B_perp| */
     int32_t kdir;         /* 0 isotropic axion directions, 1 outward hemisphere */
     int32_t speeds;       /* 0 every axion at |k_inf| = m_a v0; 1 Maxwellian |k_inf|, dispersion k0 = m_a v0 */
+    int32_t flags;        /* bit 0: no conversion on open field lines (r / sin^2 theta_mag >= c / Omega) */
 } orc_star;
 
 typedef struct {
@@ -46,7 +47,8 @@ typedef struct {
 } orc_tol;
 
 enum { ORC_OK = 0, ORC_ESCAPED = 1, ORC_HIT_STAR = 2, ORC_NO_RESONANCE = 3,
-       ORC_MAX_STEPS = 4, ORC_STEP_UNDERFLOW = 5, ORC_NONFINITE = 6 };
+       ORC_MAX_STEPS = 4, ORC_STEP_UNDERFLOW = 5, ORC_NONFINITE = 6, ORC_EXCISED = 7 };
+enum { ORC_FLAG_EXCISE_OPEN = 1 };
 
 /* number of doubles per final record and their order */
 #define ORC_NFIN 16  /* y_f[8], theta, phi, psi, omega, H_f, lam_f, r_f, h_last */
@@ -96,6 +98,13 @@ int orc_trace_backward(const orc_star* s, const orc_tol* tol, double D_km, doubl
 int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double incl, double phi_o,
                       const double* b1, const double* b2, int64_t n, int32_t K, double Lc_max_km, double* wsum,
                       double* ev, int32_t* nev, double* fin, int32_t* ifin, int nthreads);
+/* resonant cyclotron optical depth of Sec. 6 for each escaped forward ray (fin, ifin as
+   written by orc_trace_forward, r_emit[n] = emission radii): tau[n] (0 for other rays) */
+int orc_cyclotron_depth(const orc_star* s, const double* fin, const int32_t* ifin, const double* r_emit, int64_t n,
+                        double* tau, double* r_cyc);
+/* whether x (at time t) lies on an open field line of the rotating dipole */
+int orc_open_field(const orc_star* s, const double* x, double t);
+
 /* x = (|k_inf|/k0)^2 at quantile u of the Maxwellian of Sec. 4.3 eq. (GaussianDist) */
 double orc_maxwell_x(double u);
 /* the weight of one production event at state y[8] (and its conversion length [km]) */

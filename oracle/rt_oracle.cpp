@@ -171,7 +171,7 @@ struct Inst {
     P Period;  // [s]
     double g_eV;   // coupling [eV^-1]
     double Btest;  // constant |B_perp| of the zero-variance test [G]
-    int plasma, density, weights, kdir, speeds;
+    int plasma, density, weights, kdir, speeds, flags;
 };
 
 template <class P>
@@ -207,6 +207,7 @@ static Inst<P> make_inst(const orc_star& s, const P p[6]) {
     I.Btest = s.B_test_G;
     I.plasma = s.plasma; I.density = s.density; I.weights = s.weights; I.kdir = s.kdir;
     I.speeds = s.speeds;
+    I.flags = s.flags;
     return I;
 }
 
@@ -359,6 +360,66 @@ static S energy_t(const Inst<P>& I, const S x[3], const P& t, const K k[3]) {
 }
 
 // ---------------------------------------------------------------------------
+// Magnetar options of Sec. 6.
+// Open field lines: the dipole's field lines are r = L sin^2 theta_mag; a line is open when
+// its apex L reaches the light cylinder r_LC = c/Omega, so a point is on an open line when
+// r / sin^2 theta_mag >= r_LC, written r >= r_LC sin^2 theta_mag (true on the magnetic axis).
+// ---------------------------------------------------------------------------
+template <class P>
+static bool on_open_field_line(const Inst<P>& I, const double x[3], double t) {
+    const double r = std::sqrt(dot3(x, x));
+    const double ph = val(I.Om) * t;
+    const double m[3] = {val(I.sm) * std::cos(ph), val(I.sm) * std::sin(ph), val(I.cm)};
+    const double mu = dot3(m, x) / r;
+    const double rLC = 1.0 / val(I.Om);  // [km]
+    return r >= rLC * (1.0 - mu * mu);
+}
+
+// Resonant cyclotron absorption (Sec. 6): with the trajectory taken radial along the ray's
+// asymptotic direction nhat, the photon is at radius r at time t(r) = t_f + (r - r_f) and has
+// local frequency w(r) = w_f / sqrt(A(r)); the resonance is the radius where the electron
+// cyclotron frequency hbar e |B| / (m_e c) equals w (dipole |B|), and there
+//   tau = (pi/3) (w_p^2 / w) r.
+// No absorption when the resonance lies inside the emission radius or w exceeds the cyclotron
+// frequency at the surface.  The root is bracketed by doubling and bisected.
+static double hbar_omega_c_per_gauss() {  // [eV / G]: hbar e B/(m_e c) in Gaussian units
+    return HBARC_EVCM * E_STATC / (M_E_EV / EV_PER_ERG);
+}
+
+static double cyclotron_tau(const Inst<double>& I, const double fin[ORC_NFIN], double r_emit, double* r_res) {
+    const double th = fin[8], ph = fin[9];
+    const double nh[3] = {std::sin(th) * std::cos(ph), std::sin(th) * std::sin(ph), std::cos(th)};
+    const double tf = fin[3], rf = fin[14];
+    const double wf = fin[11] * I.w_inf;  // energy at infinity [eV]
+    const double kc = hbar_omega_c_per_gauss();
+    auto g = [&](double r) {
+        const double x[3] = {r * nh[0], r * nh[1], r * nh[2]};
+        double B[3];
+        bfield_t(I, x, tf + (r - rf), B);
+        return kc * std::sqrt(dot3(B, B)) - wf / std::sqrt(1.0 - I.rs / r);
+    };
+    *r_res = -1.0;
+    const double R = I.R;
+    if (!(g(R) > 0.0)) return 0.0;
+    double lo = R, hi = 2.0 * R;
+    for (int j = 0; j < 200 && !(g(hi) < 0.0); ++j) { lo = hi; hi *= 2.0; }
+    if (!(g(hi) < 0.0)) return 0.0;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (g(mid) > 0.0) lo = mid; else hi = mid;
+    }
+    const double rc = 0.5 * (lo + hi);
+    *r_res = rc;
+    if (rc < r_emit) return 0.0;
+    const double x[3] = {rc * nh[0], rc * nh[1], rc * nh[2]};
+    const double tc = tf + (rc - rf);
+    const double wp2 = wp2_tilde(I, x, tc) * I.w_inf * I.w_inf;  // [eV^2]
+    const double w = wf / std::sqrt(1.0 - I.rs / rc);
+    return (PI / 3.0) * (wp2 / w) * (rc / HBARC_EVKM);
+}
+
+// ---------------------------------------------------------------------------
 // Resonance foliation (Sec. 3 eq. (Hypersurfaces), Sec. 4 kinematic matching
 // k^a_mu = k^gamma_mu).  The axion has conserved k_t = -w_inf and is on shell,
 // so in the static frame w^2 = w_inf^2/A and |k_a|^2 = w^2 - m_a^2.  Putting
@@ -507,6 +568,15 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     // the second form without the cancellation of the first (|k_a| << w_inf far from the star)
     P ka = sqrt((x2 * I.kv2 + I.ma2 * (I.rs / rc)) / A);
     P x[3] = {rc * n[0], rc * n[1], rc * n[2]};
+    if (I.flags & ORC_FLAG_EXCISE_OPEN) {
+        const double xv[3] = {val(x[0]), val(x[1]), val(x[2])};
+        if (on_open_field_line(I, xv, val(t0))) {
+            for (int d = 0; d < 8; ++d) o.y[d] = P(0.0);
+            o.w = P(0.0);
+            o.status = ORC_EXCISED;
+            return o;
+        }
+    }
     // photon momentum = axion momentum: orthonormal |k_a| khat -> Cartesian covariant
     P ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
     P nko = dot3(n, ko);
@@ -1019,6 +1089,10 @@ static void backward_pixel(const Inst<double>& I, const orc_tol& tol, double D, 
 static double event_weight(const Inst<double>& I, const double y[8], double Lc_max_km, double* Lc_out) {
     const double x[3] = {y[0], y[1], y[2]};
     const double t = y[3];
+    if ((I.flags & ORC_FLAG_EXCISE_OPEN) && on_open_field_line(I, x, t)) {
+        if (Lc_out) *Lc_out = 0.0;
+        return 0.0;
+    }
     const double k[3] = {y[4], y[5], y[6]};
     const double r = std::sqrt(dot3(x, x));
     const double A = 1.0 - I.rs / r, sA = std::sqrt(A);
@@ -1092,7 +1166,8 @@ static int nthreads_or_default(int nt) {
 extern "C" {
 
 int orc_constants(double* out, int n) {
-    double v[] = {C_KMS, HBARC_EVKM, ALPHA, M_E_EV, E_STATC, GM_SUN_KM, gauss_in_eV2(), wp2_per_ne()};
+    double v[] = {C_KMS, HBARC_EVKM, ALPHA, M_E_EV, E_STATC, GM_SUN_KM, gauss_in_eV2(), wp2_per_ne(),
+                  hbar_omega_c_per_gauss()};
     int m = (int)(sizeof(v) / sizeof(v[0]));
     for (int i = 0; i < n && i < m; ++i) out[i] = v[i];
     return m;
@@ -1276,6 +1351,25 @@ int orc_backward_rays(const orc_star* s, const orc_tol* tol, double D_km, double
 }
 
 double orc_maxwell_x(double u) { return maxwell_x(u); }
+
+int orc_open_field(const orc_star* s, const double* x, double t) {
+    Inst<double> I = make_inst_d(*s);
+    return on_open_field_line(I, x, t) ? 1 : 0;
+}
+
+int orc_cyclotron_depth(const orc_star* s, const double* fin, const int32_t* ifin, const double* r_emit, int64_t n,
+                        double* tau, double* r_cyc) {
+    Inst<double> I = make_inst_d(*s);
+    for (int64_t q = 0; q < n; ++q) {
+        tau[q] = 0.0;
+        r_cyc[q] = -1.0;
+        if (ifin[2 * n + q] != ORC_ESCAPED) continue;
+        double f[ORC_NFIN];
+        for (int d = 0; d < ORC_NFIN; ++d) f[d] = fin[(int64_t)d * n + q];
+        tau[q] = cyclotron_tau(I, f, r_emit[q], &r_cyc[q]);
+    }
+    return 0;
+}
 
 int orc_event_weight(const orc_star* s, const double* y, double Lc_max_km, double* w, double* Lc) {
     Inst<double> I = make_inst_d(*s);

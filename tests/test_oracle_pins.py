@@ -458,6 +458,73 @@ def test_flat_anisotropic_weight_from_printed_probability(orc):
     assert checked >= 10
 
 
+# ---------------------------------------------------------------- magnetar options (Sec. 6)
+def test_open_field_excision_fraction(orc):
+    """Open field lines (Sec. 6): for an aligned rotator the magnetic colatitude is the polar
+    angle, so a seed on a sphere of radius r_c is excised when sin^2(theta) <= r_c / r_LC,
+    r_LC = c P / (2 pi): a fraction 1 - sqrt(1 - r_c/r_LC) of uniformly drawn cos(theta).  A
+    fast rotator puts r_LC near r_c.  Excised seeds carry status EXCISED and weight 0; the
+    others are the unflagged run's seeds bit for bit."""
+    s = W.star(M_Msun=0.0, theta_m=0.0, P_s=2e-3, m_a_eV=1e-4, plasma=W.PLASMA_ISO,
+               density=W.DENSITY_SPHERICAL, flags=W.FLAG_EXCISE_OPEN)
+    c = orc.constants()
+    n = 20000
+    rays, st = orc.sample(s, 2, n)
+    plain, st0 = orc.sample(dict(s, flags=0), 2, n)
+    assert np.all(st0 == 0)
+    rc = plain[9][0]
+    rlc = c["c_kms"] * s["P_s"] / (2 * math.pi)
+    assert 0.3 < rc / rlc < 0.9
+    exc = st == W.STATUS_EXCISED
+    assert np.all(rays[8][exc] == 0.0)
+    assert np.array_equal(rays[:, ~exc], plain[:, ~exc])
+    f_expect = 1 - math.sqrt(1 - rc / rlc)
+    sig = math.sqrt(f_expect * (1 - f_expect) / n)
+    assert abs(exc.mean() - f_expect) < 5 * sig, (exc.mean(), f_expect)
+    # the decision follows the emission point's polar angle
+    ct = plain[2] / rc
+    assert np.array_equal(exc, 1 - ct ** 2 <= rc / rlc)
+
+
+def test_cyclotron_constant_and_depth(orc):
+    """Resonant cyclotron absorption (Sec. 6).  hbar e/(m_e c) per gauss against CODATA
+    (scipy.constants, SI: hbar B/m_e); the optical depth of rays leaving an aligned GJ rotator
+    (M = 0) along the magnetic axis and in the magnetic equator, where the dipole |B| is B0
+    (R/r)^3 and B0/2 (R/r)^3 and the density factor |3 cos^2 - 1| is 2 and 1, so the resonance
+    radius is a cube root and tau = (pi/3)(w_p^2/w) r a closed form.  A ray emitted beyond
+    the resonance is not absorbed."""
+    from scipy import constants as K
+    c = orc.constants()
+    kc = c["hbar_omega_c_per_G"]
+    assert abs(kc / (K.hbar * 1e-4 / K.m_e) - 1) < 1e-8  # hbar e B / m_e [J] / e, B = 1e-4 T
+    s = W.star(M_Msun=0.0, theta_m=0.0, plasma=W.PLASMA_ISO, m_a_eV=1e-5, density=W.DENSITY_GJ)
+    v0 = s["v0_kms"] / c["c_kms"]
+    w = s["m_a_eV"] * math.sqrt(1 + v0 ** 2)
+    n0 = (2 * math.pi / s["P_s"]) * s["B0_G"] / (4 * math.pi * c["e_statC"] * 2.99792458e10)
+    fin = np.zeros((16, 3))
+    ifin = np.zeros((3, 3), dtype=np.int32)
+    ifin[2] = W.STATUS_ESCAPED
+    fin[8] = [0.0, 0.5 * math.pi, 0.0]  # theta: pole, equator, pole
+    fin[11] = 1.0
+    fin[14] = 1e4
+    fin[3] = 123.0
+    r_emit = np.array([40.0, 40.0, 1e6])
+    tau, rcyc = orc.cyclotron_depth(s, fin, ifin, r_emit)
+    for q, (bfac, dens) in enumerate([(1.0, 2.0), (0.5, 1.0), (1.0, 2.0)]):
+        r = s["R_km"] * (kc * s["B0_G"] * bfac / w) ** (1 / 3)
+        assert abs(rcyc[q] / r - 1) < 1e-13, (q, rcyc[q], r)
+        wp2 = c["wp2_per_ne"] * n0 * dens * (s["R_km"] / r) ** 3
+        t_expect = (math.pi / 3) * wp2 / w * r / c["hbarc_eVkm"]
+        if q < 2:
+            assert abs(tau[q] / t_expect - 1) < 1e-12, (q, tau[q], t_expect)
+        else:
+            assert tau[q] == 0.0
+    # other statuses: no depth
+    ifin[2] = W.STATUS_HIT_STAR
+    tau, rcyc = orc.cyclotron_depth(s, fin, ifin, r_emit)
+    assert np.all(tau == 0.0) and np.all(rcyc == -1.0)
+
+
 # ---------------------------------------------------------------- integrator
 def test_dopri_convergence_orders(orc):
     # fixed steps: global error of order 5

@@ -23,15 +23,16 @@ DENSITY_GJ, DENSITY_MAGNETAR, DENSITY_SPHERICAL, DENSITY_NONE = 0, 1, 2, 3
 WEIGHTS_UNIT, WEIGHTS_CONVERSION, WEIGHTS_CONST_B = 0, 1, 2
 KDIR_ISOTROPIC, KDIR_OUTWARD = 0, 1
 SPEEDS_MONO, SPEEDS_MAXWELL = 0, 1
+FLAG_EXCISE_OPEN = 1  # no conversion on open magnetic field lines (Sec. 6)
 
 STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
-STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE = 4, 5, 6
+STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE, STATUS_EXCISED = 4, 5, 6, 7
 
 FIDUCIAL = dict(
     B0_G=1e14, P_s=1.0, theta_m=0.0, M_Msun=1.0, R_km=10.0, m_a_eV=1e-5,
     g_agg_GeV=1e-12, v0_kms=220.0, rho_GeVcm3=0.45, multiplicity=1.0, psi_twist=0.2,
     B_test_G=1e12, plasma=PLASMA_ANISO, density=DENSITY_GJ, weights=WEIGHTS_CONVERSION,
-    kdir=KDIR_ISOTROPIC, speeds=SPEEDS_MONO,
+    kdir=KDIR_ISOTROPIC, speeds=SPEEDS_MONO, flags=0,
 )
 
 TOL = dict(rtol=1e-8, atol=1e-12, r_max_km=1e4, max_steps=1 << 20)
@@ -83,6 +84,17 @@ CFG5 = dict(
     name="adjoint-smoothed-flux-1e6",
     star=CFG1["star"], tol=tol(), n=1_000_000, seed=0, n_obs=32, sigma=0.02, ckpt_every=64,
 )
+
+
+# The four magnetar models of Sec. 6 (the twisted-magnetosphere density, psi = 0.2, P = 3.76 s,
+# M = 1.4, theta_m = 0.5 as in the backward workload): (lambda, B0) = M1 (1, 1.6e14 G),
+# M2 (20, 1.6e14 G), M3 (1, 4e14 G), M4 (20, 4e14 G), with conversion on open field lines
+# removed.
+MAGNETAR_MODELS = {
+    name: star(B0_G=B0, P_s=3.76, theta_m=0.5, M_Msun=1.4, plasma=PLASMA_ANISO, density=DENSITY_MAGNETAR,
+               m_a_eV=1e-4, multiplicity=lam, psi_twist=0.2, flags=FLAG_EXCISE_OPEN)
+    for name, lam, B0 in (("M1", 1.0, 1.6e14), ("M2", 20.0, 1.6e14), ("M3", 1.0, 4e14), ("M4", 20.0, 4e14))
+}
 
 
 def observers(n_obs: int = 32) -> np.ndarray:
