@@ -297,6 +297,48 @@ def bench_maxwell(args, rt, W, np, torch):
     return out
 
 
+def bench_magnetar(args, rt, W, np, torch):
+    """The four magnetar models of Sec. 6 (M1-M4: lambda in {1, 20}, B0 in {1.6e14, 4e14} G,
+    twisted-magnetosphere density, m_a = 1e-4 eV, conversion on open field lines removed):
+    1e6 seeds each through seeding, tracing, resonant cyclotron depth and binning; time per
+    pass, escaped power before and after absorption, excised fraction."""
+    t = W.tol()
+    bins = dict(n_theta=64, n_psi=128, n_omega=1, d_omega=1.0)
+    n = 1_000_000
+    out = {}
+    for name, s in W.MAGNETAR_MODELS.items():
+        print(f"bench: magnetar {name}", file=sys.stderr, flush=True)
+        ws = rt.workspace(rt.OP_TRACE_FORWARD, n)
+
+        def one():
+            rays, st = rt.rt_sample_resonance(s, 0, n)
+            fin, ifin = rt.rt_trace_forward(s, t, rays, st, ws=ws)
+            tau, rcyc, w_out = rt.rt_cyclotron_depth(s, rays, fin, ifin)
+            hist, cnt, over = rt.rt_bin_flux(fin, ifin, w_out, bins)
+            return rays, st, fin, ifin, tau, w_out, hist
+
+        one()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(2, min(args.steps, 3))
+        e0.record(torch.cuda.current_stream())
+        for _ in range(reps):
+            rays, st, fin, ifin, tau, w_out, hist = one()
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        esc = ifin[2] == 1
+        ok = st == 0
+        out[name] = dict(ms_per_pass=e0.elapsed_time(e1) / reps, multiplicity=s["multiplicity"], B0_G=s["B0_G"],
+                         excised_fraction=float((st == 7).double().mean()),
+                         no_resonance_fraction=float((st == 3).double().mean()),
+                         median_r_c_km=float(rays[9][ok].median()) if bool(ok.any()) else None,
+                         escaped_power_eV2=float(rays[8][esc].sum()) / n,
+                         absorbed_power_eV2=float(w_out[esc].sum()) / n,
+                         median_tau=float(tau[esc].median()) if bool(esc.any()) else None,
+                         accepted_steps=float(ifin[0].double().sum()))
+    return out
+
+
 def bench_adjoint(args, rt, W, np, torch):
     """Smoothed flux at 32 observers and its gradient with respect to the six star parameters
     (config-1 star, 1e6 rays, checkpoint every 64 accepted steps): forward phase (trace with
@@ -354,10 +396,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,fbtotal",
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,magnetar,fbtotal",
                     help="comma list of forms to time beside plain (the headline value): batched, adjoint, "
-                         "backward, maxwell (Maxwellian axion speeds), fbtotal (forward against backward "
-                         "total power of the magnetar star)")
+                         "backward, maxwell (Maxwellian axion speeds), magnetar (models M1-M4 with excision "
+                         "and cyclotron absorption), fbtotal (forward against backward total power of the "
+                         "magnetar star)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the plain form's schedule too (default: the library's default schedule)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
@@ -481,6 +524,8 @@ def main():
         out["forms"]["adjoint"] = bench_adjoint(args, rt, W, np, torch)
     if "backward" in forms:
         out["forms"]["backward"] = bench_backward(args, rt, W, np, torch)
+    if "magnetar" in forms:
+        out["forms"]["magnetar"] = bench_magnetar(args, rt, W, np, torch)
     if "maxwell" in forms:
         out["forms"]["maxwell"] = bench_maxwell(args, rt, W, np, torch)
     if "fbtotal" in forms:

@@ -37,7 +37,7 @@ enum { RT_OK = 0, RT_EINVAL = -1, RT_EHIP = -2, RT_ENOWS = -3, RT_EUNSUPPORTED =
 
 /* per-ray status */
 enum { RT_ST_OK = 0, RT_ST_ESCAPED = 1, RT_ST_HIT_STAR = 2, RT_ST_NO_RESONANCE = 3,
-       RT_ST_MAX_STEPS = 4, RT_ST_STEP_UNDERFLOW = 5, RT_ST_NONFINITE = 6 };
+       RT_ST_MAX_STEPS = 4, RT_ST_STEP_UNDERFLOW = 5, RT_ST_NONFINITE = 6, RT_ST_EXCISED = 7 };
 
 enum { RT_PLASMA_ISO = 0, RT_PLASMA_ANISO = 1 };                /* Sec. 4.1 */
 enum { RT_DENSITY_GJ = 0, RT_DENSITY_MAGNETAR = 1,              /* eqs. (GJDensity), (neMag) */
@@ -45,6 +45,10 @@ enum { RT_DENSITY_GJ = 0, RT_DENSITY_MAGNETAR = 1,              /* eqs. (GJDensi
 enum { RT_WEIGHTS_UNIT = 0, RT_WEIGHTS_CONVERSION = 1, RT_WEIGHTS_CONST_B = 2 };
 enum { RT_KDIR_ISOTROPIC = 0, RT_KDIR_OUTWARD = 1 };
 enum { RT_SPEEDS_MONO = 0, RT_SPEEDS_MAXWELL = 1 };
+/* rt_star.flags: RT_FLAG_EXCISE_OPEN removes conversion on open magnetic field lines
+   (Sec. 6: r / sin^2 theta_mag >= r_LC = c / Omega): such seeds get RT_ST_EXCISED and weight
+   0, such backward events weigh 0 */
+enum { RT_FLAG_EXCISE_OPEN = 1 };
 
 /* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
 typedef struct rt_star {
@@ -66,6 +70,7 @@ typedef struct rt_star {
     int32_t kdir;         /* RT_KDIR_*: axion directions isotropic or in the outward hemisphere */
     int32_t speeds;       /* RT_SPEEDS_*: axion momentum at infinity k0 = m_a v0 (Sec. 4.3 eq.
                              (fa_approx)) or Maxwellian with dispersion k0 (eq. (GaussianDist)) */
+    int32_t flags;        /* RT_FLAG_* bits */
 } rt_star;
 
 /* Integrator tolerances: embedded DOPRI5 error test with scale atol + rtol max(|y|,|y_new|)
@@ -125,8 +130,8 @@ enum { RT_OP_TRACE_FORWARD = 1, RT_OP_TRACE_BACKWARD = 2, RT_OP_BIN = 3, RT_OP_B
  * sqrt(m_a^2 + k_inf^2) (k_t = -that / (m_a sqrt(1 + v0^2))) and its focused density
  * n_inf |k_a| / k_inf.  The photon takes the axion's 4-momentum where the kinematic
  * matching k^a = k^gamma holds.
- * Output rays "[10][n]": x, y, z, t, k_x, k_y, k_z, k_t, w, r_c; status[n] = RT_ST_OK or
- * RT_ST_NO_RESONANCE (then w = 0).  The unbiased power estimate is (1/n) sum w [eV^2].
+ * Output rays "[10][n]": x, y, z, t, k_x, k_y, k_z, k_t, w, r_c; status[n] = RT_ST_OK,
+ * RT_ST_NO_RESONANCE or RT_ST_EXCISED (then w = 0; an excised ray keeps its r_c).  The unbiased power estimate is (1/n) sum w [eV^2].
  * Errors: RT_EINVAL for n < 0, null arrays or non-finite / out-of-range parameters. */
 int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t instance, int64_t first, int64_t n,
                         double* rays, int32_t* status, void* stream);
@@ -141,6 +146,17 @@ int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t instance, in
 int rt_trace_forward(const rt_star* star, const rt_tol* tol, const double* rays, const int32_t* status,
                      int64_t n, double* fin, int32_t* ifin, void* ws, size_t ws_bytes,
                      const rt_schedule* sched, void* stream);
+
+/* rt_cyclotron_depth -- resonant cyclotron absorption of escaped forward rays (Sec. 6): the
+ * photon is taken to move radially along its asymptotic direction from its final state; at
+ * the radius where the electron cyclotron frequency of the dipole field equals the photon's
+ * local frequency, tau = (pi/3) (w_p^2 / w) r.  rays "[>=10][n]" of rt_sample_resonance
+ * (weight w = rays[8], emission radius r_c = rays[9]), fin/ifin of rt_trace_forward (device).
+ * Output (device): tau[n] (0 for rays that do not escape, that have no resonance above the
+ * surface, or that are emitted beyond it); r_cyc[n] the resonance radius [km] or -1 (may be
+ * NULL); w_out[n] = w e^{-tau} (may be NULL), ready for rt_bin_flux.  Errors: RT_EINVAL. */
+int rt_cyclotron_depth(const rt_star* star, const double* rays, const double* fin, const int32_t* ifin, int64_t n,
+                       double* tau, double* r_cyc, double* w_out, void* stream);
 
 /* rt_bin_flux -- top-hat sky/frequency binning of escaped rays (Sec. 2.2): hist and cnt are
  * "[n_theta][n_psi][n_omega]" (sum of w and ray count, both double, overwritten), over[2]

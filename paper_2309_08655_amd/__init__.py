@@ -20,7 +20,7 @@ OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD, OP_BACKWA
 FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi", "omega", "H", "lam", "r", "h"]
 
 EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_backward_rays",
-           "rt_backward_power", "rt_trace_batched",
+           "rt_backward_power", "rt_cyclotron_depth", "rt_trace_batched",
            "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
            "rt_workspace_size", "rt_timing", "rt_kernel_times", "rt_last_error", "rt_version"]
 KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace_bwd_kernel", 4: "adj_fwd_kernel",
@@ -30,7 +30,7 @@ KERNEL_KINDS = {1: "trace_fwd_kernel", 2: "trace_fwd_kernel(batched)", 3: "trace
 class RtStar(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV", "g_agg_GeV",
                                           "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")] + \
-               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds")]
+               [(n, C.c_int32) for n in ("plasma", "density", "weights", "kdir", "speeds", "flags")]
 
 
 class RtTol(C.Structure):
@@ -84,6 +84,7 @@ def lib():
                                              C.c_int32, dp, ip, dp, ip, vp, C.c_size_t, C.POINTER(RtSchedule), vp]
         L.rt_backward_power.argtypes = [sp, dp, ip, C.c_int64, C.c_int32, C.c_double, dp, C.c_double, dp, dp, vp,
                                         C.c_size_t, vp]
+        L.rt_cyclotron_depth.argtypes = [sp, dp, dp, ip, C.c_int64, dp, dp, dp, vp]
         L.rt_batch_workspace_size.argtypes = [C.c_int32, C.POINTER(C.c_int64)]
         L.rt_batch_workspace_size.restype = C.c_size_t
         L.rt_batch_prepare.argtypes = [sp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(RtBatch), vp, C.c_size_t, vp]
@@ -274,6 +275,24 @@ def rt_backward_power(star: dict, ev, nev, Lc_max_km: float = 0.0, area=None, pi
                                    _ptr(area) if area is not None else None, float(pixel_area_km2), _ptr(wsum),
                                    _ptr(total), _ptr(ws), ws.numel(), _stream()), "rt_backward_power")
     return wsum, total
+
+
+def rt_cyclotron_depth(star: dict, rays, fin, ifin):
+    """Resonant cyclotron depth of escaped forward rays: (tau[n], r_cyc[n], w e^{-tau}[n])."""
+    dev = _device()
+    n = fin.shape[1]
+    for t in (rays, fin):
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("rays and fin must be contiguous float64")
+    if rays.shape[0] < 10 or rays.shape[1] != n or ifin.shape != (RT_NIFIN, n) or ifin.dtype != torch.int32:
+        raise ValueError("rays [>=10][n], fin [16][n] and ifin [3][n] int32 must describe the same rays")
+    tau = torch.empty(n, dtype=torch.float64, device=dev)
+    rcyc = torch.empty(n, dtype=torch.float64, device=dev)
+    w_out = torch.empty(n, dtype=torch.float64, device=dev)
+    s = make_star(star)
+    _check(lib().rt_cyclotron_depth(C.byref(s), _ptr(rays), _ptr(fin), _ptr(ifin.contiguous()), n, _ptr(tau),
+                                    _ptr(rcyc), _ptr(w_out), _stream()), "rt_cyclotron_depth")
+    return tau, rcyc, w_out
 
 
 def version() -> str:

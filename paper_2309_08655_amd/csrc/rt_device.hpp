@@ -204,7 +204,8 @@ enum { W_UNIT = 0, W_CONV = 1, W_CONV_CONSTB = 2 };
 enum { KD_ISO = 0, KD_OUT = 1 };
 enum { SP_MONO = 0, SP_MAXWELL = 1 };
 enum { ST_OK = 0, ST_ESCAPED = 1, ST_HIT_STAR = 2, ST_NO_RESONANCE = 3, ST_MAX_STEPS = 4,
-       ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6 };
+       ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6, ST_EXCISED = 7 };
+enum { FLAG_EXCISE_OPEN = 1 };
 
 template <class T>
 struct InstT {

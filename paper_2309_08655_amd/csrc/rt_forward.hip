@@ -329,9 +329,43 @@ __global__ void __launch_bounds__(256) bin_tiles_kernel(const int32_t* __restric
     }
 }
 
+// resonant cyclotron depth of each escaped ray and the attenuated weight w e^{-tau}
+__global__ void __launch_bounds__(256) cyclotron_kernel(InstT<double> I, SeedT<double> C,
+                                                        const double* __restrict__ rays,
+                                                        const double* __restrict__ fin,
+                                                        const int32_t* __restrict__ ifin, int64_t n,
+                                                        double* __restrict__ tau, double* __restrict__ rcyc,
+                                                        double* __restrict__ w_out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        double t = 0.0, rr = -1.0;
+        if (ifin[2 * n + j] == ST_ESCAPED)
+            t = cyclotron_tau(I, C, fin[8 * n + j], fin[9 * n + j], fin[3 * n + j], fin[14 * n + j],
+                              fin[11 * n + j], rays[9 * n + j], &rr);
+        tau[j] = t;
+        if (rcyc) rcyc[j] = rr;
+        if (w_out) w_out[j] = rays[8 * n + j] * ::exp(-t);
+    }
+}
+
 }  // namespace rtd
 
 using namespace rtd;
+
+extern "C" int rt_cyclotron_depth(const rt_star* star, const double* rays, const double* fin, const int32_t* ifin,
+                                  int64_t n, double* tau, double* r_cyc, double* w_out, void* stream) {
+    clear_error();
+    if (!validate_star(star)) return RT_EINVAL;
+    if (n < 0) return fail(RT_EINVAL, "rt_cyclotron_depth: negative n");
+    if (n == 0) return RT_OK;
+    if (!rays || !fin || !ifin || !tau) return fail(RT_EINVAL, "rt_cyclotron_depth: null array");
+    InstT<double> I = make_inst(*star);
+    SeedT<double> C = make_seed_consts(*star);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(cyclotron_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, C, rays, fin, ifin, n, tau,
+                       r_cyc, w_out);
+    return check_launch("cyclotron_kernel");
+}
 
 extern "C" int rt_sample_resonance(const rt_star* star, uint64_t seed, int32_t instance, int64_t first, int64_t n,
                                    double* rays, int32_t* status, void* stream) {

@@ -35,7 +35,7 @@ RT_HD double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * 
 // parameters of a star that are never differentiated
 struct StarFixed {
     double g_agg_GeV, v0_kms, rho_GeVcm3, multiplicity, psi_twist, B_test_G;
-    int plasma, density, weights, kdir, speeds;
+    int plasma, density, weights, kdir, speeds, flags;
 };
 
 // seeding / weight constants
@@ -50,7 +50,7 @@ struct SeedT {
     double Btest;  // constant |B_perp| [G] (zero-variance test)
     double hbarc;  // [eV km]
     double kv2;    // (k0 / w_inf)^2 = v0^2 / (1 + v0^2)
-    int weights, kdir, speeds;
+    int weights, kdir, speeds, flags;
 };
 
 template <class T>
@@ -111,6 +111,7 @@ RT_HD SeedT<T> make_seed_t(const T p[6], const StarFixed& f) {
     C.weights = f.weights;
     C.kdir = f.kdir;
     C.speeds = f.speeds;
+    C.flags = f.flags;
     C.kv2 = v0 * v0 / (1.0 + v0 * v0);
     return C;
 }
@@ -196,6 +197,18 @@ RT_HD double maxwell_x(double u) {
         x = xn;
     }
     return x;
+}
+
+// Open field lines of the rotating dipole (Sec. 6): the line through x has apex
+// L = r / sin^2 theta_mag; it is open when L >= r_LC = c / Omega, i.e. r >= r_LC sin^2 theta_mag.
+template <class T>
+RT_HD bool on_open_field_line(const InstT<T>& I, const double x[3], double t) {
+    const double r = ::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    double s, c;
+    sincos_t(value(I.Om) * t, &s, &c);
+    const double sm = value(I.sm);
+    const double mu = (sm * c * x[0] + sm * s * x[1] + value(I.cm) * x[2]) / r;
+    return r * value(I.Om) >= 1.0 - mu * mu;
 }
 
 // the six uniforms of ray gi (Philox4x32-10, key = seed, counter = (gi, instance, block))
@@ -289,6 +302,14 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     // |k_a|^2 = om^2/A - m~^2 = (x kv2 + m~^2 s)/A without the cancellation of the first form
     T ka = sqrt((x2 * C.kv2 + I.ma2 * s) * rcp(A));
     T x[3] = {rc * n[0], rc * n[1], rc * n[2]};
+    if (C.flags & FLAG_EXCISE_OPEN) {
+        const double xv[3] = {rcv * n[0], rcv * n[1], rcv * n[2]};
+        if (on_open_field_line(I, xv, value(t0))) {
+            for (int d = 0; d < 9; ++d) out[d] = T(0.0);
+            out[9] = rc;
+            return ST_EXCISED;
+        }
+    }
     // photon covariant momentum from the static-frame axion momentum |k_a| kh
     T ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
     T nko = n[0] * ko[0] + n[1] * ko[1] + n[2] * ko[2];
@@ -354,6 +375,63 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     return ST_OK;
 }
 
+// Resonant cyclotron absorption (Sec. 6).  The escaped photon is taken to move radially along
+// its asymptotic direction nhat: at radius r it is there at time t_f + (r - r_f) with local
+// frequency w_f / sqrt(A(r)).  Its cyclotron resonance is where hbar e |B| / (m_e c) (dipole
+// |B| = (B0/2)(R/r)^3 sqrt(1 + 3 mu^2)) equals that frequency, and there
+//   tau = (pi/3) (w_p^2 / w) r.
+// The root of ln(hbar w_c / w) is bracketed by doubling from R, then refined by the step
+// r -> r exp(ln(hbar w_c / w)/3) (exact for the r^-3 falloff alone) inside the bracket, with
+// geometric bisection whenever that step leaves it.  No absorption (tau = 0) without a
+// resonance above the surface or with the emission point beyond it; *r_res = -1 when there
+// is no resonance.
+RT_HD double cyclotron_tau(const InstT<double>& I, const SeedT<double>& C, double th, double ph, double tf, double rf,
+                           double omf, double r_emit, double* r_res) {
+    double st, ct, sp, cp;
+    sincos_t(th, &st, &ct);
+    sincos_t(ph, &sp, &cp);
+    const double nh[3] = {st * cp, st * sp, ct};
+    const double wf = omf * value(C.w_inf);
+    const double kc = phys::hbarc_eVcm * phys::e_statC / (phys::m_e_eV * phys::erg_per_eV);  // eV per gauss
+    const double R = value(I.R);
+    auto lng = [&](double r) {
+        double m[3], mt[3];
+        magnetic_axis(I, tf + (r - rf), m, mt);
+        const double mu = m[0] * nh[0] + m[1] * nh[1] + m[2] * nh[2];
+        const double Rr = R / r;
+        const double B = 0.5 * value(C.B0) * Rr * Rr * Rr * ::sqrt(1.0 + 3.0 * mu * mu);
+        return ::log(kc * B * ::sqrt(1.0 - value(I.rs) / r) / wf);
+    };
+    *r_res = -1.0;
+    double glo = lng(R);
+    if (!(glo > 0.0)) return 0.0;
+    double lo = R, hi = 2.0 * R, ghi = lng(hi);
+    for (int j = 0; j < 200 && !(ghi < 0.0); ++j) { lo = hi; glo = ghi; hi *= 2.0; ghi = lng(hi); }
+    if (!(ghi < 0.0)) return 0.0;
+    double r = lo * ::exp(glo / 3.0);
+    if (!(r > lo && r < hi)) r = ::sqrt(lo * hi);
+    for (int it = 0; it < 200; ++it) {
+        const double g = lng(r);
+        if (g > 0.0) lo = r; else hi = r;
+        if (g == 0.0) break;
+        double rn = r * ::exp(g / 3.0);
+        if (!(rn > lo && rn < hi)) rn = ::sqrt(lo * hi);
+        const bool done = ::fabs(rn - r) <= 1e-15 * r || hi - lo <= 1e-15 * hi;
+        r = rn;
+        if (done) break;
+    }
+    *r_res = r;
+    if (r < r_emit) return 0.0;
+    double m[3], mt[3];
+    const double tc = tf + (r - rf);
+    magnetic_axis(I, tc, m, mt);
+    const double mu = m[0] * nh[0] + m[1] * nh[1] + m[2] * nh[2];
+    const Plasma<double> pl = plasma_eval(I, nh, 1.0 / r, m, mu, 0.0);
+    const double wp2 = pl.P * value(C.w_inf) * value(C.w_inf);
+    const double w = wf / ::sqrt(1.0 - value(I.rs) / r);
+    return (phys::pi / 3.0) * (wp2 / w) * (r / C.hbarc);
+}
+
 // Weight of one backward production event (Sec. 2.1 eq. (BackPower), Sec. 3): a ray's
 // photon density is the sum over its events of P_ag f_a, with the focused monochromatic
 // axion density f_a = v_a n_c delta(w - w_c)/(4 pi k^2) of Sec. 4.3 and P_ag of Sec. 4.4,
@@ -370,6 +448,10 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
 // cutoff of Sec. 4.4).
 RT_HD double event_weight(const InstT<double>& I, const SeedT<double>& C, const double y[8], double Lc_max,
                           double* Lc) {
+    if ((C.flags & FLAG_EXCISE_OPEN) && on_open_field_line(I, y, y[3])) {
+        if (Lc) *Lc = 0.0;
+        return 0.0;
+    }
     const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
     const double ir = rcp(::sqrt(r2));
     const double n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};

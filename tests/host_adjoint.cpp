@@ -11,7 +11,7 @@ using namespace rtd;
 
 extern "C" {
 // p = (B0, P, theta_m, M, R, m_a); fd = (g_agg, v0, rho, multiplicity, psi, B_test);
-// fi = (plasma, density, weights, kdir, speeds); tl = (rtol, atol, r_max).
+// fi = (plasma, density, weights, kdir, speeds, flags); tl = (rtol, atol, r_max).
 // Writes flux[n_obs], grad[6] = sum_j gbar_j dF_j/dp, per-ray status/n_acc and
 // per-ray gradients gray[n][6]; returns the number of steps the recompute missed.
 long long host_flux_grad(const double* p, const double* fd, const int* fi, const double* tl, long long max_steps,
@@ -30,6 +30,7 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
     fx.weights = fi[2];
     fx.kdir = fi[3];
     fx.speeds = fi[4];
+    fx.flags = fi[5];
     InstT<double> I = make_inst_t<double>(p, fx);
     I.oblique = 1;
     SeedT<double> Cs = make_seed_t<double>(p, fx);

@@ -43,7 +43,7 @@ def host_flux_grad(L, s, t, seed, n, obs, sigma, gbar, C_every=64, max_ckpt=4096
     P = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
     p = np.array([s[k] for k in ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")])
     fd = np.array([s[k] for k in ("g_agg_GeV", "v0_kms", "rho_GeVcm3", "multiplicity", "psi_twist", "B_test_G")])
-    fi = np.array([s["plasma"], s["density"], s["weights"], s["kdir"], s["speeds"]], dtype=np.int32)
+    fi = np.array([s["plasma"], s["density"], s["weights"], s["kdir"], s["speeds"], s["flags"]], dtype=np.int32)
     tl = np.array([t["rtol"], t["atol"], t["r_max_km"]])
     obs = np.ascontiguousarray(obs, dtype=np.float64)
     flux, grad = np.zeros(len(obs)), np.zeros(6)

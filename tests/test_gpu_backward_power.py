@@ -41,6 +41,8 @@ STARS = {
     "spherical_constb": W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ISO,
                                weights=W.WEIGHTS_CONST_B),
     "gj_aniso_oblique": W.star(M_Msun=1.4, theta_m=0.3, plasma=W.PLASMA_ANISO, m_a_eV=1e-5),
+    "fast_rotator_excised": W.star(M_Msun=1.4, theta_m=0.0, P_s=2e-3, m_a_eV=1e-4, plasma=W.PLASMA_ISO,
+                                   density=W.DENSITY_SPHERICAL, flags=W.FLAG_EXCISE_OPEN),
 }
 
 
@@ -49,7 +51,7 @@ def test_event_weights_on_oracle_events(rt, orc, name):
     import torch
     s = STARS[name]
     rng = np.random.default_rng(3)
-    half = 12.0 if s["density"] == W.DENSITY_SPHERICAL else 30.0
+    half = 12.0 if s["weights"] == W.WEIGHTS_CONST_B else 30.0
     b1, b2 = rng.uniform(-half, half, 96), rng.uniform(-half, half, 96)
     t = W.tol(r_max_km=1e5, rtol=1e-10, atol=1e-14)
     K = 8
