@@ -431,10 +431,11 @@ static double cyclotron_tau(const Inst<double>& I, const double fin[ORC_NFIN], d
 // monochromatic distribution).
 // ---------------------------------------------------------------------------
 template <class S, class P>
-static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double khat[3], double om2 = 1.0) {
+static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double khat[3], double om2 = 1.0,
+                     bool thin = false) {
     S tt = S(0.0) + t0;
     S wp2 = wp2_tilde(I, x, tt);
-    if (I.plasma == PL_ISO) return wp2 - I.ma2;
+    if (I.plasma == PL_ISO || thin) return wp2 - I.ma2;
     S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     S A = 1.0 - I.rs / r;
     S w2 = om2 / A;
@@ -447,9 +448,9 @@ static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double k
 
 template <class P>
 static P F_on_ray(const Inst<P>& I, const P& r, const double n[3], const P& t0, const double khat[3],
-                  double om2) {
+                  double om2, bool thin) {
     P x[3] = {r * n[0], r * n[1], r * n[2]};
-    return resonance_F(I, x, t0, khat, om2);
+    return resonance_F(I, x, t0, khat, om2, thin);
 }
 
 // Root of F along the radial line through n, above the stellar surface.
@@ -458,10 +459,10 @@ static P F_on_ray(const Inst<P>& I, const P& r, const double n[3], const P& t0, 
 // implicit-function derivative dr/dp = -(dF/dp)/(dF/dr).
 template <class P>
 static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, const double khat[3],
-                            double om2 = 1.0) {
+                            double om2 = 1.0, bool thin = false) {
     double R = val(I.R);
     Inst<double> Id;  // value copy for the bracketing
-    auto Fval = [&](double r) { return val(F_on_ray(I, P(0.0) + r, n, t0, khat, om2)); };
+    auto Fval = [&](double r) { return val(F_on_ray(I, P(0.0) + r, n, t0, khat, om2, thin)); };
     if (!(Fval(R) > 0.0)) return P(-1.0);
     double lo = R, hi = 2.0 * R;
     int j = 0;
@@ -477,7 +478,7 @@ static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, co
         using D1 = Dual<1, P>;
         D1 rd = D1::var(P(0.0) + rc, 0);
         D1 xd[3] = {rd * n[0], rd * n[1], rd * n[2]};
-        D1 Fd = resonance_F(I, xd, t0, khat, om2);
+        D1 Fd = resonance_F(I, xd, t0, khat, om2, thin);
         P corr = Fd.v / Fd.d[0];
         P out = (P(0.0) + rc) - corr;
         out.v = rc;
@@ -514,6 +515,14 @@ static P resonance_radius_t(const Inst<P>& I, const double n[3], const P& t0, co
 //        on-shell |k_a| = sqrt(w_inf^2/A - m_a^2) instead of the Newtonian k_c).
 // Gradients are spatial, at fixed covariant k, with norms |v|^2 = g^{ij} v_i v_j.
 // ---------------------------------------------------------------------------
+template <class P>
+struct SeedOut;
+
+// flat-propagation variant (App. B): the photon leaves with its local (static-frame)
+// frequency and momentum, to be traced with M = 0
+template <class P>
+static void finish_flat(const Inst<P>& I, SeedOut<P>& o, const P ko[3], double om, const P& sA);
+
 template <class P>
 struct SeedOut {
     P y[8];
@@ -553,7 +562,9 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     const double ma2v = val(I.ma2);
     const double om2 = ma2v + x2 * I.kv2;
     const double om = std::sqrt(om2);
-    P rc = resonance_radius_t(I, n, t0, kh, om2);
+    // thin-surface variant (App. B): the resonance is taken on w_p = m_a alone
+    const bool thin = (I.flags & ORC_FLAG_THIN_SURFACE) != 0;
+    P rc = resonance_radius_t(I, n, t0, kh, om2, thin);
     o.rc = rc;
     if (val(rc) < 0.0) {
         for (int d = 0; d < 8; ++d) o.y[d] = P(0.0);
@@ -577,8 +588,19 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
             return o;
         }
     }
-    // photon momentum = axion momentum: orthonormal |k_a| khat -> Cartesian covariant
-    P ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
+    // photon momentum = axion momentum (kinematic matching), orthonormal |k| khat -> Cartesian
+    // covariant.  On the thin surface the photon keeps the axion's frequency and direction and
+    // takes |k| from the LO dispersion relation there, |k|^2 = E^2 (E^2 - w_p^2)/(E^2 - w_p^2 cos^2).
+    P kg = ka;
+    if (thin && I.plasma == PL_ANISO) {
+        P Bt[3];
+        bfield_t(I, x, t0, Bt);
+        P cBt = dot3(kh, Bt) / sqrt(dot3(Bt, Bt));
+        P E2 = om2 / A;
+        P wpt = wp2_tilde(I, x, t0);
+        kg = sqrt(E2 * (E2 - wpt) / (E2 - wpt * cBt * cBt));
+    }
+    P ko[3] = {kg * kh[0], kg * kh[1], kg * kh[2]};
     P nko = dot3(n, ko);
     P k[3];
     for (int d = 0; d < 3; ++d) k[d] = (ko[d] - nko * n[d]) + (nko / sA) * n[d];
@@ -594,13 +616,28 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
     // surface element from the gradient of F at fixed khat and t0
     using D3 = Dual<3, P>;
     D3 xd[3] = {D3::var(x[0], 0), D3::var(x[1], 1), D3::var(x[2], 2)};
-    D3 Fd = resonance_F(I, xd, t0, kh, om2);
+    D3 Fd = resonance_F(I, xd, t0, kh, om2, thin);
     P gF[3] = {Fd.d[0], Fd.d[1], Fd.d[2]};
     P Fr = dot3(n, gF);
     P gp2 = P(0.0);
     for (int d = 0; d < 3; ++d) { P gp = gF[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
     P Vt = A * rc * rc * sqrt(1.0 + gp2 / (A * Fr * Fr));     // km^2
     Vt = Vt / (HBARC_EVKM * HBARC_EVKM);                      // eV^-2
+    // cos theta_n of eq. (AngleDef): the axion direction against the unit normal of the
+    // surface in the static orthonormal frame (radial covector component times sqrt(A))
+    P gFo[3];
+    for (int d = 0; d < 3; ++d) gFo[d] = (gF[d] - Fr * n[d]) + sA * Fr * n[d];
+    P cos_n = dot3(kh, gFo) / sqrt(dot3(gFo, gFo));
+    if (I.flags & ORC_FLAG_RENORM_WEIGHTS) {
+        // Sec. 6 eq. (reweight): P_ag = 1 and each ray rescaled by
+        // R = (1 cm^-3 / n_a(r)) (m_a / |k_a|) / sqrt(1 - r_s/r), which leaves
+        // w = C_k Vt |cos theta_n| m_a (1 cm^-3) / sqrt(A)
+        const double n1 = HBARC_EVCM * HBARC_EVCM * HBARC_EVCM;  // 1 cm^-3 [eV^3]
+        P m_a = I.w_inf * sqrt(I.ma2);
+        o.w = Ck * Vt * fabs(cos_n) * m_a * n1 / sA;
+        finish_flat(I, o, ko, om, sA);
+        return o;
+    }
     P E = om * I.w_inf / sA;                                  // local photon energy [eV]
     P Bv[3];
     bfield_t(I, x, t0, Bv);
@@ -629,10 +666,29 @@ static SeedOut<P> seed_ray(const Inst<P>& I, uint64_t seed, int32_t instance, in
         P wp2 = wp2_tilde(I, x, t0) * I.w_inf * I.w_inf;      // [eV^2]
         P c2 = cB * cB, s2 = 1.0 - c2;
         P Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
-        Q = 0.5 * PI * I.g_eV * I.g_eV * Bperp2 * E * E * E * E * E / (Dd * dE);
+        if (thin) {
+            // the surface is no level set of the photon energy, so cos theta_n and the
+            // 1/|k.dE| of P_ag do not cancel: Q = |cos theta_n| v_a E P_ag with the photon's
+            // k.dE = k^a d_a E (contravariant k)
+            P kc[3];
+            for (int a = 0; a < 3; ++a) kc[a] = gij[a][0] * k[0] + gij[a][1] * k[1] + gij[a][2] * k[2];
+            P kdE = HBARC_EVKM * I.w_inf * I.w_inf * (kc[0] * Ed.d[0] + kc[1] * Ed.d[1] + kc[2] * Ed.d[2]);
+            P Pag = 0.5 * PI * I.g_eV * I.g_eV * Bperp2 * E * E * E * E * E / (Dd * fabs(kdE));
+            Q = fabs(cos_n) * (ka * I.w_inf) * Pag;  // |cos theta_n| v_a E P with v_a E = |k_a|
+        } else {
+            Q = 0.5 * PI * I.g_eV * I.g_eV * Bperp2 * E * E * E * E * E / (Dd * dE);
+        }
     }
     o.w = Ck * n_c * Vt * Q;
+    finish_flat(I, o, ko, om, sA);
     return o;
+}
+
+template <class P>
+static void finish_flat(const Inst<P>& I, SeedOut<P>& o, const P ko[3], double om, const P& sA) {
+    if (!(I.flags & ORC_FLAG_FLAT_PROPAGATION)) return;
+    for (int d = 0; d < 3; ++d) o.y[4 + d] = ko[d];
+    o.y[7] = -om / sA;
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,6 +1288,9 @@ int orc_sample(const orc_star* s, uint64_t seed, int32_t instance, int64_t first
 int orc_trace_forward(const orc_star* s, const orc_tol* tol, const double* rays, const int32_t* status_in, int64_t n,
                       double* fin, int32_t* ifin, int nthreads) {
     Inst<double> I = make_inst_d(*s);
+    // flat-propagation variant: the seeds carry curved initial conditions, Hamilton's
+    // equations are integrated with M = 0
+    if (I.flags & ORC_FLAG_FLAT_PROPAGATION) I.rs = 0.0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(nthreads))
     for (int64_t j = 0; j < n; ++j) {
         if (status_in && status_in[j] != ORC_OK) {

@@ -525,6 +525,138 @@ def test_cyclotron_constant_and_depth(orc):
     assert np.all(tau == 0.0) and np.all(rcyc == -1.0)
 
 
+# ---------------------------------------------------------------- approximation variants (App. B, Sec. 6)
+def _ortho(k, x, rs):
+    """static orthonormal components of the covariant spatial momentum k at x"""
+    r = np.linalg.norm(x)
+    n = x / r
+    A = 1 - rs / r
+    return k - (n @ k) * n + math.sqrt(A) * (n @ k) * n
+
+
+def test_flat_propagation_variant(orc):
+    """App. B 'artificial gravity': curved initial conditions, M = 0 in the tracing.  The seed
+    keeps its curved weight, position and time; its photon carries the static-frame momentum
+    and local frequency, so it is on shell for the flat Hamiltonian; a static star keeps that
+    local frequency to infinity.  At M = 0 the variant is the plain method."""
+    c = orc.constants()
+    s = W.star(M_Msun=1.4, theta_m=0.0, plasma=W.PLASMA_ISO, density=W.DENSITY_SPHERICAL, m_a_eV=1e-5)
+    sf = dict(s, flags=W.FLAG_FLAT_PROPAGATION)
+    rays, st = orc.sample(s, 1, 200)
+    rf, stf = orc.sample(sf, 1, 200)
+    assert np.array_equal(st, stf)
+    assert np.array_equal(rays[8], rf[8]) and np.array_equal(rays[:4], rf[:4])
+    rs = 2 * c["GMsun_km"] * 1.4
+    flat = dict(s, M_Msun=0.0)
+    for i in range(0, 200, 7):
+        x = rays[:3, i]
+        A = 1 - rs / np.linalg.norm(x)
+        assert np.allclose(rf[4:7, i], _ortho(rays[4:7, i], x, rs), rtol=1e-14, atol=1e-15)
+        assert abs(rf[7, i] * math.sqrt(A) - rays[7, i]) < 1e-15
+        assert abs(orc.hamiltonian(flat, rf[:8, i])) < 1e-13
+    fin, ifin = orc.trace_forward(sf, W.tol(), rf, stf)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    assert esc.sum() > 50
+    assert np.allclose(fin[11][esc], -rf[7][esc], rtol=1e-12, atol=0)
+    # M = 0: nothing changes
+    s0 = W.CFG1["star"]
+    a, sa = orc.sample(s0, 2, 64)
+    b, sb = orc.sample(dict(s0, flags=W.FLAG_FLAT_PROPAGATION), 2, 64)
+    assert np.array_equal(sa, sb) and np.allclose(a, b, rtol=1e-15, atol=1e-15)
+
+
+def test_renormalised_weights(orc):
+    """Sec. 6 eq. (reweight): with P_ag = 1 and R = (1 cm^-3/n_a)(m_a/|k_a|)/sqrt(1 - r_s/r)
+    the weight reduces to C_k Vt |cos theta_n| m_a (1 cm^-3) / sqrt(A); on the spherical
+    surface of the isotropic plasma Vt = A r_c^2 and the normal is radial, so each ray weighs
+    4 pi sqrt(A) r_c^2 |khat.rhat| m_a (1 cm^-3), with khat the static-frame axion direction."""
+    c = orc.constants()
+    hc = c["hbarc_eVkm"]
+    for M in (0.0, 1.4):
+        s = W.star(M_Msun=M, plasma=W.PLASMA_ISO, density=W.DENSITY_SPHERICAL, m_a_eV=1e-5,
+                   flags=W.FLAG_RENORM_WEIGHTS)
+        rays, st = orc.sample(s, 6, 300)
+        ok = st == 0
+        assert ok.sum() > 200
+        rs = 2 * c["GMsun_km"] * M
+        n1 = (hc * 1e5) ** 3
+        for i in np.nonzero(ok)[0]:
+            x = rays[:3, i]
+            r = np.linalg.norm(x)
+            A = 1 - rs / r
+            kh = _ortho(rays[4:7, i], x, rs)
+            kh /= np.linalg.norm(kh)
+            expect = 4 * math.pi * math.sqrt(A) * (r / hc) ** 2 * abs(kh @ x / r) * s["m_a_eV"] * n1
+            assert abs(rays[8, i] / expect - 1) < 1e-12, (M, i, rays[8, i], expect)
+
+
+def test_thin_surface_variant(orc):
+    """App. B thin surface: seeds on w_p = m_a (not on the foliation k^a = k^gamma); the photon
+    keeps the axion's frequency and direction with |k| from the LO dispersion, so it is on
+    shell.  The weight, in flat space, equals the printed pieces multiplied out with
+    finite-difference gradients: C_k n_c Vt |cos theta_n| |k_a| P_ag, Vt and the normal from
+    the gradient of w_p^2, P_ag = (pi/2) g^2 |B_perp|^2 E^5 / (D |k.grad E|).  For the
+    isotropic plasma the thin surface is the resonance itself and nothing changes."""
+    c = orc.constants()
+    hc, G2 = c["hbarc_eVkm"], c["gauss_eV2"]
+    # isotropic: identical
+    s_iso = W.CFG2["star"] | dict(plasma=W.PLASMA_ISO)
+    a, sa = orc.sample(s_iso, 3, 128)
+    b, sb = orc.sample(dict(s_iso, flags=W.FLAG_THIN_SURFACE), 3, 128)
+    assert np.array_equal(sa, sb) and np.allclose(a, b, rtol=1e-13, atol=1e-15)
+    # anisotropic, GR: on w_p = m_a and on shell
+    s = dict(W.CFG2["star"], flags=W.FLAG_THIN_SURFACE)
+    rays, st = orc.sample(s, 3, 128)
+    v0 = s["v0_kms"] / c["c_kms"]
+    ma2 = 1 / (1 + v0 ** 2)
+    ok = np.nonzero(st == 0)[0]
+    assert len(ok) > 60
+    for i in ok[:40]:
+        assert abs(orc.wp2(s, rays[:3, i], rays[3, i]) / ma2 - 1) < 1e-12
+        assert abs(orc.hamiltonian(s, rays[:8, i])) < 1e-12
+    # flat anisotropic: printed pieces
+    s = W.star(M_Msun=0.0, theta_m=0.0, plasma=W.PLASMA_ANISO, m_a_eV=2e-5, kdir=W.KDIR_ISOTROPIC,
+               flags=W.FLAG_THIN_SURFACE)
+    rays, st = orc.sample(s, 3, 64)
+    ma = s["m_a_eV"]
+    w_inf = ma * math.sqrt(1 + v0 ** 2)
+    g = s["g_agg_GeV"] * 1e-9
+    n_inf = s["rho_GeVcm3"] * 1e9 * (hc * 1e5) ** 3 / ma
+    checked = 0
+    for i in np.nonzero(st == 0)[0][:20]:
+        x, t0 = rays[:3, i], rays[3, i]
+        k = rays[4:7, i] * w_inf  # photon momentum [eV]
+        r = np.linalg.norm(x)
+        h = 1e-5 * r
+
+        def E_of(xx):  # eq. (LOEnergy), flat space, at fixed k
+            wp2 = orc.wp2(s, xx, t0) * w_inf ** 2
+            B = orc.bfield(s, xx, t0)
+            cb = k @ B / np.linalg.norm(k) / np.linalg.norm(B)
+            kk = k @ k
+            return math.sqrt(0.5 * (wp2 + kk + math.sqrt(kk ** 2 + wp2 ** 2 + 2 * kk * wp2 * (1 - 2 * cb ** 2))))
+
+        E = E_of(x)
+        assert abs(E / w_inf - 1) < 1e-12  # the photon has the axion's frequency
+        gE = np.array([(E_of(x + h * e) - E_of(x - h * e)) / (2 * h) for e in np.eye(3)]) * hc
+        gw = np.array([(orc.wp2(s, x + h * e, t0) - orc.wp2(s, x - h * e, t0)) / (2 * h) for e in np.eye(3)])
+        nrm = gw / np.linalg.norm(gw)
+        kh = k / np.linalg.norm(k)
+        B = orc.bfield(s, x, t0)
+        cb = kh @ B / np.linalg.norm(B)
+        wp2 = orc.wp2(s, x, t0) * w_inf ** 2
+        D = cb ** 2 * wp2 * (wp2 - 2 * E ** 2) + E ** 4
+        P = 0.5 * math.pi * g ** 2 * (B @ B) * G2 ** 2 * (1 - cb ** 2) * E ** 5 / (D * abs(k @ gE))
+        ka = math.sqrt(w_inf ** 2 - ma ** 2)
+        n = x / r
+        gp = gw - (gw @ n) * n
+        V = r ** 2 * math.sqrt(1 + gp @ gp / (gw @ n) ** 2) / hc ** 2
+        w = 4 * math.pi * n_inf * V * abs(kh @ nrm) * ka * P
+        assert abs(w / rays[8, i] - 1) < 2e-6, (w, rays[8, i])
+        checked += 1
+    assert checked >= 10
+
+
 # ---------------------------------------------------------------- integrator
 def test_dopri_convergence_orders(orc):
     # fixed steps: global error of order 5

@@ -24,6 +24,9 @@ WEIGHTS_UNIT, WEIGHTS_CONVERSION, WEIGHTS_CONST_B = 0, 1, 2
 KDIR_ISOTROPIC, KDIR_OUTWARD = 0, 1
 SPEEDS_MONO, SPEEDS_MAXWELL = 0, 1
 FLAG_EXCISE_OPEN = 1  # no conversion on open magnetic field lines (Sec. 6)
+FLAG_FLAT_PROPAGATION = 2  # curved initial conditions, M = 0 in the tracing (App. B)
+FLAG_RENORM_WEIGHTS = 4  # P_ag = 1 and the rescaling R_i of Sec. 6 eq. (reweight)
+FLAG_THIN_SURFACE = 8  # resonance on w_p = m_a instead of k^a = k^gamma (App. B)
 
 STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
 STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE, STATUS_EXCISED = 4, 5, 6, 7
