@@ -339,6 +339,46 @@ def bench_magnetar(args, rt, W, np, torch):
     return out
 
 
+def bench_variants(args, rt, W, np, torch):
+    """The approximation variants of App. B and Sec. 6 beside the full method on the full
+    forward workload (1e6 seeds): time of seeding + tracing, escaped power relative to the
+    full method, and the change of the sky distribution: half the L1 distance between the
+    normalised escaped-power histograms over cos(theta) (64 bins) of the variant and of the
+    full method (0 = same shape, 1 = disjoint)."""
+    cfg = W.CFG2
+    n = cfg["n"]
+    out = {}
+    ref = None
+    for label, flag in (("full", 0), ("flat_propagation", W.FLAG_FLAT_PROPAGATION),
+                        ("thin_surface", W.FLAG_THIN_SURFACE), ("renormalised", W.FLAG_RENORM_WEIGHTS)):
+        star = dict(cfg["star"], flags=flag)
+        print(f"bench: variant {label}", file=sys.stderr, flush=True)
+        ws = rt.workspace(rt.OP_TRACE_FORWARD, n)
+        rays, st = rt.rt_sample_resonance(star, cfg["seed"], n)
+        fin, ifin = rt.rt_trace_forward(star, cfg["tol"], rays, st, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(2, min(args.steps, 3))
+        e0.record(torch.cuda.current_stream())
+        for _ in range(reps):
+            rays, st = rt.rt_sample_resonance(star, cfg["seed"], n)
+            fin, ifin = rt.rt_trace_forward(star, cfg["tol"], rays, st, ws=ws)
+        e1.record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        esc = (ifin[2] == 1).cpu().numpy()
+        w = rays[8].cpu().numpy()[esc]
+        ct = np.cos(fin[8].cpu().numpy()[esc])
+        h, _ = np.histogram(ct, bins=64, range=(-1.0, 1.0), weights=w)
+        h = h / h.sum()
+        if ref is None:
+            ref = (h, w.sum())
+        out[label] = dict(ms_per_step=e0.elapsed_time(e1) / reps, escaped_power_eV2=float(w.sum()) / n,
+                          power_vs_full=float(w.sum() / ref[1]),
+                          sky_shape_change=float(0.5 * np.abs(h - ref[0]).sum()))
+    out["workload"] = cfg["name"] + " (renormalised weights: P_ag = 1, arbitrary normalisation)"
+    return out
+
+
 def bench_adjoint(args, rt, W, np, torch):
     """Smoothed flux at 32 observers and its gradient with respect to the six star parameters
     (config-1 star, 1e6 rays, checkpoint every 64 accepted steps): forward phase (trace with
@@ -396,11 +436,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
-    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,magnetar,fbtotal",
+    ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,magnetar,variants,fbtotal",
                     help="comma list of forms to time beside plain (the headline value): batched, adjoint, "
                          "backward, maxwell (Maxwellian axion speeds), magnetar (models M1-M4 with excision "
-                         "and cyclotron absorption), fbtotal (forward against backward total power of the "
-                         "magnetar star)")
+                         "and cyclotron absorption), variants (flat propagation, thin surface, renormalised "
+                         "weights), fbtotal (forward against backward total power of the magnetar star)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the plain form's schedule too (default: the library's default schedule)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner in the batched form")
@@ -526,6 +566,8 @@ def main():
         out["forms"]["backward"] = bench_backward(args, rt, W, np, torch)
     if "magnetar" in forms:
         out["forms"]["magnetar"] = bench_magnetar(args, rt, W, np, torch)
+    if "variants" in forms:
+        out["forms"]["variants"] = bench_variants(args, rt, W, np, torch)
     if "maxwell" in forms:
         out["forms"]["maxwell"] = bench_maxwell(args, rt, W, np, torch)
     if "fbtotal" in forms:

@@ -45,10 +45,20 @@ enum { RT_DENSITY_GJ = 0, RT_DENSITY_MAGNETAR = 1,              /* eqs. (GJDensi
 enum { RT_WEIGHTS_UNIT = 0, RT_WEIGHTS_CONVERSION = 1, RT_WEIGHTS_CONST_B = 2 };
 enum { RT_KDIR_ISOTROPIC = 0, RT_KDIR_OUTWARD = 1 };
 enum { RT_SPEEDS_MONO = 0, RT_SPEEDS_MAXWELL = 1 };
-/* rt_star.flags: RT_FLAG_EXCISE_OPEN removes conversion on open magnetic field lines
-   (Sec. 6: r / sin^2 theta_mag >= r_LC = c / Omega): such seeds get RT_ST_EXCISED and weight
-   0, such backward events weigh 0 */
-enum { RT_FLAG_EXCISE_OPEN = 1 };
+/* rt_star.flags (bits):
+   RT_FLAG_EXCISE_OPEN removes conversion on open magnetic field lines (Sec. 6:
+     r / sin^2 theta_mag >= r_LC = c / Omega): such seeds get RT_ST_EXCISED and weight 0, such
+     backward events weigh 0;
+   the approximation variants (App. B; Sec. 6 eq. (reweight)), forward tracing only:
+   RT_FLAG_FLAT_PROPAGATION seeds with curved initial conditions (static-frame momentum and
+     local frequency) and traces with M = 0;
+   RT_FLAG_RENORM_WEIGHTS sets P_ag = 1 and rescales each ray by
+     R = (1 cm^-3 / n_a)(m_a / |k_a|)/sqrt(1 - r_s/r), i.e. w = C_k Vt |cos theta_n| m_a (1 cm^-3)/sqrt(A);
+   RT_FLAG_THIN_SURFACE seeds on w_p = m_a instead of the foliation k^a = k^gamma; the photon
+     keeps the axion's frequency and direction, |k| from the LO dispersion relation, and the
+     weight is the un-cancelled |cos theta_n| v_a E P_ag. */
+enum { RT_FLAG_EXCISE_OPEN = 1, RT_FLAG_FLAT_PROPAGATION = 2, RT_FLAG_RENORM_WEIGHTS = 4,
+       RT_FLAG_THIN_SURFACE = 8 };
 
 /* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
 typedef struct rt_star {

@@ -299,6 +299,8 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     if (ckpt_every <= 0 || ckpt_every > 1024 || max_ckpt <= 0)
         return fail(RT_EINVAL, "rt_flux_grad: need 1 <= ckpt_every <= 1024 and max_ckpt >= 1");
     if (star->weights == RT_WEIGHTS_CONST_B) return fail(RT_EUNSUPPORTED, "rt_flux_grad: constant-B test weights");
+    if (star->flags & RT_FLAG_FLAT_PROPAGATION)
+        return fail(RT_EUNSUPPORTED, "rt_flux_grad: flat-propagation variant");
     if (phase != 0 && phase != 1) return fail(RT_EINVAL, "rt_flux_grad: phase must be 0 (forward) or 1 (reverse)");
     const size_t need = rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt);
     if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_flux_grad: workspace too small");

@@ -144,6 +144,8 @@ extern "C" int rt_batch_prepare(const rt_star* stars, int32_t n_inst, const int6
         if (stars[k].plasma != stars[0].plasma || stars[k].density != stars[0].density ||
             stars[k].weights != stars[0].weights || stars[k].kdir != stars[0].kdir)
             return fail(RT_EINVAL, "rt_batch_prepare: instances must share plasma, density, weights and kdir");
+        if (stars[k].flags & RT_FLAG_FLAT_PROPAGATION)
+            return fail(RT_EUNSUPPORTED, "rt_batch_prepare: flat-propagation variant");
     }
     int64_t N = ray_offset[n_inst];
     if (N > INT32_MAX) return fail(RT_EINVAL, "rt_batch_prepare: more than 2^31 - 1 rays");

@@ -205,7 +205,7 @@ enum { KD_ISO = 0, KD_OUT = 1 };
 enum { SP_MONO = 0, SP_MAXWELL = 1 };
 enum { ST_OK = 0, ST_ESCAPED = 1, ST_HIT_STAR = 2, ST_NO_RESONANCE = 3, ST_MAX_STEPS = 4,
        ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6, ST_EXCISED = 7 };
-enum { FLAG_EXCISE_OPEN = 1 };
+enum { FLAG_EXCISE_OPEN = 1, FLAG_FLAT_PROPAGATION = 2, FLAG_RENORM_WEIGHTS = 4, FLAG_THIN_SURFACE = 8 };
 
 template <class T>
 struct InstT {

@@ -395,6 +395,8 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_trace_forward: workspace too small");
     rt_schedule sc = resolve_schedule(sched);
     InstT<double> I = make_inst(*star);
+    // flat-propagation variant: Hamilton's equations with M = 0 for curved initial conditions
+    if (star->flags & RT_FLAG_FLAT_PROPAGATION) I.rs = 0.0;
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     FwdWs W = carve_fwd_ws(ws, n);
     hipStream_t st = (hipStream_t)stream;

@@ -130,7 +130,7 @@ RT_HD InstT<S> lift_inst(const InstT<T>& I) {
 //   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
 // (isotropic plasma: F = P - m_a^2), at a general point x, for axis m.
 template <class S, class T>
-RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3], double om2) {
+RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3], double om2, bool thin) {
     InstT<S> J = lift_inst<S>(I);
     S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
     S ir = rcp(r);
@@ -138,7 +138,7 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
     S mm[3] = {S(m[0]), S(m[1]), S(m[2])};
     S mu = mm[0] * n[0] + mm[1] * n[1] + mm[2] * n[2];
     Plasma<S> pl = plasma_eval(J, n, ir, mm, mu, S(0.0));
-    if (I.plasma == PL_ISO) return pl.P - J.ma2;
+    if (I.plasma == PL_ISO || thin) return pl.P - J.ma2;
     S u[3];
     for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - mm[i];
     S ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
@@ -150,14 +150,14 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
 // F along the radial line through n at radius r (values only: the bisection)
 template <class T>
 RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m[3], double mu, double cB2,
-                            double om2, double r) {
+                            double om2, bool thin, double r) {
     InstT<double> J;
     J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
     J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2);
     J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
     double ir = 1.0 / r;
     Plasma<double> pl = plasma_eval(J, n, ir, m, mu, 0.0);
-    if (I.plasma == PL_ISO) return pl.P - J.ma2;
+    if (I.plasma == PL_ISO || thin) return pl.P - J.ma2;
     double w2 = om2 / (1.0 - J.rs * ir);
     return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
 }
@@ -263,19 +263,21 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     const double x2 = (C.speeds == SP_MAXWELL) ? maxwell_x(u[5]) : 1.0;
     const double om2 = value(I.ma2) + x2 * C.kv2;
     const double om = ::sqrt(om2);
+    // thin-surface variant: the resonance on w_p = m_a alone
+    const bool thin = (C.flags & FLAG_THIN_SURFACE) != 0;
 
     // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
     double R = value(I.R);
     double rcv = -1.0;
-    if (resonance_line(I, n, m, mu, cB2, om2, R) > 0.0) {
+    if (resonance_line(I, n, m, mu, cB2, om2, thin, R) > 0.0) {
         double lo = R, hi = 2.0 * R;
         int j = 0;
-        while (!(resonance_line(I, n, m, mu, cB2, om2, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
-        if (resonance_line(I, n, m, mu, cB2, om2, hi) < 0.0) {
+        while (!(resonance_line(I, n, m, mu, cB2, om2, thin, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
+        if (resonance_line(I, n, m, mu, cB2, om2, thin, hi) < 0.0) {
             for (int it = 0; it < 200; ++it) {
                 double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
-                if (resonance_line(I, n, m, mu, cB2, om2, mid) > 0.0) lo = mid; else hi = mid;
+                if (resonance_line(I, n, m, mu, cB2, om2, thin, mid) > 0.0) lo = mid; else hi = mid;
             }
             rcv = 0.5 * (lo + hi);
         }
@@ -292,7 +294,7 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
         D1 rd{T(rcv)};
         rd.d[0] = T(1.0);
         D1 xd[3] = {rd * n[0], rd * n[1], rd * n[2]};
-        D1 Fd = resonance_point<D1, T>(I, xd, mT, kh, om2);
+        D1 Fd = resonance_point<D1, T>(I, xd, mT, kh, om2, thin);
         rc = T(rcv) - Fd.v * rcp(Fd.d[0]);
         set_value(rc, rcv);
     }
@@ -310,15 +312,39 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
             return ST_EXCISED;
         }
     }
-    // photon covariant momentum from the static-frame axion momentum |k_a| kh
-    T ko[3] = {ka * kh[0], ka * kh[1], ka * kh[2]};
+    // photon covariant momentum from the static-frame axion momentum |k_a| kh; on the thin
+    // surface the photon keeps kh and the frequency, with |k|^2 = E^2 (E^2 - P)/(E^2 - P cos^2)
+    // from the LO dispersion relation (P = w_p^2 there)
+    T kg = ka;
+    if (thin && I.plasma == PL_ANISO) {
+        T ir0 = rcp(rc);
+        T nT0[3] = {T(n[0]), T(n[1]), T(n[2])};
+        T mu0 = mT[0] * nT0[0] + mT[1] * nT0[1] + mT[2] * nT0[2];
+        Plasma<T> p0 = plasma_eval(I, nT0, ir0, mT, mu0, T(0.0));
+        // cos^2 between kh and the dipole direction 3 mu n - m (the axis depends on theta_m, P)
+        T ku0 = T(0.0);
+        for (int d = 0; d < 3; ++d) ku0 = ku0 + kh[d] * (3.0 * mu0 * n[d] - mT[d]);
+        T cB20 = ku0 * ku0 * rcp(1.0 + 3.0 * mu0 * mu0);
+        T E2 = om2 * rcp(A);
+        kg = sqrt(E2 * (E2 - p0.P) * rcp(E2 - p0.P * cB20));
+    }
+    T ko[3] = {kg * kh[0], kg * kh[1], kg * kh[2]};
     T nko = n[0] * ko[0] + n[1] * ko[1] + n[2] * ko[2];
     T corr = nko * rcp(sA) - nko;
     T k[3] = {ko[0] + corr * n[0], ko[1] + corr * n[1], ko[2] + corr * n[2]};
     out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = t0;
     out[4] = k[0]; out[5] = k[1]; out[6] = k[2]; out[7] = T(-om);
     out[9] = rc;
-    if (C.weights == W_UNIT) { out[8] = T(1.0); return ST_OK; }
+    // flat-propagation variant: the photon leaves with its static-frame momentum and local
+    // frequency (to be traced with M = 0); the weight below uses the curved state
+    auto finish = [&]() {
+        if (C.flags & FLAG_FLAT_PROPAGATION) {
+            out[4] = ko[0]; out[5] = ko[1]; out[6] = ko[2];
+            out[7] = -(om * rcp(sA));
+        }
+        return ST_OK;
+    };
+    if (C.weights == W_UNIT) { out[8] = T(1.0); return finish(); }
 
     // ---- weight w = C_k n_c Vt Q ----
     const double Ck = (C.kdir == KD_ISO) ? 4.0 * phys::pi : 2.0 * phys::pi;
@@ -327,12 +353,24 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     typedef gdual<3, T> D3;
     D3 xd[3];
     for (int d = 0; d < 3; ++d) { xd[d] = D3(x[d]); xd[d].d[d] = T(1.0); }
-    D3 Fd = resonance_point<D3, T>(I, xd, mT, kh, om2);
+    D3 Fd = resonance_point<D3, T>(I, xd, mT, kh, om2, thin);
     T Fr = n[0] * Fd.d[0] + n[1] * Fd.d[1] + n[2] * Fd.d[2];
     T gp2 = T(0.0);
     for (int d = 0; d < 3; ++d) { T gp = Fd.d[d] - Fr * n[d]; gp2 = gp2 + gp * gp; }
     // sqrt|g_tt| times the printed sqrt|h_k| (which already carries A^{1/2})
     T Vt = A * rc * rc * sqrt(1.0 + gp2 * rcp(A * Fr * Fr)) * (1.0 / (C.hbarc * C.hbarc));
+    // cos theta_n (eq. (AngleDef)): kh against the surface normal in the static orthonormal
+    // frame, whose radial component is sqrt(A) F_r
+    T khg = kh[0] * Fd.d[0] + kh[1] * Fd.d[1] + kh[2] * Fd.d[2];
+    T khn = kh[0] * n[0] + kh[1] * n[1] + kh[2] * n[2];
+    T cos_n = (khg - Fr * khn + sA * Fr * khn) * rcp(sqrt(gp2 + A * Fr * Fr));
+    if (C.flags & FLAG_RENORM_WEIGHTS) {
+        // Sec. 6 eq. (reweight): P_ag = 1, rescaled by (1 cm^-3/n_a)(m_a/|k_a|)/sqrt(A)
+        const double n1 = phys::hbarc_eVcm * phys::hbarc_eVcm * phys::hbarc_eVcm;  // 1 cm^-3 [eV^3]
+        T m_a = C.w_inf * sqrt(I.ma2);
+        out[8] = Ck * Vt * fabs(cos_n) * m_a * n1 * rcp(sA);
+        return finish();
+    }
     T E = (C.w_inf * om) * rcp(sA);
     T ir = rcp(rc);
     T Rr = I.R * ir;
@@ -369,10 +407,21 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
         T c2 = cB2T, s2 = 1.0 - cB2T;
         T Dd = (E * E - c2 * wp2) * (E * E - c2 * wp2) + c2 * s2 * wp2 * wp2;
         T E2 = E * E;
-        Q = (0.5 * phys::pi * C.g2) * Bperp2 * E2 * E2 * E * rcp(Dd * dEn);
+        if (thin) {
+            // no cancellation on the thin surface: Q = |cos theta_n| v_a E P_ag, with the photon's
+            // k.dE = k^a d_a E (contravariant k = k - s (n.k) n)
+            T q = n[0] * k[0] + n[1] * k[1] + n[2] * k[2];
+            T kdE = T(0.0);
+            for (int a = 0; a < 3; ++a) kdE = kdE + (k[a] - s * q * n[a]) * dE[a];
+            kdE = (C.hbarc * C.w_inf * C.w_inf) * kdE;
+            T Pag = (0.5 * phys::pi * C.g2) * Bperp2 * E2 * E2 * E * rcp(Dd * fabs(kdE));
+            Q = fabs(cos_n) * (ka * C.w_inf) * Pag;
+        } else {
+            Q = (0.5 * phys::pi * C.g2) * Bperp2 * E2 * E2 * E * rcp(Dd * dEn);
+        }
     }
     out[8] = Ck * n_c * Vt * Q;
-    return ST_OK;
+    return finish();
 }
 
 // Resonant cyclotron absorption (Sec. 6).  The escaped photon is taken to move radially along

@@ -1,0 +1,97 @@
+"""GPU parity of the approximation variants (App. B; Sec. 6 eq. (reweight)) against the CPU
+oracle: flat propagation of curved initial conditions, renormalised weights and the thin
+resonance surface w_p = m_a.  Seeds: statuses equal, states 1e-12, weights 1e-9 relative (the
+same criteria as the plain method); traces with the conditioning-aware criterion; the
+smoothed-flux adjoint on the kink-free spherical star (every ray well conditioned) per ray
+1e-8 and in total; unsupported combinations are refused."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import assert_trace_parity, oracle_conditioning
+from tests.test_gpu_adjoint import PER_RAY_TOL, SPHERICAL, gpu_flux_grad, per_ray_errors
+
+pytestmark = pytest.mark.gpu
+
+FLAGS = {"flat": W.FLAG_FLAT_PROPAGATION, "renorm": W.FLAG_RENORM_WEIGHTS, "thin": W.FLAG_THIN_SURFACE}
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_08655_amd as rt
+    rt.lib()
+    return rt
+
+
+@pytest.mark.parametrize("variant", sorted(FLAGS))
+@pytest.mark.parametrize("base", ["cfg1", "cfg2"])
+def test_variant_seeds_match_oracle(rt, orc, variant, base):
+    cfg = {"cfg1": W.CFG1, "cfg2": W.CFG2}[base]
+    s = dict(cfg["star"], flags=FLAGS[variant])
+    n = 3000
+    print(f"variant seeds {variant} {base}", flush=True)
+    rays_g, st_g = rt.rt_sample_resonance(s, cfg["seed"], n)
+    rays_g, st_g = rays_g.cpu().numpy(), st_g.cpu().numpy()
+    rays_o, st_o = orc.sample(s, cfg["seed"], n)
+    assert np.array_equal(st_g, st_o)
+    ok = st_o == 0
+    assert ok.sum() > n // 2
+    scale = np.maximum(np.abs(rays_o[:8]), 1e-3)
+    assert np.max(np.abs(rays_g[:8, ok] - rays_o[:8, ok]) / scale[:, ok]) < 1e-12
+    assert np.max(np.abs(rays_g[8, ok] / rays_o[8, ok] - 1)) < 1e-9
+
+
+@pytest.mark.parametrize("variant", ["flat", "thin"])
+def test_variant_traces_match_oracle(rt, orc, variant):
+    import torch
+    cfg = W.CFG2
+    s = dict(cfg["star"], flags=FLAGS[variant])
+    n = 2048
+    print(f"variant traces {variant}", flush=True)
+    rays_o, st_o = orc.sample(s, cfg["seed"], n)
+    fin_o, ifin_o = orc.trace_forward(s, cfg["tol"], rays_o, st_o)
+    fin_g, ifin_g = rt.rt_trace_forward(s, cfg["tol"], torch.from_numpy(rays_o).cuda(), torch.from_numpy(st_o).cuda())
+    sd, ch = oracle_conditioning(orc, s, cfg["tol"], rays_o, st_o, fin_o, ifin_o)
+    out = assert_trace_parity(fin_g.cpu().numpy(), ifin_g.cpu().numpy(), fin_o, ifin_o, sd, ch)
+    print(out, flush=True)
+    assert out["well"] >= 0.15 * out["escaped"]
+
+
+@pytest.mark.parametrize("variant", ["renorm", "thin"])
+def test_variant_adjoint_matches_oracle(rt, orc, variant):
+    s = dict(SPHERICAL, flags=FLAGS[variant])
+    tol = W.tol()
+    obs = W.observers(32)
+    n = 300
+    gbar = np.random.default_rng(12).standard_normal(32)
+    print(f"variant adjoint {variant}", flush=True)
+    F, g, gr, info = gpu_flux_grad(rt, s, tol, 0, n, obs, 0.05, gbar)
+    Fo, dFo, fray, dray, sto = orc.flux_fwdmode(s, tol, 0, n, obs, 0.05, per_ray=True)
+    assert np.array_equal(info[2], sto)
+    esc = sto == W.STATUS_ESCAPED
+    assert esc.sum() > 100
+    go = np.einsum("j,njq->nq", gbar, dray)
+    err = per_ray_errors(gr, go)
+    assert err[esc].max() <= PER_RAY_TOL, err[esc].max()
+    assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
+    assert np.linalg.norm(g - gbar @ dFo) <= PER_RAY_TOL * np.linalg.norm(gbar @ dFo)
+
+
+def test_unsupported_combinations_are_refused(rt):
+    import torch
+    flat = dict(W.CFG2["star"], flags=W.FLAG_FLAT_PROPAGATION)
+    with pytest.raises(rt.RtError, match="flat-propagation"):
+        rt.FluxGrad(flat, W.tol(), 0, 64, W.observers(4), 0.05, 64, 64).forward()
+    image = dict(D_km=1e5, incl=1.0, phi_o=0.0, half_width_km=40.0, nx=8, ny=8)
+    with pytest.raises(rt.RtError, match="forward only"):
+        rt.rt_trace_backward(flat, W.tol(r_max_km=1e5), image, K=2)
+    ev, nev, _, _ = rt.rt_trace_backward(W.CFG3["star"], W.CFG3["tol"], image, K=2)
+    with pytest.raises(rt.RtError, match="forward only"):
+        rt.rt_backward_power(dict(W.CFG3["star"], flags=W.FLAG_RENORM_WEIGHTS), ev, nev, pixel_area_km2=1.0)
+    with pytest.raises(rt.RtError, match="flat-propagation"):
+        rt.Batch([flat, flat], [10, 10], 0, W.tol(), W.CFG4["bins"])
+    with pytest.raises(rt.RtError, match="enumeration"):
+        rt.rt_sample_resonance(dict(W.CFG2["star"], flags=16), 0, 8)
