@@ -12,12 +12,14 @@ LIB = os.path.join(HERE, "librt.so")
 SOURCES = ["rt_api.hip", "rt_forward.hip", "rt_backward.hip", "rt_batched.hip", "rt_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# Per-file additions.  The adjoint's forward pass and its recompute inline the same step
-# code into two kernels.  With -ffp-contract=on, multiply-adds are fused only within one
+# Per-file additions.  With -ffp-contract=on, multiply-adds are fused only within one
 # source expression, decided by the front end, never by the backend across the inlined
-# context: every copy produces the same bits, and the recompute replays the forward
-# pass's accept/reject decisions exactly.
-FILE_FLAGS = {"rt_adjoint.hip": ["-ffp-contract=on"]}
+# context, so every copy of the step code produces the same bits: the adjoint's recompute
+# replays its forward pass's accept/reject decisions exactly, and the tracing kernels
+# specialised at compile time for one plasma, density and rotation round exactly like the
+# generic ones (results do not depend on the schedule).
+FILE_FLAGS = {"rt_adjoint.hip": ["-ffp-contract=on"], "rt_forward.hip": ["-ffp-contract=on"],
+              "rt_backward.hip": ["-ffp-contract=on"]}
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

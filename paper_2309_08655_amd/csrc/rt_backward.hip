@@ -116,7 +116,7 @@ __device__ __forceinline__ void write_final_bwd(const InstT<double>& I, const do
     ifin[2 * n + p] = status;
 }
 
-template <int BLOCK, int MINW>
+template <int BLOCK, int MINW, int SPEC = 0>
 __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I, TolC tol, double D, int64_t n,
                                                           WorkCtr* ctr, const int32_t* __restrict__ list,
                                                           const double* __restrict__ h0s,
@@ -125,6 +125,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
                                                           double* __restrict__ ev, int32_t* __restrict__ nev,
                                                           double* __restrict__ fin, int32_t* __restrict__ ifin,
                                                           int refill_min) {
+    // specialised instantiations (SPEC = 1 + plasma + 2 density + 8 oblique) fix these
+    // switches at compile time, with the same arithmetic as the generic kernel
+    if constexpr (SPEC > 0) {
+        I.plasma = (SPEC - 1) & 1;
+        I.density = ((SPEC - 1) >> 1) & 3;
+        I.oblique = ((SPEC - 1) >> 3) & 1;
+    }
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
@@ -245,14 +252,14 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
     if (lane == 0) atomicAdd(&ctr->iters, iters);
 }
 
-template <int BLOCK, int MINW>
+template <int BLOCK, int MINW, int SPEC = 0>
 static int launch_bwd_block(const rt_schedule& sc, const InstT<double>& I, const TolC& T, double D, int64_t n,
                             const FwdWs& W, const double* y0s, int32_t K, double* ev, int32_t* nev, double* fin,
                             int32_t* ifin, hipStream_t st) {
-    int grid = persistent_grid(sc, (const void*)trace_bwd_kernel<BLOCK, MINW>, BLOCK);
+    int grid = persistent_grid(sc, (const void*)trace_bwd_kernel<BLOCK, MINW, SPEC>, BLOCK);
     timing_begin(st, RT_KERNEL_TRACE_BACKWARD);
-    hipLaunchKernelGGL((trace_bwd_kernel<BLOCK, MINW>), dim3(grid), dim3(BLOCK), 0, st, I, T, D, n, W.ctr, W.list,
-                       W.h0, W.k1, y0s, K, ev, nev, fin, ifin, sc.refill_min);
+    hipLaunchKernelGGL((trace_bwd_kernel<BLOCK, MINW, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, T, D, n, W.ctr,
+                       W.list, W.h0, W.k1, y0s, K, ev, nev, fin, ifin, sc.refill_min);
     timing_end(st);
     return check_launch("trace_bwd_kernel");
 }
@@ -325,6 +332,18 @@ static int trace_backward_common(const rt_star* star, const rt_tol* tol, const I
     hipLaunchKernelGGL(bwd_init_kernel, dim3(grid), dim3(256), 0, st, I, T, im, n, W.ctr, W.list, W.h0, W.k1, y0s, nev);
     int rc = check_launch("bwd_init_kernel");
     if (rc) return rc;
+    if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128) {
+        const int spec = 1 + (I.plasma & 1) + 2 * (I.density & 3) + 8 * (I.oblique ? 1 : 0);
+#define RT_BWD_SPEC(S) \
+    case S: return launch_bwd_block<256, 2, S>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+        switch (spec) {
+            RT_BWD_SPEC(1) RT_BWD_SPEC(2) RT_BWD_SPEC(3) RT_BWD_SPEC(4) RT_BWD_SPEC(5) RT_BWD_SPEC(6)
+            RT_BWD_SPEC(7) RT_BWD_SPEC(8) RT_BWD_SPEC(9) RT_BWD_SPEC(10) RT_BWD_SPEC(11) RT_BWD_SPEC(12)
+            RT_BWD_SPEC(13) RT_BWD_SPEC(14) RT_BWD_SPEC(15)
+            default: return launch_bwd_block<256, 2, 16>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);
+        }
+#undef RT_BWD_SPEC
+    }
     if (sc.occupancy == 2) {
         switch (sc.block) {
             case 64: return launch_bwd_block<64, 2>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const
 // instance constants on refill (plasma and density types are common to all
 // instances; the rotating-axis formula is used for every lane when any instance
 // is oblique, exact for the aligned ones).
-template <int BLOCK, int MINW, bool BATCHED>
+template <int BLOCK, int MINW, bool BATCHED, int SPEC = 0>
 __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
                                                           const int32_t* __restrict__ inst_of, int any_oblique,
                                                           TolC tol, const double* __restrict__ rays,
@@ -116,6 +116,15 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           int32_t* __restrict__ ifin, int refill_min) {
     InstT<double> I = I0;
     if (BATCHED) I.oblique = any_oblique;
+    // a specialised instantiation (SPEC = 1 + plasma + 2 density + 8 oblique) fixes these
+    // switches at compile time: the Hamiltonian and its gradient become branch-free code with
+    // the same arithmetic (the file is built with -ffp-contract=on, so the generic and the
+    // specialised kernels round identically)
+    if constexpr (SPEC > 0) {
+        I.plasma = (SPEC - 1) & 1;
+        I.density = ((SPEC - 1) >> 1) & 3;
+        I.oblique = ((SPEC - 1) >> 3) & 1;
+    }
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
@@ -408,14 +417,14 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
 }
 
 namespace rtd {
-template <int BLOCK, int MINW, bool BATCHED>
+template <int BLOCK, int MINW, bool BATCHED, int SPEC = 0>
 static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
                             const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                             const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
-    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED>, BLOCK);
+    int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>, BLOCK);
     timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
-    hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED>), dim3(grid), dim3(BLOCK), 0, st, I, itab, inst_of,
-                       any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min);
+    hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, itab,
+                       inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min);
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;
@@ -424,10 +433,45 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
     return check_launch("finalize_kernel");
 }
 
+// the default schedule (256 threads, occupancy 2) of a single star: one instantiation per
+// (plasma, density, rotation)
+template <int S>
+static int launch_spec(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays, int64_t n,
+                       const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    return launch_fwd_block<256, 2, false, S>(sc, I, nullptr, nullptr, 0, T, rays, n, W, fin, ifin, st);
+}
+
+static int launch_specialised(const rt_schedule& sc, const InstT<double>& I, const TolC& T, const double* rays,
+                              int64_t n, const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    const int spec = 1 + (I.plasma & 1) + 2 * (I.density & 3) + 8 * (I.oblique ? 1 : 0);
+    switch (spec) {
+        case 1: return launch_spec<1>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 2: return launch_spec<2>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 3: return launch_spec<3>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 4: return launch_spec<4>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 5: return launch_spec<5>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 6: return launch_spec<6>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 7: return launch_spec<7>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 8: return launch_spec<8>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 9: return launch_spec<9>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 10: return launch_spec<10>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 11: return launch_spec<11>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 12: return launch_spec<12>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 13: return launch_spec<13>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 14: return launch_spec<14>(sc, I, T, rays, n, W, fin, ifin, st);
+        case 15: return launch_spec<15>(sc, I, T, rays, n, W, fin, ifin, st);
+        default: return launch_spec<16>(sc, I, T, rays, n, W, fin, ifin, st);
+    }
+}
+
 template <bool BATCHED>
 static int launch_trace_variant(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
                                 const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                                 const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    if constexpr (!BATCHED) {
+        if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128)
+            return launch_specialised(sc, I, T, rays, n, W, fin, ifin, st);
+    }
     if (sc.occupancy == 2) {
         switch (sc.block) {
             case 64: return launch_fwd_block<64, 2, BATCHED>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
