@@ -114,17 +114,21 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
                                                           int32_t* __restrict__ ifin, int refill_min) {
-    InstT<double> I = I0;
-    if (BATCHED) I.oblique = any_oblique;
     // a specialised instantiation (SPEC = 1 + plasma + 2 density + 8 oblique) fixes these
     // switches at compile time: the Hamiltonian and its gradient become branch-free code with
     // the same arithmetic (the file is built with -ffp-contract=on, so the generic and the
-    // specialised kernels round identically)
-    if constexpr (SPEC > 0) {
-        I.plasma = (SPEC - 1) & 1;
-        I.density = ((SPEC - 1) >> 1) & 3;
-        I.oblique = ((SPEC - 1) >> 3) & 1;
-    }
+    // specialised kernels round identically).  Batched instances share plasma and density,
+    // and all take the batch's rotation switch.
+    auto fix = [&](InstT<double>& J) {
+        if (BATCHED) J.oblique = any_oblique;
+        if constexpr (SPEC > 0) {
+            J.plasma = (SPEC - 1) & 1;
+            J.density = ((SPEC - 1) >> 1) & 3;
+            J.oblique = ((SPEC - 1) >> 3) & 1;
+        }
+    };
+    InstT<double> I = I0;
+    fix(I);
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
@@ -157,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                         j = list[q];
                         if (BATCHED) {
                             I = itab[inst_of[j]];
-                            I.oblique = any_oblique;
+                            fix(I);
                         }
                         for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
                         h = h0s[j];
@@ -464,6 +468,29 @@ static int launch_specialised(const rt_schedule& sc, const InstT<double>& I, con
     }
 }
 
+// batched launches at 256 threads: one instantiation per (plasma, density, rotation) and occupancy
+template <int MINW, int S>
+static int launch_bspec(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
+                        const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
+                        const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    return launch_fwd_block<256, MINW, true, S>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+}
+
+template <int MINW>
+static int launch_batched_specialised(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
+                                      const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays,
+                                      int64_t n, const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
+    const int spec = 1 + (I.plasma & 1) + 2 * (I.density & 3) + 8 * (any_oblique ? 1 : 0);
+#define RT_BSPEC(S) \
+    case S: return launch_bspec<MINW, S>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+    switch (spec) {
+        RT_BSPEC(1) RT_BSPEC(2) RT_BSPEC(3) RT_BSPEC(4) RT_BSPEC(5) RT_BSPEC(6) RT_BSPEC(7) RT_BSPEC(8)
+        RT_BSPEC(9) RT_BSPEC(10) RT_BSPEC(11) RT_BSPEC(12) RT_BSPEC(13) RT_BSPEC(14) RT_BSPEC(15)
+        default: return launch_bspec<MINW, 16>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+    }
+#undef RT_BSPEC
+}
+
 template <bool BATCHED>
 static int launch_trace_variant(const rt_schedule& sc, const InstT<double>& I, const InstT<double>* itab,
                                 const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
@@ -471,6 +498,12 @@ static int launch_trace_variant(const rt_schedule& sc, const InstT<double>& I, c
     if constexpr (!BATCHED) {
         if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128)
             return launch_specialised(sc, I, T, rays, n, W, fin, ifin, st);
+    } else {
+        if (sc.block != 64 && sc.block != 128) {
+            if (sc.occupancy == 2)
+                return launch_batched_specialised<2>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+            return launch_batched_specialised<1>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
+        }
     }
     if (sc.occupancy == 2) {
         switch (sc.block) {
