@@ -231,7 +231,11 @@ def forward_vs_backward_total(rt, W, np, torch, n_mu=24, n_phi=8, npx=1024, half
     """Total power of the magnetar workload star two ways (Sec. 2.4 reports agreement within
     a few percent): forward, the escaped seed weight over N = 2e6 seeds; backward, the image
     sum dP/dOmega over n_mu Gauss-Legendre polar nodes x n_phi azimuths of npx^2 pixels at
-    1e5 km, integrated over the sky (the rotating star's total is time independent)."""
+    1e5 km, integrated over the sky (the rotating star's total is time independent).  The
+    azimuth-averaged dP/dOmega at each polar node is also set against the forward escaped
+    weight per unit solid angle in the cell of cos(theta) around the node (Fig. 4's
+    comparison); polar_shape_distance is half the L1 distance of the two normalised polar
+    distributions."""
     star = W.CFG3["star"]
     tol = W.tol(r_max_km=1e5)
     N = 2_000_000
@@ -247,6 +251,7 @@ def forward_vs_backward_total(rt, W, np, torch, n_mu=24, n_phi=8, npx=1024, half
     ws = rt.workspace(rt.OP_TRACE_BACKWARD, npx * npx)
     wsp = rt.workspace(rt.OP_BACKWARD_POWER, npx * npx)
     acc = {0.0: 0.0, 1.0: 0.0, 2.0: 0.0}
+    dpdo_b = {0.0: np.zeros(n_mu), 1.0: np.zeros(n_mu)}  # azimuth-averaged dP/dOmega per polar node
     for a in range(n_mu):
         for b in range(n_phi):
             image["incl"] = math.acos(xg[a])
@@ -255,10 +260,30 @@ def forward_vs_backward_total(rt, W, np, torch, n_mu=24, n_phi=8, npx=1024, half
             for Lc in acc:
                 _, tot = rt.rt_backward_power(star, ev, nev, Lc, pixel_area_km2=area, ws=wsp)
                 acc[Lc] += tot.item() * wg[a] * 2 * math.pi / n_phi
+                if Lc in dpdo_b:
+                    dpdo_b[Lc][a] += tot.item() / n_phi
+    # the forward side on the same polar nodes: escaped weight in the cell of cos(theta) around
+    # each node (bounded by the midpoints between nodes), per unit solid angle
+    mu = torch.cos(fin[8][esc]).cpu().numpy()
+    wf = rays[8][esc].cpu().numpy() / N
+    edges = np.concatenate([[-1.0], 0.5 * (xg[1:] + xg[:-1]), [1.0]])
+    cell, _ = np.histogram(mu, bins=edges, weights=wf)
+    dpdo_f = cell / (2 * math.pi * np.diff(edges))
+    pf = cell / cell.sum()
+    shape = {}
+    node_ratio = {}
+    for Lc, d in dpdo_b.items():
+        key = f"Lc_max_{Lc:g}km" if Lc else "no_cutoff"
+        pb = d * wg / (d * wg).sum()
+        shape[key] = float(0.5 * np.abs(pf - pb).sum())
+        node_ratio[key] = [float(x) for x in d / dpdo_f]
     return dict(workload=f"{W.CFG3['name']} star, {n_mu}x{n_phi} directions x {npx}^2 pixels, {N} forward seeds",
                 P_forward_eV2=P_fwd, P_backward_eV2={f"Lc_max_{k:g}km" if k else "no_cutoff": v
                                                      for k, v in acc.items()},
                 ratio={f"Lc_max_{k:g}km" if k else "no_cutoff": v / P_fwd for k, v in acc.items()},
+                polar_nodes_cos_theta=[float(x) for x in xg],
+                dP_dOmega_ratio_backward_over_forward=node_ratio,
+                polar_shape_distance=shape,
                 seconds=time.time() - t0)
 
 
