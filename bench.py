@@ -458,7 +458,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="rays per step (default: the workload's 1e6)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 16)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19,
+                    help="rays of the CPU oracle sample (about 15 s on 16 host threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--schedule", type=str, default=None, help="JSON rt_schedule override")
     ap.add_argument("--forms", type=str, default="plain,batched,adjoint,backward,maxwell,magnetar,variants,fbtotal",
