@@ -40,7 +40,8 @@ typedef struct {
     int32_t speeds;       /* 0 every axion at |k_inf| = m_a v0; 1 Maxwellian |k_inf|, dispersion k0 = m_a v0 */
     int32_t flags;        /* ORC_FLAG_* bits: 1 no conversion on open field lines (r / sin^2 theta_mag >= c/Omega);
                              2 flat propagation (curved initial conditions, M = 0 in the tracing);
-                             4 renormalised weights (P_ag = 1 times R_i); 8 thin surface w_p = m_a */
+                             4 renormalised weights (P_ag = 1 times R_i); 8 thin surface w_p = m_a;
+                             16 the Schwarzschild vacuum dipole instead of the flat one */
 } orc_star;
 
 typedef struct {
@@ -51,7 +52,7 @@ typedef struct {
 enum { ORC_OK = 0, ORC_ESCAPED = 1, ORC_HIT_STAR = 2, ORC_NO_RESONANCE = 3,
        ORC_MAX_STEPS = 4, ORC_STEP_UNDERFLOW = 5, ORC_NONFINITE = 6, ORC_EXCISED = 7 };
 enum { ORC_FLAG_EXCISE_OPEN = 1, ORC_FLAG_FLAT_PROPAGATION = 2, ORC_FLAG_RENORM_WEIGHTS = 4,
-       ORC_FLAG_THIN_SURFACE = 8 };
+       ORC_FLAG_THIN_SURFACE = 8, ORC_FLAG_GR_DIPOLE = 16 };
 
 /* number of doubles per final record and their order */
 #define ORC_NFIN 16  /* y_f[8], theta, phi, psi, omega, H_f, lam_f, r_f, h_last */

@@ -253,8 +253,29 @@ static S wp2_tilde(const Inst<P>& I, const S x[3], const S& t) {
     return I.Cwp * Rr3;  // spherical test profile
 }
 
-// Dipole field of polar strength B0 [G], components in the static orthonormal
-// frame (the flat-space dipole placed in that frame; identical at M = 0).
+// Radial profiles of the static vacuum dipole in Schwarzschild, x = r_s / r: the vector
+// potential is A_phi = (mu sin^2 theta / r) G(x) with
+//   G(x) = -3 [ln(1 - x) + x + x^2/2] / x^3 = 3 sum_{j>=0} x^j / (j + 3)   (G(0) = 1),
+// so that, in the static orthonormal frame,
+//   B_rhat = (2 mu cos theta / r^3) G,   B_thetahat = (mu sin theta / r^3) F,
+//   F = sqrt(1 - x) (G + x G')   (F follows from div B = 0, G from curl(sqrt(A) B) = 0).
+// The power series converges for x < 1 and has no cancellation.
+template <class S>
+static void gr_dipole_profiles(const S& x, S& G, S& F) {
+    S g = S(0.0), gp = S(0.0), xp = S(1.0);
+    for (int j = 0; j < 400; ++j) {
+        g = g + xp * (3.0 / (j + 3.0));
+        if (j >= 1) gp = gp + (3.0 * j / (j + 3.0)) * (xp / x);
+        xp = xp * x;
+        if (val(xp) < 1e-19) break;
+    }
+    G = g;
+    F = sqrt(1.0 - x) * (g + x * gp);
+}
+
+// Dipole field of polar surface strength B0 [G], components in the static orthonormal frame:
+// the flat-space dipole placed in that frame (identical at M = 0), or with the GR flag the
+// Schwarzschild vacuum dipole above, normalised to B0 at the surface pole.
 template <class S, class P>
 static void bfield_t(const Inst<P>& I, const S x[3], const S& t, S B[3]) {
     S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -264,6 +285,14 @@ static void bfield_t(const Inst<P>& I, const S x[3], const S& t, S B[3]) {
     S mu = dot3(m, n);
     S Rr = I.R / r;
     S amp = 0.5 * I.B0 * Rr * Rr * Rr;
+    if ((I.flags & ORC_FLAG_GR_DIPOLE) && val(I.rs) > 0.0) {
+        S G, F, GR, FR;
+        gr_dipole_profiles(S(0.0) + I.rs / r, G, F);
+        gr_dipole_profiles(S(0.0) + I.rs / I.R, GR, FR);
+        // B = (mu_B / r^3) [(2G + F) mu n - F m], mu_B = B0 R^3 / (2 G(r_s/R))
+        for (int i = 0; i < 3; ++i) B[i] = (amp / GR) * ((2.0 * G + F) * mu * n[i] - F * m[i]);
+        return;
+    }
     for (int i = 0; i < 3; ++i) B[i] = amp * (3.0 * mu * n[i] - m[i]);
 }
 

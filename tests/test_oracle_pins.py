@@ -657,6 +657,65 @@ def test_thin_surface_variant(orc):
     assert checked >= 10
 
 
+def test_gr_dipole_solves_maxwell_in_schwarzschild(orc):
+    """The Schwarzschild vacuum dipole (App. B's GR-corrected field): in the static orthonormal
+    frame its components satisfy div B = 0 with the spatial volume element r^2 sin/sqrt(A),
+      sin d_r(r^2 B_r) + (r/sqrt(A)) d_theta(sin B_theta) = 0,
+    and the static vacuum curl condition curl(sqrt(A) B) = 0,
+      d_r(sqrt(A) r B_theta) - d_theta B_r = 0,
+    both checked by central differences; the flat dipole placed in curved space fails the
+    second.  The profile G(x) matches -3 [ln(1-x) + x + x^2/2]/x^3, the surface polar field is
+    B0, and far away the field is the flat dipole of moment B0 R^3 / (2 G(r_s/R))."""
+    c = orc.constants()
+    M = 1.4
+    s = W.star(M_Msun=M, theta_m=0.0, flags=W.FLAG_GR_DIPOLE)
+    flat = W.star(M_Msun=M, theta_m=0.0)
+    rs = 2 * c["GMsun_km"] * M
+
+    def comps(star, r, th):
+        n = np.array([math.sin(th), 0.0, math.cos(th)])
+        e_th = np.array([math.cos(th), 0.0, -math.sin(th)])
+        B = orc.bfield(star, r * n, 0.0)
+        return B @ n, B @ e_th
+
+    R = s["R_km"]
+    Bp, _ = comps(s, R, 0.0)
+    assert abs(Bp / s["B0_G"] - 1) < 1e-13
+    hr, ht = 1e-4, 1e-5
+    worst_div = worst_curl = 0.0
+    flat_curl = 0.0
+    for r in (11.0, 15.0, 30.0):
+        A = 1 - rs / r
+        for th in (0.3, 0.9, 1.4):
+            br = lambda rr, tt, st=s: comps(st, rr, tt)[0]
+            bt = lambda rr, tt, st=s: comps(st, rr, tt)[1]
+            div = math.sin(th) * ((r + hr) ** 2 * br(r + hr, th) - (r - hr) ** 2 * br(r - hr, th)) / (2 * hr) \
+                + r / math.sqrt(A) * (math.sin(th + ht) * bt(r, th + ht) - math.sin(th - ht) * bt(r, th - ht)) / (2 * ht)
+            scale = abs(math.sin(th) * r * br(r, th)) + abs(r / math.sqrt(A) * math.cos(th) * bt(r, th))
+            worst_div = max(worst_div, abs(div) / scale)
+
+            def curl(st):
+                a = lambda rr: math.sqrt(1 - rs / rr) * rr * comps(st, rr, th)[1]
+                return (a(r + hr) - a(r - hr)) / (2 * hr) - (comps(st, r, th + ht)[0] - comps(st, r, th - ht)[0]) / (2 * ht)
+
+            sc = abs(comps(s, r, th)[0]) + abs(comps(s, r, th)[1])
+            worst_curl = max(worst_curl, abs(curl(s)) / sc)
+            flat_curl = max(flat_curl, abs(curl(flat)) / (abs(comps(flat, r, th)[0]) + abs(comps(flat, r, th)[1])))
+    assert worst_div < 1e-7 and worst_curl < 1e-7, (worst_div, worst_curl)
+    assert flat_curl > 1e-2
+    # the profile against its closed form: on the axis B_r = B0 (R/r)^3 G(r_s/r) / G(r_s/R)
+    Gc = lambda x: -3 * (math.log1p(-x) + x + x * x / 2) / x ** 3
+    xR = rs / R
+    G_R = Gc(xR)
+    for r in (R, 12.0, 20.0, 60.0):
+        b_axis, _ = comps(s, r, 0.0)
+        assert abs(b_axis / (s["B0_G"] * (R / r) ** 3) / (Gc(rs / r) / G_R) - 1) < 1e-10, r
+    r = 1e5
+    bg, _ = comps(s, r, 0.0)
+    bf, _ = comps(flat, r, 0.0)
+    assert abs(bg / bf * G_R - 1) < 1e-4
+
+
 # ---------------------------------------------------------------- integrator
 def test_dopri_convergence_orders(orc):
     # fixed steps: global error of order 5

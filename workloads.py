@@ -27,6 +27,7 @@ FLAG_EXCISE_OPEN = 1  # no conversion on open magnetic field lines (Sec. 6)
 FLAG_FLAT_PROPAGATION = 2  # curved initial conditions, M = 0 in the tracing (App. B)
 FLAG_RENORM_WEIGHTS = 4  # P_ag = 1 and the rescaling R_i of Sec. 6 eq. (reweight)
 FLAG_THIN_SURFACE = 8  # resonance on w_p = m_a instead of k^a = k^gamma (App. B)
+FLAG_GR_DIPOLE = 16  # the Schwarzschild vacuum dipole field instead of the flat one
 
 STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
 STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE, STATUS_EXCISED = 4, 5, 6, 7
