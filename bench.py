@@ -365,8 +365,8 @@ def bench_magnetar(args, rt, W, np, torch):
 
 
 def bench_variants(args, rt, W, np, torch):
-    """The approximation variants of App. B and Sec. 6 beside the full method on the full
-    forward workload (1e6 seeds): time of seeding + tracing, escaped power relative to the
+    """The approximation variants of App. B and Sec. 6, and the Schwarzschild vacuum dipole
+    field, beside the full method on the full forward workload (1e6 seeds): time of seeding + tracing, escaped power relative to the
     full method, and the change of the sky distribution: half the L1 distance between the
     normalised escaped-power histograms over cos(theta) (64 bins) of the variant and of the
     full method (0 = same shape, 1 = disjoint)."""
@@ -375,7 +375,8 @@ def bench_variants(args, rt, W, np, torch):
     out = {}
     ref = None
     for label, flag in (("full", 0), ("flat_propagation", W.FLAG_FLAT_PROPAGATION),
-                        ("thin_surface", W.FLAG_THIN_SURFACE), ("renormalised", W.FLAG_RENORM_WEIGHTS)):
+                        ("thin_surface", W.FLAG_THIN_SURFACE), ("renormalised", W.FLAG_RENORM_WEIGHTS),
+                        ("gr_dipole", W.FLAG_GR_DIPOLE)):
         star = dict(cfg["star"], flags=flag)
         print(f"bench: variant {label}", file=sys.stderr, flush=True)
         ws = rt.workspace(rt.OP_TRACE_FORWARD, n)

@@ -56,9 +56,15 @@ enum { RT_SPEEDS_MONO = 0, RT_SPEEDS_MAXWELL = 1 };
      R = (1 cm^-3 / n_a)(m_a / |k_a|)/sqrt(1 - r_s/r), i.e. w = C_k Vt |cos theta_n| m_a (1 cm^-3)/sqrt(A);
    RT_FLAG_THIN_SURFACE seeds on w_p = m_a instead of the foliation k^a = k^gamma; the photon
      keeps the axion's frequency and direction, |k| from the LO dispersion relation, and the
-     weight is the un-cancelled |cos theta_n| v_a E P_ag. */
+     weight is the un-cancelled |cos theta_n| v_a E P_ag;
+   RT_FLAG_GR_DIPOLE replaces the flat dipole placed in the static frame by the static vacuum
+     dipole of Schwarzschild (vector potential (mu sin^2 theta / r) G(r_s/r),
+     G(x) = -3 [ln(1 - x) + x + x^2/2]/x^3), normalised to B0 at the surface pole: the field
+     direction enters the LO Hamiltonian, its strength the conversion weights and the
+     cyclotron depth; the Goldreich-Julian density keeps its printed form.  Everywhere
+     (forward, backward, batched, adjoint). */
 enum { RT_FLAG_EXCISE_OPEN = 1, RT_FLAG_FLAT_PROPAGATION = 2, RT_FLAG_RENORM_WEIGHTS = 4,
-       RT_FLAG_THIN_SURFACE = 8 };
+       RT_FLAG_THIN_SURFACE = 8, RT_FLAG_GR_DIPOLE = 16 };
 
 /* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
 typedef struct rt_star {

@@ -32,6 +32,7 @@ inline FC rcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
 inline FC frcp(FC a) { ++g_flops; return FC(1.0 / a.v); }
 inline FC frcp_coarse(FC a) { ++g_flops; return FC(1.0 / a.v); }
 inline FC frsqrt(FC a) { ++g_flops; return FC(1.0 / std::sqrt(a.v)); }
+inline FC log1p_t(FC a) { ++g_flops; return FC(std::log1p(a.v)); }
 inline FC fabs(FC a) { return FC(std::fabs(a.v)); }
 inline FC fmax(FC a, FC b) { return FC(std::fmax(a.v, b.v)); }
 inline void sincos_t(FC a, FC* s, FC* c) { g_flops += 2; s->v = std::sin(a.v); c->v = std::cos(a.v); }
@@ -47,6 +48,7 @@ static InstT<FC> inst(int plasma, int density, bool oblique) {
     I.rs = FC(4.13); I.R = FC(10.0); I.Om = FC(2e-5); I.cm = FC(oblique ? 0.95 : 1.0);
     I.sm = FC(oblique ? 0.3 : 0.0); I.Cwp = FC(1.0); I.R3 = FC(1000.0); I.ma2 = FC(0.99);
     I.plasma = plasma; I.density = density; I.oblique = oblique ? 1 : 0;
+    I.gr_dipole = 0; I.bnorm = FC(1.0);
     return I;
 }
 

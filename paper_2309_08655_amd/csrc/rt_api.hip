@@ -42,7 +42,7 @@ bool validate_star(const rt_star* s) {
         return false;
     }
     if (s->plasma < 0 || s->plasma > 1 || s->density < 0 || s->density > 3 || s->weights < 0 || s->weights > 2 ||
-        s->kdir < 0 || s->kdir > 1 || s->speeds < 0 || s->speeds > 1 || (s->flags & ~15) != 0) {
+        s->kdir < 0 || s->kdir > 1 || s->speeds < 0 || s->speeds > 1 || (s->flags & ~31) != 0) {
         set_error("rt_star: enumeration out of range");
         return false;
     }

@@ -70,9 +70,10 @@ __global__ void __launch_bounds__(256) bwd_init_kernel(InstT<double> I, TolC tol
             if (I.plasma == PL_ISO) {
                 kap2 = w2 - pl.P;
             } else {
+                const DipoleShape<double> sh = dipole_shape(I, ir);
                 double u[3];
-                dipole_dir(nn, m, mu, u);
-                double cB = (im.no[0] * u[0] + im.no[1] * u[1] + im.no[2] * u[2]) / sqrt(1.0 + 3.0 * mu * mu);
+                dipole_dir(nn, m, mu, u, sh.g);
+                double cB = (im.no[0] * u[0] + im.no[1] * u[1] + im.no[2] * u[2]) / sqrt(1.0 + sh.c * mu * mu);
                 kap2 = w2 * (w2 - pl.P) / (w2 - pl.P * cB * cB);
             }
             double kap = sqrt(kap2);
@@ -127,10 +128,11 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
                                                           int refill_min) {
     // specialised instantiations (SPEC = 1 + plasma + 2 density + 8 oblique) fix these
     // switches at compile time, with the same arithmetic as the generic kernel
-    if constexpr (SPEC > 0) {
+    if constexpr (SPEC > 0) {  // the flat dipole (GR-dipole stars take the generic kernel)
         I.plasma = (SPEC - 1) & 1;
         I.density = ((SPEC - 1) >> 1) & 3;
         I.oblique = ((SPEC - 1) >> 3) & 1;
+        I.gr_dipole = 0;
     }
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -332,7 +334,7 @@ static int trace_backward_common(const rt_star* star, const rt_tol* tol, const I
     hipLaunchKernelGGL(bwd_init_kernel, dim3(grid), dim3(256), 0, st, I, T, im, n, W.ctr, W.list, W.h0, W.k1, y0s, nev);
     int rc = check_launch("bwd_init_kernel");
     if (rc) return rc;
-    if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128) {
+    if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128 && !I.gr_dipole) {
         const int spec = 1 + (I.plasma & 1) + 2 * (I.density & 3) + 8 * (I.oblique ? 1 : 0);
 #define RT_BWD_SPEC(S) \
     case S: return launch_bwd_block<256, 2, S>(sc, I, T, im.D, n, W, y0s, K, ev, nev, fin, ifin, st);

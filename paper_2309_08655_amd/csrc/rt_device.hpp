@@ -185,6 +185,13 @@ template <int N, class T> RT_HD gdual<N, T> exp(const gdual<N, T>& a) {
     for (int i = 0; i < N; ++i) r.d[i] = r.v * a.d[i];
     return r;
 }
+RT_HD double log1p_t(double a) { return ::log1p(a); }
+template <int N, class T> RT_HD gdual<N, T> log1p_t(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = log1p_t(a.v);
+    T g = rcp(1.0 + a.v);
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
 template <int N, class T> RT_HD gdual<N, T> atan2(const gdual<N, T>& y, const gdual<N, T>& x) {
     gdual<N, T> r; r.v = atan2(y.v, x.v);
     T den = rcp(x.v * x.v + y.v * y.v);
@@ -205,7 +212,8 @@ enum { KD_ISO = 0, KD_OUT = 1 };
 enum { SP_MONO = 0, SP_MAXWELL = 1 };
 enum { ST_OK = 0, ST_ESCAPED = 1, ST_HIT_STAR = 2, ST_NO_RESONANCE = 3, ST_MAX_STEPS = 4,
        ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6, ST_EXCISED = 7 };
-enum { FLAG_EXCISE_OPEN = 1, FLAG_FLAT_PROPAGATION = 2, FLAG_RENORM_WEIGHTS = 4, FLAG_THIN_SURFACE = 8 };
+enum { FLAG_EXCISE_OPEN = 1, FLAG_FLAT_PROPAGATION = 2, FLAG_RENORM_WEIGHTS = 4, FLAG_THIN_SURFACE = 8,
+       FLAG_GR_DIPOLE = 16 };
 
 template <class T>
 struct InstT {
@@ -217,8 +225,69 @@ struct InstT {
     T R3;      // R^3
     T ma2;     // (m_a / w_inf)^2
     int plasma, density;
-    int oblique;  // sm != 0
+    int oblique;    // sm != 0
+    int gr_dipole;  // the Schwarzschild vacuum dipole instead of the flat one
+    T bnorm;        // field-strength factor: 1, or 1 / G(r_s/R) for the GR dipole (B0 at the pole)
 };
+
+// ----------------------------------------------------------------------------
+// Dipole field shape.  The field is B = (B0/2) bnorm (R/r)^3 F (g mu n - m), mu = m.n, with
+// |g mu n - m|^2 = 1 + c mu^2, c = g^2 - 2g.  Flat dipole: g = 3, c = 3, F = 1.  Schwarzschild
+// vacuum dipole (x = r_s/r): the vector potential (mu sin^2/r) G(x),
+//   G(x) = -3 [ln(1 - x) + x + x^2/2] / x^3,  F = sqrt(1 - x) (G + x G'),  g = 1 + 2G/F,
+// with G from its power series 3 sum_j x^j/(j + 3) below x = 1/8 (no cancellation) and the
+// logarithm above.  dg and dc are the radial derivatives of g and c.
+// ----------------------------------------------------------------------------
+template <class T>
+struct DipoleShape {
+    T g, c, F, dg, dc;
+};
+
+template <class T>
+RT_HD void gr_dipole_G(const T& x, T& G, T& G1, T& G2) {
+    if (value(x) < 0.125) {
+        G = T(0.0); G1 = T(0.0); G2 = T(0.0);
+        T xp = T(1.0), xm1 = T(0.0), xm2 = T(0.0);  // x^j, x^(j-1), x^(j-2)
+        for (int j = 0; j < 26; ++j) {
+            const double a = 3.0 / (j + 3.0);
+            G = G + a * xp;
+            if (j >= 1) G1 = G1 + (a * j) * xm1;
+            if (j >= 2) G2 = G2 + (a * j * (j - 1)) * xm2;
+            xm2 = xm1;
+            xm1 = xp;
+            xp = xp * x;
+        }
+    } else {
+        const T ix = rcp(x), ix1 = rcp(1.0 - x);
+        const T S = log1p_t(T(0.0) - x) + x + 0.5 * x * x;
+        G = -3.0 * S * ix * ix * ix;
+        G1 = 3.0 * ix * ix1 - 3.0 * G * ix;          // G' = 3/(x(1-x)) - 3G/x
+        G2 = 3.0 * (2.0 * x - 1.0) * (ix * ix1) * (ix * ix1) - 3.0 * G1 * ix + 3.0 * G * ix * ix;
+    }
+}
+
+template <class T>
+RT_HD DipoleShape<T> dipole_shape(const InstT<T>& I, const T& ir) {
+    DipoleShape<T> d;
+    if (!I.gr_dipole) {
+        d.g = T(3.0); d.c = T(3.0); d.F = T(1.0); d.dg = T(0.0); d.dc = T(0.0);
+        return d;
+    }
+    const T x = I.rs * ir;
+    T G, G1, G2;
+    gr_dipole_G(x, G, G1, G2);
+    const T sq = sqrt(1.0 - x);
+    const T H = G + x * G1;
+    d.F = sq * H;
+    const T dF = (0.0 - 0.5) * H * rcp(sq) + sq * (2.0 * G1 + x * G2);  // dF/dx
+    const T iF = rcp(d.F);
+    d.g = 1.0 + 2.0 * G * iF;
+    const T dgdx = 2.0 * (G1 * d.F - G * dF) * iF * iF;
+    d.dg = (0.0 - x * ir) * dgdx;  // dx/dr = -x/r
+    d.c = d.g * d.g - 2.0 * d.g;
+    d.dc = (2.0 * d.g - 2.0) * d.dg;
+    return d;
+}
 
 // ----------------------------------------------------------------------------
 // plasma: P = w_p^2 / w_inf^2, its spatial gradient and time derivative
@@ -425,12 +494,16 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
         g[3] = g[3] + p.gt;
         return;
     }
-    // anisotropic (strong-B LO mode): H += P (1 - K)
+    // anisotropic (strong-B LO mode): H += P (1 - K), K = A N^2 / (k_t^2 (1 + c mu^2)),
+    // N = (static-frame k).(g mu n - m) = b mu q - m.k with b = 1 + (g - 1) sqrt(A)
+    // (flat dipole: g = c = 3)
     T a = A * ia;
-    T b = 1.0 + 2.0 * a;
+    DipoleShape<T> sh;
+    if (I.gr_dipole) sh = dipole_shape(I, ir);
+    T b = I.gr_dipole ? 1.0 + (sh.g - 1.0) * a : 1.0 + 2.0 * a;
     T mk = m[0] * kx + m[1] * ky + m[2] * kz;
     T Nn = b * mu * q - mk;
-    T den = frcp(1.0 + 3.0 * mu * mu);
+    T den = frcp(1.0 + (I.gr_dipole ? sh.c : T(3.0)) * mu * mu);
     T ikt = frcp(kt);
     T ikt2 = ikt * ikt;
     T N2d = Nn * Nn * ikt2 * den;  // N^2 / (k_t^2 (1 + 3 mu^2))
@@ -444,10 +517,22 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     g[6] = g[6] - PK * (bmu * n[2] - m[2]);
     // dK/dk_t = -2 K / k_t  ->  dH/dk_t += 2 P K / k_t
     g[7] = g[7] + 2.0 * p.P * K * ikt;
-    // dN/dx = (mu q s /(a r)) n + b [q (m - mu n) + mu (k - q n)] / r
-    // dK/dx = N2d (s/r) n + c1 dN/dx - 6 K mu den (m - mu n) / r
-    T e_n = N2d * sr + c1 * (mu * q * s * ir * ia) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
-    T e_m = c1 * b * ir * q - 6.0 * K * mu * den * ir;
+    // db/dr = g' sqrt(A) + (g - 1) s / (2 sqrt(A) r)  (flat: s / (sqrt(A) r))
+    // dN/dx = mu q (db/dr) n + b [q (m - mu n) + mu (k - q n)] / r
+    // dD/dx = c' mu^2 n + 2 c mu (m - mu n) / r,  D = 1 + c mu^2
+    // dK/dx = N2d (s/r) n + c1 dN/dx - K den dD/dx
+    T e_n, e_m;
+    T cc2 = 6.0;
+    if (I.gr_dipole) {
+        T dbdr = sh.dg * a + (sh.g - 1.0) * (0.5 * s * ir * ia);
+        cc2 = 2.0 * sh.c;
+        e_n = N2d * sr + c1 * (mu * q * dbdr) - c1 * b * ir * 2.0 * mu * q + cc2 * K * mu * den * ir * mu -
+              K * den * sh.dc * mu * mu;
+        e_m = c1 * b * ir * q - cc2 * K * mu * den * ir;
+    } else {
+        e_n = N2d * sr + c1 * (mu * q * s * ir * ia) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
+        e_m = c1 * b * ir * q - 6.0 * K * mu * den * ir;
+    }
     T e_k = c1 * b * ir * mu;
     T omK = 1.0 - K;
     g[0] = g[0] + omK * p.gx - p.P * (e_n * n[0] + e_m * m[0] + e_k * kx);
@@ -456,7 +541,7 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     // time: dN/dt = b q dmu - mt.k ; dK/dt = c1 dN/dt - 6 K mu den dmu
     if (I.oblique) {
         T mtk = mt[0] * kx + mt[1] * ky + mt[2] * kz;
-        T dKdt = c1 * (b * q * dmu - mtk) - 6.0 * K * mu * den * dmu;
+        T dKdt = c1 * (b * q * dmu - mtk) - cc2 * K * mu * den * dmu;
         g[3] = g[3] + omK * p.gt - p.P * dKdt;
     }
 }
@@ -492,9 +577,11 @@ RT_HD T hamiltonian(const InstT<T>& I, const T y[8], const AxisRef* ref = nullpt
     Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
     if (I.plasma == PL_ISO) return Hv + p.P;
     T a = sqrt(A);
+    DipoleShape<T> sh;
+    if (I.gr_dipole) sh = dipole_shape(I, ir);
     T mk = m[0] * y[4] + m[1] * y[5] + m[2] * y[6];
-    T Nn = (1.0 + 2.0 * a) * mu * q - mk;
-    T K = A * Nn * Nn * rcp(y[7] * y[7] * (1.0 + 3.0 * mu * mu));
+    T Nn = (I.gr_dipole ? 1.0 + (sh.g - 1.0) * a : 1.0 + 2.0 * a) * mu * q - mk;
+    T K = A * Nn * Nn * rcp(y[7] * y[7] * (1.0 + (I.gr_dipole ? sh.c : T(3.0)) * mu * mu));
     return Hv + p.P * (1.0 - K);
 }
 
@@ -510,8 +597,8 @@ RT_HD T g_kk(const InstT<T>& I, const T y[8]) {
 
 // dipole field direction u = 3 mu n - m (|u|^2 = 1 + 3 mu^2) and magnitude factor
 template <class T>
-RT_HD void dipole_dir(const T n[3], const T m[3], const T& mu, T u[3]) {
-    for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - m[i];
+RT_HD void dipole_dir(const T n[3], const T m[3], const T& mu, T u[3], const T& g = T(3.0)) {
+    for (int i = 0; i < 3; ++i) u[i] = g * mu * n[i] - m[i];
 }
 
 // ----------------------------------------------------------------------------

@@ -74,6 +74,14 @@ RT_HD InstT<T> make_inst_t(const T p[6], const StarFixed& f) {
     I.cm = c_;
     I.sm = s_;
     I.oblique = (value(s_) != 0.0) ? 1 : 0;
+    // field shape: the Schwarzschild vacuum dipole, normalised to B0 at the surface pole
+    I.gr_dipole = ((f.flags & FLAG_GR_DIPOLE) && value(I.rs) > 0.0) ? 1 : 0;
+    I.bnorm = T(1.0);
+    if (I.gr_dipole) {
+        T G, G1, G2;
+        gr_dipole_G(I.rs * rcp(R), G, G1, G2);
+        I.bnorm = rcp(G);
+    }
     double v0 = f.v0_kms / phys::c_kms;
     T w_inf = ma * ::sqrt(1.0 + v0 * v0);
     I.ma2 = T(1.0 / (1.0 + v0 * v0));
@@ -120,8 +128,8 @@ template <class S, class T>
 RT_HD InstT<S> lift_inst(const InstT<T>& I) {
     InstT<S> J;
     J.rs = S(I.rs); J.R = S(I.R); J.Om = S(I.Om); J.cm = S(I.cm); J.sm = S(I.sm); J.Cwp = S(I.Cwp);
-    J.R3 = S(I.R3); J.ma2 = S(I.ma2);
-    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
+    J.R3 = S(I.R3); J.ma2 = S(I.ma2); J.bnorm = S(I.bnorm);
+    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
     return J;
 }
 
@@ -139,10 +147,16 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
     S mu = mm[0] * n[0] + mm[1] * n[1] + mm[2] * n[2];
     Plasma<S> pl = plasma_eval(J, n, ir, mm, mu, S(0.0));
     if (I.plasma == PL_ISO || thin) return pl.P - J.ma2;
+    S gsh = S(3.0), csh = S(3.0);
+    if (I.gr_dipole) {
+        const DipoleShape<S> sh = dipole_shape(J, ir);
+        gsh = sh.g;
+        csh = sh.c;
+    }
     S u[3];
-    for (int i = 0; i < 3; ++i) u[i] = 3.0 * mu * n[i] - mm[i];
+    for (int i = 0; i < 3; ++i) u[i] = gsh * mu * n[i] - mm[i];
     S ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
-    S cB2 = ku * ku * rcp(1.0 + 3.0 * mu * mu);
+    S cB2 = ku * ku * rcp(1.0 + csh * mu * mu);
     S w2 = om2 * rcp(1.0 - J.rs * ir);
     return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
 }
@@ -150,14 +164,20 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
 // F along the radial line through n at radius r (values only: the bisection)
 template <class T>
 RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m[3], double mu, double cB2,
-                            double om2, bool thin, double r) {
+                            double om2, bool thin, double r, const double kh[3]) {
     InstT<double> J;
     J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
-    J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2);
-    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique;
+    J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2); J.bnorm = value(I.bnorm);
+    J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
     double ir = 1.0 / r;
     Plasma<double> pl = plasma_eval(J, n, ir, m, mu, 0.0);
     if (I.plasma == PL_ISO || thin) return pl.P - J.ma2;
+    if (I.gr_dipole) {  // the field direction along the line changes with r
+        const DipoleShape<double> sh = dipole_shape(J, ir);
+        double ku = 0.0;
+        for (int i = 0; i < 3; ++i) ku += kh[i] * (sh.g * mu * n[i] - m[i]);
+        cB2 = ku * ku / (1.0 + sh.c * mu * mu);
+    }
     double w2 = om2 / (1.0 - J.rs * ir);
     return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
 }
@@ -269,15 +289,15 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     // root of F above the surface: bracket R 2^j, then bisection to adjacent doubles
     double R = value(I.R);
     double rcv = -1.0;
-    if (resonance_line(I, n, m, mu, cB2, om2, thin, R) > 0.0) {
+    if (resonance_line(I, n, m, mu, cB2, om2, thin, R, kh) > 0.0) {
         double lo = R, hi = 2.0 * R;
         int j = 0;
-        while (!(resonance_line(I, n, m, mu, cB2, om2, thin, hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
-        if (resonance_line(I, n, m, mu, cB2, om2, thin, hi) < 0.0) {
+        while (!(resonance_line(I, n, m, mu, cB2, om2, thin, hi, kh) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; }
+        if (resonance_line(I, n, m, mu, cB2, om2, thin, hi, kh) < 0.0) {
             for (int it = 0; it < 200; ++it) {
                 double mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
-                if (resonance_line(I, n, m, mu, cB2, om2, thin, mid) > 0.0) lo = mid; else hi = mid;
+                if (resonance_line(I, n, m, mu, cB2, om2, thin, mid, kh) > 0.0) lo = mid; else hi = mid;
             }
             rcv = 0.5 * (lo + hi);
         }
@@ -321,10 +341,16 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
         T nT0[3] = {T(n[0]), T(n[1]), T(n[2])};
         T mu0 = mT[0] * nT0[0] + mT[1] * nT0[1] + mT[2] * nT0[2];
         Plasma<T> p0 = plasma_eval(I, nT0, ir0, mT, mu0, T(0.0));
-        // cos^2 between kh and the dipole direction 3 mu n - m (the axis depends on theta_m, P)
+        // cos^2 between kh and the dipole direction g mu n - m (the axis depends on theta_m, P)
+        T g0 = T(3.0), c0 = T(3.0);
+        if (I.gr_dipole) {
+            const DipoleShape<T> sh0 = dipole_shape(I, ir0);
+            g0 = sh0.g;
+            c0 = sh0.c;
+        }
         T ku0 = T(0.0);
-        for (int d = 0; d < 3; ++d) ku0 = ku0 + kh[d] * (3.0 * mu0 * n[d] - mT[d]);
-        T cB20 = ku0 * ku0 * rcp(1.0 + 3.0 * mu0 * mu0);
+        for (int d = 0; d < 3; ++d) ku0 = ku0 + kh[d] * (g0 * mu0 * n[d] - mT[d]);
+        T cB20 = ku0 * ku0 * rcp(1.0 + c0 * mu0 * mu0);
         T E2 = om2 * rcp(A);
         kg = sqrt(E2 * (E2 - p0.P) * rcp(E2 - p0.P * cB20));
     }
@@ -376,11 +402,19 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     T Rr = I.R * ir;
     T nT[3] = {T(n[0]), T(n[1]), T(n[2])};
     T muT = mT[0] * nT[0] + mT[1] * nT[1] + mT[2] * nT[2];
-    T Bmag = 0.5 * C.B0 * Rr * Rr * Rr * sqrt(1.0 + 3.0 * muT * muT);
+    T gT = T(3.0), cT = T(3.0), fT = T(1.0);
+    if (I.gr_dipole) {
+        const DipoleShape<T> shT = dipole_shape(I, ir);
+        gT = shT.g;
+        cT = shT.c;
+        fT = I.bnorm * shT.F;
+    }
+    T Bmag = 0.5 * C.B0 * Rr * Rr * Rr * sqrt(1.0 + cT * muT * muT);
+    if (I.gr_dipole) Bmag = Bmag * fT;
     T uT[3];
-    for (int d = 0; d < 3; ++d) uT[d] = 3.0 * muT * nT[d] - mT[d];
+    for (int d = 0; d < 3; ++d) uT[d] = gT * muT * nT[d] - mT[d];
     T kuT = kh[0] * uT[0] + kh[1] * uT[1] + kh[2] * uT[2];
-    T cB2T = kuT * kuT * rcp(1.0 + 3.0 * muT * muT);
+    T cB2T = kuT * kuT * rcp(1.0 + cT * muT * muT);
     T Bperp2 = (C.weights == W_CONV_CONSTB) ? T((C.Btest * C.G2) * (C.Btest * C.G2))
                                             : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2T);
     T Q;
@@ -448,7 +482,8 @@ RT_HD double cyclotron_tau(const InstT<double>& I, const SeedT<double>& C, doubl
         magnetic_axis(I, tf + (r - rf), m, mt);
         const double mu = m[0] * nh[0] + m[1] * nh[1] + m[2] * nh[2];
         const double Rr = R / r;
-        const double B = 0.5 * value(C.B0) * Rr * Rr * Rr * ::sqrt(1.0 + 3.0 * mu * mu);
+        const DipoleShape<double> sh = dipole_shape(I, 1.0 / r);
+        const double B = 0.5 * value(C.B0) * value(I.bnorm) * sh.F * Rr * Rr * Rr * ::sqrt(1.0 + sh.c * mu * mu);
         return ::log(kc * B * ::sqrt(1.0 - value(I.rs) / r) / wf);
     };
     *r_res = -1.0;
@@ -520,13 +555,14 @@ RT_HD double event_weight(const InstT<double>& I, const SeedT<double>& C, const 
     double m[3], mt[3];
     magnetic_axis(I, y[3], m, mt);
     const double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    const DipoleShape<double> sh = dipole_shape(I, ir);  // flat: g = c = 3, F = 1
     double u[3];
-    dipole_dir(n, m, mu, u);
-    const double u2 = 1.0 + 3.0 * mu * mu;
+    dipole_dir(n, m, mu, u, sh.g);
+    const double u2 = 1.0 + sh.c * mu * mu;
     const double ko_u = ko[0] * u[0] + ko[1] * u[1] + ko[2] * u[2];
     const double cB2 = ko_u * ko_u * rcp(ku * ku * u2);
     const double Rr = I.R * ir;
-    const double Bmag = 0.5 * value(C.B0) * Rr * Rr * Rr * ::sqrt(u2);
+    const double Bmag = 0.5 * value(C.B0) * value(I.bnorm) * sh.F * Rr * Rr * Rr * ::sqrt(u2);
     const double Bperp2 = (C.weights == W_CONV_CONSTB) ? (C.Btest * C.G2) * (C.Btest * C.G2)
                                                        : (Bmag * C.G2) * (Bmag * C.G2) * (1.0 - cB2);
     const double w = value(C.w_inf);

@@ -13,11 +13,12 @@ static InstT<double> inst_from(const double* c, const int* e) {
     I.rs = c[0]; I.R = c[1]; I.Om = c[2]; I.cm = c[3]; I.sm = c[4]; I.Cwp = c[5]; I.R3 = c[1] * c[1] * c[1];
     I.ma2 = c[6];
     I.plasma = e[0]; I.density = e[1]; I.oblique = (I.sm != 0.0) ? 1 : 0;
+    I.gr_dipole = e[2]; I.bnorm = c[7];
     return I;
 }
 
 extern "C" {
-// c = (rs, R, Om, cos theta_m, sin theta_m, Cwp, ma2); e = (plasma, density)
+// c = (rs, R, Om, cos theta_m, sin theta_m, Cwp, ma2, bnorm); e = (plasma, density, gr_dipole)
 void host_grad_h(const double* c, const int* e, const double* y, double* g) {
     InstT<double> I = inst_from(c, e);
     grad_h(I, y, g);

@@ -43,20 +43,29 @@ def consts(orc, s):
     Cwp = {0: Cp * s["multiplicity"] * n0,
            1: Cp * s["multiplicity"] * s["psi_twist"] * s["B0_G"] / (4 * math.pi * c["e_statC"] * 1e5),
            2: Cp * s["multiplicity"] * n0, 3: 0.0}[s["density"]]
-    cc = np.array([2 * c["GMsun_km"] * s["M_Msun"], s["R_km"], 2 * math.pi / s["P_s"] / c["c_kms"],
-                   math.cos(s["theta_m"]), math.sin(s["theta_m"]), Cwp, 1 / (1 + v0 * v0)])
-    return cc, np.array([s["plasma"], s["density"]], dtype=np.int32)
+    rs = 2 * c["GMsun_km"] * s["M_Msun"]
+    gr = 1 if (s["flags"] & W.FLAG_GR_DIPOLE) and rs > 0 else 0
+    bnorm = 1.0
+    if gr:  # 1 / G(r_s/R): the GR dipole normalised to B0 at the surface pole
+        x = rs / s["R_km"]
+        bnorm = 1.0 / (-3 * (math.log1p(-x) + x + x * x / 2) / x ** 3)
+    cc = np.array([rs, s["R_km"], 2 * math.pi / s["P_s"] / c["c_kms"],
+                   math.cos(s["theta_m"]), math.sin(s["theta_m"]), Cwp, 1 / (1 + v0 * v0), bnorm])
+    return cc, np.array([s["plasma"], s["density"], gr], dtype=np.int32)
 
 
 def _p(a, t=C.c_double):
     return a.ctypes.data_as(C.POINTER(t))
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "spherical_gr", "vacuum_gr"])
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "spherical_gr", "vacuum_gr", "cfg2_gr_dipole",
+                                  "magnetar_gr_dipole"])
 def test_hand_gradient_matches_oracle_autodiff(orc, host, name):
     s = {"cfg1": W.CFG1["star"], "cfg2": W.CFG2["star"], "cfg3": W.CFG3["star"],
          "spherical_gr": W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ANISO, theta_m=0.7),
-         "vacuum_gr": W.star(M_Msun=1.4, density=W.DENSITY_NONE)}[name]
+         "vacuum_gr": W.star(M_Msun=1.4, density=W.DENSITY_NONE),
+         "cfg2_gr_dipole": dict(W.CFG2["star"], flags=W.FLAG_GR_DIPOLE),
+         "magnetar_gr_dipole": dict(W.CFG3["star"], flags=W.FLAG_GR_DIPOLE)}[name]
     cc, e = consts(orc, s)
     rng = np.random.default_rng(0)
     for _ in range(300):

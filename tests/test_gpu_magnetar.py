@@ -106,5 +106,5 @@ def test_cyclotron_depth_errors(rt):
     with pytest.raises(ValueError):
         rt.rt_cyclotron_depth(s, z[:10, :3].contiguous(), z, torch.zeros((3, 4), dtype=torch.int32, device="cuda"))
     with pytest.raises(rt.RtError, match="enumeration"):
-        rt.rt_cyclotron_depth(dict(s, flags=16), z[:10].contiguous(), z, torch.zeros((3, 4), dtype=torch.int32,
+        rt.rt_cyclotron_depth(dict(s, flags=64), z[:10].contiguous(), z, torch.zeros((3, 4), dtype=torch.int32,
                                                                                      device="cuda"))

@@ -1,6 +1,6 @@
-"""GPU parity of the approximation variants (App. B; Sec. 6 eq. (reweight)) against the CPU
-oracle: flat propagation of curved initial conditions, renormalised weights and the thin
-resonance surface w_p = m_a.  Seeds: statuses equal, states 1e-12, weights 1e-9 relative (the
+"""GPU parity of the approximation variants (App. B; Sec. 6 eq. (reweight)) and of the
+Schwarzschild vacuum dipole against the CPU oracle: flat propagation of curved initial
+conditions, renormalised weights, the thin resonance surface w_p = m_a, the GR dipole field.  Seeds: statuses equal, states 1e-12, weights 1e-9 relative (the
 same criteria as the plain method); traces with the conditioning-aware criterion; the
 smoothed-flux adjoint on the kink-free spherical star (every ray well conditioned) per ray
 1e-8 and in total; unsupported combinations are refused."""
@@ -13,7 +13,8 @@ from tests.test_gpu_adjoint import PER_RAY_TOL, SPHERICAL, gpu_flux_grad, per_ra
 
 pytestmark = pytest.mark.gpu
 
-FLAGS = {"flat": W.FLAG_FLAT_PROPAGATION, "renorm": W.FLAG_RENORM_WEIGHTS, "thin": W.FLAG_THIN_SURFACE}
+FLAGS = {"flat": W.FLAG_FLAT_PROPAGATION, "renorm": W.FLAG_RENORM_WEIGHTS, "thin": W.FLAG_THIN_SURFACE,
+         "gr_dipole": W.FLAG_GR_DIPOLE}
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +45,7 @@ def test_variant_seeds_match_oracle(rt, orc, variant, base):
     assert np.max(np.abs(rays_g[8, ok] / rays_o[8, ok] - 1)) < 1e-9
 
 
-@pytest.mark.parametrize("variant", ["flat", "thin"])
+@pytest.mark.parametrize("variant", ["flat", "thin", "gr_dipole"])
 def test_variant_traces_match_oracle(rt, orc, variant):
     import torch
     cfg = W.CFG2
@@ -60,7 +61,7 @@ def test_variant_traces_match_oracle(rt, orc, variant):
     assert out["well"] >= 0.15 * out["escaped"]
 
 
-@pytest.mark.parametrize("variant", ["renorm", "thin"])
+@pytest.mark.parametrize("variant", ["renorm", "thin", "gr_dipole"])
 def test_variant_adjoint_matches_oracle(rt, orc, variant):
     s = dict(SPHERICAL, flags=FLAGS[variant])
     tol = W.tol()
@@ -94,4 +95,30 @@ def test_unsupported_combinations_are_refused(rt):
     with pytest.raises(rt.RtError, match="flat-propagation"):
         rt.Batch([flat, flat], [10, 10], 0, W.tol(), W.CFG4["bins"])
     with pytest.raises(rt.RtError, match="enumeration"):
-        rt.rt_sample_resonance(dict(W.CFG2["star"], flags=16), 0, 8)
+        rt.rt_sample_resonance(dict(W.CFG2["star"], flags=64), 0, 8)
+
+
+def test_gr_dipole_backward_matches_oracle(rt, orc):
+    """Backward rays and event weights through the GR dipole field (magnetar star): events and
+    statuses as the oracle's where it is well conditioned, per-ray weights 1e-6."""
+    s = dict(W.CFG3["star"], flags=W.FLAG_GR_DIPOLE)
+    t = W.tol(r_max_km=1e5)
+    rng = np.random.default_rng(21)
+    n = 300
+    b1, b2 = rng.uniform(-35, 35, n), rng.uniform(-35, 35, n)
+    print("gr dipole backward", flush=True)
+    ev, nev, fin, ifin = rt.rt_trace_backward_rays(s, t, 1e5, 0.8, 0.1, b1, b2, K=4)
+    wsum, total = rt.rt_backward_power(s, ev, nev, pixel_area_km2=1.0)
+    w_o, ev_o, nev_o, fin_o, ifin_o = orc.backward_rays(s, t, 1e5, 0.8, 0.1, b1, b2, K=4)
+    bad = np.zeros(n, dtype=bool)
+    for fac in (1 + 2.0 ** -50, 1 - 2.0 ** -50):
+        w2, ev2, nev2, fin2, ifin2 = orc.backward_rays(s, t, 1e5 * fac, 0.8, 0.1, b1, b2, K=4)
+        bad |= (nev2 != nev_o) | (ifin2[2] != ifin_o[2]) | (ifin2[0] != ifin_o[0])
+        bad |= (nev2 > 0) & (np.abs(w2 - w_o) > 1e-8 * np.abs(w_o))
+    assert bad.mean() <= 0.03
+    ok = ~bad
+    nev_g, ifin_g, w_g = nev.cpu().numpy(), ifin.cpu().numpy(), wsum.cpu().numpy()
+    assert np.array_equal(nev_g[ok], nev_o[ok]) and np.array_equal(ifin_g[2][ok], ifin_o[2][ok])
+    m = ok & (nev_o > 0)
+    assert m.sum() >= 30
+    assert np.allclose(w_g[m], w_o[m], rtol=1e-6, atol=0), np.abs(w_g[m] / w_o[m] - 1).max()
