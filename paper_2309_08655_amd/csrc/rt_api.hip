@@ -129,33 +129,65 @@ int persistent_grid(const rt_schedule& sc, const void* kernel, int block) {
 }
 
 // ---------------------------------------------------------------------------
-// counting sort of the work list by bucket key
+// partition: counting sort of indices by bucket, without per-element global atomics
 // ---------------------------------------------------------------------------
-static __global__ void order_clear_kernel(int32_t* buckets, WorkCtr* ctr) {
-    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) buckets[b] = 0;
-    if (threadIdx.x == 0) { ctr->head = 0ull; ctr->len = 0ull; ctr->iters = 0ull; }
-}
+// Workgroup g owns the contiguous chunk [g c, (g+1) c) of the keys.  Pass 1 counts its
+// chunk per bucket in LDS and writes the counts as row g of tab (G x nb).  Pass 2 turns
+// every column of tab into exclusive offsets over g and emits the column totals; pass 3
+// scans the totals into bucket starts.  Pass 4 re-reads the chunk and places element i
+// at start[b] + tab[g][b] + (its rank among the chunk's elements of bucket b, from an LDS
+// counter).  Element i belongs to bucket keys[i] >> shift when keys[i] >= 0 and that
+// bucket is below nb; every other element is left out of the list.
 
-static __global__ void order_hist_kernel(const int32_t* __restrict__ keys, int64_t n, int32_t* buckets) {
-    __shared__ int32_t sh[ORDER_BUCKETS];
-    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) sh[b] = 0;
+static __global__ void __launch_bounds__(256) part_hist_kernel(const int32_t* __restrict__ keys, int64_t n,
+                                                                int64_t chunk, int shift, int nb,
+                                                                int32_t* __restrict__ tab) {
+    __shared__ int32_t sh[PART_BUCKETS];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) sh[b] = 0;
     __syncthreads();
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int32_t k = keys[i];
-        if (k >= 0 && k < ORDER_BUCKETS) atomicAdd(&sh[k], 1);
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const int32_t k = keys[i];
+        if (k >= 0 && (k >> shift) < nb) atomicAdd(&sh[k >> shift], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x)
-        if (sh[b]) atomicAdd(&buckets[b], sh[b]);
+    int32_t* row = tab + (int64_t)blockIdx.x * nb;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) row[b] = sh[b];
 }
 
-// exclusive prefix sum over the buckets (one workgroup of 1024 threads, 4 buckets each)
-static __global__ void __launch_bounds__(1024) order_scan_kernel(int32_t* buckets, WorkCtr* ctr) {
+// 64 buckets per workgroup (one per lane); its 16 waves split the G rows in 16 slices
+static __global__ void __launch_bounds__(1024) part_cols_kernel(int32_t* __restrict__ tab, int G, int nb,
+                                                                 int32_t* __restrict__ totals) {
+    constexpr int NW = 16;
+    __shared__ int32_t part[NW][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * 64 + lane;
+    const int g0 = (G * wv) / NW, g1 = (G * (wv + 1)) / NW;
+    int32_t s = 0;
+    if (b < nb)
+        for (int g = g0; g < g1; ++g) s += tab[(int64_t)g * nb + b];
+    part[wv][lane] = s;
+    __syncthreads();
+    int32_t run = 0;
+    for (int q = 0; q < wv; ++q) run += part[q][lane];
+    if (b < nb)
+        for (int g = g0; g < g1; ++g) {
+            const int32_t c = tab[(int64_t)g * nb + b];
+            tab[(int64_t)g * nb + b] = run;
+            run += c;
+        }
+    if (wv == NW - 1 && b < PART_BUCKETS) totals[b] = (b < nb) ? run : 0;
+}
+
+// exclusive prefix sum of the PART_BUCKETS totals in place (one workgroup of 1024 threads,
+// 4 buckets each); start[PART_BUCKETS] receives the list length.  With a work counter, the
+// list is also armed for a persistent kernel: length set, head and iteration count cleared.
+static __global__ void __launch_bounds__(1024) part_scan_kernel(int32_t* start, WorkCtr* ctr) {
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
     int32_t v[4], s = 0;
-    for (int q = 0; q < 4; ++q) { v[q] = buckets[4 * t + q]; s += v[q]; }
+    for (int q = 0; q < 4; ++q) { v[q] = start[4 * t + q]; s += v[q]; }
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -165,28 +197,53 @@ static __global__ void __launch_bounds__(1024) order_scan_kernel(int32_t* bucket
         __syncthreads();
     }
     int32_t base = part[t] - s;
-    for (int q = 0; q < 4; ++q) { buckets[4 * t + q] = base; base += v[q]; }
-    if (t == 1023) ctr->len = (unsigned long long)part[1023];
-}
-
-static __global__ void order_scatter_kernel(const int32_t* __restrict__ keys, int64_t n, int32_t* buckets,
-                                            int32_t* __restrict__ list) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int32_t k = keys[i];
-        if (k >= 0 && k < ORDER_BUCKETS) list[atomicAdd(&buckets[k], 1)] = (int32_t)i;
+    for (int q = 0; q < 4; ++q) { start[4 * t + q] = base; base += v[q]; }
+    if (t == 1023) {
+        start[PART_BUCKETS] = part[1023];
+        if (ctr) { ctr->head = 0ull; ctr->len = (unsigned long long)part[1023]; ctr->iters = 0ull; }
     }
 }
 
+static __global__ void __launch_bounds__(256) part_scatter_kernel(const int32_t* __restrict__ keys, int64_t n,
+                                                                   int64_t chunk, int shift, int nb,
+                                                                   const int32_t* __restrict__ tab,
+                                                                   const int32_t* __restrict__ start,
+                                                                   int32_t* __restrict__ list) {
+    __shared__ int32_t sh[PART_BUCKETS];
+    __shared__ int32_t base[PART_BUCKETS];
+    const int32_t* row = tab + (int64_t)blockIdx.x * nb;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        sh[b] = 0;
+        base[b] = start[b] + row[b];
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * chunk;
+    const int64_t i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        const int32_t k = keys[i];
+        if (k >= 0 && (k >> shift) < nb) {
+            const int b = k >> shift;
+            list[base[b] + atomicAdd(&sh[b], 1)] = (int32_t)i;
+        }
+    }
+}
+
+int partition_keys(const int32_t* keys, int64_t n, int shift, int nb, int32_t* tab, int32_t* start,
+                   int32_t* list, WorkCtr* ctr, hipStream_t st) {
+    if (nb < 1 || nb > PART_BUCKETS || n < 0 || n > INT32_MAX)
+        return fail(RT_EINVAL, "partition_keys: bucket count or length out of range");
+    const int G = partition_blocks(n);
+    const int64_t chunk = (n + G - 1) / G;
+    hipLaunchKernelGGL(part_hist_kernel, dim3(G), dim3(256), 0, st, keys, n, chunk, shift, nb, tab);
+    hipLaunchKernelGGL(part_cols_kernel, dim3(PART_BUCKETS / 64), dim3(1024), 0, st, tab, G, nb, start);
+    hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, st, start, ctr);
+    hipLaunchKernelGGL(part_scatter_kernel, dim3(G), dim3(256), 0, st, keys, n, chunk, shift, nb, tab, start, list);
+    return check_launch("partition_keys");
+}
+
 int order_work_list(const FwdWs& W, int64_t n, hipStream_t st) {
-    static_assert(ORDER_BUCKETS == 4096, "scan kernel assumes 4096 buckets");
-    hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(256), 0, st, W.buckets, W.ctr);
-    int g = grid_for(n, 256, 16);
-    hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, st, W.keys, n, W.buckets);
-    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, st, W.buckets, W.ctr);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.keys, n, W.buckets,
-                       W.list);
-    return check_launch("order_work_list");
+    static_assert(ORDER_BUCKETS == PART_BUCKETS, "the work list uses one bucket per partition slot");
+    return partition_keys(W.keys, n, 0, ORDER_BUCKETS, W.tab, W.buckets, W.list, W.ctr, st);
 }
 
 }  // namespace rtd
@@ -202,7 +259,7 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
         case RT_OP_TRACE_BACKWARD:  // + initial states of the pixels
             return fwd_ws_bytes(n) + align256(sizeof(double) * 8 * (size_t)n);
         case RT_OP_BIN:
-            return align256(sizeof(int32_t) * (size_t)n);
+            return bin_ws_bytes(n);
         case RT_OP_BACKWARD_POWER:  // block partials of the image sum
             return align256(sizeof(double) * 1024);
         case RT_OP_FLUX_GRAD:  // 64 observers, a checkpoint every 64 steps, up to 64 of them

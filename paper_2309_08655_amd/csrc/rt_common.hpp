@@ -55,16 +55,36 @@ struct WorkCtr {
 // persistent kernel's tail stays short.
 constexpr int ORDER_BUCKETS = 4096;
 
+// Partition (counting sort by bucket) of up to 2^31 - 1 indices into at most
+// PART_BUCKETS buckets: one workgroup per chunk of at least PART_CHUNK_MIN keys, at most
+// PART_MAX_BLOCKS of them, each with a row of PART_BUCKETS counters in the table.
+constexpr int PART_BUCKETS = 4096;
+constexpr int PART_MAX_BLOCKS = 256;
+constexpr int64_t PART_CHUNK_MIN = 4096;
+
+inline int partition_blocks(int64_t n) {
+    int64_t g = (n + PART_CHUNK_MIN - 1) / PART_CHUNK_MIN;
+    if (g > PART_MAX_BLOCKS) g = PART_MAX_BLOCKS;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
 struct FwdWs {
     WorkCtr* ctr;
     int32_t* list;
     double* h0;
     double* k1;
     int32_t* keys;     // [n] bucket of each ray (-1: not traced)
-    int32_t* buckets;  // [ORDER_BUCKETS] counts, then insertion offsets
+    int32_t* buckets;  // [ORDER_BUCKETS + 1] first list entry of each bucket, then the list length
+    int32_t* tab;      // [partition_blocks(n) x ORDER_BUCKETS] per-workgroup bucket offsets
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+inline size_t part_tab_bytes(int64_t n) {
+    return align256(sizeof(int32_t) * (size_t)partition_blocks(n) * PART_BUCKETS);
+}
+inline size_t part_start_bytes() { return align256(sizeof(int32_t) * (PART_BUCKETS + 1)); }
 
 inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     char* p = (char*)ws;
@@ -80,13 +100,45 @@ inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     W.keys = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)n);
     W.buckets = (int32_t*)p;
+    p += part_start_bytes();
+    W.tab = (int32_t*)p;
     return W;
 }
 
 inline size_t fwd_ws_bytes(int64_t n) {
     return align256(sizeof(WorkCtr)) + align256(sizeof(int32_t) * (size_t)n) + align256(sizeof(double) * (size_t)n) +
-           align256(sizeof(double) * 8 * (size_t)n) + align256(sizeof(int32_t) * (size_t)n) +
-           align256(sizeof(int32_t) * ORDER_BUCKETS);
+           align256(sizeof(double) * 8 * (size_t)n) + align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() +
+           part_tab_bytes(n);
+}
+
+// Groups the indices i < n with keys[i] >= 0 and keys[i] >> shift < nb (nb <= PART_BUCKETS)
+// by bucket keys[i] >> shift into list (order inside a bucket is arbitrary); start[b] is
+// the first list entry of bucket b and start[nb .. PART_BUCKETS] the list length.  tab
+// holds part_tab_bytes(n).  With ctr, the list is armed for a persistent kernel.
+int partition_keys(const int32_t* keys, int64_t n, int shift, int nb, int32_t* tab, int32_t* start,
+                   int32_t* list, WorkCtr* ctr, hipStream_t st);
+
+// workspace of rt_bin_flux: bin key and tile-ordered list of every ray, partition table
+struct BinWs {
+    int32_t* keys;
+    int32_t* list;
+    int32_t* start;
+    int32_t* tab;
+};
+inline size_t bin_ws_bytes(int64_t n) {
+    return 2 * align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() + part_tab_bytes(n);
+}
+inline BinWs carve_bin_ws(void* ws, int64_t n) {
+    char* p = (char*)ws;
+    BinWs B;
+    B.keys = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)n);
+    B.list = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)n);
+    B.start = (int32_t*)p;
+    p += part_start_bytes();
+    B.tab = (int32_t*)p;
+    return B;
 }
 
 // builds W.list from W.keys (counting sort by bucket; order inside a bucket is arbitrary)
@@ -118,7 +170,7 @@ int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const 
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
                       int32_t* ifin, hipStream_t st);
 int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
-               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, int32_t* keys,
+               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, void* ws,
                hipStream_t st);
 
 // optional HIP-event timing of the persistent kernels (rt_timing / rt_kernel_times):

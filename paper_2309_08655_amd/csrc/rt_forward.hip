@@ -240,12 +240,11 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
 // the energy at infinity -k_t, H and r.
 __global__ void __launch_bounds__(256) finalize_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
                                                        const int32_t* __restrict__ inst_of,
-                                                       const int32_t* __restrict__ list, const WorkCtr* ctr,
-                                                       int64_t n, double* __restrict__ fin) {
-    const int64_t nlist = (int64_t)ctr->len;
+                                                       const int32_t* __restrict__ keys, int64_t n,
+                                                       double* __restrict__ fin) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nlist; q += stride) {
-        int64_t j = list[q];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        if (keys[j] < 0) continue;  // not traced: the init pass wrote its final record
         const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
         double yf[8];
         for (int d = 0; d < 8; ++d) yf[d] = fin[d * n + j];
@@ -313,32 +312,53 @@ __global__ void __launch_bounds__(256) bin_keys_kernel(const double* __restrict_
     }
 }
 
-constexpr int BIN_TILE = 4096;  // bins per LDS tile: 2 x 32 KiB of FP64
+constexpr int BIN_SHIFT = 12;
+constexpr int BIN_TILE = 1 << BIN_SHIFT;  // bins per LDS tile: 2 x 32 KiB of FP64
 
-__global__ void __launch_bounds__(256) bin_tiles_kernel(const int32_t* __restrict__ keys, const double* __restrict__ w,
-                                                        int64_t n, int64_t nbins, int64_t chunk,
-                                                        double* __restrict__ hist, double* __restrict__ cnt) {
+// The rays are first partitioned by tile (key >> BIN_SHIFT); workgroup (t, s) then takes
+// slice s of tile t's rays, accumulates them in LDS and merges the touched bins into the
+// global map with FP64 atomics.  Every ray is read once.
+__global__ void __launch_bounds__(256) bin_part_kernel(const int32_t* __restrict__ keys, const double* __restrict__ w,
+                                                       const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ start, int64_t nbins,
+                                                       int32_t slices, double* __restrict__ hist,
+                                                       double* __restrict__ cnt) {
     __shared__ double sh_w[BIN_TILE];
     __shared__ double sh_c[BIN_TILE];
-    const int64_t tile0 = (int64_t)blockIdx.x * BIN_TILE;
-    const int64_t r0 = (int64_t)blockIdx.y * chunk;
-    const int64_t r1 = (r0 + chunk < n) ? r0 + chunk : n;
+    const int64_t t = blockIdx.x;
+    const int64_t lo = start[t], len = (int64_t)start[t + 1] - lo;
+    const int64_t a = lo + (len * blockIdx.y) / slices;
+    const int64_t e = lo + (len * (blockIdx.y + 1)) / slices;
+    if (a == e) return;  // uniform over the workgroup
+    const int64_t tile0 = t * BIN_TILE;
     for (int b = threadIdx.x; b < BIN_TILE; b += blockDim.x) { sh_w[b] = 0.0; sh_c[b] = 0.0; }
     __syncthreads();
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        int32_t k = keys[i];
-        int64_t rel = (int64_t)k - tile0;
-        if (k >= 0 && rel >= 0 && rel < BIN_TILE) {
-            atomicAdd(&sh_w[rel], w[i]);
-            atomicAdd(&sh_c[rel], 1.0);
-        }
+    for (int64_t q = a + threadIdx.x; q < e; q += blockDim.x) {
+        const int32_t i = list[q];
+        const int rel = (int)((int64_t)keys[i] - tile0);
+        atomicAdd(&sh_w[rel], w[i]);
+        atomicAdd(&sh_c[rel], 1.0);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < BIN_TILE; b += blockDim.x) {
-        int64_t gb = tile0 + b;
+        const int64_t gb = tile0 + b;
         if (gb < nbins && sh_c[b] != 0.0) {
             atomicAdd(&hist[gb], sh_w[b]);
             atomicAdd(&cnt[gb], sh_c[b]);
+        }
+    }
+}
+
+// maps of more than PART_BUCKETS tiles: one FP64 atomic pair per ray
+__global__ void __launch_bounds__(256) bin_direct_kernel(const int32_t* __restrict__ keys, const double* __restrict__ w,
+                                                         int64_t n, double* __restrict__ hist,
+                                                         double* __restrict__ cnt) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t k = keys[i];
+        if (k >= 0) {
+            atomicAdd(&hist[k], w[i]);
+            atomicAdd(&cnt[k], 1.0);
         }
     }
 }
@@ -433,8 +453,8 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, itab, inst_of, W.list, W.ctr,
-                       n, fin);
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, I, itab, inst_of, W.keys, n,
+                       fin);
     return check_launch("finalize_kernel");
 }
 
@@ -550,7 +570,7 @@ int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const 
 
 namespace rtd {
 int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
-               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, int32_t* keys,
+               const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, void* ws,
                hipStream_t st) {
     int32_t ninst = inst_offset ? n_inst : 1;
     int64_t per = (int64_t)bins->n_theta * bins->n_psi * bins->n_omega;
@@ -560,20 +580,27 @@ int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t 
     hipLaunchKernelGGL(fill_kernel, dim3(zg), dim3(256), 0, st, cnt, nbins, 0.0);
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, st, over, (int64_t)2, 0.0);
     if (n == 0) return check_launch("fill_kernel");
+    if (n > INT32_MAX) return fail(RT_EINVAL, "rt_bin_flux: n exceeds 2^31 - 1");
+    BinWs B = carve_bin_ws(ws, n);
     int g1 = grid_for(n, 256, 8);
     hipLaunchKernelGGL(bin_keys_kernel, dim3(g1), dim3(256), 0, st, fin, ifin, n, bins->n_theta, bins->n_psi,
-                       bins->n_omega, bins->d_omega, inst_offset, ninst, keys, w, over);
-    int64_t ntiles = (nbins + BIN_TILE - 1) / BIN_TILE;
-    // enough ray chunks to fill the device, each chunk re-read once per tile
-    int64_t nchunks = (2048 + ntiles - 1) / ntiles;
-    if (nchunks < 1) nchunks = 1;
-    if (nchunks > 1024) nchunks = 1024;
-    int64_t chunk = (n + nchunks - 1) / nchunks;
-    nchunks = (n + chunk - 1) / chunk;
-    if (ntiles > 65535 || nchunks > 65535) return fail(RT_EINVAL, "rt_bin_flux: grid too large");
-    hipLaunchKernelGGL(bin_tiles_kernel, dim3((unsigned)ntiles, (unsigned)nchunks), dim3(256), 0, st, keys, w, n, nbins,
-                       chunk, hist, cnt);
-    return check_launch("bin_tiles_kernel");
+                       bins->n_omega, bins->d_omega, inst_offset, ninst, B.keys, w, over);
+    const int64_t ntiles = (nbins + BIN_TILE - 1) / BIN_TILE;
+    if (ntiles > PART_BUCKETS) {
+        hipLaunchKernelGGL(bin_direct_kernel, dim3(grid_for(n, 256, 4)), dim3(256), 0, st, B.keys, w, n, hist, cnt);
+        return check_launch("bin_direct_kernel");
+    }
+    int rc = partition_keys(B.keys, n, BIN_SHIFT, (int)ntiles, B.tab, B.start, B.list, nullptr, st);
+    if (rc) return rc;
+    // about 2048 workgroups over the tiles, none with fewer than ~256 rays on average
+    int64_t slices = (2048 + ntiles - 1) / ntiles;
+    const int64_t by_rays = n / (256 * ntiles);
+    if (slices > by_rays) slices = by_rays;
+    if (slices < 1) slices = 1;
+    if (slices > 1024) slices = 1024;
+    hipLaunchKernelGGL(bin_part_kernel, dim3((unsigned)ntiles, (unsigned)slices), dim3(256), 0, st, B.keys, w, B.list,
+                       B.start, nbins, (int32_t)slices, hist, cnt);
+    return check_launch("bin_part_kernel");
 }
 }  // namespace rtd
 
@@ -593,5 +620,5 @@ extern "C" int rt_bin_flux(const double* fin, const int32_t* ifin, const double*
     size_t need = rt_workspace_size(RT_OP_BIN, n);
     if (n > 0 && (!ws || ws_bytes < need)) return fail(RT_ENOWS, "rt_bin_flux: workspace too small");
     if (n > 0 && (!fin || !ifin || !w)) return fail(RT_EINVAL, "rt_bin_flux: null input");
-    return launch_bin(fin, ifin, w, n, bins, inst_offset, n_inst, hist, cnt, over, (int32_t*)ws, (hipStream_t)stream);
+    return launch_bin(fin, ifin, w, n, bins, inst_offset, n_inst, hist, cnt, over, ws, (hipStream_t)stream);
 }

@@ -124,5 +124,32 @@ def batched_instances(n_inst: int = 256, seed: int = 1, n_lo: float = 1e4, n_hi:
     return stars, counts
 
 
+def final_records(n: int, bins: dict, seed: int = 0, hot_frac: float = 0.3, out_frac: float = 0.02):
+    """Synthetic final records of n traced rays for binning tests: float64 fin [16, n] and
+    int32 ifin [3, n] in the tracer's layout (theta in fin[8], co-rotating azimuth in fin[10],
+    energy at infinity in fin[11], status in ifin[2]) and positive weights w [n].
+
+    Directions are uniform on the sphere, energies spread over the frequency bins with a
+    fraction out_frac beyond them; a fraction hot_frac of the rays is piled into eight
+    directions at omega = 1 (the sharp line of the signal), which makes hot bins; 10 %
+    of the rays carry a status other than escaped.  numpy PCG64 seeded `seed`."""
+    rng = np.random.default_rng(seed)
+    fin = np.zeros((16, n))
+    ifin = np.zeros((3, n), dtype=np.int32)
+    fin[8] = np.arccos(1.0 - 2.0 * rng.random(n))
+    fin[10] = 2.0 * math.pi * rng.random(n)
+    half = 0.5 * bins["n_omega"] * bins["d_omega"]
+    fin[11] = 1.0 + (2.0 * rng.random(n) - 1.0) * half * (1.0 + 2.0 * out_frac)
+    hot = rng.random(n) < hot_frac
+    spot = rng.integers(0, 8, n)
+    fin[8][hot] = (0.3 + 0.3 * spot[hot]) % math.pi
+    fin[10][hot] = 0.7 * spot[hot] + 0.1
+    fin[11][hot] = 1.0
+    ifin[2] = np.where(rng.random(n) < 0.9, STATUS_ESCAPED,
+                       rng.choice([STATUS_HIT_STAR, STATUS_MAX_STEPS, STATUS_NO_RESONANCE], n)).astype(np.int32)
+    w = np.exp(rng.normal(0.0, 2.0, n))
+    return fin, ifin, w
+
+
 CFG4 = dict(name="batched-256-instances", n_inst=256, seed=1, bins=dict(n_theta=64, n_psi=128, n_omega=1,
                                                                         d_omega=1.0))
