@@ -98,3 +98,36 @@ extern "C" {
 double host_inv_fifth_root(double err) { return inv_fifth_root(err); }
 double host_step_factor(double err, double facmax, int accepted) { return step_factor(err, facmax, accepted != 0); }
 }
+
+#include "../paper_2309_08655_amd/csrc/rt_seed.hpp"
+
+extern "C" {
+// root of F along the radial line through n (the seeding's search, and a plain bisection on
+// the same bracket for comparison); d = (mu, cB2) as the seeding forms them from n, m, kh
+double host_resonance_radius(const double* c, const int* e, const double* n, const double* m, const double* kh,
+                             double om2, int thin, int bisect, int* nevals) {
+    InstT<double> I = inst_from(c, e);
+    double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    double ku = 0.0;
+    for (int d = 0; d < 3; ++d) ku += kh[d] * (3.0 * mu * n[d] - m[d]);
+    const double cB2 = ku * ku / (1.0 + 3.0 * mu * mu);
+    if (!bisect) return resonance_radius(I, n, m, mu, cB2, om2, thin != 0, kh, nevals);
+    auto F = [&](double r) { return resonance_line(I, n, m, mu, cB2, om2, thin != 0, r, kh); };
+    int ne = 1;
+    const double R = I.R;
+    if (!(F(R) > 0.0)) { *nevals = ne; return -1.0; }
+    double lo = R, hi = 2.0 * R;
+    int j = 0;
+    while (!(F(hi) < 0.0) && j < 80) { lo = hi; hi *= 2.0; ++j; ++ne; }
+    ++ne;
+    if (!(F(hi) < 0.0)) { *nevals = ne; return -1.0; }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        ++ne;
+        if (F(mid) > 0.0) lo = mid; else hi = mid;
+    }
+    *nevals = ne;
+    return 0.5 * (lo + hi);
+}
+}

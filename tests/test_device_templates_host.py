@@ -162,3 +162,58 @@ def test_controller_fifth_root_matches_pow(host):
         assert host.host_step_factor(e, 1.0, 1) == pytest.approx(min(1.0, ref), rel=1e-15), e
     for e in (1.0000001, 3.0, 1e5, 1e40, 1e300):
         assert host.host_step_factor(e, 10.0, 0) == pytest.approx(max(0.2, 0.9 * e ** -0.2), rel=1e-15), e
+
+
+def _named_star(name):
+    return {"cfg1": W.CFG1["star"], "cfg2": W.CFG2["star"], "cfg3": W.CFG3["star"],
+            "magnetar": W.MAGNETAR_MODELS["M4"], "cfg2_gr_dipole": dict(W.CFG2["star"], flags=W.FLAG_GR_DIPOLE),
+            "thin": dict(W.CFG2["star"], flags=W.FLAG_THIN_SURFACE)}[name]
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "magnetar", "cfg2_gr_dipole", "thin"])
+def test_resonance_search_matches_bisection(orc, host, name):
+    """The seeding's root search along the radial line (Illinois false position, safeguarded)
+    stops at the adjacent doubles a bisection of the same bracket reaches: identical radii,
+    except where F evaluated in double precision changes sign more than once within a few
+    ulp of the root (the GR dipole's series), where either method may stop at another of
+    those changes: within 8 ulp.  Fewer than half the evaluations of F, on average and for
+    the slowest ray of each group of 64 (a wave waits for its slowest lane)."""
+    s = _named_star(name)
+    cc, e = consts(orc, s)
+    host.host_resonance_radius.restype = C.c_double
+    host.host_resonance_radius.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double, C.c_int,
+                                           C.c_int, C.POINTER(C.c_int)]
+    rng = np.random.default_rng(7)
+    thin = 1 if name == "thin" else 0
+    m_ax = np.array([math.sin(s["theta_m"]), 0.0, math.cos(s["theta_m"])])
+    v0 = s["v0_kms"] / orc.constants()["c_kms"]
+    om2 = cc[6] * (1.0 + v0 * v0)  # m~^2 + k0^2 with m~^2 = 1 / (1 + v0^2)
+    same, close, found, ev_new, ev_old = 0, 0, 0, 0, 0
+    per_ray = []
+    for _ in range(3000):
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        kh = rng.normal(size=3); kh /= np.linalg.norm(kh)
+        ne = [C.c_int(), C.c_int()]
+        r = [host.host_resonance_radius(_p(cc), _p(e, C.c_int), _p(n), _p(m_ax), _p(kh), om2, thin, b,
+                                        C.byref(ne[b])) for b in (0, 1)]
+        assert (r[0] < 0) == (r[1] < 0)
+        if r[1] < 0:
+            continue
+        found += 1
+        ev_new += ne[0].value; ev_old += ne[1].value
+        per_ray.append((ne[0].value, ne[1].value))
+        if r[0] == r[1]:
+            same += 1
+        else:
+            assert abs(r[0] / r[1] - 1.0) < 8 * 2.0 ** -52, (r[0], r[1])
+            close += 1
+    print(name, "found", found, "identical", same, "within 8 ulp", close, "evaluations", ev_new / max(found, 1),
+          "vs", ev_old / max(found, 1))
+    assert found > 300
+    assert same >= (0.95 if name == "cfg2_gr_dipole" else 0.995) * found
+    assert ev_new < 0.5 * ev_old
+    # a wave waits for its slowest lane: the largest count in each group of 64 rays
+    pr = np.array(per_ray[: 64 * (len(per_ray) // 64)]).reshape(-1, 64, 2).max(axis=1).mean(axis=0)
+    print("mean over waves of the slowest lane", pr[0], "vs", pr[1])
+    assert pr[0] < 0.5 * pr[1], pr

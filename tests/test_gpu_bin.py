@@ -63,6 +63,7 @@ CASES = [
     ("full-size bins, 1e6 rays", W.CFG2["bins"], 1_000_017, 0.3),
     ("all rays in eight bins", W.CFG2["bins"], 200_000, 1.0),
     ("33.5M bins (direct path)", dict(n_theta=256, n_psi=512, n_omega=256, d_omega=1e-4), 200_001, 0.3),
+    ("3e6 rays (256 sorting workgroups, ragged chunks)", W.CFG1["bins"], 3_000_001, 0.3),
 ]
 
 
