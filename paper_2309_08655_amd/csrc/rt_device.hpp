@@ -294,8 +294,17 @@ RT_HD DipoleShape<T> dipole_shape(const InstT<T>& I, const T& ir) {
 // ----------------------------------------------------------------------------
 template <class T>
 struct Plasma {
-    T P, gx, gy, gz, gt;
+    // P and its derivatives: grad_x P = pn n + pm m + pz e_z, dP/dt = pt
+    T P, pn, pm, pz, pt;
 };
+
+// the Cartesian components of grad_x P
+template <class T>
+RT_HD void plasma_grad(const Plasma<T>& p, const T n[3], const T m[3], T g[3]) {
+    g[0] = p.pn * n[0] + p.pm * m[0];
+    g[1] = p.pn * n[1] + p.pm * m[1];
+    g[2] = p.pn * n[2] + p.pm * m[2] + p.pz;
+}
 
 // sin and cos of a rotation angle from Taylor polynomials: for |x| <= 1/32 the
 // series truncated after x^7 and x^8; otherwise after x^13 and x^14 (error below
@@ -408,45 +417,42 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
                             const T& dmu) {
     Plasma<T> p;
     if (I.density == DEN_NONE) {
-        p.P = T(0.0); p.gx = T(0.0); p.gy = T(0.0); p.gz = T(0.0); p.gt = T(0.0);
+        p.P = T(0.0); p.pn = T(0.0); p.pm = T(0.0); p.pz = T(0.0); p.pt = T(0.0);
         return p;
     }
     T ir3 = ir * ir * ir;
     T D3 = I.Cwp * I.R3 * ir3;  // Cwp (R/r)^3
     if (I.density == DEN_GJ) {
-        // P = D3 |g|, g = 3 n_z mu - cos(theta_m)
-        // grad g = (3/r)(mu z + n_z m - 2 n_z mu n)
+        // P = D3 |g|, g = 3 n_z mu - cos(theta_m); with a = 3 sign(g),
+        // grad P = (D3/r) [a (n_z m + mu e_z) - (2 a n_z mu + 3 |g|) n],  dP/dt = D3 a n_z dmu
         T g = 3.0 * n[2] * mu - I.cm;
         double sg = (value(g) < 0.0) ? -1.0 : 1.0;
         T ag = sg * g;
         p.P = D3 * ag;
         T c = D3 * ir;
-        T a = 3.0 * sg;
-        T nzmu2 = 2.0 * n[2] * mu;
-        // components: c * [a (mu e_z + n_z m - 2 n_z mu n) - 3 |g| n]
-        T rad = a * nzmu2 + 3.0 * ag;  // coefficient of -n
-        p.gx = c * (a * (n[2] * m[0]) - rad * n[0]);
-        p.gy = c * (a * (n[2] * m[1]) - rad * n[1]);
-        p.gz = c * (a * (mu + n[2] * m[2]) - rad * n[2]);
-        p.gt = D3 * a * n[2] * dmu;
+        T ca = (3.0 * sg) * c;
+        T nzmu = n[2] * mu;
+        p.pn = T(0.0) - (2.0 * ca * nzmu + 3.0 * c * ag);
+        p.pm = ca * n[2];
+        p.pz = ca * mu;
+        p.pt = ((3.0 * sg) * D3) * (n[2] * dmu);
     } else if (I.density == DEN_MAG) {
         // P = D3 (1 - mu^2) / r; grad P = (D3/r^2)(-4 (1 - mu^2) n - 2 mu (m - mu n))
         T s2 = 1.0 - mu * mu;
         T D4 = D3 * ir;
         p.P = D4 * s2;
         T c = D4 * ir;
-        T rad = 4.0 * s2 - 2.0 * mu * mu;  // coefficient of -n
-        T tm = 2.0 * mu;                   // coefficient of -m
-        p.gx = -(c * (rad * n[0] + tm * m[0]));
-        p.gy = -(c * (rad * n[1] + tm * m[1]));
-        p.gz = -(c * (rad * n[2] + tm * m[2]));
-        p.gt = -(D4 * tm * dmu);
+        p.pn = T(0.0) - c * (4.0 * s2 - 2.0 * mu * mu);
+        p.pm = (-2.0 * c) * mu;
+        p.pz = T(0.0);
+        p.pt = (-2.0 * D4) * (mu * dmu);
     } else {
         // spherical test profile P = D3
         p.P = D3;
-        T c = -3.0 * D3 * ir;
-        p.gx = c * n[0]; p.gy = c * n[1]; p.gz = c * n[2];
-        p.gt = T(0.0);
+        p.pn = -3.0 * D3 * ir;
+        p.pm = T(0.0);
+        p.pz = T(0.0);
+        p.pt = T(0.0);
     }
     return p;
 }
@@ -467,31 +473,39 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     T ia = aniso ? frsqrt(A) : T(0.0);
     T iA = aniso ? ia * ia : frcp(A);
     T q = n[0] * kx + n[1] * ky + n[2] * kz;
-    T kt2 = kt * kt;
+    T sr = s * ir;
     // vacuum: dH/dk = 2k - 2 s q n; dH/dk_t = -2 k_t / A;
     //         dH/dx = (s/r) [(k_t^2/A^2 + 3 q^2) n - 2 q k]
-    T sq2 = 2.0 * s * q;
-    g[4] = 2.0 * kx - sq2 * n[0];
-    g[5] = 2.0 * ky - sq2 * n[1];
-    g[6] = 2.0 * kz - sq2 * n[2];
-    g[7] = -2.0 * kt * iA;
-    T sr = s * ir;
-    T cn = sr * (kt2 * iA * iA + 3.0 * q * q);
-    T ck = 2.0 * sr * q;
-    g[0] = cn * n[0] - ck * kx;
-    g[1] = cn * n[1] - ck * ky;
-    g[2] = cn * n[2] - ck * kz;
-    g[3] = T(0.0);
-    if (I.density == DEN_NONE) return;
+    // Each spatial part is assembled below as Cn n + Cm m + Ck k (+ Cz e_z).
+    T kti = kt * iA;
+    T q3 = 3.0 * q;
+    T kn = -2.0 * s * q;                    // n coefficient of dH/dk
+    T Cn = sr * (kti * kti + q3 * q);       // n coefficient of dH/dx
+    T Ck = kn * ir;                         // k coefficient of dH/dx (-2 s q / r)
+    g[7] = -2.0 * kti;
+    if (I.density == DEN_NONE) {
+        for (int i = 0; i < 3; ++i) {
+            g[4 + i] = kn * n[i] + 2.0 * y[4 + i];
+            g[i] = Cn * n[i] + Ck * y[4 + i];
+        }
+        g[3] = T(0.0);
+        return;
+    }
 
     T m[3], mt[3];
     magnetic_axis(I, y[3], m, mt, ref);
     T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
-    T dmu = mt[0] * n[0] + mt[1] * n[1] + mt[2] * n[2];
+    // dm/dt = Omega e_z x m, so (dm/dt).v = Omega (m_x v_y - m_y v_x)
+    T dmu = I.oblique ? I.Om * (m[0] * n[1] - m[1] * n[0]) : T(0.0);
     Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
     if (I.plasma == PL_ISO) {
-        g[0] = g[0] + p.gx; g[1] = g[1] + p.gy; g[2] = g[2] + p.gz;
-        g[3] = g[3] + p.gt;
+        const T Cn2 = Cn + p.pn;
+        for (int i = 0; i < 3; ++i) {
+            g[4 + i] = kn * n[i] + 2.0 * y[4 + i];
+            g[i] = Cn2 * n[i] + p.pm * m[i] + Ck * y[4 + i];
+        }
+        g[2] = g[2] + p.pz;
+        g[3] = p.pt;
         return;
     }
     // anisotropic (strong-B LO mode): H += P (1 - K), K = A N^2 / (k_t^2 (1 + c mu^2)),
@@ -502,47 +516,50 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     if (I.gr_dipole) sh = dipole_shape(I, ir);
     T b = I.gr_dipole ? 1.0 + (sh.g - 1.0) * a : 1.0 + 2.0 * a;
     T mk = m[0] * kx + m[1] * ky + m[2] * kz;
-    T Nn = b * mu * q - mk;
-    T den = frcp(1.0 + (I.gr_dipole ? sh.c : T(3.0)) * mu * mu);
-    T ikt = frcp(kt);
-    T ikt2 = ikt * ikt;
-    T N2d = Nn * Nn * ikt2 * den;  // N^2 / (k_t^2 (1 + 3 mu^2))
-    T K = A * N2d;
-    T c1 = 2.0 * A * Nn * ikt2 * den;  // dK/dN
-    // dK/dk = c1 (b mu n - m)
     T bmu = b * mu;
+    T muq = mu * q;
+    T Nn = b * muq - mk;
+    T cc = I.gr_dipole ? sh.c : T(3.0);
+    T den = frcp(1.0 + cc * mu * mu);
+    T ikt = frcp(kt);
+    T Nd = Nn * (ikt * ikt) * den;  // N / (k_t^2 (1 + c mu^2))
+    T N2d = Nn * Nd;                // N^2 / (k_t^2 (1 + c mu^2))
+    T K = A * N2d;
+    T c1 = 2.0 * A * Nd;            // dK/dN
+    // dK/dk = c1 (b mu n - m);  dK/dk_t = -2 K / k_t
     T PK = p.P * c1;
-    g[4] = g[4] - PK * (bmu * n[0] - m[0]);
-    g[5] = g[5] - PK * (bmu * n[1] - m[1]);
-    g[6] = g[6] - PK * (bmu * n[2] - m[2]);
-    // dK/dk_t = -2 K / k_t  ->  dH/dk_t += 2 P K / k_t
+    T kn2 = kn - PK * bmu;
+    for (int i = 0; i < 3; ++i) g[4 + i] = kn2 * n[i] + (PK * m[i] + 2.0 * y[4 + i]);
     g[7] = g[7] + 2.0 * p.P * K * ikt;
-    // db/dr = g' sqrt(A) + (g - 1) s / (2 sqrt(A) r)  (flat: s / (sqrt(A) r))
-    // dN/dx = mu q (db/dr) n + b [q (m - mu n) + mu (k - q n)] / r
-    // dD/dx = c' mu^2 n + 2 c mu (m - mu n) / r,  D = 1 + c mu^2
-    // dK/dx = N2d (s/r) n + c1 dN/dx - K den dD/dx
-    T e_n, e_m;
-    T cc2 = 6.0;
+    // dK/dx = e_n n + e_m m + e_k k with
+    //   dN/dx = mu q (db/dr) n + b [q (m - mu n) + mu (k - q n)] / r   (flat: db/dr = s / (sqrt(A) r))
+    //   dD/dx = c' mu^2 n + 2 c mu (m - mu n) / r,  D = 1 + c mu^2
+    //   dK/dx = N2d (s/r) n + c1 dN/dx - K den dD/dx
+    T cbi = c1 * b * ir;
+    T e_k = cbi * mu;
+    T KDt = 2.0 * cc * K * den * mu;  // 2 c K mu den
+    T KD = KDt * ir;                  // 2 c K mu den / r
+    T e_m = cbi * q - KD;
+    T e_n;
     if (I.gr_dipole) {
         T dbdr = sh.dg * a + (sh.g - 1.0) * (0.5 * s * ir * ia);
-        cc2 = 2.0 * sh.c;
-        e_n = N2d * sr + c1 * (mu * q * dbdr) - c1 * b * ir * 2.0 * mu * q + cc2 * K * mu * den * ir * mu -
-              K * den * sh.dc * mu * mu;
-        e_m = c1 * b * ir * q - cc2 * K * mu * den * ir;
+        e_n = N2d * sr + muq * (c1 * dbdr - 2.0 * cbi) + KD * mu - K * den * sh.dc * mu * mu;
     } else {
-        e_n = N2d * sr + c1 * (mu * q * s * ir * ia) - c1 * b * ir * 2.0 * mu * q + 6.0 * K * mu * den * ir * mu;
-        e_m = c1 * b * ir * q - 6.0 * K * mu * den * ir;
+        e_n = N2d * sr + muq * (c1 * (sr * ia) - 2.0 * cbi) + KD * mu;
     }
-    T e_k = c1 * b * ir * mu;
+    // dH/dx = vacuum + (1 - K) grad P - P dK/dx
     T omK = 1.0 - K;
-    g[0] = g[0] + omK * p.gx - p.P * (e_n * n[0] + e_m * m[0] + e_k * kx);
-    g[1] = g[1] + omK * p.gy - p.P * (e_n * n[1] + e_m * m[1] + e_k * ky);
-    g[2] = g[2] + omK * p.gz - p.P * (e_n * n[2] + e_m * m[2] + e_k * kz);
-    // time: dN/dt = b q dmu - mt.k ; dK/dt = c1 dN/dt - 6 K mu den dmu
+    T Cn2 = Cn + (omK * p.pn - p.P * e_n);
+    T Cm = omK * p.pm - p.P * e_m;
+    T Ck2 = Ck - p.P * e_k;
+    for (int i = 0; i < 3; ++i) g[i] = Cn2 * n[i] + (Cm * m[i] + Ck2 * y[4 + i]);
+    g[2] = g[2] + omK * p.pz;
+    // time: dN/dt = b q dmu - mt.k ; dK/dt = c1 dN/dt - 2 c K mu den dmu
+    g[3] = T(0.0);
     if (I.oblique) {
-        T mtk = mt[0] * kx + mt[1] * ky + mt[2] * kz;
-        T dKdt = c1 * (b * q * dmu - mtk) - cc2 * K * mu * den * dmu;
-        g[3] = g[3] + omK * p.gt - p.P * dKdt;
+        T mtk = I.Om * (m[0] * ky - m[1] * kx);
+        T dKdt = c1 * (b * q * dmu - mtk) - KDt * dmu;
+        g[3] = omK * p.pt - p.P * dKdt;
     }
 }
 

@@ -475,8 +475,10 @@ RT_HD int seed_ray(const InstT<T>& I, const SeedT<T>& C, uint64_t seed, int32_t 
     T Q;
     Plasma<T> pl = plasma_eval(I, nT, ir, mT, muT, T(0.0));
     if (I.plasma == PL_ISO) {
-        T gn = n[0] * pl.gx + n[1] * pl.gy + n[2] * pl.gz;
-        T g2 = pl.gx * pl.gx + pl.gy * pl.gy + pl.gz * pl.gz - s * gn * gn;
+        T gP[3];
+        plasma_grad(pl, nT, mT, gP);
+        T gn = n[0] * gP[0] + n[1] * gP[1] + n[2] * gP[2];
+        T g2 = gP[0] * gP[0] + gP[1] * gP[1] + gP[2] * gP[2] - s * gn * gn;
         T dwp2 = C.hbarc * C.w_inf * C.w_inf * sqrt(g2);
         Q = (phys::pi * C.g2) * Bperp2 * E * E * rcp(dwp2);
     } else {
@@ -624,7 +626,9 @@ RT_HD double event_weight(const InstT<double>& I, const SeedT<double>& C, const 
     const Plasma<double> pl = plasma_eval(I, n, ir, m, mu, 0.0);
     double P, kdE;  // kdE = k^a d_a E [eV^2 / km]
     if (I.plasma == PL_ISO) {
-        const double kdw = kc[0] * pl.gx + kc[1] * pl.gy + kc[2] * pl.gz;  // [w_inf^3 / km]
+        double gP[3];
+        plasma_grad(pl, n, m, gP);
+        const double kdw = kc[0] * gP[0] + kc[1] * gP[1] + kc[2] * gP[2];  // [w_inf^3 / km]
         P = (phys::pi * C.g2) * Bperp2 * E * E * rcp(::fabs(C.hbarc * w * w * w * kdw));
         kdE = w * w * w * kdw * rcp(2.0 * E);
     } else {
