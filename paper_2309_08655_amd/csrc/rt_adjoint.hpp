@@ -79,17 +79,17 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
         for (int q = 0; q < 7; ++q) e += E[q] * K[q * 8 + d];
         e *= hh;
         const double sc = atol + rtol * fmax(fabs(y[d]), fabs(ynew[d]));
-        const double qq = e / sc;
+        const double qq = e * frcp_coarse(sc);
         acc += qq * qq;
     }
-    double err = sqrt(acc * 0.125);
-    if (!__builtin_isfinite(err)) err = 1e300;
-    if (!(err <= 1.0)) {
-        *h = hh * step_factor(err, *facmax, false);
+    double err2 = acc * 0.125;  // the square of the RMS error ratio
+    if (!__builtin_isfinite(err2)) err2 = 1e300;
+    if (!(err2 <= 1.0)) {
+        *h = hh * step_factor(err2, *facmax, false);
         *facmax = 1.0;
         return 0;
     }
-    *h = hh * step_factor(err, *facmax, true);
+    *h = hh * step_factor(err2, *facmax, true);
     *facmax = 10.0;
     return 1;
 }

@@ -181,11 +181,11 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
         }
         ++iters;
 
-        double err = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
+        double err2 = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
         if (!active) continue;
-        if (!(err <= 1.0)) {
+        if (!(err2 <= 1.0)) {
             ++nrej;
-            h *= step_factor(err, facmax, false);
+            h *= step_factor(err2, facmax, false);
             facmax = 1.0;
             if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) {
                 write_final_bwd(I, y, lam, h, nacc, nrej, ST_STEP_UNDERFLOW, p, n, fin, ifin, &ref);
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
         else if (rnew > 1.01 * D && rnew > rprev) status = ST_ESCAPED;
         if (status == ST_OK) {
             rprev = rnew;
-            h = step_cap(y, S.K[0], h * step_factor(err, facmax, true));
+            h = step_cap(y, S.K[0], h * step_factor(err2, facmax, true));
             facmax = 10.0;
             if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
             else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;

@@ -146,6 +146,8 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     y[7] = -1.0;
     AxisRef ref = axis_ref_at(I, 0.0);
     auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref); };
+    const double rmax2 = tol.rmax * tol.rmax;
+    double R2 = I.R * I.R;
 
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -163,6 +165,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                         if (BATCHED) {
                             I = itab[inst_of[j]];
                             fix(I);
+                            R2 = I.R * I.R;
                         }
                         for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
                         h = h0s[j];
@@ -180,23 +183,24 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
         }
         ++iters;
 
-        double err = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
+        double err2 = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
         if (!active) continue;
         // on termination y holds the final state (the raw record is completed by
         // finalize_kernel, which keeps the observables out of this loop)
         int status = ST_OK;
         double lam_out = lam;
-        if (!(err <= 1.0)) {
+        if (!(err2 <= 1.0)) {
             ++nrej;
-            h *= step_factor(err, facmax, false);
+            h *= step_factor(err2, facmax, false);
             facmax = 1.0;
             if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
         } else {
             ++nacc;
-            double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+            // radii compared squared (r >= r_max <=> r^2 >= r_max^2)
+            double r2new = ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2];
             bool finite_ok = true;
             for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(ynew[d]);
-            if (finite_ok && rnew >= tol.rmax) {
+            if (finite_ok && r2new >= rmax2) {
                 // locate r(theta) = r_max on the continuous extension
                 const double th = locate_crossing(y, ynew, S, h, tol.rmax);
                 double yt[8];
@@ -205,16 +209,16 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                 status = ST_ESCAPED;
                 lam_out = lam + th * h;
             } else {
-                if (I.oblique && finite_ok && rnew > I.R) axis_ref_advance(I, ref, ynew[3]);
+                if (I.oblique && finite_ok && r2new > R2) axis_ref_advance(I, ref, ynew[3]);
                 for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
                 lam += h;
                 lam_out = lam;
                 if (!finite_ok) {
                     status = ST_NONFINITE;
-                } else if (rnew <= I.R) {
+                } else if (r2new <= R2) {
                     status = ST_HIT_STAR;
                 } else {
-                    h *= step_factor(err, facmax, true);
+                    h *= step_factor(err2, facmax, true);
                     facmax = 10.0;
                     if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
                     else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;

@@ -40,7 +40,8 @@ using Stages = StagesT<double>;
 RT_HD bool finite_value(double x) { return __builtin_isfinite(x); }
 
 // One attempted step of length h from y with K[0] = f(y) already set.
-// Fills K[1..6], ynew, and returns the RMS error ratio (not yet checked).
+// Fills K[1..6], ynew, and returns the square of the RMS error ratio (not yet checked;
+// the step is accepted when it is <= 1, and non-finite values arrive as 1e300).
 template <class T, class RHS>
 RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], double rtol, double atol) {
     using namespace dp5;
@@ -81,8 +82,8 @@ RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], doub
         T qq = e * frcp_coarse(sc);
         acc = acc + qq * qq;
     }
-    T err = sqrt(acc * 0.125);
-    return finite_value(err) ? err : T(1e300);
+    T err2 = acc * 0.125;
+    return finite_value(err2) ? err2 : T(1e300);
 }
 
 // Continuous extension at theta of components [c0, c1) (accepted step y -> ynew).
@@ -152,29 +153,32 @@ RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stag
     return th;
 }
 
-// Step-size update after an attempt (HNW I-controller, order 5):
+// Step-size update after an attempt (HNW I-controller, order 5), from err2 = err^2:
 // accepted: h *= min(facmax, max(0.2, 0.9 err^-1/5)) (err = 0 -> facmax);
 // rejected: h *= max(0.2, 0.9 err^-1/5) and facmax = 1 for the next accepted step.
-// err^(-1/5) for the controller: a single-precision estimate refined by two Newton steps
-// in double on u = x^5 err = 1 (x <- x (1 - (u - 1)/(5 u))), accurate to a few ulp.  err
-// is clamped to [1e-30, 1e30], outside which the factor saturates at facmax or 0.2 anyway.
-RT_HD double inv_fifth_root(double err) {
-    const double e = fmin(fmax(err, 1e-30), 1e30);
-    double x = (double)exp2f(-0.2f * log2f((float)e));
+// err^(-1/5) = err2^(-1/10): a single-precision estimate refined by two Newton steps in
+// double on u = x^10 err2 = 1, x <- x (1 - (u - 1)/(10 u)), with 1/u replaced by 2 - u
+// (u is within ~1e-6 of 1 after the estimate, so the replacement costs nothing in
+// accuracy): a few ulp, no division.  err2 is clamped to [1e-30, 1e30] (single-precision
+// range for the estimate), outside which the factor saturates at facmax or 0.2 anyway.
+RT_HD double inv_tenth_root(double err2) {
+    const double e = fmin(fmax(err2, 1e-30), 1e30);
+    double x = (double)exp2f(-0.1f * log2f((float)e));
     for (int it = 0; it < 2; ++it) {
         const double x2 = x * x;
-        const double u = x2 * x2 * x * e;
-        x = x - x * (u - 1.0) / (5.0 * u);
+        const double x4 = x2 * x2;
+        const double u = (x4 * x4) * x2 * e;
+        x = x - (x * (u - 1.0)) * (0.1 * (2.0 - u));
     }
     return x;
 }
 
-RT_HD double step_factor(double err, double facmax, bool accepted) {
+RT_HD double step_factor(double err2, double facmax, bool accepted) {
     if (accepted) {
-        if (err == 0.0) return facmax;
-        return fmin(facmax, fmax(0.2, 0.9 * inv_fifth_root(err)));
+        if (err2 == 0.0) return facmax;
+        return fmin(facmax, fmax(0.2, 0.9 * inv_tenth_root(err2)));
     }
-    return fmax(0.2, 0.9 * inv_fifth_root(err));
+    return fmax(0.2, 0.9 * inv_tenth_root(err2));
 }
 
 // Starting step (HNW Sec. II.4, order 5), norm scale atol + rtol |y0|.

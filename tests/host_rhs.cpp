@@ -27,7 +27,7 @@ double host_hamiltonian(const double* c, const int* e, const double* y) {
     InstT<double> I = inst_from(c, e);
     return hamiltonian(I, y);
 }
-// one attempted step: returns err, writes ynew
+// one attempted step: returns err^2, writes ynew
 double host_attempt(const double* c, const int* e, const double* y, double h, double* ynew, double rtol,
                     double atol) {
     InstT<double> I = inst_from(c, e);
@@ -53,10 +53,10 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
     double lam = 0.0, facmax = 10.0;
     int nacc = 0, nrej = 0, status = 0;
     while (status == 0) {
-        double err = dopri_attempt(f, y, S, h, ynew, rtol, atol);
-        if (!(err <= 1.0)) {
+        double err2 = dopri_attempt(f, y, S, h, ynew, rtol, atol);
+        if (!(err2 <= 1.0)) {
             ++nrej;
-            h *= step_factor(err, facmax, false);
+            h *= step_factor(err2, facmax, false);
             facmax = 1.0;
             if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = 5;
         } else {
@@ -82,7 +82,7 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
             } else {
                 lam += h;
                 for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
-                h *= step_factor(err, facmax, true);
+                h *= step_factor(err2, facmax, true);
                 facmax = 10.0;
                 if (nacc >= max_steps) status = 4;
             }
@@ -94,9 +94,9 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
 }
 
 extern "C" {
-// the controller's err^(-1/5) and step factor
-double host_inv_fifth_root(double err) { return inv_fifth_root(err); }
-double host_step_factor(double err, double facmax, int accepted) { return step_factor(err, facmax, accepted != 0); }
+// the controller's err^(-1/5) = err2^(-1/10) and step factor, from err2 = err^2
+double host_inv_tenth_root(double err2) { return inv_tenth_root(err2); }
+double host_step_factor(double err2, double facmax, int accepted) { return step_factor(err2, facmax, accepted != 0); }
 }
 
 #include "../paper_2309_08655_amd/csrc/rt_seed.hpp"

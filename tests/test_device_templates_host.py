@@ -144,24 +144,26 @@ def test_newton_crossing_locator_matches_bisection(orc, host, cfg):
 
 
 def test_controller_fifth_root_matches_pow(host):
-    """The kernels' err^(-1/5) (single-precision seed + two Newton steps in double) agrees with
+    """The kernels take err^2 from the attempt and form err^(-1/5) = err2^(-1/10) from a
+    single-precision estimate and two division-free Newton steps in double: it agrees with
     pow to a few ulp over the controller's range, and the step factor saturates as pow's does."""
-    host.host_inv_fifth_root.restype = C.c_double
-    host.host_inv_fifth_root.argtypes = [C.c_double]
+    host.host_inv_tenth_root.restype = C.c_double
+    host.host_inv_tenth_root.argtypes = [C.c_double]
     host.host_step_factor.restype = C.c_double
     host.host_step_factor.argtypes = [C.c_double, C.c_double, C.c_int]
     rng = np.random.default_rng(2)
-    errs = np.concatenate([10.0 ** rng.uniform(-30, 30, 20000), 1.0 + rng.uniform(-1e-6, 1e-6, 2000),
-                           [1.0, 1e-30, 1e30, 0.5, 2.0]])
-    worst = max(abs(host.host_inv_fifth_root(e) / e ** -0.2 - 1.0) for e in errs)
+    errs = np.concatenate([10.0 ** rng.uniform(-15, 15, 20000), 1.0 + rng.uniform(-1e-6, 1e-6, 2000),
+                           [1.0, 1e-15, 1e15, 0.5, 2.0]])
+    worst = max(abs(host.host_inv_tenth_root(e * e) / e ** -0.2 - 1.0) for e in errs)
     assert worst < 8 * 2.0 ** -52, worst
     # accepted steps have err <= 1, rejected ones err > 1 (non-finite errors arrive as 1e300)
     for e in (0.0, 1e-300, 1e-40, 1e-6, 0.3, 1.0):
         ref = 10.0 if e == 0 else min(10.0, max(0.2, 0.9 * e ** -0.2))
-        assert host.host_step_factor(e, 10.0, 1) == pytest.approx(ref, rel=1e-15), e
-        assert host.host_step_factor(e, 1.0, 1) == pytest.approx(min(1.0, ref), rel=1e-15), e
-    for e in (1.0000001, 3.0, 1e5, 1e40, 1e300):
-        assert host.host_step_factor(e, 10.0, 0) == pytest.approx(max(0.2, 0.9 * e ** -0.2), rel=1e-15), e
+        assert host.host_step_factor(e * e, 10.0, 1) == pytest.approx(ref, rel=1e-15), e
+        assert host.host_step_factor(e * e, 1.0, 1) == pytest.approx(min(1.0, ref), rel=1e-15), e
+    for e in (1.0000001, 3.0, 1e5, 1e40, 1e150):
+        assert host.host_step_factor(e * e, 10.0, 0) == pytest.approx(max(0.2, 0.9 * e ** -0.2), rel=1e-15), e
+    assert host.host_step_factor(1e300, 10.0, 0) == pytest.approx(0.2, rel=1e-15)
 
 
 def _named_star(name):
