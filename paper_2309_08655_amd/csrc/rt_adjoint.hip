@@ -94,7 +94,7 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
 // cost-ordered work list; checkpoints, per-ray counters and the flux
-__global__ void __launch_bounds__(256) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
+__global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
                                                       const double* __restrict__ h0s, int C, int Kc,
                                                       double* __restrict__ ckpt, int32_t* __restrict__ nseg_out,

@@ -34,7 +34,20 @@ typedef gdual<14> D14;
 // it computes the same bits and the recompute reproduces the forward pass's decisions
 // and step sizes (the reverse sweep checks this at every checkpoint).
 // ----------------------------------------------------------------------------
-RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) { rhs(I, y, f, 1.0); }
+// The right-hand side must be a function of the state and the attempt alone (the
+// recompute starts from checkpointed states and must reproduce every bit).  The magnetic
+// axis is rotated from a reference phase: adj_rhs(I, y, f) takes it at y's own time (the
+// first and last stage of an attempt, so the last stage's value serves the next attempt
+// as its first, as in the forward pass), and the inner stages take the attempt's
+// reference at its starting time and rotate by the small stage angle.  Both avoid a full
+// sincos per evaluation.
+RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, const AxisRef& ref) {
+    rhs(I, y, f, 1.0, &ref);
+}
+RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) {
+    const AxisRef ref = axis_ref_at(I, y[3]);
+    rhs(I, y, f, 1.0, &ref);
+}
 
 // One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
 // the last = f(ynew)), ynew and, if Ys != nullptr, the stage states Ys[0..47]
@@ -50,6 +63,7 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
                             {a61, a62, a63, a64, a65, 0},
                             {b1, 0.0, b3, b4, b5, b6}};
     const double hh = *h;
+    const AxisRef ref0 = axis_ref_at(I, y[3]);
     double tmp[8];
     if (Ys)
         for (int d = 0; d < 8; ++d) Ys[d] = y[d];
@@ -68,7 +82,10 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
         } else {
             for (int d = 0; d < 8; ++d) ynew[d] = tmp[d];
         }
-        adj_rhs(I, tmp, K + (s + 1) * 8);
+        if (s < 5)
+            adj_rhs(I, tmp, K + (s + 1) * 8, ref0);
+        else
+            adj_rhs(I, tmp, K + (s + 1) * 8);
     }
     const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
     double acc = 0.0;
