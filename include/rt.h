@@ -119,6 +119,8 @@ typedef struct rt_schedule {
     int32_t refill_min;   /* idle lanes a wave waits for before refilling from the queue */
     int32_t occupancy;    /* register budget of the tracing kernels: 1 = one wave per SIMD (no
                              spills), 2 = two waves per SIMD (a few spills to scratch) */
+    int32_t cross_batch;  /* forward tracing of the GJ density: crossings of the null surface a
+                             wave lets wait before restarting them together (1..64; 0 = 8) */
 } rt_schedule;
 
 /* Number of doubles / int32 per final record (fin: "[RT_NFIN][n]", ifin: "[RT_NIFIN][n]"):

@@ -72,7 +72,7 @@ def lib():
         L.orc_energy_aniso.argtypes = [sp, dp, C.c_double, dp]
         L.orc_energy_aniso.restype = C.c_double
         L.orc_sample.argtypes = [sp, C.c_uint64, C.c_int32, C.c_int64, C.c_int64, dp, ip, C.c_int]
-        L.orc_trace_forward.argtypes = [sp, tp, dp, ip, C.c_int64, dp, ip, C.c_int]
+        L.orc_trace_forward.argtypes = [sp, tp, dp, ip, C.c_int64, dp, ip, C.c_int, C.c_int]
         L.orc_trace_reverse.argtypes = [sp, tp, dp, C.c_int64, C.c_double, dp, ip, C.c_int]
         L.orc_bin.argtypes = [dp, ip, dp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_double, dp, dp, dp]
         L.orc_trace_backward.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -187,8 +187,10 @@ def sample(s, seed, n, instance=0, first=0, nthreads=0):
     return rays, st
 
 
-def trace_forward(s, t, rays, status=None, nthreads=0):
-    """Trace seeds to r_max.  Returns (fin[16, n], ifin[3, n] = n_acc, n_rej, status)."""
+def trace_forward(s, t, rays, status=None, nthreads=0, kinks=True):
+    """Trace seeds to r_max.  Returns (fin[16, n], ifin[3, n] = n_acc, n_rej, status).
+    kinks: cut and restart steps at the GJ density's null surface (the forward-tracing
+    definition); False integrates |g| as it stands (the adjoint's discretised map)."""
     rays = np.ascontiguousarray(rays, dtype=np.float64)
     n = rays.shape[1]
     if rays.shape[0] < 10:
@@ -199,7 +201,7 @@ def trace_forward(s, t, rays, status=None, nthreads=0):
     ifin = np.zeros((NIFIN, n), dtype=np.int32)
     stp = None if status is None else _ip(np.ascontiguousarray(status, dtype=np.int32))
     lib().orc_trace_forward(C.byref(make_star(s)), C.byref(make_tol(t)), _dp(rays), stp, n, _dp(fin), _ip(ifin),
-                            nthreads)
+                            nthreads, 1 if kinks else 0)
     return fin, ifin
 
 

@@ -77,9 +77,12 @@ double orc_resonance_radius(const orc_star* s, const double nhat[3], const doubl
 double orc_energy_aniso(const orc_star* s, const double x[3], double t, const double k[3]);
 
 /* forward trace: rays[10][n] as produced by orc_sample (w and r_c unused);
-   status_in[n]; fin[ORC_NFIN][n]; ifin[ORC_NIFIN][n] */
+   status_in[n]; fin[ORC_NFIN][n]; ifin[ORC_NIFIN][n].  kinks != 0: for the GJ density,
+   one smooth piece at a time, cut and restarted at every crossing of the null surface
+   (the forward-tracing definition); kinks = 0: the density |g| as it stands, as the
+   adjoint's discretised map integrates it */
 int orc_trace_forward(const orc_star* s, const orc_tol* tol, const double* rays, const int32_t* status_in,
-                      int64_t n, double* fin, int32_t* ifin, int nthreads);
+                      int64_t n, double* fin, int32_t* ifin, int nthreads, int kinks);
 /* same, backward in the worldline parameter (for the time-reversal check) */
 int orc_trace_reverse(const orc_star* s, const orc_tol* tol, const double* rays, int64_t n,
                       double lam_stop_abs, double* fin, int32_t* ifin, int nthreads);

@@ -172,6 +172,9 @@ struct Inst {
     double g_eV;   // coupling [eV^-1]
     double Btest;  // constant |B_perp| of the zero-variance test [G]
     int plasma, density, weights, kdir, speeds, flags;
+    // GJ density only: 0 = the density itself, |g|; +1 or -1 = the smooth piece s g of it
+    // that forward tracing integrates between crossings of the null surface g = 0
+    double gj_branch;
 };
 
 template <class P>
@@ -208,6 +211,7 @@ static Inst<P> make_inst(const orc_star& s, const P p[6]) {
     I.plasma = s.plasma; I.density = s.density; I.weights = s.weights; I.kdir = s.kdir;
     I.speeds = s.speeds;
     I.flags = s.flags;
+    I.gj_branch = 0.0;
     return I;
 }
 
@@ -244,13 +248,25 @@ static S wp2_tilde(const Inst<P>& I, const S x[3], const S& t) {
     S Rr3 = Rr * Rr * Rr;
     if (I.density == DEN_GJ) {
         // |2 Omega.B| with the dipole field below: Omega.B ~ 3 cos(theta) (m.n) - cos(theta_m)
-        return I.Cwp * Rr3 * fabs(3.0 * n[2] * mu - I.cm);
+        const S g = 3.0 * n[2] * mu - I.cm;
+        return I.Cwp * Rr3 * ((I.gj_branch != 0.0) ? I.gj_branch * g : fabs(g));
     }
     if (I.density == DEN_MAG) {
         // sin^2 of the magnetic colatitude
         return I.Cwp * Rr3 * (1.0 - mu * mu) / r;
     }
     return I.Cwp * Rr3;  // spherical test profile
+}
+
+// The GJ factor g = 3 cos(theta) (m.n) - cos(theta_m) at a point (its sign picks the
+// smooth piece of the density; the null surface is g = 0).
+template <class P>
+static double gj_factor(const Inst<P>& I, const double x[3], double t) {
+    const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double n[3] = {x[0] / r, x[1] / r, x[2] / r};
+    const double ph = val(I.Om) * t;
+    const double m[3] = {val(I.sm) * std::cos(ph), val(I.sm) * std::sin(ph), val(I.cm)};
+    return 3.0 * n[2] * (m[0] * n[0] + m[1] * n[1] + m[2] * n[2]) - val(I.cm);
 }
 
 // Radial profiles of the static vacuum dipole in Schwarzschild, x = r_s / r: the vector
@@ -889,11 +905,24 @@ struct TraceOut {
 
 // One forward ray from y0 to r = r_max (or another terminal condition).
 // hfix != nullptr replays a recorded sequence of accepted steps (frozen steps).
+// kinks: for the GJ density, integrate one smooth piece s g of |g| at a time.  The
+// density has a kink on the null surface g = 0, where the right-hand side jumps; an
+// accepted step whose end lies on the other side is cut at the crossing, located by 60
+// bisections on its continuous extension (the first point past it), and the ray restarts
+// there on the other piece with a fresh derivative (the treatment of a discontinuity
+// in Hairer, Norsett & Wanner I, Sec. II.6).  Without it the step size collapses at every
+// crossing and the error control loses accuracy there.
 template <class S, class P>
 static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8], double sign,
-                             std::vector<double>* hrec, const double* hfix, int64_t nfix) {
+                             std::vector<double>* hrec, const double* hfix, int64_t nfix, bool kinks = false) {
     TraceOut<S> o;
-    auto f = [&](const S* yy, S* ff) { rhs_t(I, yy, ff, sign); };
+    Inst<P> J = I;  // J.gj_branch: the piece being integrated
+    const bool kinky = kinks && I.density == DEN_GJ;
+    if (kinky) {
+        const double x0[3] = {val(y0[0]), val(y0[1]), val(y0[2])};
+        J.gj_branch = (gj_factor(I, x0, val(y0[3])) < 0.0) ? -1.0 : 1.0;
+    }
+    auto f = [&](const S* yy, S* ff) { rhs_t(J, yy, ff, sign); };
     S y[8], k1[8];
     for (int i = 0; i < 8; ++i) y[i] = y0[i];
     f(y, k1);
@@ -933,6 +962,20 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
             for (int i = 0; i < 8; ++i) o.yf[i] = st.ynew[i];
             o.status = ORC_HIT_STAR; lam += h; break;
         }
+        // crossing of the null surface inside the step (none: thk > 1)
+        double thk = 2.0;
+        if (kinky && J.gj_branch * gj_factor(I, yv, yv[3]) < 0.0) {
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 60; ++it) {
+                double mid = 0.5 * (lo + hi);
+                S ym[8];
+                dense_eval(y, st, h, mid, ym);
+                const double xm[3] = {val(ym[0]), val(ym[1]), val(ym[2])};
+                if (J.gj_branch * gj_factor(I, xm, val(ym[3])) > 0.0) lo = mid; else hi = mid;
+            }
+            thk = hi;
+        }
+        double th = 2.0;
         if (rnew >= tol.r_max_km) {
             // locate r(theta) = r_max on the continuous extension: 60 bisections
             double lo = 0.0, hi = 1.0;
@@ -943,7 +986,9 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
                 double rm = std::sqrt(val(ym[0]) * val(ym[0]) + val(ym[1]) * val(ym[1]) + val(ym[2]) * val(ym[2]));
                 if (rm >= tol.r_max_km) hi = mid; else lo = mid;
             }
-            double th = hi;
+            th = hi;
+        }
+        if (th <= 1.0 && th <= thk) {
             if constexpr (is_dual<S>::value) {
                 // implicit derivative of the crossing: r(y(theta)) = r_max
                 S yth[8], dy[8];
@@ -961,8 +1006,18 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
             lam += th * h;
             break;
         }
-        lam += h;
-        for (int i = 0; i < 8; ++i) { y[i] = st.ynew[i]; k1[i] = st.K[6][i]; }
+        if (thk <= 1.0) {
+            // restart at the first point past the null surface, on the other piece
+            S yk[8];
+            dense_eval(y, st, h, thk, yk);
+            for (int i = 0; i < 8; ++i) y[i] = yk[i];
+            lam += thk * h;
+            J.gj_branch = -J.gj_branch;
+            f(y, k1);
+        } else {
+            lam += h;
+            for (int i = 0; i < 8; ++i) { y[i] = st.ynew[i]; k1[i] = st.K[6][i]; }
+        }
         if (hfix == nullptr) {
             double fac = (err == 0.0) ? facmax : std::min(facmax, std::max(0.2, 0.9 * std::pow(err, -0.2)));
             h *= fac;
@@ -1315,7 +1370,7 @@ int orc_sample(const orc_star* s, uint64_t seed, int32_t instance, int64_t first
 }
 
 int orc_trace_forward(const orc_star* s, const orc_tol* tol, const double* rays, const int32_t* status_in, int64_t n,
-                      double* fin, int32_t* ifin, int nthreads) {
+                      double* fin, int32_t* ifin, int nthreads, int kinks) {
     Inst<double> I = make_inst_d(*s);
     // flat-propagation variant: the seeds carry curved initial conditions, Hamilton's
     // equations are integrated with M = 0
@@ -1329,7 +1384,7 @@ int orc_trace_forward(const orc_star* s, const orc_tol* tol, const double* rays,
         }
         double y0[8];
         for (int d = 0; d < 8; ++d) y0[d] = rays[d * n + j];
-        TraceOut<double> o = trace_one<double, double>(I, *tol, y0, 1.0, nullptr, nullptr, 0);
+        TraceOut<double> o = trace_one<double, double>(I, *tol, y0, 1.0, nullptr, nullptr, 0, kinks != 0);
         store_final(I, o, j, n, fin, ifin);
     }
     return 0;

@@ -411,10 +411,12 @@ RT_HD void magnetic_axis(const InstT<T>& I, const T& t, T m[3], T mt[3], const A
     }
 }
 
-// n = unit position, ir = 1/r, m = axis, mu = m.n, dmu = dm/dt . n
+// n = unit position, ir = 1/r, m = axis, mu = m.n, dmu = dm/dt . n.  gjs (GJ density only):
+// 0 = the density D3 |g| itself; +1 or -1 = its smooth piece D3 gjs g, which forward
+// tracing integrates between crossings of the null surface g = 0.
 template <class T>
 RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const T m[3], const T& mu,
-                            const T& dmu) {
+                            const T& dmu, double gjs = 0.0) {
     Plasma<T> p;
     if (I.density == DEN_NONE) {
         p.P = T(0.0); p.pn = T(0.0); p.pm = T(0.0); p.pz = T(0.0); p.pt = T(0.0);
@@ -426,7 +428,7 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
         // P = D3 |g|, g = 3 n_z mu - cos(theta_m); with a = 3 sign(g),
         // grad P = (D3/r) [a (n_z m + mu e_z) - (2 a n_z mu + 3 |g|) n],  dP/dt = D3 a n_z dmu
         T g = 3.0 * n[2] * mu - I.cm;
-        double sg = (value(g) < 0.0) ? -1.0 : 1.0;
+        double sg = (gjs != 0.0) ? gjs : ((value(g) < 0.0) ? -1.0 : 1.0);
         T ag = sg * g;
         p.P = D3 * ag;
         T c = D3 * ir;
@@ -461,7 +463,7 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
 // gradient of H: g = (dH/dx, dH/dy, dH/dz, dH/dt, dH/dk_x, dH/dk_y, dH/dk_z, dH/dk_t)
 // ----------------------------------------------------------------------------
 template <class T>
-RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = nullptr) {
+RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = nullptr, double gjs = 0.0) {
     const T& kx = y[4]; const T& ky = y[5]; const T& kz = y[6]; const T& kt = y[7];
     T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
     T ir = frsqrt(r2);
@@ -497,7 +499,7 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
     // dm/dt = Omega e_z x m, so (dm/dt).v = Omega (m_x v_y - m_y v_x)
     T dmu = I.oblique ? I.Om * (m[0] * n[1] - m[1] * n[0]) : T(0.0);
-    Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu);
+    Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu, gjs);
     if (I.plasma == PL_ISO) {
         const T Cn2 = Cn + p.pn;
         for (int i = 0; i < 3; ++i) {
@@ -564,10 +566,12 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
 }
 
 // Hamilton's equations, eq. (Hamilton); sign = -1 integrates backwards in the worldline parameter.
+// gjs selects the piece of the GJ density (see plasma_eval).
 template <class T>
-RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign, const AxisRef* ref = nullptr) {
+RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign, const AxisRef* ref = nullptr,
+               double gjs = 0.0) {
     T g[8];
-    grad_h(I, y, g, ref);
+    grad_h(I, y, g, ref, gjs);
     for (int i = 0; i < 4; ++i) {
         f[i] = sign * g[4 + i];
         f[4 + i] = -sign * g[i];
@@ -610,6 +614,17 @@ RT_HD T g_kk(const InstT<T>& I, const T y[8]) {
     T q = (y[0] * y[4] + y[1] * y[5] + y[2] * y[6]) * ir;
     T kk = y[4] * y[4] + y[5] * y[5] + y[6] * y[6];
     return -(y[7] * y[7]) * frcp(1.0 - s) + kk - s * q * q;
+}
+
+// The GJ factor g = 3 n_z (m.n) - cos(theta_m) at the state y (the density is
+// proportional to |g|; the null surface is g = 0)
+template <class T>
+RT_HD double gj_factor(const InstT<T>& I, const double y[8], const AxisRef* ref = nullptr) {
+    const double ir = frsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    const double n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
+    double m[3], mt[3];
+    magnetic_axis(I, y[3], m, mt, ref);
+    return 3.0 * n[2] * (m[0] * n[0] + m[1] * n[1] + m[2] * n[2]) - value(I.cm);
 }
 
 // dipole field direction u = 3 mu n - m (|u|^2 = 1 + 3 mu^2) and magnitude factor

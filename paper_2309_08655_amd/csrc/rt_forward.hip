@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const
                                                          const int32_t* __restrict__ status, int64_t n,
                                                          int32_t* __restrict__ keys, double* __restrict__ h0s,
                                                          double* __restrict__ k1s, double* __restrict__ fin,
-                                                         int32_t* __restrict__ ifin) {
+                                                         int32_t* __restrict__ ifin, int cut_gj) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
@@ -84,7 +84,11 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const
         } else {
             double y[8], f0[8];
             for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
-            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+            // GJ density, cut at the null surface (forward tracing): the smooth piece of |g|
+            // the seed lies on, which the tracing kernel integrates from here (also for the
+            // starting step's probe); the adjoint integrates |g| itself (cut_gj = 0)
+            const double gjs = (cut_gj && I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
+            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, nullptr, gjs); };
             f(y, f0);
             double h = initial_step(f, y, f0, tol.rtol, tol.atol);
             h0s[j] = h;
@@ -113,7 +117,8 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           int64_t n, WorkCtr* ctr, const int32_t* __restrict__ list,
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
-                                                          int32_t* __restrict__ ifin, int refill_min) {
+                                                          int32_t* __restrict__ ifin, int refill_min,
+                                                          int cross_batch) {
     // a specialised instantiation (SPEC = 1 + plasma + 2 density + 8 oblique) fixes these
     // switches at compile time: the Hamiltonian and its gradient become branch-free code with
     // the same arithmetic (the file is built with -ffp-contract=on, so the generic and the
@@ -145,7 +150,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     y[0] = 1e4;  // harmless dummy state for idle lanes
     y[7] = -1.0;
     AxisRef ref = axis_ref_at(I, 0.0);
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref); };
+    // GJ density: the lane integrates the smooth piece gjs g of |g| (gjs = +1 or -1) and
+    // restarts on the other piece where a step crosses the null surface g = 0; phi = gjs g
+    // at y.  Other densities: gjs = 0.
+    double gjs = 0.0, phi = 0.0;
+    bool pending = false;          // a crossing waits for its restart
+    double phi1 = 0.0, errp = 0.0;  // its step's end value of gjs g and its error
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref, gjs); };
     const double rmax2 = tol.rmax * tol.rmax;
     double R2 = I.R * I.R;
 
@@ -171,6 +182,12 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                         h = h0s[j];
                         lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
                         if (I.oblique) ref = axis_ref_at(I, y[3]);
+                        if (I.density == DEN_GJ) {
+                            const double g0 = gj_factor(I, y, &ref);
+                            gjs = (g0 < 0.0) ? -1.0 : 1.0;
+                            phi = gjs * g0;
+                        }
+                        pending = false;
                         active = true;
                     }
                 }
@@ -183,48 +200,97 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
         }
         ++iters;
 
-        double err2 = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
-        if (!active) continue;
         // on termination y holds the final state (the raw record is completed by
         // finalize_kernel, which keeps the observables out of this loop)
         int status = ST_OK;
         double lam_out = lam;
-        if (!(err2 <= 1.0)) {
-            ++nrej;
-            h *= step_factor(err2, facmax, false);
-            facmax = 1.0;
-            if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
-        } else {
-            ++nacc;
-            // radii compared squared (r >= r_max <=> r^2 >= r_max^2)
-            double r2new = ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2];
-            bool finite_ok = true;
-            for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(ynew[d]);
-            if (finite_ok && r2new >= rmax2) {
-                // locate r(theta) = r_max on the continuous extension
-                const double th = locate_crossing(y, ynew, S, h, tol.rmax);
+        // Lanes whose last accepted step crossed the GJ null surface wait (their step,
+        // stages and error kept) and are restarted together once cross_batch of them, or
+        // half of the wave's active lanes, wait: the restart (locating the crossing and a
+        // fresh derivative) then costs the wave one pass for many lanes.
+        const unsigned long long waiting = __ballot(pending);
+        const int nwait = __popcll(waiting);
+        if (nwait > 0 && (nwait >= cross_batch || 2 * nwait >= __popcll(__ballot(active)))) {
+            if (pending) {
+                double phik;
+                const double thk = locate_null_crossing(I, y, ynew, S, h, gjs, phi, phi1, &ref, &phik);
+                // the step may also have reached r_max: whichever comes first
+                const double r2new = ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2];
+                const double th = (r2new >= rmax2) ? locate_crossing(y, ynew, S, h, tol.rmax) : 2.0;
+                const double tc = (th <= thk) ? th : thk;
                 double yt[8];
-                dense_at(y, ynew, S, h, th, yt, 0, 8);
+                dense_at(y, ynew, S, h, tc, yt, 0, 8);
                 for (int d = 0; d < 8; ++d) y[d] = yt[d];
-                status = ST_ESCAPED;
-                lam_out = lam + th * h;
-            } else {
-                if (I.oblique && finite_ok && r2new > R2) axis_ref_advance(I, ref, ynew[3]);
-                for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
-                lam += h;
-                lam_out = lam;
-                if (!finite_ok) {
-                    status = ST_NONFINITE;
-                } else if (r2new <= R2) {
-                    status = ST_HIT_STAR;
+                if (th <= thk) {
+                    status = ST_ESCAPED;
+                    lam_out = lam + th * h;
                 } else {
-                    h *= step_factor(err2, facmax, true);
+                    lam += thk * h;
+                    lam_out = lam;
+                    gjs = -gjs;
+                    phi = -phik;  // the new piece's value there, >= 0
+                    if (I.oblique) axis_ref_advance(I, ref, y[3]);
+                    f(y, S.K[0]);
+                    h *= step_factor(errp, facmax, true);
                     facmax = 10.0;
                     if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
                     else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
                 }
+                pending = false;
             }
         }
+        if (active && !pending && status == ST_OK) {
+            const double err2 = dopri_attempt(f, y, S, h, ynew, tol.rtol, tol.atol);
+            if (!(err2 <= 1.0)) {
+                ++nrej;
+                h *= step_factor(err2, facmax, false);
+                facmax = 1.0;
+                if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
+            } else {
+                ++nacc;
+                // radii compared squared (r >= r_max <=> r^2 >= r_max^2)
+                double r2new = ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2];
+                bool finite_ok = true;
+                for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(ynew[d]);
+                // crossing of the GJ null surface inside the step
+                double g1 = 0.0;
+                bool cross = false;
+                if (I.density == DEN_GJ && finite_ok && r2new > R2) {
+                    g1 = gj_factor(I, ynew, &ref);
+                    cross = (gjs * g1 < 0.0);
+                }
+                if (cross) {
+                    pending = true;  // restarted (or ended at r_max) with the next batch
+                    phi1 = gjs * g1;
+                    errp = err2;
+                } else if (finite_ok && r2new >= rmax2) {
+                    // locate r(theta) = r_max on the continuous extension
+                    const double th = locate_crossing(y, ynew, S, h, tol.rmax);
+                    double yt[8];
+                    dense_at(y, ynew, S, h, th, yt, 0, 8);
+                    for (int d = 0; d < 8; ++d) y[d] = yt[d];
+                    status = ST_ESCAPED;
+                    lam_out = lam + th * h;
+                } else {
+                    if (I.oblique && finite_ok && r2new > R2) axis_ref_advance(I, ref, ynew[3]);
+                    for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+                    lam += h;
+                    lam_out = lam;
+                    phi = gjs * g1;
+                    if (!finite_ok) {
+                        status = ST_NONFINITE;
+                    } else if (r2new <= R2) {
+                        status = ST_HIT_STAR;
+                    } else {
+                        h *= step_factor(err2, facmax, true);
+                        facmax = 10.0;
+                        if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
+                        else if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = ST_STEP_UNDERFLOW;
+                    }
+                }
+            }
+        }
+        if (!active) continue;
         if (status != ST_OK) {
             for (int d = 0; d < 8; ++d) fin[d * n + j] = y[d];
             fin[13 * n + j] = lam_out;
@@ -438,7 +504,7 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     FwdWs W = carve_fwd_ws(ws, n);
     hipStream_t st = (hipStream_t)stream;
-    int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st);
+    int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st, 1);
     if (rc) return rc;
     rc = order_work_list(W, n, st);
     if (rc) return rc;
@@ -453,7 +519,8 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
     int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>, BLOCK);
     timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
     hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, itab,
-                       inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min);
+                       inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min,
+                       sc.cross_batch);
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;
@@ -564,9 +631,9 @@ int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, 
 
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
-                      int32_t* ifin, hipStream_t st) {
+                      int32_t* ifin, hipStream_t st, int cut_gj) {
     hipLaunchKernelGGL(trace_init_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, T, rays,
-                       status, n, W.keys, W.h0, W.k1, fin, ifin);
+                       status, n, W.keys, W.h0, W.k1, fin, ifin, cut_gj);
     return check_launch("trace_init_kernel");
 }
 

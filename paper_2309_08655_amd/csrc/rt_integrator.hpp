@@ -153,6 +153,94 @@ RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stag
     return th;
 }
 
+// Location theta of the crossing of the GJ density's null surface g = 0 on the continuous
+// extension of an accepted step: phi(theta) = sg g(x(theta), t(theta)) with phi0 = phi(0) >= 0
+// > phi1 = phi(1) (sg: the piece being integrated).  Newton's method from the linear
+// interpolation of phi, with dphi/dtheta from the extension's derivative, safeguarded by
+// the bracket [lo, hi] (a step leaving it bisects), converges to the root to about an ulp
+// in a few iterations; the result is then moved forward by 1, 2, 4, ... ulp to the first
+// point strictly past the surface (phi < 0), where the ray restarts on the other piece,
+// so that the next step starts strictly inside it.  *phi_past = phi there.
+RT_HD double locate_null_crossing(const InstT<double>& I, const double y[8], const double ynew[8], const Stages& S,
+                                  double h, double sg, double phi0, double phi1, const AxisRef* ref,
+                                  double* phi_past) {
+    using namespace dp5;
+    double a[4], b[4], c[4], d[4];
+    for (int i = 0; i < 4; ++i) {
+        a[i] = ynew[i] - y[i];
+        b[i] = h * S.K[0][i] - a[i];
+        c[i] = a[i] - h * S.K[6][i] - b[i];
+        d[i] = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
+                    d7 * S.K[6][i]);
+    }
+    // phi and dphi/dtheta on the extension
+    auto eval = [&](double th, double* dphi) {
+        const double om = 1.0 - th;
+        double x[4], dx[4];
+        for (int i = 0; i < 4; ++i) {
+            const double q = b[i] + th * (c[i] + om * d[i]);
+            const double p = a[i] + om * q;
+            x[i] = y[i] + th * p;
+            dx[i] = p + th * (-q + om * (c[i] + (1.0 - 2.0 * th) * d[i]));
+        }
+        const double ir = frsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        const double n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
+        double m[3], mt[3];
+        magnetic_axis(I, x[3], m, mt, ref);
+        const double mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+        const double ndx = n[0] * dx[0] + n[1] * dx[1] + n[2] * dx[2];
+        double dn[3], mdn = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            dn[i] = (dx[i] - n[i] * ndx) * ir;
+            mdn += m[i] * dn[i];
+        }
+        const double dmu = (mt[0] * n[0] + mt[1] * n[1] + mt[2] * n[2]) * dx[3] + mdn;
+        *dphi = sg * 3.0 * (dn[2] * mu + n[2] * dmu);
+        return sg * (3.0 * n[2] * mu - I.cm);
+    };
+    double lo = 0.0, hi = 1.0, fhi = phi1;
+    double th = (phi0 > 0.0 && phi1 < 0.0) ? phi0 / (phi0 - phi1) : 0.5;
+    if (!(th > 0.0 && th < 1.0)) th = 0.5;
+    double ph = 0.0;
+    for (int it = 0; it < 24; ++it) {
+        double dph;
+        ph = eval(th, &dph);
+        if (ph > 0.0) lo = th; else { hi = th; fhi = ph; }
+        if (ph == 0.0) break;  // th is the root
+        const double step = ph / dph;
+        double tn = th - step;
+        if (tn > lo && tn < hi) {
+            if (fabs(step) <= 4.0e-16 * th) {  // converged to about an ulp
+                th = tn;
+                double dd;
+                ph = eval(th, &dd);
+                if (ph > 0.0) lo = th; else { hi = th; fhi = ph; }
+                break;
+            }
+        } else {
+            if (hi - lo <= 4.0e-16 * hi) break;  // the bracket is down to an ulp
+            tn = 0.5 * (lo + hi);
+        }
+        th = tn;
+    }
+    // the first point strictly past the surface (hi is always past or on it)
+    double dz = th * 0x1p-52;
+    for (int k = 0; k < 64 && !(ph < 0.0); ++k) {
+        double tn = th + dz;
+        if (!(tn < hi)) {
+            th = hi;
+            ph = fhi;
+            break;
+        }
+        double dd;
+        th = tn;
+        ph = eval(th, &dd);
+        dz *= 2.0;
+    }
+    *phi_past = ph;
+    return th;
+}
+
 // Step-size update after an attempt (HNW I-controller, order 5), from err2 = err^2:
 // accepted: h *= min(facmax, max(0.2, 0.9 err^-1/5)) (err = 0 -> facmax);
 // rejected: h *= max(0.2, 0.9 err^-1/5) and facmax = 1 for the next accepted step.

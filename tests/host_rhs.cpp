@@ -40,18 +40,34 @@ double host_attempt(const double* c, const int* e, const double* y, double h, do
 
 extern "C" {
 // host run of the tracing loop of the persistent kernel for one ray (same decisions)
-// locate = 0: the kernels' Newton locator of the r = rmax crossing; 1: 60 bisections
+// locate = 0: the kernels' Newton locators of the r = rmax and null-surface crossings;
+// 1: 60 bisections for both (the oracle's definition)
 int host_trace(const double* c, const int* e, const double* y0, double rtol, double atol, double rmax,
                long long max_steps, double* yf, int* nacc_out, int* nrej_out, int locate) {
     InstT<double> I = inst_from(c, e);
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0); };
+    double gjs = 0.0, phi = 0.0;
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, nullptr, gjs); };
     Stages S;
     double y[8], ynew[8];
     for (int d = 0; d < 8; ++d) y[d] = y0[d];
+    if (I.density == DEN_GJ) {
+        const double g0 = gj_factor(I, y);
+        gjs = (g0 < 0.0) ? -1.0 : 1.0;
+        phi = gjs * g0;
+    }
     f(y, S.K[0]);
     double h = initial_step(f, y, S.K[0], rtol, atol);
     double lam = 0.0, facmax = 10.0;
     int nacc = 0, nrej = 0, status = 0;
+    auto bisect = [&](auto&& inside) {  // first theta of the extension with !inside(theta)
+        double lo = 0.0, hi = 1.0, yt[8];
+        for (int it = 0; it < 60; ++it) {
+            double mid = 0.5 * (lo + hi);
+            dense_at(y, ynew, S, h, mid, yt, 0, 8);
+            if (inside(yt)) lo = mid; else hi = mid;
+        }
+        return hi;
+    };
     while (status == 0) {
         double err2 = dopri_attempt(f, y, S, h, ynew, rtol, atol);
         if (!(err2 <= 1.0)) {
@@ -59,34 +75,54 @@ int host_trace(const double* c, const int* e, const double* y0, double rtol, dou
             h *= step_factor(err2, facmax, false);
             facmax = 1.0;
             if (!(fabs(h) >= 1e-14 * (1.0 + fabs(lam)))) status = 5;
-        } else {
-            ++nacc;
-            double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
-            if (rnew <= I.R) { status = 2; for (int d = 0; d < 8; ++d) yf[d] = ynew[d]; }
-            else if (rnew >= rmax) {
-                double th;
-                if (locate == 0) {
-                    th = locate_crossing(y, ynew, S, h, rmax);
-                } else {
-                    double lo = 0.0, hi = 1.0, yt[8];
-                    for (int it = 0; it < 60; ++it) {
-                        double mid = 0.5 * (lo + hi);
-                        dense_at(y, ynew, S, h, mid, yt, 0, 3);
-                        double rm = sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]);
-                        if (rm >= rmax) hi = mid; else lo = mid;
-                    }
-                    th = hi;
-                }
-                dense_at(y, ynew, S, h, th, yf, 0, 8);
-                status = 1;
+            continue;
+        }
+        ++nacc;
+        double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+        if (rnew <= I.R) { status = 2; for (int d = 0; d < 8; ++d) yf[d] = ynew[d]; break; }
+        double g1 = 0.0, thk = 2.0;
+        bool cross = false;
+        if (I.density == DEN_GJ) {
+            g1 = gj_factor(I, ynew);
+            cross = gjs * g1 < 0.0;
+        }
+        double phik = 0.0;
+        if (cross) {
+            if (locate == 0) {
+                thk = locate_null_crossing(I, y, ynew, S, h, gjs, phi, gjs * g1, nullptr, &phik);
             } else {
-                lam += h;
-                for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
-                h *= step_factor(err2, facmax, true);
-                facmax = 10.0;
-                if (nacc >= max_steps) status = 4;
+                thk = bisect([&](const double* yt) { return gjs * gj_factor(I, yt) > 0.0; });
+                double yt[8];
+                dense_at(y, ynew, S, h, thk, yt, 0, 8);
+                phik = gjs * gj_factor(I, yt);
             }
         }
+        if (rnew >= rmax) {
+            double th = (locate == 0) ? locate_crossing(y, ynew, S, h, rmax) : bisect([&](const double* yt) {
+                return sqrt(yt[0] * yt[0] + yt[1] * yt[1] + yt[2] * yt[2]) < rmax;
+            });
+            if (th <= thk) {
+                dense_at(y, ynew, S, h, th, yf, 0, 8);
+                status = 1;
+                break;
+            }
+        }
+        if (cross) {
+            double yt[8];
+            dense_at(y, ynew, S, h, thk, yt, 0, 8);
+            for (int d = 0; d < 8; ++d) y[d] = yt[d];
+            lam += thk * h;
+            gjs = -gjs;
+            phi = -phik;
+            f(y, S.K[0]);
+        } else {
+            lam += h;
+            for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+            phi = gjs * g1;
+        }
+        h *= step_factor(err2, facmax, true);
+        facmax = 10.0;
+        if (nacc >= max_steps) status = 4;
     }
     *nacc_out = nacc; *nrej_out = nrej;
     return status;

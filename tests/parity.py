@@ -37,16 +37,17 @@ def angle_between(th1, ph1, th2, ph2):
     return 2.0 * np.arcsin(np.clip(np.linalg.norm(a - b, axis=0) / 2.0, 0.0, 1.0))
 
 
-def oracle_conditioning(orc, star, tol, rays, status, fin_o, ifin_o):
+def oracle_conditioning(orc, star, tol, rays, status, fin_o, ifin_o, kinks=True):
     """Per-ray self-difference of the oracle under 2^-50 relative perturbations (both
-    signs) of the seed position and momentum.  Returns (selfdiff[n], seq_changed[n])."""
+    signs) of the seed position and momentum.  Returns (selfdiff[n], seq_changed[n]).
+    kinks selects the oracle's forward integration (see oracle.trace_forward)."""
     eps = 2.0 ** -50
     sd = np.zeros(rays.shape[1])
     changed = np.zeros(rays.shape[1], dtype=bool)
     for sl, f in ((slice(0, 3), 1 + eps), (slice(4, 7), 1 - eps), (slice(0, 3), 1 - eps), (slice(4, 7), 1 + eps)):
         r2 = np.array(rays, copy=True)
         r2[sl] *= f
-        fin2, ifin2 = orc.trace_forward(star, tol, r2, status)
+        fin2, ifin2 = orc.trace_forward(star, tol, r2, status, kinks=kinks)
         d = angle_between(fin2[8], fin2[9], fin_o[8], fin_o[9])
         sd = np.maximum(sd, np.where((ifin2[2] == 1) & (ifin_o[2] == 1), d, 0.0))
         changed |= (ifin2[0] != ifin_o[0]) | (ifin2[1] != ifin_o[1]) | (ifin2[2] != ifin_o[2])

@@ -115,32 +115,47 @@ def test_host_tracing_loop_matches_oracle(orc, host, cfg):
 
 @pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])
 def test_newton_crossing_locator_matches_bisection(orc, host, cfg):
-    """The kernels locate r = r_max on the last step's continuous extension by a
-    safeguarded Newton iteration; the definition is 60 bisections.  Same step sequence,
-    so the final states must agree to roundoff (1e-13 relative, r = r_max to 1e-15)."""
+    """The kernels locate r = r_max and the crossings of the GJ density's null surface on
+    a step's continuous extension by safeguarded Newton iterations; the definition is 60
+    bisections.  Same step sequence and statuses; r = r_max to 1e-15; the final states
+    differ only by the roundoff of the located points carried through the rest of the
+    ray: within 8 times the spread the bisection run itself shows under 2^-50 relative
+    perturbations of the seed position (+ 1e-15)."""
     s, t = cfg["star"], cfg["tol"]
     cc, e = consts(orc, s)
     rays, st = orc.sample(s, 0, 300)
+
+    def run(y0, mode):
+        yf = np.zeros(8)
+        na, nr = C.c_int(), C.c_int()
+        stt = host.host_trace(_p(cc), _p(e, C.c_int), _p(np.ascontiguousarray(y0)), t["rtol"], t["atol"],
+                              t["r_max_km"], t["max_steps"], _p(yf), C.byref(na), C.byref(nr), mode)
+        return stt, na.value, nr.value, yf
+
+    def rel(a, b):
+        return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300 + np.abs(b).max() * 1e-3)))
+
     worst, nesc = 0.0, 0
     for i in range(rays.shape[1]):
         if st[i] != 0:
             continue
-        y0 = np.ascontiguousarray(rays[:8, i])
-        out = []
-        for mode in (0, 1):
-            yf = np.zeros(8)
-            na, nr = C.c_int(), C.c_int()
-            stt = host.host_trace(_p(cc), _p(e, C.c_int), _p(y0), t["rtol"], t["atol"], t["r_max_km"],
-                                  t["max_steps"], _p(yf), C.byref(na), C.byref(nr), mode)
-            out.append((stt, na.value, nr.value, yf))
-        assert out[0][:3] == out[1][:3]
-        if out[0][0] == W.STATUS_ESCAPED:
-            nesc += 1
-            a, b = out[0][3], out[1][3]
-            assert abs(np.linalg.norm(a[:3]) / t["r_max_km"] - 1.0) < 1e-15
-            worst = max(worst, float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300 + np.abs(b).max() * 1e-3))))
+        y0 = rays[:8, i].copy()
+        newton, bis = run(y0, 0), run(y0, 1)
+        assert newton[:3] == bis[:3]
+        if newton[0] != W.STATUS_ESCAPED:
+            continue
+        nesc += 1
+        assert abs(np.linalg.norm(newton[3][:3]) / t["r_max_km"] - 1.0) < 1e-15
+        spread = 0.0
+        for f in (1 + 2.0 ** -50, 1 - 2.0 ** -50):
+            yp = y0.copy()
+            yp[:3] *= f
+            p = run(yp, 1)
+            if p[0] == W.STATUS_ESCAPED:
+                spread = max(spread, rel(p[3], bis[3]))
+        worst = max(worst, rel(newton[3], bis[3]) / (spread + 1e-15))
     assert nesc > 200
-    assert worst < 1e-13, worst
+    assert worst <= 8.0, worst
 
 
 def test_controller_fifth_root_matches_pow(host):

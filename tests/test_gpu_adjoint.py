@@ -51,8 +51,9 @@ def gpu_flux_grad(rt, star, tol, seed, n, obs, sigma, gbar, ckpt_every=64, max_c
 
 def well_conditioned(orc, star, tol, n, sto):
     rays, status = orc.sample(star, 0, n)
-    fin, ifin = orc.trace_forward(star, tol, rays, status)
-    sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin)
+    # the adjoint integrates the density as it stands (no cut at the null surface)
+    fin, ifin = orc.trace_forward(star, tol, rays, status, kinks=False)
+    sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin, kinks=False)
     return (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED), ifin
 
 
