@@ -69,8 +69,19 @@ inline int partition_blocks(int64_t n) {
     return (int)g;
 }
 
+// Per-lane slots of the forward tracing kernel for a lane whose step crossed the GJ null
+// surface and waits for its restart: the step's start y (8), the coefficients a, b, c, d of
+// its continuous extension (4 x 8), a spare field, phi(0), phi(1), the step's error and
+// |x(1)|^2 (the step size stays in the lane's registers).
+// Lane-major ([lane][STASH_STRIDE]): one base address and immediate field offsets.
+constexpr int STASH_FIELDS = 45;
+constexpr int STASH_STRIDE = 48;
+constexpr int STASH_LANES_PER_CU = 512;  // the tracing kernels run at most 8 waves per CU
+
 struct FwdWs {
     WorkCtr* ctr;
+    double* stash;  // [stash_lanes][STASH_STRIDE]
+    int64_t stash_lanes;
     int32_t* list;
     double* h0;
     double* k1;
@@ -86,11 +97,18 @@ inline size_t part_tab_bytes(int64_t n) {
 }
 inline size_t part_start_bytes() { return align256(sizeof(int32_t) * (PART_BUCKETS + 1)); }
 
+int device_cu_count();
+inline int64_t stash_lanes() { return (int64_t)device_cu_count() * STASH_LANES_PER_CU; }
+inline size_t stash_bytes() { return align256(sizeof(double) * STASH_STRIDE * (size_t)stash_lanes()); }
+
 inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     char* p = (char*)ws;
     FwdWs W;
     W.ctr = (WorkCtr*)p;
     p += align256(sizeof(WorkCtr));
+    W.stash = (double*)p;
+    W.stash_lanes = stash_lanes();
+    p += stash_bytes();
     W.list = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)n);
     W.h0 = (double*)p;
@@ -106,7 +124,8 @@ inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
 }
 
 inline size_t fwd_ws_bytes(int64_t n) {
-    return align256(sizeof(WorkCtr)) + align256(sizeof(int32_t) * (size_t)n) + align256(sizeof(double) * (size_t)n) +
+    return align256(sizeof(WorkCtr)) + stash_bytes() + align256(sizeof(int32_t) * (size_t)n) +
+           align256(sizeof(double) * (size_t)n) +
            align256(sizeof(double) * 8 * (size_t)n) + align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() +
            part_tab_bytes(n);
 }

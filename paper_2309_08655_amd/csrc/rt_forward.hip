@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
                                                           int32_t* __restrict__ ifin, int refill_min,
-                                                          int cross_batch) {
+                                                          int cross_batch, double* __restrict__ stash) {
     // a specialised instantiation (SPEC = 1 + plasma + 2 density + 8 oblique) fixes these
     // switches at compile time: the Hamiltonian and its gradient become branch-free code with
     // the same arithmetic (the file is built with -ffp-contract=on, so the generic and the
@@ -154,8 +154,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     // restarts on the other piece where a step crosses the null surface g = 0; phi = gjs g
     // at y.  Other densities: gjs = 0.
     double gjs = 0.0, phi = 0.0;
-    bool pending = false;          // a crossing waits for its restart
-    double phi1 = 0.0, errp = 0.0;  // its step's end value of gjs g and its error
+    bool pending = false;  // a crossing waits for its restart, its step in the lane's stash slot
+    double* slot = stash + ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * STASH_STRIDE;
+    auto st_put = [&](int fld, double v) { slot[fld] = v; };
+    auto st_get = [&](int fld) { return slot[fld]; };
     auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref, gjs); };
     const double rmax2 = tol.rmax * tol.rmax;
     double R2 = I.R * I.R;
@@ -212,15 +214,24 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
         const int nwait = __popcll(waiting);
         if (nwait > 0 && (nwait >= cross_batch || 2 * nwait >= __popcll(__ballot(active)))) {
             if (pending) {
+                // components 0..3 (position and time) locate the crossings
+                double y0[4], ca[4], cb[4], cc[4], cd[4];
+                for (int d = 0; d < 4; ++d) {
+                    y0[d] = st_get(d);
+                    ca[d] = st_get(8 + d);
+                    cb[d] = st_get(16 + d);
+                    cc[d] = st_get(24 + d);
+                    cd[d] = st_get(32 + d);
+                }
+                const double phi0 = st_get(41), phi1 = st_get(42), errp = st_get(43), r2new = st_get(44);
                 double phik;
-                const double thk = locate_null_crossing(I, y, ynew, S, h, gjs, phi, phi1, &ref, &phik);
+                const double thk = locate_null_crossing_c(I, y0, ca, cb, cc, cd, gjs, phi0, phi1, &ref, &phik);
                 // the step may also have reached r_max: whichever comes first
-                const double r2new = ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2];
-                const double th = (r2new >= rmax2) ? locate_crossing(y, ynew, S, h, tol.rmax) : 2.0;
+                const double th = (r2new >= rmax2) ? locate_crossing_c(y0, ca, cb, cc, cd, sqrt(r2new), tol.rmax)
+                                                   : 2.0;
                 const double tc = (th <= thk) ? th : thk;
-                double yt[8];
-                dense_at(y, ynew, S, h, tc, yt, 0, 8);
-                for (int d = 0; d < 8; ++d) y[d] = yt[d];
+                for (int d = 0; d < 8; ++d)
+                    y[d] = dense_value(st_get(d), st_get(8 + d), st_get(16 + d), st_get(24 + d), st_get(32 + d), tc);
                 if (th <= thk) {
                     status = ST_ESCAPED;
                     lam_out = lam + th * h;
@@ -260,9 +271,22 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                     cross = (gjs * g1 < 0.0);
                 }
                 if (cross) {
-                    pending = true;  // restarted (or ended at r_max) with the next batch
-                    phi1 = gjs * g1;
-                    errp = err2;
+                    // restarted (or ended at r_max) with the next batch: the step goes to the
+                    // stash, so that no register stays held while the lane waits
+                    pending = true;
+                    for (int d = 0; d < 8; ++d) {
+                        double ca, cb, cc, cd;
+                        dense_coeffs(y, ynew, S, h, d, d + 1, &ca, &cb, &cc, &cd);
+                        st_put(d, y[d]);
+                        st_put(8 + d, ca);
+                        st_put(16 + d, cb);
+                        st_put(24 + d, cc);
+                        st_put(32 + d, cd);
+                    }
+                    st_put(41, phi);
+                    st_put(42, gjs * g1);
+                    st_put(43, err2);
+                    st_put(44, r2new);
                 } else if (finite_ok && r2new >= rmax2) {
                     // locate r(theta) = r_max on the continuous extension
                     const double th = locate_crossing(y, ynew, S, h, tol.rmax);
@@ -517,10 +541,11 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
                             const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                             const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
     int grid = persistent_grid(sc, (const void*)trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>, BLOCK);
+    if ((int64_t)grid * BLOCK > W.stash_lanes) return fail(RT_EINVAL, "trace_fwd_kernel: more lanes than stash slots");
     timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
     hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, itab,
                        inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min,
-                       sc.cross_batch);
+                       sc.cross_batch, W.stash);
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;

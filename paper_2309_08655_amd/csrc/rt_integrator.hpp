@@ -86,6 +86,25 @@ RT_HD T dopri_attempt(RHS&& f, const T y[8], StagesT<T>& S, T h, T ynew[8], doub
     return finite_value(err2) ? err2 : T(1e300);
 }
 
+// Coefficients of the continuous extension of components [c0, c1) of an accepted step:
+// y(theta) = y + theta (a + om (b + theta (c + om d))), om = 1 - theta.
+RT_HD void dense_coeffs(const double y[8], const double ynew[8], const Stages& S, double h, int c0, int c1,
+                        double* a, double* b, double* c, double* d) {
+    using namespace dp5;
+    for (int i = c0; i < c1; ++i) {
+        const double ydiff = ynew[i] - y[i];
+        const double r3 = h * S.K[0][i] - ydiff;
+        const double r4 = ydiff - h * S.K[6][i] - r3;
+        const double r5 = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
+                               d7 * S.K[6][i]);
+        a[i - c0] = ydiff; b[i - c0] = r3; c[i - c0] = r4; d[i - c0] = r5;
+    }
+}
+RT_HD double dense_value(double y, double a, double b, double c, double d, double th) {
+    const double om = 1.0 - th;
+    return y + th * (a + om * (b + th * (c + om * d)));
+}
+
 // Continuous extension at theta of components [c0, c1) (accepted step y -> ynew).
 template <class T>
 RT_HD void dense_at(const T y[8], const T ynew[8], const StagesT<T>& S, T h, T th, T out[8], int c0, int c1) {
@@ -107,18 +126,10 @@ RT_HD void dense_at(const T y[8], const T ynew[8], const StagesT<T>& S, T h, T t
 // safeguarded by the bracket [lo, hi] (a step leaving it bisects instead).  Converges
 // to the root to about an ulp in a few iterations, where plain bisection to the same
 // precision takes 60 evaluations.
-RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stages& S, double h, double rmax) {
-    using namespace dp5;
-    double a[3], b[3], c[3], d[3];
-    for (int i = 0; i < 3; ++i) {
-        a[i] = ynew[i] - y[i];
-        b[i] = h * S.K[0][i] - a[i];
-        c[i] = a[i] - h * S.K[6][i] - b[i];
-        d[i] = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
-                    d7 * S.K[6][i]);
-    }
+// (from the coefficients a..d of components 0..2, see dense_coeffs, and r1 = |x(1)|)
+RT_HD double locate_crossing_c(const double y[3], const double a[3], const double b[3], const double c[3],
+                               const double d[3], double r1, double rmax) {
     const double r0 = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-    const double r1 = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
     const double R2 = rmax * rmax;
     double lo = 0.0, hi = 1.0;
     double th = (r1 > r0) ? (rmax - r0) / (r1 - r0) : 1.0;
@@ -153,6 +164,13 @@ RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stag
     return th;
 }
 
+RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stages& S, double h, double rmax) {
+    double a[3], b[3], c[3], d[3];
+    dense_coeffs(y, ynew, S, h, 0, 3, a, b, c, d);
+    const double r1 = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
+    return locate_crossing_c(y, a, b, c, d, r1, rmax);
+}
+
 // Location theta of the crossing of the GJ density's null surface g = 0 on the continuous
 // extension of an accepted step: phi(theta) = sg g(x(theta), t(theta)) with phi0 = phi(0) >= 0
 // > phi1 = phi(1) (sg: the piece being integrated).  Newton's method from the linear
@@ -161,18 +179,9 @@ RT_HD double locate_crossing(const double y[8], const double ynew[8], const Stag
 // in a few iterations; the result is then moved forward by 1, 2, 4, ... ulp to the first
 // point strictly past the surface (phi < 0), where the ray restarts on the other piece,
 // so that the next step starts strictly inside it.  *phi_past = phi there.
-RT_HD double locate_null_crossing(const InstT<double>& I, const double y[8], const double ynew[8], const Stages& S,
-                                  double h, double sg, double phi0, double phi1, const AxisRef* ref,
-                                  double* phi_past) {
-    using namespace dp5;
-    double a[4], b[4], c[4], d[4];
-    for (int i = 0; i < 4; ++i) {
-        a[i] = ynew[i] - y[i];
-        b[i] = h * S.K[0][i] - a[i];
-        c[i] = a[i] - h * S.K[6][i] - b[i];
-        d[i] = h * (d1 * S.K[0][i] + d3 * S.K[2][i] + d4 * S.K[3][i] + d5 * S.K[4][i] + d6 * S.K[5][i] +
-                    d7 * S.K[6][i]);
-    }
+RT_HD double locate_null_crossing_c(const InstT<double>& I, const double y[4], const double a[4], const double b[4],
+                                    const double c[4], const double d[4], double sg, double phi0, double phi1,
+                                    const AxisRef* ref, double* phi_past) {
     // phi and dphi/dtheta on the extension
     auto eval = [&](double th, double* dphi) {
         const double om = 1.0 - th;
@@ -239,6 +248,15 @@ RT_HD double locate_null_crossing(const InstT<double>& I, const double y[8], con
     }
     *phi_past = ph;
     return th;
+}
+
+// the same from an accepted step's stages
+RT_HD double locate_null_crossing(const InstT<double>& I, const double y[8], const double ynew[8], const Stages& S,
+                                  double h, double sg, double phi0, double phi1, const AxisRef* ref,
+                                  double* phi_past) {
+    double a[4], b[4], c[4], d[4];
+    dense_coeffs(y, ynew, S, h, 0, 4, a, b, c, d);
+    return locate_null_crossing_c(I, y, a, b, c, d, sg, phi0, phi1, ref, phi_past);
 }
 
 // Step-size update after an attempt (HNW I-controller, order 5), from err2 = err^2:
