@@ -550,6 +550,7 @@ def main():
     stn = status.cpu().numpy()
     # wave-iterations of the persistent loop (third 64-bit word of the work counter)
     wave_iters = int(ws[16:24].cpu().numpy().view(np.uint64)[0])
+    restarts = int(ws[32:40].cpu().numpy().view(np.uint64)[0])  # work counter pad[1]
     att = (ifn[0].astype(np.int64) + ifn[1])[stn == 0]
     acc = float(ifn[0].astype(np.float64).sum())
     rej = float(ifn[1].astype(np.float64).sum())
@@ -580,6 +581,7 @@ def main():
                            rays_per_s=rays_per_s, accepted_steps=acc, rejected_steps=rej,
                            statuses={str(k): int(v) for k, v in zip(*np.unique(ifn[2], return_counts=True))},
                            lane_efficiency=(acc + rej) / max(1, 64 * wave_iters),
+                           null_surface_restarts=restarts,
                            attempts_per_ray=dict(mean=float(att.mean()), p99=float(np.percentile(att, 99)),
                                                  p9999=float(np.percentile(att, 99.99)), max=int(att.max())),
                            schedule=sched, autotune_ms=tune_times),

@@ -202,7 +202,12 @@ static __global__ void __launch_bounds__(1024) part_scan_kernel(int32_t* start, 
     for (int q = 0; q < 4; ++q) { start[4 * t + q] = base; base += v[q]; }
     if (t == 1023) {
         start[PART_BUCKETS] = part[1023];
-        if (ctr) { ctr->head = 0ull; ctr->len = (unsigned long long)part[1023]; ctr->iters = 0ull; }
+        if (ctr) {
+            ctr->head = 0ull;
+            ctr->len = (unsigned long long)part[1023];
+            ctr->iters = 0ull;
+            ctr->pad[1] = 0ull;
+        }
     }
 }
 

@@ -46,7 +46,7 @@ struct WorkCtr {
     unsigned long long head;   // next list entry to hand out
     unsigned long long len;    // list length
     unsigned long long iters;  // wave-iterations of the persistent loop (lane efficiency diagnostic)
-    unsigned long long pad[29];
+    unsigned long long pad[29];  // pad[0]: the adjoint's seal; pad[1]: null-surface restarts of a forward launch
 };
 
 // Work-list ordering: rays are handed out in ascending order of a cost key (a

@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     // at y.  Other densities: gjs = 0.
     double gjs = 0.0, phi = 0.0;
     bool pending = false;  // a crossing waits for its restart, its step in the lane's stash slot
+    unsigned int ncross = 0;  // restarts of this lane (diagnostic)
     double* slot = stash + ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * STASH_STRIDE;
     auto st_put = [&](int fld, double v) { slot[fld] = v; };
     auto st_get = [&](int fld) { return slot[fld]; };
@@ -242,6 +243,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                     phi = -phik;  // the new piece's value there, >= 0
                     if (I.oblique) axis_ref_advance(I, ref, y[3]);
                     f(y, S.K[0]);
+                    ++ncross;
                     h *= step_factor(errp, facmax, true);
                     facmax = 10.0;
                     if (nacc >= tol.max_steps) status = ST_MAX_STEPS;
@@ -326,6 +328,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
         }
     }
     if (lane == 0) atomicAdd(&ctr->iters, iters);
+    if (ncross) atomicAdd(&ctr->pad[1], (unsigned long long)ncross);
 }
 
 // Observables of every traced ray from its final state (Sec. 2.2: the asymptotic
