@@ -123,7 +123,9 @@ int orc_dopri_test(int32_t problem, double rtol, double atol, double t_end, doub
                    int64_t* n_acc, int64_t* n_rej, double h_fixed, double* dense_err);
 
 /* smoothed flux and its forward-mode derivative with respect to
-   (B0, P, theta_m, M, R, m_a); steps frozen at the nominal run.  If fray/dray are
+   (B0, P, theta_m, M, R, m_a); steps frozen at the nominal run.  Rays are traced as
+   orc_trace_forward does with kinks != 0 (the GJ density one smooth piece at a time),
+   restart points carrying the implicit derivative of g(y(theta)) = 0.  If fray/dray are
    not NULL they receive each ray's share (w K / n and its derivative; zero for rays
    that do not escape) and ray_status each ray's status. */
 int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_t n,

@@ -269,6 +269,24 @@ static double gj_factor(const Inst<P>& I, const double x[3], double t) {
     return 3.0 * n[2] * (m[0] * n[0] + m[1] * n[1] + m[2] * n[2]) - val(I.cm);
 }
 
+// g and its derivative along a curve with tangent (dx, dt), in any scalar type (the implicit
+// derivative of a null-surface crossing): dg = 3 (dn_z mu + n_z dmu), dn = (dx - n (n.dx))/r,
+// dmu = (dm/dt . n) dt + m.dn, dm/dt = Omega e_z x m.
+template <class S, class P>
+static S gj_factor_t(const Inst<P>& I, const S x[3], const S& t, const S dx[3], const S& dt, S* dg) {
+    S r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    S n[3] = {x[0] / r, x[1] / r, x[2] / r};
+    S m[3];
+    mhat_at(I, t, m);
+    S mu = dot3(m, n);
+    S ndx = dot3(n, dx);
+    S dn[3] = {(dx[0] - n[0] * ndx) / r, (dx[1] - n[1] * ndx) / r, (dx[2] - n[2] * ndx) / r};
+    S mdot[3] = {(S(0.0) - I.Om) * m[1], I.Om * m[0], S(0.0)};
+    S dmu = dot3(mdot, n) * dt + dot3(m, dn);
+    *dg = 3.0 * (dn[2] * mu + n[2] * dmu);
+    return 3.0 * n[2] * mu - I.cm;
+}
+
 // Radial profiles of the static vacuum dipole in Schwarzschild, x = r_s / r: the vector
 // potential is A_phi = (mu sin^2 theta / r) G(x) with
 //   G(x) = -3 [ln(1 - x) + x + x^2/2] / x^3 = 3 sum_{j>=0} x^j / (j + 3)   (G(0) = 1),
@@ -1007,9 +1025,20 @@ static TraceOut<S> trace_one(const Inst<P>& I, const orc_tol& tol, const S y0[8]
             break;
         }
         if (thk <= 1.0) {
-            // restart at the first point past the null surface, on the other piece
+            // restart at the first point past the null surface, on the other piece; for dual
+            // parameters the location carries the implicit derivative of g(y(theta)) = 0
             S yk[8];
-            dense_eval(y, st, h, thk, yk);
+            if constexpr (is_dual<S>::value) {
+                S yth[8], dy[8], dg;
+                dense_eval(y, st, h, thk, yth);
+                dense_deriv(y, st, h, thk, dy);
+                const S g = gj_factor_t(I, yth, yth[3], dy, dy[3], &dg);
+                S thd = (S(0.0) + thk) - g / dg;
+                thd.v = thk;
+                dense_eval(y, st, h, thd, yk);
+            } else {
+                dense_eval(y, st, h, thk, yk);
+            }
             for (int i = 0; i < 8; ++i) y[i] = yk[i];
             lam += thk * h;
             J.gj_branch = -J.gj_branch;
@@ -1605,7 +1634,7 @@ int orc_flux_fwdmode(const orc_star* s, const orc_tol* tol, uint64_t seed, int64
             SeedOut<D6> so = seed_ray(I, seed, 0, i);
             if (ray_status) ray_status[i] = so.status;
             if (so.status != ORC_OK) continue;
-            TraceOut<D6> o = trace_one<D6, D6>(I, *tol, so.y, 1.0, nullptr, nullptr, 0);
+            TraceOut<D6> o = trace_one<D6, D6>(I, *tol, so.y, 1.0, nullptr, nullptr, 0, true);
             if (ray_status) ray_status[i] = o.status;
             if (o.status != ORC_ESCAPED) continue;
             D6 th, ph, ps, v[3];
@@ -1646,7 +1675,7 @@ int orc_flux_replay(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_
             if (record) {
                 if (so.status != ORC_OK) { stat[i] = so.status; nseq[i] = 0; continue; }
                 std::vector<double> hr;
-                o = trace_one<double, double>(I, *tol, so.y, 1.0, &hr, nullptr, 0);
+                o = trace_one<double, double>(I, *tol, so.y, 1.0, &hr, nullptr, 0, true);
                 int32_t m = (int32_t)std::min<size_t>(hr.size(), (size_t)max_rec);
                 for (int32_t q = 0; q < m; ++q) hseq[(size_t)i * max_rec + q] = hr[q];
                 nseq[i] = m;
@@ -1654,7 +1683,7 @@ int orc_flux_replay(const orc_star* s, const orc_tol* tol, uint64_t seed, int64_
                 if (stat[i] != ORC_ESCAPED) continue;
             } else {
                 if (stat[i] != ORC_ESCAPED || so.status != ORC_OK) continue;
-                o = trace_one<double, double>(I, *tol, so.y, 1.0, nullptr, hseq + (size_t)i * max_rec, nseq[i]);
+                o = trace_one<double, double>(I, *tol, so.y, 1.0, nullptr, hseq + (size_t)i * max_rec, nseq[i], true);
                 if (o.status != ORC_ESCAPED) {
                     // the replayed final step no longer reaches r_max: locate on its extension anyway
                     continue;

@@ -46,12 +46,12 @@ struct AdjWs {
     int32_t* ifin;    // [RT_NIFIN][n]: n_acc, n_rej, status
     int32_t* nseg;    // [n] checkpoints stored
     double* theta;    // [n] location of r = r_max on the last step
-    double* ckpt;     // [max_ckpt][10][n]: y[8], h, facmax
+    double* ckpt;     // [max_ckpt][11][n]: y[8], h, facmax, gjs
     WorkCtr* rctr;    // reverse pass: head of the work list, seal, iters = steps the recompute missed
     double* obs;      // [n_obs][3]
     double* facc;     // [MAX_OBS] flux accumulators
     double* gacc;     // [8] gradient accumulators
-    double* replay;   // [C * 9][REV_LANES]
+    double* replay;   // [C * 11][REV_LANES]
 };
 
 static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int32_t Kc, AdjWs* W) {
@@ -68,12 +68,12 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
     char* ifin = take(sizeof(int32_t) * RT_NIFIN_ * (size_t)n);
     char* nseg = take(sizeof(int32_t) * (size_t)n);
     char* theta = take(sizeof(double) * (size_t)n);
-    char* ckpt = take(sizeof(double) * 10 * (size_t)Kc * (size_t)n);
+    char* ckpt = take(sizeof(double) * 11 * (size_t)Kc * (size_t)n);
     char* rctr = take(sizeof(WorkCtr));
     char* obs = take(sizeof(double) * 3 * (size_t)n_obs);
     char* facc = take(sizeof(double) * MAX_OBS);
     char* gacc = take(sizeof(double) * 8);
-    char* replay = take(sizeof(double) * 9 * (size_t)C * REV_LANES);
+    char* replay = take(sizeof(double) * 11 * (size_t)C * REV_LANES);
     if (W) {
         W->fw = carve_fwd_ws(fwbase, n);
         W->rays = (double*)rays;
@@ -110,10 +110,11 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
     bool active = false, exhausted = false;
     int64_t j = 0;
     AdjRay R;
-    auto store = [&](int s, const double* y, double h, double facmax) {
-        for (int d = 0; d < 8; ++d) ckpt[((int64_t)s * 10 + d) * n + j] = y[d];
-        ckpt[((int64_t)s * 10 + 8) * n + j] = h;
-        ckpt[((int64_t)s * 10 + 9) * n + j] = facmax;
+    auto store = [&](int s, const double* y, double h, double facmax, double gjs) {
+        for (int d = 0; d < 8; ++d) ckpt[((int64_t)s * 11 + d) * n + j] = y[d];
+        ckpt[((int64_t)s * 11 + 8) * n + j] = h;
+        ckpt[((int64_t)s * 11 + 9) * n + j] = facmax;
+        ckpt[((int64_t)s * 11 + 10) * n + j] = gjs;
     };
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long missing = 0;
     const unsigned long long rlen = lctr->len < (unsigned long long)n ? lctr->len : (unsigned long long)n;
-    auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 9 + d) * REV_LANES + lane_g]; };
+    auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 11 + d) * REV_LANES + lane_g]; };
     const int lane = __lane_id();
     while (true) {
         // the wave takes 64 consecutive rays of the step-ordered list
@@ -248,10 +249,11 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
         if (j < 0 || j >= n) continue;
         const int S = ifin[j], nseg = nseg_in[j];
         if (nseg < 1 || nseg > Kc || S < 1 || S > nseg * C) continue;
-        auto load = [&](int s, double* y, double* h, double* facmax) {
-            for (int d = 0; d < 8; ++d) y[d] = ckpt[((int64_t)s * 10 + d) * n + j];
-            *h = ckpt[((int64_t)s * 10 + 8) * n + j];
-            *facmax = ckpt[((int64_t)s * 10 + 9) * n + j];
+        auto load = [&](int s, double* y, double* h, double* facmax, double* gjs) {
+            for (int d = 0; d < 8; ++d) y[d] = ckpt[((int64_t)s * 11 + d) * n + j];
+            *h = ckpt[((int64_t)s * 11 + 8) * n + j];
+            *facmax = ckpt[((int64_t)s * 11 + 9) * n + j];
+            *gjs = ckpt[((int64_t)s * 11 + 10) * n + j];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
         const int miss = adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, obs,
@@ -319,7 +321,7 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         rc = rt_sample_resonance(star, seed, 0, 0, n, W.rays, W.status, stream);
         if (rc) return rc;
-        rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st, 0);
+        rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st, 1);
         if (rc) return rc;
         rc = order_work_list(W.fw, n, st);
         if (rc) return rc;

@@ -41,12 +41,14 @@ typedef gdual<14> D14;
 // as its first, as in the forward pass), and the inner stages take the attempt's
 // reference at its starting time and rotate by the small stage angle.  Both avoid a full
 // sincos per evaluation.
-RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, const AxisRef& ref) {
-    rhs(I, y, f, 1.0, &ref);
+// gjs: the piece of the GJ density being integrated (0 for the other densities; see
+// plasma_eval); the adjoint follows forward tracing, which cuts steps at the null surface.
+RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, const AxisRef& ref, double gjs = 0.0) {
+    rhs(I, y, f, 1.0, &ref, gjs);
 }
-RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) {
+RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, double gjs = 0.0) {
     const AxisRef ref = axis_ref_at(I, y[3]);
-    rhs(I, y, f, 1.0, &ref);
+    rhs(I, y, f, 1.0, &ref, gjs);
 }
 
 // One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
@@ -54,7 +56,7 @@ RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f) {
 // (Ys[0..7] = y).  Applies the step-size controller to *h and *facmax and returns
 // 1 if the step is accepted.
 RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
-                      double* h, double* facmax, double* Ys) {
+                      double* h, double* facmax, double* Ys, double gjs = 0.0) {
     using namespace dp5;
     const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
                             {a31, a32, 0, 0, 0, 0},
@@ -83,9 +85,9 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
             for (int d = 0; d < 8; ++d) ynew[d] = tmp[d];
         }
         if (s < 5)
-            adj_rhs(I, tmp, K + (s + 1) * 8, ref0);
+            adj_rhs(I, tmp, K + (s + 1) * 8, ref0, gjs);
         else
-            adj_rhs(I, tmp, K + (s + 1) * 8);
+            adj_rhs(I, tmp, K + (s + 1) * 8, gjs);
     }
     const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
     double acc = 0.0;
@@ -109,6 +111,80 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
     *h = hh * step_factor(err2, *facmax, true);
     *facmax = 10.0;
     return 1;
+}
+
+// The crossing of the GJ null surface inside an accepted step from y (K: its stages, ynew:
+// its end), as forward tracing locates it: theta of the first point strictly past the
+// surface, or 2 when the step stays on its piece (other densities: always 2).  A function
+// of the step alone, so that the recompute reproduces it.
+RT_HD double adj_null_crossing(const InstT<double>& I, const double* y, const double* K, const double* ynew, double h,
+                               double gjs) {
+    if (gjs == 0.0) return 2.0;
+    const double g1 = gj_factor(I, ynew);
+    if (!(gjs * g1 < 0.0)) return 2.0;
+    Stages S;
+    for (int s = 0; s < 7; ++s)
+        for (int d = 0; d < 8; ++d) S.K[s][d] = K[s * 8 + d];
+    double phik;
+    return locate_null_crossing(I, y, ynew, S, h, gjs, gjs * gj_factor(I, y), gjs * g1, nullptr, &phik);
+}
+
+// the piece of the GJ density a ray starts on (0 for the other densities)
+RT_HD double adj_start_piece(const InstT<double>& I, const double* y) {
+    if (I.density != DEN_GJ) return 0.0;
+    return (gj_factor(I, y) < 0.0) ? -1.0 : 1.0;
+}
+
+// Moves an accepted step's start y (stages K, size h, end ynew) to the next step's start:
+// ynew, or for a crossing at thk <= 1 the point there on the continuous extension, where
+// the ray goes on along the other piece (*gjs flips) with a fresh derivative in K[0..7].
+RT_HD void adj_advance(const InstT<double>& I, double* y, double* K, const double* ynew, double h, double thk,
+                       double* gjs) {
+    using namespace dp5;
+    if (thk <= 1.0) {
+        for (int i = 0; i < 8; ++i) {
+            const double ydiff = ynew[i] - y[i];
+            const double r3 = h * K[i] - ydiff;
+            const double r4 = ydiff - h * K[48 + i] - r3;
+            const double r5 =
+                h * (d1 * K[i] + d3 * K[16 + i] + d4 * K[24 + i] + d5 * K[32 + i] + d6 * K[40 + i] + d7 * K[48 + i]);
+            y[i] = dense_value(y[i], ydiff, r3, r4, r5, thk);
+        }
+        *gjs = -*gjs;
+        adj_rhs(I, y, K, *gjs);
+    } else {
+        for (int d = 0; d < 8; ++d) {
+            y[d] = ynew[d];
+            K[d] = K[48 + d];
+        }
+    }
+}
+
+// g = 3 n_z (m . n) - cos theta_m at y and its derivatives: gy[0..3] by (x, t), *gOm by
+// Omega, *gth by theta_m (dual numbers, 6 tangents)
+RT_HD_NOINLINE void gj_factor_grad(const InstT<double>& I, const double* y, double gy[4], double* gOm, double* gth) {
+    typedef gdual<6, double> G6;
+    G6 x[4];
+    for (int i = 0; i < 4; ++i) {
+        x[i] = G6(y[i]);
+        x[i].d[i] = 1.0;
+    }
+    InstT<G6> J;
+    J.Om = G6(I.Om);
+    J.Om.d[4] = 1.0;
+    J.cm = G6(I.cm);
+    J.cm.d[5] = -I.sm;
+    J.sm = G6(I.sm);
+    J.sm.d[5] = I.cm;
+    J.oblique = I.oblique;
+    const G6 ir = rcp(sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+    const G6 n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
+    G6 m[3], mt[3];
+    magnetic_axis(J, x[3], m, mt);
+    const G6 g = 3.0 * n[2] * (m[0] * n[0] + m[1] * n[1] + m[2] * n[2]) - J.cm;
+    for (int i = 0; i < 4; ++i) gy[i] = g.d[i];
+    *gOm = g.d[4];
+    *gth = g.d[5];
 }
 
 // ----------------------------------------------------------------------------
@@ -160,20 +236,22 @@ RT_HD double smoothing_kernel(double c, double sigma) {
 struct AdjRay {
     double y[8], K[56];
     double h, facmax, lam;
+    double gjs;  // the piece of the GJ density being integrated
     int nacc, nrej, nseg;
 };
 
 template <class Store>
 RT_HD void adj_ray_start(const InstT<double>& I, const double y0[8], double h0, AdjRay& R, Store&& store) {
     for (int d = 0; d < 8; ++d) R.y[d] = y0[d];
-    adj_rhs(I, R.y, R.K);
+    R.gjs = adj_start_piece(I, R.y);
+    adj_rhs(I, R.y, R.K, R.gjs);
     R.h = h0;
     R.facmax = 10.0;
     R.lam = 0.0;
     R.nacc = 0;
     R.nrej = 0;
     R.nseg = 1;
-    store(0, R.y, R.h, R.facmax);
+    store(0, R.y, R.h, R.facmax, R.gjs);
 }
 
 // One attempt; returns ST_OK while the ray continues.  On ST_ESCAPED, yf is the
@@ -183,7 +261,7 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
                        double* theta) {
     double ynew[8];
     const double hused = R.h;
-    if (!adj_attempt(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr)) {
+    if (!adj_attempt(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr, R.gjs)) {
         ++R.nrej;
         return (fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam))) ? ST_OK : ST_STEP_UNDERFLOW;
     }
@@ -191,29 +269,31 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
     const double rnew = sqrt(ynew[0] * ynew[0] + ynew[1] * ynew[1] + ynew[2] * ynew[2]);
     bool finite_ok = true;
     for (int d = 0; d < 8; ++d) finite_ok = finite_ok && __builtin_isfinite(ynew[d]);
+    // a crossing of the GJ null surface ends the step there (the ray restarts on the other
+    // piece) unless r = r_max comes first
+    const double thk = (finite_ok && rnew > value(I.R)) ? adj_null_crossing(I, R.y, R.K, ynew, hused, R.gjs) : 2.0;
     if (finite_ok && rnew >= tol.rmax) {
         // r = r_max on the continuous extension
         Stages S;
         for (int s = 0; s < 7; ++s)
             for (int d = 0; d < 8; ++d) S.K[s][d] = R.K[s * 8 + d];
         const double th = locate_crossing(R.y, ynew, S, hused, tol.rmax);
-        dense_at(R.y, ynew, S, hused, th, yf, 0, 8);
-        *theta = th;
-        R.lam += th * hused;
-        return ST_ESCAPED;
+        if (th <= thk) {
+            dense_at(R.y, ynew, S, hused, th, yf, 0, 8);
+            *theta = th;
+            R.lam += th * hused;
+            return ST_ESCAPED;
+        }
     }
-    for (int d = 0; d < 8; ++d) {
-        R.y[d] = ynew[d];
-        R.K[d] = R.K[48 + d];
-    }
-    R.lam += hused;
+    adj_advance(I, R.y, R.K, ynew, hused, thk, &R.gjs);
+    R.lam += (thk <= 1.0) ? thk * hused : hused;
     if (!finite_ok) return ST_NONFINITE;
     if (rnew <= value(I.R)) return ST_HIT_STAR;
     if (R.nacc >= tol.max_steps) return ST_MAX_STEPS;
     if (!(fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam)))) return ST_STEP_UNDERFLOW;
     if (R.nacc % C == 0) {
         if (R.nseg >= Kc) return ST_MAX_STEPS;  // beyond the checkpoint budget
-        store(R.nseg, R.y, R.h, R.facmax);
+        store(R.nseg, R.y, R.h, R.facmax, R.gjs);
         ++R.nseg;
     }
     return ST_OK;
@@ -313,7 +393,7 @@ RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t
 // v^T df/dy (vy) and the four channels vc of v^T df/dp at the state Y (S = double;
 // generic for the host operation counter)
 template <class S = double>
-RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc) {
+RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
     typedef gdual<4, S> DS;
     const VjpInst<S> V = make_vjp_inst<S>(I);
     DS yd[8], fd[8];
@@ -323,7 +403,7 @@ RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S*
         yd[4 + i] = DS(Y[4 + i]);
         yd[4 + i].d[0] = v[i];  // u_k = v_x
     }
-    rhs(V.I4, yd, fd, 1.0);
+    rhs(V.I4, yd, fd, 1.0, nullptr, gjs);
     // the tangent of f is J Hess(H) u; Hess(H) u = J^T (J Hess(H) u)
     for (int i = 0; i < 4; ++i) {
         vy[i] = S(0.0) - fd[4 + i].d[0];
@@ -346,7 +426,7 @@ RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S*
 // adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and to the
 // parameter channels tc.
 template <class S = double>
-RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* tc) {
+RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* tc, double gjs = 0.0) {
     using namespace dp5;
     const double A[6][5] = {{0, 0, 0, 0, 0},
                             {a21, 0, 0, 0, 0},
@@ -356,7 +436,7 @@ RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* 
                             {a61, a62, a63, a64, a65}};
     S vy[8], vc[4];
     for (int i = 5; i >= 0; --i) {
-        rhs_vjp<S>(I, Ys + i * 8, Kb + i * 8, vy, vc);
+        rhs_vjp<S>(I, Ys + i * 8, Kb + i * 8, vy, vc, gjs);
         for (int c = 0; c < 4; ++c) tc[c] = tc[c] + vc[c];
         for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
         for (int jj = 0; jj < i; ++jj) {
@@ -367,10 +447,69 @@ RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* 
     }
 }
 
-// Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing at
-// theta on the last step).  load(s, y, &h, &facmax) reads checkpoint s; rb(idx, d)
-// is the replay buffer (C steps x 9 values).  Adds d(w G(y_f))/dp to pb.  Returns the
-// number of steps or checkpoints the recompute could not reproduce (0 when all is well).
+// Adjoint of y(theta) = E(theta) on the continuous extension of the step yn -> ynew (stages
+// K, size hn) at fixed theta: gyf is the adjoint of y(theta); writes the adjoint of yn to
+// yb and of K_1..K_6 to Kb (the part through K_7 = f(ynew) and ynew is taken here), and
+// adds to the parameter channels tc.
+RT_HD_NOINLINE void dense_adjoint(const InstT<double>& I, const double* yn, const double* K, const double* ynew,
+                                  double hn, double t, const double* gyf, double* yb, double* Kb, double* tc,
+                                  double gjs) {
+    using namespace dp5;
+    const double om = 1.0 - t;
+    const double c3 = t * om, c4 = t * t * om, c5 = t * t * om * om, cy = t - c3 + 2.0 * c4;
+    double ynb[8], K7b[8];
+    for (int d = 0; d < 8; ++d) {
+        ynb[d] = cy * gyf[d];
+        yb[d] = (1.0 - cy) * gyf[d];
+        Kb[d] = hn * (c3 - c4 + c5 * d1) * gyf[d];
+        Kb[8 + d] = 0.0;
+        Kb[16 + d] = hn * c5 * d3 * gyf[d];
+        Kb[24 + d] = hn * c5 * d4 * gyf[d];
+        Kb[32 + d] = hn * c5 * d5 * gyf[d];
+        Kb[40 + d] = hn * c5 * d6 * gyf[d];
+        K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
+    }
+    // K7 = f(ynew)
+    double vy[8], vc[4];
+    rhs_vjp<double>(I, ynew, K7b, vy, vc, gjs);
+    for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
+    for (int c = 0; c < 4; ++c) tc[c] += vc[c];
+    // ynew = y + h sum_i b_i K_i
+    for (int d = 0; d < 8; ++d) {
+        yb[d] += ynb[d];
+        Kb[d] += hn * b1 * ynb[d];
+        Kb[16 + d] += hn * b3 * ynb[d];
+        Kb[24 + d] += hn * b4 * ynb[d];
+        Kb[32 + d] += hn * b5 * ynb[d];
+        Kb[40 + d] += hn * b6 * ynb[d];
+    }
+}
+
+// E(theta) and dE/dtheta on the continuous extension of the step yn -> ynew
+RT_HD void dense_point_deriv(const double* yn, const double* K, const double* ynew, double hn, double t, double* e,
+                             double* et) {
+    using namespace dp5;
+    const double om = 1.0 - t;
+    const double dd[7] = {d1, 0.0, d3, d4, d5, d6, d7};
+    for (int d = 0; d < 8; ++d) {
+        const double ydiff = ynew[d] - yn[d];
+        const double r3 = hn * K[d] - ydiff;
+        const double r4 = ydiff - hn * K[48 + d] - r3;
+        double r5 = 0.0;
+        for (int q = 0; q < 7; ++q) r5 += dd[q] * K[q * 8 + d];
+        r5 *= hn;
+        const double Qq = r3 + t * (r4 + om * r5);
+        e[d] = yn[d] + t * (ydiff + om * Qq);
+        const double dP = -Qq + om * (r4 + (1.0 - 2.0 * t) * r5);
+        et[d] = ydiff + om * Qq + t * dP;
+    }
+}
+
+// Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing of r_max
+// at theta on the last step).  load(s, y, &h, &facmax, &gjs) reads checkpoint s; rb(idx, d)
+// is the replay buffer (C steps x 11 values: y, h, the null-surface crossing thk (2: none)
+// and the piece gjs of the step).  Adds d(w G(y_f))/dp to pb.  Returns the number of
+// steps or checkpoints the recompute could not reproduce (0 when all is well).
 template <class Load, class Replay>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
                           int nseg, double th, double w, int C, Load&& load, Replay&& rb, const double* obs,
@@ -381,30 +520,31 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
     double wG = 0.0;
     int missing = 0;
     for (int s = nseg - 1; s >= 0; --s) {
-        // recompute the segment from its checkpoint
-        double y[8], ynew[8], K[56], h, facmax;
-        load(s, y, &h, &facmax);
+        // recompute the segment from its checkpoint, with the forward pass's decisions
+        double y[8], ynew[8], K[56], h, facmax, gjs;
+        load(s, y, &h, &facmax, &gjs);
         const int first = s * C;
         const int count = (S - first < C) ? (S - first) : C;
-        adj_rhs(I, y, K);
+        adj_rhs(I, y, K, gjs);
         int stored = 0;
         for (int guard = 0; stored < count && guard < 64 * C; ++guard) {
             const double hused = h;
-            if (!adj_attempt(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr)) continue;
+            if (!adj_attempt(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr, gjs)) continue;
+            // the last step ends at r_max (its own crossing test does not matter)
+            const double thk = (first + stored == S - 1) ? 2.0 : adj_null_crossing(I, y, K, ynew, hused, gjs);
             for (int d = 0; d < 8; ++d) rb(stored, d) = y[d];
             rb(stored, 8) = hused;
+            rb(stored, 9) = thk;
+            rb(stored, 10) = gjs;
             ++stored;
-            for (int d = 0; d < 8; ++d) {
-                y[d] = ynew[d];
-                K[d] = K[48 + d];
-            }
+            adj_advance(I, y, K, ynew, hused, thk, &gjs);
         }
         missing += count - stored;
         if (stored == count && s + 1 < nseg) {
             // the recomputed segment must end exactly on the next checkpoint
-            double yc[8], hc, fc;
-            load(s + 1, yc, &hc, &fc);
-            bool same = (hc == h) && (fc == facmax);
+            double yc[8], hc, fc, gc;
+            load(s + 1, yc, &hc, &fc, &gc);
+            bool same = (hc == h) && (fc == facmax) && (gc == gjs);
             for (int d = 0; d < 8; ++d) same = same && (yc[d] == y[d]);
             if (!same) ++missing;
         }
@@ -412,68 +552,39 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         for (int idx = stored - 1; idx >= 0; --idx) {
             double yn[8], Ys[48], Kb[48];
             for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
-            const double hn = rb(idx, 8);
+            const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
             double hdummy = hn, fdummy = 10.0;
-            adj_rhs(I, yn, K);
-            adj_attempt(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys);
-            if (first + idx == S - 1) {
-                // y_f = E(theta) = y + cy (ynew - y) + h (c3 - c4) K1 - h c4 K7 + c5 h sum_i d_i K_i
-                const double t = th, om = 1.0 - t;
-                const double c3 = t * om, c4 = t * t * om, c5 = t * t * om * om, cy = t - c3 + 2.0 * c4;
-                const double dd[7] = {d1, 0.0, d3, d4, d5, d6, d7};
-                double yf[8], yth[8];
-                for (int d = 0; d < 8; ++d) {
-                    const double ydiff = ynew[d] - yn[d];
-                    const double r3 = hn * K[d] - ydiff;
-                    const double r4 = ydiff - hn * K[48 + d] - r3;
-                    double r5 = 0.0;
-                    for (int q = 0; q < 7; ++q) r5 += dd[q] * K[q * 8 + d];
-                    r5 *= hn;
-                    const double Qq = r3 + t * (r4 + om * r5);
-                    yf[d] = yn[d] + t * (ydiff + om * Qq);
-                    const double dP = -Qq + om * (r4 + (1.0 - 2.0 * t) * r5);
-                    yth[d] = ydiff + om * Qq + t * dP;  // dE/dtheta
+            adj_rhs(I, yn, K, gn);
+            adj_attempt(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys, gn);
+            if (first + idx == S - 1 || thk <= 1.0) {
+                // the step ends inside, at E(theta): y_f at r(E) = r_max, or the restart
+                // point on the null surface g(E) = 0.  The adjoint of E(theta) loses its
+                // component along dE/dtheta against the surface's gradient q:
+                //   beta = (ybar . dE/dtheta) / (q . dE/dtheta),  ybar -= beta q,
+                // and for g the parameters' part -beta dg/dp joins the channels.
+                const double t = (first + idx == S - 1) ? th : thk;
+                double e[8], et[8], gyf[8], q[4], gOm = 0.0, gth = 0.0;
+                dense_point_deriv(yn, K, ynew, hn, t, e, et);
+                if (first + idx == S - 1) {
+                    // the observable with 8 state and 6 parameter tangents
+                    double gp[6];
+                    wG = observable_grad(A, e, obs, gbar, n_obs, sigma, gyf, gp);
+                    for (int d = 0; d < 8; ++d) gyf[d] *= w;
+                    for (int k = 0; k < 6; ++k) pb[k] += w * gp[k];
+                    const double r = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+                    q[0] = e[0] / r; q[1] = e[1] / r; q[2] = e[2] / r; q[3] = 0.0;
+                } else {
+                    for (int d = 0; d < 8; ++d) gyf[d] = yb[d];
+                    gj_factor_grad(I, e, q, &gOm, &gth);
                 }
-                // the observable with 8 state and 6 parameter tangents
-                double gyf[8], gp[6];
-                wG = observable_grad(A, yf, obs, gbar, n_obs, sigma, gyf, gp);
-                for (int d = 0; d < 8; ++d) gyf[d] *= w;
-                for (int q = 0; q < 6; ++q) pb[q] += w * gp[q];
-                // crossing r(E(theta)) = r_max: remove the component along dE/dtheta
-                const double r = sqrt(yf[0] * yf[0] + yf[1] * yf[1] + yf[2] * yf[2]);
-                const double gr[3] = {yf[0] / r, yf[1] / r, yf[2] / r};
                 double num = 0.0, den = 0.0;
-                for (int d = 0; d < 8; ++d) num += gyf[d] * yth[d];
-                for (int d = 0; d < 3; ++d) den += gr[d] * yth[d];
+                for (int d = 0; d < 8; ++d) num += gyf[d] * et[d];
+                for (int d = 0; d < 4; ++d) den += q[d] * et[d];
                 const double beta = num / den;
-                for (int d = 0; d < 3; ++d) gyf[d] -= beta * gr[d];
-                // through E at fixed theta
-                double ynb[8], K7b[8];
-                for (int d = 0; d < 8; ++d) {
-                    ynb[d] = cy * gyf[d];
-                    yb[d] = (1.0 - cy) * gyf[d];
-                    Kb[d] = hn * (c3 - c4 + c5 * d1) * gyf[d];
-                    Kb[8 + d] = 0.0;
-                    Kb[16 + d] = hn * c5 * d3 * gyf[d];
-                    Kb[24 + d] = hn * c5 * d4 * gyf[d];
-                    Kb[32 + d] = hn * c5 * d5 * gyf[d];
-                    Kb[40 + d] = hn * c5 * d6 * gyf[d];
-                    K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
-                }
-                // K7 = f(ynew)
-                double vy[8], vc[4];
-                rhs_vjp<double>(I, ynew, K7b, vy, vc);
-                for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
-                for (int c = 0; c < 4; ++c) tc[c] += vc[c];
-                // ynew = y + h sum_i b_i K_i
-                for (int d = 0; d < 8; ++d) {
-                    yb[d] += ynb[d];
-                    Kb[d] += hn * b1 * ynb[d];
-                    Kb[16 + d] += hn * b3 * ynb[d];
-                    Kb[24 + d] += hn * b4 * ynb[d];
-                    Kb[32 + d] += hn * b5 * ynb[d];
-                    Kb[40 + d] += hn * b6 * ynb[d];
-                }
+                for (int d = 0; d < 4; ++d) gyf[d] -= beta * q[d];
+                tc[1] -= beta * gOm;
+                tc[2] -= beta * gth;
+                dense_adjoint(I, yn, K, ynew, hn, t, gyf, yb, Kb, tc, gn);
             } else {
                 // y_{n+1} = y_n + h sum_i b_i K_i; yb holds the adjoint of y_{n+1}
                 for (int d = 0; d < 8; ++d) {
@@ -485,7 +596,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     Kb[40 + d] = hn * b6 * yb[d];
                 }
             }
-            stages_adjoint<double>(I, Ys, hn, Kb, yb, tc);
+            stages_adjoint<double>(I, Ys, hn, Kb, yb, tc, gn);
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels

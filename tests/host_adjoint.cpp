@@ -40,7 +40,7 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
     for (int q = 0; q < n_obs; ++q) flux[q] = 0.0;
     for (int q = 0; q < 6; ++q) grad[q] = 0.0;
     long long missing = 0;
-    std::vector<double> ck((size_t)Kc * 10), rbuf((size_t)C * 9);
+    std::vector<double> ck((size_t)Kc * 11), rbuf((size_t)C * 11);
     for (long long i = 0; i < n; ++i) {
         for (int q = 0; q < 6; ++q) gray[i * 6 + q] = 0.0;
         double seedv[10];
@@ -54,10 +54,11 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
         adj_rhs(I, seedv, f0);
         auto f = [&](const double* yy, double* ff) { adj_rhs(I, yy, ff); };
         const double h0 = initial_step(f, seedv, f0, tol.rtol, tol.atol);
-        auto store = [&](int s, const double* y, double h, double facmax) {
-            for (int d = 0; d < 8; ++d) ck[(size_t)s * 10 + d] = y[d];
-            ck[(size_t)s * 10 + 8] = h;
-            ck[(size_t)s * 10 + 9] = facmax;
+        auto store = [&](int s, const double* y, double h, double facmax, double gjs) {
+            for (int d = 0; d < 8; ++d) ck[(size_t)s * 11 + d] = y[d];
+            ck[(size_t)s * 11 + 8] = h;
+            ck[(size_t)s * 11 + 9] = facmax;
+            ck[(size_t)s * 11 + 10] = gjs;
         };
         AdjRay R;
         adj_ray_start(I, seedv, h0, R, store);
@@ -73,12 +74,13 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
             const double c = nh[0] * obs[3 * o] + nh[1] * obs[3 * o + 1] + nh[2] * obs[3 * o + 2];
             flux[o] += seedv[8] * smoothing_kernel(c, sigma);
         }
-        auto load = [&](int sg, double* y, double* h, double* facmax) {
-            for (int d = 0; d < 8; ++d) y[d] = ck[(size_t)sg * 10 + d];
-            *h = ck[(size_t)sg * 10 + 8];
-            *facmax = ck[(size_t)sg * 10 + 9];
+        auto load = [&](int sg, double* y, double* h, double* facmax, double* gjs) {
+            for (int d = 0; d < 8; ++d) y[d] = ck[(size_t)sg * 11 + d];
+            *h = ck[(size_t)sg * 11 + 8];
+            *facmax = ck[(size_t)sg * 11 + 9];
+            *gjs = ck[(size_t)sg * 11 + 10];
         };
-        auto rb = [&](int idx, int d) -> double& { return rbuf[(size_t)idx * 9 + d]; };
+        auto rb = [&](int idx, int d) -> double& { return rbuf[(size_t)idx * 11 + d]; };
         double pb[6] = {0, 0, 0, 0, 0, 0};
         missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, seedv[8], C, load, rb, obs, gbar, n_obs,
                                    sigma, pb);

@@ -96,3 +96,19 @@ def same_bin_mask(fin_a, ifin_a, fin_b, ifin_b, bins):
 
     ka, kb = key(fin_a, ifin_a), key(fin_b, ifin_b)
     return ka == kb, ka, kb
+
+
+def per_ray_errors(g, go, floor=1e-6):
+    """Relative error of each ray's gradient share g[i] against go[i]: the norm over the six
+    parameters, each scaled by its RMS over the rays.  A ray's own norm is floored at
+    `floor` times the largest ray's: a ray deep in the smoothing kernel's tail (share
+    exp(-(1 - c) / sigma^2) far below the others) has its relative derivative moved by
+    direction differences at the conditioning level times the exponent's slope, up to
+    1 / sigma^2 per radian, and it counts for nothing in the total; such rays are compared
+    in absolute terms at that floor."""
+    sc = np.sqrt((go ** 2).mean(axis=0))
+    sc = np.where(sc > 0, sc, 1.0)
+    num = np.linalg.norm((g - go) / sc, axis=1)
+    den = np.linalg.norm(go / sc, axis=1)
+    den = np.maximum(den, floor * den.max()) if den.size else den
+    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)

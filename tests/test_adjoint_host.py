@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import WELL_TOL, oracle_conditioning
+from tests.parity import WELL_TOL, oracle_conditioning, per_ray_errors
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PER_RAY_TOL = 1e-8
@@ -55,14 +55,6 @@ def host_flux_grad(L, s, t, seed, n, obs, sigma, gbar, C_every=64, max_ckpt=4096
     return flux, grad, st, na, gr, miss
 
 
-def per_ray_errors(g, go):
-    sc = np.sqrt((go ** 2).mean(axis=0))
-    sc = np.where(sc > 0, sc, 1.0)
-    num = np.linalg.norm((g - go) / sc, axis=1)
-    den = np.linalg.norm(go / sc, axis=1)
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
-
-
 CASES = {
     "cfg1-gj-iso-aligned": (W.CFG1["star"], 200),
     "cfg2-gj-aniso-gr-oblique": (W.CFG2["star"], 120),
@@ -83,9 +75,9 @@ def test_host_adjoint_matches_oracle_forward_mode(orc, hadj, case):
     assert np.array_equal(st, sto)
     go = np.einsum("j,njq->nq", gbar, dray)
     rays, status = orc.sample(s, 0, n)
-    # the adjoint integrates the density as it stands (no cut at the null surface)
-    fin, ifin = orc.trace_forward(s, t, rays, status, kinks=False)
-    sd, ch = oracle_conditioning(orc, s, t, rays, status, fin, ifin, kinks=False)
+    # the adjoint traces as forward tracing does (cut at the GJ density's null surface)
+    fin, ifin = orc.trace_forward(s, t, rays, status)
+    sd, ch = oracle_conditioning(orc, s, t, rays, status, fin, ifin)
     well = (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED)
     assert well.sum() >= 20
     assert np.array_equal(na[well], ifin[0][well])

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import WELL_TOL, oracle_conditioning
+from tests.parity import WELL_TOL, oracle_conditioning, per_ray_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -32,14 +32,6 @@ def rt():
     return rt
 
 
-def per_ray_errors(g, go):
-    sc = np.sqrt((go ** 2).mean(axis=0))
-    sc = np.where(sc > 0, sc, 1.0)
-    num = np.linalg.norm((g - go) / sc, axis=1)
-    den = np.linalg.norm(go / sc, axis=1)
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
-
-
 def gpu_flux_grad(rt, star, tol, seed, n, obs, sigma, gbar, ckpt_every=64, max_ckpt=64):
     import torch
     fg = rt.FluxGrad(star, tol, seed, n, obs, sigma, ckpt_every, max_ckpt)
@@ -51,9 +43,9 @@ def gpu_flux_grad(rt, star, tol, seed, n, obs, sigma, gbar, ckpt_every=64, max_c
 
 def well_conditioned(orc, star, tol, n, sto):
     rays, status = orc.sample(star, 0, n)
-    # the adjoint integrates the density as it stands (no cut at the null surface)
-    fin, ifin = orc.trace_forward(star, tol, rays, status, kinks=False)
-    sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin, kinks=False)
+    # the adjoint traces as forward tracing does (cut at the GJ density's null surface)
+    fin, ifin = orc.trace_forward(star, tol, rays, status)
+    sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin)
     return (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED), ifin
 
 

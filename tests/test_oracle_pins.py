@@ -1073,26 +1073,29 @@ def test_smoothed_flux_kernel_normalisation(orc):
 
 def test_forward_mode_flux_equals_traced_flux(orc):
     """The forward-mode run's value part is the smoothed flux of the plain trace of the same
-    map (the density as it stands, no cut at the null surface)."""
+    map (cut at the GJ density's null surface, as forward tracing is)."""
     s, t = W.CFG1["star"], W.CFG1["tol"]
     n, obs = 200, W.observers(32)
     F, _, fray, _, st = orc.flux_fwdmode(s, t, 0, n, obs, 0.02, per_ray=True)
     rays, status = orc.sample(s, 0, n)
-    fin, ifin = orc.trace_forward(s, t, rays, status, kinks=False)
+    fin, ifin = orc.trace_forward(s, t, rays, status)
     Ft = orc.smoothed_flux(fin, ifin, rays[8], obs, 0.02, n)
     assert np.array_equal(st, ifin[2])
     assert np.allclose(F, Ft, rtol=1e-12, atol=1e-12 * np.abs(Ft).max())
     assert np.allclose(fray.sum(axis=0), F, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("plasma", [W.PLASMA_ISO, W.PLASMA_ANISO])
-def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma):
+@pytest.mark.parametrize("plasma,density", [(W.PLASMA_ISO, W.DENSITY_SPHERICAL), (W.PLASMA_ANISO, W.DENSITY_SPHERICAL),
+                                            (W.PLASMA_ANISO, W.DENSITY_GJ)])
+def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma, density):
     """dF/dp by forward mode against central differences of the flux recomputed with the
     nominal accepted step sequence replayed (the map the derivative is of), for all six
-    parameters, on a star whose density has no kink (the spherical test profile) so that
-    the map is smooth: the error falls as the square of the step (central differences)
-    down to the roundoff floor."""
-    s = W.star(M_Msun=1.4, theta_m=0.3, density=W.DENSITY_SPHERICAL, plasma=plasma, m_a_eV=1e-5,
+    parameters.  The map is smooth: the spherical test profile has no kink, and the GJ
+    density is traced one smooth piece at a time, its restart points moving smoothly with
+    the parameters (the implicit derivative of g(y(theta)) = 0, with Omega and theta_m in
+    g, is what the GJ case pins).  The error falls as the square of the step (central
+    differences) down to the roundoff floor."""
+    s = W.star(M_Msun=1.4, theta_m=0.3, density=density, plasma=plasma, m_a_eV=1e-5,
                kdir=W.KDIR_OUTWARD)
     t = W.tol()
     n, obs, sigma = 120, W.observers(32), 0.05
@@ -1110,11 +1113,14 @@ def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma):
 
     for q, k in enumerate(("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")):
         scale = np.abs(dF[:, q]).max()
-        e3 = np.abs(fd(k, 1e-3) - dF[:, q]).max() / scale
-        e5 = np.abs(fd(k, 1e-5) - dF[:, q]).max() / scale
-        assert e5 < 1e-7, (k, e5)
-        # second-order convergence where truncation dominates
-        assert e3 < 1e-4 and (e3 < 1e-8 or e3 > 20 * e5), (k, e3, e5)
+        e = [np.abs(fd(k, rel) - dF[:, q]).max() / scale for rel in (1e-3, 1e-4, 1e-5, 1e-6)]
+        # down to the roundoff floor; the flux of the GJ star bends fast in theta_m, so its
+        # truncation error reaches the floor only at the smallest step
+        assert min(e) < 1e-7, (k, e)
+        # second-order convergence (a factor 100 per decade) where truncation dominates
+        for big, small in zip(e, e[1:]):
+            if big > 1e-6:
+                assert big > 50 * small, (k, e)
 
 
 def _directions(fin):
