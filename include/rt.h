@@ -272,9 +272,12 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
  * The derivative is that of the computed map: accepted DOPRI5 step sizes and each ray's
  * status frozen at the nominal p; resonance root, photon momentum and weight differentiated
  * through the seeding; the r = r_max crossing implicitly on the continuous extension; every
- * accepted step through its stages (Hamilton's equations, Sec. 2 eq. (Hamilton)).
+ * accepted step through its stages (Hamilton's equations, Sec. 2 eq. (Hamilton)).  Rays are
+ * traced as rt_trace_forward traces them: for the GJ density one smooth piece at a time,
+ * restarting where a step crosses the null surface g = 0; the restart point is
+ * differentiated implicitly through g = 0 (with g's own dependence on Omega and theta_m).
  *   phase 0 (forward): seeds n rays (seed, instance 0), traces them with a checkpoint of
- *     (y, h, controller state) every ckpt_every accepted steps, writes flux[n_obs] (device)
+ *     (y, h, controller state, density piece) every ckpt_every accepted steps, writes flux[n_obs] (device)
  *     and, if ray_info != NULL, ray_info "[3][n]" = n_acc, n_rej, status (device).
  *     A ray that would need more than max_ckpt checkpoints ends as RT_ST_MAX_STEPS.
  *   phase 1 (reverse): given gbar[n_obs] (device), recomputes each segment from its
@@ -285,7 +288,7 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
  * obs: HOST array "[n_obs][3]" of unit vectors, 1 <= n_obs <= 64; sigma > 0 [rad];
  * 1 <= ckpt_every <= 1024; max_ckpt >= 1; weights RT_WEIGHTS_CONST_B is not supported.
  * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt) bytes (about
- * n (316 + 80 max_ckpt) + 4.7 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
+ * n (316 + 88 max_ckpt) + 5.8 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
  * RT_EUNSUPPORTED or RT_EHIP. */
 int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
                  int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
