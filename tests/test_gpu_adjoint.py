@@ -6,8 +6,10 @@ its step counts stay put under 2^-50 seed perturbations) the GPU and the oracle 
 the same frozen-step map, so each ray's gradient share must agree to 1e-8 (relative norm
 over the six parameters, each scaled by its RMS over the rays).  Statuses must agree on
 every ray.  On a star without the Goldreich-Julian kink every ray is well conditioned and
-the totals must agree too: flux 1e-9, gradient 1e-8 (vector norm).  With the kink, the
-total flux may differ by no more than the ill-conditioned rays' own share.
+the totals must agree too: flux 1e-9, gradient 1e-8 (vector norm).  Both sides trace the GJ
+density one smooth piece at a time, restarting at its null surface, which leaves the GJ
+test stars' rays well conditioned as well; should some ray not be, the total flux may differ
+by no more than the ill-conditioned rays' own share.
 """
 import numpy as np
 import pytest
