@@ -189,7 +189,9 @@ int rt_bin_flux(const double* fin, const int32_t* ifin, const double* w, int64_t
 /* rt_trace_backward -- trace the nx x ny parallel rays of an image plane backwards in the
  * worldline parameter (Sec. 2.1; Sec. 2.3 for the role of gravity) through every level
  * crossing k^gamma = k^a (sign change of G = g^{mu nu} k_mu k_nu + m_a^2, Sec. 3), until the
- * ray hits the star or recedes beyond 1.01 D.  k_t = -1 (monochromatic, Sec. 4.3), |k| from
+ * ray hits the star or recedes beyond 1.01 D.  The GJ density is integrated one smooth
+ * piece at a time, as in rt_trace_forward: a step that crosses its null surface ends there,
+ * its events searched only on the part taken.  k_t = -1 (monochromatic, Sec. 4.3), |k| from
  * the LO branch of eq. (AnisotropicDisp).  Events are sampled at 1/4, 1/2, 3/4 and 1 of
  * every accepted step and bisected on the continuous extension.
  * Output: ev "[K][RT_NEV][nx*ny]" (first K events per pixel, pixel index i*ny + j),

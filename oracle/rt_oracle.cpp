@@ -1135,7 +1135,12 @@ static void backward_ray(const Inst<double>& I, const orc_tol& tol, double D, do
     for (int d = 0; d < 3; ++d) y[4 + d] = (ko[d] - nko * n0[d]) + (nko / std::sqrt(A0)) * n0[d];
     y[7] = -1.0;
 
-    auto f = [&](const double* yy, double* ff) { rhs_t(I, yy, ff, -1.0); };
+    // the GJ density one smooth piece at a time, as in forward tracing (J.gj_branch: the
+    // piece being integrated; a step that crosses the null surface is cut there)
+    Inst<double> J = I;
+    const bool kinky = I.density == DEN_GJ;
+    if (kinky) J.gj_branch = (gj_factor(I, y, y[3]) < 0.0) ? -1.0 : 1.0;
+    auto f = [&](const double* yy, double* ff) { rhs_t(J, yy, ff, -1.0); };
     // Backward rays start in near-vacuum far from the star, where the error
     // estimate vanishes and the step would grow without bound and could jump
     // across the whole plasma region.  A step therefore never moves the ray by
@@ -1171,12 +1176,26 @@ static void backward_ray(const Inst<double>& I, const orc_tol& tol, double D, do
             continue;
         }
         ++nacc;
-        // events: G sampled at theta = 1/4, 1/2, 3/4, 1 of the accepted step
+        // crossing of the null surface inside the step (none: thk > 1): 60 bisections, the
+        // first point past the surface
+        double thk = 2.0;
+        if (kinky && J.gj_branch * gj_factor(I, st.ynew, st.ynew[3]) < 0.0) {
+            double lo = 0.0, hi = 1.0;
+            for (int it = 0; it < 60; ++it) {
+                double mid = 0.5 * (lo + hi);
+                double ym[8];
+                dense_eval(y, st, h, mid, ym);
+                if (J.gj_branch * gj_factor(I, ym, ym[3]) > 0.0) lo = mid; else hi = mid;
+            }
+            thk = hi;
+        }
+        const double tend = (thk <= 1.0) ? thk : 1.0;
+        // events: G sampled at theta = 1/4, 1/2, 3/4, 1 of the part of the step taken
         double thp = 0.0, Gp = Gprev;
         for (int q = 1; q <= 4; ++q) {
-            double thq = 0.25 * q;
+            double thq = 0.25 * q * tend;
             double yq[8];
-            if (q == 4) { for (int d = 0; d < 8; ++d) yq[d] = st.ynew[d]; }
+            if (q == 4 && thk > 1.0) { for (int d = 0; d < 8; ++d) yq[d] = st.ynew[d]; }
             else dense_eval(y, st, h, thq, yq);
             double Gq = event_G(I, yq);
             if ((Gp > 0.0 && Gq <= 0.0) || (Gp < 0.0 && Gq >= 0.0)) {
@@ -1202,8 +1221,18 @@ static void backward_ray(const Inst<double>& I, const orc_tol& tol, double D, do
             thp = thq; Gp = Gq;
         }
         Gprev = Gp;
-        lam += h;
-        for (int d = 0; d < 8; ++d) { y[d] = st.ynew[d]; k1[d] = st.K[6][d]; }
+        if (thk <= 1.0) {
+            // restart at the crossing on the other piece, with a fresh derivative
+            double yk[8];
+            dense_eval(y, st, h, thk, yk);
+            for (int d = 0; d < 8; ++d) y[d] = yk[d];
+            lam += thk * h;
+            J.gj_branch = -J.gj_branch;
+            f(y, k1);
+        } else {
+            lam += h;
+            for (int d = 0; d < 8; ++d) { y[d] = st.ynew[d]; k1[d] = st.K[6][d]; }
+        }
         double rnew = std::sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
         if (!all_finite8(y)) { status = ORC_NONFINITE; break; }
         if (rnew <= R) { status = ORC_HIT_STAR; break; }

@@ -143,12 +143,13 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
     double y[8], ynew[8];
     Stages S;
     double h = 0.0, lam = 0.0, facmax = 10.0, Gprev = 0.0, rprev = 0.0;
+    double gjs = 0.0;  // the piece of the GJ density being integrated (0: other densities)
     int nacc = 0, nrej = 0, ne = 0;
     for (int d = 0; d < 8; ++d) { y[d] = 0.0; S.K[0][d] = 0.0; }
     y[0] = 1e5;
     y[7] = -1.0;
     AxisRef ref = axis_ref_at(I, 0.0);
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0, &ref); };
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0, &ref, gjs); };
 
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -167,6 +168,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
                         h = h0s[p];
                         lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0; ne = 0;
                         if (I.oblique) ref = axis_ref_at(I, y[3]);
+                        gjs = (I.density == DEN_GJ) ? ((gj_factor(I, y, &ref) < 0.0) ? -1.0 : 1.0) : 0.0;
                         Gprev = event_G(I, y);
                         rprev = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
                         active = true;
@@ -195,12 +197,23 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
             continue;
         }
         ++nacc;
-        // production events on this step
+        // a step that crosses the GJ density's null surface ends there: the ray goes on
+        // along the other piece from the first point past it (thk > 1: no crossing)
+        double thk = 2.0;
+        if (gjs != 0.0) {
+            const double g1 = gj_factor(I, ynew, &ref);
+            if (gjs * g1 < 0.0) {
+                double phik;
+                thk = locate_null_crossing(I, y, ynew, S, h, gjs, gjs * gj_factor(I, y, &ref), gjs * g1, &ref, &phik);
+            }
+        }
+        const double tend = (thk <= 1.0) ? thk : 1.0;
+        // production events on the part of the step taken
         double thp = 0.0, Gp = Gprev;
         for (int qq = 1; qq <= 4; ++qq) {
-            double thq = 0.25 * qq;
+            double thq = 0.25 * qq * tend;
             double Gq;
-            if (qq == 4) {
+            if (qq == 4 && thk > 1.0) {
                 Gq = event_G(I, ynew);
             } else {
                 double yq[8];
@@ -228,9 +241,19 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
             Gp = Gq;
         }
         Gprev = Gp;
-        lam += h;
-        if (I.oblique) axis_ref_advance(I, ref, ynew[3]);
-        for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+        if (thk <= 1.0) {
+            double yk[8];
+            dense_at(y, ynew, S, h, thk, yk, 0, 8);
+            lam += thk * h;
+            for (int d = 0; d < 8; ++d) y[d] = yk[d];
+            gjs = -gjs;
+            if (I.oblique) axis_ref_advance(I, ref, y[3]);
+            f(y, S.K[0]);
+        } else {
+            lam += h;
+            if (I.oblique) axis_ref_advance(I, ref, ynew[3]);
+            for (int d = 0; d < 8; ++d) { y[d] = ynew[d]; S.K[0][d] = S.K[6][d]; }
+        }
         double rnew = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
         bool finite_ok = true;
         for (int d = 0; d < 8; ++d) finite_ok = finite_ok && isfinite(y[d]);

@@ -111,11 +111,12 @@ def test_backward_small_image_matches_oracle(rt, orc, star_name):
     ev, nev, fin, ifin = rt.rt_trace_backward(s, tol, image, K=K)
     ev_o, nev_o, fin_o, ifin_o = orc.trace_backward(s, tol, image, K=K)
     excuse = _oracle_excuse(orc, s, tol, image, K, ev_o, nev_o, fin_o, ifin_o)
-    # Goldreich-Julian plasma has the |rho| kink on the null surface: most rays that reach
-    # the plasma cross it and are ill-conditioned (see tests/parity.py); the smooth magnetar
-    # plasma has none.  Excused rays must still agree in status (all but 2%) and, when both
-    # escape, in final direction to the discretisation-error scale.
-    assert excuse.mean() <= (0.02 if star_name == "cfg3" else 0.95), excuse.mean()
+    # Goldreich-Julian plasma has the |rho| kink on the null surface; both tracers integrate
+    # it one smooth piece at a time, restarting where a step crosses the surface, which
+    # leaves these images' rays well conditioned (85-88% of them were not, integrated as it
+    # stands).  Excused rays must still agree in status (all but 2%) and, when both escape,
+    # in final direction to the discretisation-error scale.
+    assert excuse.mean() <= 0.02, excuse.mean()
     ifg = ifin.cpu().numpy()
     _compare(ev.cpu().numpy(), nev.cpu().numpy(), fin.cpu().numpy(), ifg, ev_o, nev_o, fin_o, ifin_o, K, excuse)
     assert (ifg[2] != ifin_o[2]).mean() <= 0.02
