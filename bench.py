@@ -185,16 +185,18 @@ def bench_backward(args, rt, W, np, torch):
     nv = nev.cpu().numpy().astype(np.int64)
     acc, rej = float(inf[0].sum()), float(inf[1].sum())
     ft = flop_table()[variant_key(star)]
-    # per attempt one DOPRI5 attempt; per accepted step four probes of G on the continuous
-    # extension; per recorded event 60 bisection probes
-    flops = (acc + rej) * ft["attempt"] + acc * 4 * ft["event_probe"] + float(nv.sum()) * 60 * ft["event_probe"]
+    # per attempt one DOPRI5 attempt; per accepted step three probes of G on the continuous
+    # extension and one at the step's end point (no dense output there); per recorded event
+    # 60 bisection probes
+    flops = ((acc + rej) * ft["attempt"] + acc * (3 * ft["event_probe"] + ft["event_g"])
+             + float(nv.sum()) * 60 * ft["event_probe"])
     tf = flops / (kernel_ms * 1e-3) / 1e12
     st = {str(k): int(v) for k, v in zip(*np.unique(inf[2], return_counts=True))}
     out = dict(workload=cfg["name"], pixels=n, events=int(nv.sum()), rays_with_events=int((nv > 0).sum()),
                statuses=st, accepted_steps=acc, rejected_steps=rej, ms_per_image=ms_call, kernel_ms=kernel_ms,
                rays_per_s=n / (ms_call * 1e-3), ray_steps_per_s=acc / (ms_call * 1e-3), kernel_tflops=tf,
                kernel_frac=tf / FP64_VECTOR_PEAK_TFLOPS, flop_per_attempt=ft["attempt"],
-               flop_per_event_probe=ft["event_probe"])
+               flop_per_event_probe=ft["event_probe"], flop_per_end_point_probe=ft["event_g"])
     out["power"] = bench_backward_power(args, rt, W, np, torch, cfg, ev, nev)
     return out
 

@@ -309,8 +309,13 @@ size_t rt_workspace_size(int32_t op, int64_t n);
  * kernels of rt_flux_grad) and of the event-weight kernel of rt_backward_power is bracketed by a HIP event pair recorded on the caller's
  * stream, up to 1024 launches; rt_timing(0) stops recording.  rt_kernel_times waits
  * for the recorded launches and writes up to max durations [ms] and kernel kinds
- * (RT_KERNEL_*) in launch order; returns the count.  Recording is process-wide and not
- * thread-safe, and must be off while a stream is being captured into a graph. */
+ * (RT_KERNEL_*) in launch order; returns the count.  This is a measurement aid with
+ * one record list for the whole process (every thread, stream and device): the
+ * library's only mutable global besides the thread-local error string.  Its state is
+ * guarded by a mutex, so concurrent calls are safe and their launches interleave in
+ * the list in the order they were issued; a launch still in flight on another thread
+ * when rt_kernel_times runs is left out.  Recording must be off while a stream is
+ * being captured into a graph. */
 enum { RT_KERNEL_TRACE_FORWARD = 1, RT_KERNEL_TRACE_BATCHED = 2, RT_KERNEL_TRACE_BACKWARD = 3,
        RT_KERNEL_ADJOINT_FORWARD = 4, RT_KERNEL_ADJOINT_REVERSE = 5, RT_KERNEL_EVENT_POWER = 6 };
 int rt_timing(int32_t on);

@@ -94,10 +94,15 @@ int main() {
                 FC G = g_kk(I, yt) + I.ma2;
                 (void)G;
                 long long fprobe = g_flops;
+                // the same event function at a step's end point (no continuous extension)
+                g_flops = 0;
+                FC G1 = g_kk(I, ynew) + I.ma2;
+                (void)G1;
+                long long fendpt = g_flops;
                 std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld, \"vjp\": %lld, "
-                            "\"stages_adjoint\": %lld, \"event_probe\": %lld}",
+                            "\"stages_adjoint\": %lld, \"event_probe\": %lld, \"event_g\": %lld}",
                             first ? "" : ", ", pn[pl], dn[de], ob ? "oblique" : "aligned", frhs, fstep, fvjp,
-                            fstages, fprobe);
+                            fstages, fprobe, fendpt);
                 first = false;
             }
     std::printf("}\n");

@@ -321,7 +321,7 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         rc = rt_sample_resonance(star, seed, 0, 0, n, W.rays, W.status, stream);
         if (rc) return rc;
-        rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st, 1);
+        rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st);
         if (rc) return rc;
         rc = order_work_list(W.fw, n, st);
         if (rc) return rc;

@@ -1,6 +1,7 @@
 // Host side of the C ABI: validation, constants, schedules, workspace sizes,
 // error strings.
 #include "rt_common.hpp"
+#include <mutex>
 
 #include <string>
 
@@ -279,40 +280,52 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
 extern "C" const char* rt_last_error(void) { return g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
-// kernel timing: a pool of event pairs, one per timed launch, read after the fact
+// kernel timing: a pool of event pairs, one per timed launch, read after the fact.
+// One record list for the process, guarded by a mutex: a launch takes its slot under
+// the lock when its start event is recorded (the slot stays with the calling thread
+// until its stop event is recorded), and rt_kernel_times reports completed slots only.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int TIMING_SLOTS = 1024;
 struct Timing {
+    std::mutex mu;
     bool on = false;
-    int used = 0;
-    int open = -1;  // slot whose start event is recorded and stop is pending
+    int used = 0;  // slots handed out since recording started
     int kinds[TIMING_SLOTS];
+    bool done[TIMING_SLOTS];
     hipEvent_t ev[TIMING_SLOTS][2];
     bool created = false;
 };
 Timing g_timing;
+thread_local int t_open = -1;  // this thread's slot whose stop event is pending
 }  // namespace
 
 void rtd::timing_begin(hipStream_t st, int kind) {
     Timing& T = g_timing;
+    std::lock_guard<std::mutex> lock(T.mu);
+    t_open = -1;
     if (!T.on || T.used >= TIMING_SLOTS) return;
     const int k = T.used;
     if (hipEventRecord(T.ev[k][0], st) != hipSuccess) return;
     T.kinds[k] = kind;
-    T.open = k;
+    T.done[k] = false;
+    T.used = k + 1;
+    t_open = k;
 }
 
 void rtd::timing_end(hipStream_t st) {
     Timing& T = g_timing;
-    if (!T.on || T.open < 0) return;
-    if (hipEventRecord(T.ev[T.open][1], st) == hipSuccess) T.used = T.open + 1;
-    T.open = -1;
+    std::lock_guard<std::mutex> lock(T.mu);
+    const int k = t_open;
+    t_open = -1;
+    if (!T.on || k < 0 || k >= T.used) return;
+    if (hipEventRecord(T.ev[k][1], st) == hipSuccess) T.done[k] = true;
 }
 
 extern "C" int rt_timing(int32_t on) {
     clear_error();
     Timing& T = g_timing;
+    std::lock_guard<std::mutex> lock(T.mu);
     if (on && !T.created) {
         for (int k = 0; k < TIMING_SLOTS; ++k)
             for (int e = 0; e < 2; ++e)
@@ -320,20 +333,22 @@ extern "C" int rt_timing(int32_t on) {
         T.created = true;
     }
     T.on = on != 0;
-    T.open = -1;
     if (T.on) T.used = 0;  // stopping keeps the records for rt_kernel_times
     return RT_OK;
 }
 
 extern "C" int32_t rt_kernel_times(double* ms, int32_t* kind, int32_t max) {
     Timing& T = g_timing;
-    int m = T.used < max ? T.used : max;
-    for (int k = 0; k < m; ++k) {
+    std::lock_guard<std::mutex> lock(T.mu);
+    int m = 0;
+    for (int k = 0; k < T.used && m < max; ++k) {
+        if (!T.done[k]) continue;
         float t = -1.0f;
         if (hipEventSynchronize(T.ev[k][1]) != hipSuccess || hipEventElapsedTime(&t, T.ev[k][0], T.ev[k][1]) != hipSuccess)
             t = -1.0f;
-        if (ms) ms[k] = (double)t;
-        if (kind) kind[k] = T.kinds[k];
+        if (ms) ms[m] = (double)t;
+        if (kind) kind[m] = T.kinds[k];
+        ++m;
     }
     return m;
 }

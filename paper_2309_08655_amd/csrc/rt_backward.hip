@@ -82,8 +82,11 @@ __global__ void __launch_bounds__(256) bwd_init_kernel(InstT<double> I, TolC tol
             double corr = nko / sqrt(A0) - nko;
             for (int d = 0; d < 3; ++d) y[4 + d] = ko[d] + corr * nn[d];
             y[7] = -1.0;
+            // GJ density: the smooth piece of |g| the pixel's ray starts on, which the tracing
+            // kernel integrates from here (also for the starting step's probe)
+            const double gjs = (I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
             double f0[8];
-            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0); };
+            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0, nullptr, gjs); };
             f(y, f0);
             double h = step_cap(y, f0, initial_step(f, y, f0, tol.rtol, tol.atol));
             h0s[p] = h;

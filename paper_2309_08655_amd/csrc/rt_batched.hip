@@ -222,7 +222,7 @@ extern "C" int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_t
     I0.oblique = batch->any_oblique;
     int rc = launch_sample_batched(B.itab, B.ctab, B.off, n_inst, seed, N, rays, status, B.inst_of, st);
     if (rc) return rc;
-    rc = launch_trace_init(I0, B.itab, B.inst_of, T, rays, status, N, B.fw, fin, ifin, st, 1);
+    rc = launch_trace_init(I0, B.itab, B.inst_of, T, rays, status, N, B.fw, fin, ifin, st);
     if (rc) return rc;
     rc = order_work_list(B.fw, N, st);
     if (rc) return rc;

@@ -185,11 +185,11 @@ int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, con
                              const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
 int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, const int64_t* off, int32_t n_inst,
                           uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st);
-// cut_gj: evaluate the GJ density on the seed's smooth piece (forward tracing, which cuts
-// steps at the null surface) rather than as |g| (the adjoint's map)
+// FSAL derivative and starting step of every traced seed, on the seed's smooth piece of
+// the GJ density; the cost keys of the work list
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
-                      int32_t* ifin, hipStream_t st, int cut_gj);
+                      int32_t* ifin, hipStream_t st);
 int launch_bin(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
                const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over, void* ws,
                hipStream_t st);

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const
                                                          const int32_t* __restrict__ status, int64_t n,
                                                          int32_t* __restrict__ keys, double* __restrict__ h0s,
                                                          double* __restrict__ k1s, double* __restrict__ fin,
-                                                         int32_t* __restrict__ ifin, int cut_gj) {
+                                                         int32_t* __restrict__ ifin) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
         const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
@@ -84,10 +84,10 @@ __global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const
         } else {
             double y[8], f0[8];
             for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
-            // GJ density, cut at the null surface (forward tracing): the smooth piece of |g|
-            // the seed lies on, which the tracing kernel integrates from here (also for the
-            // starting step's probe); the adjoint integrates |g| itself (cut_gj = 0)
-            const double gjs = (cut_gj && I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
+            // GJ density, cut at the null surface: the smooth piece of |g| the seed lies on,
+            // which the tracing kernels (forward, batched and the adjoint's) integrate from
+            // here, also for the starting step's probe
+            const double gjs = (I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
             auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, nullptr, gjs); };
             f(y, f0);
             double h = initial_step(f, y, f0, tol.rtol, tol.atol);
@@ -531,7 +531,7 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     FwdWs W = carve_fwd_ws(ws, n);
     hipStream_t st = (hipStream_t)stream;
-    int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st, 1);
+    int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st);
     if (rc) return rc;
     rc = order_work_list(W, n, st);
     if (rc) return rc;
@@ -659,9 +659,9 @@ int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, 
 
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
-                      int32_t* ifin, hipStream_t st, int cut_gj) {
+                      int32_t* ifin, hipStream_t st) {
     hipLaunchKernelGGL(trace_init_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, T, rays,
-                       status, n, W.keys, W.h0, W.k1, fin, ifin, cut_gj);
+                       status, n, W.keys, W.h0, W.k1, fin, ifin);
     return check_launch("trace_init_kernel");
 }
 

@@ -1,30 +1,32 @@
 """Comparison helpers for GPU-vs-oracle parity tests.
 
 Conditioning.  The Goldreich-Julian density is |rho|/e: the plasma frequency has a
-V-shaped minimum on the null surface Omega.B = 0, so the force -grad(w_p^2) is
-discontinuous there and rays that cross or are channelled along that surface make
-the adaptive step control reject many steps.  For such rays the discrete solution
-at rtol 1e-8 is ill-conditioned: perturbing the seed by one part in 1e15 changes the
-asymptotic direction by up to ~1e-5 rad (while rays that never cross it agree to
-~1e-11).  Two independent implementations differ at the roundoff level, so a per-ray
-tolerance below a ray's own conditioning is unattainable.  Each ray's conditioning
-is therefore measured with the oracle alone (the oracle re-run from seeds perturbed
-by 2^-50 relative) and the tolerance applied per class:
-  well-conditioned rays (oracle self-difference <= 1e-11 rad under four
-      perturbations, same step counts):
-      direction <= 1e-9 rad, |d omega| <= 1e-12 (the per-ray target);
-  ill-conditioned rays: direction <= 1e-4 rad (the discretisation-error scale:
-      rtol 1e-8 against rtol 1e-12 differs by up to ~5e-5 rad), and the distribution
-      of GPU-oracle differences no wider than 10x the oracle's own self-differences
-      (median and 90th percentile).
-Statuses must agree (a ray may switch between escaping and hitting the star only if
-it is ill-conditioned; at most 0.5% of rays)."""
+V-shaped minimum on the null surface Omega.B = 0, where the force -grad(w_p^2) jumps.
+Integrated as it stands, rays that cross or graze that surface are ill-conditioned at
+rtol 1e-8 (a 2^-50 change of the seed moves the arrival direction by up to ~1e-5 rad).
+Both the oracle and the kernels integrate one smooth piece of |rho| at a time and
+restart on the other piece at the located crossing (Sec. 5 eq. (GJDensity) with the
+discontinuity treatment of Hairer-Norsett-Wanner I, Sec. II.6); with that cut every
+forward ray of the test workloads is well conditioned (oracle self-difference ~1e-12 rad).
+
+Each ray's conditioning is still measured with the oracle alone (the oracle re-run from
+seeds perturbed by 2^-50 relative), as a guard, and the per-ray tolerances are:
+  rays on which the GPU takes the oracle's step sequence (accepted and rejected counts
+      equal, lambda_f to 1e-12): direction <= 1e-9 rad, |d omega| <= 1e-12;
+  "flip" rays (another step sequence): at most 0.1% of the escaped rays, each with
+      direction <= 1e-6 rad;
+  at most 0.5% of the escaped rays ill-conditioned by the oracle's own measure (self-
+      difference above 1e-11 rad, or a changed step sequence, under the perturbations).
+Statuses must agree on every well-conditioned ray; a ray may switch between escaping
+and hitting the star only if it is ill-conditioned, on at most 0.1% of the rays."""
 import numpy as np
 
 WELL_TOL = 1e-11     # oracle self-difference defining a well-conditioned ray [rad]
-DIR_TOL = 1e-9       # per-ray direction tolerance for well-conditioned rays [rad]
-OMEGA_TOL = 1e-12    # energy at infinity, well-conditioned rays
-ILL_DIR_TOL = 1e-4   # direction tolerance for ill-conditioned rays [rad]
+DIR_TOL = 1e-9       # direction tolerance, rays with the oracle's step sequence [rad]
+OMEGA_TOL = 1e-12    # energy at infinity, rays with the oracle's step sequence
+FLIP_DIR_TOL = 1e-6  # direction tolerance for flip rays [rad]
+MAX_FLIP_FRAC = 1e-3  # flip rays (and status changes) per escaped ray (per ray)
+MAX_ILL_FRAC = 5e-3   # ill-conditioned escaped rays the oracle may show (a guard on the cut)
 
 
 def unit(theta, phi):
@@ -54,31 +56,43 @@ def oracle_conditioning(orc, star, tol, rays, status, fin_o, ifin_o, kinks=True)
     return sd, changed
 
 
-def assert_trace_parity(fin_g, ifin_g, fin_o, ifin_o, selfdiff, seq_changed, max_status_mismatch_frac=5e-3):
+def assert_trace_parity(fin_g, ifin_g, fin_o, ifin_o, selfdiff, seq_changed, max_flip_frac=MAX_FLIP_FRAC,
+                        max_ill_frac=MAX_ILL_FRAC, compare_lambda=True):
+    """GPU final records (fin_g, ifin_g) against the oracle's on the same seeds.
+
+    Same-sequence rays (escaped on both sides with equal accepted and rejected step counts
+    and path parameter lambda_f to 1e-12): direction <= 1e-9 rad, |d omega| <= 1e-12.
+    Flip rays (escaped on both sides, another step sequence): at most max_flip_frac of the
+    escaped rays, each within 1e-6 rad.  Statuses equal on every well-conditioned ray, and
+    at most max_flip_frac of all rays switch.  The oracle's own ill-conditioned share of
+    the escaped rays stays below max_ill_frac.  compare_lambda=False: records without
+    lambda_f (a host loop that returns the final state only) are sequenced by counts."""
     st_g, st_o = ifin_g[2], ifin_o[2]
+    n = len(st_o)
     well = (selfdiff <= WELL_TOL) & ~seq_changed
     mism = st_g != st_o
     assert not (mism & well).any(), ("status mismatch on well-conditioned rays", np.nonzero(mism & well)[0][:10])
-    assert mism.sum() <= max(1, max_status_mismatch_frac * len(st_o)), ("status mismatches", int(mism.sum()))
+    assert mism.sum() <= max_flip_frac * n, ("status mismatches", int(mism.sum()), n)
     esc = (st_o == 1) & (st_g == 1)
+    lam_g, lam_o = fin_g[13], fin_o[13]
+    same = (ifin_g[0] == ifin_o[0]) & (ifin_g[1] == ifin_o[1])
+    if compare_lambda:
+        same &= np.abs(lam_g - lam_o) <= 1e-12 * np.abs(lam_o)
     d = angle_between(fin_g[8], fin_g[9], fin_o[8], fin_o[9])
     dw = np.abs(fin_g[11] - fin_o[11])
-    wc = esc & well
+    sq = esc & same
+    fl = esc & ~same
     ill = esc & ~well
-    out = dict(n=int(len(st_o)), escaped=int(esc.sum()), well=int(wc.sum()), ill=int(ill.sum()),
-               status_mismatch=int(mism.sum()),
-               max_dir_well=float(d[wc].max()) if wc.any() else 0.0,
-               max_domega_well=float(dw[wc].max()) if wc.any() else 0.0,
-               max_dir_ill=float(d[ill].max()) if ill.any() else 0.0)
-    assert out["max_dir_well"] <= DIR_TOL, out
-    assert out["max_domega_well"] <= OMEGA_TOL, out
-    assert out["max_dir_ill"] <= ILL_DIR_TOL, out
-    if ill.sum() >= 20:
-        for q in (0.5, 0.9):
-            a, b = np.quantile(d[ill], q), np.quantile(selfdiff[ill], q)
-            out[f"q{int(q * 100)}_ill_gpu"] = float(a)
-            out[f"q{int(q * 100)}_ill_self"] = float(b)
-            assert a <= 10.0 * b + 1e-12, (q, a, b, out)
+    out = dict(n=int(n), escaped=int(esc.sum()), same_sequence=int(sq.sum()), flips=int(fl.sum()),
+               well=int((esc & well).sum()), ill=int(ill.sum()), status_mismatch=int(mism.sum()),
+               max_dir_same=float(d[sq].max()) if sq.any() else 0.0,
+               max_domega_same=float(dw[sq].max()) if sq.any() else 0.0,
+               max_dir_flip=float(d[fl].max()) if fl.any() else 0.0)
+    assert out["max_dir_same"] <= DIR_TOL, out
+    assert out["max_domega_same"] <= OMEGA_TOL, out
+    assert out["flips"] <= max_flip_frac * out["escaped"], ("too many flip rays", out)
+    assert out["max_dir_flip"] <= FLIP_DIR_TOL, out
+    assert out["ill"] <= max_ill_frac * out["escaped"], ("too many ill-conditioned rays", out)
     return out
 
 

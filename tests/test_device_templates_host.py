@@ -108,9 +108,9 @@ def test_host_tracing_loop_matches_oracle(orc, host, cfg):
         fin[9, i] = math.atan2(v[1], v[0])
         fin[11, i] = -yf[7]
     sd, ch = oracle_conditioning(orc, s, t, rays, st, fin_o, ifin_o)
-    out = assert_trace_parity(fin, ifin, fin_o, ifin_o, sd, ch)
+    out = assert_trace_parity(fin, ifin, fin_o, ifin_o, sd, ch, compare_lambda=False)
     print(out)
-    assert out["well"] > 0.15 * out["escaped"]
+    assert out["well"] == out["escaped"]
 
 
 @pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])

@@ -43,12 +43,33 @@ def gpu_flux_grad(rt, star, tol, seed, n, obs, sigma, gbar, ckpt_every=64, max_c
     return F.cpu().numpy(), g.cpu().numpy(), gr.cpu().numpy(), info.cpu().numpy()
 
 
-def well_conditioned(orc, star, tol, n, sto):
+def well_conditioned(orc, star, tol, n, sto, with_paths=False):
     rays, status = orc.sample(star, 0, n)
     # the adjoint traces as forward tracing does (cut at the GJ density's null surface)
     fin, ifin = orc.trace_forward(star, tol, rays, status)
     sd, ch = oracle_conditioning(orc, star, tol, rays, status, fin, ifin)
-    return (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED), ifin
+    well = (sd <= WELL_TOL) & ~ch & (sto == W.STATUS_ESCAPED)
+    if with_paths:
+        return well, ifin, rays, fin
+    return well, ifin
+
+
+C_KMS = 299792.458
+
+
+def gj_sign_changed(star, rays, fin):
+    """Rays whose Goldreich-Julian factor g = 3 n_z (m . n) - cos(theta_m) (Sec. 5 eq.
+    (GJDensity), the dipole axis m rotating at Omega = 2 pi / P about z) has opposite signs
+    at the seed and at the final point: such a ray crossed the density's null surface an
+    odd number of times, so its traced map contains at least one restart."""
+    def g(y):
+        r = np.sqrt(y[0] ** 2 + y[1] ** 2 + y[2] ** 2)
+        r = np.where(r > 0, r, 1.0)  # untraced rays carry zero states
+        ph = 2.0 * np.pi / (star["P_s"] * C_KMS) * y[3]
+        st, ct = np.sin(star["theta_m"]), np.cos(star["theta_m"])
+        mn = (st * np.cos(ph) * y[0] + st * np.sin(ph) * y[1] + ct * y[2]) / r
+        return 3.0 * (y[2] / r) * mn - ct
+    return np.sign(g(rays[:8])) != np.sign(g(fin[:8]))
 
 
 @pytest.mark.parametrize("name,star,n,sigma", [
@@ -66,15 +87,22 @@ def test_flux_grad_matches_oracle(rt, orc, name, star, n, sigma):
     F, g, gr, info = gpu_flux_grad(rt, star, tol, 0, n, obs, sigma, gbar)
     Fo, dFo, fray, dray, sto = orc.flux_fwdmode(star, tol, 0, n, obs, sigma, per_ray=True)
     assert np.array_equal(info[2], sto)
-    well, ifin = well_conditioned(orc, star, tol, n, sto)
+    well, ifin, rays_o, fin_o = well_conditioned(orc, star, tol, n, sto, with_paths=True)
     assert np.array_equal(info[0][well], ifin[0][well])
+    esc = sto == W.STATUS_ESCAPED
+    if star["density"] == W.DENSITY_GJ:
+        # the null-surface cut leaves every escaped ray of the GJ stars well conditioned, and
+        # the compared rays include many whose map restarts on the surface
+        assert well.sum() == esc.sum(), (int(well.sum()), int(esc.sum()))
+        crossed = gj_sign_changed(star, rays_o, fin_o) & well
+        print(name, "compared rays that restart on the null surface:", int(crossed.sum()), flush=True)
+        assert crossed.sum() >= min(10, esc.sum() // 4), int(crossed.sum())
     go = np.einsum("j,njq->nq", gbar, dray)
     err = per_ray_errors(gr, go)
     if well.any():
         assert err[well].max() <= PER_RAY_TOL, (name, err[well].max())
     assert np.all(gr[sto != W.STATUS_ESCAPED] == 0.0)
     assert np.allclose(gr.sum(axis=0), g, rtol=1e-12, atol=1e-12 * np.abs(g).max())
-    esc = sto == W.STATUS_ESCAPED
     if well.sum() == esc.sum():
         assert np.abs(F - Fo).max() <= 1e-9 * np.abs(Fo).max()
         assert np.linalg.norm(g - gbar @ dFo) <= PER_RAY_TOL * np.linalg.norm(gbar @ dFo)
@@ -207,5 +235,45 @@ def test_gradient_vs_finite_differences(rt, orc):
         fd_free[q] = gbar @ (Fp - Fm) / (2 * d)
     rel = np.abs(g - fd_frozen) / np.abs(fd_frozen)
     print("adjoint vs frozen-step FD", rel, "vs adaptive FD", np.abs(g - fd_free) / np.abs(fd_free), flush=True)
+    assert rel.max() <= 1e-6, rel
+    torch.cuda.synchronize()
+
+
+def test_gradient_vs_frozen_step_differences_on_workload_star(rt, orc):
+    """The GPU gradient on the adjoint workload's own star (flat, aligned, Goldreich-Julian
+    density, whose rays restart on the density's null surface) over its first 1000 rays,
+    against central differences of the oracle's frozen-step flux (its nominal accepted step
+    sequence replayed, the restart points and the r_max crossing re-located at p +- h):
+    agreement to 1e-6 relative per parameter.
+
+    Steps: 1e-6 relative for B0, P, R and m_a.  theta_m and M are zero on this star, so
+    their steps are absolute: 1e-7 rad, and 1e-9 Msun.  The flux bends sharply in M at
+    M = 0: the focusing term m_a^2 r_s/r of |k_a|^2 matches the free-streaming (m_a v0)^2
+    already at M ~ (v0/c)^2 r/(2 G Msun/c^2) ~ 7e-6 Msun near the resonance, so a central
+    difference over 1e-6 Msun still carries a 1% truncation error (the oracle's forward mode
+    shows it: 1.2e-2 at 1e-6, 1.2e-6 at 1e-8, 8e-9 at 1e-9); theta_m = 0 similarly needs
+    1e-7 rad (1.4e-6 at 1e-6 rad, 8e-9 at 1e-7)."""
+    import torch
+    cfg = W.CFG5
+    star, tol, obs, sigma = cfg["star"], cfg["tol"], W.observers(cfg["n_obs"]), cfg["sigma"]
+    n = 1000
+    gbar = np.random.default_rng(23).standard_normal(cfg["n_obs"])
+    print("adjoint vs frozen-step differences, workload star, n=1000", flush=True)
+    _, g, _, info = gpu_flux_grad(rt, star, tol, cfg["seed"], n, obs, sigma, gbar, cfg["ckpt_every"], 64)
+    _, hseq, nseq, stat = orc.flux_replay(star, tol, cfg["seed"], n, obs, sigma, True)
+    assert np.array_equal(stat, info[2])
+    steps = {"B0_G": 1e-6 * star["B0_G"], "P_s": 1e-6 * star["P_s"], "theta_m": 1e-7, "M_Msun": 1e-9,
+             "R_km": 1e-6 * star["R_km"], "m_a_eV": 1e-6 * star["m_a_eV"]}
+    fd = np.zeros(6)
+    for q, k in enumerate(rt.PARAMS):
+        d = steps[k]
+        sp, sm = dict(star), dict(star)
+        sp[k], sm[k] = star[k] + d, star[k] - d
+        fp = orc.flux_replay(sp, tol, cfg["seed"], n, obs, sigma, False, hseq, nseq, stat)[0]
+        fm = orc.flux_replay(sm, tol, cfg["seed"], n, obs, sigma, False, hseq, nseq, stat)[0]
+        fd[q] = gbar @ (fp - fm) / (2 * d)
+    rel = np.abs(g - fd) / np.abs(fd)
+    print("relative difference per parameter", dict(zip(rt.PARAMS, rel)), flush=True)
+    assert np.all(np.abs(fd) > 0)
     assert rel.max() <= 1e-6, rel
     torch.cuda.synchronize()

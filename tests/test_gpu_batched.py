@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import assert_trace_parity, oracle_conditioning
+from tests.parity import assert_trace_parity, oracle_conditioning, same_bin_mask
 
 pytestmark = pytest.mark.gpu
 
@@ -110,3 +110,96 @@ def test_batched_rejects_mixed_plasma(rt):
     stars[1]["plasma"] = W.PLASMA_ANISO
     with pytest.raises(rt.RtError, match="share plasma"):
         rt.Batch(stars, counts, 1, W.tol(), BINS)
+
+
+def test_full_size_scan_replay_equals_per_instance_and_oracle(rt, orc):
+    """The 256-instance scan at its full size (16 axion masses x 16 inclinations, 16,002,222
+    rays), run as the captured graph replay that is timed: every instance's rays equal one
+    launch of each entry point per instance (seeds and step counts bit for bit, final
+    records to 1e-13, maps to 1e-12 where the per-instance map is non-zero and zero where it
+    is zero, counts exactly); the first 1000 rays of 16 instances along the grid's diagonal
+    (every axion mass and every inclination once) against the oracle with the per-ray
+    tolerances; and the whole map of the smallest non-empty instance against the oracle's."""
+    import torch
+    stars, counts = W.batched_instances(W.CFG4["n_inst"], seed=W.CFG4["seed"])
+    tol, bins, seed = W.tol(), W.CFG4["bins"], W.CFG4["seed"]
+    print(f"full-size scan: {len(stars)} instances, {int(counts.sum())} rays", flush=True)
+    b = rt.Batch(stars, counts, seed, tol, bins)
+    g = b.capture()
+    b.fin.zero_()
+    b.ifin.zero_()
+    b.maps.zero_()
+    b.cnt.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    off = b.offsets
+    nmax = int(counts.max())
+    dev = torch.device("cuda")
+    rays = torch.empty((10, nmax), dtype=torch.float64, device=dev)
+    st = torch.empty(nmax, dtype=torch.int32, device=dev)
+    fin = torch.empty((rt.RT_NFIN, nmax), dtype=torch.float64, device=dev)
+    ifin = torch.empty((rt.RT_NIFIN, nmax), dtype=torch.int32, device=dev)
+    ws = rt.workspace(rt.OP_TRACE_FORWARD, nmax)
+    wsb = rt.workspace(rt.OP_BIN, nmax)
+    hist = torch.empty((1, bins["n_theta"], bins["n_psi"], bins["n_omega"]), dtype=torch.float64, device=dev)
+    cnt = torch.empty_like(hist)
+    over = torch.empty(2, dtype=torch.float64, device=dev)
+    worst_fin = 0.0
+    for k, s in enumerate(stars):
+        m = int(counts[k])
+        sl = slice(int(off[k]), int(off[k + 1]))
+        rr = rays.view(-1)[:10 * m].view(10, m)
+        ff = fin.view(-1)[:rt.RT_NFIN * m].view(rt.RT_NFIN, m)
+        ii = ifin.view(-1)[:rt.RT_NIFIN * m].view(rt.RT_NIFIN, m)
+        tt = st[:m]
+        rt.rt_sample_resonance(s, seed, m, instance=k, rays=rr, status=tt)
+        rt.rt_trace_forward(s, tol, rr, tt, ws=ws, fin=ff, ifin=ii)
+        rt.rt_bin_flux(ff, ii, rr[8], bins, ws=wsb, hist=hist, cnt=cnt, over=over)
+        assert torch.equal(b.status[sl], tt), k
+        assert torch.equal(b.rays[:, sl], rr), k
+        assert torch.equal(b.ifin[:, sl], ii), k
+        fb = b.fin[:, sl]
+        dif = (fb - ff).abs()
+        lim = 1e-13 * ff.abs()
+        assert bool((dif <= lim).all()), (k, float((dif - lim).max()))
+        worst_fin = max(worst_fin, float((dif / ff.abs().clamp_min(1e-300)).max()))
+        assert torch.equal(b.cnt[k], cnt[0]), k
+        nz = hist[0] > 0
+        assert bool((b.maps[k][nz] - hist[0][nz]).abs().le(1e-12 * hist[0][nz]).all()), k
+        assert float(b.maps[k][~nz].abs().sum()) == 0.0, k
+    print("replay = per-instance launches on all 256 instances; worst relative fin difference", worst_fin,
+          flush=True)
+
+    for k in range(0, len(stars), 17):
+        m = min(1000, int(counts[k]))
+        sl = slice(int(off[k]), int(off[k]) + m)
+        rays_o, st_o = orc.sample(stars[k], seed, m, instance=k)
+        assert np.array_equal(_np(b.status[sl]), st_o), k
+        fin_o, ifin_o = orc.trace_forward(stars[k], tol, rays_o, st_o)
+        sd, ch = oracle_conditioning(orc, stars[k], tol, rays_o, st_o, fin_o, ifin_o)
+        out = assert_trace_parity(_np(b.fin[:, sl]), _np(b.ifin[:, sl]), fin_o, ifin_o, sd, ch)
+        print(f"instance {k} (m_a {stars[k]['m_a_eV']:.3g}, theta_m {stars[k]['theta_m']:.2f}):", out, flush=True)
+    # the whole map of the smallest non-empty instance
+    k = min((q for q in range(len(stars)) if stars[q]["m_a_eV"] < 9e-5), key=lambda q: counts[q])
+    m = int(counts[k])
+    sl = slice(int(off[k]), int(off[k + 1]))
+    print(f"instance {k}: whole map vs oracle, {m} rays", flush=True)
+    rays_o, st_o = orc.sample(stars[k], seed, m, instance=k)
+    fin_o, ifin_o = orc.trace_forward(stars[k], tol, rays_o, st_o)
+    hist_o, cnt_o, _ = orc.bin_flux(fin_o, ifin_o, rays_o[8], bins)
+    fin_g, ifin_g = _np(b.fin[:, sl]), _np(b.ifin[:, sl])
+    same, kg, ko = same_bin_mask(fin_g, ifin_g, fin_o, ifin_o, bins)
+    moved = np.unique(np.concatenate([kg[~same], ko[~same]]))
+    moved = moved[(moved >= 0) & (moved < hist_o.size)]
+    excused = np.zeros(hist_o.size, dtype=bool)
+    excused[moved] = True
+    excused = excused.reshape(hist_o.shape)
+    hg = _np(b.maps[k])
+    ok = (~excused) & (hist_o > 0)
+    assert ok.sum() > 100
+    assert np.abs(hg[ok] / hist_o[ok] - 1).max() < 1e-6
+    assert np.array_equal(_np(b.cnt[k])[~excused], cnt_o[~excused])
+    assert excused.sum() <= 0.02 * (hist_o > 0).sum(), (excused.sum(), (hist_o > 0).sum())
+    esc_g, esc_o = ifin_g[2] == 1, ifin_o[2] == 1
+    assert abs(_np(b.rays[8, sl])[esc_g].sum() / rays_o[8][esc_o].sum() - 1) < 1e-9

@@ -58,7 +58,7 @@ def test_variant_traces_match_oracle(rt, orc, variant):
     sd, ch = oracle_conditioning(orc, s, cfg["tol"], rays_o, st_o, fin_o, ifin_o)
     out = assert_trace_parity(fin_g.cpu().numpy(), ifin_g.cpu().numpy(), fin_o, ifin_o, sd, ch)
     print(out, flush=True)
-    assert out["well"] >= 0.15 * out["escaped"]
+    assert out["well"] == out["escaped"]
 
 
 @pytest.mark.parametrize("variant", ["renorm", "thin", "gr_dipole"])
