@@ -186,6 +186,23 @@ int rt_bin_flux(const double* fin, const int32_t* ifin, const double* w, int64_t
                 const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over,
                 void* ws, size_t ws_bytes, void* stream);
 
+/* rt_bin_flux_noalloc -- rt_bin_flux for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * binning with no workspace argument.  Its scratch (every ray's bin key and tile-ordered
+ * list entry, the partition table) lives in one static device array of the library, sized
+ * for n <= RT_NOALLOC_BIN_MAX_RAYS rays (2^20 rays, 12.02 MiB), which every device the
+ * library runs on holds until the process ends.  Arguments, results and errors are those
+ * of rt_bin_flux; n above the maximum returns RT_EINVAL before anything is launched.  The
+ * first call on a device resolves the array's address there (hipGetSymbolAddress; not a
+ * stream operation) and keeps it; a failure returns RT_EHIP.  Every call on one device
+ * shares that array, which keeps the last call's contents: calls that overlap on a device
+ * (other streams, other threads) race, and the caller must serialise them.  Nothing in
+ * the array has to start at zero: each call writes every entry it later reads. */
+#define RT_NOALLOC_BIN_MAX_RAYS 1048576
+int rt_bin_flux_noalloc(const double* fin, const int32_t* ifin, const double* w, int64_t n, const rt_bins* bins,
+                        const int64_t* inst_offset, int32_t n_inst, double* hist, double* cnt, double* over,
+                        void* stream);
+
 /* rt_trace_backward -- trace the nx x ny parallel rays of an image plane backwards in the
  * worldline parameter (Sec. 2.1; Sec. 2.3 for the role of gravity) through every level
  * crossing k^gamma = k^a (sign change of G = g^{mu nu} k_mu k_nu + m_a^2, Sec. 3), until the

@@ -19,7 +19,7 @@ RT_NFIN, RT_NIFIN, RT_NEV = 16, 3, 10
 OP_TRACE_FORWARD, OP_TRACE_BACKWARD, OP_BIN, OP_BATCHED, OP_FLUX_GRAD, OP_BACKWARD_POWER = 1, 2, 3, 4, 5, 6
 FIN_FIELDS = ["x", "y", "z", "t", "kx", "ky", "kz", "kt", "theta", "phi", "psi", "omega", "H", "lam", "r", "h"]
 
-EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_trace_backward", "rt_trace_backward_rays",
+EXPORTS = ["rt_sample_resonance", "rt_trace_forward", "rt_bin_flux", "rt_bin_flux_noalloc", "rt_trace_backward", "rt_trace_backward_rays",
            "rt_backward_power", "rt_cyclotron_depth", "rt_trace_batched",
            "rt_batch_prepare", "rt_batch_workspace_size", "rt_flux_grad", "rt_flux_grad_workspace_size",
            "rt_workspace_size", "rt_timing", "rt_kernel_times", "rt_last_error", "rt_version"]
@@ -78,6 +78,7 @@ def lib():
                                        C.POINTER(RtSchedule), vp]
         L.rt_bin_flux.argtypes = [dp, ip, dp, C.c_int64, C.POINTER(RtBins), lp, C.c_int32, dp, dp, dp, vp,
                                   C.c_size_t, vp]
+        L.rt_bin_flux_noalloc.argtypes = [dp, ip, dp, C.c_int64, C.POINTER(RtBins), lp, C.c_int32, dp, dp, dp, vp]
         L.rt_trace_backward.argtypes = [sp, tp, C.POINTER(RtImage), C.c_int32, dp, ip, dp, ip, vp, C.c_size_t,
                                         C.POINTER(RtSchedule), vp]
         L.rt_trace_backward_rays.argtypes = [sp, tp, C.c_double, C.c_double, C.c_double, dp, dp, C.c_int64,
@@ -208,6 +209,28 @@ def rt_bin_flux(fin: torch.Tensor, ifin: torch.Tensor, w: torch.Tensor, bins: di
     _check(lib().rt_bin_flux(_ptr(fin), _ptr(ifin), _ptr(w.contiguous()), n, C.byref(b), _ptr(inst_offset),
                              n_inst, _ptr(hist), _ptr(cnt), _ptr(over), _ptr(ws), ws.numel(), _stream()),
            "rt_bin_flux")
+    if inst_offset is None:
+        return hist[0], cnt[0], over
+    return hist, cnt, over
+
+
+NOALLOC_BIN_MAX_RAYS = 1 << 20  # RT_NOALLOC_BIN_MAX_RAYS of rt.h
+
+
+def rt_bin_flux_noalloc(fin: torch.Tensor, ifin: torch.Tensor, w: torch.Tensor, bins: dict, inst_offset=None,
+                        n_inst: int = 1, hist=None, cnt=None, over=None):
+    """rt_bin_flux with the library's static device workspace (no workspace argument); pass
+    preallocated hist/cnt/over to allocate nothing on this side either."""
+    dev = _device()
+    n = fin.shape[1]
+    nmaps = n_inst if inst_offset is not None else 1
+    shape = (nmaps, bins["n_theta"], bins["n_psi"], bins["n_omega"])
+    hist = torch.empty(shape, dtype=torch.float64, device=dev) if hist is None else hist
+    cnt = torch.empty(shape, dtype=torch.float64, device=dev) if cnt is None else cnt
+    over = torch.empty(2, dtype=torch.float64, device=dev) if over is None else over
+    b = make_bins(bins)
+    _check(lib().rt_bin_flux_noalloc(_ptr(fin), _ptr(ifin), _ptr(w.contiguous()), n, C.byref(b), _ptr(inst_offset),
+                                     n_inst, _ptr(hist), _ptr(cnt), _ptr(over), _stream()), "rt_bin_flux_noalloc")
     if inst_offset is None:
         return hist[0], cnt[0], over
     return hist, cnt, over

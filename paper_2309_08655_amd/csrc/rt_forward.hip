@@ -7,6 +7,8 @@
 // (Hamiltonian, surface measure, focusing, conversion probability).
 #include "rt_common.hpp"
 
+#include <mutex>
+
 namespace rtd {
 
 // ----------------------------------------------------------------------------
@@ -720,4 +722,49 @@ extern "C" int rt_bin_flux(const double* fin, const int32_t* ifin, const double*
     if (n > 0 && (!ws || ws_bytes < need)) return fail(RT_ENOWS, "rt_bin_flux: workspace too small");
     if (n > 0 && (!fin || !ifin || !w)) return fail(RT_EINVAL, "rt_bin_flux: null input");
     return launch_bin(fin, ifin, w, n, bins, inst_offset, n_inst, hist, cnt, over, ws, (hipStream_t)stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// rt_bin_flux_noalloc: the binning scratch in a static device array (one per device,
+// resolved once per device and kept), for callers that cannot allocate
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+// bin_ws_bytes(RT_NOALLOC_BIN_MAX_RAYS): keys and list, bucket starts, a full partition table
+constexpr size_t NOALLOC_BIN_BYTES = 2 * al256(sizeof(int32_t) * (size_t)RT_NOALLOC_BIN_MAX_RAYS) +
+                                     al256(sizeof(int32_t) * (PART_BUCKETS + 1)) +
+                                     al256(sizeof(int32_t) * (size_t)PART_MAX_BLOCKS * PART_BUCKETS);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BIN_BYTES];
+
+// the array's address on the current device (host code never passes the array's name to
+// a kernel: on the host it stands for no device address)
+static void* scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" int rt_bin_flux_noalloc(const double* fin, const int32_t* ifin, const double* w, int64_t n,
+                                   const rt_bins* bins, const int64_t* inst_offset, int32_t n_inst, double* hist,
+                                   double* cnt, double* over, void* stream) {
+    clear_error();
+    if (n > (int64_t)RT_NOALLOC_BIN_MAX_RAYS)
+        return fail(RT_EINVAL, "rt_bin_flux_noalloc: n exceeds RT_NOALLOC_BIN_MAX_RAYS (1048576 rays)");
+    if (n >= 0 && bin_ws_bytes(n) > NOALLOC_BIN_BYTES)
+        return fail(RT_EINVAL, "rt_bin_flux_noalloc: static workspace smaller than the binning needs");
+    void* ws = scratch_on_current_device();
+    if (ws == nullptr) return fail(RT_EHIP, "rt_bin_flux_noalloc: no address for the static workspace on this device");
+    return rt_bin_flux(fin, ifin, w, n, bins, inst_offset, n_inst, hist, cnt, over, ws, NOALLOC_BIN_BYTES, stream);
 }
