@@ -41,7 +41,10 @@ typedef struct {
     int32_t flags;        /* ORC_FLAG_* bits: 1 no conversion on open field lines (r / sin^2 theta_mag >= c/Omega);
                              2 flat propagation (curved initial conditions, M = 0 in the tracing);
                              4 renormalised weights (P_ag = 1 times R_i); 8 thin surface w_p = m_a;
-                             16 the Schwarzschild vacuum dipole instead of the flat one */
+                             16 the Schwarzschild vacuum dipole instead of the flat one;
+                             32 finite magnetisation: the cold magnetised plasma response at the local
+                             electron cyclotron frequency (Sec. 4.1 eqs. (DisRel), (Larmor)) instead of
+                             its strong-field limit (anisotropic plasma, forward tracing) */
 } orc_star;
 
 typedef struct {
@@ -52,7 +55,7 @@ typedef struct {
 enum { ORC_OK = 0, ORC_ESCAPED = 1, ORC_HIT_STAR = 2, ORC_NO_RESONANCE = 3,
        ORC_MAX_STEPS = 4, ORC_STEP_UNDERFLOW = 5, ORC_NONFINITE = 6, ORC_EXCISED = 7 };
 enum { ORC_FLAG_EXCISE_OPEN = 1, ORC_FLAG_FLAT_PROPAGATION = 2, ORC_FLAG_RENORM_WEIGHTS = 4,
-       ORC_FLAG_THIN_SURFACE = 8, ORC_FLAG_GR_DIPOLE = 16 };
+       ORC_FLAG_THIN_SURFACE = 8, ORC_FLAG_GR_DIPOLE = 16, ORC_FLAG_FINITE_LARMOR = 32 };
 
 /* number of doubles per final record and their order */
 #define ORC_NFIN 16  /* y_f[8], theta, phi, psi, omega, H_f, lam_f, r_f, h_last */
@@ -74,6 +77,9 @@ int orc_sample(const orc_star* s, uint64_t seed, int32_t instance, int64_t first
                double* rays, int32_t* status, int nthreads);
 /* root of the resonance function along direction nhat at time t0 for axion direction khat */
 double orc_resonance_radius(const orc_star* s, const double nhat[3], const double khat[3], double t0);
+/* local photon frequency (units of w_inf) of the LO branch at covariant spatial k: eq.
+   (AnisotropicDisp) '+', or with ORC_FLAG_FINITE_LARMOR the root of eq. (DisRel) that
+   continues it */
 double orc_energy_aniso(const orc_star* s, const double x[3], double t, const double k[3]);
 
 /* forward trace: rays[10][n] as produced by orc_sample (w and r_c unused);

@@ -169,6 +169,7 @@ struct Inst {
     P n_inf;   // axion number density at infinity [eV^3]
     P k0;      // axion momentum at infinity [eV]
     P Period;  // [s]
+    P kL;      // (hbar e / (m_e c) / w_inf)^2 [G^-2]: (w_L / w_inf)^2 = kL |B|^2, w_L the cyclotron frequency
     double g_eV;   // coupling [eV^-1]
     double Btest;  // constant |B_perp| of the zero-variance test [G]
     int plasma, density, weights, kdir, speeds, flags;
@@ -206,6 +207,9 @@ static Inst<P> make_inst(const orc_star& s, const P p[6]) {
     }
     double rho_eV4 = s.rho_GeVcm3 * 1.0e9 * HBARC_EVCM * HBARC_EVCM * HBARC_EVCM;
     I.n_inf = rho_eV4 / ma;
+    // electron cyclotron energy per gauss, hbar e B / (m_e c) with e in statC and m_e c^2 in erg
+    const double hwc = HBARC_EVCM * E_STATC / (M_E_EV / EV_PER_ERG);  // [eV / G]
+    I.kL = (hwc / I.w_inf) * (hwc / I.w_inf);
     I.g_eV = s.g_agg_GeV * 1.0e-9;
     I.Btest = s.B_test_G;
     I.plasma = s.plasma; I.density = s.density; I.weights = s.weights; I.kdir = s.kdir;
@@ -355,6 +359,22 @@ static void ortho_components(const Inst<P>& I, const S x[3], const K k[3], S ko[
     for (int i = 0; i < 3; ++i) ko[i] = (k[i] - nk * n[i]) + rad * n[i];
 }
 
+// Finite magnetisation (Sec. 4.1): eq. (DisRel) in its rewritten form, with p^2 = k^2 + w^2
+// and w_L.p = w_L.k,
+//   H_L = k^2 [w^2 w_L^2 (k^2 + w_p^2) - w_p^2 (w_L.k)^2] - w^2 (w^2 - w_p^2)(k^2 + w_p^2)^2,
+// where k^2 = g^{mu nu} k_mu k_nu, w^2 the frequency in the static plasma frame and (w_L.k)^2 =
+// w_L^2 k_par^2.  By eq. (Larmor) w_L is the electron cyclotron frequency e|B|/(m_e c) (the
+// Levi-Civita contraction of the projected field tensor gives twice the field vector).  The
+// ray Hamiltonian is H_L / (w_L^2 w^2 k^2): same rays on H_L = 0 away from k^2 = 0, and as
+// w_L -> infinity it becomes eq. (StrongBHam), k^2 + (w^2 - k_par^2) w_p^2 / w^2, term for term.
+// Arguments: k2 = k^2, w2 = w^2, wp2 = w_p^2, kp2 = k_par^2, wL2 = w_L^2 (units of w_inf).
+template <class S>
+static S finite_larmor_h(const S& k2, const S& w2, const S& wp2, const S& kp2, const S& wL2) {
+    S q = k2 + wp2;
+    S HL = k2 * (w2 * wL2 * q - wp2 * wL2 * kp2) - w2 * (w2 - wp2) * q * q;
+    return HL / (wL2 * w2 * k2);
+}
+
 // Hamiltonian, eq. (StrongBHam): H = g^{mu nu} k_mu k_nu + (w^2 - k_par^2) w_p^2 / w^2,
 // with w^2 = -g^{tt} k_t^2 the frequency seen by the static plasma and k_par the
 // component of k along B in that frame.  The isotropic plasma, eq. (DispIsotropic),
@@ -380,6 +400,7 @@ static S hamiltonian_t(const Inst<P>& I, const S y[8]) {
     bfield_t(I, x, t, B);
     S Bmag = sqrt(dot3(B, B));
     S kpar = dot3(ko, B) / Bmag;
+    if (I.flags & ORC_FLAG_FINITE_LARMOR) return finite_larmor_h(gkk, w2, wp2, kpar * kpar, I.kL * dot3(B, B));
     return gkk + (w2 - kpar * kpar) * wp2 / w2;
 }
 
@@ -419,7 +440,25 @@ static S energy_t(const Inst<P>& I, const S x[3], const P& t, const K k[3]) {
     bfield_t(I, x, tt, B);
     S c = dot3(ko, B) / sqrt(dot3(B, B) * kk);
     S disc = kk * kk + wp2 * wp2 + 2.0 * kk * wp2 * (1.0 - 2.0 * c * c);
-    return sqrt(0.5 * (kk + wp2 + sqrt(disc)));
+    S E0 = sqrt(0.5 * (kk + wp2 + sqrt(disc)));
+    if (!(I.flags & ORC_FLAG_FINITE_LARMOR)) return E0;
+    // finite magnetisation: the root w^2 of H_L / (w_L^2 w^2 k^2) = 0 at this covariant k,
+    // k^2 = |k|^2 - w^2, that continues the strong-field LO root E0^2 (Newton's method from
+    // it; the tangents of S converge with the value to the implicit derivative)
+    using D1 = Dual<1, S>;
+    const S wL2 = I.kL * dot3(B, B);
+    const S kp2 = kk * c * c;
+    S W = E0 * E0;
+    int extra = -1;
+    for (int it = 0; it < 100 && extra != 0; ++it) {
+        D1 Wd = D1::var(W, 0);
+        D1 h = finite_larmor_h<D1>(D1(kk) - Wd, Wd, D1(wp2), D1(kp2), D1(wL2));
+        S step = h.v / h.d[0];
+        W = W - step;
+        if (extra > 0) --extra;
+        else if (std::fabs(val(step)) <= 1e-15 * std::fabs(val(W))) extra = 2;
+    }
+    return sqrt(W);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,6 +545,11 @@ static S resonance_F(const Inst<P>& I, const S x[3], const P& t0, const double k
     S B[3];
     bfield_t(I, x, tt, B);
     S cB = (khat[0] * B[0] + khat[1] * B[1] + khat[2] * B[2]) / sqrt(dot3(B, B));
+    if (I.flags & ORC_FLAG_FINITE_LARMOR) {
+        // the same matching in the finite-magnetisation Hamiltonian: w^2 H at k^2 = -m_a^2
+        S ma2 = S(0.0) + I.ma2;
+        return w2 * finite_larmor_h(S(0.0) - ma2, w2, wp2, ka2 * cB * cB, I.kL * dot3(B, B));
+    }
     return wp2 * (w2 - ka2 * cB * cB) - I.ma2 * w2;
 }
 

@@ -1110,9 +1110,11 @@ def test_forward_mode_flux_equals_traced_flux(orc):
     assert np.allclose(fray.sum(axis=0), F, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("plasma,density", [(W.PLASMA_ISO, W.DENSITY_SPHERICAL), (W.PLASMA_ANISO, W.DENSITY_SPHERICAL),
-                                            (W.PLASMA_ANISO, W.DENSITY_GJ)])
-def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma, density):
+@pytest.mark.parametrize("plasma,density,flags", [(W.PLASMA_ISO, W.DENSITY_SPHERICAL, 0),
+                                                  (W.PLASMA_ANISO, W.DENSITY_SPHERICAL, 0),
+                                                  (W.PLASMA_ANISO, W.DENSITY_GJ, 0),
+                                                  (W.PLASMA_ANISO, W.DENSITY_SPHERICAL, W.FLAG_FINITE_LARMOR)])
+def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma, density, flags):
     """dF/dp by forward mode against central differences of the flux recomputed with the
     nominal accepted step sequence replayed (the map the derivative is of), for all six
     parameters.  The map is smooth: the spherical test profile has no kink, and the GJ
@@ -1123,6 +1125,8 @@ def test_forward_mode_gradient_matches_frozen_step_differences(orc, plasma, dens
     s = W.star(M_Msun=1.4, theta_m=0.3, density=density, plasma=plasma, m_a_eV=1e-5,
                kdir=W.KDIR_OUTWARD)
     t = W.tol()
+    if flags & W.FLAG_FINITE_LARMOR:  # the weakly magnetised star, where the variant matters
+        s, t = W.WEAK_FIELD["star"], W.WEAK_FIELD["tol"]
     n, obs, sigma = 120, W.observers(32), 0.05
     F, dF = orc.flux_fwdmode(s, t, 0, n, obs, sigma)
     _, hseq, nseq, stat = orc.flux_replay(s, t, 0, n, obs, sigma, True)
@@ -1194,3 +1198,168 @@ def test_null_surface_cut_leaves_smooth_densities_alone(orc):
         b, bi = orc.trace_forward(s, W.tol(), rays, st, kinks=False)
         assert np.array_equal(ai, bi)
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- finite magnetisation
+def _hwc_per_gauss(orc):
+    # the oracle's cyclotron energy per gauss (pinned against CODATA to 1e-8 in
+    # test_cyclotron_constant_and_depth): the weakly magnetised checks below are sensitive
+    # to w_L at that level
+    return orc.constants()["hbar_omega_c_per_G"]
+
+
+def _appleton_hartree_n2(X, Y, cos_t, sign):
+    """Refractive index squared of the cold magnetised electron plasma (the Appleton-Hartree
+    formula of magnetoionic theory; e.g. Budden, The Propagation of Radio Waves, 1985, ch. 4),
+    X = w_p^2/w^2, Y = Omega_e/w (electron cyclotron frequency), theta between k and B."""
+    s2 = 1.0 - cos_t ** 2
+    root = math.sqrt(0.25 * Y ** 4 * s2 ** 2 + (1.0 - X) ** 2 * Y ** 2 * cos_t ** 2)
+    return 1.0 - X * (1.0 - X) / (1.0 - X - 0.5 * Y ** 2 * s2 + sign * root)
+
+
+def _covariant_from_static(x, ko, rs):
+    """covariant Cartesian k from its static orthonormal components (radial part / sqrt(A))"""
+    r = np.linalg.norm(x)
+    n = x / r
+    A = 1.0 - rs / r
+    kn = ko @ n
+    return ko + (kn / math.sqrt(A) - kn) * n
+
+
+@pytest.mark.parametrize("M", [0.0, 1.4])
+def test_finite_larmor_hamiltonian_vanishes_on_appleton_hartree_roots(orc, M):
+    """Sec. 4.1 eq. (DisRel) with eq. (Larmor), as the finite-magnetisation Hamiltonian
+    evaluates it, against textbook magnetoionic theory: at a photon whose static-frame
+    frequency w and momentum |k| = n w satisfy the Appleton-Hartree relation with Y = the
+    electron cyclotron frequency e|B|/(m_e c) over w, H = 0 on both modes (ordinary and
+    extraordinary), strongly and weakly magnetised (Y from 0.3 to 40).  A factor 2 in w_L
+    (the Larmor frequency e|B|/(2 m_e c)) fails this by orders of magnitude."""
+    rng = np.random.default_rng(17)
+    rs = 2 * orc.constants()["GMsun_km"] * M
+    hwc = _hwc_per_gauss(orc)
+    checked = weak = 0
+    for B0 in (3e4, 1e5, 1e6, 1e7):
+        s = W.star(M_Msun=M, theta_m=0.4, plasma=W.PLASMA_ANISO, density=W.DENSITY_SPHERICAL, m_a_eV=1e-5,
+                   B0_G=B0, multiplicity=1e14 / B0, flags=W.FLAG_FINITE_LARMOR)
+        v0 = s["v0_kms"] / orc.constants()["c_kms"]
+        winf = s["m_a_eV"] * math.sqrt(1 + v0 ** 2)
+        for _ in range(8):
+            x = rng.normal(size=3)
+            x = x / np.linalg.norm(x) * rng.uniform(30.0, 80.0)
+            t = rng.uniform(0.0, 3e5)
+            A = 1.0 - rs / np.linalg.norm(x)
+            w = rng.uniform(1.1, 2.0) / math.sqrt(A)  # static-frame frequency [w_inf]
+            X = orc.wp2(s, x, t) / w ** 2
+            B = orc.bfield(s, x, t)
+            Y = hwc * np.linalg.norm(B) / (winf * w)
+            khat = rng.normal(size=3)
+            khat /= np.linalg.norm(khat)
+            cos_t = float(khat @ B / np.linalg.norm(B))
+            for sign in (1.0, -1.0):
+                n2 = _appleton_hartree_n2(X, Y, cos_t, sign)
+                if not (0.0 < n2 < 0.999):  # propagating, and k^2 = (n^2 - 1) w^2 away from 0
+                    continue
+                k = _covariant_from_static(x, math.sqrt(n2) * w * khat, rs)
+                y = np.concatenate([x, [t], k, [-w * math.sqrt(A)]])
+                H = orc.hamiltonian(s, y)
+                assert abs(H) < 1e-11 * max(1.0, w * w), (B0, X, Y, cos_t, sign, H)
+                # the half-cyclotron (Larmor) frequency misses it by far more than the
+                # tolerance where the finite magnetisation matters (the term falls as 1/Y^2)
+                if Y < 5.0:
+                    sh = dict(s, B0_G=B0 / 2, multiplicity=2e14 / B0)
+                    assert abs(orc.hamiltonian(sh, y)) > 1e-9 * max(1.0, w * w), (B0, X, Y)
+                    weak += 1
+                checked += 1
+    assert checked >= 40 and weak >= 10, (checked, weak)
+
+
+def test_finite_larmor_strong_field_limit(orc):
+    """As w_L -> infinity the finite-magnetisation Hamiltonian becomes eq. (StrongBHam): at a
+    fixed state (plasma density held fixed), raising the field tenfold cuts H - H_strong by
+    exactly a hundredfold (the difference is -(w^2 - w_p^2)(k^2 + w_p^2)^2/(w_L^2 k^2))."""
+    rng = np.random.default_rng(23)
+    for _ in range(8):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(20.0, 60.0)
+        y = np.concatenate([x, [rng.uniform(0, 3e5)], rng.normal(size=3) * 0.4, [-1.0]])
+        d = []
+        for B0 in (1e6, 1e7, 1e8):
+            base = W.star(M_Msun=1.4, theta_m=0.3, plasma=W.PLASMA_ANISO, density=W.DENSITY_SPHERICAL,
+                          m_a_eV=1e-5, B0_G=B0, multiplicity=1e14 / B0)
+            H0 = orc.hamiltonian(base, y)
+            H1 = orc.hamiltonian(dict(base, flags=W.FLAG_FINITE_LARMOR), y)
+            d.append(H1 - H0)
+        assert d[0] != 0.0
+        assert abs(d[0] / d[1] / 100.0 - 1.0) < 1e-6 and abs(d[1] / d[2] / 100.0 - 1.0) < 1e-4, d
+
+
+def test_finite_larmor_gradient_matches_finite_differences(orc):
+    s = W.WEAK_FIELD["star"]
+    rng = np.random.default_rng(29)
+    rays, st = orc.sample(s, 0, 40)
+    for i in np.nonzero(st == 0)[0][:8]:
+        y = rays[:8, i] * np.concatenate([1 + 1e-3 * rng.normal(size=3), [1.0], 1 + 1e-3 * rng.normal(size=4)])
+        g = orc.grad_h(s, y)
+        for j in range(8):
+            h = 1e-6 * max(1.0, abs(y[j])) if j != 3 else 1e-2
+            yp, ym = y.copy(), y.copy()
+            yp[j] += h
+            ym[j] -= h
+            fd = (orc.hamiltonian(s, yp) - orc.hamiltonian(s, ym)) / (2 * h)
+            assert abs(fd - g[j]) <= 1e-6 * max(1e-6, abs(g[j])) + 1e-9, (j, fd, g[j])
+
+
+def test_finite_larmor_energy_and_seeds_on_shell(orc):
+    """The finite-magnetisation LO energy solves H = 0 at its covariant k and tends to the
+    strong-field energy of eq. (AnisotropicDisp) as 1/w_L^2; seeds lie on the axion's mass
+    shell (g^{mu nu} k k = -m_a^2) and on the photon's dispersion shell (H = 0), on a
+    resonance shifted from the strong-field one."""
+    s = W.WEAK_FIELD["star"]
+    strong = dict(s, flags=0)
+    rng = np.random.default_rng(31)
+    rs = 2 * orc.constants()["GMsun_km"] * s["M_Msun"]
+    for _ in range(8):
+        x = rng.normal(size=3)
+        x = x / np.linalg.norm(x) * rng.uniform(25.0, 60.0)
+        t = rng.uniform(0, 3e5)
+        k = rng.normal(size=3) * 0.6
+        E = orc.energy(s, x, t, k)
+        A = 1.0 - rs / np.linalg.norm(x)
+        assert abs(orc.hamiltonian(s, np.concatenate([x, [t], k, [-E * math.sqrt(A)]]))) < 1e-13
+        E0 = orc.energy(strong, x, t, k)
+        diffs = [orc.energy(dict(s, B0_G=b, multiplicity=1e14 / b), x, t, k) - E0 for b in (1e8, 1e9)]
+        assert diffs[0] != 0.0 and abs(diffs[0] / diffs[1] / 100.0 - 1.0) < 2e-3, diffs
+    rays, st = orc.sample(s, 0, 300)
+    rays0, st0 = orc.sample(strong, 0, 300)
+    ok = (st == 0) & (st0 == 0)
+    assert ok.sum() > 250
+    for i in np.nonzero(ok)[0]:
+        y = rays[:8, i]
+        r = np.linalg.norm(y[:3])
+        n = y[:3] / r
+        A = 1.0 - rs / r
+        gkk = -y[7] ** 2 / A + y[4:7] @ y[4:7] - (rs / r) * (n @ y[4:7]) ** 2
+        assert abs(gkk / (1.0 / (1.0 + (s["v0_kms"] / orc.constants()["c_kms"]) ** 2)) + 1.0) < 1e-12
+        assert abs(orc.hamiltonian(s, y)) < 1e-13
+    dr = np.abs(rays[9][ok] - rays0[9][ok])
+    assert dr.max() > 1e-8 and dr.max() < 1e-3 * rays0[9][ok].min()
+
+
+def test_finite_larmor_rays_conserve_h(orc):
+    """Along traced rays of the weak-field star (static for theta_m = 0: k_t conserved) H stays
+    at its seed value to the integration tolerance, and the finite magnetisation moves the
+    arrival directions away from the strong-field rays by far more than the 1e-9 rad parity
+    bar (the variant is not a no-op)."""
+    s = dict(W.WEAK_FIELD["star"], theta_m=0.0)
+    t = W.WEAK_FIELD["tol"]
+    rays, st = orc.sample(s, 0, 200)
+    fin, ifin = orc.trace_forward(s, t, rays, st)
+    esc = ifin[2] == W.STATUS_ESCAPED
+    assert esc.sum() > 150
+    assert np.all(fin[7][esc] == rays[7][esc])
+    assert np.abs(fin[12][esc]).max() < 1e-8
+    fin0, ifin0 = orc.trace_forward(dict(s, flags=0), t, rays, st)
+    both = esc & (ifin0[2] == W.STATUS_ESCAPED)
+    from tests.parity import angle_between
+    d = angle_between(fin[8], fin[9], fin0[8], fin0[9])[both]
+    assert np.median(d) > 1e-6, np.median(d)

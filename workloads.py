@@ -28,6 +28,7 @@ FLAG_FLAT_PROPAGATION = 2  # curved initial conditions, M = 0 in the tracing (Ap
 FLAG_RENORM_WEIGHTS = 4  # P_ag = 1 and the rescaling R_i of Sec. 6 eq. (reweight)
 FLAG_THIN_SURFACE = 8  # resonance on w_p = m_a instead of k^a = k^gamma (App. B)
 FLAG_GR_DIPOLE = 16  # the Schwarzschild vacuum dipole field instead of the flat one
+FLAG_FINITE_LARMOR = 32  # the cold magnetised plasma at finite cyclotron frequency (Sec. 4.1)
 
 STATUS_OK, STATUS_ESCAPED, STATUS_HIT_STAR, STATUS_NO_RESONANCE = 0, 1, 2, 3
 STATUS_MAX_STEPS, STATUS_STEP_UNDERFLOW, STATUS_NONFINITE, STATUS_EXCISED = 4, 5, 6, 7
@@ -99,6 +100,20 @@ MAGNETAR_MODELS = {
                m_a_eV=1e-4, multiplicity=lam, psi_twist=0.2, flags=FLAG_EXCISE_OPEN)
     for name, lam, B0 in (("M1", 1.0, 1.6e14), ("M2", 20.0, 1.6e14), ("M3", 1.0, 4e14), ("M4", 20.0, 4e14))
 }
+
+
+# A weakly magnetised test star for the finite-magnetisation Hamiltonian (Sec. 4.1 eq.
+# (DisRel)): the kink-free spherical density of the fiducial star (B0 multiplicity kept at
+# 1e14 G) under a 1e6 G dipole, so that the electron cyclotron frequency is 11-26 times the
+# photon frequency on the resonance (about 35 km) and still above twice it at r_max = 60 km,
+# where the finite-magnetisation terms change the rays at the 1e-3 level.  Everywhere on the
+# traced path the plasma stays magnetised (the two magnetoionic modes well separated).
+WEAK_FIELD = dict(
+    name="weak-field-finite-larmor",
+    star=star(M_Msun=1.4, theta_m=0.3, plasma=PLASMA_ANISO, density=DENSITY_SPHERICAL, m_a_eV=1e-5, B0_G=1e6,
+              multiplicity=1e8, kdir=KDIR_OUTWARD, flags=FLAG_FINITE_LARMOR),
+    tol=tol(r_max_km=60.0), seed=0,
+)
 
 
 def observers(n_obs: int = 32) -> np.ndarray:
