@@ -62,9 +62,21 @@ enum { RT_SPEEDS_MONO = 0, RT_SPEEDS_MAXWELL = 1 };
      G(x) = -3 [ln(1 - x) + x + x^2/2]/x^3), normalised to B0 at the surface pole: the field
      direction enters the LO Hamiltonian, its strength the conversion weights and the
      cyclotron depth; the Goldreich-Julian density keeps its printed form.  Everywhere
-     (forward, backward, batched, adjoint). */
+     (forward, backward, batched, adjoint);
+   RT_FLAG_FINITE_LARMOR replaces the strong-field Hamiltonian (Sec. 4.1 eq. (StrongBHam)) by
+     the cold magnetised plasma at finite magnetisation, eq. (DisRel) with eq. (Larmor):
+     H = H_L / (w_L^2 w^2 k^2) = H_strong - (w^2 - w_p^2)(k^2 + w_p^2)^2 / (w_L^2 k^2), with
+     k^2 = g^{mu nu} k_mu k_nu and w_L = e|B|/(m_e c) the electron cyclotron frequency of the
+     dipole field; the resonance (photon on its shell at the axion's momentum), the seeds'
+     momenta, the energy gradient of the weights and the traced rays follow it, while the
+     conversion probability keeps eq. (CPAnisoCurved).  Anisotropic plasma only; seeding,
+     forward tracing, binning and rt_flux_grad; not with RT_FLAG_THIN_SURFACE, the batched
+     launch or the backward entry points (RT_EUNSUPPORTED).  The rays are meaningful where
+     the plasma stays magnetised (w_L well above the plasma's share of the dispersion:
+     the two magnetoionic modes do not meet), as everywhere inside r_max for the paper's
+     stars. */
 enum { RT_FLAG_EXCISE_OPEN = 1, RT_FLAG_FLAT_PROPAGATION = 2, RT_FLAG_RENORM_WEIGHTS = 4,
-       RT_FLAG_THIN_SURFACE = 8, RT_FLAG_GR_DIPOLE = 16 };
+       RT_FLAG_THIN_SURFACE = 8, RT_FLAG_GR_DIPOLE = 16, RT_FLAG_FINITE_LARMOR = 32 };
 
 /* Star, plasma and axion parameters (Sec. 5 fiducial set; Sec. 6 magnetar models). */
 typedef struct rt_star {

@@ -48,7 +48,7 @@ static InstT<FC> inst(int plasma, int density, bool oblique) {
     I.rs = FC(4.13); I.R = FC(10.0); I.Om = FC(2e-5); I.cm = FC(oblique ? 0.95 : 1.0);
     I.sm = FC(oblique ? 0.3 : 0.0); I.Cwp = FC(1.0); I.R3 = FC(1000.0); I.ma2 = FC(0.99);
     I.plasma = plasma; I.density = density; I.oblique = oblique ? 1 : 0;
-    I.gr_dipole = 0; I.bnorm = FC(1.0);
+    I.gr_dipole = 0; I.bnorm = FC(1.0); I.larmor = 0; I.kL = FC(0.0);
     return I;
 }
 
@@ -76,10 +76,10 @@ int main() {
                 // adjoint: one stage vector-Jacobian product (dual-number Hessian-vector product
                 // with 3 parameter-channel tangents plus the vacuum part) and the reverse sweep
                 // through the six stages of a step
-                FC v[8], vy[8], vc[4], Ys[48], Kb[48], yb[8], tc[4];
+                FC v[8], vy[8], vc[5], Ys[48], Kb[48], yb[8], tc[5];
                 for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); }
                 for (int d = 0; d < 48; ++d) { Ys[d] = y[d % 8]; Kb[d] = FC(0.01 * d); }
-                for (int q = 0; q < 4; ++q) tc[q] = FC(0.0);
+                for (int q = 0; q < 5; ++q) tc[q] = FC(0.0);
                 g_flops = 0;
                 rhs_vjp<FC>(I, y, v, vy, vc);
                 long long fvjp = g_flops;

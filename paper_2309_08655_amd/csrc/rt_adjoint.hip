@@ -93,7 +93,9 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 }
 
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
-// cost-ordered work list; checkpoints, per-ray counters and the flux
+// cost-ordered work list; checkpoints, per-ray counters and the flux.  LARMOR fixes the
+// finite-magnetisation switch at compile time (the strong-field kernel carries none of it).
+template <bool LARMOR>
 __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
                                                       const double* __restrict__ h0s, int C, int Kc,
@@ -102,6 +104,7 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
                                                       const double* __restrict__ obs, int n_obs, double sigma,
                                                       double* __restrict__ facc) {
     __shared__ double sh_f[MAX_OBS];
+    I.larmor = LARMOR ? 1 : 0;
     for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) sh_f[q] = 0.0;
     __syncthreads();
     const int lane = __lane_id();
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
                     j = list[qq];
                     double y0[8];
                     for (int d = 0; d < 8; ++d) y0[d] = rays[d * n + j];
-                    adj_ray_start(I, y0, h0s[j], R, store);
+                    adj_ray_start<LARMOR>(I, y0, h0s[j], R, store);
                     active = true;
                 }
             }
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
         }
         if (!active) continue;
         double yf[8], th = 0.0;
-        const int status = adj_ray_step(I, tol, C, Kc, R, store, yf, &th);
+        const int status = adj_ray_step<LARMOR>(I, tol, C, Kc, R, store, yf, &th);
         if (status != ST_OK) {
             ifin[j] = R.nacc;
             ifin[n + j] = R.nrej;
@@ -215,7 +218,8 @@ __global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int 
     }
 }
 
-// reverse pass: one escaped ray per lane, handed out by a lane atomic
+// reverse pass: one escaped ray per lane, handed out by a lane atomic (LARMOR as above)
+template <bool LARMOR>
 __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P, StarFixed fx, TolC tol,
                                                      uint64_t seed, int64_t n, const double* __restrict__ rays,
                                                      const int32_t* __restrict__ ifin,
@@ -229,6 +233,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
                                                      double* __restrict__ grad_rays, double inv_n, int Kc,
                                                      unsigned long long seal) {
     if (rctr->pad[0] != seal) return;  // no forward phase of these arguments in this workspace
+    I.larmor = LARMOR ? 1 : 0;
     const int64_t lane_g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     AdjParams A;
     make_adj_params(P.p, fx, A);
@@ -256,7 +261,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *gjs = ckpt[((int64_t)s * 11 + 10) * n + j];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        const int miss = adj_reverse_ray(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, obs,
+        const int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, obs,
                                          gbar, n_obs, sigma, pb);
         if (miss) {
             // the recompute did not reproduce the forward pass: no gradient for this ray
@@ -326,11 +331,17 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         rc = order_work_list(W.fw, n, st);
         if (rc) return rc;
         const rt_schedule sc = resolve_schedule(nullptr);
-        const int grid = persistent_grid(sc, (const void*)adj_fwd_kernel, 256);
+        const void* fk = I.larmor ? (const void*)adj_fwd_kernel<true> : (const void*)adj_fwd_kernel<false>;
+        const int grid = persistent_grid(sc, fk, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
-        hipLaunchKernelGGL(adj_fwd_kernel, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
-                           W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma,
-                           W.facc);
+        if (I.larmor)
+            hipLaunchKernelGGL(adj_fwd_kernel<true>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
+                               W.rays, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
+                               sigma, W.facc);
+        else
+            hipLaunchKernelGGL(adj_fwd_kernel<false>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
+                               W.rays, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
+                               sigma, W.facc);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");
         if (rc) return rc;
@@ -361,9 +372,14 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
     StarFixed fx = star_fixed(*star);
     timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
-    hipLaunchKernelGGL(adj_rev_kernel, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays, W.ifin,
-                       W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs, sigma, gbar,
-                       W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    if (I.larmor)
+        hipLaunchKernelGGL(adj_rev_kernel<true>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
+                           W.ifin, W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
+                           sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    else
+        hipLaunchKernelGGL(adj_rev_kernel<false>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
+                           W.ifin, W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
+                           sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
     timing_end(st);
     rc = check_launch("adj_rev_kernel");
     if (rc) return rc;

@@ -43,18 +43,30 @@ typedef gdual<14> D14;
 // sincos per evaluation.
 // gjs: the piece of the GJ density being integrated (0 for the other densities; see
 // plasma_eval); the adjoint follows forward tracing, which cuts steps at the null surface.
+// FL = false: the star is known to take the strong-field Hamiltonian, and a local copy of the
+// instance says so at compile time (its finite-magnetisation terms fold away even where the
+// instance itself sits in memory behind the reverse sweep's calls).
+template <bool FL = true>
 RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, const AxisRef& ref, double gjs = 0.0) {
-    rhs(I, y, f, 1.0, &ref, gjs);
+    if constexpr (FL) {
+        rhs(I, y, f, 1.0, &ref, gjs);
+    } else {
+        InstT<double> J = I;
+        J.larmor = 0;
+        rhs(J, y, f, 1.0, &ref, gjs);
+    }
 }
+template <bool FL = true>
 RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, double gjs = 0.0) {
     const AxisRef ref = axis_ref_at(I, y[3]);
-    rhs(I, y, f, 1.0, &ref, gjs);
+    adj_rhs<FL>(I, y, f, ref, gjs);
 }
 
 // One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
 // the last = f(ynew)), ynew and, if Ys != nullptr, the stage states Ys[0..47]
 // (Ys[0..7] = y).  Applies the step-size controller to *h and *facmax and returns
 // 1 if the step is accepted.
+template <bool FL = true>
 RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
                       double* h, double* facmax, double* Ys, double gjs = 0.0) {
     using namespace dp5;
@@ -85,9 +97,9 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
             for (int d = 0; d < 8; ++d) ynew[d] = tmp[d];
         }
         if (s < 5)
-            adj_rhs(I, tmp, K + (s + 1) * 8, ref0, gjs);
+            adj_rhs<FL>(I, tmp, K + (s + 1) * 8, ref0, gjs);
         else
-            adj_rhs(I, tmp, K + (s + 1) * 8, gjs);
+            adj_rhs<FL>(I, tmp, K + (s + 1) * 8, gjs);
     }
     const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
     double acc = 0.0;
@@ -138,6 +150,7 @@ RT_HD double adj_start_piece(const InstT<double>& I, const double* y) {
 // Moves an accepted step's start y (stages K, size h, end ynew) to the next step's start:
 // ynew, or for a crossing at thk <= 1 the point there on the continuous extension, where
 // the ray goes on along the other piece (*gjs flips) with a fresh derivative in K[0..7].
+template <bool FL = true>
 RT_HD void adj_advance(const InstT<double>& I, double* y, double* K, const double* ynew, double h, double thk,
                        double* gjs) {
     using namespace dp5;
@@ -151,7 +164,7 @@ RT_HD void adj_advance(const InstT<double>& I, double* y, double* K, const doubl
             y[i] = dense_value(y[i], ydiff, r3, r4, r5, thk);
         }
         *gjs = -*gjs;
-        adj_rhs(I, y, K, *gjs);
+        adj_rhs<FL>(I, y, K, *gjs);
     } else {
         for (int d = 0; d < 8; ++d) {
             y[d] = ynew[d];
@@ -240,11 +253,11 @@ struct AdjRay {
     int nacc, nrej, nseg;
 };
 
-template <class Store>
+template <bool FL = true, class Store>
 RT_HD void adj_ray_start(const InstT<double>& I, const double y0[8], double h0, AdjRay& R, Store&& store) {
     for (int d = 0; d < 8; ++d) R.y[d] = y0[d];
     R.gjs = adj_start_piece(I, R.y);
-    adj_rhs(I, R.y, R.K, R.gjs);
+    adj_rhs<FL>(I, R.y, R.K, R.gjs);
     R.h = h0;
     R.facmax = 10.0;
     R.lam = 0.0;
@@ -256,12 +269,12 @@ RT_HD void adj_ray_start(const InstT<double>& I, const double y0[8], double h0, 
 
 // One attempt; returns ST_OK while the ray continues.  On ST_ESCAPED, yf is the
 // state at r = r_max on the last step's continuous extension and *theta its location.
-template <class Store>
+template <bool FL = true, class Store>
 RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, AdjRay& R, Store&& store, double yf[8],
                        double* theta) {
     double ynew[8];
     const double hused = R.h;
-    if (!adj_attempt(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr, R.gjs)) {
+    if (!adj_attempt<FL>(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr, R.gjs)) {
         ++R.nrej;
         return (fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam))) ? ST_OK : ST_STEP_UNDERFLOW;
     }
@@ -285,7 +298,7 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
             return ST_ESCAPED;
         }
     }
-    adj_advance(I, R.y, R.K, ynew, hused, thk, &R.gjs);
+    adj_advance<FL>(I, R.y, R.K, ynew, hused, thk, &R.gjs);
     R.lam += (thk <= 1.0) ? thk * hused : hused;
     if (!finite_ok) return ST_NONFINITE;
     if (rnew <= value(I.R)) return ST_HIT_STAR;
@@ -367,7 +380,9 @@ RT_HD_NOINLINE double observable_grad(const AdjParams& A, const double* yf, cons
 // End of a ray's sweep: the seed's sensitivities (root, momentum and weight in
 // 6-tangent dual numbers) contracted with the adjoint of y_0 and with G(y_f), and the
 // stage products' parameter channels mapped to the parameters,
-//   M = d(rs, Om, theta_m, log(Cwp R^3))/dp   (theta_m enters only through its own channel).
+//   M = d(rs, Om, theta_m, log(Cwp R^3), log(kL))/dp   (theta_m enters only through its own
+//   channel; kL, the finite magnetisation's cyclotron coefficient, carries B0, R and m_a).
+template <bool FL = true>
 RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t j, const double* yb, double wG,
                                       const double* tc, double* pb) {
     D6 p6[6];
@@ -377,6 +392,7 @@ RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t
     }
     InstT<D6> I6 = make_inst_t<D6>(p6, A.fx);
     I6.oblique = 1;
+    if constexpr (!FL) I6.larmor = 0;
     const SeedT<D6> C6 = make_seed_t<D6>(p6, A.fx);
     D6 sd[10];
     seed_ray<D6>(I6, C6, seed, 0, j, sd);
@@ -386,16 +402,58 @@ RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t
         for (int d = 0; d < 8; ++d) a += yb[d] * sd[d].d[q];
         a += tc[0] * I6.rs.d[q] + tc[1] * I6.Om.d[q] + ((q == 2) ? tc[2] : 0.0);
         if (cw != 0.0 && r3 != 0.0) a += tc[3] * (I6.Cwp.d[q] / cw + I6.R3.d[q] / r3);
+        if (I6.larmor && I6.kL.v != 0.0) a += tc[4] * (I6.kL.d[q] / I6.kL.v);
         pb[q] += a;
     }
 }
 
-// v^T df/dy (vy) and the four channels vc of v^T df/dp at the state Y (S = double;
-// generic for the host operation counter)
+// Finite magnetisation (Sec. 4.1 eq. (DisRel)): H is no longer linear in the plasma
+// coefficient and depends on the cyclotron coefficient kL (which carries B0, R^6 and
+// 1/w_inf^2), so both become tangents: slots 1..3 rs, Om, theta_m as below, slot 4 log(Cwp)
+// (which moves P exactly as log(Cwp R^3) does) and slot 5 log(kL); vc[3] and vc[4] are
+// those channels.
+template <class S = double>
+RT_HD_NOINLINE void rhs_vjp_larmor(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
+    typedef gdual<6, S> DS;
+    InstT<DS> J = lift_inst<DS>(I);
+    J.rs.d[1] = S(1.0);
+    J.Om.d[2] = S(1.0);
+    J.cm.d[3] = S(0.0) - I.sm;
+    J.sm.d[3] = I.cm;
+    J.Cwp.d[4] = I.Cwp;
+    J.kL.d[5] = I.kL;
+    DS yd[8], fd[8];
+    for (int i = 0; i < 4; ++i) {
+        yd[i] = DS(Y[i]);
+        yd[i].d[0] = S(0.0) - v[4 + i];
+        yd[4 + i] = DS(Y[4 + i]);
+        yd[4 + i].d[0] = v[i];
+    }
+    rhs(J, yd, fd, 1.0, nullptr, gjs);
+    for (int i = 0; i < 4; ++i) {
+        vy[i] = S(0.0) - fd[4 + i].d[0];
+        vy[4 + i] = fd[i].d[0];
+    }
+    for (int c = 0; c < 5; ++c) {
+        S a = v[0] * fd[0].d[1 + c];
+        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + c];
+        vc[c] = a;
+    }
+}
+
+// v^T df/dy (vy) and the channels vc[0..4] of v^T df/dp at the state Y (S = double;
+// generic for the host operation counter); vc[4] (the cyclotron coefficient) is zero for
+// the strong-field Hamiltonian
 template <class S = double>
 RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
+    if (I.larmor) {
+        rhs_vjp_larmor<S>(I, Y, v, vy, vc, gjs);
+        return;
+    }
     typedef gdual<4, S> DS;
-    const VjpInst<S> V = make_vjp_inst<S>(I);
+    VjpInst<S> V = make_vjp_inst<S>(I);
+    V.I4.larmor = 0;  // the strong-field Hamiltonian from here on (its terms fold away)
+    V.Ivac.larmor = 0;
     DS yd[8], fd[8];
     for (int i = 0; i < 4; ++i) {
         yd[i] = DS(Y[i]);
@@ -420,6 +478,7 @@ RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S*
     S a = v[0] * (fd[0].v - fv[0]);
     for (int i = 1; i < 8; ++i) a = a + v[i] * (fd[i].v - fv[i]);
     vc[3] = a;
+    vc[4] = S(0.0);
 }
 
 // Adjoint of the six stages of a step: on entry Kb[8 i .. 8 i + 7] holds the
@@ -434,10 +493,10 @@ RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* 
                             {a41, a42, a43, 0, 0},
                             {a51, a52, a53, a54, 0},
                             {a61, a62, a63, a64, a65}};
-    S vy[8], vc[4];
+    S vy[8], vc[5];
     for (int i = 5; i >= 0; --i) {
         rhs_vjp<S>(I, Ys + i * 8, Kb + i * 8, vy, vc, gjs);
-        for (int c = 0; c < 4; ++c) tc[c] = tc[c] + vc[c];
+        for (int c = 0; c < 5; ++c) tc[c] = tc[c] + vc[c];
         for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
         for (int jj = 0; jj < i; ++jj) {
             if (A[i][jj] == 0.0) continue;
@@ -470,10 +529,10 @@ RT_HD_NOINLINE void dense_adjoint(const InstT<double>& I, const double* yn, cons
         K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
     }
     // K7 = f(ynew)
-    double vy[8], vc[4];
+    double vy[8], vc[5];
     rhs_vjp<double>(I, ynew, K7b, vy, vc, gjs);
     for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
-    for (int c = 0; c < 4; ++c) tc[c] += vc[c];
+    for (int c = 0; c < 5; ++c) tc[c] += vc[c];
     // ynew = y + h sum_i b_i K_i
     for (int d = 0; d < 8; ++d) {
         yb[d] += ynb[d];
@@ -510,12 +569,12 @@ RT_HD void dense_point_deriv(const double* yn, const double* K, const double* yn
 // is the replay buffer (C steps x 11 values: y, h, the null-surface crossing thk (2: none)
 // and the piece gjs of the step).  Adds d(w G(y_f))/dp to pb.  Returns the number of
 // steps or checkpoints the recompute could not reproduce (0 when all is well).
-template <class Load, class Replay>
+template <bool FL = true, class Load, class Replay>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
                           int nseg, double th, double w, int C, Load&& load, Replay&& rb, const double* obs,
                           const double* gbar, int n_obs, double sigma, double pb[6]) {
     using namespace dp5;
-    double tc[4] = {0.0, 0.0, 0.0, 0.0};  // parameter channels of the stage products
+    double tc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // parameter channels of the stage products
     double yb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double wG = 0.0;
     int missing = 0;
@@ -525,11 +584,11 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         load(s, y, &h, &facmax, &gjs);
         const int first = s * C;
         const int count = (S - first < C) ? (S - first) : C;
-        adj_rhs(I, y, K, gjs);
+        adj_rhs<FL>(I, y, K, gjs);
         int stored = 0;
         for (int guard = 0; stored < count && guard < 64 * C; ++guard) {
             const double hused = h;
-            if (!adj_attempt(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr, gjs)) continue;
+            if (!adj_attempt<FL>(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr, gjs)) continue;
             // the last step ends at r_max (its own crossing test does not matter)
             const double thk = (first + stored == S - 1) ? 2.0 : adj_null_crossing(I, y, K, ynew, hused, gjs);
             for (int d = 0; d < 8; ++d) rb(stored, d) = y[d];
@@ -537,7 +596,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             rb(stored, 9) = thk;
             rb(stored, 10) = gjs;
             ++stored;
-            adj_advance(I, y, K, ynew, hused, thk, &gjs);
+            adj_advance<FL>(I, y, K, ynew, hused, thk, &gjs);
         }
         missing += count - stored;
         if (stored == count && s + 1 < nseg) {
@@ -554,8 +613,8 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
             const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
             double hdummy = hn, fdummy = 10.0;
-            adj_rhs(I, yn, K, gn);
-            adj_attempt(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys, gn);
+            adj_rhs<FL>(I, yn, K, gn);
+            adj_attempt<FL>(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys, gn);
             if (first + idx == S - 1 || thk <= 1.0) {
                 // the step ends inside, at E(theta): y_f at r(E) = r_max, or the restart
                 // point on the null surface g(E) = 0.  The adjoint of E(theta) loses its
@@ -600,7 +659,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels
-    seed_and_channels(A, seed, j, yb, wG, tc, pb);
+    seed_and_channels<FL>(A, seed, j, yb, wG, tc, pb);
     return missing;
 }
 

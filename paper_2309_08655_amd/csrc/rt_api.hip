@@ -43,8 +43,16 @@ bool validate_star(const rt_star* s) {
         return false;
     }
     if (s->plasma < 0 || s->plasma > 1 || s->density < 0 || s->density > 3 || s->weights < 0 || s->weights > 2 ||
-        s->kdir < 0 || s->kdir > 1 || s->speeds < 0 || s->speeds > 1 || (s->flags & ~31) != 0) {
+        s->kdir < 0 || s->kdir > 1 || s->speeds < 0 || s->speeds > 1 || (s->flags & ~63) != 0) {
         set_error("rt_star: enumeration out of range");
+        return false;
+    }
+    if ((s->flags & RT_FLAG_FINITE_LARMOR) && s->plasma != RT_PLASMA_ANISO) {
+        set_error("rt_star: finite magnetisation needs the anisotropic (magnetised) plasma");
+        return false;
+    }
+    if ((s->flags & RT_FLAG_FINITE_LARMOR) && (s->flags & RT_FLAG_THIN_SURFACE)) {
+        set_error("rt_star: finite magnetisation is not combined with the thin-surface variant (unsupported)");
         return false;
     }
     return true;

@@ -136,6 +136,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
         I.density = ((SPEC - 1) >> 1) & 3;
         I.oblique = ((SPEC - 1) >> 3) & 1;
         I.gr_dipole = 0;
+        I.larmor = 0;
     }
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -411,7 +412,7 @@ extern "C" int rt_trace_backward(const rt_star* star, const rt_tol* tol, const r
     if (image->D_km <= image->half_width_km * 2.0 || image->D_km <= star->R_km)
         return fail(RT_EINVAL, "rt_trace_backward: image plane must lie far outside the star");
     if (K < 0) return fail(RT_EINVAL, "rt_trace_backward: negative K");
-    if (star->flags & RT_FLAG_FLAT_PROPAGATION)
+    if (star->flags & (RT_FLAG_FLAT_PROPAGATION | RT_FLAG_FINITE_LARMOR))
         return fail(RT_EUNSUPPORTED, "rt_trace_backward: the approximation variants are forward only");
     int64_t n = (int64_t)image->nx * image->ny;
     if (n > INT32_MAX) return fail(RT_EINVAL, "rt_trace_backward: too many pixels");
@@ -439,7 +440,7 @@ extern "C" int rt_trace_backward_rays(const rt_star* star, const rt_tol* tol, do
         return fail(RT_EINVAL, "rt_trace_backward_rays: invalid image plane");
     if (D_km <= star->R_km) return fail(RT_EINVAL, "rt_trace_backward_rays: image plane must lie outside the star");
     if (K < 0) return fail(RT_EINVAL, "rt_trace_backward_rays: negative K");
-    if (star->flags & RT_FLAG_FLAT_PROPAGATION)
+    if (star->flags & (RT_FLAG_FLAT_PROPAGATION | RT_FLAG_FINITE_LARMOR))
         return fail(RT_EUNSUPPORTED, "rt_trace_backward_rays: the approximation variants are forward only");
     if (n < 0 || n > INT32_MAX) return fail(RT_EINVAL, "rt_trace_backward_rays: invalid ray count");
     if (n > 0 && (!b1 || !b2 || !nev || !fin || !ifin || (K > 0 && !ev)))
@@ -464,7 +465,8 @@ extern "C" int rt_backward_power(const rt_star* star, const double* ev, const in
     if (!validate_star(star)) return RT_EINVAL;
     if (star->speeds != RT_SPEEDS_MONO)
         return fail(RT_EUNSUPPORTED, "rt_backward_power: the event weights assume monochromatic axions");
-    if (star->flags & (RT_FLAG_FLAT_PROPAGATION | RT_FLAG_RENORM_WEIGHTS | RT_FLAG_THIN_SURFACE))
+    if (star->flags & (RT_FLAG_FLAT_PROPAGATION | RT_FLAG_RENORM_WEIGHTS | RT_FLAG_THIN_SURFACE |
+                       RT_FLAG_FINITE_LARMOR))
         return fail(RT_EUNSUPPORTED, "rt_backward_power: the approximation variants are forward only");
     if (n < 0 || K < 0) return fail(RT_EINVAL, "rt_backward_power: negative size");
     if (!std::isfinite(Lc_max_km)) return fail(RT_EINVAL, "rt_backward_power: non-finite cutoff");

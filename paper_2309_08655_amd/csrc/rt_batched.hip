@@ -146,6 +146,8 @@ extern "C" int rt_batch_prepare(const rt_star* stars, int32_t n_inst, const int6
             return fail(RT_EINVAL, "rt_batch_prepare: instances must share plasma, density, weights and kdir");
         if (stars[k].flags & RT_FLAG_FLAT_PROPAGATION)
             return fail(RT_EUNSUPPORTED, "rt_batch_prepare: flat-propagation variant");
+        if (stars[k].flags & RT_FLAG_FINITE_LARMOR)
+            return fail(RT_EUNSUPPORTED, "rt_batch_prepare: finite-magnetisation variant");
     }
     int64_t N = ray_offset[n_inst];
     if (N > INT32_MAX) return fail(RT_EINVAL, "rt_batch_prepare: more than 2^31 - 1 rays");

@@ -213,7 +213,7 @@ enum { SP_MONO = 0, SP_MAXWELL = 1 };
 enum { ST_OK = 0, ST_ESCAPED = 1, ST_HIT_STAR = 2, ST_NO_RESONANCE = 3, ST_MAX_STEPS = 4,
        ST_STEP_UNDERFLOW = 5, ST_NONFINITE = 6, ST_EXCISED = 7 };
 enum { FLAG_EXCISE_OPEN = 1, FLAG_FLAT_PROPAGATION = 2, FLAG_RENORM_WEIGHTS = 4, FLAG_THIN_SURFACE = 8,
-       FLAG_GR_DIPOLE = 16 };
+       FLAG_GR_DIPOLE = 16, FLAG_FINITE_LARMOR = 32 };
 
 template <class T>
 struct InstT {
@@ -228,6 +228,8 @@ struct InstT {
     int oblique;    // sm != 0
     int gr_dipole;  // the Schwarzschild vacuum dipole instead of the flat one
     T bnorm;        // field-strength factor: 1, or 1 / G(r_s/R) for the GR dipole (B0 at the pole)
+    int larmor;     // finite magnetisation: the plasma response at the cyclotron frequency w_L
+    T kL;           // (w_L / w_inf)^2 = kL r^-6 F^2 (1 + c mu^2): (hbar e B0 bnorm / (2 m_e c w_inf))^2 R^6
 };
 
 // ----------------------------------------------------------------------------
@@ -240,7 +242,7 @@ struct InstT {
 // ----------------------------------------------------------------------------
 template <class T>
 struct DipoleShape {
-    T g, c, F, dg, dc;
+    T g, c, F, dg, dc, dF;  // dg, dc, dF: radial derivatives
 };
 
 template <class T>
@@ -270,7 +272,7 @@ template <class T>
 RT_HD DipoleShape<T> dipole_shape(const InstT<T>& I, const T& ir) {
     DipoleShape<T> d;
     if (!I.gr_dipole) {
-        d.g = T(3.0); d.c = T(3.0); d.F = T(1.0); d.dg = T(0.0); d.dc = T(0.0);
+        d.g = T(3.0); d.c = T(3.0); d.F = T(1.0); d.dg = T(0.0); d.dc = T(0.0); d.dF = T(0.0);
         return d;
     }
     const T x = I.rs * ir;
@@ -286,6 +288,7 @@ RT_HD DipoleShape<T> dipole_shape(const InstT<T>& I, const T& ir) {
     d.dg = (0.0 - x * ir) * dgdx;  // dx/dr = -x/r
     d.c = d.g * d.g - 2.0 * d.g;
     d.dc = (2.0 * d.g - 2.0) * d.dg;
+    d.dF = (0.0 - x * ir) * dF;
     return d;
 }
 
@@ -563,6 +566,44 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
         T dKdt = c1 * (b * q * dmu - mtk) - KDt * dmu;
         g[3] = omK * p.pt - p.P * dKdt;
     }
+    if (I.larmor) {
+        // finite magnetisation (Sec. 4.1 eq. (DisRel) over w_L^2 w^2 k^2): H += C with
+        //   C = -a Q^2 / (L k2),  k2 = H_vac, a = w^2 - P, Q = k2 + P, L = (w_L / w_inf)^2,
+        //   dC = al da + be dQ - C dlog(L) + de dk2,  al = -Q^2/(L k2), be = -2 a Q/(L k2), de = -C/k2,
+        // with da = d(w^2) - dP, dQ = dk2 + dP and dk2 the vacuum gradient (Cn n + Ck k,
+        // kn n + 2 k, -2 k_t/A); dlog L = (-6/r + 2 F'/F + c' mu^2/D) n + 2 c mu (m - mu n)/(r D),
+        // D = 1 + c mu^2, and 2 c mu dmu / D in time
+        const T kk = kx * kx + ky * ky + kz * kz;
+        const T w2 = kt * kti;
+        const T k2 = kk - s * q * q - w2;
+        const T av = w2 - p.P;
+        const T Qv = k2 + p.P;
+        const T ir2 = ir * ir;
+        const T Fb2 = I.gr_dipole ? sh.F * sh.F : T(1.0);
+        const T L = I.kL * (ir2 * ir2 * ir2) * Fb2 * (1.0 + cc * mu * mu);
+        const T iLk = frcp(L * k2);
+        const T C = (0.0 - av) * Qv * Qv * iLk;
+        const T al = (0.0 - Qv) * Qv * iLk;
+        const T be = -2.0 * av * Qv * iLk;
+        const T de = (0.0 - C) * L * iLk;
+        const T bd = be + de;   // coefficient of the vacuum gradient
+        const T bma = be - al;  // coefficient of grad P
+        const T lm = 2.0 * cc * mu * ir * den;
+        T ln = -6.0 * ir - lm * mu;
+        if (I.gr_dipole) ln = ln + 2.0 * sh.dF * rcp(sh.F) + sh.dc * mu * mu * den;
+        const T xn = bd * Cn - al * (kti * kti) * sr + bma * p.pn - C * ln;
+        const T xm = bma * p.pm - C * lm;
+        const T xk = bd * Ck;
+        const T kn3 = bd * kn;
+        const T k2c = 2.0 * bd;
+        for (int i = 0; i < 3; ++i) {
+            g[i] = g[i] + (xn * n[i] + (xm * m[i] + xk * y[4 + i]));
+            g[4 + i] = g[4 + i] + (kn3 * n[i] + k2c * y[4 + i]);
+        }
+        g[2] = g[2] + bma * p.pz;
+        g[7] = g[7] + 2.0 * kti * (al - bd);
+        if (I.oblique) g[3] = g[3] + (bma * p.pt - C * (2.0 * cc * mu * dmu * den));
+    }
 }
 
 // Hamilton's equations, eq. (Hamilton); sign = -1 integrates backwards in the worldline parameter.
@@ -602,8 +643,17 @@ RT_HD T hamiltonian(const InstT<T>& I, const T y[8], const AxisRef* ref = nullpt
     if (I.gr_dipole) sh = dipole_shape(I, ir);
     T mk = m[0] * y[4] + m[1] * y[5] + m[2] * y[6];
     T Nn = (I.gr_dipole ? 1.0 + (sh.g - 1.0) * a : 1.0 + 2.0 * a) * mu * q - mk;
-    T K = A * Nn * Nn * rcp(y[7] * y[7] * (1.0 + (I.gr_dipole ? sh.c : T(3.0)) * mu * mu));
-    return Hv + p.P * (1.0 - K);
+    const T Dsh = 1.0 + (I.gr_dipole ? sh.c : T(3.0)) * mu * mu;
+    T K = A * Nn * Nn * rcp(y[7] * y[7] * Dsh);
+    T H = Hv + p.P * (1.0 - K);
+    if (I.larmor) {
+        // finite magnetisation: - (w^2 - P) (Hv + P)^2 / (L Hv), L = (w_L / w_inf)^2
+        const T ir2 = ir * ir;
+        const T L = I.kL * (ir2 * ir2 * ir2) * (I.gr_dipole ? sh.F * sh.F : T(1.0)) * Dsh;
+        const T Qv = Hv + p.P;
+        H = H - (y[7] * y[7] * rcp(A) - p.P) * Qv * Qv * rcp(L * Hv);
+    }
+    return H;
 }
 
 // g^{mu nu} k_mu k_nu (vacuum part of H)

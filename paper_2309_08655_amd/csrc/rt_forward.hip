@@ -128,11 +128,12 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     // and all take the batch's rotation switch.
     auto fix = [&](InstT<double>& J) {
         if (BATCHED) J.oblique = any_oblique;
-        if constexpr (SPEC > 0) {  // the flat dipole (GR-dipole stars take the generic kernel)
+        if constexpr (SPEC > 0) {  // the flat dipole, strong field (other stars take the generic kernel)
             J.plasma = (SPEC - 1) & 1;
             J.density = ((SPEC - 1) >> 1) & 3;
             J.oblique = ((SPEC - 1) >> 3) & 1;
             J.gr_dipole = 0;
+            J.larmor = 0;
         }
     };
     InstT<double> I = I0;
@@ -618,10 +619,10 @@ static int launch_trace_variant(const rt_schedule& sc, const InstT<double>& I, c
                                 const int32_t* inst_of, int any_oblique, const TolC& T, const double* rays, int64_t n,
                                 const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st) {
     if constexpr (!BATCHED) {
-        if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128 && !I.gr_dipole)
+        if (sc.occupancy == 2 && sc.block != 64 && sc.block != 128 && !I.gr_dipole && !I.larmor)
             return launch_specialised(sc, I, T, rays, n, W, fin, ifin, st);
     } else {
-        if (sc.block != 64 && sc.block != 128 && !I.gr_dipole) {
+        if (sc.block != 64 && sc.block != 128 && !I.gr_dipole && !I.larmor) {
             if (sc.occupancy == 2)
                 return launch_batched_specialised<2>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);
             return launch_batched_specialised<1>(sc, I, itab, inst_of, any_oblique, T, rays, n, W, fin, ifin, st);

@@ -30,6 +30,8 @@ constexpr double erg_per_eV = 1.602176634e-12;
 RT_HD double gauss_eV2() { return ::sqrt(hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / (erg_per_eV * 4.0 * pi)); }
 // w_p^2 = 4 pi alpha n_e / m_e  [eV^2 per cm^-3]
 RT_HD double wp2_per_ne() { return 4.0 * pi * alpha * hbarc_eVcm * hbarc_eVcm * hbarc_eVcm / m_e_eV; }
+// electron cyclotron energy per gauss, hbar e B / (m_e c)  [eV / G]
+RT_HD double hbar_wc_per_G() { return hbarc_eVcm * e_statC / (m_e_eV * erg_per_eV); }
 }  // namespace phys
 
 // parameters of a star that are never differentiated
@@ -98,6 +100,11 @@ RT_HD InstT<T> make_inst_t(const T p[6], const StarFixed& f) {
     }
     I.plasma = f.plasma;
     I.density = f.density;
+    // finite magnetisation: (w_L / w_inf)^2 = kL r^-6 F^2 (1 + c mu^2), w_L = e|B|/(m_e c) the
+    // cyclotron frequency of the dipole field B = (B0/2) bnorm (R/r)^3 F |g mu n - m|
+    I.larmor = (f.flags & FLAG_FINITE_LARMOR) ? 1 : 0;
+    const T bL = (0.5 * phys::hbar_wc_per_G()) * B0 * I.bnorm * rcp(w_inf);
+    I.kL = (bL * bL) * (I.R3 * I.R3);
     return I;
 }
 
@@ -128,15 +135,18 @@ template <class S, class T>
 RT_HD InstT<S> lift_inst(const InstT<T>& I) {
     InstT<S> J;
     J.rs = S(I.rs); J.R = S(I.R); J.Om = S(I.Om); J.cm = S(I.cm); J.sm = S(I.sm); J.Cwp = S(I.Cwp);
-    J.R3 = S(I.R3); J.ma2 = S(I.ma2); J.bnorm = S(I.bnorm);
+    J.R3 = S(I.R3); J.ma2 = S(I.ma2); J.bnorm = S(I.bnorm); J.kL = S(I.kL);
     J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
+    J.larmor = I.larmor;
     return J;
 }
 
 // Resonance function of the foliation (kinematic matching k^a = k^gamma at fixed axion
 // direction kh in the static frame and fixed emission time):
 //   F = P (w^2 - |k_a|^2 cos^2 theta_B) - m_a^2 w^2, w^2 = 1/A, |k_a|^2 = w^2 - m_a^2
-// (isotropic plasma: F = P - m_a^2), at a general point x, for axis m.
+// (isotropic plasma: F = P - m_a^2), at a general point x, for axis m.  It is w^2 H at the
+// axion's momentum (k^2 = -m_a^2); with finite magnetisation H gains -a Q^2/(L k^2), so F
+// gains w^2 (w^2 - P)(P - m_a^2)^2 / (L m_a^2), L = (w_L / w_inf)^2.
 template <class S, class T>
 RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const double kh[3], double om2, bool thin) {
     InstT<S> J = lift_inst<S>(I);
@@ -158,7 +168,16 @@ RT_HD S resonance_point(const InstT<T>& I, const S x[3], const T m[3], const dou
     S ku = kh[0] * u[0] + kh[1] * u[1] + kh[2] * u[2];
     S cB2 = ku * ku * rcp(1.0 + csh * mu * mu);
     S w2 = om2 * rcp(1.0 - J.rs * ir);
-    return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+    S F = pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+    if (I.larmor) {
+        S fsh = S(1.0);
+        if (I.gr_dipole) fsh = dipole_shape(J, ir).F;
+        const S ir2 = ir * ir;
+        const S L = J.kL * (ir2 * ir2 * ir2) * (fsh * fsh) * (1.0 + csh * mu * mu);
+        const S Qv = pl.P - J.ma2;
+        F = F + w2 * (w2 - pl.P) * Qv * Qv * rcp(L * J.ma2);
+    }
+    return F;
 }
 
 // F along the radial line through n at radius r (values only: the bisection)
@@ -169,17 +188,28 @@ RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m
     J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
     J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2); J.bnorm = value(I.bnorm);
     J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
+    J.kL = value(I.kL); J.larmor = I.larmor;
     double ir = 1.0 / r;
     Plasma<double> pl = plasma_eval(J, n, ir, m, mu, 0.0);
     if (I.plasma == PL_ISO || thin) return pl.P - J.ma2;
+    double fsh = 1.0, csh = 3.0;
     if (I.gr_dipole) {  // the field direction along the line changes with r
         const DipoleShape<double> sh = dipole_shape(J, ir);
         double ku = 0.0;
         for (int i = 0; i < 3; ++i) ku += kh[i] * (sh.g * mu * n[i] - m[i]);
         cB2 = ku * ku / (1.0 + sh.c * mu * mu);
+        fsh = sh.F;
+        csh = sh.c;
     }
     double w2 = om2 / (1.0 - J.rs * ir);
-    return pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+    double F = pl.P * (w2 - (w2 - J.ma2) * cB2) - J.ma2 * w2;
+    if (I.larmor) {
+        const double ir2 = ir * ir;
+        const double L = J.kL * (ir2 * ir2 * ir2) * (fsh * fsh) * (1.0 + csh * mu * mu);
+        const double Qv = pl.P - J.ma2;
+        F = F + w2 * (w2 - pl.P) * Qv * Qv / (L * J.ma2);
+    }
+    return F;
 }
 
 // Root of F along the radial line through n above the surface; -1 when F(R) <= 0 or F

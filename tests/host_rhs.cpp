@@ -14,11 +14,12 @@ static InstT<double> inst_from(const double* c, const int* e) {
     I.ma2 = c[6];
     I.plasma = e[0]; I.density = e[1]; I.oblique = (I.sm != 0.0) ? 1 : 0;
     I.gr_dipole = e[2]; I.bnorm = c[7];
+    I.kL = c[8]; I.larmor = e[3];
     return I;
 }
 
 extern "C" {
-// c = (rs, R, Om, cos theta_m, sin theta_m, Cwp, ma2, bnorm); e = (plasma, density, gr_dipole)
+// c = (rs, R, Om, cos theta_m, sin theta_m, Cwp, ma2, bnorm, kL); e = (plasma, density, gr_dipole, larmor)
 void host_grad_h(const double* c, const int* e, const double* y, double* g) {
     InstT<double> I = inst_from(c, e);
     grad_h(I, y, g);

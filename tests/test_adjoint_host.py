@@ -62,13 +62,14 @@ CASES = {
     "cfg2-gj-aniso-gr-oblique": (W.CFG2["star"], 120),
     "spherical-aniso-gr-oblique": (W.star(M_Msun=1.4, theta_m=0.3, density=W.DENSITY_SPHERICAL,
                                           plasma=W.PLASMA_ANISO, m_a_eV=1e-5, kdir=W.KDIR_OUTWARD), 120),
+    "weak-field-finite-larmor": (W.WEAK_FIELD["star"], 120),
 }
 
 
 @pytest.mark.parametrize("case", list(CASES))
 def test_host_adjoint_matches_oracle_forward_mode(orc, hadj, case):
     s, n = CASES[case]
-    t = W.tol()
+    t = W.WEAK_FIELD["tol"] if case == "weak-field-finite-larmor" else W.tol()
     obs, sigma = W.observers(32), 0.02 if "spherical" not in case else 0.05
     gbar = np.random.default_rng(7).standard_normal(32)
     fh, gh, st, na, gr, miss = host_flux_grad(hadj, s, t, 0, n, obs, sigma, gbar)

@@ -49,9 +49,12 @@ def consts(orc, s):
     if gr:  # 1 / G(r_s/R): the GR dipole normalised to B0 at the surface pole
         x = rs / s["R_km"]
         bnorm = 1.0 / (-3 * (math.log1p(-x) + x + x * x / 2) / x ** 3)
+    # finite magnetisation: (w_L / w_inf)^2 = kL r^-6 F^2 (1 + c mu^2), kL = (hbar e B0 bnorm / (2 m_e c w))^2 R^6
+    larmor = 1 if s["flags"] & W.FLAG_FINITE_LARMOR else 0
+    kL = (0.5 * c["hbar_omega_c_per_G"] * s["B0_G"] * bnorm / w) ** 2 * s["R_km"] ** 6
     cc = np.array([rs, s["R_km"], 2 * math.pi / s["P_s"] / c["c_kms"],
-                   math.cos(s["theta_m"]), math.sin(s["theta_m"]), Cwp, 1 / (1 + v0 * v0), bnorm])
-    return cc, np.array([s["plasma"], s["density"], gr], dtype=np.int32)
+                   math.cos(s["theta_m"]), math.sin(s["theta_m"]), Cwp, 1 / (1 + v0 * v0), bnorm, kL])
+    return cc, np.array([s["plasma"], s["density"], gr, larmor], dtype=np.int32)
 
 
 def _p(a, t=C.c_double):
@@ -59,13 +62,18 @@ def _p(a, t=C.c_double):
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "spherical_gr", "vacuum_gr", "cfg2_gr_dipole",
-                                  "magnetar_gr_dipole"])
+                                  "magnetar_gr_dipole", "weak_field_larmor", "weak_field_larmor_gr_dipole",
+                                  "cfg2_larmor", "weak_field_larmor_aligned"])
 def test_hand_gradient_matches_oracle_autodiff(orc, host, name):
     s = {"cfg1": W.CFG1["star"], "cfg2": W.CFG2["star"], "cfg3": W.CFG3["star"],
          "spherical_gr": W.star(M_Msun=1.4, density=W.DENSITY_SPHERICAL, plasma=W.PLASMA_ANISO, theta_m=0.7),
          "vacuum_gr": W.star(M_Msun=1.4, density=W.DENSITY_NONE),
          "cfg2_gr_dipole": dict(W.CFG2["star"], flags=W.FLAG_GR_DIPOLE),
-         "magnetar_gr_dipole": dict(W.CFG3["star"], flags=W.FLAG_GR_DIPOLE)}[name]
+         "magnetar_gr_dipole": dict(W.CFG3["star"], flags=W.FLAG_GR_DIPOLE),
+         "weak_field_larmor": W.WEAK_FIELD["star"],
+         "weak_field_larmor_gr_dipole": dict(W.WEAK_FIELD["star"], flags=W.FLAG_FINITE_LARMOR | W.FLAG_GR_DIPOLE),
+         "cfg2_larmor": dict(W.CFG2["star"], flags=W.FLAG_FINITE_LARMOR),
+         "weak_field_larmor_aligned": dict(W.WEAK_FIELD["star"], theta_m=0.0, density=W.DENSITY_GJ)}[name]
     cc, e = consts(orc, s)
     rng = np.random.default_rng(0)
     for _ in range(300):
@@ -78,7 +86,7 @@ def test_hand_gradient_matches_oracle_autodiff(orc, host, name):
         assert np.abs(g - go).max() <= 1e-13 * np.abs(go).max(), (y, g, go)
 
 
-@pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2])
+@pytest.mark.parametrize("cfg", [W.CFG1, W.CFG2, W.WEAK_FIELD])
 def test_host_tracing_loop_matches_oracle(orc, host, cfg):
     s, t = cfg["star"], cfg["tol"]
     cc, e = consts(orc, s)
