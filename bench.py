@@ -71,20 +71,94 @@ def flop_table():
         return json.load(f)
 
 
-def cpu_baseline(cfg, n_sample, threads):
-    """The oracle as it stands, on the first n_sample rays of the same workload."""
-    import numpy as np
+def host_threads():
+    """(cores this process may run on, threads the oracle uses).  One GPU's share of the
+    GPU machine's host is 16 threads, whatever the affinity mask shows there."""
+    aff = len(os.sched_getaffinity(0))
+    return aff, min(aff, 16)
+
+
+def _oracle():
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    rays, st = oracle.sample(cfg["star"], cfg["seed"], n_sample, nthreads=threads)
-    fin, ifin = oracle.trace_forward(cfg["star"], cfg["tol"], rays, st, nthreads=threads)
-    oracle.bin_flux(fin, ifin, rays[8], cfg["bins"])
-    dt = time.perf_counter() - t0
-    steps = float(ifin[0].sum())
+    return oracle
+
+
+def cpu_baseline(cfg, n_sample, threads, n_single=1 << 11):
+    """The oracle as it stands, on the first n_sample rays of the same workload (seed, trace,
+    bin) on `threads` host threads, and on its first n_single rays on one core."""
+    orc = _oracle()
+
+    def run(n, nt):
+        t0 = time.perf_counter()
+        rays, st = orc.sample(cfg["star"], cfg["seed"], n, nthreads=nt)
+        fin, ifin = orc.trace_forward(cfg["star"], cfg["tol"], rays, st, nthreads=nt)
+        orc.bin_flux(fin, ifin, rays[8], cfg["bins"])
+        dt = time.perf_counter() - t0
+        return dt, float(ifin[0].sum()), float((st == 0).sum())
+
+    dt, steps, traced = run(n_sample, threads)
+    dt1, steps1, traced1 = run(n_single, 1)
+    aff, _ = host_threads()
     return dict(value=steps / dt, unit="ray-steps/s", cores=threads, kind="oracle",
-                sample=f"first {n_sample} rays of the same workload (seed, trace, bin), {dt:.2f} s, "
-                       f"rays/s {float((st == 0).sum()) / dt:.4g}")
+                sample=f"first {n_sample} rays of the same workload (seed, trace, bin), {dt:.2f} s",
+                rays_per_s=traced / dt, affinity_cores=aff,
+                single_core=dict(ray_steps_per_s=steps1 / dt1, rays_per_s=traced1 / dt1, cores=1,
+                                 sample=f"first {n_single} rays, {dt1:.2f} s"))
+
+
+def cpu_baseline_batched(W, threads, n_per=1000, stride=17):
+    """The oracle on the batched scan's bounded sample: the first n_per rays of every
+    stride-th instance (16 instances along the grid's diagonal: every axion mass and every
+    inclination once), seeded, traced and binned per instance."""
+    orc = _oracle()
+    stars, counts = W.batched_instances(W.CFG4["n_inst"], seed=W.CFG4["seed"])
+    ks = list(range(0, len(stars), stride))
+    t0 = time.perf_counter()
+    steps = traced = 0.0
+    for k in ks:
+        m = min(n_per, int(counts[k]))
+        rays, st = orc.sample(stars[k], W.CFG4["seed"], m, instance=k, nthreads=threads)
+        fin, ifin = orc.trace_forward(stars[k], W.tol(), rays, st, nthreads=threads)
+        orc.bin_flux(fin, ifin, rays[8], W.CFG4["bins"])
+        steps += float(ifin[0].sum())
+        traced += float((st == 0).sum())
+    dt = time.perf_counter() - t0
+    return dict(value=steps / dt, unit="ray-steps/s", rays_per_s=traced / dt, cores=threads, kind="oracle",
+                sample=f"first {n_per} rays of {len(ks)} instances (every {stride}th), seed + trace + bin, "
+                       f"{dt:.2f} s")
+
+
+def cpu_baseline_adjoint(W, threads, n=1000):
+    """The oracle's forward-mode gradient of the smoothed flux (6 tangents through seeding,
+    every step and the r_max crossing) on the adjoint workload's first n rays; ray-steps/s
+    counts the accepted steps of those rays' traces."""
+    orc = _oracle()
+    cfg = W.CFG5
+    obs = W.observers(cfg["n_obs"])
+    t0 = time.perf_counter()
+    orc.flux_fwdmode(cfg["star"], cfg["tol"], cfg["seed"], n, obs, cfg["sigma"], nthreads=threads)
+    dt = time.perf_counter() - t0
+    rays, st = orc.sample(cfg["star"], cfg["seed"], n, nthreads=threads)
+    fin, ifin = orc.trace_forward(cfg["star"], cfg["tol"], rays, st, nthreads=threads)
+    return dict(value=float(ifin[0].sum()) / dt, unit="ray-steps/s", rays_per_s=float((st == 0).sum()) / dt,
+                cores=threads, kind="oracle",
+                sample=f"first {n} rays, flux and its 6-parameter gradient by forward mode, {dt:.2f} s")
+
+
+def cpu_baseline_backward(W, threads, stride=8):
+    """The oracle's backward tracer on a strided sub-grid of the image (every stride-th pixel
+    in each direction: 128^2 of the 1024^2 pixels)."""
+    orc = _oracle()
+    cfg = W.CFG3
+    im = cfg["image"]
+    ni, nj = im["nx"] // stride, im["ny"] // stride
+    t0 = time.perf_counter()
+    ev, nev, fin, ifin = orc.trace_backward(cfg["star"], cfg["tol"], im, cfg["K"], 0, 0, stride, ni, nj,
+                                            nthreads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=float(ifin[0].sum()) / dt, unit="ray-steps/s", rays_per_s=ni * nj / dt, cores=threads,
+                kind="oracle", sample=f"{ni}x{nj} pixels (every {stride}th in each direction), {dt:.2f} s")
 
 
 def bench_batched(args, rt, W, np, torch):
@@ -101,9 +175,8 @@ def bench_batched(args, rt, W, np, torch):
         def run_sc(sc):
             b.set_schedule(sc)
             b.run()
-        best, times = autotune.tune(run_sc, key=f"batched|{len(stars)}|{int(counts.sum())}", reps=2,
-                                    candidates=[c for c in autotune.CANDIDATES
-                                                if c["block"] == 256 and c["refill_min"] in (4, 16)])
+        best, times = autotune.tune(run_sc, key=f"batched|{len(stars)}|{int(counts.sum())}", reps=3,
+                                    candidates=autotune.BATCHED_CANDIDATES)
     b.set_schedule(best)
     g = b.capture()
     for _ in range(max(1, args.warmup)):
@@ -119,7 +192,20 @@ def bench_batched(args, rt, W, np, torch):
     ms = e0.elapsed_time(e1) / reps
     ifn = b.ifin.cpu().numpy()
     acc = float(ifn[0].astype(np.float64).sum())
+    rej = float(ifn[1].astype(np.float64).sum())
     traced = float((b.status.cpu().numpy() == 0).sum())
+    # the tracing kernel alone (eager runs: events are not recorded inside a captured graph),
+    # against its algorithmic work, and its lane efficiency (third word of the work counter)
+    rt.timing(True)
+    for _ in range(2):
+        b.run()
+    torch.cuda.synchronize()
+    rt.timing(False)
+    kt = [t for name, t in rt.kernel_times() if name == "trace_fwd_kernel(batched)"]
+    kernel_ms = float(np.mean(kt))
+    wave_iters = int(b.ws[16:24].cpu().numpy().view(np.uint64)[0])
+    ft = flop_table()["iso_gj_oblique"]  # the batch takes the rotating-axis formula throughout
+    ktf = (acc + rej) * ft["attempt"] / (kernel_ms * 1e-3) / 1e12
     # one launch of each entry point per instance, on buffers sized for the largest instance
     nmax = int(counts.max())
     dev = torch.device("cuda")
@@ -145,6 +231,28 @@ def bench_batched(args, rt, W, np, torch):
             rt.rt_trace_forward(s, tol, rr, t_, schedule=best, ws=ws, fin=ff, ifin=ii)
             rt.rt_bin_flux(ff, ii, rr[8], bins, ws=wsb, hist=hist, cnt=cnt, over=over)
 
+    # the plain (single-star) tracing kernel on the same physics: the scan's largest oblique
+    # instance alone, against the same per-attempt count, for the batched kernel's rate
+    kbig = max((k for k in range(len(stars)) if stars[k]["theta_m"] > 0 and stars[k]["m_a_eV"] < 9e-5),
+               key=lambda k: counts[k])
+    mb = int(counts[kbig])
+    rrb = rays.view(-1)[:10 * mb].view(10, mb)
+    ffb = fin.view(-1)[:rt.RT_NFIN * mb].view(rt.RT_NFIN, mb)
+    iib = ifin.view(-1)[:rt.RT_NIFIN * mb].view(rt.RT_NIFIN, mb)
+    rt.rt_sample_resonance(stars[kbig], W.CFG4["seed"], mb, instance=kbig, rays=rrb, status=st[:mb])
+    rt.rt_trace_forward(stars[kbig], tol, rrb, st[:mb], ws=ws, fin=ffb, ifin=iib)
+    torch.cuda.synchronize()
+    rt.timing(True)
+    for _ in range(3):
+        rt.rt_trace_forward(stars[kbig], tol, rrb, st[:mb], ws=ws, fin=ffb, ifin=iib)
+    torch.cuda.synchronize()
+    rt.timing(False)
+    kp = float(np.mean([t for name, t in rt.kernel_times() if name == "trace_fwd_kernel"]))
+    ib = iib.cpu().numpy().astype(np.float64)
+    plain_same = dict(instance=kbig, m_a_eV=stars[kbig]["m_a_eV"], theta_m=stars[kbig]["theta_m"], rays=mb,
+                      kernel_ms=kp, kernel_frac=(ib[0].sum() + ib[1].sum()) * ft["attempt"] / (kp * 1e-3) / 1e12
+                      / FP64_VECTOR_PEAK_TFLOPS)
+
     # kernels and buffers are already warm from the batched runs: time a single pass
     torch.cuda.synchronize()
     e0.record()
@@ -154,8 +262,11 @@ def bench_batched(args, rt, W, np, torch):
     ms_loop = e0.elapsed_time(e1)
     return dict(workload=W.CFG4["name"], instances=len(stars), rays=int(counts.sum()), traced_rays=traced,
                 ms_per_launch=ms, ray_steps_per_s=acc / (ms * 1e-3), rays_per_s=traced / (ms * 1e-3),
-                accepted_steps=acc, schedule=best, graph="one hipGraph replay per launch",
-                per_instance_ms=ms_loop, speedup_vs_per_instance=ms_loop / ms, tune_ms=times)
+                accepted_steps=acc, rejected_steps=rej, schedule=best, graph="one hipGraph replay per launch",
+                kernel_ms=kernel_ms, kernel_tflops=ktf, kernel_frac=ktf / FP64_VECTOR_PEAK_TFLOPS,
+                flop_per_attempt=ft["attempt"], lane_efficiency=(acc + rej) / max(1, 64 * wave_iters),
+                per_instance_ms=ms_loop, speedup_vs_per_instance=ms_loop / ms, tune_ms=times,
+                plain_kernel_same_physics=plain_same)
 
 
 def bench_backward(args, rt, W, np, torch):
@@ -604,9 +715,16 @@ def main():
     if "fbtotal" in forms:
         out["forms"]["forward_vs_backward"] = forward_vs_backward_total(rt, W, np, torch)
     if not args.no_cpu:
-        threads = min(16, len(os.sched_getaffinity(0)))
-        print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads", file=sys.stderr, flush=True)
+        aff, threads = host_threads()
+        print(f"bench: cpu baseline on {args.cpu_sample} rays, {threads} threads ({aff} cores in the affinity "
+              f"mask)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, threads)
+        # the oracle beside each form, on the bounded samples of the same workloads
+        for form, fn in (("batched", cpu_baseline_batched), ("adjoint", cpu_baseline_adjoint),
+                         ("backward", cpu_baseline_backward)):
+            if form in out["forms"]:
+                print(f"bench: cpu baseline of the {form} form", file=sys.stderr, flush=True)
+                out["forms"][form]["cpu_baseline"] = fn(W, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -133,6 +133,9 @@ typedef struct rt_schedule {
                              spills), 2 = two waves per SIMD (a few spills to scratch) */
     int32_t cross_batch;  /* forward tracing of the GJ density: crossings of the null surface a
                              wave lets wait before restarting them together (1..64; 0 = 8) */
+    int32_t chunk;        /* queue chunk: work-list entries a wave claims at once and hands to
+                             its idle lanes over several refills (64..65536); 0 = exactly the
+                             idle lanes' worth at each refill (the default) */
 } rt_schedule;
 
 /* Number of doubles / int32 per final record (fin: "[RT_NFIN][n]", ifin: "[RT_NIFIN][n]"):
@@ -265,7 +268,9 @@ int rt_backward_power(const rt_star* star, const double* ev, const int32_t* nev,
  * persistent work-queue kernel.  Instances share plasma, density, weights and kdir; each
  * has its own parameters and ray count.  Instance k owns the global rays
  * [ray_offset[k], ray_offset[k+1]) and seeds ray i with Philox counter (i - ray_offset[k], k),
- * so its rays are identical to rt_sample_resonance(..., instance = k, first = 0, ...). */
+ * so its rays are identical to rt_sample_resonance(..., instance = k, first = 0, ...).  One
+ * cost-ordered queue serves every instance (longest rays of all instances first); a lane
+ * loads its ray's instance constants when it takes the ray. */
 typedef struct rt_batch {        /* filled by rt_batch_prepare; plain host data */
     int32_t n_inst;
     int32_t any_oblique;

@@ -48,7 +48,7 @@ class RtImage(C.Structure):
 
 class RtSchedule(C.Structure):
     _fields_ = [("block", C.c_int32), ("waves_per_cu", C.c_int32), ("refill_min", C.c_int32),
-                ("occupancy", C.c_int32), ("cross_batch", C.c_int32)]
+                ("occupancy", C.c_int32), ("cross_batch", C.c_int32), ("chunk", C.c_int32)]
 
 
 class RtBatch(C.Structure):
@@ -138,7 +138,7 @@ def make_schedule(d: dict | None):
     if d is None:
         return None
     return RtSchedule(d.get("block", 256), d.get("waves_per_cu", 0), d.get("refill_min", 4), d.get("occupancy", 2),
-                      d.get("cross_batch", 0))
+                      d.get("cross_batch", 0), d.get("chunk", 0))
 
 
 def _ptr(t: torch.Tensor | None):

@@ -116,12 +116,14 @@ rt_schedule resolve_schedule(const rt_schedule* s) {
     r.refill_min = 4;
     r.occupancy = 2;
     r.cross_batch = 8;
+    r.chunk = 0;
     if (s) {
         if (s->block == 64 || s->block == 128 || s->block == 256) r.block = s->block;
         if (s->waves_per_cu > 0 && s->waves_per_cu <= 32) r.waves_per_cu = s->waves_per_cu;
         if (s->refill_min >= 1 && s->refill_min <= 64) r.refill_min = s->refill_min;
         if (s->occupancy == 1 || s->occupancy == 2) r.occupancy = s->occupancy;
         if (s->cross_batch >= 1 && s->cross_batch <= 64) r.cross_batch = s->cross_batch;
+        if (s->chunk >= 64 && s->chunk <= 65536) r.chunk = s->chunk;
     }
     return r;
 }

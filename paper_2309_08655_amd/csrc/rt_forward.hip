@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
                                                           int32_t* __restrict__ ifin, int refill_min,
-                                                          int cross_batch, double* __restrict__ stash) {
+                                                          int cross_batch, double* __restrict__ stash, int chunk) {
     // a specialised instantiation (SPEC = 1 + plasma + 2 density + 8 oblique) fixes these
     // switches at compile time: the Hamiltonian and its gradient become branch-free code with
     // the same arithmetic (the file is built with -ffp-contract=on, so the generic and the
@@ -166,38 +166,66 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     const double rmax2 = tol.rmax * tol.rmax;
     double R2 = I.R * I.R;
 
+    auto start_ray = [&](int64_t jj) {
+        j = jj;
+        if (BATCHED) {
+            I = itab[inst_of[j]];
+            fix(I);
+            R2 = I.R * I.R;
+        }
+        for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
+        h = h0s[j];
+        lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
+        if (I.oblique) ref = axis_ref_at(I, y[3]);
+        if (I.density == DEN_GJ) {
+            const double g0 = gj_factor(I, y, &ref);
+            gjs = (g0 < 0.0) ? -1.0 : 1.0;
+            phi = gjs * g0;
+        }
+        pending = false;
+        active = true;
+    };
+    // chunk > 0: the wave claims `chunk` list entries at a time and hands them to its idle
+    // lanes over several refills (one atomic per chunk); 0: exactly the idle lanes' worth
+    unsigned long long cpos = 0, cend = 0;
+
     while (true) {
         unsigned long long idle = __ballot(!active);
         if (idle && !exhausted) {
             int cnt = __popcll(idle);
             if (cnt >= refill_min || idle == __ballot(true)) {
-                int leader = __ffsll((long long)idle) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(&ctr->head, (unsigned long long)cnt);
-                base = __shfl(base, leader);
-                if (!active) {
-                    unsigned long long q = base + __popcll(idle & below);
-                    if (q < nlist) {
-                        j = list[q];
-                        if (BATCHED) {
-                            I = itab[inst_of[j]];
-                            fix(I);
-                            R2 = I.R * I.R;
+                if (chunk <= 0) {
+                    int leader = __ffsll((long long)idle) - 1;
+                    unsigned long long base = 0;
+                    if (lane == leader) base = atomicAdd(&ctr->head, (unsigned long long)cnt);
+                    base = __shfl(base, leader);
+                    if (!active) {
+                        unsigned long long q = base + __popcll(idle & below);
+                        if (q < nlist) start_ray(list[q]);
+                    }
+                    if (base + (unsigned long long)cnt >= nlist) exhausted = true;
+                } else {
+                    unsigned long long want = idle;
+                    while (want) {
+                        if (cpos >= cend) {
+                            unsigned long long b = 0;
+                            if (lane == 0) b = atomicAdd(&ctr->head, (unsigned long long)chunk);
+                            b = __shfl(b, 0);
+                            if (b >= nlist) {
+                                exhausted = true;
+                                break;
+                            }
+                            cpos = b;
+                            cend = (b + (unsigned long long)chunk < nlist) ? b + (unsigned long long)chunk : nlist;
                         }
-                        for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
-                        h = h0s[j];
-                        lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
-                        if (I.oblique) ref = axis_ref_at(I, y[3]);
-                        if (I.density == DEN_GJ) {
-                            const double g0 = gj_factor(I, y, &ref);
-                            gjs = (g0 < 0.0) ? -1.0 : 1.0;
-                            phi = gjs * g0;
-                        }
-                        pending = false;
-                        active = true;
+                        const unsigned long long avail = cend - cpos;
+                        const unsigned long long rank = (unsigned long long)__popcll(want & below);
+                        if (((want >> lane) & 1ull) && rank < avail) start_ray(list[cpos + rank]);
+                        const unsigned long long nw = (unsigned long long)__popcll(want);
+                        cpos += (avail < nw) ? avail : nw;
+                        want = __ballot(!active);
                     }
                 }
-                if (base + (unsigned long long)cnt >= nlist) exhausted = true;
             }
         }
         if (__ballot(active) == 0ull) {
@@ -551,7 +579,7 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
     timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
     hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, itab,
                        inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min,
-                       sc.cross_batch, W.stash);
+                       sc.cross_batch, W.stash, sc.chunk);
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
     if (rc) return rc;

@@ -191,7 +191,8 @@ def test_edge_cases(rt, orc):
 
 @pytest.mark.parametrize("sched", [dict(block=64, refill_min=1), dict(block=128, refill_min=8),
                                    dict(block=256, refill_min=32, waves_per_cu=8),
-                                   dict(block=256, refill_min=16, occupancy=2)])
+                                   dict(block=256, refill_min=16, occupancy=2),
+                                   dict(block=256, refill_min=4, chunk=64), dict(block=128, refill_min=8, chunk=1024)])
 def test_schedules_give_identical_rays(rt, orc, sched):
     """Per-ray results do not depend on the launch schedule (bit-identical)."""
     cfg = W.CFG2
