@@ -98,7 +98,8 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 template <bool LARMOR>
 __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
-                                                      const double* __restrict__ h0s, int C, int Kc,
+                                                      const double* __restrict__ y0q, const double* __restrict__ h0s,
+                                                      int C, int Kc,
                                                       double* __restrict__ ckpt, int32_t* __restrict__ nseg_out,
                                                       double* __restrict__ theta_out, int32_t* __restrict__ ifin,
                                                       const double* __restrict__ obs, int n_obs, double sigma,
@@ -132,8 +133,8 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
                 if (qq < nlist) {
                     j = list[qq];
                     double y0[8];
-                    for (int d = 0; d < 8; ++d) y0[d] = rays[d * n + j];
-                    adj_ray_start<LARMOR>(I, y0, h0s[j], R, store);
+                    for (int d = 0; d < 8; ++d) y0[d] = y0q[d * n + qq];  // seed states in list order
+                    adj_ray_start<LARMOR>(I, y0, h0s[qq], R, store);
                     active = true;
                 }
             }
@@ -328,19 +329,17 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st);
         if (rc) return rc;
-        rc = order_work_list(W.fw, n, st);
-        if (rc) return rc;
         const rt_schedule sc = resolve_schedule(nullptr);
         const void* fk = I.larmor ? (const void*)adj_fwd_kernel<true> : (const void*)adj_fwd_kernel<false>;
         const int grid = persistent_grid(sc, fk, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         if (I.larmor)
             hipLaunchKernelGGL(adj_fwd_kernel<true>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
+                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
                                sigma, W.facc);
         else
             hipLaunchKernelGGL(adj_fwd_kernel<false>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
+                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
                                sigma, W.facc);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");

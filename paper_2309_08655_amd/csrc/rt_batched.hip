@@ -226,8 +226,6 @@ extern "C" int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_t
     if (rc) return rc;
     rc = launch_trace_init(I0, B.itab, B.inst_of, T, rays, status, N, B.fw, fin, ifin, st);
     if (rc) return rc;
-    rc = order_work_list(B.fw, N, st);
-    if (rc) return rc;
     rc = launch_trace_fwd_batched(sc, I0, B.itab, B.inst_of, batch->any_oblique, T, rays, N, B.fw, fin, ifin, st);
     if (rc) return rc;
     hipLaunchKernelGGL(bin_keys_inst_kernel, dim3(grid_for(N, 256, 8)), dim3(256), 0, st, fin, ifin, N,

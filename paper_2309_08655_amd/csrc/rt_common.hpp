@@ -83,8 +83,9 @@ struct FwdWs {
     double* stash;  // [stash_lanes][STASH_STRIDE]
     int64_t stash_lanes;
     int32_t* list;
-    double* h0;
+    double* h0;  // forward tracing: in work-list order (entry q), like k1 and y0
     double* k1;
+    double* y0;  // [8][n] seed states in work-list order
     int32_t* keys;     // [n] bucket of each ray (-1: not traced)
     int32_t* buckets;  // [ORDER_BUCKETS + 1] first list entry of each bucket, then the list length
     int32_t* tab;      // [partition_blocks(n) x ORDER_BUCKETS] per-workgroup bucket offsets
@@ -115,6 +116,8 @@ inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     p += align256(sizeof(double) * (size_t)n);
     W.k1 = (double*)p;
     p += align256(sizeof(double) * 8 * (size_t)n);
+    W.y0 = (double*)p;
+    p += align256(sizeof(double) * 8 * (size_t)n);
     W.keys = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)n);
     W.buckets = (int32_t*)p;
@@ -125,9 +128,8 @@ inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
 
 inline size_t fwd_ws_bytes(int64_t n) {
     return align256(sizeof(WorkCtr)) + stash_bytes() + align256(sizeof(int32_t) * (size_t)n) +
-           align256(sizeof(double) * (size_t)n) +
-           align256(sizeof(double) * 8 * (size_t)n) + align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() +
-           part_tab_bytes(n);
+           align256(sizeof(double) * (size_t)n) + 2 * align256(sizeof(double) * 8 * (size_t)n) +
+           align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() + part_tab_bytes(n);
 }
 
 // Groups the indices i < n with keys[i] >= 0 and keys[i] >> shift < nb (nb <= PART_BUCKETS)
@@ -185,8 +187,10 @@ int launch_trace_fwd_batched(const rt_schedule& sc, const InstT<double>& I0, con
                              const FwdWs& W, double* fin, int32_t* ifin, hipStream_t st);
 int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, const int64_t* off, int32_t n_inst,
                           uint64_t seed, int64_t N, double* rays, int32_t* status, int32_t* inst_of, hipStream_t st);
-// FSAL derivative and starting step of every traced seed, on the seed's smooth piece of
-// the GJ density; the cost keys of the work list
+// Set-up of a forward trace: the cost keys of the seeds (and the final records of seeds
+// not traced), the work list ordered by them, then for every list entry q the seed state,
+// its FSAL derivative (on the seed's smooth piece of the GJ density) and its starting step,
+// written in list order so that the tracing kernels read them contiguously
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
                       int32_t* ifin, hipStream_t st);

@@ -64,43 +64,60 @@ __global__ void __launch_bounds__(256) sample_kernel(InstT<double> I, SeedT<doub
 }
 
 // ----------------------------------------------------------------------------
-// tracing: init pass (FSAL derivative, starting step, compacted work list)
+// tracing set-up: cost keys, then (after the work list is ordered) the starting state,
+// FSAL derivative and starting step of every list entry, in list order
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
-                                                         const int32_t* __restrict__ inst_of, TolC tol,
+__global__ void __launch_bounds__(256) trace_keys_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
+                                                         const int32_t* __restrict__ inst_of,
                                                          const double* __restrict__ rays,
                                                          const int32_t* __restrict__ status, int64_t n,
-                                                         int32_t* __restrict__ keys, double* __restrict__ h0s,
-                                                         double* __restrict__ k1s, double* __restrict__ fin,
+                                                         int32_t* __restrict__ keys, double* __restrict__ fin,
                                                          int32_t* __restrict__ ifin) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
-        const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
-        bool ok = (status == nullptr || status[j] == ST_OK);
         int32_t key = -1;
-        if (!ok) {
+        if (status != nullptr && status[j] != ST_OK) {
             for (int d = 0; d < RT_NFIN_; ++d) fin[d * n + j] = 0.0;
             ifin[j] = 0;
             ifin[n + j] = 0;
             ifin[2 * n + j] = status[j];
         } else {
-            double y[8], f0[8];
-            for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
-            // GJ density, cut at the null surface: the smooth piece of |g| the seed lies on,
-            // which the tracing kernels (forward, batched and the adjoint's) integrate from
-            // here, also for the starting step's probe
-            const double gjs = (I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
-            auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, nullptr, gjs); };
-            f(y, f0);
-            double h = initial_step(f, y, f0, tol.rtol, tol.atol);
-            h0s[j] = h;
-            for (int d = 0; d < 8; ++d) k1s[d * n + j] = f0[d];
+            const double R = (itab != nullptr) ? itab[inst_of[j]].R : I0.R;
+            const double x = rays[j], y = rays[n + j], z = rays[2 * n + j];
             // cost key: rays seeded close to the star take the most steps
-            double r = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-            double u = log2(fmax(r / I.R, 1.0)) * (ORDER_BUCKETS / 8.0);
+            const double r = sqrt(x * x + y * y + z * z);
+            const double u = log2(fmax(r / R, 1.0)) * (ORDER_BUCKETS / 8.0);
             key = (u >= 0.0 && u < (double)(ORDER_BUCKETS - 1)) ? (int32_t)u : ORDER_BUCKETS - 1;
         }
         keys[j] = key;
+    }
+}
+
+__global__ void __launch_bounds__(256) trace_init_kernel(InstT<double> I0, const InstT<double>* __restrict__ itab,
+                                                         const int32_t* __restrict__ inst_of, TolC tol,
+                                                         const double* __restrict__ rays, int64_t n,
+                                                         const WorkCtr* __restrict__ ctr,
+                                                         const int32_t* __restrict__ list, double* __restrict__ y0q,
+                                                         double* __restrict__ h0q, double* __restrict__ k1q) {
+    const int64_t nlist = (int64_t)ctr->len;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nlist; q += stride) {
+        const int64_t j = list[q];
+        const InstT<double> I = (itab != nullptr) ? itab[inst_of[j]] : I0;
+        double y[8], f0[8];
+        for (int d = 0; d < 8; ++d) y[d] = rays[d * n + j];
+        // GJ density, cut at the null surface: the smooth piece of |g| the seed lies on,
+        // which the tracing kernels (forward, batched and the adjoint's) integrate from
+        // here, also for the starting step's probe
+        const double gjs = (I.density == DEN_GJ) ? ((gj_factor(I, y) < 0.0) ? -1.0 : 1.0) : 0.0;
+        auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, nullptr, gjs); };
+        f(y, f0);
+        const double h = initial_step(f, y, f0, tol.rtol, tol.atol);
+        h0q[q] = h;
+        for (int d = 0; d < 8; ++d) {
+            y0q[d * n + q] = y[d];
+            k1q[d * n + q] = f0[d];
+        }
     }
 }
 
@@ -117,7 +134,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                                                           const int32_t* __restrict__ inst_of, int any_oblique,
                                                           TolC tol, const double* __restrict__ rays,
                                                           int64_t n, WorkCtr* ctr, const int32_t* __restrict__ list,
-                                                          const double* __restrict__ h0s,
+                                                          const double* __restrict__ y0q, const double* __restrict__ h0s,
                                                           const double* __restrict__ k1s, double* __restrict__ fin,
                                                           int32_t* __restrict__ ifin, int refill_min,
                                                           int cross_batch, double* __restrict__ stash, int chunk) {
@@ -166,15 +183,17 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     const double rmax2 = tol.rmax * tol.rmax;
     double R2 = I.R * I.R;
 
-    auto start_ray = [&](int64_t jj) {
-        j = jj;
+    // list entry q: its ray j, whose seed state, FSAL derivative and starting step the set-up
+    // wrote in list order (consecutive entries read consecutive addresses)
+    auto start_ray = [&](unsigned long long q) {
+        j = list[q];
         if (BATCHED) {
             I = itab[inst_of[j]];
             fix(I);
             R2 = I.R * I.R;
         }
-        for (int d = 0; d < 8; ++d) { y[d] = rays[d * n + j]; S.K[0][d] = k1s[d * n + j]; }
-        h = h0s[j];
+        for (int d = 0; d < 8; ++d) { y[d] = y0q[d * n + q]; S.K[0][d] = k1s[d * n + q]; }
+        h = h0s[q];
         lam = 0.0; facmax = 10.0; nacc = 0; nrej = 0;
         if (I.oblique) ref = axis_ref_at(I, y[3]);
         if (I.density == DEN_GJ) {
@@ -201,7 +220,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                     base = __shfl(base, leader);
                     if (!active) {
                         unsigned long long q = base + __popcll(idle & below);
-                        if (q < nlist) start_ray(list[q]);
+                        if (q < nlist) start_ray(q);
                     }
                     if (base + (unsigned long long)cnt >= nlist) exhausted = true;
                 } else {
@@ -220,7 +239,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                         }
                         const unsigned long long avail = cend - cpos;
                         const unsigned long long rank = (unsigned long long)__popcll(want & below);
-                        if (((want >> lane) & 1ull) && rank < avail) start_ray(list[cpos + rank]);
+                        if (((want >> lane) & 1ull) && rank < avail) start_ray(cpos + rank);
                         const unsigned long long nw = (unsigned long long)__popcll(want);
                         cpos += (avail < nw) ? avail : nw;
                         want = __ballot(!active);
@@ -564,8 +583,6 @@ extern "C" int rt_trace_forward(const rt_star* star, const rt_tol* tol, const do
     hipStream_t st = (hipStream_t)stream;
     int rc = launch_trace_init(I, nullptr, nullptr, T, rays, status, n, W, fin, ifin, st);
     if (rc) return rc;
-    rc = order_work_list(W, n, st);
-    if (rc) return rc;
     return launch_trace_fwd(sc, I, T, rays, n, W, fin, ifin, st);
 }
 
@@ -578,7 +595,7 @@ static int launch_fwd_block(const rt_schedule& sc, const InstT<double>& I, const
     if ((int64_t)grid * BLOCK > W.stash_lanes) return fail(RT_EINVAL, "trace_fwd_kernel: more lanes than stash slots");
     timing_begin(st, BATCHED ? RT_KERNEL_TRACE_BATCHED : RT_KERNEL_TRACE_FORWARD);
     hipLaunchKernelGGL((trace_fwd_kernel<BLOCK, MINW, BATCHED, SPEC>), dim3(grid), dim3(BLOCK), 0, st, I, itab,
-                       inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.h0, W.k1, fin, ifin, sc.refill_min,
+                       inst_of, any_oblique, T, rays, n, W.ctr, W.list, W.y0, W.h0, W.k1, fin, ifin, sc.refill_min,
                        sc.cross_batch, W.stash, sc.chunk);
     timing_end(st);
     int rc = check_launch("trace_fwd_kernel");
@@ -691,8 +708,14 @@ int launch_sample_batched(const InstT<double>* itab, const SeedT<double>* ctab, 
 int launch_trace_init(const InstT<double>& I0, const InstT<double>* itab, const int32_t* inst_of, const TolC& T,
                       const double* rays, const int32_t* status, int64_t n, const FwdWs& W, double* fin,
                       int32_t* ifin, hipStream_t st) {
-    hipLaunchKernelGGL(trace_init_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, T, rays,
-                       status, n, W.keys, W.h0, W.k1, fin, ifin);
+    hipLaunchKernelGGL(trace_keys_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, rays,
+                       status, n, W.keys, fin, ifin);
+    int rc = check_launch("trace_keys_kernel");
+    if (rc) return rc;
+    rc = order_work_list(W, n, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(trace_init_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, I0, itab, inst_of, T, rays, n,
+                       W.ctr, W.list, W.y0, W.h0, W.k1);
     return check_launch("trace_init_kernel");
 }
 
