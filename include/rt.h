@@ -316,25 +316,32 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
  *     (y, h, controller state, density piece) every ckpt_every accepted steps, writes flux[n_obs] (device)
  *     and, if ray_info != NULL, ray_info "[3][n]" = n_acc, n_rej, status (device).
  *     A ray that would need more than max_ckpt checkpoints ends as RT_ST_MAX_STEPS.
+ *     Checkpoints go to a pool of ckpt_pool slots shared by all rays (a traced ray needs
+ *     1 + (n_acc - 1) / ckpt_every of them, n_acc >= 1).  If ckpt_used != NULL, *ckpt_used (device int64)
+ *     receives the number of slots the rays asked for.  The flux is valid either way; if
+ *     the rays asked for more than ckpt_pool, the phase stores what fits and the reverse
+ *     phase yields NaN: call phase 0 again with ckpt_pool >= *ckpt_used (the count depends
+ *     only on the arguments, not on the pool or the schedule).
  *   phase 1 (reverse): given gbar[n_obs] (device), recomputes each segment from its
  *     checkpoint and sweeps back through the stages; writes grad[6] = sum_j gbar_j dF_j/dp
  *     (device) and, if grad_rays != NULL, each ray's share "[n][6]" (zero for rays that
  *     do not escape).  Needs the workspace of the phase-0 call of the same arguments,
  *     unchanged; phase-1 calls may be repeated with other gbar.
  * obs: HOST array "[n_obs][3]" of unit vectors, 1 <= n_obs <= 64; sigma > 0 [rad];
- * 1 <= ckpt_every <= 1024; max_ckpt >= 1; weights RT_WEIGHTS_CONST_B is not supported.
- * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt) bytes (about
- * n (316 + 88 max_ckpt) + 5.8 MB x ckpt_every).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
+ * 1 <= ckpt_every <= 1024; max_ckpt >= 1; 1 <= ckpt_pool <= 2^31 - 1; weights
+ * RT_WEIGHTS_CONST_B is not supported.
+ * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, ckpt_pool) bytes (about
+ * 384 n + 96 ckpt_pool + 5.8 MB x ckpt_every + 96 MB).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
  * RT_EUNSUPPORTED or RT_EHIP. */
 int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
-                 int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
-                 const double* gbar, double* flux, double* grad, double* grad_rays, int32_t* ray_info, void* ws,
-                 size_t ws_bytes, void* stream);
+                 int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int64_t ckpt_pool, int32_t phase,
+                 const double* gbar, double* flux, double* grad, double* grad_rays, int32_t* ray_info,
+                 int64_t* ckpt_used, void* ws, size_t ws_bytes, void* stream);
 
-size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int32_t max_ckpt);
+size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int64_t ckpt_pool);
 
 /* Workspace bytes needed by op (RT_OP_*) for n rays; RT_OP_FLUX_GRAD is
- * rt_flux_grad_workspace_size(n, 64, 64, 64). */
+ * rt_flux_grad_workspace_size(n, 64, 64, 2 n + 1). */
 size_t rt_workspace_size(int32_t op, int64_t n);
 
 /* Kernel timing.  rt_timing(1) starts recording (and forgets earlier records): every

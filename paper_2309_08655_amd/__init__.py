@@ -92,8 +92,9 @@ def lib():
         L.rt_trace_batched.argtypes = [C.POINTER(RtBatch), C.c_uint64, tp, C.POINTER(RtBins), dp, ip, dp, ip, dp, dp,
                                        vp, C.c_size_t, C.POINTER(RtSchedule), vp]
         L.rt_flux_grad.argtypes = [sp, tp, C.c_uint64, C.c_int64, C.POINTER(C.c_double), C.c_int32, C.c_double,
-                                   C.c_int32, C.c_int32, C.c_int32, dp, dp, dp, dp, ip, vp, C.c_size_t, vp]
-        L.rt_flux_grad_workspace_size.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+                                   C.c_int32, C.c_int32, C.c_int64, C.c_int32, dp, dp, dp, dp, ip, lp, vp,
+                                   C.c_size_t, vp]
+        L.rt_flux_grad_workspace_size.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int64]
         L.rt_flux_grad_workspace_size.restype = C.c_size_t
         L.rt_workspace_size.argtypes = [C.c_int32, C.c_int64]
         L.rt_workspace_size.restype = C.c_size_t
@@ -339,48 +340,78 @@ def kernel_times(max_n: int = 1024):
 PARAMS = ("B0_G", "P_s", "theta_m", "M_Msun", "R_km", "m_a_eV")  # differentiable star parameters
 
 
-def flux_grad_workspace_size(n: int, n_obs: int, ckpt_every: int = 64, max_ckpt: int = 64) -> int:
-    return int(lib().rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt))
+CKPT_POOL_MAX = 2**31 - 1
+
+
+def default_ckpt_pool(n: int) -> int:
+    """Checkpoint slots a FluxGrad starts with: two per ray (it grows the pool if the rays ask for more)."""
+    return max(1, min(2 * int(n) + 1, CKPT_POOL_MAX))
+
+
+def flux_grad_workspace_size(n: int, n_obs: int, ckpt_every: int = 64, ckpt_pool: int = None) -> int:
+    pool = default_ckpt_pool(n) if ckpt_pool is None else int(ckpt_pool)
+    return int(lib().rt_flux_grad_workspace_size(n, n_obs, ckpt_every, pool))
 
 
 def rt_flux_grad(star: dict, tol: dict, seed: int, n: int, obs, sigma: float, phase: int, ws: torch.Tensor,
-                 ckpt_every: int = 64, max_ckpt: int = 64, gbar=None, flux=None, grad=None, grad_rays=None,
-                 ray_info=None):
+                 ckpt_every: int = 64, max_ckpt: int = 64, ckpt_pool: int = None, gbar=None, flux=None, grad=None,
+                 grad_rays=None, ray_info=None, ckpt_used=None):
     """One phase of rt_flux_grad (0: forward, writes flux; 1: reverse, writes grad)."""
     import numpy as np
     obs_h = np.ascontiguousarray(np.asarray(obs, dtype=np.float64).reshape(-1, 3))
     s, t = make_star(star), make_tol(tol)
+    pool = default_ckpt_pool(n) if ckpt_pool is None else int(ckpt_pool)
     _check(lib().rt_flux_grad(C.byref(s), C.byref(t), seed, n, obs_h.ctypes.data_as(C.POINTER(C.c_double)),
-                              obs_h.shape[0], sigma, ckpt_every, max_ckpt, phase, _ptr(gbar), _ptr(flux), _ptr(grad),
-                              _ptr(grad_rays), _ptr(ray_info), _ptr(ws), ws.numel(), _stream()), "rt_flux_grad")
+                              obs_h.shape[0], sigma, ckpt_every, max_ckpt, pool, phase, _ptr(gbar), _ptr(flux),
+                              _ptr(grad), _ptr(grad_rays), _ptr(ray_info), _ptr(ckpt_used), _ptr(ws), ws.numel(),
+                              _stream()), "rt_flux_grad")
 
 
 class FluxGrad:
     """One smoothed-flux evaluation and its adjoint, holding the workspace between them.
 
     forward() traces n rays with checkpoints and returns F[n_obs]; backward(gbar) returns
-    sum_j gbar_j dF_j/dp for p = PARAMS (and may be called again with another gbar)."""
+    sum_j gbar_j dF_j/dp for p = PARAMS (and may be called again with another gbar).
+    The checkpoint pool starts at ckpt_pool slots (default two per ray); with
+    grow_pool, forward() reads back how many the rays asked for and, if the pool was too
+    small, enlarges the workspace to fit and runs the forward phase again."""
 
-    def __init__(self, star, tol, seed, n, obs, sigma, ckpt_every=64, max_ckpt=64):
+    def __init__(self, star, tol, seed, n, obs, sigma, ckpt_every=64, max_ckpt=64, ckpt_pool=None,
+                 grow_pool=True):
         import numpy as np
         dev = _device()
         self.star, self.tol, self.seed, self.n = dict(star), dict(tol), int(seed), int(n)
         self.obs = np.ascontiguousarray(np.asarray(obs, dtype=np.float64).reshape(-1, 3))
         self.sigma, self.ckpt_every, self.max_ckpt = float(sigma), int(ckpt_every), int(max_ckpt)
-        nbytes = flux_grad_workspace_size(self.n, self.obs.shape[0], self.ckpt_every, self.max_ckpt)
-        if nbytes == 0:
-            raise RtError("rt_flux_grad: invalid sizes")
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ckpt_pool = default_ckpt_pool(self.n) if ckpt_pool is None else int(ckpt_pool)
+        self.grow_pool = bool(grow_pool)
         self.flux = torch.empty(self.obs.shape[0], dtype=torch.float64, device=dev)
         self.grad = torch.empty(6, dtype=torch.float64, device=dev)
+        self.ckpt_used = torch.zeros(1, dtype=torch.int64, device=dev)
+        self._alloc()
+
+    def _alloc(self):
+        nbytes = flux_grad_workspace_size(self.n, self.obs.shape[0], self.ckpt_every, self.ckpt_pool)
+        if nbytes == 0:
+            raise RtError("rt_flux_grad: invalid sizes")
+        self.ws = None
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.flux.device)
 
     def _call(self, phase, **kw):
         rt_flux_grad(self.star, self.tol, self.seed, self.n, self.obs, self.sigma, phase, self.ws,
-                     self.ckpt_every, self.max_ckpt, **kw)
+                     self.ckpt_every, self.max_ckpt, self.ckpt_pool, **kw)
 
     def forward(self, ray_info: bool = False):
         info = torch.empty((RT_NIFIN, self.n), dtype=torch.int32, device=self.flux.device) if ray_info else None
-        self._call(0, flux=self.flux, ray_info=info)
+        self._call(0, flux=self.flux, ray_info=info, ckpt_used=self.ckpt_used)
+        if self.grow_pool:
+            used = int(self.ckpt_used.item())
+            if used > self.ckpt_pool:
+                if used > CKPT_POOL_MAX:
+                    raise RtError(f"rt_flux_grad: the rays need {used} checkpoints, above {CKPT_POOL_MAX}")
+                self.ckpt_pool = used
+                self._alloc()
+                self._call(0, flux=self.flux, ray_info=info, ckpt_used=self.ckpt_used)
         return (self.flux, info) if ray_info else self.flux
 
     def backward(self, gbar: torch.Tensor, per_ray: bool = False):

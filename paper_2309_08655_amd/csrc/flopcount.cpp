@@ -1,6 +1,6 @@
 // Static FP64 operation count of the tracer's arithmetic, obtained by running
 // the device templates (gradient of H, one DOPRI5 attempt, the adjoint's stage
-// products in 7-tangent dual numbers) on the host with a counting scalar.
+// products in dual numbers) on the host with a counting scalar.
 // Convention: +, -, x each 1; fused multiply-add 2; division, reciprocal,
 // square root, pow 1 each; sin and cos 1 each; negation, |.|, max/min,
 // comparisons 0.  Prints one JSON object keyed by the physics variant.
@@ -73,18 +73,23 @@ int main() {
                 auto fn = [&](const FC* yy, FC* ff) { rhs(I, yy, ff, 1.0); };
                 dopri_attempt(fn, y, S, FC(0.1), ynew, 1e-8, 1e-12);
                 long long fstep = g_flops + 3;  // + step-size update (pow, x0.9, x h)
-                // adjoint: one stage vector-Jacobian product (dual-number Hessian-vector product
-                // with 3 parameter-channel tangents plus the vacuum part) and the reverse sweep
-                // through the six stages of a step
-                FC v[8], vy[8], vc[5], Ys[48], Kb[48], yb[8], tc[5];
-                for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); }
-                for (int d = 0; d < 48; ++d) { Ys[d] = y[d % 8]; Kb[d] = FC(0.01 * d); }
+                // adjoint: one stage vector-Jacobian product (a 1-tangent dual-number
+                // Hessian-vector product, a 3-tangent pass for the parameter channels and the
+                // vacuum part) and the reverse sweep through the six stages of a plain step
+                FC v[8], vy[8], vc[5], ybuf[LY_SLOTS], wbuf[LW_SLOTS], yb[8], ynb[8], tc[5], gyf[8], dc[7];
+                for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); ynb[d] = FC(0.01 * d); }
+                for (int d = 0; d < LY_SLOTS; ++d) ybuf[d] = y[d % 8];
+                for (int d = 0; d < LW_SLOTS; ++d) wbuf[d] = FC(0.0);
+                for (int d = 0; d < 8; ++d) gyf[d] = FC(0.0);
+                for (int d = 0; d < 7; ++d) dc[d] = FC(0.0);
                 for (int q = 0; q < 5; ++q) tc[q] = FC(0.0);
                 g_flops = 0;
-                rhs_vjp<FC>(I, y, v, vy, vc);
+                stage_vjp<false, FC>(I, y, v, vy, vc);
                 long long fvjp = g_flops;
                 g_flops = 0;
-                stages_adjoint<FC>(I, Ys, FC(0.1), Kb, yb, tc);
+                step_adjoint<false, FC>(I, y, ynew, FC(0.1), false, gyf, dc, ynb, yb, tc,
+                                        [&](int k) -> FC& { return ybuf[k]; },
+                                        [&](int k) -> FC& { return wbuf[k]; }, 0.0);
                 long long fstages = g_flops;
                 // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension
                 FC yt[8];

@@ -17,10 +17,14 @@
 //   y_{n+1} = y_n + h sum_i b_i K_i,  K_i = f(Y_i),  Y_i = y_n + h sum_{j<i} a_ij K_j.
 // Stage vector-Jacobian products: with f = J grad(H), J = [[0, I], [-I, 0]],
 //   v^T df/dy = Hess(H) (J^T v), one directional derivative of the hand-derived
-//   gradient in dual numbers, and v^T df/dp from 6 more tangents.
-// Memory: (y, h, facmax) is checkpointed every C accepted steps; the reverse
+//   gradient in dual numbers, and v^T df/dp through the few instance constants that
+//   carry the parameters (a second, three-tangent pass).
+// Memory: (y, h, facmax) is checkpointed every C accepted steps into a pool shared by all
+// rays (slots handed out in order of need; each ray's checkpoints form a chain from its last
+// back to its first), so the pool holds what the rays need, not a worst case; the reverse
 // sweep recomputes each segment from its checkpoint into a per-lane replay
-// buffer and walks it backwards.  This file is compiled with multiply-add fusion
+// buffer and walks it backwards, one step at a time, with the step's stage states
+// and their adjoints in LDS (80 doubles a lane: 40 KB for a wave of 64).  This file is compiled with multiply-add fusion
 // decided per source expression only (-ffp-contract=on), so the forward pass and the
 // recompute, which inline the same step code, produce the same bits; a ray whose
 // recompute does not end exactly on its next checkpoint gets a NaN gradient share.
@@ -45,16 +49,20 @@ struct AdjWs {
     double* fin;      // [RT_NFIN][n] written by the trace set-up for rays it does not trace
     int32_t* ifin;    // [RT_NIFIN][n]: n_acc, n_rej, status
     int32_t* nseg;    // [n] checkpoints stored
+    int32_t* ckhead;  // [n] pool slot of each ray's last checkpoint
     double* theta;    // [n] location of r = r_max on the last step
-    double* ckpt;     // [max_ckpt][11][n]: y[8], h, facmax, gjs
-    WorkCtr* rctr;    // reverse pass: head of the work list, seal, iters = steps the recompute missed
+    double* pool;     // [ckpt_pool][CK_SLOT]: y[8], h, facmax, gjs, slot of the ray's previous checkpoint
+    WorkCtr* rctr;    // reverse pass: head of the work list, seal (pad[0]), pool slots asked for
+                      // (pad[1]), iters = steps the recompute missed
     double* obs;      // [n_obs][3]
     double* facc;     // [MAX_OBS] flux accumulators
     double* gacc;     // [8] gradient accumulators
     double* replay;   // [C * 11][REV_LANES]
 };
 
-static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int32_t Kc, AdjWs* W) {
+constexpr int CK_SLOT = 12;  // doubles per checkpoint slot
+
+static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int64_t ckpt_pool, AdjWs* W) {
     char* p = (char*)base;
     auto take = [&](size_t bytes) {
         char* q = p;
@@ -67,8 +75,9 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
     char* fin = take(sizeof(double) * RT_NFIN_ * (size_t)n);
     char* ifin = take(sizeof(int32_t) * RT_NIFIN_ * (size_t)n);
     char* nseg = take(sizeof(int32_t) * (size_t)n);
+    char* ckhead = take(sizeof(int32_t) * (size_t)n);
     char* theta = take(sizeof(double) * (size_t)n);
-    char* ckpt = take(sizeof(double) * 11 * (size_t)Kc * (size_t)n);
+    char* pool = take(sizeof(double) * CK_SLOT * (size_t)ckpt_pool);
     char* rctr = take(sizeof(WorkCtr));
     char* obs = take(sizeof(double) * 3 * (size_t)n_obs);
     char* facc = take(sizeof(double) * MAX_OBS);
@@ -81,8 +90,9 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
         W->fin = (double*)fin;
         W->ifin = (int32_t*)ifin;
         W->nseg = (int32_t*)nseg;
+        W->ckhead = (int32_t*)ckhead;
         W->theta = (double*)theta;
-        W->ckpt = (double*)ckpt;
+        W->pool = (double*)pool;
         W->rctr = (WorkCtr*)rctr;
         W->obs = (double*)obs;
         W->facc = (double*)facc;
@@ -93,14 +103,20 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 }
 
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
-// cost-ordered work list; checkpoints, per-ray counters and the flux.  LARMOR fixes the
-// finite-magnetisation switch at compile time (the strong-field kernel carries none of it).
+// cost-ordered work list; checkpoints, per-ray counters and the flux.  Each checkpoint takes
+// the next free pool slot (one atomic per wave for the lanes storing together) and links
+// to the ray's previous one; a request beyond the pool is counted but not stored (the
+// count then tells the caller the pool it needs, and the reverse pass refuses to run).
+// LARMOR fixes the finite-magnetisation switch at compile time (the strong-field kernel
+// carries none of it).
 template <bool LARMOR>
 __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
                                                       const double* __restrict__ y0q, const double* __restrict__ h0s,
-                                                      int C, int Kc,
-                                                      double* __restrict__ ckpt, int32_t* __restrict__ nseg_out,
+                                                      int C, int Kc, double* __restrict__ pool,
+                                                      long long ckpt_pool, int32_t* __restrict__ ckhead,
+                                                      unsigned long long* __restrict__ pool_next,
+                                                      int32_t* __restrict__ nseg_out,
                                                       double* __restrict__ theta_out, int32_t* __restrict__ ifin,
                                                       const double* __restrict__ obs, int n_obs, double sigma,
                                                       double* __restrict__ facc) {
@@ -113,12 +129,27 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
     const unsigned long long nlist = ctr->len;
     bool active = false, exhausted = false;
     int64_t j = 0;
+    int32_t head = -1;  // pool slot of the ray's last checkpoint (-2: a request found the pool full)
     AdjRay R;
     auto store = [&](int s, const double* y, double h, double facmax, double gjs) {
-        for (int d = 0; d < 8; ++d) ckpt[((int64_t)s * 11 + d) * n + j] = y[d];
-        ckpt[((int64_t)s * 11 + 8) * n + j] = h;
-        ckpt[((int64_t)s * 11 + 9) * n + j] = facmax;
-        ckpt[((int64_t)s * 11 + 10) * n + j] = gjs;
+        const unsigned long long storing = __ballot(1);
+        const int leader = __ffsll((long long)storing) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(pool_next, (unsigned long long)__popcll(storing));
+        base = __shfl(base, leader);
+        const unsigned long long slot = base + (unsigned long long)__popcll(storing & below);
+        if (s == 0) head = -1;
+        if (slot < (unsigned long long)ckpt_pool && head != -2) {
+            double* c = pool + (int64_t)slot * CK_SLOT;
+            for (int d = 0; d < 8; ++d) c[d] = y[d];
+            c[8] = h;
+            c[9] = facmax;
+            c[10] = gjs;
+            c[11] = (double)head;
+            head = (int32_t)slot;
+        } else {
+            head = -2;
+        }
     };
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -152,6 +183,7 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
             ifin[n + j] = R.nrej;
             ifin[2 * n + j] = status;
             nseg_out[j] = R.nseg;
+            ckhead[j] = head;
             if (status == ST_ESCAPED) {
                 theta_out[j] = th;
                 const double w = rays[8 * n + j];
@@ -189,17 +221,24 @@ __global__ void adj_scale_kernel(const double* acc, int m, double s, double* out
 
 // Seal of a completed forward phase: a word derived from the arguments that shape the
 // workspace.  The reverse kernel does nothing unless it finds the seal of its own
-// arguments (a reverse call on a workspace without its forward phase).
-static unsigned long long adj_seal(int64_t n, int32_t n_obs, int32_t C, int32_t Kc) {
+// arguments (a reverse call on a workspace without its forward phase, or after a forward
+// phase whose checkpoints did not fit the pool).
+static unsigned long long adj_seal(int64_t n, int32_t n_obs, int32_t C, int32_t Kc, int64_t ckpt_pool) {
     unsigned long long h = 0x9e3779b97f4a7c15ull;
-    const unsigned long long v[4] = {(unsigned long long)n, (unsigned long long)n_obs, (unsigned long long)C,
-                                     (unsigned long long)Kc};
-    for (int i = 0; i < 4; ++i) h = (h ^ v[i]) * 0x100000001b3ull;
+    const unsigned long long v[5] = {(unsigned long long)n, (unsigned long long)n_obs, (unsigned long long)C,
+                                     (unsigned long long)Kc, (unsigned long long)ckpt_pool};
+    for (int i = 0; i < 5; ++i) h = (h ^ v[i]) * 0x100000001b3ull;
     return h;
 }
 
-__global__ void adj_set_seal_kernel(WorkCtr* rctr, unsigned long long seal) {
-    if (threadIdx.x == 0) rctr->pad[0] = seal;
+// seals the forward phase if its checkpoints fit the pool; reports the slots asked for
+__global__ void adj_set_seal_kernel(WorkCtr* rctr, unsigned long long seal, long long ckpt_pool,
+                                    long long* ckpt_used) {
+    if (threadIdx.x == 0) {
+        const unsigned long long asked = rctr->pad[1];
+        rctr->pad[0] = (asked <= (unsigned long long)ckpt_pool) ? seal : 0ull;
+        if (ckpt_used) *ckpt_used = (long long)asked;
+    }
 }
 
 __global__ void adj_bad_seal_kernel(const WorkCtr* rctr, unsigned long long seal, double* grad) {
@@ -215,6 +254,7 @@ __global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int 
         if (clear_list) {
             rctr->len = 0ull;
             rctr->pad[0] = 0ull;
+            rctr->pad[1] = 0ull;
         }
     }
 }
@@ -226,7 +266,8 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
                                                      const int32_t* __restrict__ ifin,
                                                      const int32_t* __restrict__ nseg_in,
                                                      const double* __restrict__ theta_in,
-                                                     const double* __restrict__ ckpt, int C, WorkCtr* rctr,
+                                                     const double* __restrict__ pool, long long ckpt_pool,
+                                                     const int32_t* __restrict__ ckhead, int C, WorkCtr* rctr,
                                                      const WorkCtr* lctr, const int32_t* __restrict__ rlist,
                                                      const double* __restrict__ obs,
                                                      int n_obs, double sigma, const double* __restrict__ gbar,
@@ -242,6 +283,12 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     unsigned long long missing = 0;
     const unsigned long long rlen = lctr->len < (unsigned long long)n ? lctr->len : (unsigned long long)n;
     auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 11 + d) * REV_LANES + lane_g]; };
+    // the walked step's stage states and their adjoints in LDS (one wave a block: 40 KB, so
+    // that four blocks, one a SIMD, fill a CU's 160 KB)
+    __shared__ double ysh[LY_SLOTS * 64];
+    __shared__ double wsh[LW_SLOTS * 64];
+    auto ly = [&](int k) -> double& { return ysh[k * 64 + threadIdx.x]; };
+    auto lw = [&](int k) -> double& { return wsh[k * 64 + threadIdx.x]; };
     const int lane = __lane_id();
     while (true) {
         // the wave takes 64 consecutive rays of the step-ordered list
@@ -255,15 +302,37 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
         if (j < 0 || j >= n) continue;
         const int S = ifin[j], nseg = nseg_in[j];
         if (nseg < 1 || nseg > Kc || S < 1 || S > nseg * C) continue;
+        // the sweep reads checkpoint s, then s + 1 (the end check), then s - 1 ...: walk the
+        // ray's chain from its last checkpoint back, keeping the slot of the one after
+        int32_t cur = ckhead[j], nxt = -1;
+        int cur_s = nseg - 1;
+        bool chain_ok = true;
+        auto in_pool = [&](int32_t sl) { return sl >= 0 && (long long)sl < ckpt_pool; };
         auto load = [&](int s, double* y, double* h, double* facmax, double* gjs) {
-            for (int d = 0; d < 8; ++d) y[d] = ckpt[((int64_t)s * 11 + d) * n + j];
-            *h = ckpt[((int64_t)s * 11 + 8) * n + j];
-            *facmax = ckpt[((int64_t)s * 11 + 9) * n + j];
-            *gjs = ckpt[((int64_t)s * 11 + 10) * n + j];
+            if (s == cur_s - 1) {
+                nxt = cur;
+                cur = in_pool(cur) ? (int32_t)pool[(int64_t)cur * CK_SLOT + 11] : -1;
+                cur_s = s;
+            }
+            const int32_t sl = (s == cur_s) ? cur : ((s == cur_s + 1) ? nxt : -1);
+            if (!in_pool(sl)) {
+                chain_ok = false;
+                for (int d = 0; d < 8; ++d) y[d] = __builtin_nan("");
+                *h = __builtin_nan("");
+                *facmax = 10.0;
+                *gjs = 0.0;
+                return;
+            }
+            const double* c = pool + (int64_t)sl * CK_SLOT;
+            for (int d = 0; d < 8; ++d) y[d] = c[d];
+            *h = c[8];
+            *facmax = c[9];
+            *gjs = c[10];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        const int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, obs,
-                                         gbar, n_obs, sigma, pb);
+        int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, ly, lw,
+                                           obs, gbar, n_obs, sigma, pb);
+        if (!chain_ok) ++miss;
         if (miss) {
             // the recompute did not reproduce the forward pass: no gradient for this ray
             missing += (unsigned long long)miss;
@@ -285,9 +354,10 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
 
 using namespace rtd;
 
-extern "C" size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int32_t max_ckpt) {
-    if (n < 0 || n_obs <= 0 || n_obs > MAX_OBS || ckpt_every <= 0 || max_ckpt <= 0) return 0;
-    return adj_ws_layout(nullptr, n, n_obs, ckpt_every, max_ckpt, nullptr);
+extern "C" size_t rt_flux_grad_workspace_size(int64_t n, int32_t n_obs, int32_t ckpt_every, int64_t ckpt_pool) {
+    if (n < 0 || n_obs <= 0 || n_obs > MAX_OBS || ckpt_every <= 0 || ckpt_pool <= 0 || ckpt_pool > INT32_MAX)
+        return 0;
+    return adj_ws_layout(nullptr, n, n_obs, ckpt_every, ckpt_pool, nullptr);
 }
 
 __global__ void adj_ray_info_kernel(const int32_t* __restrict__ ifin, int64_t n, int32_t* __restrict__ out) {
@@ -296,9 +366,9 @@ __global__ void adj_ray_info_kernel(const int32_t* __restrict__ ifin, int64_t n,
 }
 
 extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
-                            int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int32_t phase,
-                            const double* gbar, double* flux, double* grad, double* grad_rays, int32_t* ray_info,
-                            void* ws, size_t ws_bytes, void* stream) {
+                            int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int64_t ckpt_pool,
+                            int32_t phase, const double* gbar, double* flux, double* grad, double* grad_rays,
+                            int32_t* ray_info, int64_t* ckpt_used, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     if (!validate_star(star) || !validate_tol(tol)) return RT_EINVAL;
     if (n <= 0 || n > INT32_MAX) return fail(RT_EINVAL, "rt_flux_grad: n must be in [1, 2^31 - 1]");
@@ -306,15 +376,18 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(RT_EINVAL, "rt_flux_grad: sigma must be positive");
     if (ckpt_every <= 0 || ckpt_every > 1024 || max_ckpt <= 0)
         return fail(RT_EINVAL, "rt_flux_grad: need 1 <= ckpt_every <= 1024 and max_ckpt >= 1");
+    if (ckpt_pool <= 0 || ckpt_pool > INT32_MAX)
+        return fail(RT_EINVAL, "rt_flux_grad: need 1 <= ckpt_pool <= 2^31 - 1");
     if (star->weights == RT_WEIGHTS_CONST_B) return fail(RT_EUNSUPPORTED, "rt_flux_grad: constant-B test weights");
     if (star->flags & RT_FLAG_FLAT_PROPAGATION)
         return fail(RT_EUNSUPPORTED, "rt_flux_grad: flat-propagation variant");
     if (phase != 0 && phase != 1) return fail(RT_EINVAL, "rt_flux_grad: phase must be 0 (forward) or 1 (reverse)");
-    const size_t need = rt_flux_grad_workspace_size(n, n_obs, ckpt_every, max_ckpt);
+    const size_t need = rt_flux_grad_workspace_size(n, n_obs, ckpt_every, ckpt_pool);
     if (!ws || ws_bytes < need) return fail(RT_ENOWS, "rt_flux_grad: workspace too small");
     hipStream_t st = (hipStream_t)stream;
     AdjWs W;
-    adj_ws_layout(ws, n, n_obs, ckpt_every, max_ckpt, &W);
+    adj_ws_layout(ws, n, n_obs, ckpt_every, ckpt_pool, &W);
+    unsigned long long* pool_next = &W.rctr->pad[1];
     InstT<double> I = make_inst(*star);
     I.oblique = 1;  // the rotating-axis formula throughout (exact at theta_m = 0, and theta_m tangents flow)
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
@@ -335,12 +408,12 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         if (I.larmor)
             hipLaunchKernelGGL(adj_fwd_kernel<true>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
-                               sigma, W.facc);
+                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.pool, (long long)ckpt_pool, W.ckhead,
+                               pool_next, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma, W.facc);
         else
             hipLaunchKernelGGL(adj_fwd_kernel<false>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.ckpt, W.nseg, W.theta, W.ifin, W.obs, n_obs,
-                               sigma, W.facc);
+                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.pool, (long long)ckpt_pool, W.ckhead,
+                               pool_next, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma, W.facc);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");
         if (rc) return rc;
@@ -352,7 +425,8 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         hipLaunchKernelGGL(adj_scale_kernel, dim3(1), dim3(64), 0, st, W.facc, n_obs, 1.0 / (double)n, flux);
         hipLaunchKernelGGL(adj_set_seal_kernel, dim3(1), dim3(64), 0, st, W.rctr,
-                           adj_seal(n, n_obs, ckpt_every, max_ckpt));
+                           adj_seal(n, n_obs, ckpt_every, max_ckpt, ckpt_pool), (long long)ckpt_pool,
+                           (long long*)ckpt_used);
         rc = check_launch("adj_set_seal_kernel");
         if (rc || !ray_info) return rc;
         hipLaunchKernelGGL(adj_ray_info_kernel, dim3(grid_for(3 * n, 256, 8)), dim3(256), 0, st, W.ifin, n, ray_info);
@@ -367,17 +441,17 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         rc = check_launch("fill_kernel");
         if (rc) return rc;
     }
-    const unsigned long long seal = adj_seal(n, n_obs, ckpt_every, max_ckpt);
+    const unsigned long long seal = adj_seal(n, n_obs, ckpt_every, max_ckpt, ckpt_pool);
     ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
     StarFixed fx = star_fixed(*star);
     timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
     if (I.larmor)
         hipLaunchKernelGGL(adj_rev_kernel<true>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
-                           W.ifin, W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
+                           W.ifin, W.nseg, W.theta, W.pool, (long long)ckpt_pool, W.ckhead, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
                            sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
     else
         hipLaunchKernelGGL(adj_rev_kernel<false>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
-                           W.ifin, W.nseg, W.theta, W.ckpt, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
+                           W.ifin, W.nseg, W.theta, W.pool, (long long)ckpt_pool, W.ckhead, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
                            sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
     timing_end(st);
     rc = check_launch("adj_rev_kernel");

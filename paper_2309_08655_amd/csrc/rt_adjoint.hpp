@@ -63,12 +63,16 @@ RT_HD void adj_rhs(const InstT<double>& I, const double* y, double* f, double gj
 }
 
 // One DOPRI5 attempt from y with K[0..7] = f(y) set; fills K[8..55] (stages 2..7,
-// the last = f(ynew)), ynew and, if Ys != nullptr, the stage states Ys[0..47]
-// (Ys[0..7] = y).  Applies the step-size controller to *h and *facmax and returns
-// 1 if the step is accepted.
-template <bool FL = true>
+// the last = f(ynew)) and ynew, and hands each inner stage state Y_i (i = 2..6) to
+// stages(i, Y_i) (NoStages: to nobody).  Applies the step-size controller to *h and
+// *facmax and returns 1 if the step is accepted.
+struct NoStages {
+    RT_HD void operator()(int, const double*) const {}
+};
+
+template <bool FL = true, class Sink>
 RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
-                      double* h, double* facmax, double* Ys, double gjs = 0.0) {
+                      double* h, double* facmax, Sink&& stages, double gjs = 0.0) {
     using namespace dp5;
     const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
                             {a31, a32, 0, 0, 0, 0},
@@ -79,8 +83,6 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
     const double hh = *h;
     const AxisRef ref0 = axis_ref_at(I, y[3]);
     double tmp[8];
-    if (Ys)
-        for (int d = 0; d < 8; ++d) Ys[d] = y[d];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
 #pragma unroll
@@ -91,8 +93,7 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
             tmp[d] = y[d] + hh * acc;
         }
         if (s < 5) {
-            if (Ys)
-                for (int d = 0; d < 8; ++d) Ys[(s + 1) * 8 + d] = tmp[d];
+            stages(s + 2, tmp);
         } else {
             for (int d = 0; d < 8; ++d) ynew[d] = tmp[d];
         }
@@ -274,7 +275,7 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
                        double* theta) {
     double ynew[8];
     const double hused = R.h;
-    if (!adj_attempt<FL>(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, nullptr, R.gjs)) {
+    if (!adj_attempt<FL>(I, tol.rtol, tol.atol, R.y, R.K, ynew, &R.h, &R.facmax, NoStages{}, R.gjs)) {
         ++R.nrej;
         return (fabs(R.h) >= 1e-14 * (1.0 + fabs(R.lam))) ? ST_OK : ST_STEP_UNDERFLOW;
     }
@@ -315,19 +316,6 @@ RT_HD int adj_ray_step(const InstT<double>& I, const TolC& tol, int C, int Kc, A
 // ----------------------------------------------------------------------------
 // reverse sweep
 // ----------------------------------------------------------------------------
-// The right-hand side depends on the star parameters only through the instance
-// constants rs, Om, (cos, sin) theta_m and the plasma coefficient Cwp R^3, and it is
-// linear in the last: H = H_vac + P or H_vac + P (1 - K) with P proportional to Cwp R^3.
-// The parameter part of a stage product is therefore v^T df/dp = sum_c T_c M_cp over
-// four channels c: the tangents of rs, Om and theta_m (dual numbers) and the plasma
-// channel T = v.(f - f_vac) with its log-derivative.  M (4 x 6) is computed once from
-// the instance constants in 6-tangent dual numbers.
-template <class S = double>
-struct VjpInst {
-    InstT<gdual<4, S>> I4;  // slot 0: state direction; slots 1..3: rs, Om, theta_m
-    InstT<S> Ivac;          // the same star without plasma
-};
-
 // What the reverse sweep of a ray needs besides the double instance: the parameter
 // values, from which each dual-number instance is built where it is used (so that no
 // dual instance stays live, in registers, across the sweep).
@@ -335,20 +323,6 @@ struct AdjParams {
     double p[6];
     StarFixed fx;
 };
-
-template <class S>
-RT_HD VjpInst<S> make_vjp_inst(const InstT<S>& I) {
-    typedef gdual<4, S> D4;
-    VjpInst<S> V;
-    V.I4 = lift_inst<D4>(I);
-    V.I4.rs.d[1] = S(1.0);
-    V.I4.Om.d[2] = S(1.0);
-    V.I4.cm.d[3] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
-    V.I4.sm.d[3] = I.cm;
-    V.Ivac = I;
-    V.Ivac.density = DEN_NONE;
-    return V;
-}
 
 RT_HD void make_adj_params(const double p[6], const StarFixed& fx, AdjParams& A) {
     for (int q = 0; q < 6; ++q) A.p[q] = p[q];
@@ -407,141 +381,222 @@ RT_HD_NOINLINE void seed_and_channels(const AdjParams& A, uint64_t seed, int64_t
     }
 }
 
-// Finite magnetisation (Sec. 4.1 eq. (DisRel)): H is no longer linear in the plasma
-// coefficient and depends on the cyclotron coefficient kL (which carries B0, R^6 and
-// 1/w_inf^2), so both become tangents: slots 1..3 rs, Om, theta_m as below, slot 4 log(Cwp)
-// (which moves P exactly as log(Cwp R^3) does) and slot 5 log(kL); vc[3] and vc[4] are
-// those channels.
-template <class S = double>
-RT_HD_NOINLINE void rhs_vjp_larmor(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
-    typedef gdual<6, S> DS;
-    InstT<DS> J = lift_inst<DS>(I);
-    J.rs.d[1] = S(1.0);
-    J.Om.d[2] = S(1.0);
-    J.cm.d[3] = S(0.0) - I.sm;
-    J.sm.d[3] = I.cm;
-    J.Cwp.d[4] = I.Cwp;
-    J.kL.d[5] = I.kL;
-    DS yd[8], fd[8];
-    for (int i = 0; i < 4; ++i) {
-        yd[i] = DS(Y[i]);
-        yd[i].d[0] = S(0.0) - v[4 + i];
-        yd[4 + i] = DS(Y[4 + i]);
-        yd[4 + i].d[0] = v[i];
-    }
-    rhs(J, yd, fd, 1.0, nullptr, gjs);
-    for (int i = 0; i < 4; ++i) {
-        vy[i] = S(0.0) - fd[4 + i].d[0];
-        vy[4 + i] = fd[i].d[0];
-    }
-    for (int c = 0; c < 5; ++c) {
-        S a = v[0] * fd[0].d[1 + c];
-        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + c];
-        vc[c] = a;
-    }
-}
+// ----------------------------------------------------------------------------
+// stage vector-Jacobian products
+// ----------------------------------------------------------------------------
+// With f = J grad(H), J = [[0, I], [-I, 0]] and Hess(H) symmetric,
+//   v^T df/dy = Hess(H) u,  u = J^T v,
+// one directional derivative of the hand-derived gradient: a pass in dual numbers with
+// one tangent.  The star parameters enter f only through the instance constants rs, Om,
+// (cos, sin) theta_m, the plasma coefficient Cwp R^3 and, with finite magnetisation, the
+// cyclotron coefficient kL, so v^T df/dp = sum_c T_c dc/dp over the channels
+// T_c = v^T df/dc = u . grad(dH/dc) (seed_and_channels maps them to p):
+//   Om: H depends on Om and t only through the axis phase Om t, so dH/dOm = (t/Om) dH/dt
+//     and T_Om = (u_t dH/dt + t (Hess(H) u)_t) / Om, from the first pass alone;
+//   rs, theta_m: a pass with two tangents;
+//   log(Cwp R^3): the strong-field Hamiltonian is linear in P, proportional to Cwp R^3
+//     (H = H_vac + P or H_vac + P (1 - K)), so T = v.(f - f_vac) (f from the first pass);
+//   with finite magnetisation (Sec. 4.1 eq. (DisRel)) H is not linear in P and depends
+//     on kL: log(Cwp) (which moves P as log(Cwp R^3) does) and log(kL) by a pass with
+//     two tangents.
+// The passes run one after another so that few dual values are live at once.
+// FL = false: the strong-field Hamiltonian, fixed at compile time.
 
-// v^T df/dy (vy) and the channels vc[0..4] of v^T df/dp at the state Y (S = double;
-// generic for the host operation counter); vc[4] (the cyclotron coefficient) is zero for
-// the strong-field Hamiltonian
-template <class S = double>
-RT_HD_NOINLINE void rhs_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
-    if (I.larmor) {
-        rhs_vjp_larmor<S>(I, Y, v, vy, vc, gjs);
-        return;
-    }
-    typedef gdual<4, S> DS;
-    VjpInst<S> V = make_vjp_inst<S>(I);
-    V.I4.larmor = 0;  // the strong-field Hamiltonian from here on (its terms fold away)
-    V.Ivac.larmor = 0;
-    DS yd[8], fd[8];
+// v^T df/dy (vy) and f(Y)
+template <bool FL, class S>
+RT_HD void vjp_state(const InstT<S>& I, const S* Y, const S* v, S* vy, S* f, double gjs) {
+    typedef gdual<1, S> D1;
+    InstT<D1> J = lift_inst<D1>(I);
+    if constexpr (!FL) J.larmor = 0;
+    D1 yd[8], fd[8];
     for (int i = 0; i < 4; ++i) {
-        yd[i] = DS(Y[i]);
-        yd[i].d[0] = S(0.0) - v[4 + i];  // u = J^T v: u_x = -v_k
-        yd[4 + i] = DS(Y[4 + i]);
+        yd[i] = D1(Y[i]);
+        yd[i].d[0] = S(0.0) - v[4 + i];  // u_x = -v_k
+        yd[4 + i] = D1(Y[4 + i]);
         yd[4 + i].d[0] = v[i];  // u_k = v_x
     }
-    rhs(V.I4, yd, fd, 1.0, nullptr, gjs);
-    // the tangent of f is J Hess(H) u; Hess(H) u = J^T (J Hess(H) u)
+    rhs(J, yd, fd, 1.0, nullptr, gjs);
+    // the tangent of f is J Hess(H) u, and Hess(H) u = J^T (J Hess(H) u)
     for (int i = 0; i < 4; ++i) {
         vy[i] = S(0.0) - fd[4 + i].d[0];
         vy[4 + i] = fd[i].d[0];
     }
-    for (int c = 0; c < 3; ++c) {
-        S a = v[0] * fd[0].d[1 + c];
-        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1 + c];
-        vc[c] = a;
-    }
-    // plasma channel: v.(f - f_vac)
-    S fv[8];
-    rhs(V.Ivac, Y, fv, 1.0);
-    S a = v[0] * (fd[0].v - fv[0]);
-    for (int i = 1; i < 8; ++i) a = a + v[i] * (fd[i].v - fv[i]);
-    vc[3] = a;
-    vc[4] = S(0.0);
+    for (int i = 0; i < 8; ++i) f[i] = fd[i].v;
 }
 
-// Adjoint of the six stages of a step: on entry Kb[8 i .. 8 i + 7] holds the
-// adjoint of K_{i+1} (i = 0..5) from the step's outputs; adds to yb and to the
-// parameter channels tc.
-template <class S = double>
-RT_HD void stages_adjoint(const InstT<S>& I, const S* Ys, S h, S* Kb, S* yb, S* tc, double gjs = 0.0) {
+// sum_i v_i (df_i/dc1, df_i/dc2) for the two tangents set on J by the caller
+template <class S>
+RT_HD void vjp_pair(const InstT<gdual<2, S>>& J, const S* Y, const S* v, S* t1, S* t2, double gjs) {
+    typedef gdual<2, S> D2;
+    D2 yd[8], fd[8];
+    for (int i = 0; i < 8; ++i) yd[i] = D2(Y[i]);
+    rhs(J, yd, fd, 1.0, nullptr, gjs);
+    S a = v[0] * fd[0].d[0], b = v[0] * fd[0].d[1];
+    for (int i = 1; i < 8; ++i) {
+        a = a + v[i] * fd[i].d[0];
+        b = b + v[i] * fd[i].d[1];
+    }
+    *t1 = a;
+    *t2 = b;
+}
+
+// The isotropic plasma's share of grad(H) (H = H_vac + P) at (x, t) = y[0..3]: grad P in
+// (x, t), nothing in k; the same terms grad_h assembles, without the vacuum part
+template <class T>
+RT_HD void grad_p(const InstT<T>& I, const T* y, T g[4], double gjs) {
+    if (I.density == DEN_NONE) {
+        for (int i = 0; i < 4; ++i) g[i] = T(0.0);
+        return;
+    }
+    T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    T ir = frsqrt(r2);
+    T n[3] = {y[0] * ir, y[1] * ir, y[2] * ir};
+    T m[3], mt[3];
+    magnetic_axis(I, y[3], m, mt, nullptr);
+    T mu = m[0] * n[0] + m[1] * n[1] + m[2] * n[2];
+    T dmu = I.oblique ? I.Om * (m[0] * n[1] - m[1] * n[0]) : T(0.0);
+    Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu, gjs);
+    for (int i = 0; i < 3; ++i) g[i] = p.pn * n[i] + p.pm * m[i];
+    g[2] = g[2] + p.pz;
+    g[3] = p.pt;
+}
+
+// v^T df/dy (vy) and the channels vc[0..4] = v^T df/dc for c = rs, Om, theta_m, the plasma
+// coefficient and kL (vc[4] = 0 for the strong-field Hamiltonian) at the state Y (S = double;
+// generic for the host operation counter).  With an isotropic plasma (or none) and the
+// strong-field Hamiltonian, H = H_vac + P with rs only in H_vac and theta_m and the plasma
+// coefficient only in P, so rs takes a one-tangent pass through the vacuum part, and theta_m
+// and the plasma channel one through grad P (whose value is the plasma part of f).
+template <bool FL = true, class S = double>
+RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
+    S f[8];
+    vjp_state<FL, S>(I, Y, v, vy, f, gjs);
+    // Om: u_t = -v_7, dH/dt = -f_7, (Hess(H) u)_t = vy_3
+    vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * rcp(I.Om);
+    if (!(FL && I.larmor) && (I.plasma == PL_ISO || I.density == DEN_NONE)) {
+        typedef gdual<1, S> D1;
+        {
+            InstT<D1> J = lift_inst<D1>(I);  // the vacuum part, rs tangent
+            J.density = DEN_NONE;
+            J.larmor = 0;
+            J.rs.d[0] = S(1.0);
+            D1 yd[8], fd[8];
+            for (int i = 0; i < 8; ++i) yd[i] = D1(Y[i]);
+            rhs(J, yd, fd, 1.0);
+            S a = v[0] * fd[0].d[0];
+            for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[0];
+            vc[0] = a;
+        }
+        {
+            InstT<D1> J = lift_inst<D1>(I);  // grad P, theta_m tangent
+            J.larmor = 0;
+            J.cm.d[0] = S(0.0) - I.sm;
+            J.sm.d[0] = I.cm;
+            D1 yd[4], gp[4];
+            for (int i = 0; i < 4; ++i) yd[i] = D1(Y[i]);
+            grad_p(J, yd, gp, gjs);
+            // the plasma part of f is J grad P: -grad P in the k rows
+            S a = v[4] * gp[0].d[0], b = v[4] * gp[0].v;
+            for (int i = 1; i < 4; ++i) {
+                a = a + v[4 + i] * gp[i].d[0];
+                b = b + v[4 + i] * gp[i].v;
+            }
+            vc[2] = S(0.0) - a;
+            vc[3] = S(0.0) - b;
+        }
+        vc[4] = S(0.0);
+        return;
+    }
+    {
+        InstT<gdual<2, S>> J = lift_inst<gdual<2, S>>(I);
+        if constexpr (!FL) J.larmor = 0;
+        J.rs.d[0] = S(1.0);
+        J.cm.d[1] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
+        J.sm.d[1] = I.cm;
+        vjp_pair<S>(J, Y, v, &vc[0], &vc[2], gjs);
+    }
+    if (FL && I.larmor) {
+        InstT<gdual<2, S>> J = lift_inst<gdual<2, S>>(I);
+        J.Cwp.d[0] = I.Cwp;
+        J.kL.d[1] = I.kL;
+        vjp_pair<S>(J, Y, v, &vc[3], &vc[4], gjs);
+    } else {
+        InstT<S> Iv = I;  // the same star without plasma
+        Iv.density = DEN_NONE;
+        Iv.larmor = 0;
+        S fv[8];
+        rhs(Iv, Y, fv, 1.0);
+        S a = v[0] * (f[0] - fv[0]);
+        for (int i = 1; i < 8; ++i) a = a + v[i] * (f[i] - fv[i]);
+        vc[3] = a;
+        vc[4] = S(0.0);
+    }
+}
+
+// Per-lane scratch of the reverse sweep's step adjoint: ly(k), k < LY_SLOTS, holds the stage
+// states Y_i (i = 2..6) of the step being walked at 8 (i - 2) + d, and lw(k), k < LW_SLOTS,
+// the stage-state adjoints w_i (i = 2..6) at 8 (i - 2) + d.
+constexpr int LY_SLOTS = 40;
+constexpr int LW_SLOTS = 40;
+
+// Adjoint of one accepted step y_n -> y_{n+1} through its stages,
+//   Y_l = y_n + h sum_{i<l} a_li K_i,  y_{n+1} = y_n + h sum_i b_i K_i,  K_i = f(Y_i).
+// On entry ly holds Y_2..Y_6 and y7 the step's end y_{n+1} = Y_7, where K_7 = f(Y_7) is taken
+// (read for dense = true only, before the first stage); yb holds the adjoint of y_n from
+// the step's output and ynb that of y_{n+1}; the output's adjoint of K_i is dc[i - 1] gyf
+// (dense = true: the step ends on its continuous extension, whose value depends on
+// K_1..K_7; otherwise the output is y_{n+1} itself and K_7 is not visited).
+// Each stage, last first, takes Kbar_i = dc_i gyf + h b_i ynb + h sum_{l>i} a_li w_l and
+// gives w_i = (df/dy(Y_i))^T Kbar_i, which goes to ynb for i = 7 and to yb otherwise;
+// w_2..w_6 are kept in lw.  Each stage state is read one stage ahead of its use.  On
+// return yb holds the adjoint of y_n; the parameter channels are added to tc.
+template <bool FL, class S, class LaneY, class LaneW>
+RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool dense, const S* gyf, const S* dc,
+                        S* ynb, S* yb, S* tc, LaneY&& ly, LaneW&& lw, double gjs) {
     using namespace dp5;
-    const double A[6][5] = {{0, 0, 0, 0, 0},
-                            {a21, 0, 0, 0, 0},
-                            {a31, a32, 0, 0, 0},
-                            {a41, a42, a43, 0, 0},
-                            {a51, a52, a53, a54, 0},
-                            {a61, a62, a63, a64, a65}};
-    S vy[8], vc[5];
-    for (int i = 5; i >= 0; --i) {
-        rhs_vjp<S>(I, Ys + i * 8, Kb + i * 8, vy, vc, gjs);
+    const double Al[5][5] = {{a21, 0, 0, 0, 0},
+                             {a31, a32, 0, 0, 0},
+                             {a41, a42, a43, 0, 0},
+                             {a51, a52, a53, a54, 0},
+                             {a61, a62, a63, a64, a65}};  // a_li: row l - 2, column i - 1
+    const double Bw[7] = {b1, 0.0, b3, b4, b5, b6, 0.0};
+    S v[8], Y[8], Yn[8], vy[8], vc[5];
+    const int top = dense ? 7 : 6;
+    if (dense) {
+        for (int d = 0; d < 8; ++d) Yn[d] = y7[d];
+    } else {
+        for (int d = 0; d < 8; ++d) Yn[d] = ly(8 * (top - 2) + d);
+    }
+#pragma unroll 1
+    for (int i = 7; i >= 1; --i) {
+        if (i > top) continue;
+        for (int d = 0; d < 8; ++d) Y[d] = Yn[d];
+        if (i > 2) {
+            for (int d = 0; d < 8; ++d) Yn[d] = ly(8 * (i - 3) + d);
+        } else if (i == 2) {
+            for (int d = 0; d < 8; ++d) Yn[d] = yn[d];
+        }
+        const S hb = h * Bw[i - 1];
+        for (int d = 0; d < 8; ++d) v[d] = hb * ynb[d];
+        if (dense)
+            for (int d = 0; d < 8; ++d) v[d] = v[d] + dc[i - 1] * gyf[d];
+#pragma unroll
+        for (int l = 2; l <= 6; ++l) {
+            if (l <= i) continue;
+            const S c = h * Al[l - 2][i - 1];
+            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * lw(8 * (l - 2) + d);
+        }
+        stage_vjp<FL, S>(I, Y, v, vy, vc, gjs);
         for (int c = 0; c < 5; ++c) tc[c] = tc[c] + vc[c];
-        for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
-        for (int jj = 0; jj < i; ++jj) {
-            if (A[i][jj] == 0.0) continue;
-            const S c = h * A[i][jj];
-            for (int d = 0; d < 8; ++d) Kb[jj * 8 + d] = Kb[jj * 8 + d] + c * vy[d];
+        if (i == 7) {
+            for (int d = 0; d < 8; ++d) ynb[d] = ynb[d] + vy[d];
+        } else {
+            for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
+            if (i >= 2)
+                for (int d = 0; d < 8; ++d) lw(8 * (i - 2) + d) = vy[d];
         }
     }
-}
-
-// Adjoint of y(theta) = E(theta) on the continuous extension of the step yn -> ynew (stages
-// K, size hn) at fixed theta: gyf is the adjoint of y(theta); writes the adjoint of yn to
-// yb and of K_1..K_6 to Kb (the part through K_7 = f(ynew) and ynew is taken here), and
-// adds to the parameter channels tc.
-RT_HD_NOINLINE void dense_adjoint(const InstT<double>& I, const double* yn, const double* K, const double* ynew,
-                                  double hn, double t, const double* gyf, double* yb, double* Kb, double* tc,
-                                  double gjs) {
-    using namespace dp5;
-    const double om = 1.0 - t;
-    const double c3 = t * om, c4 = t * t * om, c5 = t * t * om * om, cy = t - c3 + 2.0 * c4;
-    double ynb[8], K7b[8];
-    for (int d = 0; d < 8; ++d) {
-        ynb[d] = cy * gyf[d];
-        yb[d] = (1.0 - cy) * gyf[d];
-        Kb[d] = hn * (c3 - c4 + c5 * d1) * gyf[d];
-        Kb[8 + d] = 0.0;
-        Kb[16 + d] = hn * c5 * d3 * gyf[d];
-        Kb[24 + d] = hn * c5 * d4 * gyf[d];
-        Kb[32 + d] = hn * c5 * d5 * gyf[d];
-        Kb[40 + d] = hn * c5 * d6 * gyf[d];
-        K7b[d] = hn * (c5 * d7 - c4) * gyf[d];
-    }
-    // K7 = f(ynew)
-    double vy[8], vc[5];
-    rhs_vjp<double>(I, ynew, K7b, vy, vc, gjs);
-    for (int d = 0; d < 8; ++d) ynb[d] += vy[d];
-    for (int c = 0; c < 5; ++c) tc[c] += vc[c];
-    // ynew = y + h sum_i b_i K_i
-    for (int d = 0; d < 8; ++d) {
-        yb[d] += ynb[d];
-        Kb[d] += hn * b1 * ynb[d];
-        Kb[16 + d] += hn * b3 * ynb[d];
-        Kb[24 + d] += hn * b4 * ynb[d];
-        Kb[32 + d] += hn * b5 * ynb[d];
-        Kb[40 + d] += hn * b6 * ynb[d];
-    }
+    for (int d = 0; d < 8; ++d) yb[d] = yb[d] + ynb[d];
 }
 
 // E(theta) and dE/dtheta on the continuous extension of the step yn -> ynew
@@ -567,12 +622,13 @@ RT_HD void dense_point_deriv(const double* yn, const double* K, const double* yn
 // Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing of r_max
 // at theta on the last step).  load(s, y, &h, &facmax, &gjs) reads checkpoint s; rb(idx, d)
 // is the replay buffer (C steps x 11 values: y, h, the null-surface crossing thk (2: none)
-// and the piece gjs of the step).  Adds d(w G(y_f))/dp to pb.  Returns the number of
-// steps or checkpoints the recompute could not reproduce (0 when all is well).
-template <bool FL = true, class Load, class Replay>
+// and the piece gjs of the step); ly(k) and lw(k) are the per-lane scratch of step_adjoint.  Adds
+// d(w G(y_f))/dp to pb.  Returns the number of steps or checkpoints the recompute could not
+// reproduce (0 when all is well).
+template <bool FL = true, class Load, class Replay, class LaneY, class LaneW>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
-                          int nseg, double th, double w, int C, Load&& load, Replay&& rb, const double* obs,
-                          const double* gbar, int n_obs, double sigma, double pb[6]) {
+                          int nseg, double th, double w, int C, Load&& load, Replay&& rb, LaneY&& ly, LaneW&& lw,
+                          const double* obs, const double* gbar, int n_obs, double sigma, double pb[6]) {
     using namespace dp5;
     double tc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // parameter channels of the stage products
     double yb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -588,7 +644,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         int stored = 0;
         for (int guard = 0; stored < count && guard < 64 * C; ++guard) {
             const double hused = h;
-            if (!adj_attempt<FL>(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, nullptr, gjs)) continue;
+            if (!adj_attempt<FL>(I, tol.rtol, tol.atol, y, K, ynew, &h, &facmax, NoStages{}, gjs)) continue;
             // the last step ends at r_max (its own crossing test does not matter)
             const double thk = (first + stored == S - 1) ? 2.0 : adj_null_crossing(I, y, K, ynew, hused, gjs);
             for (int d = 0; d < 8; ++d) rb(stored, d) = y[d];
@@ -609,22 +665,30 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         }
         // walk the segment backwards
         for (int idx = stored - 1; idx >= 0; --idx) {
-            double yn[8], Ys[48], Kb[48];
+            double yn[8];
             for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
             const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
+            // the step's stages again, its inner stage states into ly
             double hdummy = hn, fdummy = 10.0;
             adj_rhs<FL>(I, yn, K, gn);
-            adj_attempt<FL>(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy, Ys, gn);
-            if (first + idx == S - 1 || thk <= 1.0) {
+            adj_attempt<FL>(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy,
+                            [&](int i, const double* Yi) {
+                                for (int d = 0; d < 8; ++d) ly(8 * (i - 2) + d) = Yi[d];
+                            },
+                            gn);
+            const bool last = (first + idx == S - 1);
+            const bool dense = last || thk <= 1.0;
+            double ynb[8], gyf[8], dc[7];
+            if (dense) {
                 // the step ends inside, at E(theta): y_f at r(E) = r_max, or the restart
                 // point on the null surface g(E) = 0.  The adjoint of E(theta) loses its
                 // component along dE/dtheta against the surface's gradient q:
                 //   beta = (ybar . dE/dtheta) / (q . dE/dtheta),  ybar -= beta q,
                 // and for g the parameters' part -beta dg/dp joins the channels.
-                const double t = (first + idx == S - 1) ? th : thk;
-                double e[8], et[8], gyf[8], q[4], gOm = 0.0, gth = 0.0;
+                const double t = last ? th : thk;
+                double e[8], et[8], q[4], gOm = 0.0, gth = 0.0;
                 dense_point_deriv(yn, K, ynew, hn, t, e, et);
-                if (first + idx == S - 1) {
+                if (last) {
                     // the observable with 8 state and 6 parameter tangents
                     double gp[6];
                     wG = observable_grad(A, e, obs, gbar, n_obs, sigma, gyf, gp);
@@ -643,19 +707,31 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 for (int d = 0; d < 4; ++d) gyf[d] -= beta * q[d];
                 tc[1] -= beta * gOm;
                 tc[2] -= beta * gth;
-                dense_adjoint(I, yn, K, ynew, hn, t, gyf, yb, Kb, tc, gn);
-            } else {
-                // y_{n+1} = y_n + h sum_i b_i K_i; yb holds the adjoint of y_{n+1}
+                // E(theta) = (1 - cy) y_n + cy y_{n+1} + h sum_i dc_i K_i (nested form of the
+                // continuous extension): its adjoint to y_n, y_{n+1} and each K_i
+                const double om = 1.0 - t;
+                const double c3 = t * om, c4 = t * t * om, c5 = t * t * om * om, cy = t - c3 + 2.0 * c4;
+                dc[0] = hn * (c3 - c4 + c5 * d1);
+                dc[1] = 0.0;
+                dc[2] = hn * c5 * d3;
+                dc[3] = hn * c5 * d4;
+                dc[4] = hn * c5 * d5;
+                dc[5] = hn * c5 * d6;
+                dc[6] = hn * (c5 * d7 - c4);
                 for (int d = 0; d < 8; ++d) {
-                    Kb[d] = hn * b1 * yb[d];
-                    Kb[8 + d] = 0.0;
-                    Kb[16 + d] = hn * b3 * yb[d];
-                    Kb[24 + d] = hn * b4 * yb[d];
-                    Kb[32 + d] = hn * b5 * yb[d];
-                    Kb[40 + d] = hn * b6 * yb[d];
+                    ynb[d] = cy * gyf[d];
+                    yb[d] = (1.0 - cy) * gyf[d];
                 }
+            } else {
+                // y_{n+1} = y_n + h sum_i b_i K_i is the step's output; yb holds its adjoint
+                for (int d = 0; d < 8; ++d) {
+                    ynb[d] = yb[d];
+                    yb[d] = 0.0;
+                    gyf[d] = 0.0;
+                }
+                for (int i = 0; i < 7; ++i) dc[i] = 0.0;
             }
-            stages_adjoint<double>(I, Ys, hn, Kb, yb, tc, gn);
+            step_adjoint<FL, double>(I, yn, ynew, hn, dense, gyf, dc, ynb, yb, tc, ly, lw, gn);
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels

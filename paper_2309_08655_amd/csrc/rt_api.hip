@@ -280,8 +280,8 @@ extern "C" size_t rt_workspace_size(int32_t op, int64_t n) {
             return bin_ws_bytes(n);
         case RT_OP_BACKWARD_POWER:  // block partials of the image sum
             return align256(sizeof(double) * 1024);
-        case RT_OP_FLUX_GRAD:  // 64 observers, a checkpoint every 64 steps, up to 64 of them
-            return rt_flux_grad_workspace_size(n, 64, 64, 64);
+        case RT_OP_FLUX_GRAD:  // 64 observers, a checkpoint every 64 steps, a pool of 2 per ray
+            return rt_flux_grad_workspace_size(n, 64, 64, (n > 0 && n < INT32_MAX / 2) ? 2 * n + 1 : INT32_MAX);
         default:
             return 0;
     }

@@ -36,8 +36,13 @@ def test_workspace_sizes_and_version():
     L = rt.lib()
     assert L.rt_workspace_size(rt.OP_TRACE_FORWARD, 1000) >= 76 * 1000
     assert L.rt_workspace_size(rt.OP_BIN, 1000) >= 4 * 1000
-    assert L.rt_workspace_size(rt.OP_FLUX_GRAD, 1000) == L.rt_flux_grad_workspace_size(1000, 64, 64, 64) > 0
+    assert L.rt_workspace_size(rt.OP_FLUX_GRAD, 1000) == L.rt_flux_grad_workspace_size(1000, 64, 64, 2001) > 0
     assert L.rt_flux_grad_workspace_size(1000, 65, 64, 64) == 0
+    # the checkpoint pool: 96 bytes a slot, between 1 and 2^31 - 1 slots
+    base = L.rt_flux_grad_workspace_size(1000, 8, 64, 1000)
+    assert L.rt_flux_grad_workspace_size(1000, 8, 64, 1000 + 4096) - base == 96 * 4096
+    assert L.rt_flux_grad_workspace_size(1000, 8, 64, 0) == 0
+    assert L.rt_flux_grad_workspace_size(1000, 8, 64, 2**31) == 0
     assert b"gfx950" in L.rt_version()
 
 

@@ -126,6 +126,46 @@ def test_checkpoint_interval_is_invisible(rt):
         assert np.array_equal(a[3], x[3])
 
 
+def test_checkpoint_pool_holds_what_the_rays_need(rt):
+    """The checkpoints share one pool: the forward phase reports the slots the rays asked
+    for (one at the start of a traced ray and one every ckpt_every accepted steps after
+    it); a pool too small leaves the flux intact and makes the gradient NaN; a FluxGrad
+    that grows its pool reproduces the gradient of one that never ran short, bit for bit."""
+    import torch
+    star, tol = W.CFG5["star"], W.tol()
+    obs, gbar = W.observers(16), np.ones(16)
+    n, C = 400, 16
+    ref = rt.FluxGrad(star, tol, 0, n, obs, 0.02, ckpt_every=C, max_ckpt=256)
+    F0, info = ref.forward(ray_info=True)
+    g0, gr0 = ref.backward(torch.as_tensor(gbar), per_ray=True)
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    traced = info[2] != W.STATUS_NO_RESONANCE
+    need = int((1 + np.maximum(info[0][traced] - 1, 0) // C).sum())
+    used = int(ref.ckpt_used.item())
+    assert used == need
+    # a checkpoint every 16 steps asks for more than the default two slots a ray: the pool grew
+    assert used > rt.default_ckpt_pool(n) and ref.ckpt_pool == used
+    # a pool too small, not grown: the flux is unchanged, the gradient NaN
+    short = rt.FluxGrad(star, tol, 0, n, obs, 0.02, ckpt_every=C, max_ckpt=256, ckpt_pool=used // 3,
+                        grow_pool=False)
+    F1 = short.forward().cpu().numpy()
+    assert int(short.ckpt_used.item()) == used
+    assert np.allclose(F1, F0.cpu().numpy(), rtol=1e-12, atol=0.0)  # sums in atomic order
+    assert np.all(np.isnan(short.backward(torch.as_tensor(gbar)).cpu().numpy()))
+    # the same start, grown: exactly the slots needed, and the same gradients
+    grown = rt.FluxGrad(star, tol, 0, n, obs, 0.02, ckpt_every=C, max_ckpt=256, ckpt_pool=used // 3)
+    F2 = grown.forward().cpu().numpy()
+    g2, gr2 = grown.backward(torch.as_tensor(gbar), per_ray=True)
+    assert grown.ckpt_pool == used
+    assert np.allclose(F2, F0.cpu().numpy(), rtol=1e-12, atol=0.0)
+    assert np.allclose(g2.cpu().numpy(), g0.cpu().numpy(), rtol=1e-12, atol=0.0)
+    assert np.array_equal(gr2.cpu().numpy(), gr0.cpu().numpy())
+    # the workspace grows by 96 bytes a slot (32 slots: a whole number of its 256-byte alignment)
+    assert (rt.flux_grad_workspace_size(n, 16, C, used + 32) - rt.flux_grad_workspace_size(n, 16, C, used)
+            == 96 * 32)
+
+
 def test_reverse_is_linear_in_gbar_and_repeatable(rt):
     import torch
     star, tol = W.CFG1["star"], W.tol()

@@ -58,8 +58,8 @@ def tol(**over) -> dict:
     return t
 
 
-# -- the five workloads ------------------------------------------------------------------
-# 1: plain forward trace, small: flat metric, aligned dipole, isotropic plasma,
+# -- the workloads ----------------------------------------------------------------------
+# plain forward trace, small: flat metric, aligned dipole, isotropic plasma,
 #    outward axion directions, 32 x 64 x 32 bins.
 CFG1 = dict(
     name="forward-small-flat-iso-4096",
@@ -67,14 +67,14 @@ CFG1 = dict(
     tol=tol(), n=4096, seed=0,
     bins=dict(n_theta=32, n_psi=64, n_omega=32, d_omega=6.25e-5),
 )
-# 2: full forward trace: Schwarzschild M = 1.4, oblique rotator, anisotropic LO plasma.
+# full forward trace: Schwarzschild M = 1.4, oblique rotator, anisotropic LO plasma.
 CFG2 = dict(
     name="forward-full-gr-aniso-oblique-1e6",
     star=star(M_Msun=1.4, theta_m=0.3, plasma=PLASMA_ANISO, m_a_eV=2e-5, kdir=KDIR_ISOTROPIC),
     tol=tol(), n=1_000_000, seed=0,
     bins=dict(n_theta=64, n_psi=128, n_omega=64, d_omega=3.125e-5),
 )
-# 3: backward image: 1024^2 pixels at 1e5 km, inclination 60 deg, magnetar-like star
+# backward image: 1024^2 pixels at 1e5 km, inclination 60 deg, magnetar-like star
 #    with the twisted-magnetosphere density (model M1: lambda = 1, psi = 0.2).
 CFG3 = dict(
     name="backward-image-1024sq-magnetar",
@@ -84,7 +84,8 @@ CFG3 = dict(
     image=dict(D_km=1e5, incl=math.radians(60.0), phi_o=0.0, half_width_km=80.0, nx=1024, ny=1024),
     K=8,
 )
-# 5: adjoint: config-1 rays, Gaussian-smoothed flux at 32 observers.
+# adjoint: the small forward trace's star (flat metric, aligned rotator, isotropic plasma,
+# GJ density) with 1e6 rays, Gaussian-smoothed flux at 32 observers.
 CFG5 = dict(
     name="adjoint-smoothed-flux-1e6",
     star=CFG1["star"], tol=tol(), n=1_000_000, seed=0, n_obs=32, sigma=0.02, ckpt_every=64,
@@ -123,8 +124,8 @@ def observers(n_obs: int = 32) -> np.ndarray:
 
 
 def batched_instances(n_inst: int = 256, seed: int = 1, n_lo: float = 1e4, n_hi: float = 2e5):
-    """Config 4: 16 axion masses (log-spaced over [1e-6, 1e-4] eV) x 16 inclinations
-    (linear over [0, 1.2] rad) of the config-1 star; ray counts log-uniform over
+    """The batched scan: 16 axion masses (log-spaced over [1e-6, 1e-4] eV) x 16 inclinations
+    (linear over [0, 1.2] rad) of the small forward trace's star; ray counts log-uniform over
     [n_lo, n_hi] drawn with numpy's PCG64 seeded `seed`."""
     side = int(round(math.sqrt(n_inst)))
     rng = np.random.default_rng(seed)
