@@ -689,16 +689,18 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 double e[8], et[8], q[4], gOm = 0.0, gth = 0.0;
                 dense_point_deriv(yn, K, ynew, hn, t, e, et);
                 if (last) {
-                    // the observable with 8 state and 6 parameter tangents
-                    double gp[6];
-                    wG = observable_grad(A, e, obs, gbar, n_obs, sigma, gyf, gp);
-                    for (int d = 0; d < 8; ++d) gyf[d] *= w;
+                    // the observable with 8 state and 6 parameter tangents (the non-inlined
+                    // helpers get copies, so that the sweep's own arrays never leave registers)
+                    double gp[6], gy[8];
+                    wG = observable_grad(A, e, obs, gbar, n_obs, sigma, gy, gp);
+                    for (int d = 0; d < 8; ++d) gyf[d] = gy[d] * w;
                     for (int k = 0; k < 6; ++k) pb[k] += w * gp[k];
                     const double r = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
                     q[0] = e[0] / r; q[1] = e[1] / r; q[2] = e[2] / r; q[3] = 0.0;
                 } else {
                     for (int d = 0; d < 8; ++d) gyf[d] = yb[d];
-                    gj_factor_grad(I, e, q, &gOm, &gth);
+                    const InstT<double> Ic = I;
+                    gj_factor_grad(Ic, e, q, &gOm, &gth);
                 }
                 double num = 0.0, den = 0.0;
                 for (int d = 0; d < 8; ++d) num += gyf[d] * et[d];
@@ -735,7 +737,12 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels
-    seed_and_channels<FL>(A, seed, j, yb, wG, tc, pb);
+    double ybc[8], tcc[5], pbc[6];
+    for (int d = 0; d < 8; ++d) ybc[d] = yb[d];
+    for (int c = 0; c < 5; ++c) tcc[c] = tc[c];
+    for (int k = 0; k < 6; ++k) pbc[k] = 0.0;
+    seed_and_channels<FL>(A, seed, j, ybc, wG, tcc, pbc);
+    for (int k = 0; k < 6; ++k) pb[k] += pbc[k];
     return missing;
 }
 
