@@ -102,14 +102,39 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
     return (size_t)(p - (char*)base);
 }
 
+// Compile-time forms of the adjoint kernels: the strong-field Hamiltonian with its plasma and
+// density switches read at run time (MODE_GENERIC), the finite-magnetisation one
+// (MODE_LARMOR), and the strong-field isotropic plasma with the GJ density and the flat dipole
+// (MODE_ISO_GJ, the smoothed-flux workload's star), whose switches become constants: the
+// right-hand side and the stage products are then branch-free, so the compiler can interleave
+// a product's independent passes.  The arithmetic is the same in every form (this file is
+// built with -ffp-contract=on), so a star gives the same bits whichever form traces it.
+constexpr int MODE_GENERIC = 0, MODE_LARMOR = 1, MODE_ISO_GJ = 2;
+
+template <int MODE>
+__device__ __forceinline__ void fix_mode(InstT<double>& I) {
+    I.larmor = (MODE == MODE_LARMOR) ? 1 : 0;
+    I.oblique = 1;  // the rotating-axis formula throughout (as the entry point sets it)
+    if constexpr (MODE == MODE_ISO_GJ) {
+        I.plasma = PL_ISO;
+        I.density = DEN_GJ;
+        I.gr_dipole = 0;
+    }
+}
+
+static int adj_mode(const InstT<double>& I) {
+    if (I.larmor) return MODE_LARMOR;
+    if (I.plasma == PL_ISO && I.density == DEN_GJ && !I.gr_dipole) return MODE_ISO_GJ;
+    return MODE_GENERIC;
+}
+
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
 // cost-ordered work list; checkpoints, per-ray counters and the flux.  Each checkpoint takes
 // the next free pool slot (one atomic per wave for the lanes storing together) and links
 // to the ray's previous one; a request beyond the pool is counted but not stored (the
 // count then tells the caller the pool it needs, and the reverse pass refuses to run).
-// LARMOR fixes the finite-magnetisation switch at compile time (the strong-field kernel
-// carries none of it).
-template <bool LARMOR>
+// MODE fixes the Hamiltonian's switches at compile time (fix_mode below).
+template <int MODE>
 __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC tol, int64_t n, WorkCtr* ctr,
                                                       const int32_t* __restrict__ list, const double* __restrict__ rays,
                                                       const double* __restrict__ y0q, const double* __restrict__ h0s,
@@ -121,7 +146,8 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
                                                       const double* __restrict__ obs, int n_obs, double sigma,
                                                       double* __restrict__ facc) {
     __shared__ double sh_f[MAX_OBS];
-    I.larmor = LARMOR ? 1 : 0;
+    constexpr bool LARMOR = (MODE == MODE_LARMOR);
+    fix_mode<MODE>(I);
     for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) sh_f[q] = 0.0;
     __syncthreads();
     const int lane = __lane_id();
@@ -259,8 +285,8 @@ __global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int 
     }
 }
 
-// reverse pass: one escaped ray per lane, handed out by a lane atomic (LARMOR as above)
-template <bool LARMOR>
+// reverse pass: one escaped ray per lane, handed out by a lane atomic (MODE as above)
+template <int MODE>
 __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P, StarFixed fx, TolC tol,
                                                      uint64_t seed, int64_t n, const double* __restrict__ rays,
                                                      const int32_t* __restrict__ ifin,
@@ -275,7 +301,8 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
                                                      double* __restrict__ grad_rays, double inv_n, int Kc,
                                                      unsigned long long seal) {
     if (rctr->pad[0] != seal) return;  // no forward phase of these arguments in this workspace
-    I.larmor = LARMOR ? 1 : 0;
+    constexpr bool LARMOR = (MODE == MODE_LARMOR);
+    fix_mode<MODE>(I);
     const int64_t lane_g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     AdjParams A;
     make_adj_params(P.p, fx, A);
@@ -350,6 +377,23 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     if (missing) atomicAdd(&rctr->iters, missing);
 }
 
+template <int MODE>
+static void launch_adj_fwd(int grid, hipStream_t st, const InstT<double>& I, const TolC& T, int64_t n, const AdjWs& W,
+                           int C, int Kc, int64_t ckpt_pool, unsigned long long* pool_next, int n_obs, double sigma) {
+    hipLaunchKernelGGL(adj_fwd_kernel<MODE>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
+                       W.fw.y0, W.fw.h0, C, Kc, W.pool, (long long)ckpt_pool, W.ckhead, pool_next, W.nseg, W.theta,
+                       W.ifin, W.obs, n_obs, sigma, W.facc);
+}
+
+template <int MODE>
+static void launch_adj_rev(hipStream_t st, const InstT<double>& I, const ParamVec& P, const StarFixed& fx,
+                           const TolC& T, uint64_t seed, int64_t n, const AdjWs& W, int C, int Kc, int64_t ckpt_pool,
+                           int n_obs, double sigma, const double* gbar, double* grad_rays, unsigned long long seal) {
+    hipLaunchKernelGGL(adj_rev_kernel<MODE>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
+                       W.ifin, W.nseg, W.theta, W.pool, (long long)ckpt_pool, W.ckhead, C, W.rctr, W.fw.ctr,
+                       W.fw.list, W.obs, n_obs, sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, Kc, seal);
+}
+
 }  // namespace rtd
 
 using namespace rtd;
@@ -403,17 +447,18 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         rc = launch_trace_init(I, nullptr, nullptr, T, W.rays, W.status, n, W.fw, W.fin, W.ifin, st);
         if (rc) return rc;
         const rt_schedule sc = resolve_schedule(nullptr);
-        const void* fk = I.larmor ? (const void*)adj_fwd_kernel<true> : (const void*)adj_fwd_kernel<false>;
+        const int mode = adj_mode(I);
+        const void* fk = (mode == MODE_LARMOR)   ? (const void*)adj_fwd_kernel<MODE_LARMOR>
+                         : (mode == MODE_ISO_GJ) ? (const void*)adj_fwd_kernel<MODE_ISO_GJ>
+                                                 : (const void*)adj_fwd_kernel<MODE_GENERIC>;
         const int grid = persistent_grid(sc, fk, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
-        if (I.larmor)
-            hipLaunchKernelGGL(adj_fwd_kernel<true>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.pool, (long long)ckpt_pool, W.ckhead,
-                               pool_next, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma, W.facc);
+        if (mode == MODE_LARMOR)
+            launch_adj_fwd<MODE_LARMOR>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
+        else if (mode == MODE_ISO_GJ)
+            launch_adj_fwd<MODE_ISO_GJ>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
         else
-            hipLaunchKernelGGL(adj_fwd_kernel<false>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list,
-                               W.rays, W.fw.y0, W.fw.h0, ckpt_every, max_ckpt, W.pool, (long long)ckpt_pool, W.ckhead,
-                               pool_next, W.nseg, W.theta, W.ifin, W.obs, n_obs, sigma, W.facc);
+            launch_adj_fwd<MODE_GENERIC>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");
         if (rc) return rc;
@@ -445,14 +490,16 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     ParamVec P{{star->B0_G, star->P_s, star->theta_m, star->M_Msun, star->R_km, star->m_a_eV}};
     StarFixed fx = star_fixed(*star);
     timing_begin(st, RT_KERNEL_ADJOINT_REVERSE);
-    if (I.larmor)
-        hipLaunchKernelGGL(adj_rev_kernel<true>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
-                           W.ifin, W.nseg, W.theta, W.pool, (long long)ckpt_pool, W.ckhead, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
-                           sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
+    const int mode = adj_mode(I);
+    if (mode == MODE_LARMOR)
+        launch_adj_rev<MODE_LARMOR>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma, gbar,
+                                    grad_rays, seal);
+    else if (mode == MODE_ISO_GJ)
+        launch_adj_rev<MODE_ISO_GJ>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma, gbar,
+                                    grad_rays, seal);
     else
-        hipLaunchKernelGGL(adj_rev_kernel<false>, dim3(REV_LANES / 64), dim3(64), 0, st, I, P, fx, T, seed, n, W.rays,
-                           W.ifin, W.nseg, W.theta, W.pool, (long long)ckpt_pool, W.ckhead, ckpt_every, W.rctr, W.fw.ctr, W.fw.list, W.obs, n_obs,
-                           sigma, gbar, W.replay, W.gacc, grad_rays, 1.0 / (double)n, max_ckpt, seal);
+        launch_adj_rev<MODE_GENERIC>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma, gbar,
+                                     grad_rays, seal);
     timing_end(st);
     rc = check_launch("adj_rev_kernel");
     if (rc) return rc;
