@@ -29,16 +29,18 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, AMD published (256 CU x 128 FLOP/clk x
 
 # HBM traffic of the tracing kernel, measured with hardware counters (FETCH_SIZE and
 # WRITE_SIZE per dispatch, each scaled by what it reads for a copy of known size) on this
-# workload; valid only while the kernel's sources are the ones it was measured on
+# workload; valid only while the kernel's sources and build flags are the ones it was
+# measured on
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "trace_fwd_kernel_forward-full-1e6_counters.md")
-TRACE_SOURCES = ["rt_forward.hip", "rt_common.hpp", "rt_device.hpp", "rt_integrator.hpp", "rt_seed.hpp"]
+TRACE_SOURCES = ["csrc/rt_forward.hip", "csrc/rt_common.hpp", "csrc/rt_device.hpp", "csrc/rt_integrator.hpp",
+                 "csrc/rt_seed.hpp", "build.py"]
 
 
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for f in TRACE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2309_08655_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2309_08655_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -35,7 +35,8 @@ CACHE = os.path.join(_HERE, "tuning_cache.json")
 
 
 def kernel_source_hash() -> str:
-    """sha256 (first 16 hex digits) of the HIP sources the tracing kernels are built from"""
+    """sha256 (first 16 hex digits) of the HIP sources the tracing kernels are built from and
+    of the build script that holds their compiler flags"""
     h = hashlib.sha256()
     csrc = os.path.join(_HERE, "csrc")
     for name in sorted(os.listdir(csrc)):
@@ -43,6 +44,8 @@ def kernel_source_hash() -> str:
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())
+    with open(os.path.join(_HERE, "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -18,13 +18,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # replays its forward pass's accept/reject decisions exactly, and the tracing kernels
 # specialised at compile time for one plasma, density and rotation round exactly like the
 # generic ones (results do not depend on the schedule).
-# The adjoint's kernels also keep the backend's loop-invariant code motion off: hoisting FP64
-# constants and invariant products out of their nested loops (rays, segments, steps, stages)
-# kept them live across the whole kernel, and the reverse kernel, already at one wave per
-# SIMD, spilled them to scratch (547 spilled registers, 56 without; the reverse phase of the
-# 1e6-ray gradient took 75 ms, 40 ms without).  It moves instructions only, not arithmetic.
-FILE_FLAGS = {"rt_adjoint.hip": ["-ffp-contract=on", "-mllvm", "-disable-machine-licm"],
-              "rt_forward.hip": ["-ffp-contract=on"], "rt_backward.hip": ["-ffp-contract=on"]}
+# The kernels also keep the backend's loop-invariant code motion off.  Hoisting FP64 constants
+# and invariant products out of their nested loops (rays, segments, steps, stages) kept them
+# live across the whole kernel, and the kernels that run short of registers spilled them: the
+# adjoint's reverse kernel, at one wave per SIMD, 547 spilled registers (56 without; its phase
+# of the 1e6-ray gradient 75 ms -> 40 ms), and the generic tracing kernel 34-142 (0-6 without;
+# the GR-dipole variant 17.1 -> 13.8 ms per step).  The specialised tracing kernels, which did
+# not spill, time the same either way.  It moves instructions only, not arithmetic.
+NO_MLICM = ["-mllvm", "-disable-machine-licm"]
+FILE_FLAGS = {"rt_adjoint.hip": ["-ffp-contract=on", *NO_MLICM], "rt_forward.hip": ["-ffp-contract=on", *NO_MLICM],
+              "rt_backward.hip": ["-ffp-contract=on", *NO_MLICM]}
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
