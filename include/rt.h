@@ -331,7 +331,8 @@ int rt_trace_batched(const rt_batch* batch, uint64_t seed, const rt_tol* tol, co
  * 1 <= ckpt_every <= 1024; max_ckpt >= 1; 1 <= ckpt_pool <= 2^31 - 1; weights
  * RT_WEIGHTS_CONST_B is not supported.
  * Workspace: rt_flux_grad_workspace_size(n, n_obs, ckpt_every, ckpt_pool) bytes (about
- * 384 n + 96 ckpt_pool + 5.8 MB x ckpt_every + 96 MB).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
+ * 120 n + 96 ckpt_pool + max(5.8 MB x ckpt_every, 264 n + 50 MB) + 4 MB: the reverse phase's
+ * replay buffer shares its bytes with what only the forward phase uses).  Returns RT_OK, RT_EINVAL, RT_ENOWS,
  * RT_EUNSUPPORTED or RT_EHIP. */
 int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t seed, int64_t n, const double* obs,
                  int32_t n_obs, double sigma, int32_t ckpt_every, int32_t max_ckpt, int64_t ckpt_pool, int32_t phase,

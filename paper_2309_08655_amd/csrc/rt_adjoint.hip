@@ -46,7 +46,7 @@ struct AdjWs {
     FwdWs fw;
     double* rays;     // [10][n] seeds
     int32_t* status;  // [n] seed status
-    double* fin;      // [RT_NFIN][n] written by the trace set-up for rays it does not trace
+    double* fin;      // [RT_NFIN][n] written by the trace set-up for rays it does not trace (phase 0)
     int32_t* ifin;    // [RT_NIFIN][n]: n_acc, n_rej, status
     int32_t* nseg;    // [n] checkpoints stored
     int32_t* ckhead;  // [n] pool slot of each ray's last checkpoint
@@ -57,7 +57,7 @@ struct AdjWs {
     double* obs;      // [n_obs][3]
     double* facc;     // [MAX_OBS] flux accumulators
     double* gacc;     // [8] gradient accumulators
-    double* replay;   // [C * 11][REV_LANES]
+    double* replay;   // [C * 11][REV_LANES] (phase 1), over the phase-0-only part of fw and fin
 };
 
 constexpr int CK_SLOT = 12;  // doubles per checkpoint slot
@@ -69,10 +69,19 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
         p += align256(bytes);
         return q;
     };
+    // The forward workspace, then the final records (which only the set-up of phase 0 writes,
+    // for seeds it does not trace): from the forward workspace's transient part on, both are
+    // used by phase 0 only, and the replay buffer of phase 1 lies over them (extending past
+    // them if it is larger).
     char* fwbase = take(fwd_ws_bytes(n));
+    char* fin = take(sizeof(double) * RT_NFIN_ * (size_t)n);
+    char* replay = fwbase + fwd_ws_transient_offset(n);
+    {
+        char* rend = replay + align256(sizeof(double) * 11 * (size_t)C * REV_LANES);
+        if (rend > p) p = rend;
+    }
     char* rays = take(sizeof(double) * 10 * (size_t)n);
     char* status = take(sizeof(int32_t) * (size_t)n);
-    char* fin = take(sizeof(double) * RT_NFIN_ * (size_t)n);
     char* ifin = take(sizeof(int32_t) * RT_NIFIN_ * (size_t)n);
     char* nseg = take(sizeof(int32_t) * (size_t)n);
     char* ckhead = take(sizeof(int32_t) * (size_t)n);
@@ -82,7 +91,6 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
     char* obs = take(sizeof(double) * 3 * (size_t)n_obs);
     char* facc = take(sizeof(double) * MAX_OBS);
     char* gacc = take(sizeof(double) * 8);
-    char* replay = take(sizeof(double) * 11 * (size_t)C * REV_LANES);
     if (W) {
         W->fw = carve_fwd_ws(fwbase, n);
         W->rays = (double*)rays;

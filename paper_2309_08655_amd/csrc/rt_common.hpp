@@ -102,34 +102,42 @@ int device_cu_count();
 inline int64_t stash_lanes() { return (int64_t)device_cu_count() * STASH_LANES_PER_CU; }
 inline size_t stash_bytes() { return align256(sizeof(double) * STASH_STRIDE * (size_t)stash_lanes()); }
 
+// Layout: first what outlives a trace (the work counter and the ordered work list with its sort
+// keys, bucket starts and partition table, which the adjoint reuses for its reverse list),
+// then what only the trace itself uses (the restart stash and the seeds in list order), from
+// fwd_ws_transient_offset(n) to the end, which the adjoint's reverse phase overlays.
 inline FwdWs carve_fwd_ws(void* ws, int64_t n) {
     char* p = (char*)ws;
     FwdWs W;
     W.ctr = (WorkCtr*)p;
     p += align256(sizeof(WorkCtr));
-    W.stash = (double*)p;
-    W.stash_lanes = stash_lanes();
-    p += stash_bytes();
     W.list = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)n);
-    W.h0 = (double*)p;
-    p += align256(sizeof(double) * (size_t)n);
-    W.k1 = (double*)p;
-    p += align256(sizeof(double) * 8 * (size_t)n);
-    W.y0 = (double*)p;
-    p += align256(sizeof(double) * 8 * (size_t)n);
     W.keys = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)n);
     W.buckets = (int32_t*)p;
     p += part_start_bytes();
     W.tab = (int32_t*)p;
+    p += part_tab_bytes(n);
+    W.stash = (double*)p;
+    W.stash_lanes = stash_lanes();
+    p += stash_bytes();
+    W.h0 = (double*)p;
+    p += align256(sizeof(double) * (size_t)n);
+    W.k1 = (double*)p;
+    p += align256(sizeof(double) * 8 * (size_t)n);
+    W.y0 = (double*)p;
     return W;
 }
 
+inline size_t fwd_ws_transient_offset(int64_t n) {
+    return align256(sizeof(WorkCtr)) + 2 * align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() +
+           part_tab_bytes(n);
+}
+
 inline size_t fwd_ws_bytes(int64_t n) {
-    return align256(sizeof(WorkCtr)) + stash_bytes() + align256(sizeof(int32_t) * (size_t)n) +
-           align256(sizeof(double) * (size_t)n) + 2 * align256(sizeof(double) * 8 * (size_t)n) +
-           align256(sizeof(int32_t) * (size_t)n) + part_start_bytes() + part_tab_bytes(n);
+    return fwd_ws_transient_offset(n) + stash_bytes() + align256(sizeof(double) * (size_t)n) +
+           2 * align256(sizeof(double) * 8 * (size_t)n);
 }
 
 // Groups the indices i < n with keys[i] >= 0 and keys[i] >> shift < nb (nb <= PART_BUCKETS)
