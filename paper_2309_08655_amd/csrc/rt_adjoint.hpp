@@ -461,52 +461,75 @@ RT_HD void grad_p(const InstT<T>& I, const T* y, T g[4], double gjs) {
     g[3] = p.pt;
 }
 
+// The same for an isotropic plasma (or none) and the strong-field Hamiltonian: H = H_vac + P
+// with P a function of (x, t) alone, r_s only in H_vac, and Om, theta_m and the plasma
+// coefficient only in P.  Two passes with two tangents each: the vacuum right-hand side with
+// tangents u and r_s (Hess(H_vac) u and the r_s channel), and grad P with tangents u's (x, t)
+// part and theta_m (Hess(P) u, the theta_m channel, and through its value, which is the plasma
+// part of f, the plasma channel and the Om channel).
+template <class S>
+RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs) {
+    typedef gdual<2, S> D2;
+    {
+        InstT<D2> J = lift_inst<D2>(I);  // the vacuum part
+        J.density = DEN_NONE;
+        J.larmor = 0;
+        J.rs.d[1] = S(1.0);
+        D2 yd[8], fd[8];
+        for (int i = 0; i < 4; ++i) {
+            yd[i] = D2(Y[i]);
+            yd[i].d[0] = S(0.0) - v[4 + i];  // u_x = -v_k
+            yd[4 + i] = D2(Y[4 + i]);
+            yd[4 + i].d[0] = v[i];  // u_k = v_x
+        }
+        rhs(J, yd, fd, 1.0);
+        for (int i = 0; i < 4; ++i) {
+            vy[i] = S(0.0) - fd[4 + i].d[0];
+            vy[4 + i] = fd[i].d[0];
+        }
+        S a = v[0] * fd[0].d[1];
+        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1];
+        vc[0] = a;
+    }
+    {
+        InstT<D2> J = lift_inst<D2>(I);  // grad P
+        J.larmor = 0;
+        J.cm.d[1] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
+        J.sm.d[1] = I.cm;
+        D2 yd[4], gp[4];
+        for (int i = 0; i < 4; ++i) {
+            yd[i] = D2(Y[i]);
+            yd[i].d[0] = S(0.0) - v[4 + i];
+        }
+        grad_p(J, yd, gp, gjs);
+        for (int i = 0; i < 4; ++i) vy[i] = vy[i] + gp[i].d[0];  // + Hess(P) u
+        // f's plasma part is -grad P in the k rows
+        S a = v[4] * gp[0].d[1], b = v[4] * gp[0].v;
+        for (int i = 1; i < 4; ++i) {
+            a = a + v[4 + i] * gp[i].d[1];
+            b = b + v[4 + i] * gp[i].v;
+        }
+        vc[2] = S(0.0) - a;
+        vc[3] = S(0.0) - b;
+        // Om (see stage_vjp): dH/dt = dP/dt, u_t = -v_7
+        vc[1] = (Y[3] * vy[3] - v[7] * gp[3].v) * rcp(I.Om);
+    }
+    vc[4] = S(0.0);
+}
+
 // v^T df/dy (vy) and the channels vc[0..4] = v^T df/dc for c = rs, Om, theta_m, the plasma
 // coefficient and kL (vc[4] = 0 for the strong-field Hamiltonian) at the state Y (S = double;
-// generic for the host operation counter).  With an isotropic plasma (or none) and the
-// strong-field Hamiltonian, H = H_vac + P with rs only in H_vac and theta_m and the plasma
-// coefficient only in P, so rs takes a one-tangent pass through the vacuum part, and theta_m
-// and the plasma channel one through grad P (whose value is the plasma part of f).
+// generic for the host operation counter); an isotropic plasma (or none) takes stage_vjp_iso.
 template <bool FL = true, class S = double>
 RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs = 0.0) {
+    if (!(FL && I.larmor) && (I.plasma == PL_ISO || I.density == DEN_NONE)) {
+        stage_vjp_iso<S>(I, Y, v, vy, vc, gjs);
+        return;
+    }
     S f[8];
     vjp_state<FL, S>(I, Y, v, vy, f, gjs);
     // Om: u_t = -v_7, dH/dt = -f_7, (Hess(H) u)_t = vy_3
     vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * rcp(I.Om);
-    if (!(FL && I.larmor) && (I.plasma == PL_ISO || I.density == DEN_NONE)) {
-        typedef gdual<1, S> D1;
-        {
-            InstT<D1> J = lift_inst<D1>(I);  // the vacuum part, rs tangent
-            J.density = DEN_NONE;
-            J.larmor = 0;
-            J.rs.d[0] = S(1.0);
-            D1 yd[8], fd[8];
-            for (int i = 0; i < 8; ++i) yd[i] = D1(Y[i]);
-            rhs(J, yd, fd, 1.0);
-            S a = v[0] * fd[0].d[0];
-            for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[0];
-            vc[0] = a;
-        }
-        {
-            InstT<D1> J = lift_inst<D1>(I);  // grad P, theta_m tangent
-            J.larmor = 0;
-            J.cm.d[0] = S(0.0) - I.sm;
-            J.sm.d[0] = I.cm;
-            D1 yd[4], gp[4];
-            for (int i = 0; i < 4; ++i) yd[i] = D1(Y[i]);
-            grad_p(J, yd, gp, gjs);
-            // the plasma part of f is J grad P: -grad P in the k rows
-            S a = v[4] * gp[0].d[0], b = v[4] * gp[0].v;
-            for (int i = 1; i < 4; ++i) {
-                a = a + v[4 + i] * gp[i].d[0];
-                b = b + v[4 + i] * gp[i].v;
-            }
-            vc[2] = S(0.0) - a;
-            vc[3] = S(0.0) - b;
-        }
-        vc[4] = S(0.0);
-        return;
-    }
     {
         InstT<gdual<2, S>> J = lift_inst<gdual<2, S>>(I);
         if constexpr (!FL) J.larmor = 0;
