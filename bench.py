@@ -556,9 +556,10 @@ def bench_adjoint(args, rt, W, np, torch):
     flops_fwd = float((acc + rej)[traced].sum()) * ft["attempt"] + float(traced.sum()) * 3 * ft["rhs"]
     nseg = (acc[esc] + C - 1) // C
     # reverse, per escaped ray: recompute every attempt of its segments, then per accepted step
-    # one FSAL derivative + one attempt (stage states) + the six stage adjoints + the b-weights
+    # one FSAL derivative + the step's stages again (no error estimate) + the six stage
+    # adjoints + the b-weights
     flops_rev = (float((acc + rej)[esc].sum()) * ft["attempt"] + float(nseg.sum()) * ft["rhs"]
-                 + float(acc[esc].sum()) * (ft["rhs"] + ft["attempt"] + ft["stages_adjoint"] + 80))
+                 + float(acc[esc].sum()) * (ft["rhs"] + ft["stages"] + ft["stages_adjoint"] + 80))
     tot_ms = fwd_ms + rev_ms
     return dict(workload=cfg["name"], rays=n, traced_rays=int(traced.sum()), escaped_rays=int(esc.sum()),
                 observers=cfg["n_obs"], ckpt_every=C, forward_ms=fwd_ms, reverse_ms=rev_ms,

@@ -73,6 +73,27 @@ int main() {
                 auto fn = [&](const FC* yy, FC* ff) { rhs(I, yy, ff, 1.0); };
                 dopri_attempt(fn, y, S, FC(0.1), ynew, 1e-8, 1e-12);
                 long long fstep = g_flops + 3;  // + step-size update (pow, x0.9, x h)
+                // the stages alone (the reverse sweep's recompute of an accepted step: no error
+                // estimate, no controller), in the order the adjoint computes them
+                long long fstages_only = 0;
+                {
+                    using namespace dp5;
+                    const double A[6][6] = {{a21, 0, 0, 0, 0, 0},       {a31, a32, 0, 0, 0, 0},
+                                            {a41, a42, a43, 0, 0, 0},   {a51, a52, a53, a54, 0, 0},
+                                            {a61, a62, a63, a64, a65, 0}, {b1, 0.0, b3, b4, b5, b6}};
+                    FC Kq[7][8], tmp[8];
+                    for (int d = 0; d < 8; ++d) Kq[0][d] = f[d];
+                    g_flops = 0;
+                    for (int st = 0; st < 6; ++st) {
+                        for (int d = 0; d < 8; ++d) {
+                            FC acc(0.0);
+                            for (int q = 0; q <= st; ++q) acc = acc + A[st][q] * Kq[q][d];
+                            tmp[d] = y[d] + FC(0.1) * acc;
+                        }
+                        rhs(I, tmp, Kq[st + 1], 1.0);
+                    }
+                    fstages_only = g_flops;
+                }
                 // adjoint: one stage vector-Jacobian product (a 1-tangent dual-number
                 // Hessian-vector product, a 3-tangent pass for the parameter channels and the
                 // vacuum part) and the reverse sweep through the six stages of a plain step
@@ -104,10 +125,10 @@ int main() {
                 FC G1 = g_kk(I, ynew) + I.ma2;
                 (void)G1;
                 long long fendpt = g_flops;
-                std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld, \"vjp\": %lld, "
+                std::printf("%s\"%s_%s_%s\": {\"rhs\": %lld, \"attempt\": %lld, \"stages\": %lld, \"vjp\": %lld, "
                             "\"stages_adjoint\": %lld, \"event_probe\": %lld, \"event_g\": %lld}",
-                            first ? "" : ", ", pn[pl], dn[de], ob ? "oblique" : "aligned", frhs, fstep, fvjp,
-                            fstages, fprobe, fendpt);
+                            first ? "" : ", ", pn[pl], dn[de], ob ? "oblique" : "aligned", frhs, fstep, fstages_only,
+                            fvjp, fstages, fprobe, fendpt);
                 first = false;
             }
     std::printf("}\n");

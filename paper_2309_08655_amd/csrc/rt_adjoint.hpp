@@ -70,9 +70,12 @@ struct NoStages {
     RT_HD void operator()(int, const double*) const {}
 };
 
+// The stages of a DOPRI5 step of size hh from y with K[0..7] = f(y) set: fills K[8..55]
+// (stages 2..7, the last = f(ynew)) and ynew, and hands each inner stage state Y_i
+// (i = 2..6) to stages(i, Y_i).
 template <bool FL = true, class Sink>
-RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
-                      double* h, double* facmax, Sink&& stages, double gjs = 0.0) {
+RT_HD void adj_stages(const InstT<double>& I, const double* y, double* K, double* ynew, double hh, Sink&& stages,
+                      double gjs) {
     using namespace dp5;
     const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
                             {a31, a32, 0, 0, 0, 0},
@@ -80,7 +83,6 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
                             {a51, a52, a53, a54, 0, 0},
                             {a61, a62, a63, a64, a65, 0},
                             {b1, 0.0, b3, b4, b5, b6}};
-    const double hh = *h;
     const AxisRef ref0 = axis_ref_at(I, y[3]);
     double tmp[8];
 #pragma unroll
@@ -102,6 +104,14 @@ RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const do
         else
             adj_rhs<FL>(I, tmp, K + (s + 1) * 8, gjs);
     }
+}
+
+template <bool FL = true, class Sink>
+RT_HD int adj_attempt(const InstT<double>& I, double rtol, double atol, const double* y, double* K, double* ynew,
+                      double* h, double* facmax, Sink&& stages, double gjs = 0.0) {
+    using namespace dp5;
+    const double hh = *h;
+    adj_stages<FL>(I, y, K, ynew, hh, stages, gjs);
     const double E[7] = {e1, 0.0, e3, e4, e5, e6, e7};
     double acc = 0.0;
 #pragma unroll
@@ -691,14 +701,14 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             double yn[8];
             for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
             const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
-            // the step's stages again, its inner stage states into ly
-            double hdummy = hn, fdummy = 10.0;
+            // the step's stages again (no error estimate: the step is known accepted), its
+            // inner stage states into ly
             adj_rhs<FL>(I, yn, K, gn);
-            adj_attempt<FL>(I, tol.rtol, tol.atol, yn, K, ynew, &hdummy, &fdummy,
-                            [&](int i, const double* Yi) {
-                                for (int d = 0; d < 8; ++d) ly(8 * (i - 2) + d) = Yi[d];
-                            },
-                            gn);
+            adj_stages<FL>(I, yn, K, ynew, hn,
+                           [&](int i, const double* Yi) {
+                               for (int d = 0; d < 8; ++d) ly(8 * (i - 2) + d) = Yi[d];
+                           },
+                           gn);
             const bool last = (first + idx == S - 1);
             const bool dense = last || thk <= 1.0;
             double ynb[8], gyf[8], dc[7];
