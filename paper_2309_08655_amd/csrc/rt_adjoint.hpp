@@ -522,7 +522,7 @@ RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc
         vc[2] = S(0.0) - a;
         vc[3] = S(0.0) - b;
         // Om (see stage_vjp): dH/dt = dP/dt, u_t = -v_7
-        vc[1] = (Y[3] * vy[3] - v[7] * gp[3].v) * rcp(I.Om);
+        vc[1] = (Y[3] * vy[3] - v[7] * gp[3].v) * frcp(I.Om);
     }
     vc[4] = S(0.0);
 }
@@ -539,7 +539,7 @@ RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, do
     S f[8];
     vjp_state<FL, S>(I, Y, v, vy, f, gjs);
     // Om: u_t = -v_7, dH/dt = -f_7, (Hess(H) u)_t = vy_3
-    vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * rcp(I.Om);
+    vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * frcp(I.Om);
     {
         InstT<gdual<2, S>> J = lift_inst<gdual<2, S>>(I);
         if constexpr (!FL) J.larmor = 0;

@@ -199,8 +199,20 @@ template <int N, class T> RT_HD gdual<N, T> atan2(const gdual<N, T>& y, const gd
     return r;
 }
 template <int N, class T> RT_HD gdual<N, T> fabs(const gdual<N, T>& a) { return (value(a) < 0.0) ? -a : a; }
-template <int N, class T> RT_HD gdual<N, T> frcp(const gdual<N, T>& a) { return rcp(a); }
-template <int N, class T> RT_HD gdual<N, T> frsqrt(const gdual<N, T>& a) { return rcp(sqrt(a)); }
+// the refined hardware estimates for the value, the exact derivative on top:
+// d(1/a) = -(1/a)^2 da,  d(a^-1/2) = -(a^-1/2)^3 da / 2
+template <int N, class T> RT_HD gdual<N, T> frcp(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = frcp(a.v);
+    T g = -(r.v * r.v);
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
+template <int N, class T> RT_HD gdual<N, T> frsqrt(const gdual<N, T>& a) {
+    gdual<N, T> r; r.v = frsqrt(a.v);
+    T g = (-0.5 * r.v) * (r.v * r.v);
+    for (int i = 0; i < N; ++i) r.d[i] = g * a.d[i];
+    return r;
+}
 
 // ----------------------------------------------------------------------------
 // instance constants (integrator units: km, k in units of w_inf)
