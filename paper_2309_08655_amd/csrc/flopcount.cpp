@@ -109,8 +109,8 @@ int main() {
                 long long fvjp = g_flops;
                 g_flops = 0;
                 step_adjoint<false, FC>(I, y, ynew, FC(0.1), false, gyf, dc, ynb, yb, tc,
-                                        [&](int k) -> FC& { return ybuf[k]; },
-                                        [&](int k) -> FC& { return wbuf[k]; }, 0.0);
+                                        [&](int r) { return LaneRow<FC, 1>{ybuf + 8 * r}; },
+                                        [&](int r) { return LaneRow<FC, 1>{wbuf + 8 * r}; }, 0.0);
                 long long fstages = g_flops;
                 // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension
                 FC yt[8];

@@ -293,6 +293,15 @@ __global__ void adj_clear_kernel(double* facc, double* gacc, WorkCtr* rctr, int 
     }
 }
 
+// This lane's index in the wave (the reverse kernel's blocks are one wave, so also its thread
+// index), recomputed where the LDS rows are addressed: held in a register across the sweep it
+// is spilled to scratch, and every row access then waits on a reload.
+__device__ inline int lane_now() {
+    int r;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(r));
+    return r;
+}
+
 // reverse pass: one escaped ray per lane, handed out by a lane atomic (MODE as above)
 template <int MODE>
 __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P, StarFixed fx, TolC tol,
@@ -322,8 +331,8 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     // that four blocks, one a SIMD, fill a CU's 160 KB)
     __shared__ double ysh[LY_SLOTS * 64];
     __shared__ double wsh[LW_SLOTS * 64];
-    auto ly = [&](int k) -> double& { return ysh[k * 64 + threadIdx.x]; };
-    auto lw = [&](int k) -> double& { return wsh[k * 64 + threadIdx.x]; };
+    auto ly = [&](int r) { return LaneRow<double, 64>{ysh + r * 512 + lane_now()}; };
+    auto lw = [&](int r) { return LaneRow<double, 64>{wsh + r * 512 + lane_now()}; };
     const int lane = __lane_id();
     while (true) {
         // the wave takes 64 consecutive rays of the step-ordered list

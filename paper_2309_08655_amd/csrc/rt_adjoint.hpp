@@ -566,11 +566,19 @@ RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, do
     }
 }
 
-// Per-lane scratch of the reverse sweep's step adjoint: ly(k), k < LY_SLOTS, holds the stage
-// states Y_i (i = 2..6) of the step being walked at 8 (i - 2) + d, and lw(k), k < LW_SLOTS,
-// the stage-state adjoints w_i (i = 2..6) at 8 (i - 2) + d.
+// Per-lane scratch of the reverse sweep's step adjoint, in rows of 8 values: ly(r) is the row
+// of the stage state Y_{r+2} (r < 5) of the step being walked, lw(r) that of the stage-state
+// adjoint w_{r+2}; a row is indexed [d], d < 8.  LY_SLOTS and LW_SLOTS count the values.
 constexpr int LY_SLOTS = 40;
 constexpr int LW_SLOTS = 40;
+
+// A row of 8 values of one lane, the d-th at p[d * STRIDE] (STRIDE = the wave's width where
+// the lanes' values interleave, 1 for a lane of its own)
+template <class T, int STRIDE>
+struct LaneRow {
+    T* p;
+    RT_HD T& operator[](int d) const { return p[d * STRIDE]; }
+};
 
 // Adjoint of one accepted step y_n -> y_{n+1} through its stages,
 //   Y_l = y_n + h sum_{i<l} a_li K_i,  y_{n+1} = y_n + h sum_i b_i K_i,  K_i = f(Y_i).
@@ -598,14 +606,18 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool d
     if (dense) {
         for (int d = 0; d < 8; ++d) Yn[d] = y7[d];
     } else {
-        for (int d = 0; d < 8; ++d) Yn[d] = ly(8 * (top - 2) + d);
+        const auto r = ly(top - 2);
+        for (int d = 0; d < 8; ++d) Yn[d] = r[d];
     }
 #pragma unroll 1
-    for (int i = 7; i >= 1; --i) {
+    for (int i0 = 7; i0 >= 1; --i0) {
+        // read before any lane leaves the iteration: the stage index is the wave's
+        const int i = wave_uniform(i0);
         if (i > top) continue;
         for (int d = 0; d < 8; ++d) Y[d] = Yn[d];
         if (i > 2) {
-            for (int d = 0; d < 8; ++d) Yn[d] = ly(8 * (i - 3) + d);
+            const auto r = ly(i - 3);
+            for (int d = 0; d < 8; ++d) Yn[d] = r[d];
         } else if (i == 2) {
             for (int d = 0; d < 8; ++d) Yn[d] = yn[d];
         }
@@ -617,7 +629,8 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool d
         for (int l = 2; l <= 6; ++l) {
             if (l <= i) continue;
             const S c = h * Al[l - 2][i - 1];
-            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * lw(8 * (l - 2) + d);
+            const auto r = lw(l - 2);
+            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
         }
         stage_vjp<FL, S>(I, Y, v, vy, vc, gjs);
         for (int c = 0; c < 5; ++c) tc[c] = tc[c] + vc[c];
@@ -625,8 +638,10 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool d
             for (int d = 0; d < 8; ++d) ynb[d] = ynb[d] + vy[d];
         } else {
             for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
-            if (i >= 2)
-                for (int d = 0; d < 8; ++d) lw(8 * (i - 2) + d) = vy[d];
+            if (i >= 2) {
+                const auto r = lw(i - 2);
+                for (int d = 0; d < 8; ++d) r[d] = vy[d];
+            }
         }
     }
     for (int d = 0; d < 8; ++d) yb[d] = yb[d] + ynb[d];
@@ -655,7 +670,7 @@ RT_HD void dense_point_deriv(const double* yn, const double* K, const double* yn
 // Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing of r_max
 // at theta on the last step).  load(s, y, &h, &facmax, &gjs) reads checkpoint s; rb(idx, d)
 // is the replay buffer (C steps x 11 values: y, h, the null-surface crossing thk (2: none)
-// and the piece gjs of the step); ly(k) and lw(k) are the per-lane scratch of step_adjoint.  Adds
+// and the piece gjs of the step); ly(r) and lw(r) are the per-lane rows of step_adjoint.  Adds
 // d(w G(y_f))/dp to pb.  Returns the number of steps or checkpoints the recompute could not
 // reproduce (0 when all is well).
 template <bool FL = true, class Load, class Replay, class LaneY, class LaneW>
@@ -706,7 +721,8 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             adj_rhs<FL>(I, yn, K, gn);
             adj_stages<FL>(I, yn, K, ynew, hn,
                            [&](int i, const double* Yi) {
-                               for (int d = 0; d < 8; ++d) ly(8 * (i - 2) + d) = Yi[d];
+                               const auto r = ly(i - 2);
+                               for (int d = 0; d < 8; ++d) r[d] = Yi[d];
                            },
                            gn);
             const bool last = (first + idx == S - 1);

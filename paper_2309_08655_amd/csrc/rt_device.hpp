@@ -60,6 +60,15 @@ RT_HD double frcp(double x) {
 }
 // One Newton step only: about 1e-14 relative, for values that merely feed the step
 // controller's accept test and step-size heuristic.
+// A loop counter or index that has the same value in every lane of the wave, so held in a
+// scalar register: its table look-ups become scalar loads and its tests scalar branches.
+RT_HD int wave_uniform(int x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_readfirstlane(x);
+#else
+    return x;
+#endif
+}
 RT_HD double frcp_coarse(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
     double r = __builtin_amdgcn_rcp(x);

@@ -81,8 +81,8 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
             *gjs = ck[(size_t)sg * 11 + 10];
         };
         auto rb = [&](int idx, int d) -> double& { return rbuf[(size_t)idx * 11 + d]; };
-        auto ly = [&](int k) -> double& { return ybuf[(size_t)k]; };
-        auto lw = [&](int k) -> double& { return wbuf[(size_t)k]; };
+        auto ly = [&](int r) { return LaneRow<double, 1>{ybuf.data() + 8 * r}; };
+        auto lw = [&](int r) { return LaneRow<double, 1>{wbuf.data() + 8 * r}; };
         double pb[6] = {0, 0, 0, 0, 0, 0};
         missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, seedv[8], C, load, rb, ly, lw, obs, gbar, n_obs,
                                    sigma, pb);
