@@ -97,20 +97,17 @@ int main() {
                 // adjoint: one stage vector-Jacobian product (a 1-tangent dual-number
                 // Hessian-vector product, a 3-tangent pass for the parameter channels and the
                 // vacuum part) and the reverse sweep through the six stages of a plain step
-                FC v[8], vy[8], vc[5], ybuf[LY_SLOTS], wbuf[LW_SLOTS], yb[8], ynb[8], tc[5], gyf[8], dc[7];
-                for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); ynb[d] = FC(0.01 * d); }
-                for (int d = 0; d < LY_SLOTS; ++d) ybuf[d] = y[d % 8];
-                for (int d = 0; d < LW_SLOTS; ++d) wbuf[d] = FC(0.0);
-                for (int d = 0; d < 8; ++d) gyf[d] = FC(0.0);
-                for (int d = 0; d < 7; ++d) dc[d] = FC(0.0);
+                FC v[8], vy[8], vc[5], rows[LR_SLOTS], yb[8], tc[5];
+                for (int d = 0; d < 8; ++d) { v[d] = FC(0.1 * (d + 1)); yb[d] = FC(0.0); }
+                for (int d = 0; d < LR_SLOTS; ++d) rows[d] = y[d % 8];
+                for (int d = 0; d < 8; ++d) rows[8 * LR_YNB + d] = FC(0.01 * d);
                 for (int q = 0; q < 5; ++q) tc[q] = FC(0.0);
                 g_flops = 0;
                 stage_vjp<false, FC>(I, y, v, vy, vc);
                 long long fvjp = g_flops;
                 g_flops = 0;
-                step_adjoint<false, FC>(I, y, ynew, FC(0.1), false, gyf, dc, ynb, yb, tc,
-                                        [&](int r) { return LaneRow<FC, 1>{ybuf + 8 * r}; },
-                                        [&](int r) { return LaneRow<FC, 1>{wbuf + 8 * r}; }, 0.0);
+                step_adjoint<false, FC>(I, ynew, FC(0.1), false, yb, tc,
+                                        [&](int r) { return LaneRow<FC, 1>{rows + 8 * r}; }, 0.0);
                 long long fstages = g_flops;
                 // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension
                 FC yt[8];

@@ -327,12 +327,10 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     unsigned long long missing = 0;
     const unsigned long long rlen = lctr->len < (unsigned long long)n ? lctr->len : (unsigned long long)n;
     auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 11 + d) * REV_LANES + lane_g]; };
-    // the walked step's stage states and their adjoints in LDS (one wave a block: 40 KB, so
-    // that four blocks, one a SIMD, fill a CU's 160 KB)
-    __shared__ double ysh[LY_SLOTS * 64];
-    __shared__ double wsh[LW_SLOTS * 64];
-    auto ly = [&](int r) { return LaneRow<double, 64>{ysh + r * 512 + lane_now()}; };
-    auto lw = [&](int r) { return LaneRow<double, 64>{wsh + r * 512 + lane_now()}; };
+    // the walked step's rows in LDS (one wave a block: 36 KB, so that four blocks, one a
+    // SIMD, fit a CU's 160 KB)
+    __shared__ double lsh[LR_SLOTS * 64];
+    auto lr = [&](int r) { return LaneRow<double, 64>{lsh + r * 512 + lane_now()}; };
     const int lane = __lane_id();
     while (true) {
         // the wave takes 64 consecutive rays of the step-ordered list
@@ -374,7 +372,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *gjs = c[10];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, ly, lw,
+        int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, lr,
                                            obs, gbar, n_obs, sigma, pb);
         if (!chain_ok) ++miss;
         if (miss) {

@@ -566,11 +566,18 @@ RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, do
     }
 }
 
-// Per-lane scratch of the reverse sweep's step adjoint, in rows of 8 values: ly(r) is the row
-// of the stage state Y_{r+2} (r < 5) of the step being walked, lw(r) that of the stage-state
-// adjoint w_{r+2}; a row is indexed [d], d < 8.  LY_SLOTS and LW_SLOTS count the values.
-constexpr int LY_SLOTS = 40;
-constexpr int LW_SLOTS = 40;
+// Per-lane scratch of the reverse sweep's step adjoint, in rows of 8 values: lr(r) is row r,
+// indexed [d], d < 8.
+//   rows 0..4  the stage state Y_{r+2} of the step being walked; once stage r + 2 has taken
+//              its state, the row holds that stage's adjoint w_{r+2} instead
+//   LR_YNB     the adjoint of the step's end y_{n+1}
+//   LR_GYF     the adjoint of the step's output where it ends on its continuous extension
+//   LR_DC      that output's weights of K_1..K_7 (7 values)
+//   LR_YN      the step's start y_n
+// Kept there rather than in registers, these leave the stage products room to run without
+// spilling.
+constexpr int LR_YNB = 5, LR_GYF = 6, LR_DC = 7, LR_YN = 8, LR_ROWS = 9;
+constexpr int LR_SLOTS = 8 * LR_ROWS;
 
 // A row of 8 values of one lane, the d-th at p[d * STRIDE] (STRIDE = the wave's width where
 // the lanes' values interleave, 1 for a lane of its own)
@@ -582,18 +589,18 @@ struct LaneRow {
 
 // Adjoint of one accepted step y_n -> y_{n+1} through its stages,
 //   Y_l = y_n + h sum_{i<l} a_li K_i,  y_{n+1} = y_n + h sum_i b_i K_i,  K_i = f(Y_i).
-// On entry ly holds Y_2..Y_6 and y7 the step's end y_{n+1} = Y_7, where K_7 = f(Y_7) is taken
-// (read for dense = true only, before the first stage); yb holds the adjoint of y_n from
-// the step's output and ynb that of y_{n+1}; the output's adjoint of K_i is dc[i - 1] gyf
-// (dense = true: the step ends on its continuous extension, whose value depends on
-// K_1..K_7; otherwise the output is y_{n+1} itself and K_7 is not visited).
+// On entry rows 0..4 of lr hold Y_2..Y_6, LR_YN holds y_n and y7 the step's end
+// y_{n+1} = Y_7, where K_7 = f(Y_7) is taken (read for dense = true only, before the first
+// stage); yb holds the adjoint of y_n from the step's output and row LR_YNB that of
+// y_{n+1}; with dense = true the step ends on its continuous extension, whose value depends
+// on K_1..K_7, and the output's adjoint of K_i is dc_i gyf (rows LR_DC and LR_GYF);
+// otherwise the output is y_{n+1} itself and K_7 is not visited.
 // Each stage, last first, takes Kbar_i = dc_i gyf + h b_i ynb + h sum_{l>i} a_li w_l and
 // gives w_i = (df/dy(Y_i))^T Kbar_i, which goes to ynb for i = 7 and to yb otherwise;
-// w_2..w_6 are kept in lw.  Each stage state is read one stage ahead of its use.  On
-// return yb holds the adjoint of y_n; the parameter channels are added to tc.
-template <bool FL, class S, class LaneY, class LaneW>
-RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool dense, const S* gyf, const S* dc,
-                        S* ynb, S* yb, S* tc, LaneY&& ly, LaneW&& lw, double gjs) {
+// w_2..w_6 replace Y_2..Y_6 in their rows.  On return yb holds the adjoint of y_n; the
+// parameter channels are added to tc.
+template <bool FL, class S, class Rows>
+RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, S* tc, Rows&& lr, double gjs) {
     using namespace dp5;
     const double Al[5][5] = {{a21, 0, 0, 0, 0},
                              {a31, a32, 0, 0, 0},
@@ -601,50 +608,51 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* yn, const S* y7, S h, bool d
                              {a51, a52, a53, a54, 0},
                              {a61, a62, a63, a64, a65}};  // a_li: row l - 2, column i - 1
     const double Bw[7] = {b1, 0.0, b3, b4, b5, b6, 0.0};
-    S v[8], Y[8], Yn[8], vy[8], vc[5];
+    S v[8], Y[8], vy[8], vc[5];
     const int top = dense ? 7 : 6;
-    if (dense) {
-        for (int d = 0; d < 8; ++d) Yn[d] = y7[d];
-    } else {
-        const auto r = ly(top - 2);
-        for (int d = 0; d < 8; ++d) Yn[d] = r[d];
-    }
 #pragma unroll 1
     for (int i0 = 7; i0 >= 1; --i0) {
         // read before any lane leaves the iteration: the stage index is the wave's
         const int i = wave_uniform(i0);
         if (i > top) continue;
-        for (int d = 0; d < 8; ++d) Y[d] = Yn[d];
-        if (i > 2) {
-            const auto r = ly(i - 3);
-            for (int d = 0; d < 8; ++d) Yn[d] = r[d];
-        } else if (i == 2) {
-            for (int d = 0; d < 8; ++d) Yn[d] = yn[d];
+        if (i == 7) {
+            for (int d = 0; d < 8; ++d) Y[d] = y7[d];
+        } else {
+            const auto r = lr(i >= 2 ? i - 2 : LR_YN);
+            for (int d = 0; d < 8; ++d) Y[d] = r[d];
         }
         const S hb = h * Bw[i - 1];
-        for (int d = 0; d < 8; ++d) v[d] = hb * ynb[d];
-        if (dense)
-            for (int d = 0; d < 8; ++d) v[d] = v[d] + dc[i - 1] * gyf[d];
+        {
+            const auto r = lr(LR_YNB);
+            for (int d = 0; d < 8; ++d) v[d] = hb * r[d];
+        }
+        if (dense) {
+            const S c = lr(LR_DC)[i - 1];
+            const auto r = lr(LR_GYF);
+            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
+        }
 #pragma unroll
         for (int l = 2; l <= 6; ++l) {
             if (l <= i) continue;
             const S c = h * Al[l - 2][i - 1];
-            const auto r = lw(l - 2);
+            const auto r = lr(l - 2);
             for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
         }
         stage_vjp<FL, S>(I, Y, v, vy, vc, gjs);
         for (int c = 0; c < 5; ++c) tc[c] = tc[c] + vc[c];
         if (i == 7) {
-            for (int d = 0; d < 8; ++d) ynb[d] = ynb[d] + vy[d];
+            const auto r = lr(LR_YNB);
+            for (int d = 0; d < 8; ++d) r[d] = r[d] + vy[d];
         } else {
             for (int d = 0; d < 8; ++d) yb[d] = yb[d] + vy[d];
             if (i >= 2) {
-                const auto r = lw(i - 2);
+                const auto r = lr(i - 2);
                 for (int d = 0; d < 8; ++d) r[d] = vy[d];
             }
         }
     }
-    for (int d = 0; d < 8; ++d) yb[d] = yb[d] + ynb[d];
+    const auto r = lr(LR_YNB);
+    for (int d = 0; d < 8; ++d) yb[d] = yb[d] + r[d];
 }
 
 // E(theta) and dE/dtheta on the continuous extension of the step yn -> ynew
@@ -670,12 +678,12 @@ RT_HD void dense_point_deriv(const double* yn, const double* K, const double* yn
 // Reverse sweep of one escaped ray (S accepted steps, nseg checkpoints, crossing of r_max
 // at theta on the last step).  load(s, y, &h, &facmax, &gjs) reads checkpoint s; rb(idx, d)
 // is the replay buffer (C steps x 11 values: y, h, the null-surface crossing thk (2: none)
-// and the piece gjs of the step); ly(r) and lw(r) are the per-lane rows of step_adjoint.  Adds
+// and the piece gjs of the step); lr(r) gives the per-lane rows of step_adjoint.  Adds
 // d(w G(y_f))/dp to pb.  Returns the number of steps or checkpoints the recompute could not
 // reproduce (0 when all is well).
-template <bool FL = true, class Load, class Replay, class LaneY, class LaneW>
+template <bool FL = true, class Load, class Replay, class Rows>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
-                          int nseg, double th, double w, int C, Load&& load, Replay&& rb, LaneY&& ly, LaneW&& lw,
+                          int nseg, double th, double w, int C, Load&& load, Replay&& rb, Rows&& lr,
                           const double* obs, const double* gbar, int n_obs, double sigma, double pb[6]) {
     using namespace dp5;
     double tc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // parameter channels of the stage products
@@ -716,18 +724,21 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             double yn[8];
             for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
             const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
+            {
+                const auto r = lr(LR_YN);
+                for (int d = 0; d < 8; ++d) r[d] = yn[d];
+            }
             // the step's stages again (no error estimate: the step is known accepted), its
             // inner stage states into ly
             adj_rhs<FL>(I, yn, K, gn);
             adj_stages<FL>(I, yn, K, ynew, hn,
                            [&](int i, const double* Yi) {
-                               const auto r = ly(i - 2);
+                               const auto r = lr(i - 2);
                                for (int d = 0; d < 8; ++d) r[d] = Yi[d];
                            },
                            gn);
             const bool last = (first + idx == S - 1);
             const bool dense = last || thk <= 1.0;
-            double ynb[8], gyf[8], dc[7];
             if (dense) {
                 // the step ends inside, at E(theta): y_f at r(E) = r_max, or the restart
                 // point on the null surface g(E) = 0.  The adjoint of E(theta) loses its
@@ -735,7 +746,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 //   beta = (ybar . dE/dtheta) / (q . dE/dtheta),  ybar -= beta q,
                 // and for g the parameters' part -beta dg/dp joins the channels.
                 const double t = last ? th : thk;
-                double e[8], et[8], q[4], gOm = 0.0, gth = 0.0;
+                double e[8], et[8], q[4], gyf[8], dc[7], gOm = 0.0, gth = 0.0;
                 dense_point_deriv(yn, K, ynew, hn, t, e, et);
                 if (last) {
                     // the observable with 8 state and 6 parameter tangents (the non-inlined
@@ -769,20 +780,22 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 dc[4] = hn * c5 * d5;
                 dc[5] = hn * c5 * d6;
                 dc[6] = hn * (c5 * d7 - c4);
+                const auto rg = lr(LR_GYF), rd = lr(LR_DC), rn = lr(LR_YNB);
+                for (int i = 0; i < 7; ++i) rd[i] = dc[i];
                 for (int d = 0; d < 8; ++d) {
-                    ynb[d] = cy * gyf[d];
+                    rg[d] = gyf[d];
+                    rn[d] = cy * gyf[d];
                     yb[d] = (1.0 - cy) * gyf[d];
                 }
             } else {
                 // y_{n+1} = y_n + h sum_i b_i K_i is the step's output; yb holds its adjoint
+                const auto rn = lr(LR_YNB);
                 for (int d = 0; d < 8; ++d) {
-                    ynb[d] = yb[d];
+                    rn[d] = yb[d];
                     yb[d] = 0.0;
-                    gyf[d] = 0.0;
                 }
-                for (int i = 0; i < 7; ++i) dc[i] = 0.0;
             }
-            step_adjoint<FL, double>(I, yn, ynew, hn, dense, gyf, dc, ynb, yb, tc, ly, lw, gn);
+            step_adjoint<FL, double>(I, ynew, hn, dense, yb, tc, lr, gn);
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels

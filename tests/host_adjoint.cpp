@@ -40,7 +40,7 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
     for (int q = 0; q < n_obs; ++q) flux[q] = 0.0;
     for (int q = 0; q < 6; ++q) grad[q] = 0.0;
     long long missing = 0;
-    std::vector<double> ck((size_t)Kc * 11), rbuf((size_t)C * 11), ybuf(LY_SLOTS), wbuf(LW_SLOTS);
+    std::vector<double> ck((size_t)Kc * 11), rbuf((size_t)C * 11), rows(LR_SLOTS);
     for (long long i = 0; i < n; ++i) {
         for (int q = 0; q < 6; ++q) gray[i * 6 + q] = 0.0;
         double seedv[10];
@@ -81,10 +81,9 @@ long long host_flux_grad(const double* p, const double* fd, const int* fi, const
             *gjs = ck[(size_t)sg * 11 + 10];
         };
         auto rb = [&](int idx, int d) -> double& { return rbuf[(size_t)idx * 11 + d]; };
-        auto ly = [&](int r) { return LaneRow<double, 1>{ybuf.data() + 8 * r}; };
-        auto lw = [&](int r) { return LaneRow<double, 1>{wbuf.data() + 8 * r}; };
+        auto lr = [&](int r) { return LaneRow<double, 1>{rows.data() + 8 * r}; };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, seedv[8], C, load, rb, ly, lw, obs, gbar, n_obs,
+        missing += adj_reverse_ray(I, A, tol, seed, i, R.nacc, R.nseg, th, seedv[8], C, load, rb, lr, obs, gbar, n_obs,
                                    sigma, pb);
         for (int q = 0; q < 6; ++q) {
             gray[i * 6 + q] = pb[q] / (double)n;
