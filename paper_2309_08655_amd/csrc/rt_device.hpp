@@ -338,17 +338,20 @@ template <class T>
 RT_HD void small_angle_sincos(T x, T* s, T* c) {
     if (fabs(value(x)) <= 0.03125) {
         // the angles of the tracing kernels' stages: the series to x^7 and x^8 is exact to
-        // below 3e-18 relative for |x| <= 1/32
+        // below 3e-18 relative for |x| <= 1/32.  In nested form,
+        //   sin x = x (1 - x^2/6 (1 - x^2/20 (1 - x^2/42))),
+        //   cos x = 1 - x^2/2 (1 - x^2/12 (1 - x^2/30 (1 - x^2/56))),
+        // every factor is one FMA onto the inline constant 1 (a Horner chain would need each
+        // coefficient moved into the accumulator first).
         const T x2 = x * x;
-        T ps = -1.0 / 5040.0;
-        ps = 1.0 / 120.0 + x2 * ps;
-        ps = -1.0 / 6.0 + x2 * ps;
-        *s = x + (x * x2) * ps;
-        T pc = 1.0 / 40320.0;
-        pc = -1.0 / 720.0 + x2 * pc;
-        pc = 1.0 / 24.0 + x2 * pc;
-        pc = -0.5 + x2 * pc;
-        *c = 1.0 + x2 * pc;
+        T ps = 1.0 + x2 * (-1.0 / 42.0);
+        ps = 1.0 + (x2 * (-1.0 / 20.0)) * ps;
+        ps = 1.0 + (x2 * (-1.0 / 6.0)) * ps;
+        *s = x * ps;
+        T pc = 1.0 + x2 * (-1.0 / 56.0);
+        pc = 1.0 + (x2 * (-1.0 / 30.0)) * pc;
+        pc = 1.0 + (x2 * (-1.0 / 12.0)) * pc;
+        *c = 1.0 + (x2 * -0.5) * pc;
         return;
     }
     int k = 0;
