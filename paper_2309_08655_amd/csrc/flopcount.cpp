@@ -106,7 +106,7 @@ int main() {
                 stage_vjp<false, FC>(I, y, v, vy, vc);
                 long long fvjp = g_flops;
                 g_flops = 0;
-                step_adjoint<false, FC>(I, ynew, FC(0.1), false, yb, tc,
+                step_adjoint<false, false, FC>(I, ynew, FC(0.1), false, yb, tc,
                                         [&](int r) { return LaneRow<FC, 1>{rows + 8 * r}; }, 0.0);
                 long long fstages = g_flops;
                 // backward events: one probe of G = g^{mu nu} k k + m^2 on the continuous extension

@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *gjs = c[10];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        int miss = adj_reverse_ray<LARMOR>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, lr,
+        int miss = adj_reverse_ray<LARMOR, MODE == MODE_ISO_GJ>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, lr,
                                            obs, gbar, n_obs, sigma, pb);
         if (!chain_ok) ++miss;
         if (miss) {

@@ -599,7 +599,7 @@ struct LaneRow {
 // gives w_i = (df/dy(Y_i))^T Kbar_i, which goes to ynb for i = 7 and to yb otherwise;
 // w_2..w_6 replace Y_2..Y_6 in their rows.  On return yb holds the adjoint of y_n; the
 // parameter channels are added to tc.
-template <bool FL, class S, class Rows>
+template <bool FL, bool ISO, class S, class Rows>
 RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, S* tc, Rows&& lr, double gjs) {
     using namespace dp5;
     const double Al[5][5] = {{a21, 0, 0, 0, 0},
@@ -638,7 +638,10 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, 
             const auto r = lr(l - 2);
             for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
         }
-        stage_vjp<FL, S>(I, Y, v, vy, vc, gjs);
+        if constexpr (ISO)
+            stage_vjp_iso<S>(I, Y, v, vy, vc, gjs);
+        else
+            stage_vjp<FL, S>(I, Y, v, vy, vc, gjs);
         for (int c = 0; c < 5; ++c) tc[c] = tc[c] + vc[c];
         if (i == 7) {
             const auto r = lr(LR_YNB);
@@ -681,7 +684,7 @@ RT_HD void dense_point_deriv(const double* yn, const double* K, const double* yn
 // and the piece gjs of the step); lr(r) gives the per-lane rows of step_adjoint.  Adds
 // d(w G(y_f))/dp to pb.  Returns the number of steps or checkpoints the recompute could not
 // reproduce (0 when all is well).
-template <bool FL = true, class Load, class Replay, class Rows>
+template <bool FL = true, bool ISO = false, class Load, class Replay, class Rows>
 RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC& tol, uint64_t seed, int64_t j, int S,
                           int nseg, double th, double w, int C, Load&& load, Replay&& rb, Rows&& lr,
                           const double* obs, const double* gbar, int n_obs, double sigma, double pb[6]) {
@@ -795,7 +798,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     yb[d] = 0.0;
                 }
             }
-            step_adjoint<FL, double>(I, ynew, hn, dense, yb, tc, lr, gn);
+            step_adjoint<FL, ISO, double>(I, ynew, hn, dense, yb, tc, lr, gn);
         }
     }
     // seed: y_0(p) and w(p); the stage products' channels
