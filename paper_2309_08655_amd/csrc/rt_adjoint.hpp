@@ -72,9 +72,9 @@ struct NoStages {
 
 // The stages of a DOPRI5 step of size hh from y with K[0..7] = f(y) set: fills K[8..55]
 // (stages 2..7, the last = f(ynew)) and ynew, and hands each inner stage state Y_i
-// (i = 2..6) to stages(i, Y_i).
-template <bool FL = true, class Sink>
-RT_HD void adj_stages(const InstT<double>& I, const double* y, double* K, double* ynew, double hh, Sink&& stages,
+// (i = 2..6) to stages(i, Y_i).  y is anything indexed [d] (registers, or a lane's row).
+template <bool FL = true, class Sink, class YV>
+RT_HD void adj_stages(const InstT<double>& I, const YV& y, double* K, double* ynew, double hh, Sink&& stages,
                       double gjs) {
     using namespace dp5;
     const double A[6][6] = {{a21, 0, 0, 0, 0, 0},
@@ -185,8 +185,11 @@ RT_HD void adj_advance(const InstT<double>& I, double* y, double* K, const doubl
 }
 
 // g = 3 n_z (m . n) - cos theta_m at y and its derivatives: gy[0..3] by (x, t), *gOm by
-// Omega, *gth by theta_m (dual numbers, 6 tangents)
-RT_HD_NOINLINE void gj_factor_grad(const InstT<double>& I, const double* y, double gy[4], double* gOm, double* gth) {
+// Omega, *gth by theta_m (dual numbers, 6 tangents).  The star's constants come by value, so
+// that the caller's instance never has its address taken (its switches stay compile-time
+// constants where the caller fixes them).
+RT_HD_NOINLINE void gj_factor_grad(double Om, double cm, double sm, int oblique, const double* y, double gy[4],
+                                   double* gOm, double* gth) {
     typedef gdual<6, double> G6;
     G6 x[4];
     for (int i = 0; i < 4; ++i) {
@@ -194,13 +197,13 @@ RT_HD_NOINLINE void gj_factor_grad(const InstT<double>& I, const double* y, doub
         x[i].d[i] = 1.0;
     }
     InstT<G6> J;
-    J.Om = G6(I.Om);
+    J.Om = G6(Om);
     J.Om.d[4] = 1.0;
-    J.cm = G6(I.cm);
-    J.cm.d[5] = -I.sm;
-    J.sm = G6(I.sm);
-    J.sm.d[5] = I.cm;
-    J.oblique = I.oblique;
+    J.cm = G6(cm);
+    J.cm.d[5] = -sm;
+    J.sm = G6(sm);
+    J.sm.d[5] = cm;
+    J.oblique = oblique;
     const G6 ir = rcp(sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
     const G6 n[3] = {x[0] * ir, x[1] * ir, x[2] * ir};
     G6 m[3], mt[3];
@@ -658,8 +661,9 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, 
     for (int d = 0; d < 8; ++d) yb[d] = yb[d] + r[d];
 }
 
-// E(theta) and dE/dtheta on the continuous extension of the step yn -> ynew
-RT_HD void dense_point_deriv(const double* yn, const double* K, const double* ynew, double hn, double t, double* e,
+// E(theta) and dE/dtheta on the continuous extension of the step yn -> ynew (yn indexed [d])
+template <class YV>
+RT_HD void dense_point_deriv(const YV& yn, const double* K, const double* ynew, double hn, double t, double* e,
                              double* et) {
     using namespace dp5;
     const double om = 1.0 - t;
@@ -732,9 +736,11 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 for (int d = 0; d < 8; ++d) r[d] = yn[d];
             }
             // the step's stages again (no error estimate: the step is known accepted), its
-            // inner stage states into ly
+            // inner stage states into rows 0..4
             adj_rhs<FL>(I, yn, K, gn);
-            adj_stages<FL>(I, yn, K, ynew, hn,
+            // from here on y_n is read from its row, which keeps it out of the registers
+            const auto ynr = lr(LR_YN);
+            adj_stages<FL>(I, ynr, K, ynew, hn,
                            [&](int i, const double* Yi) {
                                const auto r = lr(i - 2);
                                for (int d = 0; d < 8; ++d) r[d] = Yi[d];
@@ -750,7 +756,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                 // and for g the parameters' part -beta dg/dp joins the channels.
                 const double t = last ? th : thk;
                 double e[8], et[8], q[4], gyf[8], dc[7], gOm = 0.0, gth = 0.0;
-                dense_point_deriv(yn, K, ynew, hn, t, e, et);
+                dense_point_deriv(ynr, K, ynew, hn, t, e, et);
                 if (last) {
                     // the observable with 8 state and 6 parameter tangents (the non-inlined
                     // helpers get copies, so that the sweep's own arrays never leave registers)
@@ -762,8 +768,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     q[0] = e[0] / r; q[1] = e[1] / r; q[2] = e[2] / r; q[3] = 0.0;
                 } else {
                     for (int d = 0; d < 8; ++d) gyf[d] = yb[d];
-                    const InstT<double> Ic = I;
-                    gj_factor_grad(Ic, e, q, &gOm, &gth);
+                    gj_factor_grad(I.Om, I.cm, I.sm, I.oblique, e, q, &gOm, &gth);
                 }
                 double num = 0.0, den = 0.0;
                 for (int d = 0; d < 8; ++d) num += gyf[d] * et[d];
