@@ -47,6 +47,7 @@ static InstT<FC> inst(int plasma, int density, bool oblique) {
     InstT<FC> I;
     I.rs = FC(4.13); I.R = FC(10.0); I.Om = FC(2e-5); I.cm = FC(oblique ? 0.95 : 1.0);
     I.sm = FC(oblique ? 0.3 : 0.0); I.Cwp = FC(1.0); I.R3 = FC(1000.0); I.ma2 = FC(0.99);
+    I.iOm = FC(1.0 / I.Om.v); I.Omsm = FC(I.Om.v * I.sm.v); I.msm = FC(-I.sm.v); I.CwpR3 = FC(I.Cwp.v * I.R3.v);
     I.plasma = plasma; I.density = density; I.oblique = oblique ? 1 : 0;
     I.gr_dipole = 0; I.bnorm = FC(1.0); I.larmor = 0; I.kL = FC(0.0);
     return I;

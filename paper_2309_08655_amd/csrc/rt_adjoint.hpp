@@ -507,7 +507,7 @@ RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc
     {
         InstT<D2> J = lift_inst<D2>(I);  // grad P
         J.larmor = 0;
-        J.cm.d[1] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
+        J.cm.d[1] = I.msm;  // d/dtheta_m of (cos, sin)
         J.sm.d[1] = I.cm;
         D2 yd[4], gp[4];
         for (int i = 0; i < 4; ++i) {
@@ -525,7 +525,7 @@ RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc
         vc[2] = S(0.0) - a;
         vc[3] = S(0.0) - b;
         // Om (see stage_vjp): dH/dt = dP/dt, u_t = -v_7
-        vc[1] = (Y[3] * vy[3] - v[7] * gp[3].v) * frcp(I.Om);
+        vc[1] = (Y[3] * vy[3] - v[7] * gp[3].v) * I.iOm;
     }
     vc[4] = S(0.0);
 }
@@ -542,12 +542,12 @@ RT_HD void stage_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, do
     S f[8];
     vjp_state<FL, S>(I, Y, v, vy, f, gjs);
     // Om: u_t = -v_7, dH/dt = -f_7, (Hess(H) u)_t = vy_3
-    vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * frcp(I.Om);
+    vc[1] = (v[7] * f[7] + Y[3] * vy[3]) * I.iOm;
     {
         InstT<gdual<2, S>> J = lift_inst<gdual<2, S>>(I);
         if constexpr (!FL) J.larmor = 0;
         J.rs.d[0] = S(1.0);
-        J.cm.d[1] = S(0.0) - I.sm;  // d/dtheta_m of (cos, sin)
+        J.cm.d[1] = I.msm;  // d/dtheta_m of (cos, sin)
         J.sm.d[1] = I.cm;
         vjp_pair<S>(J, Y, v, &vc[0], &vc[2], gjs);
     }

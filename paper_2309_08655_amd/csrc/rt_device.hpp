@@ -251,6 +251,15 @@ struct InstT {
     T bnorm;        // field-strength factor: 1, or 1 / G(r_s/R) for the GR dipole (B0 at the pole)
     int larmor;     // finite magnetisation: the plasma response at the cyclotron frequency w_L
     T kL;           // (w_L / w_inf)^2 = kL r^-6 F^2 (1 + c mu^2): (hbar e B0 bnorm / (2 m_e c w_inf))^2 R^6
+    // Products of the constants above, formed once by whoever builds the instance: a product
+    // of two star constants formed in a kernel is hoisted out of its loops into a vector
+    // register held (or spilled) for the whole launch, while these arrive with the other
+    // constants in scalar registers.  Values only: dual-number code forms the products
+    // itself where derivatives must flow through them.
+    T iOm;    // 1 / Om
+    T Omsm;   // Om sin theta_m
+    T msm;    // -sin theta_m
+    T CwpR3;  // Cwp R^3
 };
 
 // ----------------------------------------------------------------------------
@@ -430,7 +439,11 @@ RT_HD void magnetic_axis(const InstT<T>& I, const T& t, T m[3], T mt[3], const A
             sincos_t(I.Om * t, &s, &c);
         }
         m[0] = I.sm * c; m[1] = I.sm * s; m[2] = I.cm;
-        T w = I.Om * I.sm;
+        T w;
+        if constexpr (std::is_same<T, double>::value)
+            w = I.Omsm;
+        else
+            w = I.Om * I.sm;
         mt[0] = -(w * s); mt[1] = w * c; mt[2] = T(0.0);
     } else {
         m[0] = T(0.0); m[1] = T(0.0); m[2] = I.cm;
@@ -450,7 +463,13 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
         return p;
     }
     T ir3 = ir * ir * ir;
-    T D3 = I.Cwp * I.R3 * ir3;  // Cwp (R/r)^3
+    // Cwp (R/r)^3 = (Cwp R^3) r^-3; in dual numbers grouped so that no product of two star
+    // constants is formed (the derivatives by Cwp flow through it)
+    T D3;
+    if constexpr (std::is_same<T, double>::value)
+        D3 = I.CwpR3 * ir3;
+    else
+        D3 = I.Cwp * (I.R3 * ir3);
     if (I.density == DEN_GJ) {
         // P = D3 |g|, g = 3 n_z mu - cos(theta_m); with a = 3 sign(g),
         // grad P = (D3/r) [a (n_z m + mu e_z) - (2 a n_z mu + 3 |g|) n],  dP/dt = D3 a n_z dmu

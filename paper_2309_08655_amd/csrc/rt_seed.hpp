@@ -76,6 +76,9 @@ RT_HD InstT<T> make_inst_t(const T p[6], const StarFixed& f) {
     I.cm = c_;
     I.sm = s_;
     I.oblique = (value(s_) != 0.0) ? 1 : 0;
+    I.iOm = rcp(I.Om);
+    I.Omsm = I.Om * I.sm;
+    I.msm = T(0.0) - I.sm;
     // field shape: the Schwarzschild vacuum dipole, normalised to B0 at the surface pole
     I.gr_dipole = ((f.flags & FLAG_GR_DIPOLE) && value(I.rs) > 0.0) ? 1 : 0;
     I.bnorm = T(1.0);
@@ -105,6 +108,7 @@ RT_HD InstT<T> make_inst_t(const T p[6], const StarFixed& f) {
     I.larmor = (f.flags & FLAG_FINITE_LARMOR) ? 1 : 0;
     const T bL = (0.5 * phys::hbar_wc_per_G()) * B0 * I.bnorm * rcp(w_inf);
     I.kL = (bL * bL) * (I.R3 * I.R3);
+    I.CwpR3 = I.Cwp * I.R3;
     return I;
 }
 
@@ -136,6 +140,7 @@ RT_HD InstT<S> lift_inst(const InstT<T>& I) {
     InstT<S> J;
     J.rs = S(I.rs); J.R = S(I.R); J.Om = S(I.Om); J.cm = S(I.cm); J.sm = S(I.sm); J.Cwp = S(I.Cwp);
     J.R3 = S(I.R3); J.ma2 = S(I.ma2); J.bnorm = S(I.bnorm); J.kL = S(I.kL);
+    J.iOm = S(I.iOm); J.Omsm = S(I.Omsm); J.msm = S(I.msm); J.CwpR3 = S(I.CwpR3);
     J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
     J.larmor = I.larmor;
     return J;
@@ -187,6 +192,7 @@ RT_HD double resonance_line(const InstT<T>& I, const double n[3], const double m
     InstT<double> J;
     J.rs = value(I.rs); J.R = value(I.R); J.Om = value(I.Om); J.cm = value(I.cm); J.sm = value(I.sm);
     J.Cwp = value(I.Cwp); J.R3 = value(I.R3); J.ma2 = value(I.ma2); J.bnorm = value(I.bnorm);
+    J.iOm = value(I.iOm); J.Omsm = value(I.Omsm); J.msm = value(I.msm); J.CwpR3 = value(I.CwpR3);
     J.plasma = I.plasma; J.density = I.density; J.oblique = I.oblique; J.gr_dipole = I.gr_dipole;
     J.kL = value(I.kL); J.larmor = I.larmor;
     double ir = 1.0 / r;

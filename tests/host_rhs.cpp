@@ -11,6 +11,7 @@ using namespace rtd;
 static InstT<double> inst_from(const double* c, const int* e) {
     InstT<double> I;
     I.rs = c[0]; I.R = c[1]; I.Om = c[2]; I.cm = c[3]; I.sm = c[4]; I.Cwp = c[5]; I.R3 = c[1] * c[1] * c[1];
+    I.iOm = 1.0 / I.Om; I.Omsm = I.Om * I.sm; I.msm = -I.sm; I.CwpR3 = I.Cwp * I.R3;
     I.ma2 = c[6];
     I.plasma = e[0]; I.density = e[1]; I.oblique = (I.sm != 0.0) ? 1 : 0;
     I.gr_dipole = e[2]; I.bnorm = c[7];
