@@ -551,8 +551,9 @@ def bench_adjoint(args, rt, W, np, torch):
     acc, rej, st = inf[0], inf[1], inf[2]
     traced = st != W.STATUS_NO_RESONANCE
     esc = st == W.STATUS_ESCAPED
-    # the adjoint always runs the rotating-axis formula, so the oblique variant's counts apply
-    ft = flop_table()["iso_gj_oblique"]
+    # the star's own counts: the right-hand sides take the aligned axis where sin theta_m = 0,
+    # and the stage products' counts include their rotating-axis pass
+    ft = flop_table()[variant_key(cfg["star"])]
     flops_fwd = float((acc + rej)[traced].sum()) * ft["attempt"] + float(traced.sum()) * 3 * ft["rhs"]
     nseg = (acc[esc] + C - 1) // C
     # reverse, per escaped ray: recompute every attempt of its segments, then per accepted step

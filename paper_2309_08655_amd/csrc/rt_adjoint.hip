@@ -113,17 +113,21 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
 // Compile-time forms of the adjoint kernels: the strong-field Hamiltonian with its plasma and
 // density switches read at run time (MODE_GENERIC), the finite-magnetisation one
 // (MODE_LARMOR), and the strong-field isotropic plasma with the GJ density and the flat dipole
-// (MODE_ISO_GJ, the smoothed-flux workload's star), whose switches become constants: the
-// right-hand side and the stage products are then branch-free, so the compiler can interleave
-// a product's independent passes.  The arithmetic is the same in every form (this file is
-// built with -ffp-contract=on), so a star gives the same bits whichever form traces it.
-constexpr int MODE_GENERIC = 0, MODE_LARMOR = 1, MODE_ISO_GJ = 2;
+// (MODE_ISO_GJ, the smoothed-flux workload's star; MODE_ISO_GJ_ALIGNED for an aligned rotator),
+// whose switches become constants: the right-hand side and the stage products are then
+// branch-free, so the compiler can interleave a product's independent passes.  The aligned
+// form evaluates the axis without the rotation wherever only values are needed (the same
+// values, sin theta_m being zero); the stage products, which carry theta_m tangents, always
+// take the rotating formula.  The arithmetic is the same in every form (this file is built
+// with -ffp-contract=on), so a star gives the same bits whichever form traces it.
+constexpr int MODE_GENERIC = 0, MODE_LARMOR = 1, MODE_ISO_GJ = 2, MODE_ISO_GJ_ALIGNED = 3;
 
 template <int MODE>
 __device__ __forceinline__ void fix_mode(InstT<double>& I) {
     I.larmor = (MODE == MODE_LARMOR) ? 1 : 0;
-    I.oblique = 1;  // the rotating-axis formula throughout (as the entry point sets it)
-    if constexpr (MODE == MODE_ISO_GJ) {
+    // the rotating-axis formula (as the entry point sets it), but for an aligned rotator
+    I.oblique = (MODE == MODE_ISO_GJ_ALIGNED) ? 0 : 1;
+    if constexpr (MODE == MODE_ISO_GJ || MODE == MODE_ISO_GJ_ALIGNED) {
         I.plasma = PL_ISO;
         I.density = DEN_GJ;
         I.gr_dipole = 0;
@@ -132,7 +136,8 @@ __device__ __forceinline__ void fix_mode(InstT<double>& I) {
 
 static int adj_mode(const InstT<double>& I) {
     if (I.larmor) return MODE_LARMOR;
-    if (I.plasma == PL_ISO && I.density == DEN_GJ && !I.gr_dipole) return MODE_ISO_GJ;
+    if (I.plasma == PL_ISO && I.density == DEN_GJ && !I.gr_dipole)
+        return (I.sm == 0.0) ? MODE_ISO_GJ_ALIGNED : MODE_ISO_GJ;
     return MODE_GENERIC;
 }
 
@@ -372,7 +377,7 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
             *gjs = c[10];
         };
         double pb[6] = {0, 0, 0, 0, 0, 0};
-        int miss = adj_reverse_ray<LARMOR, MODE == MODE_ISO_GJ>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, lr,
+        int miss = adj_reverse_ray<LARMOR, MODE == MODE_ISO_GJ || MODE == MODE_ISO_GJ_ALIGNED>(I, A, tol, seed, j, S, nseg, theta_in[j], rays[8 * n + j], C, load, rb, lr,
                                            obs, gbar, n_obs, sigma, pb);
         if (!chain_ok) ++miss;
         if (miss) {
@@ -463,15 +468,19 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         if (rc) return rc;
         const rt_schedule sc = resolve_schedule(nullptr);
         const int mode = adj_mode(I);
-        const void* fk = (mode == MODE_LARMOR)   ? (const void*)adj_fwd_kernel<MODE_LARMOR>
-                         : (mode == MODE_ISO_GJ) ? (const void*)adj_fwd_kernel<MODE_ISO_GJ>
-                                                 : (const void*)adj_fwd_kernel<MODE_GENERIC>;
+        const void* fk = (mode == MODE_LARMOR)           ? (const void*)adj_fwd_kernel<MODE_LARMOR>
+                         : (mode == MODE_ISO_GJ)         ? (const void*)adj_fwd_kernel<MODE_ISO_GJ>
+                         : (mode == MODE_ISO_GJ_ALIGNED) ? (const void*)adj_fwd_kernel<MODE_ISO_GJ_ALIGNED>
+                                                         : (const void*)adj_fwd_kernel<MODE_GENERIC>;
         const int grid = persistent_grid(sc, fk, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         if (mode == MODE_LARMOR)
             launch_adj_fwd<MODE_LARMOR>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
         else if (mode == MODE_ISO_GJ)
             launch_adj_fwd<MODE_ISO_GJ>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
+        else if (mode == MODE_ISO_GJ_ALIGNED)
+            launch_adj_fwd<MODE_ISO_GJ_ALIGNED>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs,
+                                                sigma);
         else
             launch_adj_fwd<MODE_GENERIC>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
         timing_end(st);
@@ -512,6 +521,9 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     else if (mode == MODE_ISO_GJ)
         launch_adj_rev<MODE_ISO_GJ>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma, gbar,
                                     grad_rays, seal);
+    else if (mode == MODE_ISO_GJ_ALIGNED)
+        launch_adj_rev<MODE_ISO_GJ_ALIGNED>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma,
+                                            gbar, grad_rays, seal);
     else
         launch_adj_rev<MODE_GENERIC>(st, I, P, fx, T, seed, n, W, ckpt_every, max_ckpt, ckpt_pool, n_obs, sigma, gbar,
                                      grad_rays, seal);

@@ -507,6 +507,7 @@ RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc
     {
         InstT<D2> J = lift_inst<D2>(I);  // grad P
         J.larmor = 0;
+        J.oblique = 1;  // the theta_m tangent needs the rotating axis, also where sin theta_m = 0
         J.cm.d[1] = I.msm;  // d/dtheta_m of (cos, sin)
         J.sm.d[1] = I.cm;
         D2 yd[4], gp[4];
@@ -768,7 +769,7 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
                     q[0] = e[0] / r; q[1] = e[1] / r; q[2] = e[2] / r; q[3] = 0.0;
                 } else {
                     for (int d = 0; d < 8; ++d) gyf[d] = yb[d];
-                    gj_factor_grad(I.Om, I.cm, I.sm, I.oblique, e, q, &gOm, &gth);
+                    gj_factor_grad(I.Om, I.cm, I.sm, 1, e, q, &gOm, &gth);  // theta_m tangents: rotating axis
                 }
                 double num = 0.0, den = 0.0;
                 for (int d = 0; d < 8; ++d) num += gyf[d] * et[d];
