@@ -74,6 +74,8 @@ def gj_sign_changed(star, rays, fin):
 
 @pytest.mark.parametrize("name,star,n,sigma", [
     ("cfg1-gj-iso-aligned", W.CFG1["star"], 600, 0.02),
+    # the same star tilted: the compile-time isotropic GJ form with the rotating axis
+    ("cfg1-gj-iso-oblique", dict(W.CFG1["star"], theta_m=0.3), 400, 0.02),
     ("cfg2-gj-aniso-gr-oblique", W.CFG2["star"], 300, 0.02),
     ("spherical-aniso-gr-oblique", SPHERICAL, 300, 0.05),
     ("ragged-n-37", W.CFG1["star"], 37, 0.02),
