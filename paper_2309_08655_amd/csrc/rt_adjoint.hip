@@ -141,6 +141,8 @@ static int adj_mode(const InstT<double>& I) {
     return MODE_GENERIC;
 }
 
+constexpr int ADJ_REFILL_MIN = 4;
+
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
 // cost-ordered work list; checkpoints, per-ray counters and the flux.  Each checkpoint takes
 // the next free pool slot (one atomic per wave for the lanes storing together) and links
@@ -192,7 +194,9 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
     };
     while (true) {
         unsigned long long idle = __ballot(!active);
-        if (idle && !exhausted) {
+        // refill once four lanes are idle (or the whole wave): one atomic and one pass of
+        // the start-up code for several lanes, as in the tracing kernels
+        if (idle && !exhausted && (__popcll(idle) >= ADJ_REFILL_MIN || idle == __ballot(true))) {
             int cnt = __popcll(idle);
             int leader = __ffsll((long long)idle) - 1;
             unsigned long long base = 0;
