@@ -335,7 +335,12 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     double pacc[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long missing = 0;
     const unsigned long long rlen = lctr->len < (unsigned long long)n ? lctr->len : (unsigned long long)n;
-    auto rb = [&](int idx, int d) -> double& { return replay[((int64_t)idx * 11 + d) * REV_LANES + lane_g]; };
+    // the replay buffer, addressed from a fresh lane index too: a spilled address would be
+    // reloaded just after the one-step-ahead loads, and waiting for that reload would wait
+    // for them
+    auto rb = [&](int idx, int d) -> double& {
+        return replay[((int64_t)idx * 11 + d) * REV_LANES + (int64_t)blockIdx.x * 64 + lane_now()];
+    };
     // the walked step's rows in LDS (one wave a block: 36 KB, so that four blocks, one a
     // SIMD, fit a CU's 160 KB)
     __shared__ double lsh[LR_SLOTS * 64];

@@ -727,11 +727,21 @@ RT_HD int adj_reverse_ray(const InstT<double>& I, const AdjParams& A, const TolC
             for (int d = 0; d < 8; ++d) same = same && (yc[d] == y[d]);
             if (!same) ++missing;
         }
-        // walk the segment backwards
+        // walk the segment backwards; each step's replay entry is loaded one step ahead, so
+        // that its latency hides behind the step before
+        double nyn[8], nhn = 0.0, nthk = 2.0, ngn = 0.0;
+        auto fetch = [&](int k) {
+            for (int d = 0; d < 8; ++d) nyn[d] = rb(k, d);
+            nhn = rb(k, 8);
+            nthk = rb(k, 9);
+            ngn = rb(k, 10);
+        };
+        if (stored > 0) fetch(stored - 1);
         for (int idx = stored - 1; idx >= 0; --idx) {
             double yn[8];
-            for (int d = 0; d < 8; ++d) yn[d] = rb(idx, d);
-            const double hn = rb(idx, 8), thk = rb(idx, 9), gn = rb(idx, 10);
+            for (int d = 0; d < 8; ++d) yn[d] = nyn[d];
+            const double hn = nhn, thk = nthk, gn = ngn;
+            if (idx > 0) fetch(idx - 1);
             {
                 const auto r = lr(LR_YN);
                 for (int d = 0; d < 8; ++d) r[d] = yn[d];
