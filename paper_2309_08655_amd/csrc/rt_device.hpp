@@ -329,6 +329,7 @@ template <class T>
 struct Plasma {
     // P and its derivatives: grad_x P = pn n + pm m + pz e_z, dP/dt = pt
     T P, pn, pm, pz, pt;
+    T g;  // GJ density: the factor g = 3 n_z mu - cos(theta_m) itself (0 for the others)
 };
 
 // the Cartesian components of grad_x P
@@ -459,7 +460,7 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
                             const T& dmu, double gjs = 0.0) {
     Plasma<T> p;
     if (I.density == DEN_NONE) {
-        p.P = T(0.0); p.pn = T(0.0); p.pm = T(0.0); p.pz = T(0.0); p.pt = T(0.0);
+        p.P = T(0.0); p.pn = T(0.0); p.pm = T(0.0); p.pz = T(0.0); p.pt = T(0.0); p.g = T(0.0);
         return p;
     }
     T ir3 = ir * ir * ir;
@@ -470,10 +471,12 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
         D3 = I.CwpR3 * ir3;
     else
         D3 = I.Cwp * (I.R3 * ir3);
+    p.g = T(0.0);
     if (I.density == DEN_GJ) {
         // P = D3 |g|, g = 3 n_z mu - cos(theta_m); with a = 3 sign(g),
         // grad P = (D3/r) [a (n_z m + mu e_z) - (2 a n_z mu + 3 |g|) n],  dP/dt = D3 a n_z dmu
         T g = 3.0 * n[2] * mu - I.cm;
+        p.g = g;
         double sg = (gjs != 0.0) ? gjs : ((value(g) < 0.0) ? -1.0 : 1.0);
         T ag = sg * g;
         p.P = D3 * ag;
@@ -509,7 +512,8 @@ RT_HD Plasma<T> plasma_eval(const InstT<T>& I, const T n[3], const T& ir, const 
 // gradient of H: g = (dH/dx, dH/dy, dH/dz, dH/dt, dH/dk_x, dH/dk_y, dH/dk_z, dH/dk_t)
 // ----------------------------------------------------------------------------
 template <class T>
-RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = nullptr, double gjs = 0.0) {
+RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = nullptr, double gjs = 0.0,
+                  T* gfac = nullptr) {
     const T& kx = y[4]; const T& ky = y[5]; const T& kz = y[6]; const T& kt = y[7];
     T r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
     T ir = frsqrt(r2);
@@ -546,6 +550,7 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
     // dm/dt = Omega e_z x m, so (dm/dt).v = Omega (m_x v_y - m_y v_x)
     T dmu = I.oblique ? I.Om * (m[0] * n[1] - m[1] * n[0]) : T(0.0);
     Plasma<T> p = plasma_eval(I, n, ir, m, mu, dmu, gjs);
+    if (gfac) *gfac = p.g;  // the same bits as gj_factor at y
     if (I.plasma == PL_ISO) {
         const T Cn2 = Cn + p.pn;
         for (int i = 0; i < 3; ++i) {
@@ -650,12 +655,13 @@ RT_HD void grad_h(const InstT<T>& I, const T y[8], T g[8], const AxisRef* ref = 
 }
 
 // Hamilton's equations, eq. (Hamilton); sign = -1 integrates backwards in the worldline parameter.
-// gjs selects the piece of the GJ density (see plasma_eval).
+// gjs selects the piece of the GJ density (see plasma_eval); *gfac, if given, receives the GJ
+// factor at y for a density with one (left as it was for the others).
 template <class T>
 RT_HD void rhs(const InstT<T>& I, const T y[8], T f[8], double sign, const AxisRef* ref = nullptr,
-               double gjs = 0.0) {
+               double gjs = 0.0, T* gfac = nullptr) {
     T g[8];
-    grad_h(I, y, g, ref, gjs);
+    grad_h(I, y, g, ref, gjs, gfac);
     for (int i = 0; i < 4; ++i) {
         f[i] = sign * g[4 + i];
         f[4 + i] = -sign * g[i];

@@ -179,7 +179,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
     double* slot = stash + ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * STASH_STRIDE;
     auto st_put = [&](int fld, double v) { slot[fld] = v; };
     auto st_get = [&](int fld) { return slot[fld]; };
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref, gjs); };
+    // gnew: the GJ factor at the last state f was evaluated at, which after an attempt is the
+    // step's end (its last stage); the crossing test takes it from there
+    double gnew = 0.0;
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, 1.0, &ref, gjs, &gnew); };
     const double rmax2 = tol.rmax * tol.rmax;
     double R2 = I.R * I.R;
 
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_fwd_kernel(InstT<double> I0
                 double g1 = 0.0;
                 bool cross = false;
                 if (I.density == DEN_GJ && finite_ok && r2new > R2) {
-                    g1 = gj_factor(I, ynew, &ref);
+                    g1 = gnew;  // = gj_factor(I, ynew, &ref), from the last stage
                     cross = (gjs * g1 < 0.0);
                 }
                 if (cross) {
