@@ -153,7 +153,10 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
     y[0] = 1e5;
     y[7] = -1.0;
     AxisRef ref = axis_ref_at(I, 0.0);
-    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0, &ref, gjs); };
+    // gnew: the GJ factor at the last state f was evaluated at (after an attempt, the step's
+    // end), for the null-surface test
+    double gnew = 0.0;
+    auto f = [&](const double* yy, double* ff) { rhs(I, yy, ff, -1.0, &ref, gjs, &gnew); };
 
     while (true) {
         unsigned long long idle = __ballot(!active);
@@ -205,7 +208,7 @@ __global__ void __launch_bounds__(BLOCK, MINW) trace_bwd_kernel(InstT<double> I,
         // along the other piece from the first point past it (thk > 1: no crossing)
         double thk = 2.0;
         if (gjs != 0.0) {
-            const double g1 = gj_factor(I, ynew, &ref);
+            const double g1 = gnew;  // = gj_factor(I, ynew, &ref), from the last stage
             if (gjs * g1 < 0.0) {
                 double phik;
                 thk = locate_null_crossing(I, y, ynew, S, h, gjs, gjs * gj_factor(I, y, &ref), gjs * g1, &ref, &phik);
