@@ -23,8 +23,9 @@
 // rays (slots handed out in order of need; each ray's checkpoints form a chain from its last
 // back to its first), so the pool holds what the rays need, not a worst case; the reverse
 // sweep recomputes each segment from its checkpoint into a per-lane replay
-// buffer and walks it backwards, one step at a time, with the step's stage states
-// and their adjoints in LDS (80 doubles a lane: 40 KB for a wave of 64).  This file is compiled with multiply-add fusion
+// buffer and walks it backwards, one step at a time, with the step's stage states, their
+// adjoints and the step's other per-lane vectors in LDS (72 doubles a lane: 36 KB for a wave
+// of 64).  This file is compiled with multiply-add fusion
 // decided per source expression only (-ffp-contract=on), so the forward pass and the
 // recompute, which inline the same step code, produce the same bits; a ray whose
 // recompute does not end exactly on its next checkpoint gets a NaN gradient share.
@@ -329,7 +330,6 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
     if (rctr->pad[0] != seal) return;  // no forward phase of these arguments in this workspace
     constexpr bool LARMOR = (MODE == MODE_LARMOR);
     fix_mode<MODE>(I);
-    const int64_t lane_g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     AdjParams A;
     make_adj_params(P.p, fx, A);
     double pacc[6] = {0, 0, 0, 0, 0, 0};
@@ -462,7 +462,9 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
     adj_ws_layout(ws, n, n_obs, ckpt_every, ckpt_pool, &W);
     unsigned long long* pool_next = &W.rctr->pad[1];
     InstT<double> I = make_inst(*star);
-    I.oblique = 1;  // the rotating-axis formula throughout (exact at theta_m = 0, and theta_m tangents flow)
+    // the rotating-axis formula (exact at theta_m = 0, and theta_m tangents flow); the aligned
+    // isotropic GJ form leaves it out where only values are needed
+    I.oblique = 1;
     TolC T{tol->rtol, tol->atol, tol->r_max_km, (long long)tol->max_steps};
     if (phase == 0) {
         if (!flux) return fail(RT_EINVAL, "rt_flux_grad: null flux");
