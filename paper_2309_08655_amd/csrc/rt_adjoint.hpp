@@ -474,36 +474,62 @@ RT_HD void grad_p(const InstT<T>& I, const T* y, T g[4], double gjs) {
     g[3] = p.pt;
 }
 
+// Stage product of the vacuum part H_vac = -k_t^2/A + k.k - s q^2 (s = r_s/r, A = 1 - s,
+// q = n.k, Sec. 2.1's metric), derived by hand: its gradient is
+//   dH/dk = 2 k + kn n,  dH/dk_t = -2 kti,  dH/dx = Cn n + Ck k,  dH/dt = 0,
+//   kn = -2 s q,  kti = k_t / A,  Cn = (s/r) W,  W = kti^2 + 3 q^2,  Ck = kn / r,
+// and vy = Hess(H_vac) u is its derivative along u = (-v_k, v_x) (position -v_k, momentum
+// v_x), through dr = n.dx, dn = (dx - n dr)/r, ds = -(s/r) dr, d(1/A) = -(s/r) dr / A^2,
+// dq = dn.k + n.dk; vc0 = v^T df/dr_s with f = (dH/dk, -dH/dx) takes the same gradient's
+// derivative in r_s at fixed state (ds/dr_s = 1/r).
+template <class S>
+RT_HD void vacuum_vjp(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc0) {
+    const S ir = frsqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]);
+    const S n[3] = {Y[0] * ir, Y[1] * ir, Y[2] * ir};
+    const S s = I.rs * ir;
+    const S iA = frcp(1.0 - s);
+    const S q = n[0] * Y[4] + n[1] * Y[5] + n[2] * Y[6];
+    const S sr = s * ir;
+    const S kti = Y[7] * iA;
+    const S kn = -2.0 * s * q;
+    const S W = kti * kti + 3.0 * q * q;
+    const S Cn = sr * W;
+    const S Ck = kn * ir;
+    // along u: dx = -v_k, dk = v_x, dk_t = v_3 (dt = -v_7 does not enter the vacuum part)
+    const S dr = (S(0.0) - n[0] * v[4]) - n[1] * v[5] - n[2] * v[6];
+    S dn[3];
+    for (int i = 0; i < 3; ++i) dn[i] = (S(0.0) - v[4 + i] - n[i] * dr) * ir;
+    const S sdr = sr * dr;  // -ds
+    const S dq = (dn[0] * Y[4] + dn[1] * Y[5] + dn[2] * Y[6]) + (n[0] * v[0] + n[1] * v[1] + n[2] * v[2]);
+    const S dkti = (v[3] - kti * sdr) * iA;
+    const S dkn = 2.0 * (sdr * q - s * dq);
+    const S dCn = sr * (2.0 * kti * dkti + 6.0 * q * dq) - 2.0 * sdr * ir * W;
+    const S dCk = (dkn - kn * ir * dr) * ir;
+    for (int i = 0; i < 3; ++i) {
+        vy[i] = dCn * n[i] + Cn * dn[i] + dCk * Y[4 + i] + Ck * v[i];
+        vy[4 + i] = dkn * n[i] + kn * dn[i] + 2.0 * v[i];
+    }
+    vy[3] = S(0.0);
+    vy[7] = -2.0 * dkti;
+    // r_s: d kn = -2 q / r, d kti = kti / (A r), d Cn = W / r^2 + 2 (s/r) kti d kti, d Ck = d kn / r
+    const S pkn = -2.0 * q * ir;
+    const S pkti = kti * iA * ir;
+    const S pCn = W * ir * ir + 2.0 * sr * kti * pkti;
+    const S vxn = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+    const S vkn = v[4] * n[0] + v[5] * n[1] + v[6] * n[2];
+    const S vkk = v[4] * Y[4] + v[5] * Y[5] + v[6] * Y[6];
+    *vc0 = pkn * vxn - 2.0 * v[3] * pkti - pCn * vkn - pkn * ir * vkk;
+}
+
 // The same for an isotropic plasma (or none) and the strong-field Hamiltonian: H = H_vac + P
 // with P a function of (x, t) alone, r_s only in H_vac, and Om, theta_m and the plasma
-// coefficient only in P.  Two passes with two tangents each: the vacuum right-hand side with
-// tangents u and r_s (Hess(H_vac) u and the r_s channel), and grad P with tangents u's (x, t)
-// part and theta_m (Hess(P) u, the theta_m channel, and through its value, which is the plasma
-// part of f, the plasma channel and the Om channel).
+// coefficient only in P.  The vacuum part in closed form (vacuum_vjp), then grad P in dual
+// numbers with tangents u's (x, t) part and theta_m (Hess(P) u, the theta_m channel, and
+// through its value, which is the plasma part of f, the plasma channel and the Om channel).
 template <class S>
 RT_HD void stage_vjp_iso(const InstT<S>& I, const S* Y, const S* v, S* vy, S* vc, double gjs) {
     typedef gdual<2, S> D2;
-    {
-        InstT<D2> J = lift_inst<D2>(I);  // the vacuum part
-        J.density = DEN_NONE;
-        J.larmor = 0;
-        J.rs.d[1] = S(1.0);
-        D2 yd[8], fd[8];
-        for (int i = 0; i < 4; ++i) {
-            yd[i] = D2(Y[i]);
-            yd[i].d[0] = S(0.0) - v[4 + i];  // u_x = -v_k
-            yd[4 + i] = D2(Y[4 + i]);
-            yd[4 + i].d[0] = v[i];  // u_k = v_x
-        }
-        rhs(J, yd, fd, 1.0);
-        for (int i = 0; i < 4; ++i) {
-            vy[i] = S(0.0) - fd[4 + i].d[0];
-            vy[4 + i] = fd[i].d[0];
-        }
-        S a = v[0] * fd[0].d[1];
-        for (int i = 1; i < 8; ++i) a = a + v[i] * fd[i].d[1];
-        vc[0] = a;
-    }
+    vacuum_vjp(I, Y, v, vy, &vc[0]);
     {
         InstT<D2> J = lift_inst<D2>(I);  // grad P
         J.larmor = 0;
