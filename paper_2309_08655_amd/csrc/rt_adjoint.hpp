@@ -632,11 +632,13 @@ struct LaneRow {
 template <bool FL, bool ISO, class S, class Rows>
 RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, S* tc, Rows&& lr, double gjs) {
     using namespace dp5;
-    const double Al[5][5] = {{a21, 0, 0, 0, 0},
-                             {a31, a32, 0, 0, 0},
-                             {a41, a42, a43, 0, 0},
-                             {a51, a52, a53, a54, 0},
-                             {a61, a62, a63, a64, a65}};  // a_li: row l - 2, column i - 1
+    // a_li by column: row i - 1 holds a_{i+1,i} .. a_{6,i} at l - 2, so that a stage's
+    // coefficients are contiguous (one wide scalar load for the wave-uniform i)
+    const double Al[5][5] = {{a21, a31, a41, a51, a61},
+                             {0, a32, a42, a52, a62},
+                             {0, 0, a43, a53, a63},
+                             {0, 0, 0, a54, a64},
+                             {0, 0, 0, 0, a65}};
     const double Bw[7] = {b1, 0.0, b3, b4, b5, b6, 0.0};
     S v[8], Y[8], vy[8], vc[5];
     const int top = dense ? 7 : 6;
@@ -661,12 +663,16 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, 
             const auto r = lr(LR_GYF);
             for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
         }
+        double al[5];
+        for (int q = 0; q < 5; ++q) al[q] = Al[i - 1][q];
 #pragma unroll
         for (int l = 2; l <= 6; ++l) {
             if (l <= i) continue;
-            const S c = h * Al[l - 2][i - 1];
+            const S c = h * al[l - 2];
             const auto r = lr(l - 2);
-            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
+            S w[8];  // the whole row first: its reads go out together
+            for (int d = 0; d < 8; ++d) w[d] = r[d];
+            for (int d = 0; d < 8; ++d) v[d] = v[d] + c * w[d];
         }
         if constexpr (ISO)
             stage_vjp_iso<S>(I, Y, v, vy, vc, gjs);
