@@ -145,7 +145,9 @@ static int adj_mode(const InstT<double>& I) {
 constexpr int ADJ_REFILL_MIN = 4;
 
 // forward pass: persistent, one ray per lane with wave-aggregated refill from the
-// cost-ordered work list; checkpoints, per-ray counters and the flux.  Each checkpoint takes
+// cost-ordered work list; checkpoints, per-ray counters, and the final state of each escaped
+// ray in fin (rows 0..7), from which adj_flux_kernel forms the flux outside this loop (the
+// observer sum of a finishing lane would hold its whole wave).  Each checkpoint takes
 // the next free pool slot (one atomic per wave for the lanes storing together) and links
 // to the ray's previous one; a request beyond the pool is counted but not stored (the
 // count then tells the caller the pool it needs, and the reverse pass refuses to run).
@@ -159,13 +161,9 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
                                                       unsigned long long* __restrict__ pool_next,
                                                       int32_t* __restrict__ nseg_out,
                                                       double* __restrict__ theta_out, int32_t* __restrict__ ifin,
-                                                      const double* __restrict__ obs, int n_obs, double sigma,
-                                                      double* __restrict__ facc) {
-    __shared__ double sh_f[MAX_OBS];
+                                                      double* __restrict__ fin) {
     constexpr bool LARMOR = (MODE == MODE_LARMOR);
     fix_mode<MODE>(I);
-    for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) sh_f[q] = 0.0;
-    __syncthreads();
     const int lane = __lane_id();
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long nlist = ctr->len;
@@ -230,15 +228,42 @@ __global__ void __launch_bounds__(256, 2) adj_fwd_kernel(InstT<double> I, TolC t
             ckhead[j] = head;
             if (status == ST_ESCAPED) {
                 theta_out[j] = th;
-                const double w = rays[8 * n + j];
-                double nh[3];
-                arrival_direction(I, yf, nh);
-                for (int o = 0; o < n_obs; ++o) {
-                    const double c = nh[0] * obs[3 * o] + nh[1] * obs[3 * o + 1] + nh[2] * obs[3 * o + 2];
-                    atomicAdd(&sh_f[o], w * smoothing_kernel(c, sigma));
-                }
+                for (int d = 0; d < 8; ++d) fin[d * n + j] = yf[d];
             }
             active = false;
+        }
+    }
+}
+
+// Smoothed flux of the forward pass, Sec. 2.2 eq. (Power) smoothed on the sky:
+// F_o += w_j K(n_j . o) over the escaped rays (final states in fin rows 0..7, arrival
+// direction n_j), summed across each wave by shuffles, per workgroup in LDS, then over
+// workgroups with one atomic per observer.  The ray loop's bound is the workgroup's, so
+// every lane of a wave takes part in each shuffle.
+__global__ void __launch_bounds__(256) adj_flux_kernel(InstT<double> I, const double* __restrict__ fin,
+                                                       const int32_t* __restrict__ ifin,
+                                                       const double* __restrict__ rays, int64_t n,
+                                                       const double* __restrict__ obs, int n_obs, double sigma,
+                                                       double* __restrict__ facc) {
+    __shared__ double sh_f[MAX_OBS];
+    for (int q = threadIdx.x; q < MAX_OBS; q += blockDim.x) sh_f[q] = 0.0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t j = base + threadIdx.x;
+        const bool esc = (j < n) && ifin[2 * n + j] == ST_ESCAPED;
+        double nh[3] = {0.0, 0.0, 0.0}, w = 0.0;
+        if (esc) {
+            double yf[8];
+            for (int d = 0; d < 8; ++d) yf[d] = fin[d * n + j];
+            arrival_direction(I, yf, nh);
+            w = rays[8 * n + j];
+        }
+        for (int o = 0; o < n_obs; ++o) {
+            const double c = nh[0] * obs[3 * o] + nh[1] * obs[3 * o + 1] + nh[2] * obs[3 * o + 2];
+            double v = esc ? w * smoothing_kernel(c, sigma) : 0.0;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (__lane_id() == 0 && v != 0.0) atomicAdd(&sh_f[o], v);
         }
     }
     __syncthreads();
@@ -408,10 +433,10 @@ __global__ void __launch_bounds__(64) adj_rev_kernel(InstT<double> I, ParamVec P
 
 template <int MODE>
 static void launch_adj_fwd(int grid, hipStream_t st, const InstT<double>& I, const TolC& T, int64_t n, const AdjWs& W,
-                           int C, int Kc, int64_t ckpt_pool, unsigned long long* pool_next, int n_obs, double sigma) {
+                           int C, int Kc, int64_t ckpt_pool, unsigned long long* pool_next) {
     hipLaunchKernelGGL(adj_fwd_kernel<MODE>, dim3(grid), dim3(256), 0, st, I, T, n, W.fw.ctr, W.fw.list, W.rays,
                        W.fw.y0, W.fw.h0, C, Kc, W.pool, (long long)ckpt_pool, W.ckhead, pool_next, W.nseg, W.theta,
-                       W.ifin, W.obs, n_obs, sigma, W.facc);
+                       W.ifin, W.fin);
 }
 
 template <int MODE>
@@ -486,16 +511,19 @@ extern "C" int rt_flux_grad(const rt_star* star, const rt_tol* tol, uint64_t see
         const int grid = persistent_grid(sc, fk, 256);
         timing_begin(st, RT_KERNEL_ADJOINT_FORWARD);
         if (mode == MODE_LARMOR)
-            launch_adj_fwd<MODE_LARMOR>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
+            launch_adj_fwd<MODE_LARMOR>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next);
         else if (mode == MODE_ISO_GJ)
-            launch_adj_fwd<MODE_ISO_GJ>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
+            launch_adj_fwd<MODE_ISO_GJ>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next);
         else if (mode == MODE_ISO_GJ_ALIGNED)
-            launch_adj_fwd<MODE_ISO_GJ_ALIGNED>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs,
-                                                sigma);
+            launch_adj_fwd<MODE_ISO_GJ_ALIGNED>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next);
         else
-            launch_adj_fwd<MODE_GENERIC>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next, n_obs, sigma);
+            launch_adj_fwd<MODE_GENERIC>(grid, st, I, T, n, W, ckpt_every, max_ckpt, ckpt_pool, pool_next);
         timing_end(st);
         rc = check_launch("adj_fwd_kernel");
+        if (rc) return rc;
+        hipLaunchKernelGGL(adj_flux_kernel, dim3(grid_for(n, 256, 2)), dim3(256), 0, st, I, W.fin, W.ifin, W.rays, n,
+                           W.obs, n_obs, sigma, W.facc);
+        rc = check_launch("adj_flux_kernel");
         if (rc) return rc;
         // the forward list is spent: reuse its buffers for the step-ordered reverse list
         hipLaunchKernelGGL(adj_rev_keys_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, st, W.ifin, n, W.fw.keys);
