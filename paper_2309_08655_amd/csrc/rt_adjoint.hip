@@ -47,7 +47,8 @@ struct AdjWs {
     FwdWs fw;
     double* rays;     // [10][n] seeds
     int32_t* status;  // [n] seed status
-    double* fin;      // [RT_NFIN][n] written by the trace set-up for rays it does not trace (phase 0)
+    double* fin;      // [RT_NFIN][n] (phase 0): the trace set-up's records of rays it does not trace;
+                      // rows 0..7 of an escaped ray: its final state, for the flux kernel
     int32_t* ifin;    // [RT_NIFIN][n]: n_acc, n_rej, status
     int32_t* nseg;    // [n] checkpoints stored
     int32_t* ckhead;  // [n] pool slot of each ray's last checkpoint
@@ -70,8 +71,8 @@ static size_t adj_ws_layout(void* base, int64_t n, int32_t n_obs, int32_t C, int
         p += align256(bytes);
         return q;
     };
-    // The forward workspace, then the final records (which only the set-up of phase 0 writes,
-    // for seeds it does not trace): from the forward workspace's transient part on, both are
+    // The forward workspace, then the final records (which phase 0 writes: the set-up for seeds
+    // it does not trace, the forward kernel for escaped rays): from the forward workspace's transient part on, both are
     // used by phase 0 only, and the replay buffer of phase 1 lies over them (extending past
     // them if it is larger).
     char* fwbase = take(fwd_ws_bytes(n));
