@@ -115,6 +115,22 @@ def test_flux_grad_matches_oracle(rt, orc, name, star, n, sigma):
           float(err[well].max()) if well.any() else None, flush=True)
 
 
+
+def test_flux_at_the_most_observers_matches_oracle(rt, orc):
+    """64 observers, the most the boundary takes (every slot of the flux kernel's per-workgroup
+    sums in use), on a ragged ray count: the flux against the oracle's."""
+    star, tol, n, sigma = W.CFG1["star"], W.tol(), 333, 0.05
+    print(f"adjoint flux at 64 observers n={n}", flush=True)
+    obs = W.observers(64)
+    F, g, gr, info = gpu_flux_grad(rt, star, tol, 0, n, obs, sigma, np.ones(64))
+    Fo, dFo, fray, dray, sto = orc.flux_fwdmode(star, tol, 0, n, obs, sigma, per_ray=True)
+    assert np.array_equal(info[2], sto)
+    well, _ = well_conditioned(orc, star, tol, n, sto)
+    esc = sto == W.STATUS_ESCAPED
+    ill_share = fray[esc & ~well].sum(axis=0)
+    assert F.shape == (64,) and np.abs(Fo).max() > 0.0
+    assert np.all(np.abs(F - Fo) <= 1e-9 * np.abs(Fo).max() + ill_share)
+
 def test_checkpoint_interval_is_invisible(rt):
     """Forward pass and recompute run the same step code, so the checkpoint interval
     changes nothing: per-ray gradients are identical bit for bit."""
