@@ -475,7 +475,7 @@ RT_HD void grad_p(const InstT<T>& I, const T* y, T g[4], double gjs) {
 }
 
 // Stage product of the vacuum part H_vac = -k_t^2/A + k.k - s q^2 (s = r_s/r, A = 1 - s,
-// q = n.k, Sec. 2.1's metric), derived by hand: its gradient is
+// q = n.k; Sec. 4.1 eq. (SchwarzshildMetric1)), derived by hand: its gradient is
 //   dH/dk = 2 k + kn n,  dH/dk_t = -2 kti,  dH/dx = Cn n + Ck k,  dH/dt = 0,
 //   kn = -2 s q,  kti = k_t / A,  Cn = (s/r) W,  W = kti^2 + 3 q^2,  Ck = kn / r,
 // and vy = Hess(H_vac) u is its derivative along u = (-v_k, v_x) (position -v_k, momentum
