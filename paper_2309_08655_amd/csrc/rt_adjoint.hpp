@@ -632,14 +632,16 @@ struct LaneRow {
 template <bool FL, bool ISO, class S, class Rows>
 RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, S* tc, Rows&& lr, double gjs) {
     using namespace dp5;
-    // a_li by column: row i - 1 holds a_{i+1,i} .. a_{6,i} at l - 2, so that a stage's
-    // coefficients are contiguous (one wide scalar load for the wave-uniform i)
-    const double Al[5][5] = {{a21, a31, a41, a51, a61},
-                             {0, a32, a42, a52, a62},
-                             {0, 0, a43, a53, a63},
-                             {0, 0, 0, a54, a64},
-                             {0, 0, 0, 0, a65}};
-    const double Bw[7] = {b1, 0.0, b3, b4, b5, b6, 0.0};
+    // stage i's coefficients in row i - 1: b_i, then a_{l,i} at 1 + l - 2 for l = 2..6 (the
+    // column of a), contiguous so that the wave-uniform i reads them with one wide scalar load,
+    // issued at the top of the stage so that it lands while the stage rows are read
+    const double Cf[7][6] = {{b1, a21, a31, a41, a51, a61},
+                             {0.0, 0, a32, a42, a52, a62},
+                             {b3, 0, 0, a43, a53, a63},
+                             {b4, 0, 0, 0, a54, a64},
+                             {b5, 0, 0, 0, 0, a65},
+                             {b6, 0, 0, 0, 0, 0},
+                             {0.0, 0, 0, 0, 0, 0}};
     S v[8], Y[8], vy[8], vc[5];
     const int top = dense ? 7 : 6;
 #pragma unroll 1
@@ -647,13 +649,15 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, 
         // read before any lane leaves the iteration: the stage index is the wave's
         const int i = wave_uniform(i0);
         if (i > top) continue;
+        double cf[6];
+        for (int q = 0; q < 6; ++q) cf[q] = Cf[i - 1][q];
         if (i == 7) {
             for (int d = 0; d < 8; ++d) Y[d] = y7[d];
         } else {
             const auto r = lr(i >= 2 ? i - 2 : LR_YN);
             for (int d = 0; d < 8; ++d) Y[d] = r[d];
         }
-        const S hb = h * Bw[i - 1];
+        const S hb = h * cf[0];
         {
             const auto r = lr(LR_YNB);
             for (int d = 0; d < 8; ++d) v[d] = hb * r[d];
@@ -663,12 +667,10 @@ RT_HD void step_adjoint(const InstT<S>& I, const S* y7, S h, bool dense, S* yb, 
             const auto r = lr(LR_GYF);
             for (int d = 0; d < 8; ++d) v[d] = v[d] + c * r[d];
         }
-        double al[5];
-        for (int q = 0; q < 5; ++q) al[q] = Al[i - 1][q];
 #pragma unroll
         for (int l = 2; l <= 6; ++l) {
             if (l <= i) continue;
-            const S c = h * al[l - 2];
+            const S c = h * cf[l - 1];
             const auto r = lr(l - 2);
             S w[8];  // the whole row first: its reads go out together
             for (int d = 0; d < 8; ++d) w[d] = r[d];
